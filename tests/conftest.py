@@ -1,0 +1,21 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+    config.addinivalue_line("markers", "slow: full-size case (minutes on the CPU side)")
+
+
+@pytest.fixture(scope="session", autouse=True)
+def _oracle_built():
+    # The oracle is plain C built with gcc; build it once per session if missing.
+    from oracle.build import LIB_PATH, build
+    if not os.path.exists(LIB_PATH):
+        build()
