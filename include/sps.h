@@ -1,0 +1,175 @@
+/*
+ * sps.h -- C ABI of the MI355X single-pulse search hot path.
+ *
+ * The library computes, on one AMD Instinct MI355X (gfx950):
+ *   1. brute-force incoherent dedispersion of a channelised 8-bit filterbank
+ *      over a grid of trial DMs (ASTROFLOW, arXiv:2511.02328, Sec. 2.3: the
+ *      direct method of cost N_DM N_t N_f, with per-channel integer delays
+ *      from Eq. (KDM) rounded as in Eq. (coarse_delay));
+ *   2. a boxcar matched-filter S/N search over the DM-time plane (Sec. 1,
+ *      step (iii) of the standard single-pulse workflow);
+ *   3. candidate detection producing DM, arrival time referenced to the top
+ *      of the band, width and S/N (Sec. 2, the candidate record).
+ *
+ * Conventions for every call:
+ *   - All functions return sps_status.  No exception, abort or exit crosses
+ *     the ABI.  On failure a message is available from sps_last_error()
+ *     (thread-local, valid until the next call on the same thread).
+ *   - Arguments are validated before any work is enqueued; a call that
+ *     returns SPS_ERR_INVALID_ARG / RANGE / OVERFLOW has done nothing.
+ *   - "device" pointers are HIP device memory on the device that was current
+ *     when the plan was created; "host" pointers are ordinary host memory.
+ *     The caller owns every buffer it passes; the library never frees or
+ *     retains them after the call returns (device buffers must stay valid
+ *     until the enqueued work completes).
+ *   - stream is a hipStream_t passed as void* (NULL = the null stream).
+ *     sps_dedisperse and sps_boxcar_snr are asynchronous with respect to the
+ *     host; sps_detect synchronises the stream before it returns.
+ *   - A plan may be used by one stream at a time (it owns scratch memory).
+ *   - Errors from kernels that ran earlier on the stream surface as
+ *     SPS_ERR_DEVICE from the call that observes them.
+ */
+#ifndef SPS_H
+#define SPS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SPS_OK = 0,
+  SPS_ERR_INVALID_ARG = 1, /* NULL pointer, bad size, bad ordering, bad layout */
+  SPS_ERR_RANGE = 2,       /* sizes inconsistent with each other or the plan */
+  SPS_ERR_NOMEM = 3,       /* device or host allocation failed */
+  SPS_ERR_DEVICE = 4,      /* a HIP runtime call or kernel failed */
+  SPS_ERR_OVERFLOW = 5,    /* a sum could exceed its integer type */
+  SPS_ERR_TRUNCATED = 6    /* sps_detect found more candidates than cap */
+} sps_status;
+
+/* Observation description (Sec. 2.3, Eq. KDM): channel centre frequencies,
+ * the reference frequency the delays are measured from (the top of the band,
+ * Sec. 2), the sampling time, and the trial DMs. */
+typedef struct {
+  int32_t nchan;          /* number of channels, >= 1 */
+  const double *freq_mhz; /* host [nchan] channel centres in MHz, each in (0, fref_mhz]; copied */
+  double fref_mhz;        /* reference frequency in MHz (arrival times are quoted here) */
+  double tsamp_s;         /* sampling time in seconds, > 0 */
+  int32_t ndm;            /* number of trial DMs, >= 1 */
+  const double *dm;       /* host [ndm] trial DMs in pc cm^-3, each >= 0; copied */
+} sps_obs_desc;
+
+typedef struct sps_plan_s *sps_plan;
+
+/* Creates a plan on the current HIP device: computes the integer delay table
+ *   D[d][c] = floor(x + 1/2),  x = (K_DM * dm[d] / tsamp_s) * (1/f_c^2 - 1/f_ref^2)
+ * with K_DM = 4.148808e3 s MHz^2 pc^-1 cm^3 (Eq. KDM; the paper prints the
+ * unit as ms, which would be 10^3 too small) in IEEE double on the host, and
+ * uploads it.  INVALID_ARG: NULL pointers, nchan/ndm < 1, tsamp_s <= 0,
+ * a channel above fref_mhz or at a non-positive frequency, a negative DM.
+ * OVERFLOW: a delay above 2^31 - 1 samples, or 255 * nchan >= 2^31.
+ * NOMEM / DEVICE: allocation or upload failed.  *out is NULL on failure. */
+sps_status sps_plan_create(const sps_obs_desc *desc, sps_plan *out);
+
+/* Frees the plan and its device memory.  NULL is accepted.  The caller must
+ * make sure no enqueued work still uses the plan. */
+sps_status sps_plan_destroy(sps_plan plan);
+
+/* Copies the delay table to host_out ([ndm][nchan] int32, row-major) when it
+ * is not NULL, and the largest delay to *max_delay when that is not NULL. */
+sps_status sps_plan_delays(sps_plan plan, int32_t *host_out, int32_t *max_delay);
+
+/* Dedispersion flags. */
+#define SPS_ZERO_PAD 1u /* allow nsamp_in < nout + max_delay: samples at or past
+                           nsamp_in contribute zero (Eq. stage1's convention) */
+
+/* Brute-force dedispersion (Sec. 2.3):
+ *   Y[d][t] = sum_c X[c][t + D[d][c]],  t in [0, nout),
+ * exact in unsigned 32-bit integers (every sum is at most 255 * nchan).
+ *   X:        device uint8 [nchan][pitch], channel-major; only the first
+ *             nsamp_in samples of each row are read, the rest of the row is
+ *             padding.  X must be 16-byte aligned and pitch a multiple of 16
+ *             (INVALID_ARG otherwise); the buffer holds nchan * pitch bytes.
+ *   nsamp_in: valid samples per channel row, 0 <= nsamp_in <= pitch.
+ *   Y:        device uint32 [ndm][nout], fully overwritten.
+ *   nout:     output samples per DM row, 1 <= nout <= 2^31 - 1.
+ *   flags:    0 requires nsamp_in >= nout + max_delay (RANGE otherwise), so
+ *             every output is a full sum; SPS_ZERO_PAD relaxes it.
+ * Output time index t is the arrival time at f_ref (Sec. 2).  Asynchronous. */
+sps_status sps_dedisperse(sps_plan plan, const uint8_t *X, int64_t pitch, int64_t nsamp_in,
+                          uint32_t *Y, int64_t nout, uint32_t flags, void *stream);
+
+/* Boxcar matched-filter S/N over the DM-time plane (Sec. 1, step iii).
+ * Per DM row d: med_d = lower median of Y[d][0..nout) (rank floor((n-1)/2)),
+ * MAD_d = lower median of |Y[d][t] - med_d|, sigma_d = 1.4826 * MAD_d.
+ * For each width w = widths[i] with t + w <= nout:
+ *   S/N_w(t) = (sum_{k<w} Y[d][t+k] - w * med_d) / (sigma_d * sqrt(w)),
+ * the numerator exact in integers, the scale in binary32.  Outputs:
+ *   snr[d][t]    = max over fitting widths (binary32); 0 if MAD_d = 0;
+ *   best_w[d][t] = index i of the smallest width attaining the maximum,
+ *                  0xFF if no width fits (then snr is 0).
+ *   Y:       device uint32 [ndm][nout] (the dedispersed plane).
+ *   widths:  host int32 [nw], 1 <= nw <= 64, strictly ascending, widths[0] >= 1,
+ *            widths[nw-1] <= nout (INVALID_ARG / RANGE otherwise).
+ *   snr:     device float [ndm][nout];  best_w: device uint8 [ndm][nout].
+ *   stats:   device int32 [ndm][2] receiving (med_d, MAD_d), or NULL.
+ * OVERFLOW if widths[nw-1] * 255 * nchan >= 2^31.  Asynchronous. */
+sps_status sps_boxcar_snr(sps_plan plan, const uint32_t *Y, int64_t nout,
+                          const int32_t *widths, int32_t nw, float *snr, uint8_t *best_w,
+                          int32_t *stats, void *stream);
+
+/* One detected candidate (Sec. 2: DM, TOA referenced to the top of the band,
+ * S/N, width). */
+typedef struct {
+  int32_t dm_idx; /* trial index d */
+  int32_t width;  /* boxcar width in samples, widths[best_w[d][t]] */
+  int64_t t_idx;  /* window start sample */
+  float snr;      /* S/N at (d, t) */
+  float reserved; /* 0 */
+  double dm;      /* trial DM value, pc cm^-3 */
+  double toa_s;   /* (t_idx + width / 2) * tsamp_s: window centre at f_ref */
+} sps_candidate;
+
+typedef struct {
+  float threshold; /* keep tile maxima with S/N >= threshold; must be > 0 */
+  int32_t tile_dm; /* tile height in DM trials, >= 1 */
+  int64_t tile_t;  /* tile length in samples, >= 1; tile_dm * tile_t < 2^32 */
+  int32_t nms_dm;  /* suppression radius in trials, >= 0 */
+  int64_t nms_t;   /* suppression radius in samples, >= 0 */
+} sps_detect_params;
+
+/* Candidate detection on a boxcar S/N plane.  The plane is cut into tiles of
+ * tile_dm x tile_t (the last ones ragged); each tile offers its maximum
+ * (ties: smallest t, then smallest d) if it reaches the threshold.  Offers
+ * are taken in order of S/N descending, then t, then d, and accepted unless
+ * an accepted one lies within |dd| <= nms_dm and |dt| <= nms_t.
+ *   snr, best_w: device planes as written by sps_boxcar_snr.
+ *   widths/nw:   the same host width list.
+ *   out:         host array of cap records (may be NULL when cap == 0),
+ *                receiving the first min(n, cap) accepted in that order.
+ *   n_found:     host, receives n, the number accepted.
+ * Returns SPS_ERR_TRUNCATED (after filling out) if n > cap.  RANGE if more
+ * than 8192 tiles reach the threshold (raise the threshold or the tile size).
+ * Synchronises the stream. */
+sps_status sps_detect(sps_plan plan, const float *snr, const uint8_t *best_w, int64_t nout,
+                      const int32_t *widths, int32_t nw, const sps_detect_params *params,
+                      sps_candidate *out, int32_t cap, int32_t *n_found, void *stream);
+
+/* Tiling of the dedispersion kernel (for tuning; sps_plan_create picks a
+ * default).  m: output dwords per lane (odd), dpw: trials per wave, nw: waves
+ * per workgroup, cs: channels per LDS slab.  m == 0 selects the plain
+ * global-memory kernel.  INVALID_ARG if the combination is not compiled in,
+ * RANGE if its LDS slab would exceed 160 KiB for this plan's delays. */
+sps_status sps_plan_set_tiling(sps_plan plan, int32_t m, int32_t dpw, int32_t nw, int32_t cs);
+sps_status sps_plan_get_tiling(sps_plan plan, int32_t *m, int32_t *dpw, int32_t *nw, int32_t *cs,
+                               int32_t *lds_bytes);
+
+/* Message for the last failed call on this thread ("" if none). */
+const char *sps_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPS_H */

@@ -1,0 +1,124 @@
+// boxcar.hip -- boxcar matched-filter S/N over the DM-time plane on gfx950.
+//
+// For every trial row and start sample t the window sums B_w(t) of all
+// requested widths come from one prefix sum P of the row segment held in LDS:
+// B_w(t) = P(t + w) - P(t).  P is kept in wrapping u32 arithmetic; every
+// window sum is below 2^31 (checked on the host), so the differences are
+// exact.  The S/N numerator B_w - w med is an exact integer; it is scaled by
+// 1 / (1.4826 MAD sqrt(w)) in binary32, and the maximum over widths (ties to
+// the smallest width) is written with the index of its width.
+//
+// One workgroup of 256 threads covers 4096 consecutive outputs of one row
+// plus a halo of w_max - 1 samples.  Lanes run along time, so the plane reads
+// and the S/N writes are fully coalesced and the LDS reads P[t + w] of a wave
+// are consecutive words (conflict-free).  HBM-bound: one read of Y, one write
+// of snr and best_w.
+#include "sps_internal.h"
+
+namespace sps {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kSeg = 4096;
+constexpr int kPer = kSeg / kThreads;
+
+__device__ uint32_t block_exclusive_scan256(uint32_t v, uint32_t *tmp /* >= 4 */) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t inc = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += y;
+  }
+  if (lane == 63) tmp[wave] = inc;
+  __syncthreads();
+  uint32_t off = 0;
+#pragma unroll
+  for (int w = 0; w < kThreads / 64; ++w) off += (w < wave) ? tmp[w] : 0u;
+  __syncthreads();
+  return off + inc - v;
+}
+
+__global__ __launch_bounds__(kThreads) void boxcar_kernel(
+    const uint32_t *__restrict__ Y, int64_t nout, int nseg, const int32_t *__restrict__ stats,
+    WidthList widths, float *__restrict__ snr, uint8_t *__restrict__ best) {
+  extern __shared__ uint32_t P[];  // [kSeg + w_max]
+  __shared__ float scale[kMaxWidths];
+  __shared__ uint32_t tmp[4];
+
+  const int64_t blk = blockIdx.x;
+  const int d = (int)(blk / nseg);
+  const int seg = (int)(blk - (int64_t)d * nseg);
+  const int64_t t0 = (int64_t)seg * kSeg;
+  const uint32_t *row = Y + (int64_t)d * nout;
+  const int nw = widths.n;
+  const int wmax = widths.w[nw - 1];
+  const int32_t med = stats[2 * (int64_t)d];
+  const int32_t mad = stats[2 * (int64_t)d + 1];
+
+  if (threadIdx.x < nw) {
+    const double w = (double)widths.w[threadIdx.x];
+    scale[threadIdx.x] = mad > 0 ? (float)(1.0 / (1.4826 * (double)mad * sqrt(w))) : 0.0f;
+  }
+
+  // Samples this segment needs: [t0, t0 + len), len <= kSeg + wmax - 1.
+  const int64_t avail = nout - t0;
+  const int len = (int)(avail < (int64_t)(kSeg + wmax - 1) ? avail : (int64_t)(kSeg + wmax - 1));
+  for (int i = threadIdx.x; i < len; i += kThreads) P[i + 1] = row[t0 + i];
+  __syncthreads();
+
+  // Exclusive prefix: each thread owns a contiguous chunk of ch samples.
+  const int ch = (len + kThreads - 1) / kThreads;
+  const int lo = threadIdx.x * ch;
+  const int hi = lo + ch < len ? lo + ch : len;
+  uint32_t part = 0;
+  for (int i = lo; i < hi; ++i) part += P[i + 1];
+  uint32_t run = block_exclusive_scan256(part, tmp);
+  for (int i = lo; i < hi; ++i) {
+    run += P[i + 1];
+    P[i + 1] = run;
+  }
+  if (threadIdx.x == 0) P[0] = 0u;
+  __syncthreads();
+
+  const int seg_len = avail < kSeg ? (int)avail : kSeg;
+  float *srow = snr + (int64_t)d * nout + t0;
+  uint8_t *brow = best + (int64_t)d * nout + t0;
+#pragma unroll 4
+  for (int m = 0; m < kPer; ++m) {
+    const int tl = threadIdx.x + kThreads * m;
+    if (tl >= seg_len) break;
+    const uint32_t p0 = P[tl];
+    const int64_t room = avail - tl;  // widths with w <= room fit
+    float bs = 0.0f;
+    int bi = 0xFF;
+    for (int i = 0; i < nw; ++i) {
+      const int w = widths.w[i];
+      if (w > room) break;
+      const int32_t num = (int32_t)(P[tl + w] - p0) - w * med;
+      const float s = mad > 0 ? (float)num * scale[i] : 0.0f;
+      if (bi == 0xFF || s > bs) {
+        bs = s;
+        bi = i;
+      }
+    }
+    srow[tl] = bi == 0xFF ? 0.0f : bs;
+    brow[tl] = (uint8_t)bi;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_boxcar(const uint32_t *Y, int ndm, int64_t nout, const int32_t *stats,
+                         const WidthList &widths, float *snr, uint8_t *best,
+                         hipStream_t stream) {
+  const int64_t nseg = (nout + kSeg - 1) / kSeg;
+  const int64_t grid = nseg * ndm;
+  if (grid > 0x7FFFFFFF || nseg > 0x7FFFFFFF) return hipErrorInvalidValue;
+  const size_t lds = (size_t)(kSeg + widths.w[widths.n - 1] + 1) * sizeof(uint32_t);
+  hipLaunchKernelGGL(boxcar_kernel, dim3((unsigned)grid), dim3(kThreads), lds, stream, Y, nout,
+                     (int)nseg, stats, widths, snr, best);
+  return hipGetLastError();
+}
+
+}  // namespace sps

@@ -1,0 +1,191 @@
+// detect.hip -- candidate detection on the boxcar S/N plane (gfx950).
+//
+// Stage 1 (tile_peaks_kernel): one workgroup per tile of tile_dm x tile_t
+// finds the tile's largest S/N.  Ties are broken towards the smallest t, then
+// the smallest d, by reducing a 64-bit key: the S/N's bits mapped to an
+// order-preserving unsigned integer in the high word, the complement of the
+// in-tile position t_local * tile_dm + d_local in the low word.
+// Stage 2 (select_nms_kernel): one workgroup gathers the peaks at or above
+// the threshold into LDS, sorts them (bitonic) by S/N descending, then t,
+// then d, and accepts them greedily unless an accepted one lies within the
+// suppression radius.  The candidate record carries DM, arrival time at the
+// top of the band, width and S/N (ASTROFLOW Sec. 2).
+#include <float.h>
+#include <limits.h>
+
+#include "sps_internal.h"
+
+namespace sps {
+namespace {
+
+constexpr int kTileThreads = 256;
+constexpr int kNmsThreads = 1024;
+
+__device__ __forceinline__ uint32_t ordered_bits(float v) {
+  const uint32_t u = __float_as_uint(v);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__device__ __forceinline__ uint64_t max_u64(uint64_t a, uint64_t b) { return a > b ? a : b; }
+
+__global__ __launch_bounds__(kTileThreads) void tile_peaks_kernel(
+    const float *__restrict__ snr, const uint8_t *__restrict__ best, int ndm, int64_t nout,
+    int tile_dm, int64_t tile_t, int64_t ntt, TilePeak *__restrict__ peaks) {
+  __shared__ uint64_t red[kTileThreads / 64];
+  const int64_t tile = blockIdx.x;
+  const int a = (int)(tile / ntt);
+  const int64_t b = tile - (int64_t)a * ntt;
+  const int d0 = a * tile_dm;
+  const int d1 = min(d0 + tile_dm, ndm);
+  const int64_t t0 = b * tile_t;
+  const int64_t t1 = t0 + tile_t < nout ? t0 + tile_t : nout;
+
+  uint64_t key = 0;
+  for (int d = d0; d < d1; ++d) {
+    const float *row = snr + (int64_t)d * nout;
+    for (int64_t t = t0 + threadIdx.x; t < t1; t += kTileThreads) {
+      const uint32_t pos = (uint32_t)((t - t0) * tile_dm + (d - d0));
+      const uint64_t k = ((uint64_t)ordered_bits(row[t]) << 32) | (uint64_t)(~pos);
+      key = max_u64(key, k);
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint32_t lo = __shfl_xor((uint32_t)key, o, 64);
+    const uint32_t hi = __shfl_xor((uint32_t)(key >> 32), o, 64);
+    key = max_u64(key, ((uint64_t)hi << 32) | lo);
+  }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = key;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kTileThreads / 64; ++w) key = max_u64(key, red[w]);
+    const uint32_t pos = ~(uint32_t)key;
+    int64_t tl = pos / (uint32_t)tile_dm;
+    int dl = (int)(pos - (uint32_t)tl * (uint32_t)tile_dm);
+    if (key == 0 || t0 + tl >= t1 || d0 + dl >= d1) {  // only if every value was NaN
+      tl = 0;
+      dl = 0;
+    }
+    const int d = d0 + dl;
+    const int64_t t = t0 + tl;
+    TilePeak p;
+    p.snr = snr[(int64_t)d * nout + t];
+    p.d = d;
+    p.t = (int32_t)t;
+    p.w = best[(int64_t)d * nout + t];
+    peaks[tile] = p;
+  }
+}
+
+// True if a comes before b: S/N descending, then t, then d.
+__device__ __forceinline__ bool before(const TilePeak &a, const TilePeak &b) {
+  if (a.snr != b.snr) return a.snr > b.snr;
+  if (a.t != b.t) return a.t < b.t;
+  return a.d < b.d;
+}
+
+__global__ __launch_bounds__(kNmsThreads) void select_nms_kernel(
+    const TilePeak *__restrict__ peaks, int64_t npeaks, float threshold, int nms_dm,
+    int64_t nms_t, TilePeak *__restrict__ out, int32_t *__restrict__ status) {
+  __shared__ TilePeak offer[kMaxOffers];
+  __shared__ uint16_t accepted[kMaxOffers];
+  __shared__ int count;
+  __shared__ int naccept;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    count = 0;
+    naccept = 0;
+  }
+  __syncthreads();
+  for (int64_t i = tid; i < npeaks; i += kNmsThreads) {
+    const TilePeak p = peaks[i];
+    if (p.snr >= threshold) {
+      const int slot = atomicAdd(&count, 1);
+      if (slot < kMaxOffers) offer[slot] = p;
+    }
+  }
+  __syncthreads();
+  const int n = count;
+  if (n > kMaxOffers) {
+    if (tid == 0) {
+      status[0] = n;
+      status[1] = 0;
+      status[2] = 1;
+    }
+    return;
+  }
+  int npow = 1;
+  while (npow < n) npow <<= 1;
+  for (int i = n + tid; i < npow; i += kNmsThreads) {
+    TilePeak s;
+    s.snr = -FLT_MAX;
+    s.d = INT_MAX;
+    s.t = INT_MAX;
+    s.w = 0xFF;
+    offer[i] = s;
+  }
+  __syncthreads();
+  // Bitonic sort of offer[0, npow) into "before" order.
+  for (int size = 2; size <= npow; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = tid; i < npow / 2; i += kNmsThreads) {
+        const int lo = 2 * i - (i & (stride - 1));
+        const int hi = lo + stride;
+        const bool up = (lo & size) == 0;
+        const TilePeak x = offer[lo], y = offer[hi];
+        if (up ? before(y, x) : before(x, y)) {
+          offer[lo] = y;
+          offer[hi] = x;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // Greedy suppression in order.
+  for (int i = 0; i < n; ++i) {
+    const TilePeak c = offer[i];
+    const int na = naccept;
+    bool near = false;
+    for (int j = tid; j < na; j += kNmsThreads) {
+      const TilePeak q = offer[accepted[j]];
+      const int64_t dd = (int64_t)c.d - q.d, dt = (int64_t)c.t - q.t;
+      if ((dd < 0 ? -dd : dd) <= nms_dm && (dt < 0 ? -dt : dt) <= nms_t) near = true;
+    }
+    const int any = __syncthreads_or(near);
+    if (!any && tid == 0) {
+      accepted[na] = (uint16_t)i;
+      naccept = na + 1;
+    }
+    __syncthreads();
+  }
+  const int na = naccept;
+  for (int j = tid; j < na; j += kNmsThreads) out[j] = offer[accepted[j]];
+  if (tid == 0) {
+    status[0] = n;
+    status[1] = na;
+    status[2] = 0;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_tile_peaks(const float *snr, const uint8_t *best, int ndm, int64_t nout,
+                             int tile_dm, int64_t tile_t, TilePeak *peaks,
+                             hipStream_t stream) {
+  const int64_t ntd = (ndm + tile_dm - 1) / tile_dm;
+  const int64_t ntt = (nout + tile_t - 1) / tile_t;
+  if (ntd * ntt > 0x7FFFFFFF) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(tile_peaks_kernel, dim3((unsigned)(ntd * ntt)), dim3(kTileThreads), 0,
+                     stream, snr, best, ndm, nout, tile_dm, tile_t, ntt, peaks);
+  return hipGetLastError();
+}
+
+hipError_t launch_select_nms(const TilePeak *peaks, int64_t npeaks, float threshold,
+                             int nms_dm, int64_t nms_t, TilePeak *out, int32_t *status,
+                             hipStream_t stream) {
+  hipLaunchKernelGGL(select_nms_kernel, dim3(1), dim3(kNmsThreads), 0, stream, peaks, npeaks,
+                     threshold, nms_dm, nms_t, out, status);
+  return hipGetLastError();
+}
+
+}  // namespace sps

@@ -1,0 +1,72 @@
+// sps_internal.h -- declarations shared by the HIP sources of libsps (not part
+// of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sps {
+
+// Tile configuration of the dedispersion kernel.
+//   m   : output dwords per lane (odd, so lane-strided LDS reads hit distinct
+//         banks); a wave covers 64 lanes x 4m samples = 256 m outputs.
+//   dpw : DM trials each wave accumulates at once.
+//   nw  : waves per workgroup; a workgroup covers nw * dpw trials.
+//   cs  : channels per LDS slab (even, divides 256).
+struct DedispConfig {
+  int m, dpw, nw, cs;
+  int nt() const { return 256 * m; }
+  int nd() const { return nw * dpw; }
+};
+
+// Bytes of one staged channel row for a config whose DM blocks span at most
+// `spread` samples of delay in any channel.
+int64_t dedisp_lds_pitch(const DedispConfig &cfg, int spread);
+
+// Largest delay difference within any block of nd consecutive trials.
+int dedisp_block_spread(const int32_t *delays_host, int nchan, int ndm, int nd);
+
+// True if the config is one the library instantiates.
+bool dedisp_config_supported(const DedispConfig &cfg);
+
+hipError_t launch_dedisperse(const DedispConfig &cfg, int lds_pitch, const uint8_t *X,
+                             int64_t pitch, int64_t nsamp_in, const int32_t *D, int nchan,
+                             int ndm, uint32_t *Y, int64_t nout, hipStream_t stream);
+
+hipError_t launch_row_stats(const uint32_t *Y, int ndm, int64_t nout, uint32_t vmax,
+                            int32_t *stats, hipStream_t stream);
+
+constexpr int kMaxWidths = 64;
+constexpr int kMaxWidth = 8192;
+
+struct WidthList {
+  int32_t n;
+  int32_t w[kMaxWidths];
+};
+
+hipError_t launch_boxcar(const uint32_t *Y, int ndm, int64_t nout, const int32_t *stats,
+                         const WidthList &widths, float *snr, uint8_t *best,
+                         hipStream_t stream);
+
+// Tile peak record written by the first detection kernel.
+struct TilePeak {
+  float snr;
+  int32_t d;
+  int32_t t;
+  int32_t w;
+};
+
+constexpr int kMaxOffers = 8192;
+
+hipError_t launch_tile_peaks(const float *snr, const uint8_t *best, int ndm, int64_t nout,
+                             int tile_dm, int64_t tile_t, TilePeak *peaks,
+                             hipStream_t stream);
+
+// Selects tile peaks >= threshold, orders them and applies greedy
+// suppression; writes accepted peaks (in order) to out and, to status[0..2]:
+// number of offers, number accepted, overflow flag.
+hipError_t launch_select_nms(const TilePeak *peaks, int64_t npeaks, float threshold,
+                             int nms_dm, int64_t nms_t, TilePeak *out, int32_t *status,
+                             hipStream_t stream);
+
+}  // namespace sps
