@@ -34,9 +34,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="full_scale_4096ch_2p20t_2048dm")
-    ap.add_argument("--cpu-rows", type=int, default=32,
+    ap.add_argument("--cpu-rows", type=int, default=128,
                     help="DM rows of the chunk the CPU oracle processes (0 = skip)")
-    ap.add_argument("--tiling", default="", help="m,dpw,nw,cs override of the dedispersion tiling")
+    ap.add_argument("--tiling", default="", help="m,dpw,nw,cs[,waves_per_eu] override of the dedispersion tiling")
     return ap.parse_args()
 
 

@@ -156,14 +156,16 @@ sps_status sps_detect(sps_plan plan, const float *snr, const uint8_t *best_w, in
                       const int32_t *widths, int32_t nw, const sps_detect_params *params,
                       sps_candidate *out, int32_t cap, int32_t *n_found, void *stream);
 
-/* Tiling of the dedispersion kernel (for tuning; sps_plan_create picks a
+/* Tiling of the dedispersion kernel, for tuning (sps_plan_create picks a
  * default).  m: output dwords per lane (odd), dpw: trials per wave, nw: waves
- * per workgroup, cs: channels per LDS slab.  m == 0 selects the plain
- * global-memory kernel.  INVALID_ARG if the combination is not compiled in,
- * RANGE if its LDS slab would exceed 160 KiB for this plan's delays. */
-sps_status sps_plan_set_tiling(sps_plan plan, int32_t m, int32_t dpw, int32_t nw, int32_t cs);
+ * per workgroup, cs: channels per LDS slab, waves_per_eu: register budget
+ * (0 = any compiled variant).  m == 0 selects the plain global-memory
+ * kernel.  INVALID_ARG if the combination is not compiled in, RANGE if its
+ * double-buffered LDS slab would exceed 160 KiB for this plan's delays. */
+sps_status sps_plan_set_tiling(sps_plan plan, int32_t m, int32_t dpw, int32_t nw, int32_t cs,
+                               int32_t waves_per_eu);
 sps_status sps_plan_get_tiling(sps_plan plan, int32_t *m, int32_t *dpw, int32_t *nw, int32_t *cs,
-                               int32_t *lds_bytes);
+                               int32_t *waves_per_eu, int32_t *lds_bytes);
 
 /* Message for the last failed call on this thread ("" if none). */
 const char *sps_last_error(void);

@@ -44,16 +44,17 @@ __device__ __forceinline__ uint32_t even_selector(int off) {
   return 0x0C000C00u | r | ((r + 2u) << 16);
 }
 
-// Adds two channels' windows (byte offsets offa, offb into staged rows r and
-// r + 1) into the packed accumulators of one trial.
+// Adds two channels' windows into the packed accumulators of one trial.  sa,
+// sb: uniform LDS dword offsets of the windows (row base + delay / 4); offa,
+// offb: the byte offsets, whose low two bits pick the perm selectors.
 template <int M>
 __device__ __forceinline__ void add_pair(uint32_t (&ev)[M], uint32_t (&od)[M],
-                                         const uint32_t *lds32, int row_dw, int lane, int r,
-                                         int offa, int offb) {
+                                         const uint32_t *lds32, int lane_m, int sa, int offa,
+                                         int sb, int offb) {
   const uint32_t sea = even_selector(offa), soa = sea + 0x00010001u;
   const uint32_t seb = even_selector(offb), sob = seb + 0x00010001u;
-  const uint32_t *pa = lds32 + r * row_dw + (offa >> 2) + lane * M;
-  const uint32_t *pb = lds32 + (r + 1) * row_dw + (offb >> 2) + lane * M;
+  const uint32_t *pa = lds32 + (lane_m + sa);
+  const uint32_t *pb = lds32 + (lane_m + sb);
   uint32_t wa[M + 1], wb[M + 1];
 #pragma unroll
   for (int j = 0; j <= M; ++j) {
@@ -69,10 +70,9 @@ __device__ __forceinline__ void add_pair(uint32_t (&ev)[M], uint32_t (&od)[M],
 
 template <int M>
 __device__ __forceinline__ void add_one(uint32_t (&ev)[M], uint32_t (&od)[M],
-                                        const uint32_t *lds32, int row_dw, int lane, int r,
-                                        int offa) {
+                                        const uint32_t *lds32, int lane_m, int sa, int offa) {
   const uint32_t sea = even_selector(offa), soa = sea + 0x00010001u;
-  const uint32_t *pa = lds32 + r * row_dw + (offa >> 2) + lane * M;
+  const uint32_t *pa = lds32 + (lane_m + sa);
   uint32_t wa[M + 1];
 #pragma unroll
   for (int j = 0; j <= M; ++j) wa[j] = pa[j];
@@ -83,16 +83,97 @@ __device__ __forceinline__ void add_one(uint32_t (&ev)[M], uint32_t (&od)[M],
   }
 }
 
-template <int M, int DPW, int NW, int CS>
-__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4))) void dedisperse_kernel(
-    const uint8_t *__restrict__ X, int64_t pitch, int64_t nsamp_in,
-    const int32_t *__restrict__ D, int nchan, int ndm, uint32_t *__restrict__ Y,
-    int64_t nout, int lds_pitch, int ntiles, int ndmb, int per_xcd, int vec_store) {
+template <int CS, int NW, int KMAX>
+struct SlabRegs {
+  static constexpr int RPW = CS / NW;
+  uint4 v[RPW][KMAX];
+};
+
+// Global -> registers for the slab starting at channel c0.  Rows whose whole
+// window lies below nsamp_in take a guard-free path; the others zero-fill
+// every byte at or past nsamp_in.
+template <int CS, int NW, int KMAX>
+__device__ __forceinline__ void slab_load(SlabRegs<CS, NW, KMAX> &st, const uint8_t *__restrict__ X,
+                                          int64_t pitch, int64_t nsamp_in,
+                                          const int32_t *__restrict__ Dlo, int c0, int ncs,
+                                          int64_t t0, int vpr, int wave, int lane) {
+#pragma unroll
+  for (int i = 0; i < SlabRegs<CS, NW, KMAX>::RPW; ++i) {
+    const int r = wave + NW * i;
+#pragma unroll
+    for (int u = 0; u < KMAX; ++u) st.v[i][u] = make_uint4(0u, 0u, 0u, 0u);
+    if (r < ncs) {
+      const int64_t base = t0 + (int64_t)(Dlo[c0 + r] & ~15);
+      const uint8_t *rowp = X + (int64_t)(c0 + r) * pitch;
+      if (base + 16 * (int64_t)vpr <= nsamp_in) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(rowp + base);
+#pragma unroll
+        for (int u = 0; u < KMAX; ++u) {
+          const int k = lane + 64 * u;
+          if (k < vpr) st.v[i][u] = src[k];
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < KMAX; ++u) {
+          const int k = lane + 64 * u;
+          const int64_t s0 = base + 16 * (int64_t)k;
+          if (k < vpr && s0 < nsamp_in) {
+            uint4 v = *reinterpret_cast<const uint4 *>(rowp + s0);
+            const int64_t nv = nsamp_in - s0;
+            if (nv < 16) {
+              uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                const int64_t keep = nv - 4 * q;
+                w4[q] = keep >= 4 ? w4[q]
+                                  : (keep <= 0 ? 0u : (w4[q] & ((1u << (8 * keep)) - 1u)));
+              }
+              v = make_uint4(w4[0], w4[1], w4[2], w4[3]);
+            }
+            st.v[i][u] = v;
+          }
+        }
+      }
+    }
+  }
+}
+
+template <int CS, int NW, int KMAX>
+__device__ __forceinline__ void slab_store(const SlabRegs<CS, NW, KMAX> &st, uint4 *buf, int ncs,
+                                           int vpr, int wave, int lane) {
+#pragma unroll
+  for (int i = 0; i < SlabRegs<CS, NW, KMAX>::RPW; ++i) {
+    const int r = wave + NW * i;
+    if (r < ncs) {
+#pragma unroll
+      for (int u = 0; u < KMAX; ++u) {
+        const int k = lane + 64 * u;
+        if (k < vpr) buf[r * vpr + k] = st.v[i][u];
+      }
+    }
+  }
+}
+
+// Uniform LDS dword offset of a (row, delay) pair, kept opaque so that the
+// compiler forms each lane address with one add instead of holding a
+// register per staged row.
+__device__ __forceinline__ int uniform_offset(int row_base_dw, int off) {
+  int s = row_base_dw + (off >> 2);
+  asm volatile("" : "+s"(s));
+  return s;
+}
+
+template <int M, int DPW, int NW, int CS, int KMAX, int WPE>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) void
+dedisperse_kernel(const uint8_t *__restrict__ X, int64_t pitch, int64_t nsamp_in,
+                  const int32_t *__restrict__ D, int nchan, int ndm, uint32_t *__restrict__ Y,
+                  int64_t nout, int lds_pitch, int ntiles, int ndmb, int per_xcd, int vec_store) {
   static_assert(M % 2 == 1, "lane stride must be odd for conflict-free LDS reads");
   static_assert(CS % 2 == 0 && 256 % CS == 0, "slab must be even and divide 256");
+  static_assert(CS % NW == 0, "every wave stages the same number of rows");
   constexpr int NT = 256 * M;
   constexpr int ND = NW * DPW;
-  extern __shared__ uint4 smem[];
+  extern __shared__ uint4 smem[];  // two slab buffers of CS rows x lds_pitch bytes
 
   const int blk = blockIdx.x;
   const int logical = (blk & 7) * per_xcd + (blk >> 3);
@@ -107,6 +188,8 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4))) vo
   const int dw0 = d_lo + wave * DPW;
   const int vpr = lds_pitch >> 4;
   const int row_dw = lds_pitch >> 2;
+  const int buf_dw = CS * row_dw;
+  const int lane_m = lane * M;
 
   uint32_t acc[DPW][M][4];
   uint32_t ev[DPW][M], od[DPW][M];
@@ -122,76 +205,51 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4))) vo
 
   const int32_t *Dlo = D + (int64_t)d_lo * nchan;
   const uint32_t *lds32 = reinterpret_cast<const uint32_t *>(smem);
+  SlabRegs<CS, NW, KMAX> st;
 
+  slab_load(st, X, pitch, nsamp_in, Dlo, 0, min(CS, nchan), t0, vpr, wave, lane);
+  slab_store(st, smem, min(CS, nchan), vpr, wave, lane);
+  __syncthreads();
+
+  int parity = 0;
   for (int c0 = 0; c0 < nchan; c0 += CS) {
     const int ncs = min(CS, nchan - c0);
-    __syncthreads();
-    // Stage the slab: wave w loads rows w, w + NW, ...
-    for (int r = wave; r < ncs; r += NW) {
-      const int64_t base = t0 + (int64_t)(Dlo[c0 + r] & ~15);
-      const uint8_t *rowp = X + (int64_t)(c0 + r) * pitch;
-      uint4 *dst = smem + r * vpr;
-      for (int k0 = 0; k0 < vpr; k0 += 256) {
-        uint4 v[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int k = k0 + lane + 64 * u;
-          const int64_t s0 = base + 16 * (int64_t)k;
-          v[u] = make_uint4(0u, 0u, 0u, 0u);
-          if (k < vpr && s0 < nsamp_in) {
-            v[u] = *reinterpret_cast<const uint4 *>(rowp + s0);
-            const int64_t nv = nsamp_in - s0;
-            if (nv < 16) {
-              uint32_t w4[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
-#pragma unroll
-              for (int q = 0; q < 4; ++q) {
-                const int64_t keep = nv - 4 * q;
-                w4[q] = keep >= 4 ? w4[q] : (keep <= 0 ? 0u : (w4[q] & ((1u << (8 * keep)) - 1u)));
-              }
-              v[u] = make_uint4(w4[0], w4[1], w4[2], w4[3]);
-            }
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int k = k0 + lane + 64 * u;
-          if (k < vpr) dst[k] = v[u];
-        }
-      }
-    }
-    __syncthreads();
+    const int c1 = c0 + CS;
+    const bool more = c1 < nchan;
+    const int ncs1 = more ? min(CS, nchan - c1) : 0;
+    if (more) slab_load(st, X, pitch, nsamp_in, Dlo, c1, ncs1, t0, vpr, wave, lane);
 
-    if (ncs == CS) {
-      // Full slab: delays of all CS channels are loaded to SGPRs up front and
-      // the channel loop is unrolled.
+    const int bo = parity * buf_dw;
 #pragma unroll
-      for (int k = 0; k < DPW; ++k) {
-        const int d = dw0 + k;
-        if (d < ndm) {
-          const int32_t *Dd = D + (int64_t)d * nchan + c0;
+    for (int k = 0; k < DPW; ++k) {
+      const int d = dw0 + k;
+      if (d < ndm) {
+        const int32_t *Dd = D + (int64_t)d * nchan + c0;
+        if (ncs == CS) {
 #pragma unroll
           for (int r = 0; r < CS; r += 2)
-            add_pair<M>(ev[k], od[k], lds32, row_dw, lane, r, Dd[r] - (Dlo[c0 + r] & ~15),
+            add_pair<M>(ev[k], od[k], lds32, lane_m,
+                        uniform_offset(bo + r * row_dw, Dd[r] - (Dlo[c0 + r] & ~15)),
+                        Dd[r] - (Dlo[c0 + r] & ~15),
+                        uniform_offset(bo + (r + 1) * row_dw, Dd[r + 1] - (Dlo[c0 + r + 1] & ~15)),
                         Dd[r + 1] - (Dlo[c0 + r + 1] & ~15));
-        }
-      }
-    } else {
-#pragma unroll
-      for (int k = 0; k < DPW; ++k) {
-        const int d = dw0 + k;
-        if (d < ndm) {
-          const int32_t *Dd = D + (int64_t)d * nchan + c0;
+        } else {
           int r = 0;
           for (; r + 1 < ncs; r += 2)
-            add_pair<M>(ev[k], od[k], lds32, row_dw, lane, r, Dd[r] - (Dlo[c0 + r] & ~15),
+            add_pair<M>(ev[k], od[k], lds32, lane_m,
+                        uniform_offset(bo + r * row_dw, Dd[r] - (Dlo[c0 + r] & ~15)),
+                        Dd[r] - (Dlo[c0 + r] & ~15),
+                        uniform_offset(bo + (r + 1) * row_dw, Dd[r + 1] - (Dlo[c0 + r + 1] & ~15)),
                         Dd[r + 1] - (Dlo[c0 + r + 1] & ~15));
           if (r < ncs)
-            add_one<M>(ev[k], od[k], lds32, row_dw, lane, r, Dd[r] - (Dlo[c0 + r] & ~15));
+            add_one<M>(ev[k], od[k], lds32, lane_m,
+                       uniform_offset(bo + r * row_dw, Dd[r] - (Dlo[c0 + r] & ~15)),
+                       Dd[r] - (Dlo[c0 + r] & ~15));
         }
       }
     }
 
-    if (((c0 + CS) & 255) == 0 || c0 + CS >= nchan) {
+    if ((c1 & 255) == 0 || !more) {
 #pragma unroll
       for (int k = 0; k < DPW; ++k)
 #pragma unroll
@@ -204,6 +262,9 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4))) vo
           od[k][j] = 0u;
         }
     }
+    if (more) slab_store(st, smem + (parity ^ 1) * (buf_dw >> 2), ncs1, vpr, wave, lane);
+    __syncthreads();
+    parity ^= 1;
   }
 
 #pragma unroll
@@ -250,29 +311,29 @@ __global__ __launch_bounds__(256) void dedisperse_direct_kernel(
   }
 }
 
-template <int M, int DPW, int NW, int CS>
+template <int M, int DPW, int NW, int CS, int KMAX, int WPE>
 hipError_t launch_cfg(int lds_pitch, const uint8_t *X, int64_t pitch, int64_t nsamp_in,
                       const int32_t *D, int nchan, int ndm, uint32_t *Y, int64_t nout,
                       hipStream_t stream) {
   constexpr int NT = 256 * M;
   constexpr int ND = NW * DPW;
+  if (lds_pitch > 16 * 64 * KMAX || lds_pitch % 16 != 0) return hipErrorInvalidValue;
   const int64_t ntiles64 = (nout + NT - 1) / NT;
   const int ndmb = (ndm + ND - 1) / ND;
   const int64_t total = ntiles64 * ndmb;
   if (total > (int64_t)0x7FFFFFFF - 8) return hipErrorInvalidValue;
   const int per_xcd = (int)((total + 7) / 8);
   const int grid = per_xcd * 8;
-  const size_t lds = (size_t)CS * (size_t)lds_pitch;
+  const size_t lds = 2 * (size_t)CS * (size_t)lds_pitch;
   const int vec_store = (nout % 4 == 0) && ((reinterpret_cast<uintptr_t>(Y) & 15) == 0);
+  auto kern = dedisperse_kernel<M, DPW, NW, CS, KMAX, WPE>;
   if (lds > 64 * 1024) {
-    const hipError_t e = hipFuncSetAttribute(
-        reinterpret_cast<const void *>(&dedisperse_kernel<M, DPW, NW, CS>),
-        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((dedisperse_kernel<M, DPW, NW, CS>), dim3(grid), dim3(NW * 64), lds, stream,
-                     X, pitch, nsamp_in, D, nchan, ndm, Y, nout, lds_pitch, (int)ntiles64, ndmb,
-                     per_xcd, vec_store);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(NW * 64), lds, stream, X, pitch, nsamp_in, D, nchan,
+                     ndm, Y, nout, lds_pitch, (int)ntiles64, ndmb, per_xcd, vec_store);
   return hipGetLastError();
 }
 
@@ -298,19 +359,24 @@ int dedisp_block_spread(const int32_t *Dh, int nchan, int ndm, int nd) {
   return spread;
 }
 
+// Compiled tilings: (m, dpw, nw, cs, kmax, waves per EU).  kmax bounds the
+// staged row length (lds_pitch <= 1024 kmax bytes).
 #define SPS_DEDISP_CONFIGS(X) \
-  X(5, 2, 8, 16)              \
-  X(3, 2, 8, 16)              \
-  X(7, 2, 8, 16)              \
-  X(5, 1, 8, 16)              \
-  X(5, 2, 4, 16)              \
-  X(3, 4, 4, 16)              \
-  X(5, 2, 8, 32)              \
-  X(3, 4, 8, 16)
+  X(5, 2, 8, 16, 2, 4)        \
+  X(5, 2, 8, 16, 4, 4)        \
+  X(5, 1, 16, 16, 2, 8)       \
+  X(5, 1, 16, 16, 2, 4)       \
+  X(5, 1, 16, 16, 4, 4)       \
+  X(3, 2, 8, 16, 2, 4)        \
+  X(3, 1, 16, 16, 2, 8)       \
+  X(7, 1, 16, 16, 3, 4)       \
+  X(5, 2, 16, 16, 2, 4)
 
 bool dedisp_config_supported(const DedispConfig &c) {
-#define SPS_MATCH(m_, dpw_, nw_, cs_) \
-  if (c.m == m_ && c.dpw == dpw_ && c.nw == nw_ && c.cs == cs_) return true;
+#define SPS_MATCH(m_, dpw_, nw_, cs_, kmax_, wpe_)                                      \
+  if (c.m == m_ && c.dpw == dpw_ && c.nw == nw_ && c.cs == cs_ && c.kmax == kmax_ && \
+      c.wpe == wpe_)                                                                  \
+    return true;
   SPS_DEDISP_CONFIGS(SPS_MATCH)
 #undef SPS_MATCH
   return false;
@@ -328,10 +394,11 @@ hipError_t launch_dedisperse(const DedispConfig &c, int lds_pitch, const uint8_t
                        stream, X, pitch, nsamp_in, D, nchan, ndm, Y, nout);
     return hipGetLastError();
   }
-#define SPS_LAUNCH(m_, dpw_, nw_, cs_)                                                    \
-  if (c.m == m_ && c.dpw == dpw_ && c.nw == nw_ && c.cs == cs_)                           \
-    return launch_cfg<m_, dpw_, nw_, cs_>(lds_pitch, X, pitch, nsamp_in, D, nchan, ndm, Y, \
-                                          nout, stream);
+#define SPS_LAUNCH(m_, dpw_, nw_, cs_, kmax_, wpe_)                                     \
+  if (c.m == m_ && c.dpw == dpw_ && c.nw == nw_ && c.cs == cs_ && c.kmax == kmax_ &&    \
+      c.wpe == wpe_)                                                                     \
+    return launch_cfg<m_, dpw_, nw_, cs_, kmax_, wpe_>(lds_pitch, X, pitch, nsamp_in, D, \
+                                                       nchan, ndm, Y, nout, stream);
   SPS_DEDISP_CONFIGS(SPS_LAUNCH)
 #undef SPS_LAUNCH
   return hipErrorInvalidValue;

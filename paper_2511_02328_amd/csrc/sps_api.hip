@@ -65,7 +65,7 @@ struct sps_plan_s {
   int32_t max_delay = 0;
   int32_t *d_delays = nullptr;
   int32_t *d_stats = nullptr;  // [ndm][2] used when the caller passes none
-  sps::DedispConfig cfg{5, 2, 8, 16};
+  sps::DedispConfig cfg{5, 1, 16, 16, 2, 8};
   int lds_pitch = 0;
   // detection scratch
   sps::TilePeak *d_peaks = nullptr;
@@ -86,24 +86,35 @@ void free_plan(sps_plan p) {
   delete p;
 }
 
-// Picks the first tiling, in order of preference, whose slab fits the LDS
-// budget (64 KiB keeps two workgroups per CU; up to 160 KiB is allowed for
-// the narrower ones); otherwise the plain global-memory kernel is used.
+// Compiled tilings in order of preference (see dedisperse.hip).
+const sps::DedispConfig kPrefs[] = {
+    {5, 1, 16, 16, 2, 8}, {5, 2, 8, 16, 2, 4}, {5, 1, 16, 16, 2, 4}, {5, 2, 16, 16, 2, 4},
+    {5, 2, 8, 16, 4, 4}, {5, 1, 16, 16, 4, 4}, {3, 2, 8, 16, 2, 4}, {3, 1, 16, 16, 2, 8},
+    {7, 1, 16, 16, 3, 4}};
+
+// Staged-row bytes of config c for this plan, or -1 if it does not fit.
+int64_t fitted_pitch(sps_plan p, const sps::DedispConfig &c, int64_t lds_budget) {
+  const int spread = sps::dedisp_block_spread(p->delays.data(), p->nchan, p->ndm, c.nd());
+  const int64_t pitch = sps::dedisp_lds_pitch(c, spread);
+  if (pitch > 1024 * (int64_t)c.kmax || c.lds_bytes(pitch) > lds_budget) return -1;
+  return pitch;
+}
+
+// Picks the first preferred tiling whose double-buffered slab fits the LDS
+// budget (64 KiB keeps two workgroups per CU; up to 160 KiB is allowed
+// next); otherwise the plain global-memory kernel is used.
 sps_status choose_tiling(sps_plan p) {
-  static const sps::DedispConfig prefs[] = {{5, 2, 8, 16}, {5, 2, 4, 16}, {5, 1, 8, 16},
-                                            {3, 2, 8, 16}};
   for (int64_t budget : {(int64_t)64 * 1024, (int64_t)160 * 1024}) {
-    for (const auto &c : prefs) {
-      const int spread = sps::dedisp_block_spread(p->delays.data(), p->nchan, p->ndm, c.nd());
-      const int64_t pitch = sps::dedisp_lds_pitch(c, spread);
-      if ((int64_t)c.cs * pitch <= budget) {
+    for (const auto &c : kPrefs) {
+      const int64_t pitch = fitted_pitch(p, c, budget);
+      if (pitch > 0) {
         p->cfg = c;
         p->lds_pitch = (int)pitch;
         return SPS_OK;
       }
     }
   }
-  p->cfg = sps::DedispConfig{0, 0, 0, 0};
+  p->cfg = sps::DedispConfig{0, 0, 0, 0, 0, 0};
   p->lds_pitch = 0;
   return SPS_OK;
 }
@@ -214,35 +225,44 @@ sps_status sps_plan_delays(sps_plan plan, int32_t *host_out, int32_t *max_delay)
   return SPS_OK;
 }
 
-sps_status sps_plan_set_tiling(sps_plan plan, int32_t m, int32_t dpw, int32_t nw, int32_t cs) {
+sps_status sps_plan_set_tiling(sps_plan plan, int32_t m, int32_t dpw, int32_t nw, int32_t cs,
+                               int32_t waves_per_eu) {
   g_error.clear();
   if (!plan) return fail(SPS_ERR_INVALID_ARG, "plan is NULL");
   if (m == 0) {
-    plan->cfg = sps::DedispConfig{0, 0, 0, 0};
+    plan->cfg = sps::DedispConfig{0, 0, 0, 0, 0, 0};
     plan->lds_pitch = 0;
     return SPS_OK;
   }
-  const sps::DedispConfig c{m, dpw, nw, cs};
-  if (!sps::dedisp_config_supported(c))
-    return fail(SPS_ERR_INVALID_ARG, "tiling (%d, %d, %d, %d) is not compiled in", m, dpw, nw, cs);
-  const int spread = sps::dedisp_block_spread(plan->delays.data(), plan->nchan, plan->ndm, c.nd());
-  const int64_t pitch = sps::dedisp_lds_pitch(c, spread);
-  if ((int64_t)cs * pitch > 160 * 1024)
-    return fail(SPS_ERR_RANGE, "tiling needs %lld bytes of LDS", (long long)(cs * pitch));
-  plan->cfg = c;
-  plan->lds_pitch = (int)pitch;
-  return SPS_OK;
+  bool known = false;
+  for (const auto &c : kPrefs) {
+    if (c.m != m || c.dpw != dpw || c.nw != nw || c.cs != cs) continue;
+    if (waves_per_eu != 0 && c.wpe != waves_per_eu) continue;
+    known = true;
+    const int64_t pitch = fitted_pitch(plan, c, 160 * 1024);
+    if (pitch > 0) {
+      plan->cfg = c;
+      plan->lds_pitch = (int)pitch;
+      return SPS_OK;
+    }
+  }
+  if (!known)
+    return fail(SPS_ERR_INVALID_ARG, "tiling (%d, %d, %d, %d, %d) is not compiled in", m, dpw, nw,
+                cs, waves_per_eu);
+  return fail(SPS_ERR_RANGE, "tiling (%d, %d, %d, %d) does not fit this plan's delay spread", m,
+              dpw, nw, cs);
 }
 
 sps_status sps_plan_get_tiling(sps_plan plan, int32_t *m, int32_t *dpw, int32_t *nw, int32_t *cs,
-                               int32_t *lds_bytes) {
+                               int32_t *waves_per_eu, int32_t *lds_bytes) {
   g_error.clear();
   if (!plan) return fail(SPS_ERR_INVALID_ARG, "plan is NULL");
   if (m) *m = plan->cfg.m;
   if (dpw) *dpw = plan->cfg.dpw;
   if (nw) *nw = plan->cfg.nw;
   if (cs) *cs = plan->cfg.cs;
-  if (lds_bytes) *lds_bytes = plan->cfg.cs * plan->lds_pitch;
+  if (waves_per_eu) *waves_per_eu = plan->cfg.wpe;
+  if (lds_bytes) *lds_bytes = (int32_t)plan->cfg.lds_bytes(plan->lds_pitch);
   return SPS_OK;
 }
 

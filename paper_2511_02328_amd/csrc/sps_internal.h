@@ -8,15 +8,19 @@
 namespace sps {
 
 // Tile configuration of the dedispersion kernel.
-//   m   : output dwords per lane (odd, so lane-strided LDS reads hit distinct
-//         banks); a wave covers 64 lanes x 4m samples = 256 m outputs.
-//   dpw : DM trials each wave accumulates at once.
-//   nw  : waves per workgroup; a workgroup covers nw * dpw trials.
-//   cs  : channels per LDS slab (even, divides 256).
+//   m    : output dwords per lane (odd, so lane-strided LDS reads hit distinct
+//          banks); a wave covers 64 lanes x 4m samples = 256 m outputs.
+//   dpw  : DM trials each wave accumulates at once.
+//   nw   : waves per workgroup; a workgroup covers nw * dpw trials.
+//   cs   : channels per LDS slab (even, divides 256, multiple of nw).
+//   kmax : 16-byte vectors per lane per staged row (row <= 1024 kmax bytes).
+//   wpe  : waves per SIMD the register budget is sized for.
+// m == 0 selects the plain global-memory kernel.
 struct DedispConfig {
-  int m, dpw, nw, cs;
+  int m, dpw, nw, cs, kmax, wpe;
   int nt() const { return 256 * m; }
   int nd() const { return nw * dpw; }
+  int64_t lds_bytes(int64_t pitch) const { return 2 * (int64_t)cs * pitch; }
 };
 
 // Bytes of one staged channel row for a config whose DM blocks span at most

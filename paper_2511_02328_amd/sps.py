@@ -69,8 +69,8 @@ def library() -> ctypes.CDLL:
         lib.sps_boxcar_snr.argtypes = [P, P, i64, P, i32, P, P, P, P]
         lib.sps_detect.argtypes = [P, P, P, i64, P, i32, ctypes.POINTER(sps_detect_params),
                                    ctypes.POINTER(sps_candidate), i32, ctypes.POINTER(i32), P]
-        lib.sps_plan_set_tiling.argtypes = [P, i32, i32, i32, i32]
-        lib.sps_plan_get_tiling.argtypes = [P] + [ctypes.POINTER(i32)] * 5
+        lib.sps_plan_set_tiling.argtypes = [P, i32, i32, i32, i32, i32]
+        lib.sps_plan_get_tiling.argtypes = [P] + [ctypes.POINTER(i32)] * 6
         for f in ("sps_plan_create", "sps_plan_destroy", "sps_plan_delays", "sps_dedisperse",
                   "sps_boxcar_snr", "sps_detect", "sps_plan_set_tiling", "sps_plan_get_tiling"):
             getattr(lib, f).restype = ctypes.c_int
@@ -160,15 +160,17 @@ def sps_plan_delays(plan: Plan):
     return D, int(mx.value)
 
 
-def sps_plan_set_tiling(plan: Plan, m: int, dpw: int, nw: int, cs: int) -> None:
-    _check(library().sps_plan_set_tiling(plan.handle, m, dpw, nw, cs), "sps_plan_set_tiling")
+def sps_plan_set_tiling(plan: Plan, m: int, dpw: int, nw: int, cs: int,
+                        waves_per_eu: int = 0) -> None:
+    _check(library().sps_plan_set_tiling(plan.handle, m, dpw, nw, cs, waves_per_eu),
+           "sps_plan_set_tiling")
 
 
 def sps_plan_get_tiling(plan: Plan) -> dict:
-    v = [ctypes.c_int32() for _ in range(5)]
+    v = [ctypes.c_int32() for _ in range(6)]
     _check(library().sps_plan_get_tiling(plan.handle, *[ctypes.byref(x) for x in v]),
            "sps_plan_get_tiling")
-    return dict(zip(("m", "dpw", "nw", "cs", "lds_bytes"), (x.value for x in v)))
+    return dict(zip(("m", "dpw", "nw", "cs", "waves_per_eu", "lds_bytes"), (x.value for x in v)))
 
 
 def sps_dedisperse(plan: Plan, X: torch.Tensor, nsamp_in: int, Y: torch.Tensor, nout: int,
