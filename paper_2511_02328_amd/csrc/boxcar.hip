@@ -13,6 +13,8 @@
 // and the S/N writes are fully coalesced and the LDS reads P[t + w] of a wave
 // are consecutive words (conflict-free).  HBM-bound: one read of Y, one write
 // of snr and best_w.
+#include <math.h>
+
 #include "sps_internal.h"
 
 namespace sps {
@@ -84,6 +86,36 @@ __global__ __launch_bounds__(kThreads) void boxcar_kernel(
   const int seg_len = avail < kSeg ? (int)avail : kSeg;
   float *srow = snr + (int64_t)d * nout + t0;
   uint8_t *brow = best + (int64_t)d * nout + t0;
+  const bool live = mad > 0;
+
+  if (avail >= (int64_t)(kSeg + wmax - 1)) {
+    // Every width fits at every output of this segment: no per-width guard.
+    // Widths, w * med and the scales are wave-uniform (kernel argument and
+    // LDS), so a width costs one v_add3 (numerator), cvt, mul, compare and
+    // two selects.
+#pragma unroll 2
+    for (int m = 0; m < kPer; ++m) {
+      const int tl = threadIdx.x + kThreads * m;
+      const uint32_t neg_p0 = 0u - P[tl];
+      float bs = -INFINITY;
+      int bi = 0;
+#pragma unroll
+      for (int i = 0; i < kMaxWidths; ++i) {
+        if (i >= nw) break;
+        const int w = widths.w[i];
+        const int32_t num = (int32_t)(P[tl + w] + neg_p0 - (uint32_t)(w * med));
+        const float s = (float)num * scale[i];
+        if (s > bs) {
+          bs = s;
+          bi = i;
+        }
+      }
+      srow[tl] = live ? bs : 0.0f;
+      brow[tl] = (uint8_t)bi;
+    }
+    return;
+  }
+
 #pragma unroll 4
   for (int m = 0; m < kPer; ++m) {
     const int tl = threadIdx.x + kThreads * m;
@@ -96,7 +128,7 @@ __global__ __launch_bounds__(kThreads) void boxcar_kernel(
       const int w = widths.w[i];
       if (w > room) break;
       const int32_t num = (int32_t)(P[tl + w] - p0) - w * med;
-      const float s = mad > 0 ? (float)num * scale[i] : 0.0f;
+      const float s = live ? (float)num * scale[i] : 0.0f;
       if (bi == 0xFF || s > bs) {
         bs = s;
         bi = i;

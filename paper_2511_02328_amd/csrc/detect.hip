@@ -84,13 +84,31 @@ __device__ __forceinline__ bool before(const TilePeak &a, const TilePeak &b) {
   return a.d < b.d;
 }
 
+__device__ __forceinline__ bool near(const TilePeak &a, const TilePeak &b, int nms_dm,
+                                     int64_t nms_t) {
+  const int64_t dd = (int64_t)a.d - b.d, dt = (int64_t)a.t - b.t;
+  return (dd < 0 ? -dd : dd) <= nms_dm && (dt < 0 ? -dt : dt) <= nms_t;
+}
+
+// Selection and greedy suppression in one workgroup.  Offers (tile peaks at
+// or above the threshold) are gathered into LDS and bitonic-sorted into
+// "before" order.  Greedy acceptance in that order has a unique result; when
+// the suppression radius spans few tiles it is computed in parallel rounds:
+// an offer is rejected once an accepted, earlier, nearby offer exists, and
+// accepted once every earlier nearby offer is rejected.  Each round decides
+// at least the earliest undecided offer, and decisions are final, so reading
+// neighbours' states while they change is safe.  Otherwise the offers are
+// scanned one by one.
 __global__ __launch_bounds__(kNmsThreads) void select_nms_kernel(
-    const TilePeak *__restrict__ peaks, int64_t npeaks, float threshold, int nms_dm,
-    int64_t nms_t, TilePeak *__restrict__ out, int32_t *__restrict__ status) {
+    const TilePeak *__restrict__ peaks, int64_t npeaks, int ntd, int64_t ntt, int tile_dm,
+    int64_t tile_t, float threshold, int nms_dm, int64_t nms_t, TilePeak *__restrict__ out,
+    int32_t *__restrict__ status) {
   __shared__ TilePeak offer[kMaxOffers];
-  __shared__ uint16_t accepted[kMaxOffers];
+  __shared__ int16_t aux[kMaxOffers];  // tile -> offer rank, or the accepted list
+  __shared__ uint8_t state[kMaxOffers];  // 0 undecided, 1 accepted, 2 rejected
   __shared__ int count;
   __shared__ int naccept;
+  __shared__ uint32_t tmp[kNmsThreads / 64];
   const int tid = threadIdx.x;
   if (tid == 0) {
     count = 0;
@@ -125,7 +143,6 @@ __global__ __launch_bounds__(kNmsThreads) void select_nms_kernel(
     offer[i] = s;
   }
   __syncthreads();
-  // Bitonic sort of offer[0, npow) into "before" order.
   for (int size = 2; size <= npow; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
       for (int i = tid; i < npow / 2; i += kNmsThreads) {
@@ -141,28 +158,94 @@ __global__ __launch_bounds__(kNmsThreads) void select_nms_kernel(
       __syncthreads();
     }
   }
-  // Greedy suppression in order.
-  for (int i = 0; i < n; ++i) {
-    const TilePeak c = offer[i];
-    const int na = naccept;
-    bool near = false;
-    for (int j = tid; j < na; j += kNmsThreads) {
-      const TilePeak q = offer[accepted[j]];
-      const int64_t dd = (int64_t)c.d - q.d, dt = (int64_t)c.t - q.t;
-      if ((dd < 0 ? -dd : dd) <= nms_dm && (dt < 0 ? -dt : dt) <= nms_t) near = true;
-    }
-    const int any = __syncthreads_or(near);
-    if (!any && tid == 0) {
-      accepted[na] = (uint16_t)i;
-      naccept = na + 1;
+
+  const int span_d = (nms_dm + tile_dm - 1) / tile_dm;
+  const int64_t span_t = (nms_t + tile_t - 1) / tile_t;
+  const bool grid = npeaks <= kMaxOffers && (2 * span_d + 1) * (2 * span_t + 1) <= 49;
+  if (grid) {
+    for (int i = tid; i < (int)npeaks; i += kNmsThreads) aux[i] = -1;
+    for (int i = tid; i < n; i += kNmsThreads) state[i] = 0;
+    __syncthreads();
+    for (int i = tid; i < n; i += kNmsThreads) {
+      const TilePeak c = offer[i];
+      aux[(int64_t)(c.d / tile_dm) * ntt + c.t / tile_t] = (int16_t)i;
     }
     __syncthreads();
+    int undecided = 1;
+    while (undecided) {
+      int mine = 0;
+      for (int i = tid; i < n; i += kNmsThreads) {
+        if (state[i] != 0) continue;
+        const TilePeak c = offer[i];
+        const int a = c.d / tile_dm;
+        const int64_t b = c.t / tile_t;
+        bool blocked = false, rejected = false;
+        for (int da = -span_d; da <= span_d && !rejected; ++da) {
+          const int aa = a + da;
+          if (aa < 0 || aa >= ntd) continue;
+          for (int64_t db = -span_t; db <= span_t; ++db) {
+            const int64_t bb = b + db;
+            if (bb < 0 || bb >= ntt) continue;
+            const int j = aux[(int64_t)aa * ntt + bb];
+            if (j < 0 || j >= i) continue;
+            if (!near(c, offer[j], nms_dm, nms_t)) continue;
+            const uint8_t sj = *(volatile uint8_t *)&state[j];
+            if (sj == 1) {
+              rejected = true;
+              break;
+            }
+            if (sj == 0) blocked = true;
+          }
+        }
+        if (rejected)
+          state[i] = 2;
+        else if (!blocked)
+          state[i] = 1;
+        else
+          mine = 1;
+      }
+      undecided = __syncthreads_or(mine);
+    }
+    // Accepted offers in order: block-wide exclusive scan of per-thread counts
+    // over contiguous runs.
+    const int per = (n + kNmsThreads - 1) / kNmsThreads;
+    const int lo = tid * per, hi = min(lo + per, n);
+    uint32_t cnt = 0;
+    for (int i = lo; i < hi; ++i) cnt += state[i] == 1;
+    const int lane = tid & 63, wave = tid >> 6;
+    uint32_t inc = cnt;
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += y;
+    }
+    if (lane == 63) tmp[wave] = inc;
+    __syncthreads();
+    uint32_t pos = inc - cnt;
+    for (int w = 0; w < wave; ++w) pos += tmp[w];
+    for (int i = lo; i < hi; ++i)
+      if (state[i] == 1) out[pos++] = offer[i];
+    if (tid == kNmsThreads - 1) naccept = (int)pos;
+    __syncthreads();
+  } else {
+    for (int i = 0; i < n; ++i) {
+      const TilePeak c = offer[i];
+      const int na = naccept;
+      bool hit = false;
+      for (int j = tid; j < na; j += kNmsThreads)
+        if (near(c, offer[(uint16_t)aux[j]], nms_dm, nms_t)) hit = true;
+      const int any = __syncthreads_or(hit);
+      if (!any && tid == 0) {
+        aux[na] = (int16_t)i;
+        naccept = na + 1;
+      }
+      __syncthreads();
+    }
+    const int na = naccept;
+    for (int j = tid; j < na; j += kNmsThreads) out[j] = offer[(uint16_t)aux[j]];
   }
-  const int na = naccept;
-  for (int j = tid; j < na; j += kNmsThreads) out[j] = offer[accepted[j]];
   if (tid == 0) {
     status[0] = n;
-    status[1] = na;
+    status[1] = naccept;
     status[2] = 0;
   }
 }
@@ -180,11 +263,14 @@ hipError_t launch_tile_peaks(const float *snr, const uint8_t *best, int ndm, int
   return hipGetLastError();
 }
 
-hipError_t launch_select_nms(const TilePeak *peaks, int64_t npeaks, float threshold,
-                             int nms_dm, int64_t nms_t, TilePeak *out, int32_t *status,
-                             hipStream_t stream) {
-  hipLaunchKernelGGL(select_nms_kernel, dim3(1), dim3(kNmsThreads), 0, stream, peaks, npeaks,
-                     threshold, nms_dm, nms_t, out, status);
+hipError_t launch_select_nms(const TilePeak *peaks, int ndm, int64_t nout, int tile_dm,
+                             int64_t tile_t, float threshold, int nms_dm, int64_t nms_t,
+                             TilePeak *out, int32_t *status, hipStream_t stream) {
+  const int ntd = (ndm + tile_dm - 1) / tile_dm;
+  const int64_t ntt = (nout + tile_t - 1) / tile_t;
+  hipLaunchKernelGGL(select_nms_kernel, dim3(1), dim3(kNmsThreads), 0, stream, peaks,
+                     (int64_t)ntd * ntt, ntd, ntt, tile_dm, tile_t, threshold, nms_dm, nms_t, out,
+                     status);
   return hipGetLastError();
 }
 

@@ -3,19 +3,20 @@
 // The boxcar S/N is normalised by each dedispersed row's median and median
 // absolute deviation (sigma = 1.4826 MAD).  Both are order statistics of
 // integers no larger than 255 * nchan (< 2^24 for nchan <= 65536), so they
-// are found exactly by a two-level radix selection: a 4096-bin histogram of
-// the high bits locates the bin holding rank floor((n-1)/2), a second
-// histogram of the low bits inside that bin gives the value.  The same two
-// passes over |Y - med| give the MAD.  One workgroup of 1024 threads owns a
-// row; histograms live in LDS; the row is streamed with 16-byte loads when
-// its start is 16-byte aligned.
+// are found exactly from histograms: a 4096-bin histogram of the high bits
+// locates the bin holding rank floor((n-1)/2) and bounds the MAD; one exact
+// histogram over a window of values around that bin then yields both the
+// median and the MAD, in two reads of the row.  One workgroup of 1024
+// threads owns a row; histograms live in LDS (LDS atomics); the row is
+// streamed with 16-byte loads when its start is 16-byte aligned.
 #include "sps_internal.h"
 
 namespace sps {
 namespace {
 
 constexpr int kThreads = 1024;
-constexpr int kBins = 4096;
+constexpr int kBins = 4096;             // coarse histogram
+constexpr int kFine = 16384;            // exact window histogram (64 KiB of LDS)
 constexpr int kPerThread = kBins / kThreads;
 
 // Exclusive scan of one value per thread across the workgroup.
@@ -68,6 +69,30 @@ __device__ void locate_rank(const uint32_t *hist, uint32_t k, uint32_t *tmp, uin
   __syncthreads();
 }
 
+// As locate_rank over hist[0, n) for any n <= kFine: each thread owns a
+// contiguous run of ceil(n / kThreads) bins.
+__device__ void locate_rank_n(const uint32_t *hist, int n, uint32_t k, uint32_t *tmp,
+                              uint32_t *out) {
+  const int per = (n + kThreads - 1) / kThreads;
+  const int lo = threadIdx.x * per;
+  const int hi = min(lo + per, n);
+  uint32_t part = 0;
+  for (int i = lo; i < hi; ++i) part += hist[i];
+  uint32_t below = block_exclusive_scan(part, tmp);
+  if (k >= below && k < below + part) {
+    for (int i = lo; i < hi; ++i) {
+      const uint32_t h = hist[i];
+      if (k < below + h) {
+        out[0] = (uint32_t)i;
+        out[1] = below;
+        break;
+      }
+      below += h;
+    }
+  }
+  __syncthreads();
+}
+
 template <typename F>
 __device__ __forceinline__ void for_each_value(const uint32_t *row, int64_t n, bool vec, F f) {
   if (vec) {
@@ -89,24 +114,114 @@ __device__ __forceinline__ void for_each_value(const uint32_t *row, int64_t n, b
 __global__ __launch_bounds__(kThreads) void row_stats_kernel(const uint32_t *__restrict__ Y,
                                                              int64_t nout, int shift,
                                                              int32_t *__restrict__ stats) {
-  __shared__ uint32_t hist[kBins];
+  // Pass 1: histogram of the high bits (4096 bins of width 2^shift) gives the
+  // bin b holding the median and, from the counts around b, a bound on the
+  // MAD.  Pass 2: an exact histogram of the values in the window of coarse
+  // bins [b - r - 1, b + r + 1] gives the median and then the MAD, whose
+  // deviations all fall inside the window.  Rows whose window would not fit
+  // in LDS fall back to two more passes over |Y - med|.
+  __shared__ uint32_t hist[kFine];
   __shared__ uint32_t tmp[16];
   __shared__ uint32_t sel[2];
+  __shared__ int radius;
   const int d = blockIdx.x;
   const uint32_t *row = Y + (int64_t)d * nout;
   const bool vec = ((reinterpret_cast<uintptr_t>(row) & 15) == 0);
   const uint32_t k = (uint32_t)((nout - 1) / 2);
-  const uint32_t fmask = (1u << shift) - 1u;
-  uint32_t result[2];
+  const uint32_t width = 1u << shift;
 
-  uint32_t med = 0;
-  for (int pass = 0; pass < 2; ++pass) {  // pass 0: median of Y; pass 1: of |Y - med|
-    const uint32_t m = med;
-    const bool dev = pass == 1;
+  for (int i = threadIdx.x; i < kBins; i += kThreads) hist[i] = 0u;
+  __syncthreads();
+  for_each_value(row, nout, vec, [&](uint32_t v) {
+    atomicAdd(&hist[min(v >> shift, (uint32_t)(kBins - 1))], 1u);
+  });
+  __syncthreads();
+  locate_rank(hist, k, tmp, sel);
+  const int b = (int)sel[0];
+  const uint32_t below_b = sel[1];
+  // Smallest r with at least k + 1 values in bins [b - r, b + r]: then every
+  // |v - med| up to the MAD is at most (r + 1) 2^shift - 1.
+  if (threadIdx.x == 0) {
+    uint32_t cnt = hist[b];
+    int r = 0;
+    while (cnt < k + 1) {
+      ++r;
+      if (b - r >= 0) cnt += hist[b - r];
+      if (b + r < kBins) cnt += hist[b + r];
+    }
+    radius = r;
+  }
+  __syncthreads();
+  const int r = radius;
+  const int lo_bin = max(b - r - 1, 0);
+  const int hi_bin = min(b + r + 1, kBins - 1);
+  const int64_t nwin = (int64_t)(hi_bin - lo_bin + 1) << shift;
+  uint32_t below_lo = 0;
+  if (nwin <= kFine) {
+    // values below the window, from the coarse histogram
+    if (threadIdx.x == 0) {
+      uint32_t c = below_b;
+      for (int j = lo_bin; j < b; ++j) c -= hist[j];
+      sel[0] = c;
+    }
+    __syncthreads();
+    below_lo = sel[0];
+  }
+  __syncthreads();
+
+  uint32_t med, mad;
+  if (nwin <= kFine) {
+    const uint32_t lo = (uint32_t)lo_bin << shift;
+    for (int i = threadIdx.x; i < kFine; i += kThreads) hist[i] = 0u;
+    __syncthreads();
+    for_each_value(row, nout, vec, [&](uint32_t v) {
+      const uint32_t x = v - lo;
+      if (v >= lo && x < (uint32_t)nwin) atomicAdd(&hist[x], 1u);
+    });
+    __syncthreads();
+    locate_rank_n(hist, (int)nwin, k - below_lo, tmp, sel);
+    const uint32_t mloc = sel[0];  // median - lo
+    med = lo + mloc;
+    __syncthreads();
+    // deviation histogram: dev[m] = #(|v - med| == m) for m < mspan, formed
+    // in place after the window histogram is read into registers
+    const int mspan = (int)((uint32_t)(r + 1) << shift);
+    // count(|v - med| <= m) >= k + 1 first happens at m = MAD <= mspan - 1.
+    uint32_t devc[kFine / kThreads];
+#pragma unroll
+    for (int q = 0; q < kFine / kThreads; ++q) {
+      const int m = threadIdx.x + kThreads * q;
+      uint32_t c = 0;
+      if (m < mspan) {
+        const int64_t a = (int64_t)mloc - m, z = (int64_t)mloc + m;
+        if (a >= 0 && a < nwin) c += hist[a];
+        if (m > 0 && z >= 0 && z < nwin) c += hist[z];
+      }
+      devc[q] = c;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kFine / kThreads; ++q) hist[threadIdx.x + kThreads * q] = devc[q];
+    __syncthreads();
+    locate_rank_n(hist, mspan, k, tmp, sel);
+    mad = sel[0];
+  } else {
+    // Wide row: radix selection of the median's low bits, then of |Y - med|.
+    const uint32_t fmask = width - 1u;
     for (int i = threadIdx.x; i < kBins; i += kThreads) hist[i] = 0u;
     __syncthreads();
     for_each_value(row, nout, vec, [&](uint32_t v) {
-      const uint32_t x = dev ? (v >= m ? v - m : m - v) : v;
+      if ((v >> shift) == (uint32_t)b) atomicAdd(&hist[v & fmask], 1u);
+    });
+    __syncthreads();
+    locate_rank(hist, k - below_b, tmp, sel);
+    med = ((uint32_t)b << shift) | sel[0];
+    __syncthreads();
+    for (int i = threadIdx.x; i < kBins; i += kThreads) hist[i] = 0u;
+    __syncthreads();
+    const uint32_t m0 = med;
+    for_each_value(row, nout, vec, [&](uint32_t v) {
+      const uint32_t x = v >= m0 ? v - m0 : m0 - v;
       atomicAdd(&hist[min(x >> shift, (uint32_t)(kBins - 1))], 1u);
     });
     __syncthreads();
@@ -116,18 +231,16 @@ __global__ __launch_bounds__(kThreads) void row_stats_kernel(const uint32_t *__r
     for (int i = threadIdx.x; i < kBins; i += kThreads) hist[i] = 0u;
     __syncthreads();
     for_each_value(row, nout, vec, [&](uint32_t v) {
-      const uint32_t x = dev ? (v >= m ? v - m : m - v) : v;
+      const uint32_t x = v >= m0 ? v - m0 : m0 - v;
       if ((x >> shift) == hb) atomicAdd(&hist[x & fmask], 1u);
     });
     __syncthreads();
     locate_rank(hist, rank_in, tmp, sel);
-    result[pass] = (hb << shift) | sel[0];
-    med = result[0];
-    __syncthreads();
+    mad = (hb << shift) | sel[0];
   }
   if (threadIdx.x == 0) {
-    stats[2 * (int64_t)d] = (int32_t)result[0];
-    stats[2 * (int64_t)d + 1] = (int32_t)result[1];
+    stats[2 * (int64_t)d] = (int32_t)med;
+    stats[2 * (int64_t)d + 1] = (int32_t)mad;
   }
 }
 

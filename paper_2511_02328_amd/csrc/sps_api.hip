@@ -369,8 +369,9 @@ sps_status sps_detect(sps_plan plan, const float *snr, const uint8_t *best_w, in
   e = sps::launch_tile_peaks(snr, best_w, plan->ndm, nout, prm->tile_dm, prm->tile_t,
                              plan->d_peaks, s);
   if (e != hipSuccess) return hip_fail(e, "tile peak launch");
-  e = sps::launch_select_nms(plan->d_peaks, ntiles, prm->threshold, prm->nms_dm, prm->nms_t,
-                             plan->d_accepted, plan->d_status, s);
+  e = sps::launch_select_nms(plan->d_peaks, plan->ndm, nout, prm->tile_dm, prm->tile_t,
+                             prm->threshold, prm->nms_dm, prm->nms_t, plan->d_accepted,
+                             plan->d_status, s);
   if (e != hipSuccess) return hip_fail(e, "selection launch");
   int32_t status[4] = {0, 0, 0, 0};
   e = hipMemcpyAsync(status, plan->d_status, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, s);

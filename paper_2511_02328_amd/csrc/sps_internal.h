@@ -69,8 +69,8 @@ hipError_t launch_tile_peaks(const float *snr, const uint8_t *best, int ndm, int
 // Selects tile peaks >= threshold, orders them and applies greedy
 // suppression; writes accepted peaks (in order) to out and, to status[0..2]:
 // number of offers, number accepted, overflow flag.
-hipError_t launch_select_nms(const TilePeak *peaks, int64_t npeaks, float threshold,
-                             int nms_dm, int64_t nms_t, TilePeak *out, int32_t *status,
-                             hipStream_t stream);
+hipError_t launch_select_nms(const TilePeak *peaks, int ndm, int64_t nout, int tile_dm,
+                             int64_t tile_t, float threshold, int nms_dm, int64_t nms_t,
+                             TilePeak *out, int32_t *status, hipStream_t stream);
 
 }  // namespace sps

@@ -251,3 +251,51 @@ def test_argument_errors(sps):
         with pytest.raises(sps.SpsError) as ei:
             sps.sps_dedisperse(plan, X, 40000, Y, 64, flags=2)
         assert ei.value.name == "SPS_ERR_INVALID_ARG"
+
+
+@pytest.mark.parametrize("radius", [(1, 1), (2, 3), (10, 10)])
+def test_detect_dense_chains(sps, radius):
+    # one offer per element: long suppression chains; (10, 10) forces the
+    # one-by-one scan, the others the parallel rounds
+    rng = np.random.Generator(np.random.PCG64(sum(radius)))
+    ndm, nout = 40, 200
+    snr = (10 + rng.standard_normal((ndm, nout))).astype(np.float32)
+    snr[5, 5:60] = 20.0 - np.arange(55, dtype=np.float32) * 0.1  # a ridge of decreasing peaks
+    best = np.zeros((ndm, nout), np.uint8)
+    rd, rt = radius
+    co = oracle.detect(snr, best, 8.0, 1, 1, rd, rt, cap=100000)
+    wl = Workload("d", 8, 1000.0, 1500.0, 1e-4, nout, ndm, 0.0, 10.0, (1,))
+    with sps.plan_for(wl) as plan:
+        cands, n = sps.sps_detect(plan, torch.from_numpy(snr).cuda(), torch.from_numpy(best).cuda(),
+                                  nout, [1], 8.0, 1, 1, rd, rt, cap=8192)
+    assert n == co["n_found"]
+    assert np.array_equal(cands["dm_idx"], co["d"]) and np.array_equal(cands["t_idx"], co["t"])
+
+
+@pytest.mark.parametrize("case", ["noise", "narrow", "near_zero", "near_top", "spiky"])
+def test_stats_windowed_rows(sps, case):
+    rng = np.random.Generator(np.random.PCG64(len(case)))
+    nchan, ndm, nout = 4096, 6, 50000
+    vmax = 255 * nchan
+    if case == "noise":
+        Y = rng.normal(524288, 1024, (ndm, nout))
+    elif case == "narrow":
+        Y = rng.normal(300000, 3, (ndm, nout))
+    elif case == "near_zero":
+        Y = np.abs(rng.normal(0, 700, (ndm, nout)))
+    elif case == "near_top":
+        Y = vmax - np.abs(rng.normal(0, 900, (ndm, nout)))
+    else:
+        Y = rng.normal(500000, 800, (ndm, nout))
+        Y[:, ::7] += rng.uniform(0, 200000, Y[:, ::7].shape)
+    Y = np.clip(np.rint(Y), 0, vmax).astype(np.uint32)
+    sto = oracle.stats(Y)
+    wl = Workload("s", nchan, 1000.0, 1500.0, 1e-4, nout, ndm, 0.0, 1.0, (1, 2, 4))
+    with sps.plan_for(wl) as plan:
+        snr = torch.empty((ndm, nout), dtype=torch.float32, device="cuda")
+        best = torch.empty((ndm, nout), dtype=torch.uint8, device="cuda")
+        st = torch.empty((ndm, 2), dtype=torch.int32, device="cuda")
+        sps.sps_boxcar_snr(plan, torch.from_numpy(Y.view(np.int32)).cuda(), nout, [1, 2, 4], snr,
+                           best, st)
+        torch.cuda.synchronize()
+        assert np.array_equal(st.cpu().numpy().astype(np.int64), sto)
