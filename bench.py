@@ -28,6 +28,26 @@ if ROOT not in sys.path:
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
 
+def measured_traffic(wl):
+    """Calibrated HBM bytes per dedispersion launch from the committed counter
+    summary, if it was taken on this workload and on the current kernel
+    source; otherwise None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "full_scale_path_counters.txt")
+    src = os.path.join(ROOT, "paper_2511_02328_amd", "csrc", "dedisperse.hip")
+    if wl.name != "full_scale_4096ch_2p20t_2048dm" or not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if vals.get("dedisperse_source_sha256_16") != sha:
+        return None
+    return float(vals["dedisperse_hbm_bytes_calibrated"])
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -37,6 +57,9 @@ def parse():
     ap.add_argument("--cpu-rows", type=int, default=128,
                     help="DM rows of the chunk the CPU oracle processes (0 = skip)")
     ap.add_argument("--tiling", default="", help="m,dpw,nw,cs[,waves_per_eu] override of the dedispersion tiling")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one device-to-device copy of this many MiB first (reference "
+                         "dispatch for scaling hardware byte counters)")
     return ap.parse_args()
 
 
@@ -86,6 +109,14 @@ def main():
             ev[3].record(stream)
         return cands, n
 
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib << 20
+        a = torch.ones(n, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        print(f"[bench] calibration copy of {args.copy_calibration_mib} MiB done", flush=True)
     torch.cuda.synchronize()
     print(f"[bench] warmup {args.warmup}", flush=True)
     for _ in range(args.warmup):
@@ -133,7 +164,9 @@ def main():
         "candidates": n,
         "roofline": {"kernel": "dedisperse_kernel", "bound": "alu", "achieved": achieved,
                      "peak": ALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / ALU_PEAK_TOPS,
-                     "traffic": None,
+                     "traffic": measured_traffic(wl),
+                     "traffic_unit": "bytes per launch (FETCH_SIZE x2.0 + WRITE_SIZE x1.0, "
+                                     "scaled by a 1 GiB copy)",
                      "work_per_launch": f"{adds} sample-adds (ndm x nout x nchan)"},
     }
 
