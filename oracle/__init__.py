@@ -18,6 +18,12 @@ names the passage of the paper it follows:
   fields from Sec. 2 (DM, TOA referenced to the top of the band, S/N, width).
 * :func:`row_checksums` -- per-row sums of the dedispersed plane from
   per-channel prefix sums (a property that holds at any size).
+* :func:`subband_residuals`, :func:`subband_dedisperse` -- the paper's
+  two-stage subband method, Sec. 2.3, Eq. (coarse_delay), Eq. (stage1),
+  Eq. (residual), Eq. (stage2).
+* :func:`zero_dm` -- the zero-DM filter cited in Sec. 2.1 (formula read as
+  channel-mean subtraction, stated in the C source).
+* :func:`downsample_sqrt` -- square-law downsampling, Sec. 2.2.
 
 Every function here is pinned by tests against values the paper and the
 mathematics fix (closed forms, exact rational arithmetic, brute force on tiny
@@ -54,8 +60,15 @@ def _load():
                                           i32, P, P, P, P, P]
         lib.sps_oracle_row_checksums.argtypes = [i32, P, i64, i64, i32, P, i64, P]
         lib.sps_oracle_threads.argtypes = []
+        lib.sps_oracle_subband_residuals.argtypes = [i32, P, f64, f64, i32, P, i32, f64, f64,
+                                                     i32, P, P, P]
+        lib.sps_oracle_subband_dedisperse.argtypes = [i32, P, i64, i64, i32, P, i32, P, i32, i32,
+                                                      P, i64, P]
+        lib.sps_oracle_zero_dm.argtypes = [i32, P, i64, i64, P, i64]
+        lib.sps_oracle_downsample_sqrt.argtypes = [i32, P, i64, i64, i32, P, i64]
         for name in ("delays", "dedisperse", "stats", "boxcar", "detect",
-                     "row_checksums", "threads"):
+                     "row_checksums", "threads", "subband_residuals", "subband_dedisperse",
+                     "zero_dm", "downsample_sqrt"):
             getattr(lib, "sps_oracle_" + name).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -170,3 +183,58 @@ def pipeline(X: np.ndarray, D: np.ndarray, nout: int, widths, nsamp_in=None):
     st = stats(Y)
     snr, best = boxcar(Y, st, widths)
     return Y, st, snr, best
+
+
+def equal_subbands(nchan: int, nsub: int) -> np.ndarray:
+    """Subband boundaries [nsub + 1]: contiguous, sizes differing by at most one."""
+    return np.array([(s * nchan) // nsub for s in range(nsub + 1)], dtype=np.int32)
+
+
+def subband_residuals(freq_mhz, fref_mhz: float, tsamp_s: float, sub, ndm: int, dm_lo: float,
+                      ddm: float, n0: int):
+    """(R int32 [ndm][nsub], F_s [nsub], coarse DMs [ceil(ndm/n0)]); Eq. (residual)."""
+    f = np.ascontiguousarray(freq_mhz, dtype=np.float64)
+    sb = np.ascontiguousarray(sub, dtype=np.int32)
+    nsub = sb.size - 1
+    R = np.empty((ndm, nsub), dtype=np.int32)
+    F = np.empty(nsub, dtype=np.float64)
+    dmc = np.empty((ndm + n0 - 1) // n0, dtype=np.float64)
+    _check(_load().sps_oracle_subband_residuals(f.size, _ptr(f), float(fref_mhz), float(tsamp_s),
+                                                nsub, _ptr(sb), int(ndm), float(dm_lo), float(ddm),
+                                                int(n0), _ptr(R), _ptr(F), _ptr(dmc)),
+           "subband_residuals")
+    return R, F, dmc
+
+
+def subband_dedisperse(X: np.ndarray, Dc: np.ndarray, sub, R: np.ndarray, n0: int, nout: int,
+                       nsamp_in=None) -> np.ndarray:
+    """Two-stage subband dedispersion, Eq. (stage1) + Eq. (stage2) (uint32 [ndm][nout])."""
+    X, pitch, n = _x_layout(X, nsamp_in)
+    Dc = np.ascontiguousarray(Dc, dtype=np.int32)
+    sb = np.ascontiguousarray(sub, dtype=np.int32)
+    R = np.ascontiguousarray(R, dtype=np.int32)
+    Y = np.empty((R.shape[0], int(nout)), dtype=np.uint32)
+    _check(_load().sps_oracle_subband_dedisperse(X.shape[0], _ptr(X), pitch, n, Dc.shape[0],
+                                                 _ptr(Dc), sb.size - 1, _ptr(sb), R.shape[0],
+                                                 int(n0), _ptr(R), int(nout), _ptr(Y)),
+           "subband_dedisperse")
+    return Y
+
+
+def zero_dm(X: np.ndarray, nsamp=None) -> np.ndarray:
+    """Zero-DM filtered copy of X[:, :nsamp] (uint8)."""
+    X, pitch, n = _x_layout(X, nsamp)
+    out = np.zeros((X.shape[0], n), dtype=np.uint8)
+    _check(_load().sps_oracle_zero_dm(X.shape[0], _ptr(X), pitch, n, _ptr(out), max(n, 1) if n else 0),
+           "zero_dm")
+    return out
+
+
+def downsample_sqrt(X: np.ndarray, factor: int, nsamp=None) -> np.ndarray:
+    """Square-law downsampled copy (uint8 [nchan][nsamp // factor])."""
+    X, pitch, n = _x_layout(X, nsamp)
+    nout = n // int(factor)
+    out = np.zeros((X.shape[0], max(nout, 1)), dtype=np.uint8)
+    _check(_load().sps_oracle_downsample_sqrt(X.shape[0], _ptr(X), pitch, n, int(factor),
+                                              _ptr(out), max(nout, 1)), "downsample_sqrt")
+    return out[:, :nout]

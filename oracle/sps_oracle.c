@@ -355,3 +355,154 @@ int sps_oracle_threads(void) {
   return 1;
 #endif
 }
+
+/* ---------------------------------------------------------------------------
+ * The paper's own dedispersion (Sec. 2.3): two-stage subband method, and the
+ * pre-dedispersion steps of Sec. 2.1 / Sec. 2.2.
+ * ------------------------------------------------------------------------- */
+
+/*
+ * Residual shift table of Eq. (residual).  Fine grid DM_m = dm_lo + m*ddm,
+ * coarse grid DM_j = dm_lo + j*n0*ddm, j(m) = floor(m / n0), and
+ * dDM_m = DM_m - DM_j(m).  Subband s holds channels [sub[s], sub[s+1]) and is
+ * represented by F_s with 1/F_s^2 = mean of 1/f_c^2 over its channels (the
+ * "1/f^2-weighted centre").  R[m][s] = floor(K dDM_m / t_samp (1/F_s^2 -
+ * 1/f_ref^2) + 1/2).  F (optional) receives F_s.  Coarse DMs are returned in
+ * dm_coarse[ceil(ndm / n0)] (optional).
+ */
+int sps_oracle_subband_residuals(int32_t nchan, const double *freq_mhz, double fref_mhz,
+                                 double tsamp_s, int32_t nsub, const int32_t *sub,
+                                 int32_t ndm, double dm_lo, double ddm, int32_t n0,
+                                 int32_t *R, double *F, double *dm_coarse) {
+  if (nchan <= 0 || nsub <= 0 || ndm <= 0 || n0 <= 0 || !freq_mhz || !sub || !R)
+    return ORACLE_EINVAL;
+  if (!(tsamp_s > 0.0) || !(ddm >= 0.0) || !(dm_lo >= 0.0)) return ORACLE_EINVAL;
+  if (sub[0] != 0 || sub[nsub] != nchan) return ORACLE_EINVAL;
+  for (int32_t s = 0; s < nsub; ++s)
+    if (sub[s + 1] <= sub[s]) return ORACLE_EINVAL;
+  for (int32_t c = 0; c < nchan; ++c)
+    if (!(freq_mhz[c] > 0.0) || freq_mhz[c] > fref_mhz) return ORACLE_EINVAL;
+  int32_t ncoarse = (ndm + n0 - 1) / n0;
+  if (dm_coarse)
+    for (int32_t j = 0; j < ncoarse; ++j) dm_coarse[j] = dm_lo + (double)j * (double)n0 * ddm;
+  for (int32_t s = 0; s < nsub; ++s) {
+    double acc = 0.0;
+    for (int32_t c = sub[s]; c < sub[s + 1]; ++c) acc += 1.0 / (freq_mhz[c] * freq_mhz[c]);
+    double inv_f2 = acc / (double)(sub[s + 1] - sub[s]);
+    if (F) F[s] = 1.0 / sqrt(inv_f2);
+    double k = inv_f2 - 1.0 / (fref_mhz * fref_mhz);
+    for (int32_t m = 0; m < ndm; ++m) {
+      double dm_m = dm_lo + (double)m * ddm;
+      double dm_j = dm_lo + (double)((m / n0) * n0) * ddm;
+      double x = (ORACLE_K_DM * (dm_m - dm_j) / tsamp_s) * k;
+      double r = floor(x + 0.5);
+      if (r > 2147483647.0 || r < 0.0) return ORACLE_EOVERFLOW;
+      R[(int64_t)m * nsub + s] = (int32_t)r;
+    }
+  }
+  return ORACLE_OK;
+}
+
+/*
+ * Two-stage subband dedispersion, Eq. (stage1) and Eq. (stage2), without
+ * time blocking (blocking with the overlap of Eq. L1 gives the same values).
+ *   Stage 1: I[j][s][u] = sum_{c in s} X[c][u + Dc[j][c]], zero past nsamp_in,
+ *            for u in [0, nout + max R).
+ *   Stage 2: Y[m][t] = sum_s I[j(m)][s][t + R[m][s]].
+ * Dc is the coarse-grid delay table [ncoarse][nchan] (from
+ * sps_oracle_delays on the coarse DMs).
+ */
+int sps_oracle_subband_dedisperse(int32_t nchan, const uint8_t *X, int64_t pitch,
+                                  int64_t nsamp_in, int32_t ncoarse, const int32_t *Dc,
+                                  int32_t nsub, const int32_t *sub, int32_t ndm, int32_t n0,
+                                  const int32_t *R, int64_t nout, uint32_t *Y) {
+  if (nchan <= 0 || ncoarse <= 0 || nsub <= 0 || ndm <= 0 || n0 <= 0 || nout < 0 ||
+      !X || !Dc || !sub || !R || !Y || pitch < nsamp_in || (ndm + n0 - 1) / n0 > ncoarse)
+    return ORACLE_EINVAL;
+  int32_t rmax = 0;
+  for (int64_t i = 0; i < (int64_t)ndm * nsub; ++i)
+    if (R[i] > rmax) rmax = R[i];
+  int64_t len = nout + rmax;
+  uint64_t *I = (uint64_t *)calloc((size_t)ncoarse * nsub * (size_t)(len > 0 ? len : 1), sizeof(uint64_t));
+  if (!I) return ORACLE_ENOMEM;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int32_t j = 0; j < ncoarse; ++j) {
+    for (int32_t s = 0; s < nsub; ++s) {
+      uint64_t *row = I + ((int64_t)j * nsub + s) * len;
+      for (int32_t c = sub[s]; c < sub[s + 1]; ++c) {
+        const uint8_t *x = X + (int64_t)c * pitch;
+        int64_t shift = Dc[(int64_t)j * nchan + c];
+        for (int64_t u = 0; u < len; ++u)
+          if (u + shift < nsamp_in) row[u] += x[u + shift];
+      }
+    }
+  }
+  int err = ORACLE_OK;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int32_t m = 0; m < ndm; ++m) {
+    int32_t j = m / n0;
+    for (int64_t t = 0; t < nout; ++t) {
+      uint64_t acc = 0;
+      for (int32_t s = 0; s < nsub; ++s)
+        acc += I[((int64_t)j * nsub + s) * len + t + R[(int64_t)m * nsub + s]];
+      if (acc > 0xFFFFFFFFull) {
+#pragma omp atomic write
+        err = ORACLE_EOVERFLOW;
+      }
+      Y[(int64_t)m * nout + t] = (uint32_t)acc;
+    }
+  }
+  free(I);
+  return err;
+}
+
+/*
+ * Zero-DM filter (cited in Sec. 2.1; the paper gives no formula): subtract
+ * from every channel the DM = 0 series, the channel mean at each sample,
+ * m(t) = floor((sum_c X[c][t] + nchan/2) / nchan), and restore the 8-bit
+ * mid-level: X'[c][t] = clip(X[c][t] - m(t) + 128, 0, 255).
+ */
+int sps_oracle_zero_dm(int32_t nchan, const uint8_t *X, int64_t pitch, int64_t nsamp,
+                       uint8_t *Xo, int64_t pitch_out) {
+  if (nchan <= 0 || nsamp < 0 || !X || !Xo || pitch < nsamp || pitch_out < nsamp)
+    return ORACLE_EINVAL;
+  for (int64_t t = 0; t < nsamp; ++t) {
+    int64_t sum = 0;
+    for (int32_t c = 0; c < nchan; ++c) sum += X[(int64_t)c * pitch + t];
+    int64_t m = (sum + nchan / 2) / nchan;
+    for (int32_t c = 0; c < nchan; ++c) {
+      int64_t v = (int64_t)X[(int64_t)c * pitch + t] - m + 128;
+      Xo[(int64_t)c * pitch_out + t] = (uint8_t)(v < 0 ? 0 : (v > 255 ? 255 : v));
+    }
+  }
+  return ORACLE_OK;
+}
+
+/*
+ * Square-law downsampling, Sec. 2.2:
+ *   out = min{ V sqrt(S) / sqrt(N V), V } = min{ sqrt(V S / N), V },
+ * S the sum of the N samples of a bin, V = 255, rounded half up to an
+ * integer.  Bins are the full ones, t in [0, floor(nsamp / N)).  The rounding
+ * is settled exactly in integers: r is the value with
+ * (2r - 1)^2 N <= 4 V S < (2r + 1)^2 N.
+ */
+int sps_oracle_downsample_sqrt(int32_t nchan, const uint8_t *X, int64_t pitch, int64_t nsamp,
+                               int32_t factor, uint8_t *Xo, int64_t pitch_out) {
+  if (nchan <= 0 || nsamp < 0 || factor <= 0 || !X || !Xo || pitch < nsamp)
+    return ORACLE_EINVAL;
+  const int64_t V = 255;
+  int64_t nout = nsamp / factor;
+  if (pitch_out < nout) return ORACLE_EINVAL;
+  for (int32_t c = 0; c < nchan; ++c) {
+    for (int64_t t = 0; t < nout; ++t) {
+      int64_t S = 0;
+      for (int32_t k = 0; k < factor; ++k) S += X[(int64_t)c * pitch + t * factor + k];
+      int64_t r = (int64_t)floor(sqrt((double)V * (double)S / (double)factor) + 0.5);
+      while ((2 * r + 1) * (2 * r + 1) * (int64_t)factor <= 4 * V * S) ++r;
+      while (r > 0 && (2 * r - 1) * (2 * r - 1) * (int64_t)factor > 4 * V * S) --r;
+      if (r > V) r = V;
+      Xo[(int64_t)c * pitch_out + t] = (uint8_t)r;
+    }
+  }
+  return ORACLE_OK;
+}

@@ -11,7 +11,7 @@ from oracle.build import SRC, build
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 PIN_FILES = ["test_oracle_delays.py", "test_oracle_dedisperse.py",
-             "test_oracle_stats_boxcar.py", "test_oracle_detect.py"]
+             "test_oracle_stats_boxcar.py", "test_oracle_detect.py", "test_oracle_subband.py"]
 
 MUTATIONS = {
     "truncate_instead_of_round": ("floor(x + 0.5)", "floor(x)"),
@@ -29,6 +29,14 @@ MUTATIONS = {
     "strict_nms_radius": ("if (dd <= nms_dm && dt <= nms_t)", "if (dd < nms_dm && dt <= nms_t)"),
     "order_ignores_t": ("if (p->t != q->t) return p->t < q->t ? -1 : 1;", ""),
     "checksum_no_clamp": ("if (hi > nsamp_in) hi = nsamp_in;", ""),
+    "residual_full_dm": ("(ORACLE_K_DM * (dm_m - dm_j) / tsamp_s)", "(ORACLE_K_DM * dm_m / tsamp_s)"),
+    "subband_top_channel_centre": ("double inv_f2 = acc / (double)(sub[s + 1] - sub[s]);",
+                                   "double inv_f2 = 1.0 / (freq_mhz[sub[s]] * freq_mhz[sub[s]]);"),
+    "stage2_wrong_subband": ("t + R[(int64_t)m * nsub + s]]", "t + R[(int64_t)m * nsub + (nsub - 1 - s)]]"),
+    "stage1_no_bounds": ("if (u + shift < nsamp_in) row[u]", "if (u + shift <= nsamp_in) row[u]"),
+    "zero_dm_truncating_mean": ("(sum + nchan / 2) / nchan", "sum / nchan"),
+    "downsample_ties_down": ("while (r > 0 && (2 * r - 1) * (2 * r - 1) * (int64_t)factor > 4 * V * S) --r;",
+                             "while (r > 0 && (2 * r - 1) * (2 * r - 1) * (int64_t)factor >= 4 * V * S) --r;"),
 }
 
 
