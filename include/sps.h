@@ -167,6 +167,124 @@ sps_status sps_plan_set_tiling(sps_plan plan, int32_t m, int32_t dpw, int32_t nw
 sps_status sps_plan_get_tiling(sps_plan plan, int32_t *m, int32_t *dpw, int32_t *nw, int32_t *cs,
                                int32_t *waves_per_eu, int32_t *lds_bytes);
 
+/* ---- The paper's own dedispersion (Sec. 2.3) and pre-processing (Sec. 2.1-2.2) ---- */
+
+/* Subband (two-stage) plan.  Fine grid DM_m = dm_lo + m dm_step (m < ndm),
+ * coarse grid DM_j = dm_lo + j n0 dm_step.  Channels are split into nsub
+ * contiguous subbands, subband s holding channels
+ * [floor(s nchan / nsub), floor((s + 1) nchan / nsub)), represented by F_s
+ * with 1/F_s^2 the mean of 1/f^2 over its channels (the paper allows "a
+ * 1/f^2-weighted centre").  The plan is a superset of sps_plan_create's
+ * (its fine delay table serves sps_dedisperse too) and adds:
+ *   coarse delays  D_jc = round((K DM_j / t_samp)(1/f_c^2 - 1/f_ref^2))   Eq. (coarse_delay)
+ *   residuals      R_ms = round((K (DM_m - DM_j(m)) / t_samp)(1/F_s^2 - 1/f_ref^2)),
+ *                  j(m) = floor(m / n0)                                    Eq. (residual)
+ * (round = half up).  INVALID_ARG / OVERFLOW as sps_plan_create, plus
+ * n0 < 1, nsub outside [1, nchan], negative or non-finite DMs. */
+typedef struct {
+  int32_t nchan;
+  const double *freq_mhz; /* host [nchan] channel centres, each in (0, fref_mhz]; copied */
+  double fref_mhz;
+  double tsamp_s;
+  int32_t ndm;    /* fine trials */
+  double dm_lo;   /* first trial DM */
+  double dm_step; /* fine DM step */
+  int32_t n0;     /* coarse step = n0 fine steps */
+  int32_t nsub;   /* number of subbands */
+} sps_subband_desc;
+sps_status sps_subband_plan_create(const sps_subband_desc *desc, sps_plan *out);
+
+/* Host copies of the subband tables: coarse_delays [ceil(ndm/n0)][nchan],
+ * residuals [ndm][nsub], fsub [nsub] (MHz); each may be NULL.  *max_delay
+ * receives the largest effective delay D_j(m)c + R_m,s(c). */
+sps_status sps_subband_tables(sps_plan plan, int32_t *coarse_delays, int32_t *residuals,
+                              double *fsub, int32_t *max_delay);
+
+/* Two-stage subband dedispersion (Eq. stage1, Eq. stage2):
+ *   I[j][s][u] = sum_{c in s} X[c][u + D_jc],  Y[m][t] = sum_s I[j(m)][s][t + R_ms],
+ * samples past nsamp_in counting zero.  Equals brute force with the
+ * effective delays D_j(m)c + R_m,s(c), and brute force itself when n0 = 1.
+ * Arguments and flags as sps_dedisperse, with the effective max delay in the
+ * strict-mode check.  The plan allocates nsub x ceil(ndm/n0) x (nout + max
+ * R) x 4 bytes of device scratch on first use (and grows it).  Asynchronous. */
+sps_status sps_dedisperse_subband(sps_plan plan, const uint8_t *X, int64_t pitch,
+                                  int64_t nsamp_in, uint32_t *Y, int64_t nout, uint32_t flags,
+                                  void *stream);
+
+/* Zero-DM filter (Sec. 2.1 cites it; no formula is given).  Read as
+ * subtraction of the DM = 0 series, the channel mean at each sample rounded
+ * half up, m(t) = floor((sum_c X[c][t] + nchan/2) / nchan), about the 8-bit
+ * mid-level:  Xo[c][t] = clip(X[c][t] - m(t) + 128, 0, 255).
+ * X, Xo: device uint8 [nchan][pitch] / [nchan][pitch_out], 16-byte aligned,
+ * pitches multiples of 16; Xo may equal X.  Asynchronous. */
+sps_status sps_zero_dm(const uint8_t *X, int64_t pitch, int64_t nsamp, int32_t nchan, uint8_t *Xo,
+                       int64_t pitch_out, void *stream);
+
+/* Square-law downsampling by an integer factor N (Sec. 2.2):
+ *   Xo[c][t] = min{ 255 sqrt(S) / sqrt(255 N), 255 },  S = sum_{k<N} X[c][tN + k],
+ * rounded half up (exactly, in integers), for the full bins t < nsamp / N.
+ * X: device uint8 [nchan][pitch]; Xo: device uint8 [nchan][pitch_out],
+ * pitch_out >= nsamp / N.  1 <= nchan <= 65535.  Asynchronous. */
+sps_status sps_downsample_sqrt(const uint8_t *X, int64_t pitch, int64_t nsamp, int32_t nchan,
+                               int32_t factor, uint8_t *Xo, int64_t pitch_out, void *stream);
+
+/* ---- Many filterbanks sharing one plan (beams of one receiver) ---- */
+
+/* One filterbank of a batch and its outputs (all device pointers, caller-owned;
+ * layouts as in sps_dedisperse / sps_boxcar_snr).  Beams may have different
+ * lengths (nout, nsamp_in). */
+typedef struct {
+  const uint8_t *X; /* [nchan][pitch], 16-byte aligned, pitch % 16 == 0 */
+  int64_t pitch;
+  int64_t nsamp_in;
+  uint32_t *Y;      /* [ndm][nout] */
+  int64_t nout;     /* >= largest width */
+  float *snr;       /* [ndm][nout] */
+  uint8_t *best_w;  /* [ndm][nout] */
+  int32_t *stats;   /* [ndm][2] */
+} sps_beam;
+
+typedef struct sps_batch_s *sps_batch;
+
+/* Fixes a batch: validates every beam as the single-filterbank calls would,
+ * uploads the work description and allocates all scratch, so that running
+ * the batch allocates nothing and never waits on the host.  The plan's
+ * current tiling is used (call sps_plan_autotune / sps_plan_set_tiling
+ * first); the plan must outlive the batch.  RANGE if a beam has more than
+ * 8192 detection tiles or the plan needs the plain kernel. */
+sps_status sps_batch_create(sps_plan plan, int32_t nbeams, const sps_beam *beams,
+                            const int32_t *widths, int32_t nw, const sps_detect_params *params,
+                            uint32_t flags, sps_batch *out);
+sps_status sps_batch_destroy(sps_batch batch);
+
+/* Enqueues the whole search for every beam: one persistent dedispersion
+ * launch over all (beam, time tile, DM block) items, then batched row
+ * statistics, boxcar S/N and detection (4 + 1 launches in total).  Makes no
+ * allocation and no host synchronisation, so it may be captured into a HIP
+ * graph.  Asynchronous. */
+sps_status sps_batch_enqueue(sps_batch batch, void *stream);
+
+/* As sps_batch_enqueue, replayed from a HIP graph captured on the first call
+ * (and re-captured if the stream changes).  stream must not be NULL. */
+sps_status sps_batch_launch_graph(sps_batch batch, void *stream);
+
+/* Synchronises the stream and returns beam's candidates as sps_detect does
+ * (same order, TRUNCATED / RANGE rules). */
+sps_status sps_batch_candidates(sps_batch batch, int32_t beam, sps_candidate *out, int32_t cap,
+                                int32_t *n_found, void *stream);
+
+/* Autotuner: times every compiled dedispersion tiling that fits the plan on
+ * a probe of nout_probe output samples (iters timed runs each, HIP events,
+ * after one warm-up) and keeps the fastest.  ms_out (optional) receives the
+ * mean time per tiling index (-1 for tilings that do not fit), see
+ * sps_tiling_describe; *n_tried the number timed.  Allocates and frees its
+ * probe buffers; synchronises the stream. */
+sps_status sps_plan_autotune(sps_plan plan, int64_t nout_probe, int32_t iters, void *stream,
+                             float *ms_out, int32_t *n_tried);
+int32_t sps_tiling_count(void);
+sps_status sps_tiling_describe(int32_t index, int32_t *m, int32_t *dpw, int32_t *nw, int32_t *cs,
+                               int32_t *waves_per_eu);
+
 /* Message for the last failed call on this thread ("" if none). */
 const char *sps_last_error(void);
 

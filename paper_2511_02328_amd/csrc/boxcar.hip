@@ -41,16 +41,15 @@ __device__ uint32_t block_exclusive_scan256(uint32_t v, uint32_t *tmp /* >= 4 */
   return off + inc - v;
 }
 
-__global__ __launch_bounds__(kThreads) void boxcar_kernel(
-    const uint32_t *__restrict__ Y, int64_t nout, int nseg, const int32_t *__restrict__ stats,
-    WidthList widths, float *__restrict__ snr, uint8_t *__restrict__ best) {
-  extern __shared__ uint32_t P[];  // [kSeg + w_max]
+// NPOW > 0: the widths are exactly 1, 2, 4, ..., 2^(NPOW-1), so window
+// offsets are immediates of the LDS reads and width indices are constants.
+template <int NPOW>
+__device__ __forceinline__ void boxcar_segment(const uint32_t *__restrict__ Y, int64_t nout, int d,
+                                               int seg, const int32_t *__restrict__ stats,
+                                               const WidthList &widths, float *__restrict__ snr,
+                                               uint8_t *__restrict__ best, uint32_t *P) {
   __shared__ float scale[kMaxWidths];
   __shared__ uint32_t tmp[4];
-
-  const int64_t blk = blockIdx.x;
-  const int d = (int)(blk / nseg);
-  const int seg = (int)(blk - (int64_t)d * nseg);
   const int64_t t0 = (int64_t)seg * kSeg;
   const uint32_t *row = Y + (int64_t)d * nout;
   const int nw = widths.n;
@@ -87,6 +86,32 @@ __global__ __launch_bounds__(kThreads) void boxcar_kernel(
   float *srow = snr + (int64_t)d * nout + t0;
   uint8_t *brow = best + (int64_t)d * nout + t0;
   const bool live = mad > 0;
+
+  if (NPOW > 0 && avail >= (int64_t)(kSeg + wmax - 1)) {
+    float sc[NPOW > 0 ? NPOW : 1];
+#pragma unroll
+    for (int i = 0; i < NPOW; ++i) sc[i] = scale[i];
+#pragma unroll 2
+    for (int m = 0; m < kPer; ++m) {
+      const int tl = threadIdx.x + kThreads * m;
+      const uint32_t *pt = P + tl;
+      const uint32_t neg_p0 = 0u - pt[0];
+      float bs = -INFINITY;
+      int bi = 0;
+#pragma unroll
+      for (int i = 0; i < NPOW; ++i) {
+        const int32_t num = (int32_t)(pt[1 << i] + neg_p0 - (uint32_t)((1 << i) * med));
+        const float s = (float)num * sc[i];
+        if (s > bs) {
+          bs = s;
+          bi = i;
+        }
+      }
+      srow[tl] = live ? bs : 0.0f;
+      brow[tl] = (uint8_t)bi;
+    }
+    return;
+  }
 
   if (avail >= (int64_t)(kSeg + wmax - 1)) {
     // Every width fits at every output of this segment: no per-width guard.
@@ -139,6 +164,32 @@ __global__ __launch_bounds__(kThreads) void boxcar_kernel(
   }
 }
 
+template <int NPOW>
+__global__ __launch_bounds__(kThreads) void boxcar_kernel(
+    const uint32_t *__restrict__ Y, int64_t nout, int nseg, const int32_t *__restrict__ stats,
+    WidthList widths, float *__restrict__ snr, uint8_t *__restrict__ best) {
+  extern __shared__ uint32_t P[];  // [kSeg + w_max]
+  const int64_t blk = blockIdx.x;
+  const int d = (int)(blk / nseg);
+  const int seg = (int)(blk - (int64_t)d * nseg);
+  boxcar_segment<NPOW>(Y, nout, d, seg, stats, widths, snr, best, P);
+}
+
+// One workgroup per (beam, DM row, segment) of a batch.
+template <int NPOW>
+__global__ __launch_bounds__(kThreads) void boxcar_batch_kernel(
+    const BeamWork *__restrict__ beams, int nbeams, WidthList widths) {
+  extern __shared__ uint32_t P[];
+  const int64_t blk = blockIdx.x;
+  int b = 0;
+  while (b + 1 < nbeams && beams[b + 1].bx_begin <= blk) ++b;
+  const BeamWork &bw = beams[b];
+  const int64_t local = blk - bw.bx_begin;
+  const int d = (int)(local / bw.nseg);
+  const int seg = (int)(local - (int64_t)d * bw.nseg);
+  boxcar_segment<NPOW>(bw.Y, bw.nout, d, seg, bw.stats, widths, bw.snr, bw.best, P);
+}
+
 }  // namespace
 
 hipError_t launch_boxcar(const uint32_t *Y, int ndm, int64_t nout, const int32_t *stats,
@@ -148,9 +199,45 @@ hipError_t launch_boxcar(const uint32_t *Y, int ndm, int64_t nout, const int32_t
   const int64_t grid = nseg * ndm;
   if (grid > 0x7FFFFFFF || nseg > 0x7FFFFFFF) return hipErrorInvalidValue;
   const size_t lds = (size_t)(kSeg + widths.w[widths.n - 1] + 1) * sizeof(uint32_t);
-  hipLaunchKernelGGL(boxcar_kernel, dim3((unsigned)grid), dim3(kThreads), lds, stream, Y, nout,
+  bool pow2 = widths.n <= 13;
+  for (int i = 0; i < widths.n && pow2; ++i) pow2 = widths.w[i] == (1 << i);
+#define SPS_BOXCAR_CASE(n_)                                                                    \
+  if (pow2 && widths.n == n_) {                                                                \
+    hipLaunchKernelGGL(boxcar_kernel<n_>, dim3((unsigned)grid), dim3(kThreads), lds, stream, Y, \
+                       nout, (int)nseg, stats, widths, snr, best);                             \
+    return hipGetLastError();                                                                  \
+  }
+  SPS_BOXCAR_CASE(1) SPS_BOXCAR_CASE(2) SPS_BOXCAR_CASE(3) SPS_BOXCAR_CASE(4) SPS_BOXCAR_CASE(5)
+  SPS_BOXCAR_CASE(6) SPS_BOXCAR_CASE(7) SPS_BOXCAR_CASE(8) SPS_BOXCAR_CASE(9) SPS_BOXCAR_CASE(10)
+  SPS_BOXCAR_CASE(11) SPS_BOXCAR_CASE(12) SPS_BOXCAR_CASE(13)
+#undef SPS_BOXCAR_CASE
+  hipLaunchKernelGGL(boxcar_kernel<0>, dim3((unsigned)grid), dim3(kThreads), lds, stream, Y, nout,
                      (int)nseg, stats, widths, snr, best);
   return hipGetLastError();
 }
+
+hipError_t launch_boxcar_batch(const BeamWork *beams, int nbeams, int64_t total_blocks,
+                               const WidthList &widths, hipStream_t stream) {
+  if (total_blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
+  const size_t lds = (size_t)(kSeg + widths.w[widths.n - 1] + 1) * sizeof(uint32_t);
+  bool pow2 = widths.n <= 13;
+  for (int i = 0; i < widths.n && pow2; ++i) pow2 = widths.w[i] == (1 << i);
+#define SPS_BOXCAR_BCASE(n_)                                                                 \
+  if (pow2 && widths.n == n_) {                                                              \
+    hipLaunchKernelGGL(boxcar_batch_kernel<n_>, dim3((unsigned)total_blocks), dim3(kThreads), \
+                       lds, stream, beams, nbeams, widths);                                  \
+    return hipGetLastError();                                                                \
+  }
+  SPS_BOXCAR_BCASE(1) SPS_BOXCAR_BCASE(2) SPS_BOXCAR_BCASE(3) SPS_BOXCAR_BCASE(4)
+  SPS_BOXCAR_BCASE(5) SPS_BOXCAR_BCASE(6) SPS_BOXCAR_BCASE(7) SPS_BOXCAR_BCASE(8)
+  SPS_BOXCAR_BCASE(9) SPS_BOXCAR_BCASE(10) SPS_BOXCAR_BCASE(11) SPS_BOXCAR_BCASE(12)
+  SPS_BOXCAR_BCASE(13)
+#undef SPS_BOXCAR_BCASE
+  hipLaunchKernelGGL(boxcar_batch_kernel<0>, dim3((unsigned)total_blocks), dim3(kThreads), lds,
+                     stream, beams, nbeams, widths);
+  return hipGetLastError();
+}
+
+int64_t boxcar_segments(int64_t nout) { return (nout + kSeg - 1) / kSeg; }
 
 }  // namespace sps

@@ -163,26 +163,17 @@ __device__ __forceinline__ int uniform_offset(int row_base_dw, int off) {
   return s;
 }
 
-template <int M, int DPW, int NW, int CS, int KMAX, int WPE>
-__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) void
-dedisperse_kernel(const uint8_t *__restrict__ X, int64_t pitch, int64_t nsamp_in,
-                  const int32_t *__restrict__ D, int nchan, int ndm, uint32_t *__restrict__ Y,
-                  int64_t nout, int lds_pitch, int ntiles, int ndmb, int per_xcd, int vec_store) {
+// One workgroup's share: trials [d_lo, d_lo + nw dpw) x outputs
+// [t0, t0 + 256 m) of one filterbank.  Ends with a barrier, so the caller may
+// reuse the LDS buffers right away.
+template <int M, int DPW, int NW, int CS, int KMAX>
+__device__ __forceinline__ void dedisperse_block(
+    const uint8_t *__restrict__ X, int64_t pitch, int64_t nsamp_in,
+    const int32_t *__restrict__ D, int nchan, int ndm, uint32_t *__restrict__ Y, int64_t nout,
+    int lds_pitch, int vec_store, int64_t t0, int d_lo, uint4 *smem) {
   static_assert(M % 2 == 1, "lane stride must be odd for conflict-free LDS reads");
   static_assert(CS % 2 == 0 && 256 % CS == 0, "slab must be even and divide 256");
   static_assert(CS % NW == 0, "every wave stages the same number of rows");
-  constexpr int NT = 256 * M;
-  constexpr int ND = NW * DPW;
-  extern __shared__ uint4 smem[];  // two slab buffers of CS rows x lds_pitch bytes
-
-  const int blk = blockIdx.x;
-  const int logical = (blk & 7) * per_xcd + (blk >> 3);
-  if (logical >= ntiles * ndmb) return;
-  const int dblk = logical % ndmb;
-  const int tile = logical / ndmb;
-  const int64_t t0 = (int64_t)tile * NT;
-  const int d_lo = dblk * ND;
-
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int dw0 = d_lo + wave * DPW;
@@ -287,6 +278,47 @@ dedisperse_kernel(const uint8_t *__restrict__ X, int64_t pitch, int64_t nsamp_in
   }
 }
 
+template <int M, int DPW, int NW, int CS, int KMAX, int WPE>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) void
+dedisperse_kernel(const uint8_t *__restrict__ X, int64_t pitch, int64_t nsamp_in,
+                  const int32_t *__restrict__ D, int nchan, int ndm, uint32_t *__restrict__ Y,
+                  int64_t nout, int lds_pitch, int ntiles, int ndmb, int per_xcd, int vec_store) {
+  extern __shared__ uint4 smem[];  // two slab buffers of CS rows x lds_pitch bytes
+  const int blk = blockIdx.x;
+  const int logical = (blk & 7) * per_xcd + (blk >> 3);
+  if (logical >= ntiles * ndmb) return;
+  const int dblk = logical % ndmb;
+  const int tile = logical / ndmb;
+  dedisperse_block<M, DPW, NW, CS, KMAX>(X, pitch, nsamp_in, D, nchan, ndm, Y, nout, lds_pitch,
+                                         vec_store, (int64_t)tile * (256 * M), dblk * (NW * DPW),
+                                         smem);
+}
+
+// Persistent kernel over many filterbanks that share a plan (beams of one
+// receiver, chunks of different lengths): the work items (beam, time tile,
+// DM block) form one flat range; workgroup w takes items w', w' + G, ...,
+// with w' the XCD-contiguous renumbering of w, until the range is done.
+template <int M, int DPW, int NW, int CS, int KMAX, int WPE>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) void
+dedisperse_batch_kernel(const BeamWork *__restrict__ beams, int nbeams, int64_t total_items,
+                        const int32_t *__restrict__ D, int nchan, int ndm, int lds_pitch,
+                        int ndmb) {
+  extern __shared__ uint4 smem[];
+  const int G = gridDim.x;
+  const int w = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
+  for (int64_t item = w; item < total_items; item += G) {
+    int b = 0;
+    while (b + 1 < nbeams && beams[b + 1].dd_begin <= item) ++b;
+    const BeamWork &bw = beams[b];
+    const int64_t local = item - bw.dd_begin;
+    const int dblk = (int)(local % ndmb);
+    const int64_t tile = local / ndmb;
+    dedisperse_block<M, DPW, NW, CS, KMAX>(bw.X, bw.pitch, bw.nsamp_in, D, nchan, ndm, bw.Y,
+                                           bw.nout, lds_pitch, bw.vec_store,
+                                           tile * (256 * M), dblk * (NW * DPW), smem);
+  }
+}
+
 // Plain fallback for delay spreads too wide to stage in LDS: one thread sums
 // four consecutive outputs of one trial straight from global memory.
 __global__ __launch_bounds__(256) void dedisperse_direct_kernel(
@@ -337,6 +369,25 @@ hipError_t launch_cfg(int lds_pitch, const uint8_t *X, int64_t pitch, int64_t ns
   return hipGetLastError();
 }
 
+template <int M, int DPW, int NW, int CS, int KMAX, int WPE>
+hipError_t launch_batch_cfg(int lds_pitch, const BeamWork *beams, int nbeams, int64_t total,
+                            const int32_t *D, int nchan, int ndm, int grid, hipStream_t stream) {
+  constexpr int ND = NW * DPW;
+  if (lds_pitch > 16 * 64 * KMAX || lds_pitch % 16 != 0 || grid % 8 != 0)
+    return hipErrorInvalidValue;
+  const int ndmb = (ndm + ND - 1) / ND;
+  const size_t lds = 2 * (size_t)CS * (size_t)lds_pitch;
+  auto kern = dedisperse_batch_kernel<M, DPW, NW, CS, KMAX, WPE>;
+  if (lds > 64 * 1024) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(NW * 64), lds, stream, beams, nbeams, total, D, nchan,
+                     ndm, lds_pitch, ndmb);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 int64_t dedisp_lds_pitch(const DedispConfig &cfg, int spread) {
@@ -380,6 +431,25 @@ bool dedisp_config_supported(const DedispConfig &c) {
   SPS_DEDISP_CONFIGS(SPS_MATCH)
 #undef SPS_MATCH
   return false;
+}
+
+int64_t dedisp_batch_items(const DedispConfig &c, int ndm, int64_t nout) {
+  const int64_t nt = 256 * c.m, nd = c.nw * c.dpw;
+  return ((nout + nt - 1) / nt) * ((ndm + nd - 1) / nd);
+}
+
+hipError_t launch_dedisperse_batch(const DedispConfig &c, int lds_pitch, const BeamWork *beams,
+                                   int nbeams, int64_t total_items, const int32_t *D, int nchan,
+                                   int ndm, int grid, hipStream_t stream) {
+#define SPS_BLAUNCH(m_, dpw_, nw_, cs_, kmax_, wpe_)                                          \
+  if (c.m == m_ && c.dpw == dpw_ && c.nw == nw_ && c.cs == cs_ && c.kmax == kmax_ &&         \
+      c.wpe == wpe_)                                                                          \
+    return launch_batch_cfg<m_, dpw_, nw_, cs_, kmax_, wpe_>(lds_pitch, beams, nbeams,        \
+                                                             total_items, D, nchan, ndm, grid, \
+                                                             stream);
+  SPS_DEDISP_CONFIGS(SPS_BLAUNCH)
+#undef SPS_BLAUNCH
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_dedisperse(const DedispConfig &c, int lds_pitch, const uint8_t *X,

@@ -28,11 +28,11 @@ __device__ __forceinline__ uint32_t ordered_bits(float v) {
 
 __device__ __forceinline__ uint64_t max_u64(uint64_t a, uint64_t b) { return a > b ? a : b; }
 
-__global__ __launch_bounds__(kTileThreads) void tile_peaks_kernel(
-    const float *__restrict__ snr, const uint8_t *__restrict__ best, int ndm, int64_t nout,
-    int tile_dm, int64_t tile_t, int64_t ntt, TilePeak *__restrict__ peaks) {
+__device__ __forceinline__ void tile_peak(const float *__restrict__ snr,
+                                          const uint8_t *__restrict__ best, int ndm,
+                                          int64_t nout, int tile_dm, int64_t tile_t, int64_t ntt,
+                                          int64_t tile, TilePeak *__restrict__ out) {
   __shared__ uint64_t red[kTileThreads / 64];
-  const int64_t tile = blockIdx.x;
   const int a = (int)(tile / ntt);
   const int64_t b = tile - (int64_t)a * ntt;
   const int d0 = a * tile_dm;
@@ -73,8 +73,25 @@ __global__ __launch_bounds__(kTileThreads) void tile_peaks_kernel(
     p.d = d;
     p.t = (int32_t)t;
     p.w = best[(int64_t)d * nout + t];
-    peaks[tile] = p;
+    *out = p;
   }
+}
+
+__global__ __launch_bounds__(kTileThreads) void tile_peaks_kernel(
+    const float *__restrict__ snr, const uint8_t *__restrict__ best, int ndm, int64_t nout,
+    int tile_dm, int64_t tile_t, int64_t ntt, TilePeak *__restrict__ peaks) {
+  tile_peak(snr, best, ndm, nout, tile_dm, tile_t, ntt, blockIdx.x, peaks + blockIdx.x);
+}
+
+__global__ __launch_bounds__(kTileThreads) void tile_peaks_batch_kernel(
+    const BeamWork *__restrict__ beams, int nbeams, int ndm, int tile_dm, int64_t tile_t,
+    TilePeak *__restrict__ peaks) {
+  const int64_t blk = blockIdx.x;
+  int b = 0;
+  while (b + 1 < nbeams && beams[b + 1].tp_begin <= blk) ++b;
+  const BeamWork &bw = beams[b];
+  tile_peak(bw.snr, bw.best, ndm, bw.nout, tile_dm, tile_t, bw.ntt, blk - bw.tp_begin,
+            peaks + blk);
 }
 
 // True if a comes before b: S/N descending, then t, then d.
@@ -99,10 +116,10 @@ __device__ __forceinline__ bool near(const TilePeak &a, const TilePeak &b, int n
 // at least the earliest undecided offer, and decisions are final, so reading
 // neighbours' states while they change is safe.  Otherwise the offers are
 // scanned one by one.
-__global__ __launch_bounds__(kNmsThreads) void select_nms_kernel(
-    const TilePeak *__restrict__ peaks, int64_t npeaks, int ntd, int64_t ntt, int tile_dm,
-    int64_t tile_t, float threshold, int nms_dm, int64_t nms_t, TilePeak *__restrict__ out,
-    int32_t *__restrict__ status) {
+__device__ void select_nms(const TilePeak *__restrict__ peaks, int64_t npeaks, int ntd,
+                           int64_t ntt, int tile_dm, int64_t tile_t, float threshold, int nms_dm,
+                           int64_t nms_t, TilePeak *__restrict__ out,
+                           int32_t *__restrict__ status) {
   __shared__ TilePeak offer[kMaxOffers];
   __shared__ int16_t aux[kMaxOffers];  // tile -> offer rank, or the accepted list
   __shared__ uint8_t state[kMaxOffers];  // 0 undecided, 1 accepted, 2 rejected
@@ -250,6 +267,26 @@ __global__ __launch_bounds__(kNmsThreads) void select_nms_kernel(
   }
 }
 
+__global__ __launch_bounds__(kNmsThreads) void select_nms_kernel(
+    const TilePeak *__restrict__ peaks, int64_t npeaks, int ntd, int64_t ntt, int tile_dm,
+    int64_t tile_t, float threshold, int nms_dm, int64_t nms_t, TilePeak *__restrict__ out,
+    int32_t *__restrict__ status) {
+  select_nms(peaks, npeaks, ntd, ntt, tile_dm, tile_t, threshold, nms_dm, nms_t, out, status);
+}
+
+// One workgroup per beam: accepted peaks of beam b go to out[b * kMaxOffers ...]
+// and its status to status[4 b ...].
+__global__ __launch_bounds__(kNmsThreads) void select_nms_batch_kernel(
+    const BeamWork *__restrict__ beams, int ndm, int tile_dm, int64_t tile_t, float threshold,
+    int nms_dm, int64_t nms_t, const TilePeak *__restrict__ peaks, TilePeak *__restrict__ out,
+    int32_t *__restrict__ status) {
+  const int b = blockIdx.x;
+  const BeamWork &bw = beams[b];
+  const int ntd = (ndm + tile_dm - 1) / tile_dm;
+  select_nms(peaks + bw.tp_begin, (int64_t)ntd * bw.ntt, ntd, bw.ntt, tile_dm, tile_t, threshold,
+             nms_dm, nms_t, out + (int64_t)b * kMaxOffers, status + 4 * (int64_t)b);
+}
+
 }  // namespace
 
 hipError_t launch_tile_peaks(const float *snr, const uint8_t *best, int ndm, int64_t nout,
@@ -271,6 +308,20 @@ hipError_t launch_select_nms(const TilePeak *peaks, int ndm, int64_t nout, int t
   hipLaunchKernelGGL(select_nms_kernel, dim3(1), dim3(kNmsThreads), 0, stream, peaks,
                      (int64_t)ntd * ntt, ntd, ntt, tile_dm, tile_t, threshold, nms_dm, nms_t, out,
                      status);
+  return hipGetLastError();
+}
+
+hipError_t launch_detect_batch(const BeamWork *beams, int nbeams, int ndm, int64_t total_tiles,
+                               int tile_dm, int64_t tile_t, float threshold, int nms_dm,
+                               int64_t nms_t, TilePeak *peaks, TilePeak *out, int32_t *status,
+                               hipStream_t stream) {
+  if (total_tiles > 0x7FFFFFFF) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(tile_peaks_batch_kernel, dim3((unsigned)total_tiles), dim3(kTileThreads), 0,
+                     stream, beams, nbeams, ndm, tile_dm, tile_t, peaks);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(select_nms_batch_kernel, dim3(nbeams), dim3(kNmsThreads), 0, stream, beams,
+                     ndm, tile_dm, tile_t, threshold, nms_dm, nms_t, peaks, out, status);
   return hipGetLastError();
 }
 

@@ -111,9 +111,9 @@ __device__ __forceinline__ void for_each_value(const uint32_t *row, int64_t n, b
   }
 }
 
-__global__ __launch_bounds__(kThreads) void row_stats_kernel(const uint32_t *__restrict__ Y,
-                                                             int64_t nout, int shift,
-                                                             int32_t *__restrict__ stats) {
+// Median and MAD of one row (the whole workgroup), written to out[0..1].
+__device__ void row_stats_row(const uint32_t *__restrict__ row, int64_t nout, int shift,
+                              int32_t *__restrict__ out) {
   // Pass 1: histogram of the high bits (4096 bins of width 2^shift) gives the
   // bin b holding the median and, from the counts around b, a bound on the
   // MAD.  Pass 2: an exact histogram of the values in the window of coarse
@@ -124,8 +124,6 @@ __global__ __launch_bounds__(kThreads) void row_stats_kernel(const uint32_t *__r
   __shared__ uint32_t tmp[16];
   __shared__ uint32_t sel[2];
   __shared__ int radius;
-  const int d = blockIdx.x;
-  const uint32_t *row = Y + (int64_t)d * nout;
   const bool vec = ((reinterpret_cast<uintptr_t>(row) & 15) == 0);
   const uint32_t k = (uint32_t)((nout - 1) / 2);
   const uint32_t width = 1u << shift;
@@ -239,18 +237,47 @@ __global__ __launch_bounds__(kThreads) void row_stats_kernel(const uint32_t *__r
     mad = (hb << shift) | sel[0];
   }
   if (threadIdx.x == 0) {
-    stats[2 * (int64_t)d] = (int32_t)med;
-    stats[2 * (int64_t)d + 1] = (int32_t)mad;
+    out[0] = (int32_t)med;
+    out[1] = (int32_t)mad;
   }
+}
+
+__global__ __launch_bounds__(kThreads) void row_stats_kernel(const uint32_t *__restrict__ Y,
+                                                             int64_t nout, int shift,
+                                                             int32_t *__restrict__ stats) {
+  const int d = blockIdx.x;
+  row_stats_row(Y + (int64_t)d * nout, nout, shift, stats + 2 * (int64_t)d);
+}
+
+// One workgroup per (beam, DM row) of a batch.
+__global__ __launch_bounds__(kThreads) void row_stats_batch_kernel(
+    const BeamWork *__restrict__ beams, int ndm, int shift) {
+  const int b = blockIdx.x / ndm;
+  const int d = blockIdx.x - b * ndm;
+  const BeamWork &bw = beams[b];
+  row_stats_row(bw.Y + (int64_t)d * bw.nout, bw.nout, shift, bw.stats + 2 * (int64_t)d);
 }
 
 }  // namespace
 
+static int stats_shift(uint32_t vmax) {
+  const int bits = 32 - __builtin_clz(vmax | 1u);
+  return bits > 24 ? -1 : (bits > 12 ? bits - 12 : 0);
+}
+
+hipError_t launch_row_stats_batch(const BeamWork *beams, int nbeams, int ndm, uint32_t vmax,
+                                  hipStream_t stream) {
+  const int shift = stats_shift(vmax);
+  if (shift < 0 || (int64_t)nbeams * ndm > 0x7FFFFFFF) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(row_stats_batch_kernel, dim3(nbeams * ndm), dim3(kThreads), 0, stream, beams,
+                     ndm, shift);
+  return hipGetLastError();
+}
+
 hipError_t launch_row_stats(const uint32_t *Y, int ndm, int64_t nout, uint32_t vmax,
                             int32_t *stats, hipStream_t stream) {
-  int bits = 32 - __builtin_clz(vmax | 1u);
-  if (bits > 24) return hipErrorInvalidValue;
-  const int shift = bits > 12 ? bits - 12 : 0;
+  const int shift = stats_shift(vmax);
+  if (shift < 0) return hipErrorInvalidValue;
   hipLaunchKernelGGL(row_stats_kernel, dim3(ndm), dim3(kThreads), 0, stream, Y, nout, shift,
                      stats);
   return hipGetLastError();

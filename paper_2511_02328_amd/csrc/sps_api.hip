@@ -67,6 +67,20 @@ struct sps_plan_s {
   int32_t *d_stats = nullptr;  // [ndm][2] used when the caller passes none
   sps::DedispConfig cfg{5, 1, 16, 16, 2, 8};
   int lds_pitch = 0;
+  // subband method (sps_subband_plan_create)
+  bool subband = false;
+  int n0 = 0, nsub = 0, ncoarse = 0;
+  std::vector<int32_t> sub;            // [nsub + 1] channel boundaries
+  std::vector<double> fsub;            // representative frequencies
+  std::vector<int32_t> coarse_delays;  // [ncoarse][nchan]
+  std::vector<int32_t> residuals;      // [ndm][nsub]
+  int32_t rmax = 0, eff_max_delay = 0;
+  std::vector<int32_t *> d_coarse_sub;  // per subband: [ncoarse][channels of s]
+  std::vector<sps::DedispConfig> sub_cfg;
+  std::vector<int> sub_pitch;
+  int32_t *d_resid = nullptr;
+  uint32_t *d_I = nullptr;
+  size_t I_bytes = 0;
   // detection scratch
   sps::TilePeak *d_peaks = nullptr;
   int64_t peaks_cap = 0;
@@ -83,6 +97,10 @@ void free_plan(sps_plan p) {
   if (p->d_peaks) (void)hipFree(p->d_peaks);
   if (p->d_accepted) (void)hipFree(p->d_accepted);
   if (p->d_status) (void)hipFree(p->d_status);
+  for (int32_t *q : p->d_coarse_sub)
+    if (q) (void)hipFree(q);
+  if (p->d_resid) (void)hipFree(p->d_resid);
+  if (p->d_I) (void)hipFree(p->d_I);
   delete p;
 }
 
@@ -92,30 +110,39 @@ const sps::DedispConfig kPrefs[] = {
     {5, 2, 8, 16, 4, 4}, {5, 1, 16, 16, 4, 4}, {3, 2, 8, 16, 2, 4}, {3, 1, 16, 16, 2, 8},
     {7, 1, 16, 16, 3, 4}};
 
-// Staged-row bytes of config c for this plan, or -1 if it does not fit.
-int64_t fitted_pitch(sps_plan p, const sps::DedispConfig &c, int64_t lds_budget) {
-  const int spread = sps::dedisp_block_spread(p->delays.data(), p->nchan, p->ndm, c.nd());
+// Staged-row bytes of config c for a delay table, or -1 if it does not fit.
+int64_t fitted_pitch(const int32_t *D, int nchan, int ndm, const sps::DedispConfig &c,
+                     int64_t lds_budget) {
+  const int spread = sps::dedisp_block_spread(D, nchan, ndm, c.nd());
   const int64_t pitch = sps::dedisp_lds_pitch(c, spread);
   if (pitch > 1024 * (int64_t)c.kmax || c.lds_bytes(pitch) > lds_budget) return -1;
   return pitch;
 }
 
+int64_t fitted_pitch(sps_plan p, const sps::DedispConfig &c, int64_t lds_budget) {
+  return fitted_pitch(p->delays.data(), p->nchan, p->ndm, c, lds_budget);
+}
+
 // Picks the first preferred tiling whose double-buffered slab fits the LDS
 // budget (64 KiB keeps two workgroups per CU; up to 160 KiB is allowed
-// next); otherwise the plain global-memory kernel is used.
-sps_status choose_tiling(sps_plan p) {
+// next); otherwise the plain global-memory kernel (m = 0) is used.
+void pick_tiling(const int32_t *D, int nchan, int ndm, sps::DedispConfig *cfg, int *pitch) {
   for (int64_t budget : {(int64_t)64 * 1024, (int64_t)160 * 1024}) {
     for (const auto &c : kPrefs) {
-      const int64_t pitch = fitted_pitch(p, c, budget);
-      if (pitch > 0) {
-        p->cfg = c;
-        p->lds_pitch = (int)pitch;
-        return SPS_OK;
+      const int64_t pp = fitted_pitch(D, nchan, ndm, c, budget);
+      if (pp > 0) {
+        *cfg = c;
+        *pitch = (int)pp;
+        return;
       }
     }
   }
-  p->cfg = sps::DedispConfig{0, 0, 0, 0, 0, 0};
-  p->lds_pitch = 0;
+  *cfg = sps::DedispConfig{0, 0, 0, 0, 0, 0};
+  *pitch = 0;
+}
+
+sps_status choose_tiling(sps_plan p) {
+  pick_tiling(p->delays.data(), p->nchan, p->ndm, &p->cfg, &p->lds_pitch);
   return SPS_OK;
 }
 
@@ -405,6 +432,559 @@ sps_status sps_detect(sps_plan plan, const float *snr, const uint8_t *best_w, in
   }
   *n_found = na;
   if (na > cap) return fail(SPS_ERR_TRUNCATED, "%d candidates found, %d returned", na, cap);
+  return SPS_OK;
+}
+
+sps_status sps_subband_plan_create(const sps_subband_desc *desc, sps_plan *out) {
+  g_error.clear();
+  if (!out) return fail(SPS_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!desc || !desc->freq_mhz) return fail(SPS_ERR_INVALID_ARG, "NULL descriptor");
+  if (desc->ndm < 1 || desc->n0 < 1 || desc->nsub < 1 || desc->nsub > desc->nchan)
+    return fail(SPS_ERR_INVALID_ARG, "need ndm >= 1, n0 >= 1 and 1 <= nsub <= nchan");
+  if (!(desc->dm_lo >= 0) || !(desc->dm_step >= 0) || !isfinite(desc->dm_lo) ||
+      !isfinite(desc->dm_step))
+    return fail(SPS_ERR_INVALID_ARG, "dm_lo and dm_step must be finite and >= 0");
+  std::vector<double> dm;
+  try {
+    dm.resize((size_t)desc->ndm);
+  } catch (...) {
+    return fail(SPS_ERR_NOMEM, "host allocation failed");
+  }
+  for (int m = 0; m < desc->ndm; ++m) dm[(size_t)m] = desc->dm_lo + (double)m * desc->dm_step;
+  sps_obs_desc base{desc->nchan, desc->freq_mhz, desc->fref_mhz, desc->tsamp_s, desc->ndm,
+                    dm.data()};
+  sps_plan p = nullptr;
+  sps_status st = sps_plan_create(&base, &p);
+  if (st != SPS_OK) return st;
+  DeviceScope scope(p->device);
+  p->subband = true;
+  p->n0 = desc->n0;
+  p->nsub = desc->nsub;
+  p->ncoarse = (p->ndm + p->n0 - 1) / p->n0;
+  const int nchan = p->nchan, nsub = p->nsub, ncoarse = p->ncoarse, ndm = p->ndm;
+  try {
+    p->sub.resize((size_t)nsub + 1);
+    p->fsub.resize((size_t)nsub);
+    p->coarse_delays.resize((size_t)ncoarse * nchan);
+    p->residuals.resize((size_t)ndm * nsub);
+    p->d_coarse_sub.assign((size_t)nsub, nullptr);
+    p->sub_cfg.resize((size_t)nsub);
+    p->sub_pitch.resize((size_t)nsub);
+  } catch (...) {
+    free_plan(p);
+    return fail(SPS_ERR_NOMEM, "host allocation failed");
+  }
+  for (int s = 0; s <= nsub; ++s) p->sub[(size_t)s] = (int32_t)(((int64_t)s * nchan) / nsub);
+  const double inv_ref2 = 1.0 / (p->fref_mhz * p->fref_mhz);
+  // Eq. (coarse_delay) on the coarse grid DM_j = dm_lo + j n0 dDM.
+  for (int j = 0; j < ncoarse; ++j) {
+    const double dmj = desc->dm_lo + (double)j * (double)p->n0 * desc->dm_step;
+    const double a = kKdm * dmj / p->tsamp_s;
+    for (int c = 0; c < nchan; ++c) {
+      const double f = p->freq[(size_t)c];
+      const double x = floor(a * (1.0 / (f * f) - inv_ref2) + 0.5);
+      if (x > 2147483647.0) {
+        free_plan(p);
+        return fail(SPS_ERR_OVERFLOW, "coarse delay exceeds 2^31-1 samples");
+      }
+      p->coarse_delays[(size_t)j * nchan + c] = (int32_t)x;
+    }
+  }
+  // Eq. (residual): subband s represented by F_s with 1/F_s^2 the mean of
+  // 1/f^2 over its channels; dDM_m = DM_m - DM_j(m).
+  int32_t rmax = 0;
+  for (int s = 0; s < nsub; ++s) {
+    double acc = 0.0;
+    for (int c = p->sub[(size_t)s]; c < p->sub[(size_t)s + 1]; ++c) {
+      const double f = p->freq[(size_t)c];
+      acc += 1.0 / (f * f);
+    }
+    const double inv_f2 = acc / (double)(p->sub[(size_t)s + 1] - p->sub[(size_t)s]);
+    p->fsub[(size_t)s] = 1.0 / sqrt(inv_f2);
+    const double k = inv_f2 - inv_ref2;
+    for (int m = 0; m < ndm; ++m) {
+      const double dm_m = desc->dm_lo + (double)m * desc->dm_step;
+      const double dm_j = desc->dm_lo + (double)((m / p->n0) * p->n0) * desc->dm_step;
+      const double x = floor((kKdm * (dm_m - dm_j) / p->tsamp_s) * k + 0.5);
+      if (x > 2147483647.0 || x < 0) {
+        free_plan(p);
+        return fail(SPS_ERR_OVERFLOW, "residual shift out of range");
+      }
+      p->residuals[(size_t)m * nsub + s] = (int32_t)x;
+      if ((int32_t)x > rmax) rmax = (int32_t)x;
+    }
+  }
+  p->rmax = rmax;
+  int32_t eff = 0;
+  for (int m = 0; m < ndm; ++m)
+    for (int s = 0; s < nsub; ++s)
+      for (int c = p->sub[(size_t)s]; c < p->sub[(size_t)s + 1]; ++c) {
+        const int64_t v = (int64_t)p->coarse_delays[(size_t)(m / p->n0) * nchan + c] +
+                          p->residuals[(size_t)m * nsub + s];
+        if (v > 2147483647) {
+          free_plan(p);
+          return fail(SPS_ERR_OVERFLOW, "effective delay exceeds 2^31-1 samples");
+        }
+        if (v > eff) eff = (int32_t)v;
+      }
+  p->eff_max_delay = eff;
+  // Per-subband coarse tables and stage-1 tilings.
+  std::vector<int32_t> tab;
+  for (int s = 0; s < nsub; ++s) {
+    const int c0 = p->sub[(size_t)s], ns = p->sub[(size_t)s + 1] - c0;
+    tab.resize((size_t)ncoarse * ns);
+    for (int j = 0; j < ncoarse; ++j)
+      for (int c = 0; c < ns; ++c)
+        tab[(size_t)j * ns + c] = p->coarse_delays[(size_t)j * nchan + c0 + c];
+    pick_tiling(tab.data(), ns, ncoarse, &p->sub_cfg[(size_t)s], &p->sub_pitch[(size_t)s]);
+    hipError_t e = hipMalloc(&p->d_coarse_sub[(size_t)s], tab.size() * sizeof(int32_t));
+    if (e == hipSuccess)
+      e = hipMemcpy(p->d_coarse_sub[(size_t)s], tab.data(), tab.size() * sizeof(int32_t),
+                    hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      free_plan(p);
+      (void)hipGetLastError();
+      return fail(SPS_ERR_NOMEM, "device allocation of subband tables failed");
+    }
+  }
+  hipError_t e = hipMalloc(&p->d_resid, p->residuals.size() * sizeof(int32_t));
+  if (e == hipSuccess)
+    e = hipMemcpy(p->d_resid, p->residuals.data(), p->residuals.size() * sizeof(int32_t),
+                  hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    free_plan(p);
+    (void)hipGetLastError();
+    return fail(SPS_ERR_NOMEM, "device allocation of the residual table failed");
+  }
+  *out = p;
+  return SPS_OK;
+}
+
+sps_status sps_subband_tables(sps_plan plan, int32_t *coarse_delays, int32_t *residuals,
+                              double *fsub, int32_t *max_delay) {
+  g_error.clear();
+  if (!plan || !plan->subband) return fail(SPS_ERR_INVALID_ARG, "not a subband plan");
+  if (coarse_delays)
+    memcpy(coarse_delays, plan->coarse_delays.data(),
+           plan->coarse_delays.size() * sizeof(int32_t));
+  if (residuals)
+    memcpy(residuals, plan->residuals.data(), plan->residuals.size() * sizeof(int32_t));
+  if (fsub) memcpy(fsub, plan->fsub.data(), plan->fsub.size() * sizeof(double));
+  if (max_delay) *max_delay = plan->eff_max_delay;
+  return SPS_OK;
+}
+
+sps_status sps_dedisperse_subband(sps_plan plan, const uint8_t *X, int64_t pitch,
+                                  int64_t nsamp_in, uint32_t *Y, int64_t nout, uint32_t flags,
+                                  void *stream) {
+  g_error.clear();
+  if (!plan || !X || !Y) return fail(SPS_ERR_INVALID_ARG, "NULL plan or buffer");
+  if (!plan->subband) return fail(SPS_ERR_INVALID_ARG, "plan was not made by sps_subband_plan_create");
+  if (flags & ~SPS_ZERO_PAD) return fail(SPS_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+  if (!aligned16(X) || pitch % 16 != 0)
+    return fail(SPS_ERR_INVALID_ARG, "X must be 16-byte aligned with a pitch multiple of 16");
+  if (nsamp_in < 0 || pitch < nsamp_in) return fail(SPS_ERR_RANGE, "need 0 <= nsamp_in <= pitch");
+  if (nout < 1 || nout > 0x7FFFFFFF - plan->rmax)
+    return fail(SPS_ERR_RANGE, "nout must be in [1, 2^31-1 - max residual]");
+  if (!(flags & SPS_ZERO_PAD) && nsamp_in < nout + plan->eff_max_delay)
+    return fail(SPS_ERR_RANGE, "nsamp_in %lld < nout %lld + effective max delay %d",
+                (long long)nsamp_in, (long long)nout, plan->eff_max_delay);
+  DeviceScope scope(plan->device);
+  if (scope.err != hipSuccess) return hip_fail(scope.err, "selecting the plan's device");
+  const int64_t len1 = nout + plan->rmax;
+  const size_t need = (size_t)plan->nsub * plan->ncoarse * (size_t)len1 * sizeof(uint32_t);
+  if (plan->I_bytes < need) {
+    if (plan->d_I) (void)hipFree(plan->d_I);
+    plan->d_I = nullptr;
+    plan->I_bytes = 0;
+    hipError_t e = hipMalloc(&plan->d_I, need);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(SPS_ERR_NOMEM, "device allocation of %zu bytes of subband series failed", need);
+    }
+    plan->I_bytes = need;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  for (int b = 0; b < plan->nsub; ++b) {
+    const int c0 = plan->sub[(size_t)b], ns = plan->sub[(size_t)b + 1] - c0;
+    hipError_t e = sps::launch_dedisperse(
+        plan->sub_cfg[(size_t)b], plan->sub_pitch[(size_t)b], X + (int64_t)c0 * pitch, pitch,
+        nsamp_in, plan->d_coarse_sub[(size_t)b], ns, plan->ncoarse,
+        plan->d_I + (size_t)b * plan->ncoarse * (size_t)len1, len1, s);
+    if (e != hipSuccess) return hip_fail(e, "subband stage 1 launch");
+  }
+  hipError_t e = sps::launch_subband_stage2(plan->d_I, len1, plan->ncoarse, plan->nsub,
+                                            plan->d_resid, plan->ndm, plan->n0, Y, nout, s);
+  if (e != hipSuccess) return hip_fail(e, "subband stage 2 launch");
+  return SPS_OK;
+}
+
+sps_status sps_zero_dm(const uint8_t *X, int64_t pitch, int64_t nsamp, int32_t nchan, uint8_t *Xo,
+                       int64_t pitch_out, void *stream) {
+  g_error.clear();
+  if (!X || !Xo) return fail(SPS_ERR_INVALID_ARG, "NULL buffer");
+  if (nchan < 1) return fail(SPS_ERR_INVALID_ARG, "nchan must be >= 1");
+  if (!aligned16(X) || !aligned16(Xo) || pitch % 16 != 0 || pitch_out % 16 != 0)
+    return fail(SPS_ERR_INVALID_ARG, "buffers must be 16-byte aligned with pitches multiple of 16");
+  if (nsamp < 0 || pitch < nsamp || pitch_out < nsamp)
+    return fail(SPS_ERR_RANGE, "need 0 <= nsamp <= pitch, pitch_out");
+  if ((int64_t)nchan * 255 >= (1ll << 31)) return fail(SPS_ERR_OVERFLOW, "too many channels");
+  hipError_t e = sps::launch_zero_dm(X, pitch, nsamp, nchan, Xo, pitch_out, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "zero-DM launch");
+  return SPS_OK;
+}
+
+sps_status sps_downsample_sqrt(const uint8_t *X, int64_t pitch, int64_t nsamp, int32_t nchan,
+                               int32_t factor, uint8_t *Xo, int64_t pitch_out, void *stream) {
+  g_error.clear();
+  if (!X || !Xo) return fail(SPS_ERR_INVALID_ARG, "NULL buffer");
+  if (nchan < 1 || nchan > 65535 || factor < 1 || factor > (1 << 20))
+    return fail(SPS_ERR_INVALID_ARG, "need 1 <= nchan <= 65535 and 1 <= factor <= 2^20");
+  if (nsamp < 0 || pitch < nsamp || pitch_out < nsamp / factor)
+    return fail(SPS_ERR_RANGE, "need 0 <= nsamp <= pitch and pitch_out >= nsamp / factor");
+  hipError_t e = sps::launch_downsample_sqrt(X, pitch, nsamp, nchan, factor, Xo, pitch_out,
+                                             (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "downsampling launch");
+  return SPS_OK;
+}
+
+/* ---------------- batches of filterbanks sharing one plan ---------------- */
+
+}  // extern "C"
+
+struct sps_batch_s {
+  sps_plan plan = nullptr;
+  int nbeams = 0;
+  std::vector<sps::BeamWork> beams;
+  std::vector<int64_t> nout;
+  sps::BeamWork *d_beams = nullptr;
+  int64_t dd_items = 0, bx_blocks = 0, tp_tiles = 0;
+  sps::WidthList widths{};
+  std::vector<int32_t> widths_host;
+  sps_detect_params prm{};
+  sps::DedispConfig cfg{};
+  int lds_pitch = 0;
+  int grid_dd = 0;
+  sps::TilePeak *d_peaks = nullptr, *d_out = nullptr;
+  int32_t *d_status = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t graph_stream = nullptr;
+};
+
+namespace {
+
+void free_batch(sps_batch b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->d_beams) (void)hipFree(b->d_beams);
+  if (b->d_peaks) (void)hipFree(b->d_peaks);
+  if (b->d_out) (void)hipFree(b->d_out);
+  if (b->d_status) (void)hipFree(b->d_status);
+  delete b;
+}
+
+sps_status batch_enqueue(sps_batch b, hipStream_t s) {
+  sps_plan p = b->plan;
+  hipError_t e = sps::launch_dedisperse_batch(b->cfg, b->lds_pitch, b->d_beams, b->nbeams,
+                                              b->dd_items, p->d_delays, p->nchan, p->ndm,
+                                              b->grid_dd, s);
+  if (e != hipSuccess) return hip_fail(e, "batched dedispersion launch");
+  e = sps::launch_row_stats_batch(b->d_beams, b->nbeams, p->ndm, 255u * (uint32_t)p->nchan, s);
+  if (e != hipSuccess) return hip_fail(e, "batched statistics launch");
+  e = sps::launch_boxcar_batch(b->d_beams, b->nbeams, b->bx_blocks, b->widths, s);
+  if (e != hipSuccess) return hip_fail(e, "batched boxcar launch");
+  e = sps::launch_detect_batch(b->d_beams, b->nbeams, p->ndm, b->tp_tiles, b->prm.tile_dm,
+                               b->prm.tile_t, b->prm.threshold, b->prm.nms_dm, b->prm.nms_t,
+                               b->d_peaks, b->d_out, b->d_status, s);
+  if (e != hipSuccess) return hip_fail(e, "batched detection launch");
+  return SPS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sps_status sps_batch_create(sps_plan plan, int32_t nbeams, const sps_beam *beams,
+                            const int32_t *widths, int32_t nw, const sps_detect_params *prm,
+                            uint32_t flags, sps_batch *out) {
+  g_error.clear();
+  if (!out) return fail(SPS_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!plan || !beams || !widths || !prm) return fail(SPS_ERR_INVALID_ARG, "NULL argument");
+  if (nbeams < 1 || nbeams > 4096) return fail(SPS_ERR_INVALID_ARG, "nbeams must be in [1, 4096]");
+  if (flags & ~SPS_ZERO_PAD) return fail(SPS_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+  if (plan->cfg.m == 0)
+    return fail(SPS_ERR_RANGE, "the plan's delay spread needs the plain kernel, which has no batched form");
+  if (nw < 1 || nw > sps::kMaxWidths) return fail(SPS_ERR_INVALID_ARG, "bad width count");
+  for (int i = 0; i < nw; ++i)
+    if (widths[i] < 1 || (i > 0 && widths[i] <= widths[i - 1]))
+      return fail(SPS_ERR_INVALID_ARG, "widths must be >= 1 and strictly ascending");
+  if (widths[nw - 1] > sps::kMaxWidth) return fail(SPS_ERR_RANGE, "largest width above %d", sps::kMaxWidth);
+  const uint32_t vmax = 255u * (uint32_t)plan->nchan;
+  if ((uint64_t)widths[nw - 1] * vmax >= (1ull << 31))
+    return fail(SPS_ERR_OVERFLOW, "width x 255 x nchan reaches 2^31");
+  if (!(prm->threshold > 0.0f) || prm->tile_dm < 1 || prm->tile_t < 1 || prm->nms_dm < 0 ||
+      prm->nms_t < 0 || (uint64_t)prm->tile_dm * (uint64_t)prm->tile_t >= (1ull << 32))
+    return fail(SPS_ERR_INVALID_ARG, "bad detection parameters");
+  sps_batch b = new (std::nothrow) sps_batch_s;
+  if (!b) return fail(SPS_ERR_NOMEM, "host allocation failed");
+  b->plan = plan;
+  b->nbeams = nbeams;
+  b->prm = *prm;
+  b->cfg = plan->cfg;
+  b->lds_pitch = plan->lds_pitch;
+  b->widths.n = nw;
+  for (int i = 0; i < sps::kMaxWidths; ++i) b->widths.w[i] = i < nw ? widths[i] : 0;
+  b->widths_host.assign(widths, widths + nw);
+  b->beams.resize((size_t)nbeams);
+  b->nout.resize((size_t)nbeams);
+  const int64_t ntd = (plan->ndm + prm->tile_dm - 1) / prm->tile_dm;
+  for (int i = 0; i < nbeams; ++i) {
+    const sps_beam &q = beams[i];
+    if (!q.X || !q.Y || !q.snr || !q.best_w || !q.stats) {
+      free_batch(b);
+      return fail(SPS_ERR_INVALID_ARG, "beam %d has a NULL buffer", i);
+    }
+    if (!aligned16(q.X) || q.pitch % 16 != 0) {
+      free_batch(b);
+      return fail(SPS_ERR_INVALID_ARG, "beam %d: X must be 16-byte aligned, pitch a multiple of 16", i);
+    }
+    if (q.nout < widths[nw - 1] || q.nout > 0x7FFFFFFF || q.nsamp_in < 0 || q.pitch < q.nsamp_in) {
+      free_batch(b);
+      return fail(SPS_ERR_RANGE, "beam %d: bad nout / nsamp_in / pitch", i);
+    }
+    if (!(flags & SPS_ZERO_PAD) && q.nsamp_in < q.nout + plan->max_delay) {
+      free_batch(b);
+      return fail(SPS_ERR_RANGE, "beam %d: nsamp_in < nout + max delay", i);
+    }
+    sps::BeamWork &w = b->beams[(size_t)i];
+    w.X = q.X;
+    w.pitch = q.pitch;
+    w.nsamp_in = q.nsamp_in;
+    w.Y = q.Y;
+    w.nout = q.nout;
+    w.snr = q.snr;
+    w.best = q.best_w;
+    w.stats = q.stats;
+    w.dd_begin = b->dd_items;
+    w.bx_begin = b->bx_blocks;
+    w.tp_begin = b->tp_tiles;
+    w.nseg = sps::boxcar_segments(q.nout);
+    w.ntt = (q.nout + prm->tile_t - 1) / prm->tile_t;
+    w.vec_store = (q.nout % 4 == 0) && aligned16(q.Y);
+    w.pad = 0;
+    b->dd_items += sps::dedisp_batch_items(b->cfg, plan->ndm, q.nout);
+    b->bx_blocks += w.nseg * plan->ndm;
+    b->tp_tiles += w.ntt * ntd;
+    b->nout[(size_t)i] = q.nout;
+    if (w.ntt * ntd > sps::kMaxOffers) {
+      free_batch(b);
+      return fail(SPS_ERR_RANGE, "beam %d has more than %d detection tiles", i, sps::kMaxOffers);
+    }
+  }
+  if (b->bx_blocks > 0x7FFFFFFF || b->tp_tiles > 0x7FFFFFFF) {
+    free_batch(b);
+    return fail(SPS_ERR_RANGE, "batch too large");
+  }
+  const int64_t persistent = 256 * 2;
+  const int64_t g = b->dd_items < persistent ? b->dd_items : persistent;
+  b->grid_dd = (int)(((g + 7) / 8) * 8);
+  DeviceScope scope(plan->device);
+  hipError_t e = hipMalloc(&b->d_beams, sizeof(sps::BeamWork) * (size_t)nbeams);
+  if (e == hipSuccess) e = hipMalloc(&b->d_peaks, sizeof(sps::TilePeak) * (size_t)b->tp_tiles);
+  if (e == hipSuccess)
+    e = hipMalloc(&b->d_out, sizeof(sps::TilePeak) * (size_t)sps::kMaxOffers * nbeams);
+  if (e == hipSuccess) e = hipMalloc(&b->d_status, sizeof(int32_t) * 4 * (size_t)nbeams);
+  if (e == hipSuccess)
+    e = hipMemcpy(b->d_beams, b->beams.data(), sizeof(sps::BeamWork) * (size_t)nbeams,
+                  hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    free_batch(b);
+    (void)hipGetLastError();
+    return fail(SPS_ERR_NOMEM, "device allocation for the batch failed");
+  }
+  *out = b;
+  return SPS_OK;
+}
+
+sps_status sps_batch_destroy(sps_batch batch) {
+  g_error.clear();
+  if (!batch) return SPS_OK;
+  DeviceScope scope(batch->plan->device);
+  free_batch(batch);
+  return SPS_OK;
+}
+
+sps_status sps_batch_enqueue(sps_batch batch, void *stream) {
+  g_error.clear();
+  if (!batch) return fail(SPS_ERR_INVALID_ARG, "batch is NULL");
+  DeviceScope scope(batch->plan->device);
+  if (scope.err != hipSuccess) return hip_fail(scope.err, "selecting the plan's device");
+  return batch_enqueue(batch, (hipStream_t)stream);
+}
+
+sps_status sps_batch_launch_graph(sps_batch batch, void *stream) {
+  g_error.clear();
+  if (!batch) return fail(SPS_ERR_INVALID_ARG, "batch is NULL");
+  if (!stream) return fail(SPS_ERR_INVALID_ARG, "graph replay needs a non-null stream");
+  DeviceScope scope(batch->plan->device);
+  if (scope.err != hipSuccess) return hip_fail(scope.err, "selecting the plan's device");
+  hipStream_t s = (hipStream_t)stream;
+  if (!batch->exec || batch->graph_stream != s) {
+    if (batch->exec) (void)hipGraphExecDestroy(batch->exec);
+    if (batch->graph) (void)hipGraphDestroy(batch->graph);
+    batch->exec = nullptr;
+    batch->graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "beginning stream capture");
+    sps_status st = batch_enqueue(batch, s);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(s, &g);
+    if (st != SPS_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return hip_fail(e, "ending stream capture");
+    e = hipGraphInstantiate(&batch->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return hip_fail(e, "instantiating the graph");
+    }
+    batch->graph = g;
+    batch->graph_stream = s;
+  }
+  hipError_t e = hipGraphLaunch(batch->exec, s);
+  if (e != hipSuccess) return hip_fail(e, "launching the graph");
+  return SPS_OK;
+}
+
+sps_status sps_batch_candidates(sps_batch batch, int32_t beam, sps_candidate *out, int32_t cap,
+                                int32_t *n_found, void *stream) {
+  g_error.clear();
+  if (!batch || !n_found) return fail(SPS_ERR_INVALID_ARG, "NULL argument");
+  if (beam < 0 || beam >= batch->nbeams) return fail(SPS_ERR_RANGE, "beam out of range");
+  if (cap < 0 || (cap > 0 && !out)) return fail(SPS_ERR_INVALID_ARG, "bad output array");
+  DeviceScope scope(batch->plan->device);
+  if (scope.err != hipSuccess) return hip_fail(scope.err, "selecting the plan's device");
+  hipStream_t s = (hipStream_t)stream;
+  int32_t status[4] = {0, 0, 0, 0};
+  hipError_t e = hipMemcpyAsync(status, batch->d_status + 4 * (size_t)beam, 3 * sizeof(int32_t),
+                                hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "reading detection status");
+  if (status[2]) {
+    *n_found = 0;
+    return fail(SPS_ERR_RANGE, "%d tiles reach the threshold; at most %d are supported", status[0],
+                sps::kMaxOffers);
+  }
+  const int32_t na = status[1];
+  const int32_t ncopy = na < cap ? na : cap;
+  std::vector<sps::TilePeak> acc((size_t)ncopy);
+  if (ncopy > 0) {
+    e = hipMemcpyAsync(acc.data(), batch->d_out + (size_t)beam * sps::kMaxOffers,
+                       sizeof(sps::TilePeak) * (size_t)ncopy, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "reading candidates");
+  }
+  const sps_plan p = batch->plan;
+  const int nw = (int)batch->widths_host.size();
+  for (int32_t i = 0; i < ncopy; ++i) {
+    const sps::TilePeak &q = acc[(size_t)i];
+    sps_candidate c;
+    c.dm_idx = q.d;
+    c.t_idx = q.t;
+    c.width = (q.w >= 0 && q.w < nw) ? batch->widths_host[(size_t)q.w] : 0;
+    c.snr = q.snr;
+    c.reserved = 0.0f;
+    c.dm = (q.d >= 0 && q.d < p->ndm) ? p->dm[(size_t)q.d] : 0.0;
+    c.toa_s = ((double)q.t + 0.5 * (double)c.width) * p->tsamp_s;
+    out[i] = c;
+  }
+  *n_found = na;
+  if (na > cap) return fail(SPS_ERR_TRUNCATED, "%d candidates found, %d returned", na, cap);
+  return SPS_OK;
+}
+
+sps_status sps_plan_autotune(sps_plan plan, int64_t nout_probe, int32_t iters, void *stream,
+                             float *ms_out, int32_t *n_tried) {
+  g_error.clear();
+  if (!plan) return fail(SPS_ERR_INVALID_ARG, "plan is NULL");
+  if (nout_probe < 1 || nout_probe > (1 << 26) || iters < 1 || iters > 100)
+    return fail(SPS_ERR_INVALID_ARG, "need 1 <= nout_probe <= 2^26 and 1 <= iters <= 100");
+  DeviceScope scope(plan->device);
+  if (scope.err != hipSuccess) return hip_fail(scope.err, "selecting the plan's device");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t nsamp = nout_probe + plan->max_delay;
+  const int64_t pitch = (nsamp + 255) / 256 * 256;
+  uint8_t *X = nullptr;
+  uint32_t *Y = nullptr;
+  hipError_t e = hipMalloc(&X, (size_t)pitch * plan->nchan);
+  if (e == hipSuccess) e = hipMalloc(&Y, sizeof(uint32_t) * (size_t)plan->ndm * nout_probe);
+  if (e == hipSuccess) e = hipMemsetAsync(X, 0x5A, (size_t)pitch * plan->nchan, s);
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  if (e == hipSuccess) e = hipEventCreate(&ev0);
+  if (e == hipSuccess) e = hipEventCreate(&ev1);
+  float best_ms = 1e30f;
+  sps::DedispConfig best_cfg = plan->cfg;
+  int best_pitch = plan->lds_pitch;
+  int tried = 0;
+  const int nprefs = (int)(sizeof(kPrefs) / sizeof(kPrefs[0]));
+  for (int i = 0; i < nprefs && e == hipSuccess; ++i) {
+    const sps::DedispConfig &c = kPrefs[i];
+    const int64_t lp = fitted_pitch(plan, c, 160 * 1024);
+    if (ms_out) ms_out[i] = -1.0f;
+    if (lp <= 0) continue;
+    e = sps::launch_dedisperse(c, (int)lp, X, pitch, nsamp, plan->d_delays, plan->nchan, plan->ndm,
+                               Y, nout_probe, s);  // warm-up
+    float total = 0.0f;
+    for (int it = 0; it < iters && e == hipSuccess; ++it) {
+      e = hipEventRecord(ev0, s);
+      if (e == hipSuccess)
+        e = sps::launch_dedisperse(c, (int)lp, X, pitch, nsamp, plan->d_delays, plan->nchan,
+                                   plan->ndm, Y, nout_probe, s);
+      if (e == hipSuccess) e = hipEventRecord(ev1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(ev1);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
+      total += ms;
+    }
+    if (e != hipSuccess) break;
+    const float mean = total / (float)iters;
+    if (ms_out) ms_out[i] = mean;
+    ++tried;
+    if (mean < best_ms) {
+      best_ms = mean;
+      best_cfg = c;
+      best_pitch = (int)lp;
+    }
+  }
+  if (ev0) (void)hipEventDestroy(ev0);
+  if (ev1) (void)hipEventDestroy(ev1);
+  if (X) (void)hipFree(X);
+  if (Y) (void)hipFree(Y);
+  if (n_tried) *n_tried = tried;
+  if (e != hipSuccess) return hip_fail(e, "autotuning");
+  if (tried == 0) return fail(SPS_ERR_RANGE, "no compiled tiling fits this plan");
+  plan->cfg = best_cfg;
+  plan->lds_pitch = best_pitch;
+  return SPS_OK;
+}
+
+int32_t sps_tiling_count(void) { return (int32_t)(sizeof(kPrefs) / sizeof(kPrefs[0])); }
+
+sps_status sps_tiling_describe(int32_t index, int32_t *m, int32_t *dpw, int32_t *nw, int32_t *cs,
+                               int32_t *waves_per_eu) {
+  g_error.clear();
+  if (index < 0 || index >= sps_tiling_count()) return fail(SPS_ERR_RANGE, "index out of range");
+  const sps::DedispConfig &c = kPrefs[index];
+  if (m) *m = c.m;
+  if (dpw) *dpw = c.dpw;
+  if (nw) *nw = c.nw;
+  if (cs) *cs = c.cs;
+  if (waves_per_eu) *waves_per_eu = c.wpe;
   return SPS_OK;
 }
 

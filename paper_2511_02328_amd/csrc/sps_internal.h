@@ -33,6 +33,32 @@ int dedisp_block_spread(const int32_t *delays_host, int nchan, int ndm, int nd);
 // True if the config is one the library instantiates.
 bool dedisp_config_supported(const DedispConfig &cfg);
 
+// Per-filterbank work description of a batched call (device memory).  The
+// *_begin fields are exclusive prefix sums of each kernel's work items over
+// the preceding beams.
+struct BeamWork {
+  const uint8_t *X;
+  int64_t pitch;
+  int64_t nsamp_in;
+  uint32_t *Y;
+  int64_t nout;
+  float *snr;
+  uint8_t *best;
+  int32_t *stats;
+  int64_t dd_begin;     // dedispersion items (time tile x DM block)
+  int64_t bx_begin;     // boxcar workgroups (DM row x segment)
+  int64_t tp_begin;     // detection tiles
+  int64_t nseg;         // boxcar segments per row
+  int64_t ntt;          // detection tiles along time
+  int32_t vec_store;
+  int32_t pad;
+};
+
+int64_t dedisp_batch_items(const DedispConfig &c, int ndm, int64_t nout);
+hipError_t launch_dedisperse_batch(const DedispConfig &c, int lds_pitch, const BeamWork *beams,
+                                   int nbeams, int64_t total_items, const int32_t *D, int nchan,
+                                   int ndm, int grid, hipStream_t stream);
+
 hipError_t launch_dedisperse(const DedispConfig &cfg, int lds_pitch, const uint8_t *X,
                              int64_t pitch, int64_t nsamp_in, const int32_t *D, int nchan,
                              int ndm, uint32_t *Y, int64_t nout, hipStream_t stream);
@@ -72,5 +98,24 @@ hipError_t launch_tile_peaks(const float *snr, const uint8_t *best, int ndm, int
 hipError_t launch_select_nms(const TilePeak *peaks, int ndm, int64_t nout, int tile_dm,
                              int64_t tile_t, float threshold, int nms_dm, int64_t nms_t,
                              TilePeak *out, int32_t *status, hipStream_t stream);
+
+hipError_t launch_subband_stage2(const uint32_t *I, int64_t len1, int ncoarse, int nsub,
+                                 const int32_t *R, int ndm, int n0, uint32_t *Y, int64_t nout,
+                                 hipStream_t stream);
+hipError_t launch_zero_dm(const uint8_t *X, int64_t pitch, int64_t nsamp, int nchan, uint8_t *Xo,
+                          int64_t pitch_out, hipStream_t stream);
+hipError_t launch_downsample_sqrt(const uint8_t *X, int64_t pitch, int64_t nsamp, int nchan,
+                                  int factor, uint8_t *Xo, int64_t pitch_out,
+                                  hipStream_t stream);
+
+hipError_t launch_row_stats_batch(const BeamWork *beams, int nbeams, int ndm, uint32_t vmax,
+                                  hipStream_t stream);
+hipError_t launch_boxcar_batch(const BeamWork *beams, int nbeams, int64_t total_blocks,
+                               const WidthList &widths, hipStream_t stream);
+int64_t boxcar_segments(int64_t nout);
+hipError_t launch_detect_batch(const BeamWork *beams, int nbeams, int ndm, int64_t total_tiles,
+                               int tile_dm, int64_t tile_t, float threshold, int nms_dm,
+                               int64_t nms_t, TilePeak *peaks, TilePeak *out, int32_t *status,
+                               hipStream_t stream);
 
 }  // namespace sps

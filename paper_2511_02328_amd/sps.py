@@ -46,6 +46,19 @@ class sps_candidate(ctypes.Structure):
                 ("toa_s", ctypes.c_double)]
 
 
+class sps_subband_desc(ctypes.Structure):
+    _fields_ = [("nchan", ctypes.c_int32), ("freq_mhz", ctypes.POINTER(ctypes.c_double)),
+                ("fref_mhz", ctypes.c_double), ("tsamp_s", ctypes.c_double),
+                ("ndm", ctypes.c_int32), ("dm_lo", ctypes.c_double), ("dm_step", ctypes.c_double),
+                ("n0", ctypes.c_int32), ("nsub", ctypes.c_int32)]
+
+
+class sps_beam(ctypes.Structure):
+    _fields_ = [("X", ctypes.c_void_p), ("pitch", ctypes.c_int64), ("nsamp_in", ctypes.c_int64),
+                ("Y", ctypes.c_void_p), ("nout", ctypes.c_int64), ("snr", ctypes.c_void_p),
+                ("best_w", ctypes.c_void_p), ("stats", ctypes.c_void_p)]
+
+
 class sps_detect_params(ctypes.Structure):
     _fields_ = [("threshold", ctypes.c_float), ("tile_dm", ctypes.c_int32),
                 ("tile_t", ctypes.c_int64), ("nms_dm", ctypes.c_int32), ("nms_t", ctypes.c_int64)]
@@ -71,8 +84,28 @@ def library() -> ctypes.CDLL:
                                    ctypes.POINTER(sps_candidate), i32, ctypes.POINTER(i32), P]
         lib.sps_plan_set_tiling.argtypes = [P, i32, i32, i32, i32, i32]
         lib.sps_plan_get_tiling.argtypes = [P] + [ctypes.POINTER(i32)] * 6
+        lib.sps_subband_plan_create.argtypes = [ctypes.POINTER(sps_subband_desc), ctypes.POINTER(P)]
+        lib.sps_subband_tables.argtypes = [P, P, P, P, ctypes.POINTER(i32)]
+        lib.sps_dedisperse_subband.argtypes = [P, P, i64, i64, P, i64, u32, P]
+        lib.sps_zero_dm.argtypes = [P, i64, i64, i32, P, i64, P]
+        lib.sps_downsample_sqrt.argtypes = [P, i64, i64, i32, i32, P, i64, P]
+        lib.sps_batch_create.argtypes = [P, i32, ctypes.POINTER(sps_beam), P, i32,
+                                         ctypes.POINTER(sps_detect_params), u32, ctypes.POINTER(P)]
+        lib.sps_batch_destroy.argtypes = [P]
+        lib.sps_batch_enqueue.argtypes = [P, P]
+        lib.sps_batch_launch_graph.argtypes = [P, P]
+        lib.sps_batch_candidates.argtypes = [P, i32, ctypes.POINTER(sps_candidate), i32,
+                                             ctypes.POINTER(i32), P]
+        lib.sps_plan_autotune.argtypes = [P, i64, i32, P, P, ctypes.POINTER(i32)]
+        lib.sps_tiling_count.argtypes = []
+        lib.sps_tiling_count.restype = i32
+        lib.sps_tiling_describe.argtypes = [i32] + [ctypes.POINTER(i32)] * 5
         for f in ("sps_plan_create", "sps_plan_destroy", "sps_plan_delays", "sps_dedisperse",
-                  "sps_boxcar_snr", "sps_detect", "sps_plan_set_tiling", "sps_plan_get_tiling"):
+                  "sps_boxcar_snr", "sps_detect", "sps_plan_set_tiling", "sps_plan_get_tiling",
+                  "sps_subband_plan_create", "sps_subband_tables", "sps_dedisperse_subband",
+                  "sps_zero_dm", "sps_downsample_sqrt", "sps_batch_create", "sps_batch_destroy",
+                  "sps_batch_enqueue", "sps_batch_launch_graph", "sps_batch_candidates",
+                  "sps_plan_autotune", "sps_tiling_describe"):
             getattr(lib, f).restype = ctypes.c_int
         lib.sps_last_error.argtypes = []
         lib.sps_last_error.restype = ctypes.c_char_p
@@ -85,7 +118,8 @@ def header_functions() -> list:
     hdr = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
                        "include", "sps.h")
     text = open(hdr).read()
-    return sorted(set(re.findall(r"^\s*(?:sps_status|const char \*)\s*(sps_\w+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:sps_status|const char \*|int32_t)\s*(sps_\w+)\s*\(",
+                                 text, re.M)))
 
 
 def sps_last_error() -> str:
@@ -219,6 +253,157 @@ def sps_detect(plan: Plan, snr: torch.Tensor, best_w: torch.Tensor, nout: int,
     k = min(int(n.value), cap)
     arr = np.frombuffer(bytes(out)[:k * ctypes.sizeof(sps_candidate)], dtype=CANDIDATE_DTYPE).copy()
     return arr, int(n.value)
+
+
+def sps_subband_plan_create(freq_mhz: Sequence[float], fref_mhz: float, tsamp_s: float, ndm: int,
+                            dm_lo: float, dm_step: float, n0: int, nsub: int) -> Plan:
+    f = np.ascontiguousarray(freq_mhz, dtype=np.float64)
+    desc = sps_subband_desc(f.size, f.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                            float(fref_mhz), float(tsamp_s), int(ndm), float(dm_lo),
+                            float(dm_step), int(n0), int(nsub))
+    h = ctypes.c_void_p()
+    _check(library().sps_subband_plan_create(ctypes.byref(desc), ctypes.byref(h)),
+           "sps_subband_plan_create")
+    plan = Plan(h.value, f.size, int(ndm))
+    plan.n0, plan.nsub = int(n0), int(nsub)
+    return plan
+
+
+def sps_subband_tables(plan: Plan):
+    """(coarse delays [ceil(ndm/n0)][nchan], residuals [ndm][nsub], F_s [nsub], max delay)."""
+    nc = (plan.ndm + plan.n0 - 1) // plan.n0
+    Dc = np.empty((nc, plan.nchan), dtype=np.int32)
+    R = np.empty((plan.ndm, plan.nsub), dtype=np.int32)
+    F = np.empty(plan.nsub, dtype=np.float64)
+    mx = ctypes.c_int32()
+    _check(library().sps_subband_tables(plan.handle, Dc.ctypes.data, R.ctypes.data,
+                                        F.ctypes.data, ctypes.byref(mx)), "sps_subband_tables")
+    return Dc, R, F, int(mx.value)
+
+
+def sps_dedisperse_subband(plan: Plan, X: torch.Tensor, nsamp_in: int, Y: torch.Tensor, nout: int,
+                           flags: int = 0, stream=None) -> None:
+    if X.dim() != 2 or X.stride(1) != 1:
+        raise ValueError("X must be [nchan][pitch] with unit sample stride")
+    if Y.dim() != 2 or not Y.is_contiguous():
+        raise ValueError("Y must be a contiguous [ndm][nout] tensor")
+    xp = _dev(X, torch.uint8, "X")
+    yp = _dev(Y, torch.int32, "Y") if Y.dtype == torch.int32 else _dev(Y, torch.uint32, "Y")
+    _check(library().sps_dedisperse_subband(plan.handle, xp, X.stride(0), int(nsamp_in), yp,
+                                            int(nout), int(flags), _stream(stream)),
+           "sps_dedisperse_subband")
+
+
+def sps_zero_dm(X: torch.Tensor, nsamp: int, Xo: torch.Tensor, stream=None) -> None:
+    if X.stride(1) != 1 or Xo.stride(1) != 1 or X.shape[0] != Xo.shape[0]:
+        raise ValueError("X and Xo must be [nchan][pitch] with unit sample stride")
+    _check(library().sps_zero_dm(_dev(X, torch.uint8, "X"), X.stride(0), int(nsamp), X.shape[0],
+                                 _dev(Xo, torch.uint8, "Xo"), Xo.stride(0), _stream(stream)),
+           "sps_zero_dm")
+
+
+def sps_downsample_sqrt(X: torch.Tensor, nsamp: int, factor: int, Xo: torch.Tensor,
+                        stream=None) -> None:
+    if X.stride(1) != 1 or Xo.stride(1) != 1 or X.shape[0] != Xo.shape[0]:
+        raise ValueError("X and Xo must be [nchan][pitch] with unit sample stride")
+    _check(library().sps_downsample_sqrt(_dev(X, torch.uint8, "X"), X.stride(0), int(nsamp),
+                                         X.shape[0], int(factor), _dev(Xo, torch.uint8, "Xo"),
+                                         Xo.stride(0), _stream(stream)), "sps_downsample_sqrt")
+
+
+class Batch:
+    """Owns an sps_batch handle and keeps its plan and tensors alive."""
+
+    def __init__(self, handle, plan, keep, widths):
+        self.handle, self.plan, self._keep, self.widths = handle, plan, keep, widths
+
+    def close(self) -> None:
+        if self.handle:
+            sps_batch_destroy(self)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def sps_batch_create(plan: Plan, beams: Sequence[dict], widths: Sequence[int], threshold: float,
+                     tile_dm: int, tile_t: int, nms_dm: int, nms_t: int, flags: int = 0) -> Batch:
+    """beams: dicts with tensors X, Y, snr, best_w, stats and ints nsamp_in, nout."""
+    arr = (sps_beam * len(beams))()
+    keep = []
+    for i, b in enumerate(beams):
+        X, Y = b["X"], b["Y"]
+        if X.dim() != 2 or X.stride(1) != 1:
+            raise ValueError("X must be [nchan][pitch] with unit sample stride")
+        yp = _dev(Y, torch.int32, "Y") if Y.dtype == torch.int32 else _dev(Y, torch.uint32, "Y")
+        arr[i] = sps_beam(_dev(X, torch.uint8, "X"), X.stride(0), int(b["nsamp_in"]), yp,
+                          int(b["nout"]), _dev(b["snr"], torch.float32, "snr"),
+                          _dev(b["best_w"], torch.uint8, "best_w"),
+                          _dev(b["stats"], torch.int32, "stats"))
+        keep.append(b)
+    w = np.ascontiguousarray(widths, dtype=np.int32)
+    prm = sps_detect_params(float(threshold), int(tile_dm), int(tile_t), int(nms_dm), int(nms_t))
+    h = ctypes.c_void_p()
+    _check(library().sps_batch_create(plan.handle, len(beams), arr, w.ctypes.data, w.size,
+                                      ctypes.byref(prm), int(flags), ctypes.byref(h)),
+           "sps_batch_create")
+    return Batch(h.value, plan, keep, [int(x) for x in w])
+
+
+def sps_batch_destroy(batch: Batch) -> None:
+    h, batch.handle = batch.handle, None
+    if h:
+        _check(library().sps_batch_destroy(h), "sps_batch_destroy")
+
+
+def sps_batch_enqueue(batch: Batch, stream=None) -> None:
+    _check(library().sps_batch_enqueue(batch.handle, _stream(stream)), "sps_batch_enqueue")
+
+
+def sps_batch_launch_graph(batch: Batch, stream) -> None:
+    _check(library().sps_batch_launch_graph(batch.handle, _stream(stream)), "sps_batch_launch_graph")
+
+
+def sps_batch_candidates(batch: Batch, beam: int, cap: int = 4096, stream=None,
+                         allow_truncated: bool = False):
+    out = (sps_candidate * max(cap, 1))()
+    n = ctypes.c_int32()
+    rc = library().sps_batch_candidates(batch.handle, int(beam), out, int(cap), ctypes.byref(n),
+                                        _stream(stream))
+    if not (rc == 6 and allow_truncated):
+        _check(rc, "sps_batch_candidates")
+    k = min(int(n.value), cap)
+    arr = np.frombuffer(bytes(out)[:k * ctypes.sizeof(sps_candidate)], dtype=CANDIDATE_DTYPE).copy()
+    return arr, int(n.value)
+
+
+def sps_tiling_count() -> int:
+    return int(library().sps_tiling_count())
+
+
+def sps_tiling_describe(index: int) -> dict:
+    v = [ctypes.c_int32() for _ in range(5)]
+    _check(library().sps_tiling_describe(int(index), *[ctypes.byref(x) for x in v]),
+           "sps_tiling_describe")
+    return dict(zip(("m", "dpw", "nw", "cs", "waves_per_eu"), (x.value for x in v)))
+
+
+def sps_plan_autotune(plan: Plan, nout_probe: int, iters: int = 3, stream=None) -> list:
+    """Mean ms per compiled tiling (-1 where it does not fit); keeps the fastest."""
+    n = sps_tiling_count()
+    ms = np.full(n, -1.0, dtype=np.float32)
+    tried = ctypes.c_int32()
+    _check(library().sps_plan_autotune(plan.handle, int(nout_probe), int(iters), _stream(stream),
+                                       ms.ctypes.data, ctypes.byref(tried)), "sps_plan_autotune")
+    return [float(x) for x in ms]
 
 
 def plan_for(wl) -> Plan:

@@ -74,7 +74,8 @@ def draw_events(wl: Workload, nsamp_in: int, seed: Optional[int] = None) -> Trut
         dm = rng.uniform(*pm.dm_range)
         fw = math.exp(rng.uniform(math.log(pm.fwhm_range_s[0]), math.log(pm.fwhm_range_s[1])))
         amp = rng.uniform(*pm.amp_range_sigma) * sig
-        toa = rng.uniform(3 * fw, span - 3 * fw)
+        lo = min(3 * fw, span / 2)
+        toa = rng.uniform(lo, max(span - 3 * fw, lo))
         pulses.append(Pulse(dm, fw, amp, toa))
     rm = wl.rfi
     sines = []

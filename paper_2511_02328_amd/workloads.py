@@ -108,4 +108,41 @@ FULL_SCALE = Workload(
     seed=2,
 )
 
+@dataclass(frozen=True)
+class BatchWorkload:
+    """Many beams of one receiver searched together: each beam has the base
+    workload's band, sampling and DM grid, its own chunk length (drawn from
+    `lengths`, seeded) and its own noise, pulses and RFI."""
+    name: str
+    base: Workload
+    nbeams: int
+    lengths: Tuple[int, ...]
+    seed: int
+
+    def beam_lengths(self) -> list:
+        rng = np.random.Generator(np.random.PCG64(self.seed))
+        return [int(x) for x in rng.choice(self.lengths, size=self.nbeams)]
+
+    def beam_seeds(self) -> list:
+        return [int(s.generate_state(1)[0] & 0x7FFFFFFF)
+                for s in np.random.SeedSequence(self.seed).spawn(self.nbeams)]
+
+    def beam_workload(self, i: int, nout: int) -> Workload:
+        from dataclasses import replace
+        return replace(self.base, name=f"{self.name}_beam{i}", nout=nout, seed=self.beam_seeds()[i])
+
+
+# 19 beams shaped like the single-beam set-up (256 channels, 98.304 us,
+# 512 DMs 0-1000, widths 1..64), chunks of 2^18, 2^19 or 2^20 samples, each
+# with its own pulses (DM 50-1000) and RFI.
+BATCHED = BatchWorkload(
+    name="batched_19beams_256ch_512dm",
+    base=Workload(name="batched_beam", nchan=256, f_lo_mhz=1000.0, f_hi_mhz=1500.0,
+                  tsamp_s=98.304e-6, nout=1 << 18, ndm=512, dm_lo=0.0, dm_hi=1000.0,
+                  widths=(1, 2, 4, 8, 16, 32, 64),
+                  pulses=PulseModel(count=4, dm_range=(50.0, 1000.0)),
+                  rfi=RfiModel(chan_fraction=0.05, n_impulses=4)),
+    nbeams=19, lengths=(1 << 18, 1 << 19, 1 << 20), seed=3)
+
 WORKLOADS = {w.name: w for w in (SINGLE_BEAM, FULL_SCALE)}
+BATCH_WORKLOADS = {BATCHED.name: BATCHED}

@@ -1,0 +1,127 @@
+"""GPU parity of the batched path (many beams of one plan in persistent
+launches, optionally replayed from a HIP graph) against the single-beam calls
+and the oracle, and of the autotuner's choice."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from paper_2511_02328_amd import synth  # noqa: E402
+from paper_2511_02328_amd.workloads import SINGLE_BEAM, Workload, PulseModel  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DET = dict(threshold=7.0, tile_dm=16, tile_t=1024, nms_dm=8, nms_t=64)
+
+
+@pytest.fixture(scope="module")
+def sps():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2511_02328_amd import sps as mod
+    mod.library()
+    return mod
+
+
+def _wl(nout, seed):
+    return Workload("b", 256, 1000.0, 1500.0, 98.304e-6, nout, 64, 0.0, 300.0, (1, 2, 4, 8, 16),
+                    pulses=PulseModel(count=2, dm_range=(30.0, 280.0)), seed=seed)
+
+
+def _beams(sps, plan, nouts, dmax, pad):
+    beams = []
+    for i, nout in enumerate(nouts):
+        wl = _wl(nout, 100 + i)
+        nsamp = nout + dmax
+        X, _ = synth.make_filterbank(wl, nsamp)
+        p = ((nsamp + 15) // 16) * 16 + 16 * pad
+        Xd = torch.zeros((wl.nchan, p), dtype=torch.uint8, device="cuda")
+        Xd[:, :nsamp] = torch.from_numpy(X).cuda()
+        beams.append(dict(X=Xd, Xh=X, nsamp_in=nsamp, nout=nout,
+                          Y=torch.zeros((64, nout), dtype=torch.int32, device="cuda"),
+                          snr=torch.zeros((64, nout), dtype=torch.float32, device="cuda"),
+                          best_w=torch.zeros((64, nout), dtype=torch.uint8, device="cuda"),
+                          stats=torch.zeros((64, 2), dtype=torch.int32, device="cuda")))
+    return beams
+
+
+def _single(sps, plan, b, widths):
+    Y = torch.empty_like(b["Y"])
+    snr = torch.empty_like(b["snr"])
+    best = torch.empty_like(b["best_w"])
+    st = torch.empty_like(b["stats"])
+    sps.sps_dedisperse(plan, b["X"], b["nsamp_in"], Y, b["nout"])
+    sps.sps_boxcar_snr(plan, Y, b["nout"], widths, snr, best, st)
+    c, n = sps.sps_detect(plan, snr, best, b["nout"], widths, **DET)
+    return Y, st, snr, best, c, n
+
+
+def _check_beams(sps, plan, batch, beams, widths):
+    for i, b in enumerate(beams):
+        Y, st, snr, best, c, n = _single(sps, plan, b, widths)
+        assert torch.equal(b["Y"], Y), f"beam {i} dedispersion"
+        assert torch.equal(b["stats"], st), f"beam {i} stats"
+        assert torch.equal(b["snr"], snr) and torch.equal(b["best_w"], best), f"beam {i} S/N"
+        cb, nb = sps.sps_batch_candidates(batch, i)
+        assert nb == n and np.array_equal(cb, c), f"beam {i} candidates"
+
+
+@pytest.mark.parametrize("nouts", [[3000, 5000, 1281, 7777, 4096], [16], [20000] * 3])
+def test_batch_equals_single_calls(sps, nouts):
+    wl = _wl(nouts[0], 0)
+    widths = list(wl.widths)
+    with sps.plan_for(wl) as plan:
+        _, dmax = sps.sps_plan_delays(plan)
+        beams = _beams(sps, plan, nouts, dmax, pad=1)
+        with sps.sps_batch_create(plan, beams, widths, **DET) as batch:
+            sps.sps_batch_enqueue(batch)
+            torch.cuda.synchronize()
+            _check_beams(sps, plan, batch, beams, widths)
+        # and against the oracle for the first beam
+        D = oracle.delays(wl.freqs_mhz(), wl.fref_mhz, wl.tsamp_s, wl.dms())
+        Yo = oracle.dedisperse(beams[0]["Xh"], D, nouts[0])
+        assert np.array_equal(beams[0]["Y"].cpu().numpy().view(np.uint32), Yo)
+
+
+def test_graph_replays_match_eager(sps):
+    nouts = [4000, 2500, 9000, 1300]
+    wl = _wl(nouts[0], 0)
+    widths = list(wl.widths)
+    stream = torch.cuda.Stream()
+    with sps.plan_for(wl) as plan:
+        _, dmax = sps.sps_plan_delays(plan)
+        beams = _beams(sps, plan, nouts, dmax, pad=0)
+        with sps.sps_batch_create(plan, beams, widths, **DET) as batch:
+            for rep in range(3):
+                with torch.cuda.stream(stream):
+                    # eager work between replays: new data in one beam
+                    beams[rep % len(beams)]["X"][:, :64].random_(0, 256)
+                    for b in beams:
+                        b["Y"].zero_()
+                        b["snr"].zero_()
+                    sps.sps_batch_launch_graph(batch, stream)
+                stream.synchronize()
+                _check_beams(sps, plan, batch, beams, widths)
+
+
+def test_autotune_keeps_results(sps):
+    wl = SINGLE_BEAM
+    with sps.plan_for(wl) as plan:
+        _, dmax = sps.sps_plan_delays(plan)
+        X = synth.random_bytes(wl.nchan, wl.nout + dmax, seed=5)
+        Xd = torch.zeros((wl.nchan, ((wl.nout + dmax + 15) // 16) * 16), dtype=torch.uint8,
+                         device="cuda")
+        Xd[:, :wl.nout + dmax] = torch.from_numpy(X).cuda()
+        Y0 = torch.empty((wl.ndm, wl.nout), dtype=torch.int32, device="cuda")
+        sps.sps_dedisperse(plan, Xd, wl.nout + dmax, Y0, wl.nout)
+        ms = sps.sps_plan_autotune(plan, 8192, 2)
+        assert sum(m > 0 for m in ms) >= 2
+        chosen = sps.sps_plan_get_tiling(plan)
+        fastest = min((m, i) for i, m in enumerate(ms) if m > 0)[1]
+        d = sps.sps_tiling_describe(fastest)
+        assert all(chosen[k] == d[k] for k in ("m", "dpw", "nw", "cs", "waves_per_eu"))
+        Y1 = torch.empty_like(Y0)
+        sps.sps_dedisperse(plan, Xd, wl.nout + dmax, Y1, wl.nout)
+        torch.cuda.synchronize()
+        assert torch.equal(Y0, Y1)
