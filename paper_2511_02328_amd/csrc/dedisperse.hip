@@ -413,15 +413,13 @@ int dedisp_block_spread(const int32_t *Dh, int nchan, int ndm, int nd) {
 // Compiled tilings: (m, dpw, nw, cs, kmax, waves per EU).  kmax bounds the
 // staged row length (lds_pitch <= 1024 kmax bytes).
 #define SPS_DEDISP_CONFIGS(X) \
-  X(5, 2, 8, 16, 2, 4)        \
-  X(5, 2, 8, 16, 4, 4)        \
   X(5, 1, 16, 16, 2, 8)       \
   X(5, 1, 16, 16, 2, 4)       \
   X(5, 1, 16, 16, 4, 4)       \
-  X(3, 2, 8, 16, 2, 4)        \
   X(3, 1, 16, 16, 2, 8)       \
   X(7, 1, 16, 16, 3, 4)       \
-  X(5, 2, 16, 16, 2, 4)
+  X(5, 1, 8, 8, 5, 4)         \
+  X(5, 1, 8, 8, 8, 4)
 
 bool dedisp_config_supported(const DedispConfig &c) {
 #define SPS_MATCH(m_, dpw_, nw_, cs_, kmax_, wpe_)                                      \

@@ -106,9 +106,8 @@ void free_plan(sps_plan p) {
 
 // Compiled tilings in order of preference (see dedisperse.hip).
 const sps::DedispConfig kPrefs[] = {
-    {5, 1, 16, 16, 2, 8}, {5, 2, 8, 16, 2, 4}, {5, 1, 16, 16, 2, 4}, {5, 2, 16, 16, 2, 4},
-    {5, 2, 8, 16, 4, 4}, {5, 1, 16, 16, 4, 4}, {3, 2, 8, 16, 2, 4}, {3, 1, 16, 16, 2, 8},
-    {7, 1, 16, 16, 3, 4}};
+    {5, 1, 16, 16, 2, 8}, {5, 1, 16, 16, 2, 4}, {5, 1, 16, 16, 4, 4}, {3, 1, 16, 16, 2, 8},
+    {7, 1, 16, 16, 3, 4}, {5, 1, 8, 8, 5, 4},   {5, 1, 8, 8, 8, 4}};
 
 // Staged-row bytes of config c for a delay table, or -1 if it does not fit.
 int64_t fitted_pitch(const int32_t *D, int nchan, int ndm, const sps::DedispConfig &c,
