@@ -285,6 +285,80 @@ int32_t sps_tiling_count(void);
 sps_status sps_tiling_describe(int32_t index, int32_t *m, int32_t *dpw, int32_t *nw, int32_t *cs,
                                int32_t *waves_per_eu);
 
+/* ---- Streaming: many real-time filterbank streams on one GPU ---- */
+
+/* A server searches admitted streams chunk by chunk.  Each stream keeps a
+ * device ring of nchan x (D_max + chunk_len) bytes: the last D_max samples of
+ * the previous chunk (the dispersion overlap of the time blocking in
+ * Sec. 2.3), then the new chunk, so chunk k's outputs are the dedispersed
+ * series at absolute samples [k chunk_len - D_max, (k+1) chunk_len - D_max)
+ * of the stream (the overlap is zero before chunk 0).  Worker w owns a HIP
+ * stream, one plan per observing set-up and output planes sized for the
+ * largest stream; streams of one set-up share its plans. */
+typedef struct sps_server_s *sps_server;
+
+/* hbm_budget: device bytes the server may hold (rings, plans, planes);
+ * 1 <= nworkers <= 16.  Uses the current device. */
+sps_status sps_server_create(int64_t hbm_budget, int32_t nworkers, sps_server *out);
+/* Waits for outstanding work and frees everything. */
+sps_status sps_server_destroy(sps_server server);
+
+/* Admits a stream: desc as for sps_plan_create, widths/nw and det as for
+ * sps_boxcar_snr / sps_detect, chunk_len >= largest width.  NOMEM (nothing
+ * allocated) when ring + new plans + plane growth would exceed the budget.
+ * *stream_id numbers streams 0, 1, ... in admission order. */
+sps_status sps_server_add_stream(sps_server server, const sps_obs_desc *desc,
+                                 const int32_t *widths, int32_t nw, const sps_detect_params *det,
+                                 int64_t chunk_len, int32_t *stream_id);
+/* Device bytes accounted so far and the budget. */
+sps_status sps_server_memory(sps_server server, int64_t *used, int64_t *budget);
+/* Chunk length, overlap D_max (samples) and chunk duration (s) of a stream. */
+sps_status sps_server_stream_info(sps_server server, int32_t stream_id, int64_t *chunk_len,
+                                  int64_t *overlap, double *duration_s);
+
+/* Searches the stream's next chunk now, on worker 0, and waits for it.
+ * host: [nchan][src_pitch] bytes (pinned memory for speed), first chunk_len
+ * of each row used.  Y_copy (optional): device [ndm][chunk_len] that receives
+ * the dedispersed plane.  out/cap/n_found and TRUNCATED as in sps_detect.
+ * Must not overlap sps_server_run. */
+sps_status sps_server_push(sps_server server, int32_t stream_id, const uint8_t *host,
+                           int64_t src_pitch, uint32_t *Y_copy, sps_candidate *out, int32_t cap,
+                           int32_t *n_found);
+
+/* Source of a stream's chunks in sps_server_run: nsrc chunks of
+ * [nchan][src_pitch] bytes back to back at host; chunk k of the run reads
+ * source (first + k) % nsrc. */
+typedef struct {
+  const uint8_t *host;
+  int64_t src_pitch;
+  int32_t nsrc;
+  int32_t first;
+} sps_feed;
+
+/* One searched chunk: times in seconds from the start of the run. */
+typedef struct {
+  int32_t stream;
+  int32_t worker;
+  int64_t index;    /* chunk number within the run */
+  double arrival_s; /* scheduled arrival */
+  double start_s;   /* a worker took it */
+  double end_s;     /* candidates on the host */
+  int32_t n_cand;   /* candidates found (true count) */
+  int32_t status;   /* sps_status of the chunk */
+} sps_chunk_record;
+
+/* Serves every admitted stream for run_s seconds of wall clock: stream i's
+ * chunk k arrives at phase_i + (k+1) T_i / compression (T_i = chunk_len *
+ * tsamp, phase_i = i T_i / (compression * nstreams)); arrivals after run_s are
+ * not issued, and the call returns when every issued chunk is searched.
+ * Workers take chunks in arrival order, a stream's chunks in sequence.
+ * records (cap entries) receive one record per chunk in arrival order;
+ * *n_records is the true count (TRUNCATED if above cap).  A failing chunk
+ * stops the run and its status is returned. */
+sps_status sps_server_run(sps_server server, const sps_feed *feeds, double run_s,
+                          double compression, sps_chunk_record *records, int32_t cap,
+                          int32_t *n_records);
+
 /* Message for the last failed call on this thread ("" if none). */
 const char *sps_last_error(void);
 

@@ -56,6 +56,10 @@ struct DeviceScope {
 
 }  // namespace
 
+namespace sps {
+sps_status set_error(sps_status s, const char *msg) { return fail(s, "%s", msg); }
+}  // namespace sps
+
 struct sps_plan_s {
   int device = 0;
   int nchan = 0, ndm = 0;

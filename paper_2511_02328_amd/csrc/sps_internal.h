@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "sps.h"
+
 namespace sps {
 
 // Tile configuration of the dedispersion kernel.
@@ -107,6 +109,10 @@ hipError_t launch_zero_dm(const uint8_t *X, int64_t pitch, int64_t nsamp, int nc
 hipError_t launch_downsample_sqrt(const uint8_t *X, int64_t pitch, int64_t nsamp, int nchan,
                                   int factor, uint8_t *Xo, int64_t pitch_out,
                                   hipStream_t stream);
+
+// Records msg as the calling thread's last error (sps_last_error) and
+// returns s.
+sps_status set_error(sps_status s, const char *msg);
 
 hipError_t launch_row_stats_batch(const BeamWork *beams, int nbeams, int ndm, uint32_t vmax,
                                   hipStream_t stream);

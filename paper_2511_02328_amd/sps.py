@@ -64,6 +64,17 @@ class sps_detect_params(ctypes.Structure):
                 ("tile_t", ctypes.c_int64), ("nms_dm", ctypes.c_int32), ("nms_t", ctypes.c_int64)]
 
 
+class sps_feed(ctypes.Structure):
+    _fields_ = [("host", ctypes.c_void_p), ("src_pitch", ctypes.c_int64), ("nsrc", ctypes.c_int32),
+                ("first", ctypes.c_int32)]
+
+
+class sps_chunk_record(ctypes.Structure):
+    _fields_ = [("stream", ctypes.c_int32), ("worker", ctypes.c_int32), ("index", ctypes.c_int64),
+                ("arrival_s", ctypes.c_double), ("start_s", ctypes.c_double),
+                ("end_s", ctypes.c_double), ("n_cand", ctypes.c_int32), ("status", ctypes.c_int32)]
+
+
 _lib = None
 
 
@@ -100,6 +111,23 @@ def library() -> ctypes.CDLL:
         lib.sps_tiling_count.argtypes = []
         lib.sps_tiling_count.restype = i32
         lib.sps_tiling_describe.argtypes = [i32] + [ctypes.POINTER(i32)] * 5
+        lib.sps_server_create.argtypes = [i64, i32, ctypes.POINTER(P)]
+        lib.sps_server_destroy.argtypes = [P]
+        lib.sps_server_add_stream.argtypes = [P, ctypes.POINTER(sps_obs_desc), P, i32,
+                                              ctypes.POINTER(sps_detect_params), i64,
+                                              ctypes.POINTER(i32)]
+        lib.sps_server_memory.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+        lib.sps_server_stream_info.argtypes = [P, i32, ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                               ctypes.POINTER(ctypes.c_double)]
+        lib.sps_server_push.argtypes = [P, i32, P, i64, P, ctypes.POINTER(sps_candidate), i32,
+                                        ctypes.POINTER(i32)]
+        lib.sps_server_run.argtypes = [P, ctypes.POINTER(sps_feed), ctypes.c_double,
+                                       ctypes.c_double, ctypes.POINTER(sps_chunk_record), i32,
+                                       ctypes.POINTER(i32)]
+        for f in ("sps_server_create", "sps_server_destroy", "sps_server_add_stream",
+                  "sps_server_memory", "sps_server_stream_info", "sps_server_push",
+                  "sps_server_run"):
+            getattr(lib, f).restype = ctypes.c_int
         for f in ("sps_plan_create", "sps_plan_destroy", "sps_plan_delays", "sps_dedisperse",
                   "sps_boxcar_snr", "sps_detect", "sps_plan_set_tiling", "sps_plan_get_tiling",
                   "sps_subband_plan_create", "sps_subband_tables", "sps_dedisperse_subband",
@@ -404,6 +432,131 @@ def sps_plan_autotune(plan: Plan, nout_probe: int, iters: int = 3, stream=None) 
     _check(library().sps_plan_autotune(plan.handle, int(nout_probe), int(iters), _stream(stream),
                                        ms.ctypes.data, ctypes.byref(tried)), "sps_plan_autotune")
     return [float(x) for x in ms]
+
+
+class Server:
+    """Owns an sps_server handle and keeps the feeds of a run alive."""
+
+    def __init__(self, handle):
+        self.handle = handle
+        self.widths = {}
+
+    def close(self) -> None:
+        if self.handle:
+            sps_server_destroy(self)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+RECORD_DTYPE = np.dtype([("stream", np.int32), ("worker", np.int32), ("index", np.int64),
+                         ("arrival_s", np.float64), ("start_s", np.float64),
+                         ("end_s", np.float64), ("n_cand", np.int32), ("status", np.int32)])
+
+
+def sps_server_create(hbm_budget: int, nworkers: int) -> Server:
+    h = ctypes.c_void_p()
+    _check(library().sps_server_create(int(hbm_budget), int(nworkers), ctypes.byref(h)),
+           "sps_server_create")
+    return Server(h.value)
+
+
+def sps_server_destroy(server: Server) -> None:
+    h, server.handle = server.handle, None
+    if h:
+        _check(library().sps_server_destroy(h), "sps_server_destroy")
+
+
+def sps_server_add_stream(server: Server, freq_mhz: Sequence[float], fref_mhz: float,
+                          tsamp_s: float, dm: Sequence[float], widths: Sequence[int],
+                          threshold: float, tile_dm: int, tile_t: int, nms_dm: int, nms_t: int,
+                          chunk_len: int) -> int:
+    f = np.ascontiguousarray(freq_mhz, dtype=np.float64)
+    m = np.ascontiguousarray(dm, dtype=np.float64)
+    desc = sps_obs_desc(f.size, f.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(fref_mhz),
+                        float(tsamp_s), m.size, m.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    w = np.ascontiguousarray(widths, dtype=np.int32)
+    prm = sps_detect_params(float(threshold), int(tile_dm), int(tile_t), int(nms_dm), int(nms_t))
+    sid = ctypes.c_int32()
+    _check(library().sps_server_add_stream(server.handle, ctypes.byref(desc), w.ctypes.data, w.size,
+                                           ctypes.byref(prm), int(chunk_len), ctypes.byref(sid)),
+           "sps_server_add_stream")
+    server.widths[int(sid.value)] = [int(x) for x in w]
+    return int(sid.value)
+
+
+def sps_server_memory(server: Server) -> dict:
+    u, b = ctypes.c_int64(), ctypes.c_int64()
+    _check(library().sps_server_memory(server.handle, ctypes.byref(u), ctypes.byref(b)),
+           "sps_server_memory")
+    return {"used": int(u.value), "budget": int(b.value)}
+
+
+def sps_server_stream_info(server: Server, stream_id: int) -> dict:
+    c, o, d = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double()
+    _check(library().sps_server_stream_info(server.handle, int(stream_id), ctypes.byref(c),
+                                            ctypes.byref(o), ctypes.byref(d)),
+           "sps_server_stream_info")
+    return {"chunk_len": int(c.value), "overlap": int(o.value), "duration_s": float(d.value)}
+
+
+def _host_ptr(a, name: str):
+    if isinstance(a, torch.Tensor):
+        if a.device.type != "cpu" or a.dtype != torch.uint8 or a.dim() != 2 or a.stride(1) != 1:
+            raise TypeError(f"{name} must be a uint8 [nchan][pitch] host tensor")
+        return a.data_ptr(), a.stride(0)
+    a = np.asarray(a)
+    if a.dtype != np.uint8 or a.ndim != 2 or a.strides[1] != 1:
+        raise TypeError(f"{name} must be a uint8 [nchan][pitch] host array")
+    return a.ctypes.data, a.strides[0]
+
+
+def sps_server_push(server: Server, stream_id: int, chunk, Y_copy: Optional[torch.Tensor] = None,
+                    cap: int = 4096, allow_truncated: bool = False):
+    """Searches the stream's next chunk (host uint8 [nchan][>= chunk_len]); returns
+    (candidates, number found)."""
+    hp, pitch = _host_ptr(chunk, "chunk")
+    yp = None
+    if Y_copy is not None:
+        yp = (_dev(Y_copy, torch.int32, "Y_copy") if Y_copy.dtype == torch.int32
+              else _dev(Y_copy, torch.uint32, "Y_copy"))
+    out = (sps_candidate * max(cap, 1))()
+    n = ctypes.c_int32()
+    rc = library().sps_server_push(server.handle, int(stream_id), hp, int(pitch), yp, out,
+                                   int(cap), ctypes.byref(n))
+    if not (rc == 6 and allow_truncated):
+        _check(rc, "sps_server_push")
+    k = min(int(n.value), cap)
+    arr = np.frombuffer(bytes(out)[:k * ctypes.sizeof(sps_candidate)], dtype=CANDIDATE_DTYPE).copy()
+    return arr, int(n.value)
+
+
+def sps_server_run(server: Server, feeds: Sequence[dict], run_s: float, compression: float,
+                   cap: int = 1 << 16) -> np.ndarray:
+    """feeds[i]: dict(host=uint8 tensor/array [nsrc * nchan][src_pitch], nsrc, first).
+    Returns the chunk records (structured array, arrival order)."""
+    arr = (sps_feed * len(feeds))()
+    keep = []
+    for i, f in enumerate(feeds):
+        hp, pitch = _host_ptr(f["host"], "feed")
+        arr[i] = sps_feed(hp, int(pitch), int(f.get("nsrc", 1)), int(f.get("first", 0)))
+        keep.append(f["host"])
+    recs = (sps_chunk_record * max(cap, 1))()
+    n = ctypes.c_int32()
+    _check(library().sps_server_run(server.handle, arr, float(run_s), float(compression), recs,
+                                    int(cap), ctypes.byref(n)), "sps_server_run")
+    k = min(int(n.value), cap)
+    return np.frombuffer(bytes(recs)[:k * ctypes.sizeof(sps_chunk_record)],
+                         dtype=RECORD_DTYPE).copy()
 
 
 def plan_for(wl) -> Plan:

@@ -14,6 +14,10 @@ search, not part of it.
   chunks plus the dispersion overlap, 2048 trial DMs 0..2047 in steps of 1,
   widths 1..256; 20 injected pulses and RFI per chunk.  The throughput
   workload: one chunk is 2048 x 2^20 DM-time samples.
+* ``batched_19beams_256ch_512dm``: 19 beams of the single-beam receiver with
+  uneven chunk lengths (2^18, 2^19 or 2^20 samples), searched together.
+* ``streaming_24_mixed``: 24 real-time streams of three set-ups (1024, 4096
+  and 8192 channels) served together.
 
 Channel order follows the common 8-bit filterbank convention: channel 0 is
 the top of the band, and the reference frequency of the delays is the upper
@@ -144,5 +148,35 @@ BATCHED = BatchWorkload(
                   rfi=RfiModel(chan_fraction=0.05, n_impulses=4)),
     nbeams=19, lengths=(1 << 18, 1 << 19, 1 << 20), seed=3)
 
+@dataclass(frozen=True)
+class StreamingWorkload:
+    """Concurrent real-time streams of mixed observing set-ups: `groups` holds
+    (count, workload) pairs, the workload's nout being the chunk length."""
+    name: str
+    groups: Tuple[Tuple[int, Workload], ...]
+
+    def streams(self) -> list:
+        return [wl for n, wl in self.groups for _ in range(n)]
+
+
+_STREAM_A = Workload(
+    name="stream_1024ch_64us_2p18t_1024dm", nchan=1024, f_lo_mhz=1000.0, f_hi_mhz=1500.0,
+    tsamp_s=64e-6, nout=1 << 18, ndm=1024, dm_lo=0.0, dm_hi=1000.0,
+    widths=(1, 2, 4, 8, 16, 32, 64, 128, 256), pulses=PulseModel(count=4),
+    rfi=RfiModel(chan_fraction=0.05, n_impulses=4), seed=11)
+_STREAM_C = Workload(
+    name="stream_8192ch_196us_2p18t_4096dm", nchan=8192, f_lo_mhz=1000.0, f_hi_mhz=1500.0,
+    tsamp_s=196.608e-6, nout=1 << 18, ndm=4096, dm_lo=0.0, dm_hi=4095.0,
+    widths=(1, 2, 4, 8, 16, 32, 64, 128, 256), pulses=PulseModel(count=4),
+    rfi=RfiModel(chan_fraction=0.05, n_impulses=4), seed=13)
+
+# 24 streams: 8 x (1024 channels, 64 us, 2^18-sample chunks, 1024 DMs 0-1000),
+# 12 x the full-scale set-up (4096 channels, 49.152 us, 2^20, 2048 DMs) and
+# 4 x (8192 channels, 196.608 us, 2^18, 4096 DMs 0-4095).
+STREAMING = StreamingWorkload(
+    name="streaming_24_mixed",
+    groups=((8, _STREAM_A), (12, FULL_SCALE), (4, _STREAM_C)))
+
 WORKLOADS = {w.name: w for w in (SINGLE_BEAM, FULL_SCALE)}
 BATCH_WORKLOADS = {BATCHED.name: BATCHED}
+STREAMING_WORKLOADS = {STREAMING.name: STREAMING}

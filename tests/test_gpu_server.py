@@ -1,0 +1,165 @@
+"""GPU tests of the streaming server: chunk-by-chunk search with the
+dispersion overlap kept on the device must equal the oracle's search of the
+whole concatenated series (bit-exact dedispersion, candidates as in the
+single-call path), admission must respect the memory budget, and a timed run
+must search every scheduled chunk in order."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from paper_2511_02328_amd import synth  # noqa: E402
+from paper_2511_02328_amd.workloads import PulseModel, Workload  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+SNR_RTOL = 1e-5
+DET = dict(threshold=7.0, tile_dm=16, tile_t=512, nms_dm=8, nms_t=64)
+
+
+@pytest.fixture(scope="module")
+def sps():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2511_02328_amd import sps as mod
+    mod.library()
+    return mod
+
+
+def _wl(nchan, ndm, dm_hi, tsamp, seed):
+    return Workload("s", nchan, 1000.0, 1500.0, tsamp, 0, ndm, 0.0, dm_hi, (1, 2, 4, 8, 16, 32),
+                    pulses=PulseModel(count=3, dm_range=(20.0, dm_hi * 0.9),
+                                      fwhm_range_s=(0.5e-3, 3e-3), amp_range_sigma=(2.0, 4.0)),
+                    seed=seed)
+
+
+def _add(sps, server, wl, chunk):
+    return sps.sps_server_add_stream(server, wl.freqs_mhz(), wl.fref_mhz, wl.tsamp_s, wl.dms(),
+                                     wl.widths, chunk_len=chunk, **DET)
+
+
+def _series(wl, nchunks, chunk):
+    """The stream's whole input: nchunks * chunk samples (pulses across chunk edges)."""
+    from dataclasses import replace
+    X, _ = synth.make_filterbank(replace(wl, nout=nchunks * chunk), nchunks * chunk)
+    return X
+
+
+def _oracle_chunk(wl, Xs, dmax, k, chunk):
+    """Oracle search of chunk k: samples [k chunk - dmax, (k+1) chunk) of the series,
+    zeros before its start."""
+    D = oracle.delays(wl.freqs_mhz(), wl.fref_mhz, wl.tsamp_s, wl.dms())
+    assert int(D.max()) == dmax
+    lo = k * chunk - dmax
+    win = np.zeros((wl.nchan, dmax + chunk), np.uint8)
+    a = max(lo, 0)
+    win[:, a - lo:] = Xs[:, a:(k + 1) * chunk]
+    return oracle.pipeline(win, D, chunk, wl.widths)
+
+
+def _check_chunk(Yg, cands, n, ref, widths):
+    Yo, sto, snro, besto = ref
+    assert np.array_equal(Yg, Yo), "dedispersion differs"
+    co = oracle.detect(snro, besto, DET["threshold"], DET["tile_dm"], DET["tile_t"],
+                       DET["nms_dm"], DET["nms_t"])
+    assert n == co["n_found"]
+    got = sorted(zip(cands["dm_idx"], cands["t_idx"], cands["width"]))
+    want = sorted(zip(co["d"], co["t"], [widths[i] for i in co["w"]]))
+    assert got == want
+    s_g = np.sort(cands["snr"])
+    s_o = np.sort(co["snr"])
+    assert np.allclose(s_g, s_o, rtol=SNR_RTOL, atol=0)
+
+
+@pytest.mark.parametrize("chunk", [1000, 4096, 7777])
+def test_chunks_equal_whole_series(sps, chunk):
+    # two set-ups, two streams of the first: rings are independent, plans shared
+    wa = _wl(128, 96, 150.0, 98.304e-6, 21)
+    wb = _wl(64, 40, 400.0, 196.608e-6, 22)
+    nchunks = 4
+    with sps.sps_server_create(8 << 30, 2) as server:
+        ids = [_add(sps, server, wa, chunk), _add(sps, server, wb, chunk + 512),
+               _add(sps, server, wa, chunk)]
+        setups = [(wa, chunk, 21), (wb, chunk + 512, 22), (wa, chunk, 23)]
+        series = []
+        for (wl, L, seed) in setups:
+            from dataclasses import replace
+            series.append(_series(replace(wl, seed=seed), nchunks, L))
+        for k in range(nchunks):
+            for sid, (wl, L, _), Xs in zip(ids, setups, series):
+                info = sps.sps_server_stream_info(server, sid)
+                assert info["chunk_len"] == L
+                Y = torch.zeros((wl.ndm, L), dtype=torch.int32, device="cuda")
+                host = torch.from_numpy(np.ascontiguousarray(Xs[:, k * L:(k + 1) * L]))
+                cands, n = sps.sps_server_push(server, sid, host, Y_copy=Y)
+                torch.cuda.synchronize()
+                ref = _oracle_chunk(wl, Xs, info["overlap"], k, L)
+                _check_chunk(Y.cpu().numpy().view(np.uint32), cands, n, ref, wl.widths)
+
+
+def test_admission_by_budget(sps):
+    wa = _wl(128, 96, 150.0, 98.304e-6, 1)
+    wb = _wl(64, 40, 400.0, 196.608e-6, 2)
+    with sps.sps_server_create(1 << 40, 2) as probe:
+        _add(sps, probe, wa, 4096)
+        one = sps.sps_server_memory(probe)["used"]
+        _add(sps, probe, wa, 4096)
+        two = sps.sps_server_memory(probe)["used"]
+    ring = two - one
+    assert 0 < ring < one  # a second stream of a set-up costs its ring only
+    with sps.sps_server_create(one + ring // 2, 2) as server:
+        _add(sps, server, wa, 4096)
+        assert sps.sps_server_memory(server)["used"] == one
+        with pytest.raises(sps.SpsError) as e:
+            _add(sps, server, wa, 4096)
+        assert e.value.name == "SPS_ERR_NOMEM" and "refused" in str(e.value)
+        assert sps.sps_server_memory(server)["used"] == one
+        with pytest.raises(sps.SpsError):
+            _add(sps, server, wb, 8192)  # new plans and planes do not fit either
+        assert sps.sps_server_memory(server)["used"] == one
+    with pytest.raises(sps.SpsError):
+        sps.sps_server_create(0, 1)
+    with pytest.raises(sps.SpsError):
+        sps.sps_server_create(1 << 30, 17)
+
+
+def test_timed_run_then_continue(sps):
+    # 2 streams, chunks of ~0.1 s / 0.2 s, compressed 4x: every scheduled
+    # chunk is searched in order; afterwards the rings still hold the right
+    # overlap, so a pushed chunk equals the oracle on the concatenated series
+    wa = _wl(128, 96, 150.0, 98.304e-6, 31)
+    wb = _wl(64, 40, 400.0, 196.608e-6, 32)
+    La, Lb = 4096, 4096
+    nsrc = 3
+    run_s, comp = 1.5, 4.0
+    with sps.sps_server_create(8 << 30, 2) as server:
+        ia, ib = _add(sps, server, wa, La), _add(sps, server, wb, Lb)
+        srcs = [_series(wa, nsrc, La), _series(wb, nsrc, Lb)]
+        feeds = []
+        for Xs, L in zip(srcs, (La, Lb)):
+            stacked = np.concatenate([Xs[:, k * L:(k + 1) * L] for k in range(nsrc)], axis=0)
+            feeds.append(dict(host=torch.from_numpy(np.ascontiguousarray(stacked)).pin_memory(),
+                              nsrc=nsrc, first=1))
+        recs = sps.sps_server_run(server, feeds, run_s, comp)
+        assert np.all(recs["status"] == 0)
+        for sid, wl, L in ((ia, wa, La), (ib, wb, Lb)):
+            T = L * wl.tsamp_s / comp
+            phase = T * sid / 2
+            nexp = int(np.floor((run_s - phase) / T + 1e-9))
+            r = recs[recs["stream"] == sid]
+            assert len(r) == nexp and list(r["index"]) == list(range(nexp))
+            assert np.allclose(r["arrival_s"], phase + (np.arange(nexp) + 1) * T)
+            assert np.all(r["start_s"] >= r["arrival_s"]) and np.all(r["end_s"] > r["start_s"])
+            assert np.all(np.diff(r["start_s"]) > 0)
+        # continue: the run searched chunks first, first+1, ... of the sources
+        for sid, wl, L, Xs in ((ia, wa, La, srcs[0]), (ib, wb, Lb, srcs[1])):
+            nrun = int((recs["stream"] == sid).sum())
+            order = [(1 + k) % nsrc for k in range(nrun + 1)]
+            full = np.concatenate([Xs[:, j * L:(j + 1) * L] for j in order], axis=1)
+            Y = torch.zeros((wl.ndm, L), dtype=torch.int32, device="cuda")
+            cands, n = sps.sps_server_push(server, sid, full[:, nrun * L:], Y_copy=Y)
+            torch.cuda.synchronize()
+            info = sps.sps_server_stream_info(server, sid)
+            ref = _oracle_chunk(wl, full, info["overlap"], nrun, L)
+            _check_chunk(Y.cpu().numpy().view(np.uint32), cands, n, ref, wl.widths)
