@@ -238,3 +238,24 @@ def downsample_sqrt(X: np.ndarray, factor: int, nsamp=None) -> np.ndarray:
     _check(_load().sps_oracle_downsample_sqrt(X.shape[0], _ptr(X), pitch, n, int(factor),
                                               _ptr(out), max(nout, 1)), "downsample_sqrt")
     return out[:, :nout]
+
+
+_cnn_mod = None
+
+
+def cnn():
+    """The detector oracle module (``oracle/detector.py``), or the copy named by the
+    environment variable SPS_CNN_ORACLE_SRC (used to plant mistakes in tests)."""
+    global _cnn_mod
+    if _cnn_mod is None:
+        src = os.environ.get("SPS_CNN_ORACLE_SRC")
+        if src:
+            import importlib.util
+            spec = importlib.util.spec_from_file_location("oracle_cnn_copy", src)
+            mod = importlib.util.module_from_spec(spec)
+            spec.loader.exec_module(mod)
+            _cnn_mod = mod
+        else:
+            from . import detector as mod
+            _cnn_mod = mod
+    return _cnn_mod
