@@ -359,6 +359,82 @@ sps_status sps_server_run(sps_server server, const sps_feed *feeds, double run_s
                           double compression, sps_chunk_record *records, int32_t cap,
                           int32_t *n_records);
 
+/* ---- Learned candidate detector (BF16 matrix-core CNN) ---- */
+
+/* Tiles: a boxcar S/N plane max-pooled over windows of 2 trials x 8 samples,
+ * multiplied by `scale` (binary32) and rounded to bfloat16 (nearest, ties to
+ * even); a tile is 256 rows x 512 columns, stored as bfloat16 bit patterns
+ * (uint16_t), row-major, tiles back to back.
+ *
+ * Network: six 3x3 convolutions (zero padding 1; strides 2,2,2,2,2,1;
+ * channels 1->16->32->64->128->128->128), bias and ReLU each, then a 1x1
+ * head with 3 outputs for every cell of an 8 x 16 grid (a cell covers 32 x
+ * 32 tile pixels): objectness logit, row and column offset of the pulse
+ * inside the cell in cell units.  3x3 weights are used as bfloat16,
+ * activations and back-propagated signals are stored as bfloat16, every
+ * product accumulates in FP32; head, loss and Adam are FP32.
+ *
+ * Parameters (FP32, sps_cnn_param_count() values) in this order: for each 3x3
+ * layer its weights [cout][cin][3][3] then its biases [cout]; then the head
+ * weights [3][128] and biases [3].
+ *
+ * Loss (mean over tiles): per cell, binary cross-entropy of the objectness
+ * logit against the label (positive cells weighted 32), averaged over the
+ * 128 cells, plus the squared errors of both offsets at positive cells.
+ * Labels: FP32 [n][3][8][16]: objectness (0/1), row offset, column offset.
+ *
+ * A network may be used from one stream at a time. */
+typedef struct sps_cnn_s *sps_cnn;
+
+typedef struct {
+  int32_t tile;    /* tile index in the batch */
+  int32_t cell_dm; /* cell row, 0..7 */
+  int32_t cell_t;  /* cell column, 0..15 */
+  float prob;      /* sigmoid of the objectness logit */
+  float row;       /* predicted pulse row in the tile (0..256) */
+  float col;       /* predicted pulse column in the tile (0..512) */
+} sps_cnn_candidate;
+
+int64_t sps_cnn_param_count(void);
+/* Allocates the network for batches of up to max_batch tiles (<= 4096) on
+ * the current device: parameters zero, Adam state zero. */
+sps_status sps_cnn_create(int32_t max_batch, sps_cnn *out);
+sps_status sps_cnn_destroy(sps_cnn net);
+/* Host copies of all parameters / gradients (synchronous).  set_params also
+ * resets the Adam state and step count. */
+sps_status sps_cnn_set_params(sps_cnn net, const float *host);
+sps_status sps_cnn_get_params(sps_cnn net, float *host);
+sps_status sps_cnn_set_grads(sps_cnn net, const float *host);
+sps_status sps_cnn_get_grads(sps_cnn net, float *host);
+/* The bfloat16 ReLU output of 3x3 layer `layer` (0..5) for the first n tiles
+ * of the last forward pass, NHWC [n][h][w][cout] (synchronous). */
+sps_status sps_cnn_activations(sps_cnn net, int32_t layer, int32_t n, uint16_t *host);
+
+/* Pools the S/N plane snr (device FP32 [ndm][pitch], first nout used) into
+ * tiles (device uint16 [ndm/2][nout/8]); only full windows.  Asynchronous. */
+sps_status sps_cnn_pool_tiles(const float *snr, int64_t pitch, int32_t ndm, int64_t nout,
+                              float scale, uint16_t *tiles, void *stream);
+/* Forward pass of n tiles (device, 16-byte aligned); head (optional, device
+ * FP32 [n][3][8][16]) receives the head outputs.  Asynchronous. */
+sps_status sps_cnn_forward(sps_cnn net, const uint16_t *tiles, int32_t n, float *head,
+                           void *stream);
+/* Forward, loss and backward: gradients of the mean loss into the network's
+ * gradient buffer; loss (optional, device FP32) receives the loss.
+ * Asynchronous. */
+sps_status sps_cnn_loss_grad(sps_cnn net, const uint16_t *tiles, const float *labels, int32_t n,
+                             float *loss, void *stream);
+/* One Adam step (with bias correction) from the gradient buffer.  Asynchronous. */
+sps_status sps_cnn_adam(sps_cnn net, float lr, float beta1, float beta2, float eps,
+                        void *stream);
+/* sps_cnn_loss_grad then sps_cnn_adam(lr, 0.9, 0.999, 1e-8). */
+sps_status sps_cnn_train_step(sps_cnn net, const uint16_t *tiles, const float *labels, int32_t n,
+                              float lr, float *loss, void *stream);
+/* Forward pass, then every cell whose objectness probability is >= threshold
+ * (0 < threshold < 1), in tile then cell order.  Synchronises the stream.
+ * *n_found is the true count; TRUNCATED if above cap. */
+sps_status sps_cnn_detect(sps_cnn net, const uint16_t *tiles, int32_t n, float threshold,
+                          sps_cnn_candidate *out, int32_t cap, int32_t *n_found, void *stream);
+
 /* Message for the last failed call on this thread ("" if none). */
 const char *sps_last_error(void);
 

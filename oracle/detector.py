@@ -114,14 +114,14 @@ def conv3x3_backward(x: np.ndarray, w: np.ndarray, dout: np.ndarray, stride: int
 
 
 def init_params(seed: int) -> dict:
-    """He-normal weights, zero biases (numpy PCG64).  A seeded input, not part
-    of the method: the same arrays are handed to the GPU."""
-    rng = np.random.Generator(np.random.PCG64(seed))
-    p = {}
+    """He-normal 3x3 weights, zero biases, head weights N(0, 1/128), head
+    biases (-4, 0.5, 0.5), drawn by the shared seeded input generator."""
+    from paper_2511_02328_amd.synth import seeded_weights
+    specs = []
     for i, (ci, co, _) in enumerate(LAYERS):
-        p[f"w{i}"] = rng.normal(0.0, np.sqrt(2.0 / (9 * ci)), (co, ci, 3, 3)).astype(np.float32)
-        p[f"b{i}"] = np.zeros(co, np.float32)
-    p["wh"] = rng.normal(0.0, np.sqrt(1.0 / LAYERS[-1][1]), (NHEAD, LAYERS[-1][1])).astype(np.float32)
+        specs += [(f"w{i}", (co, ci, 3, 3), np.sqrt(2.0 / (9 * ci))), (f"b{i}", (co,), 0.0)]
+    specs += [("wh", (NHEAD, LAYERS[-1][1]), np.sqrt(1.0 / LAYERS[-1][1])), ("bh", (NHEAD,), 0.0)]
+    p = seeded_weights(seed, specs)
     p["bh"] = np.array([-4.0, 0.5, 0.5], np.float32)
     return p
 

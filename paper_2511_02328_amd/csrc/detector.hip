@@ -1,0 +1,965 @@
+// detector.hip -- the learned candidate detector: a small convolutional
+// network on max-pooled S/N tiles, trained and run with BF16 matrix-core
+// (MFMA) products accumulating in FP32.
+//
+// Tiles: the boxcar S/N plane max-pooled over 2 trials x 8 samples, scaled
+// and rounded to bfloat16 (nearest, ties to even), 256 x 512 per tile.
+// Network: six 3x3 convolutions (zero padding 1; strides 2,2,2,2,2,1;
+// channels 1->16->32->64->128->128->128), each with bias and ReLU, and a
+// 1x1 head giving, per cell of the final 8 x 16 grid, an objectness logit and
+// the pulse's DM and time offsets inside the cell.  Loss: per cell binary
+// cross-entropy of the objectness (positives weighted 32) averaged over the
+// cells, plus the squared offset errors at positive cells; mean over tiles.
+// Optimiser: Adam with bias correction on FP32 master weights.
+//
+// Precision: 3x3 weights are used as bfloat16, activations are stored as
+// bfloat16 after ReLU, the back-propagated signal is stored as bfloat16 at
+// the output of every 3x3 layer (masked by the stored activation, a > 0);
+// every product sums in FP32.  The head, loss, gradients of the head and
+// Adam run in FP32.
+//
+// Layout on the device: activations NHWC ([tile][y][x][channel]) so that
+// 8 consecutive channels are one 16-byte load; weights packed twice in
+// bfloat16, [cout][tap * cin + ci] for the forward product and
+// [ci][tap * cout + co] for the backward data product.
+//
+// MFMA v_mfma_f32_16x16x32_bf16 on a 64-lane wave: lane l supplies row l%16
+// of A and column l%16 of B with the 8 K-values 8*(l/16) .. +7 (the same K
+// order on both sides, so any internal K order of the unit gives the same
+// sum), and receives D rows 4*(l/16) .. +3 of column l%16.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "sps.h"
+#include "sps_internal.h"
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kTileDm = 256, kTileT = 512, kPoolDm = 2, kPoolT = 8;
+constexpr int kGridDm = 8, kGridT = 16, kCells = kGridDm * kGridT, kHead = 3;
+constexpr float kPosWeight = 32.0f, kLambdaBox = 1.0f;
+constexpr int kNumLayers = 6;
+
+struct Layer {
+  int cin, cout, stride, hin, win, hout, wout;
+  constexpr int kpad() const { return (9 * cin + 31) / 32 * 32; }
+  constexpr int64_t wcount() const { return (int64_t)cout * cin * 9; }
+};
+constexpr Layer kLayers[kNumLayers] = {
+    {1, 16, 2, 256, 512, 128, 256},  {16, 32, 2, 128, 256, 64, 128},
+    {32, 64, 2, 64, 128, 32, 64},    {64, 128, 2, 32, 64, 16, 32},
+    {128, 128, 2, 16, 32, 8, 16},    {128, 128, 1, 8, 16, 8, 16}};
+constexpr int kFeat = 128;  // channels of the last 3x3 layer
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+__device__ __forceinline__ bool bf_positive(uint16_t b) { return b != 0 && !(b & 0x8000u); }
+
+__device__ __forceinline__ floatx4 mfma(u32x4 a, u32x4 b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                  __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
+// Tiles
+// ---------------------------------------------------------------------------
+
+// out[i][j] = bf16(scale * max over the 2 x 8 window at (2i, 8j)).
+__global__ __launch_bounds__(256) void pool_tiles_kernel(const float *__restrict__ snr,
+                                                         int64_t pitch, int64_t nd, int64_t nt,
+                                                         float scale, uint16_t *__restrict__ out) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= nd * nt) return;
+  const int64_t i = idx / nt, j = idx - i * nt;
+  float m = -INFINITY;
+  for (int a = 0; a < kPoolDm; ++a) {
+    const float *row = snr + (i * kPoolDm + a) * pitch + j * kPoolT;
+    for (int b = 0; b < kPoolT; ++b) m = fmaxf(m, row[b]);
+  }
+  out[idx] = f2bf(m * scale);
+}
+
+// ---------------------------------------------------------------------------
+// Forward
+// ---------------------------------------------------------------------------
+
+// First layer (one input channel): per output pixel, 9 taps x 16 channels on
+// the vector ALU.  x: tiles [n][256][512]; w: packed [16][32] (k = tap).
+__global__ __launch_bounds__(256) void conv0_fwd_kernel(const uint16_t *__restrict__ x,
+                                                        const uint16_t *__restrict__ wp,
+                                                        const float *__restrict__ bias,
+                                                        uint16_t *__restrict__ y, int64_t npix) {
+  constexpr Layer L = kLayers[0];
+  __shared__ float ws[16][9];
+  __shared__ float bs[16];
+  if (threadIdx.x < 144) ws[threadIdx.x / 9][threadIdx.x % 9] = bf2f(wp[(threadIdx.x / 9) * 32 + threadIdx.x % 9]);
+  if (threadIdx.x < 16) bs[threadIdx.x] = bias[threadIdx.x];
+  __syncthreads();
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= npix) return;
+  const int64_t n = p / (L.hout * L.wout);
+  const int r = (int)(p - n * L.hout * L.wout);
+  const int oy = r / L.wout, ox = r % L.wout;
+  float xv[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    const int iy = 2 * oy + t / 3 - 1, ix = 2 * ox + t % 3 - 1;
+    xv[t] = (iy >= 0 && iy < L.hin && ix >= 0 && ix < L.win)
+                ? bf2f(x[(n * L.hin + iy) * L.win + ix])
+                : 0.0f;
+  }
+  uint32_t packed[8];
+#pragma unroll
+  for (int c = 0; c < 16; c += 2) {
+    float s0 = bs[c], s1 = bs[c + 1];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      s0 += ws[c][t] * xv[t];
+      s1 += ws[c + 1][t] * xv[t];
+    }
+    packed[c / 2] = (uint32_t)f2bf(fmaxf(s0, 0.0f)) | ((uint32_t)f2bf(fmaxf(s1, 0.0f)) << 16);
+  }
+  u32x4 *dst = reinterpret_cast<u32x4 *>(y + p * 16);
+  dst[0] = u32x4{packed[0], packed[1], packed[2], packed[3]};
+  dst[1] = u32x4{packed[4], packed[5], packed[6], packed[7]};
+}
+
+// Layers 1..5: implicit GEMM, M = output pixels, N = COUT, K = taps x CIN.
+// A workgroup of 4 waves covers 64 output pixels (16 per wave) and all
+// output channels.
+template <int LI>
+__global__ __launch_bounds__(256) void conv_fwd_kernel(const uint16_t *__restrict__ x,
+                                                       const uint16_t *__restrict__ wp,
+                                                       const float *__restrict__ bias,
+                                                       uint16_t *__restrict__ y, int64_t npix) {
+  constexpr Layer L = kLayers[LI];
+  constexpr int CIN = L.cin, COUT = L.cout, S = L.stride, NB = COUT / 16;
+  constexpr int KPAD = (9 * CIN + 31) / 32 * 32;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4;
+  const int64_t pbase = (int64_t)blockIdx.x * 64 + wave * 16;
+  const int64_t p = pbase + (lane & 15);
+  const bool valid = p < npix;
+  int64_t n = 0;
+  int oy = 0, ox = 0;
+  if (valid) {
+    n = p / (L.hout * L.wout);
+    const int r = (int)(p - n * L.hout * L.wout);
+    oy = r / L.wout;
+    ox = r % L.wout;
+  }
+  floatx4 acc[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) acc[b] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const uint16_t *wrow = wp + (int64_t)(lane & 15) * KPAD + 8 * g;
+  for (int k0 = 0; k0 < KPAD; k0 += 32) {
+    const int k = k0 + 8 * g;
+    const int tap = k / CIN, ci = k % CIN;
+    u32x4 av = {0u, 0u, 0u, 0u};
+    if (valid && tap < 9) {
+      const int iy = S * oy + tap / 3 - 1, ix = S * ox + tap % 3 - 1;
+      if (iy >= 0 && iy < L.hin && ix >= 0 && ix < L.win)
+        av = *reinterpret_cast<const u32x4 *>(x + ((n * L.hin + iy) * L.win + ix) * CIN + ci);
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const u32x4 bv = *reinterpret_cast<const u32x4 *>(wrow + (int64_t)b * 16 * KPAD + k0);
+      acc[b] = mfma(av, bv, acc[b]);
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int co = b * 16 + (lane & 15);
+    const float bb = bias[co];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t q = pbase + 4 * g + j;
+      if (q < npix) y[q * COUT + co] = f2bf(fmaxf(acc[b][j] + bb, 0.0f));
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Head, loss and the signal entering the last 3x3 layer
+// ---------------------------------------------------------------------------
+
+// One thread per cell (128 cells per block).  a6: [cells][128] bf16.
+// Writes the head outputs, dz6 = bf16((wh^T g) * (a6 > 0)), and per block the
+// partial sums of the head gradients and of the loss.
+__global__ __launch_bounds__(128) void head_loss_kernel(
+    const uint16_t *__restrict__ a6, const float *__restrict__ wh, const float *__restrict__ bh,
+    const float *__restrict__ labels, int64_t ncell, float inv_n, float *__restrict__ head,
+    uint16_t *__restrict__ dz6, float *__restrict__ part_wh, float *__restrict__ part_bh,
+    float *__restrict__ part_loss, int train) {
+  __shared__ float w_s[kHead][kFeat];
+  __shared__ float g_s[128][kHead];
+  __shared__ uint16_t a_s[128][kFeat + 2];
+  __shared__ float l_s[128];
+  for (int i = threadIdx.x; i < kHead * kFeat; i += 128) w_s[i / kFeat][i % kFeat] = wh[i];
+  const int64_t cell = (int64_t)blockIdx.x * 128 + threadIdx.x;
+  const bool valid = cell < ncell;
+  // stage this block's activations (coalesced: 16 bytes per thread per step)
+  for (int v = threadIdx.x; v < 128 * kFeat / 8; v += 128) {
+    const int c = v / (kFeat / 8), f8 = (v % (kFeat / 8)) * 8;
+    const int64_t q = (int64_t)blockIdx.x * 128 + c;
+    u32x4 d = {0u, 0u, 0u, 0u};
+    if (q < ncell) d = *reinterpret_cast<const u32x4 *>(a6 + q * kFeat + f8);
+    const uint16_t *h = reinterpret_cast<const uint16_t *>(&d);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) a_s[c][f8 + i] = h[i];
+  }
+  __syncthreads();
+  float h[kHead] = {bh[0], bh[1], bh[2]};
+  for (int c = 0; c < kFeat; ++c) {
+    const float a = bf2f(a_s[threadIdx.x][c]);
+#pragma unroll
+    for (int k = 0; k < kHead; ++k) h[k] += w_s[k][c] * a;
+  }
+  const int64_t tile = cell / kCells;
+  const int64_t cidx = cell - tile * kCells;
+  float gk[kHead] = {0.f, 0.f, 0.f};
+  float lc = 0.f;
+  if (valid) {
+    if (head)
+      for (int k = 0; k < kHead; ++k) head[(tile * kHead + k) * kCells + cidx] = h[k];
+    if (train) {
+      const float y0 = labels[(tile * kHead + 0) * kCells + cidx];
+      const float y1 = labels[(tile * kHead + 1) * kCells + cidx];
+      const float y2 = labels[(tile * kHead + 2) * kCells + cidx];
+      const float o = h[0];
+      const float wgt = y0 > 0.f ? kPosWeight : 1.0f;
+      const float bce = fmaxf(o, 0.f) - y0 * o + log1pf(expf(-fabsf(o)));
+      const float e1 = h[1] - y1, e2 = h[2] - y2;
+      lc = (wgt * bce / (float)kCells + kLambdaBox * y0 * (e1 * e1 + e2 * e2)) * inv_n;
+      const float sig = 1.0f / (1.0f + expf(-o));
+      gk[0] = wgt * (sig - y0) / (float)kCells * inv_n;
+      gk[1] = 2.0f * kLambdaBox * e1 * y0 * inv_n;
+      gk[2] = 2.0f * kLambdaBox * e2 * y0 * inv_n;
+    }
+  }
+  if (!train) return;
+  for (int k = 0; k < kHead; ++k) g_s[threadIdx.x][k] = gk[k];
+  l_s[threadIdx.x] = lc;
+  if (valid) {
+    for (int c0 = 0; c0 < kFeat; c0 += 8) {
+      uint32_t pk[4];
+#pragma unroll
+      for (int i = 0; i < 8; i += 2) {
+        const int c = c0 + i;
+        const float d0 = w_s[0][c] * gk[0] + w_s[1][c] * gk[1] + w_s[2][c] * gk[2];
+        const float d1 = w_s[0][c + 1] * gk[0] + w_s[1][c + 1] * gk[1] + w_s[2][c + 1] * gk[2];
+        const uint16_t b0 = bf_positive(a_s[threadIdx.x][c]) ? f2bf(d0) : (uint16_t)0;
+        const uint16_t b1 = bf_positive(a_s[threadIdx.x][c + 1]) ? f2bf(d1) : (uint16_t)0;
+        pk[i / 2] = (uint32_t)b0 | ((uint32_t)b1 << 16);
+      }
+      *reinterpret_cast<u32x4 *>(dz6 + cell * kFeat + c0) = u32x4{pk[0], pk[1], pk[2], pk[3]};
+    }
+  }
+  __syncthreads();
+  // thread c: partial head-weight gradients of feature c over the block's cells
+  {
+    const int c = threadIdx.x;
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+    for (int q = 0; q < 128; ++q) {
+      const float a = bf2f(a_s[q][c]);
+      s0 += g_s[q][0] * a;
+      s1 += g_s[q][1] * a;
+      s2 += g_s[q][2] * a;
+    }
+    part_wh[((int64_t)blockIdx.x * kHead + 0) * kFeat + c] = s0;
+    part_wh[((int64_t)blockIdx.x * kHead + 1) * kFeat + c] = s1;
+    part_wh[((int64_t)blockIdx.x * kHead + 2) * kFeat + c] = s2;
+  }
+  if (threadIdx.x < kHead + 1) {
+    float s = 0.f;
+    for (int q = 0; q < 128; ++q) s += threadIdx.x < kHead ? g_s[q][threadIdx.x] : l_s[q];
+    if (threadIdx.x < kHead)
+      part_bh[(int64_t)blockIdx.x * kHead + threadIdx.x] = s;
+    else
+      part_loss[blockIdx.x] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Backward: data
+// ---------------------------------------------------------------------------
+
+// dx[p][ci] = bf16(mask(x[p][ci]) * sum_{tap, co} W[co][ci][tap] dz[q(p, tap)][co])
+// for layers 1..5, where q(p, tap) is the output pixel that reads input p
+// through tap (if any).  M = input pixels, N = CIN, K = taps x COUT.
+template <int LI>
+__global__ __launch_bounds__(256) void conv_bwd_data_kernel(const uint16_t *__restrict__ dz,
+                                                            const uint16_t *__restrict__ wt,
+                                                            const uint16_t *__restrict__ x,
+                                                            uint16_t *__restrict__ dx,
+                                                            int64_t npix_in) {
+  constexpr Layer L = kLayers[LI];
+  constexpr int CIN = L.cin, COUT = L.cout, S = L.stride, NB = CIN / 16, K = 9 * COUT;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4;
+  const int64_t pbase = (int64_t)blockIdx.x * 64 + wave * 16;
+  const int64_t p = pbase + (lane & 15);
+  const bool valid = p < npix_in;
+  int64_t n = 0;
+  int iy = 0, ix = 0;
+  if (valid) {
+    n = p / (L.hin * L.win);
+    const int r = (int)(p - n * L.hin * L.win);
+    iy = r / L.win;
+    ix = r % L.win;
+  }
+  floatx4 acc[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) acc[b] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const uint16_t *wrow = wt + (int64_t)(lane & 15) * K + 8 * g;
+  for (int tap = 0; tap < 9; ++tap) {
+    const int ty = iy + 1 - tap / 3, tx = ix + 1 - tap % 3;
+    const bool ok = valid && ty >= 0 && tx >= 0 && ty % S == 0 && tx % S == 0 &&
+                    ty / S < L.hout && tx / S < L.wout;
+    const int64_t src = ok ? ((n * L.hout + ty / S) * L.wout + tx / S) * COUT + 8 * g : 0;
+    for (int co0 = 0; co0 < COUT; co0 += 32) {
+      u32x4 av = {0u, 0u, 0u, 0u};
+      if (ok) av = *reinterpret_cast<const u32x4 *>(dz + src + co0);
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const u32x4 bv =
+            *reinterpret_cast<const u32x4 *>(wrow + (int64_t)b * 16 * K + tap * COUT + co0);
+        acc[b] = mfma(av, bv, acc[b]);
+      }
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int ci = b * 16 + (lane & 15);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t q = pbase + 4 * g + j;
+      if (q < npix_in) {
+        const int64_t o = q * CIN + ci;
+        dx[o] = bf_positive(x[o]) ? f2bf(acc[b][j]) : (uint16_t)0;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Backward: weights and biases
+// ---------------------------------------------------------------------------
+
+constexpr int kKP = 32;       // pixels per staged K-step
+constexpr int kLdsRow = 40;   // bf16 per LDS row (32 + 8 padding)
+
+// partial[split][co][tap][ci] = sum over the split's output pixels q of
+// dz[q][co] * x[input of q through tap][ci], layers 1..5.  Grid (9, nsplit);
+// M = COUT, N = CIN, K = pixels, staged 32 pixels at a time through LDS in
+// transposed form so that each lane's 8 K-values are one 16-byte read.
+template <int LI>
+__global__ __launch_bounds__(256) void conv_bwd_weight_kernel(const uint16_t *__restrict__ dz,
+                                                              const uint16_t *__restrict__ x,
+                                                              float *__restrict__ partial,
+                                                              int64_t npix_out, int64_t chunk) {
+  constexpr Layer L = kLayers[LI];
+  constexpr int CIN = L.cin, COUT = L.cout, S = L.stride;
+  constexpr int MB = COUT / 16, NB = CIN / 16, NBLK = MB * NB;
+  constexpr int PER_WAVE = (NBLK + 3) / 4;
+  __shared__ __attribute__((aligned(16))) uint16_t dzT[COUT][kLdsRow];
+  __shared__ __attribute__((aligned(16))) uint16_t xT[CIN][kLdsRow];
+  const int tap = blockIdx.x, ky = tap / 3, kx = tap % 3;
+  const int64_t split = blockIdx.y;
+  const int64_t pbeg = split * chunk;
+  const int64_t pend = pbeg + chunk < npix_out ? pbeg + chunk : npix_out;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4;
+  floatx4 acc[PER_WAVE];
+#pragma unroll
+  for (int b = 0; b < PER_WAVE; ++b) acc[b] = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int64_t p0 = pbeg; p0 < pend; p0 += kKP) {
+    for (int v = threadIdx.x; v < kKP * COUT / 8; v += 256) {
+      const int pix = v / (COUT / 8), c8 = (v % (COUT / 8)) * 8;
+      const int64_t q = p0 + pix;
+      u32x4 d = {0u, 0u, 0u, 0u};
+      if (q < pend) d = *reinterpret_cast<const u32x4 *>(dz + q * COUT + c8);
+      const uint16_t *h = reinterpret_cast<const uint16_t *>(&d);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) dzT[c8 + i][pix] = h[i];
+    }
+    for (int v = threadIdx.x; v < kKP * CIN / 8; v += 256) {
+      const int pix = v / (CIN / 8), c8 = (v % (CIN / 8)) * 8;
+      const int64_t q = p0 + pix;
+      u32x4 d = {0u, 0u, 0u, 0u};
+      if (q < pend) {
+        const int64_t n = q / (L.hout * L.wout);
+        const int r = (int)(q - n * L.hout * L.wout);
+        const int iy = S * (r / L.wout) + ky - 1, ix = S * (r % L.wout) + kx - 1;
+        if (iy >= 0 && iy < L.hin && ix >= 0 && ix < L.win)
+          d = *reinterpret_cast<const u32x4 *>(x + ((n * L.hin + iy) * L.win + ix) * CIN + c8);
+      }
+      const uint16_t *h = reinterpret_cast<const uint16_t *>(&d);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) xT[c8 + i][pix] = h[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < PER_WAVE; ++b) {
+      const int blk = wave * PER_WAVE + b;
+      if (blk < NBLK) {
+        const int mb = blk / NB, nb = blk % NB;
+        const u32x4 av = *reinterpret_cast<const u32x4 *>(&dzT[mb * 16 + (lane & 15)][8 * g]);
+        const u32x4 bv = *reinterpret_cast<const u32x4 *>(&xT[nb * 16 + (lane & 15)][8 * g]);
+        acc[b] = mfma(av, bv, acc[b]);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int b = 0; b < PER_WAVE; ++b) {
+    const int blk = wave * PER_WAVE + b;
+    if (blk < NBLK) {
+      const int mb = blk / NB, nb = blk % NB;
+      const int ci = nb * 16 + (lane & 15);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int co = mb * 16 + 4 * g + j;
+        partial[((split * COUT + co) * 9 + tap) * CIN + ci] = acc[b][j];
+      }
+    }
+  }
+}
+
+// First layer's weight gradient on the vector ALU: grid (9, nsplit), each
+// thread accumulates 16 output channels over its pixels, then the block
+// reduces.  partial[split][co][tap] (CIN = 1).
+__global__ __launch_bounds__(256) void conv0_bwd_weight_kernel(const uint16_t *__restrict__ dz,
+                                                               const uint16_t *__restrict__ x,
+                                                               float *__restrict__ partial,
+                                                               int64_t npix_out, int64_t chunk) {
+  constexpr Layer L = kLayers[0];
+  __shared__ float red[256][17];
+  const int tap = blockIdx.x, ky = tap / 3, kx = tap % 3;
+  const int64_t split = blockIdx.y;
+  const int64_t pbeg = split * chunk;
+  const int64_t pend = pbeg + chunk < npix_out ? pbeg + chunk : npix_out;
+  float acc[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) acc[c] = 0.f;
+  for (int64_t q = pbeg + threadIdx.x; q < pend; q += 256) {
+    const int64_t n = q / (L.hout * L.wout);
+    const int r = (int)(q - n * L.hout * L.wout);
+    const int iy = 2 * (r / L.wout) + ky - 1, ix = 2 * (r % L.wout) + kx - 1;
+    if (iy < 0 || iy >= L.hin || ix < 0 || ix >= L.win) continue;
+    const float xv = bf2f(x[(n * L.hin + iy) * L.win + ix]);
+    const u32x4 *d = reinterpret_cast<const u32x4 *>(dz + q * 16);
+    const u32x4 d0 = d[0], d1 = d[1];
+    const uint16_t *h0 = reinterpret_cast<const uint16_t *>(&d0);
+    const uint16_t *h1 = reinterpret_cast<const uint16_t *>(&d1);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      acc[c] += bf2f(h0[c]) * xv;
+      acc[c + 8] += bf2f(h1[c]) * xv;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 16; ++c) red[threadIdx.x][c] = acc[c];
+  __syncthreads();
+  if (threadIdx.x < 16) {
+    float s = 0.f;
+    for (int t = 0; t < 256; ++t) s += red[t][threadIdx.x];
+    partial[(split * 16 + threadIdx.x) * 9 + tap] = s;
+  }
+}
+
+// part[split][co] = sum over the split's pixels of dz[q][co].
+__global__ __launch_bounds__(256) void bias_partial_kernel(const uint16_t *__restrict__ dz,
+                                                           int cout, int64_t npix,
+                                                           int64_t chunk,
+                                                           float *__restrict__ part) {
+  __shared__ float red[256];
+  const int64_t split = blockIdx.x;
+  const int64_t pbeg = split * chunk;
+  const int64_t pend = pbeg + chunk < npix ? pbeg + chunk : npix;
+  const int lanes = 256 / cout;  // pixels in flight per step (cout divides 256)
+  const int c = threadIdx.x % cout, r = threadIdx.x / cout;
+  float s = 0.f;
+  for (int64_t q = pbeg + r; q < pend; q += lanes) s += bf2f(dz[q * cout + c]);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x < cout) {
+    float t = 0.f;
+    for (int k = 0; k < lanes; ++k) t += red[k * cout + threadIdx.x];
+    part[split * cout + threadIdx.x] = t;
+  }
+}
+
+// grads[co][ci][tap] = sum_s partial[s][co][tap][ci] (fixed order).
+__global__ __launch_bounds__(256) void reduce_weight_kernel(const float *__restrict__ partial,
+                                                            int nsplit, int cout, int cin,
+                                                            float *__restrict__ grad) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t total = (int64_t)cout * cin * 9;
+  if (e >= total) return;
+  const int co = (int)(e / (cin * 9));
+  const int rem = (int)(e - (int64_t)co * cin * 9);
+  const int ci = rem / 9, tap = rem % 9;
+  float s = 0.f;
+  for (int k = 0; k < nsplit; ++k) s += partial[(((int64_t)k * cout + co) * 9 + tap) * cin + ci];
+  grad[e] = s;
+}
+
+// out[i] = sum_s part[s][i] for i < count (fixed order).
+__global__ __launch_bounds__(256) void reduce_rows_kernel(const float *__restrict__ part,
+                                                          int nrows, int count,
+                                                          float *__restrict__ out) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= count) return;
+  float s = 0.f;
+  for (int k = 0; k < nrows; ++k) s += part[(int64_t)k * count + i];
+  out[i] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Optimiser and weight packing
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void adam_kernel(float *__restrict__ p,
+                                                   const float *__restrict__ g,
+                                                   float *__restrict__ m, float *__restrict__ v,
+                                                   int64_t count, float lr, float b1, float b2,
+                                                   float eps, float bc1, float bc2) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= count) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+}
+
+// wp[co][tap * cin + ci] and (if wt) wt[ci][tap * cout + co] from the master
+// weights w[co][ci][tap]; padding of wp is zero.
+__global__ __launch_bounds__(256) void pack_weights_kernel(const float *__restrict__ w, int cin,
+                                                           int cout, int kpad,
+                                                           uint16_t *__restrict__ wp,
+                                                           uint16_t *__restrict__ wt) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)cout * kpad) return;
+  const int co = (int)(e / kpad), k = (int)(e % kpad);
+  const int tap = k / cin, ci = k % cin;
+  if (tap >= 9) {
+    wp[e] = 0;
+    return;
+  }
+  const uint16_t b = f2bf(w[((int64_t)co * cin + ci) * 9 + tap]);
+  wp[e] = b;
+  if (wt) wt[(int64_t)ci * 9 * cout + tap * cout + co] = b;
+}
+
+int64_t layer_param_offset(int li) {
+  int64_t off = 0;
+  for (int i = 0; i < li; ++i) off += kLayers[i].wcount() + kLayers[i].cout;
+  return off;
+}
+constexpr int64_t head_param_offset() {
+  int64_t off = 0;
+  for (int i = 0; i < kNumLayers; ++i) off += kLayers[i].wcount() + kLayers[i].cout;
+  return off;
+}
+constexpr int64_t kParams = head_param_offset() + kHead * kFeat + kHead;
+
+int64_t npix_out(int li, int n) { return (int64_t)n * kLayers[li].hout * kLayers[li].wout; }
+int64_t npix_in(int li, int n) { return (int64_t)n * kLayers[li].hin * kLayers[li].win; }
+
+// Splits of the weight-gradient reduction: about 64-128 per layer, chunks a
+// multiple of the staged K-step.
+int64_t split_chunk(int64_t npix) {
+  int64_t c = (npix + 95) / 96;
+  c = (c + kKP - 1) / kKP * kKP;
+  return c < kKP ? kKP : c;
+}
+
+}  // namespace
+
+struct sps_cnn_s {
+  int device = 0;
+  int32_t max_batch = 0;
+  int64_t step = 0;
+  float *params = nullptr, *grads = nullptr, *m = nullptr, *v = nullptr;
+  uint16_t *wp[kNumLayers] = {}, *wt[kNumLayers] = {};
+  uint16_t *act[kNumLayers] = {}, *dz[kNumLayers] = {};
+  float *partial = nullptr;   // weight-gradient partials (largest layer)
+  float *bpart = nullptr;     // bias partials
+  float *head_part = nullptr; // per head block: [3][128] + [3] + [1]
+  float *loss = nullptr;      // device scalar of the last loss_grad
+  float *head = nullptr;      // head outputs of the last forward
+  int64_t partial_cap = 0, bpart_cap = 0;
+};
+
+namespace {
+
+sps_status cnn_dev_fail(hipError_t e, const char *what) {
+  char m[256];
+  snprintf(m, sizeof m, "%s: %s", what, hipGetErrorString(e));
+  return sps::set_error(SPS_ERR_DEVICE, m);
+}
+
+void cnn_free(sps_cnn c) {
+  void *ptrs[] = {c->params, c->grads, c->m, c->v, c->partial, c->bpart, c->head_part, c->loss,
+                  c->head};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  for (int i = 0; i < kNumLayers; ++i) {
+    if (c->wp[i]) (void)hipFree(c->wp[i]);
+    if (c->wt[i]) (void)hipFree(c->wt[i]);
+    if (c->act[i]) (void)hipFree(c->act[i]);
+    if (c->dz[i]) (void)hipFree(c->dz[i]);
+  }
+}
+
+hipError_t pack_all(sps_cnn c, hipStream_t s) {
+  for (int i = 0; i < kNumLayers; ++i) {
+    const Layer &L = kLayers[i];
+    const int64_t total = (int64_t)L.cout * L.kpad();
+    hipLaunchKernelGGL(pack_weights_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
+                       c->params + layer_param_offset(i), L.cin, L.cout, L.kpad(), c->wp[i],
+                       c->wt[i]);
+  }
+  return hipGetLastError();
+}
+
+#define SPS_LAUNCH_CHECK(what)                     \
+  do {                                             \
+    hipError_t e_ = hipGetLastError();             \
+    if (e_ != hipSuccess) return cnn_dev_fail(e_, what); \
+  } while (0)
+
+sps_status run_forward(sps_cnn c, const uint16_t *tiles, int32_t n, hipStream_t s) {
+  {
+    const int64_t np = npix_out(0, n);
+    hipLaunchKernelGGL(conv0_fwd_kernel, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s,
+                       tiles, c->wp[0], c->params + layer_param_offset(0) + kLayers[0].wcount(),
+                       c->act[0], np);
+  }
+#define SPS_FWD(LI)                                                                          \
+  {                                                                                          \
+    const int64_t np = npix_out(LI, n);                                                      \
+    hipLaunchKernelGGL(conv_fwd_kernel<LI>, dim3((unsigned)((np + 63) / 64)), dim3(256), 0, s, \
+                       c->act[LI - 1], c->wp[LI],                                            \
+                       c->params + layer_param_offset(LI) + kLayers[LI].wcount(), c->act[LI], \
+                       np);                                                                  \
+  }
+  SPS_FWD(1) SPS_FWD(2) SPS_FWD(3) SPS_FWD(4) SPS_FWD(5)
+#undef SPS_FWD
+  SPS_LAUNCH_CHECK("forward launch");
+  return SPS_OK;
+}
+
+sps_status run_head(sps_cnn c, const float *labels, int32_t n, bool train, hipStream_t s) {
+  const int64_t ncell = (int64_t)n * kCells;
+  const int nblk = (int)((ncell + 127) / 128);
+  float *part_wh = c->head_part;
+  float *part_bh = part_wh + (int64_t)nblk * kHead * kFeat;
+  float *part_loss = part_bh + (int64_t)nblk * kHead;
+  const int64_t hoff = head_param_offset();
+  hipLaunchKernelGGL(head_loss_kernel, dim3((unsigned)nblk), dim3(128), 0, s, c->act[5],
+                     c->params + hoff, c->params + hoff + kHead * kFeat, labels, ncell,
+                     1.0f / (float)n, c->head, c->dz[5], part_wh, part_bh, part_loss, train ? 1 : 0);
+  if (train) {
+    hipLaunchKernelGGL(reduce_rows_kernel, dim3((kHead * kFeat + 255) / 256), dim3(256), 0, s,
+                       part_wh, nblk, kHead * kFeat, c->grads + hoff);
+    hipLaunchKernelGGL(reduce_rows_kernel, dim3(1), dim3(256), 0, s, part_bh, nblk, kHead,
+                       c->grads + hoff + kHead * kFeat);
+    hipLaunchKernelGGL(reduce_rows_kernel, dim3(1), dim3(256), 0, s, part_loss, nblk, 1, c->loss);
+  }
+  SPS_LAUNCH_CHECK("head launch");
+  return SPS_OK;
+}
+
+sps_status run_backward(sps_cnn c, const uint16_t *tiles, int32_t n, hipStream_t s) {
+  for (int li = kNumLayers - 1; li >= 0; --li) {
+    const Layer &L = kLayers[li];
+    const int64_t np = npix_out(li, n);
+    const int64_t chunk = split_chunk(np);
+    const int64_t nsplit = (np + chunk - 1) / chunk;
+    const uint16_t *xin = li == 0 ? tiles : c->act[li - 1];
+    float *gw = c->grads + layer_param_offset(li);
+    switch (li) {
+      case 0:
+        hipLaunchKernelGGL(conv0_bwd_weight_kernel, dim3(9, (unsigned)nsplit), dim3(256), 0, s,
+                           c->dz[0], xin, c->partial, np, chunk);
+        break;
+#define SPS_BWDW(LI)                                                                       \
+  case LI:                                                                                 \
+    hipLaunchKernelGGL(conv_bwd_weight_kernel<LI>, dim3(9, (unsigned)nsplit), dim3(256), 0, s, \
+                       c->dz[LI], xin, c->partial, np, chunk);                             \
+    break;
+        SPS_BWDW(1) SPS_BWDW(2) SPS_BWDW(3) SPS_BWDW(4) SPS_BWDW(5)
+#undef SPS_BWDW
+    }
+    hipLaunchKernelGGL(reduce_weight_kernel, dim3((unsigned)((L.wcount() + 255) / 256)), dim3(256),
+                       0, s, c->partial, (int)nsplit, L.cout, L.cin, gw);
+    hipLaunchKernelGGL(bias_partial_kernel, dim3((unsigned)nsplit), dim3(256), 0, s, c->dz[li],
+                       L.cout, np, chunk, c->bpart);
+    hipLaunchKernelGGL(reduce_rows_kernel, dim3(1), dim3(256), 0, s, c->bpart, (int)nsplit, L.cout,
+                       gw + L.wcount());
+    if (li > 0) {
+      const int64_t ni = npix_in(li, n);
+      const unsigned grid = (unsigned)((ni + 63) / 64);
+      switch (li) {
+#define SPS_BWDD(LI)                                                                          \
+  case LI:                                                                                    \
+    hipLaunchKernelGGL(conv_bwd_data_kernel<LI>, dim3(grid), dim3(256), 0, s, c->dz[LI],      \
+                       c->wt[LI], c->act[LI - 1], c->dz[LI - 1], ni);                         \
+    break;
+        SPS_BWDD(1) SPS_BWDD(2) SPS_BWDD(3) SPS_BWDD(4) SPS_BWDD(5)
+#undef SPS_BWDD
+      }
+    }
+    SPS_LAUNCH_CHECK("backward launch");
+  }
+  return SPS_OK;
+}
+
+sps_status check_batch(sps_cnn c, const void *tiles, int32_t n) {
+  if (!c || !tiles) return sps::set_error(SPS_ERR_INVALID_ARG, "NULL network or tiles");
+  if (n < 1 || n > c->max_batch)
+    return sps::set_error(SPS_ERR_INVALID_ARG, "batch size must be in [1, max_batch]");
+  if ((uintptr_t)tiles % 16 != 0) return sps::set_error(SPS_ERR_INVALID_ARG, "tiles not 16-byte aligned");
+  return SPS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t sps_cnn_param_count(void) { return kParams; }
+
+sps_status sps_cnn_create(int32_t max_batch, sps_cnn *out) {
+  if (!out) return sps::set_error(SPS_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (max_batch < 1 || max_batch > 4096)
+    return sps::set_error(SPS_ERR_INVALID_ARG, "max_batch must be in [1, 4096]");
+  sps_cnn c = new (std::nothrow) sps_cnn_s;
+  if (!c) return sps::set_error(SPS_ERR_NOMEM, "host allocation failed");
+  hipError_t e = hipGetDevice(&c->device);
+  c->max_batch = max_batch;
+  int64_t pmax = 0;
+  for (int i = 0; i < kNumLayers; ++i) {
+    const int64_t np = npix_out(i, max_batch);
+    const int64_t ns = (np + split_chunk(np) - 1) / split_chunk(np);
+    pmax = ns * kLayers[i].wcount() > pmax ? ns * kLayers[i].wcount() : pmax;
+    c->bpart_cap = ns * kLayers[i].cout > c->bpart_cap ? ns * kLayers[i].cout : c->bpart_cap;
+  }
+  c->partial_cap = pmax;
+  const int64_t nblk = ((int64_t)max_batch * kCells + 127) / 128;
+  auto alloc = [&](void **p, size_t bytes) {
+    if (e == hipSuccess) e = hipMalloc(p, bytes);
+  };
+  alloc((void **)&c->params, sizeof(float) * kParams);
+  alloc((void **)&c->grads, sizeof(float) * kParams);
+  alloc((void **)&c->m, sizeof(float) * kParams);
+  alloc((void **)&c->v, sizeof(float) * kParams);
+  alloc((void **)&c->partial, sizeof(float) * (size_t)pmax);
+  alloc((void **)&c->bpart, sizeof(float) * (size_t)c->bpart_cap);
+  alloc((void **)&c->head_part, sizeof(float) * (size_t)(nblk * (kHead * kFeat + kHead + 1)));
+  alloc((void **)&c->loss, sizeof(float) * 4);
+  alloc((void **)&c->head, sizeof(float) * (size_t)max_batch * kHead * kCells);
+  for (int i = 0; i < kNumLayers; ++i) {
+    const Layer &L = kLayers[i];
+    alloc((void **)&c->wp[i], sizeof(uint16_t) * (size_t)L.cout * L.kpad());
+    if (i > 0) alloc((void **)&c->wt[i], sizeof(uint16_t) * (size_t)L.cin * 9 * L.cout);
+    const size_t a = sizeof(uint16_t) * (size_t)npix_out(i, max_batch) * L.cout;
+    alloc((void **)&c->act[i], a);
+    alloc((void **)&c->dz[i], a);
+  }
+  if (e == hipSuccess) e = hipMemset(c->params, 0, sizeof(float) * kParams);
+  if (e == hipSuccess) e = hipMemset(c->grads, 0, sizeof(float) * kParams);
+  if (e == hipSuccess) e = hipMemset(c->m, 0, sizeof(float) * kParams);
+  if (e == hipSuccess) e = hipMemset(c->v, 0, sizeof(float) * kParams);
+  if (e == hipSuccess) e = hipMemset(c->loss, 0, sizeof(float) * 4);
+  if (e == hipSuccess) {
+    e = pack_all(c, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    cnn_free(c);
+    delete c;
+    return sps::set_error(SPS_ERR_NOMEM, "device allocation for the network failed");
+  }
+  *out = c;
+  return SPS_OK;
+}
+
+sps_status sps_cnn_destroy(sps_cnn c) {
+  if (!c) return SPS_OK;
+  (void)hipDeviceSynchronize();
+  cnn_free(c);
+  delete c;
+  return SPS_OK;
+}
+
+sps_status sps_cnn_set_params(sps_cnn c, const float *host) {
+  if (!c || !host) return sps::set_error(SPS_ERR_INVALID_ARG, "NULL argument");
+  hipError_t e = hipMemcpy(c->params, host, sizeof(float) * kParams, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(c->m, 0, sizeof(float) * kParams);
+  if (e == hipSuccess) e = hipMemset(c->v, 0, sizeof(float) * kParams);
+  if (e == hipSuccess) e = pack_all(c, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) return cnn_dev_fail(e, "setting parameters");
+  c->step = 0;
+  return SPS_OK;
+}
+
+sps_status sps_cnn_get_params(sps_cnn c, float *host) {
+  if (!c || !host) return sps::set_error(SPS_ERR_INVALID_ARG, "NULL argument");
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(host, c->params, sizeof(float) * kParams, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return cnn_dev_fail(e, "reading parameters");
+  return SPS_OK;
+}
+
+sps_status sps_cnn_get_grads(sps_cnn c, float *host) {
+  if (!c || !host) return sps::set_error(SPS_ERR_INVALID_ARG, "NULL argument");
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(host, c->grads, sizeof(float) * kParams, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return cnn_dev_fail(e, "reading gradients");
+  return SPS_OK;
+}
+
+sps_status sps_cnn_set_grads(sps_cnn c, const float *host) {
+  if (!c || !host) return sps::set_error(SPS_ERR_INVALID_ARG, "NULL argument");
+  hipError_t e = hipMemcpy(c->grads, host, sizeof(float) * kParams, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return cnn_dev_fail(e, "setting gradients");
+  return SPS_OK;
+}
+
+sps_status sps_cnn_activations(sps_cnn c, int32_t layer, int32_t n, uint16_t *host) {
+  if (!c || !host || layer < 0 || layer >= kNumLayers || n < 1 || n > c->max_batch)
+    return sps::set_error(SPS_ERR_INVALID_ARG, "bad network, layer, count or output");
+  hipError_t e = hipDeviceSynchronize();
+  const size_t bytes = sizeof(uint16_t) * (size_t)npix_out(layer, n) * kLayers[layer].cout;
+  if (e == hipSuccess) e = hipMemcpy(host, c->act[layer], bytes, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return cnn_dev_fail(e, "reading activations");
+  return SPS_OK;
+}
+
+sps_status sps_cnn_pool_tiles(const float *snr, int64_t pitch, int32_t ndm, int64_t nout,
+                              float scale, uint16_t *tiles, void *stream) {
+  if (!snr || !tiles) return sps::set_error(SPS_ERR_INVALID_ARG, "NULL plane or tiles");
+  if (ndm < kPoolDm || nout < kPoolT || pitch < nout)
+    return sps::set_error(SPS_ERR_INVALID_ARG, "plane smaller than one pooling window");
+  const int64_t nd = ndm / kPoolDm, nt = nout / kPoolT;
+  const int64_t total = nd * nt;
+  if ((total + 255) / 256 > 0x7FFFFFFF) return sps::set_error(SPS_ERR_RANGE, "plane too large");
+  hipLaunchKernelGGL(pool_tiles_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
+                     (hipStream_t)stream, snr, pitch, nd, nt, scale, tiles);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return cnn_dev_fail(e, "pooling launch");
+  return SPS_OK;
+}
+
+sps_status sps_cnn_forward(sps_cnn c, const uint16_t *tiles, int32_t n, float *head,
+                           void *stream) {
+  sps_status r = check_batch(c, tiles, n);
+  if (r != SPS_OK) return r;
+  hipStream_t s = (hipStream_t)stream;
+  r = run_forward(c, tiles, n, s);
+  if (r != SPS_OK) return r;
+  r = run_head(c, nullptr, n, false, s);
+  if (r != SPS_OK) return r;
+  if (head) {
+    hipError_t e = hipMemcpyAsync(head, c->head, sizeof(float) * (size_t)n * kHead * kCells,
+                                  hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return cnn_dev_fail(e, "head copy");
+  }
+  return SPS_OK;
+}
+
+sps_status sps_cnn_loss_grad(sps_cnn c, const uint16_t *tiles, const float *labels, int32_t n,
+                             float *loss, void *stream) {
+  sps_status r = check_batch(c, tiles, n);
+  if (r != SPS_OK) return r;
+  if (!labels) return sps::set_error(SPS_ERR_INVALID_ARG, "NULL labels");
+  hipStream_t s = (hipStream_t)stream;
+  r = run_forward(c, tiles, n, s);
+  if (r == SPS_OK) r = run_head(c, labels, n, true, s);
+  if (r == SPS_OK) r = run_backward(c, tiles, n, s);
+  if (r != SPS_OK) return r;
+  if (loss) {
+    hipError_t e = hipMemcpyAsync(loss, c->loss, sizeof(float), hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return cnn_dev_fail(e, "loss copy");
+  }
+  return SPS_OK;
+}
+
+sps_status sps_cnn_adam(sps_cnn c, float lr, float beta1, float beta2, float eps, void *stream) {
+  if (!c) return sps::set_error(SPS_ERR_INVALID_ARG, "NULL network");
+  if (!(lr > 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
+    return sps::set_error(SPS_ERR_INVALID_ARG, "bad Adam hyper-parameters");
+  hipStream_t s = (hipStream_t)stream;
+  c->step += 1;
+  const double bc1 = 1.0 - pow((double)beta1, (double)c->step);
+  const double bc2 = 1.0 - pow((double)beta2, (double)c->step);
+  hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((kParams + 255) / 256)), dim3(256), 0, s,
+                     c->params, c->grads, c->m, c->v, kParams, lr, beta1, beta2, eps, (float)bc1,
+                     (float)bc2);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = pack_all(c, s);
+  if (e != hipSuccess) return cnn_dev_fail(e, "Adam launch");
+  return SPS_OK;
+}
+
+sps_status sps_cnn_train_step(sps_cnn c, const uint16_t *tiles, const float *labels, int32_t n,
+                              float lr, float *loss, void *stream) {
+  sps_status r = sps_cnn_loss_grad(c, tiles, labels, n, loss, stream);
+  if (r != SPS_OK) return r;
+  return sps_cnn_adam(c, lr, 0.9f, 0.999f, 1e-8f, stream);
+}
+
+sps_status sps_cnn_detect(sps_cnn c, const uint16_t *tiles, int32_t n, float threshold,
+                          sps_cnn_candidate *out, int32_t cap, int32_t *n_found, void *stream) {
+  if (!n_found) return sps::set_error(SPS_ERR_INVALID_ARG, "NULL n_found");
+  *n_found = 0;
+  if (cap < 0 || (cap > 0 && !out)) return sps::set_error(SPS_ERR_INVALID_ARG, "bad output array");
+  if (!(threshold > 0.0f && threshold < 1.0f))
+    return sps::set_error(SPS_ERR_INVALID_ARG, "threshold must be a probability in (0, 1)");
+  sps_status r = sps_cnn_forward(c, tiles, n, nullptr, stream);
+  if (r != SPS_OK) return r;
+  std::vector<float> h((size_t)n * kHead * kCells);
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(h.data(), c->head, sizeof(float) * h.size(), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return cnn_dev_fail(e, "reading head outputs");
+  const float logit = logf(threshold / (1.0f - threshold));
+  int32_t found = 0;
+  for (int32_t t = 0; t < n; ++t)
+    for (int cell = 0; cell < kCells; ++cell) {
+      const float o = h[((size_t)t * kHead + 0) * kCells + cell];
+      if (!(o >= logit)) continue;
+      if (found < cap) {
+        const int gy = cell / kGridT, gx = cell % kGridT;
+        sps_cnn_candidate &q = out[found];
+        q.tile = t;
+        q.cell_dm = gy;
+        q.cell_t = gx;
+        q.prob = 1.0f / (1.0f + expf(-o));
+        q.row = (gy + h[((size_t)t * kHead + 1) * kCells + cell]) * (float)(kTileDm / kGridDm);
+        q.col = (gx + h[((size_t)t * kHead + 2) * kCells + cell]) * (float)(kTileT / kGridT);
+      }
+      ++found;
+    }
+  *n_found = found;
+  if (found > cap) return sps::set_error(SPS_ERR_TRUNCATED, "more cells above threshold than cap");
+  return SPS_OK;
+}
+
+}  // extern "C"

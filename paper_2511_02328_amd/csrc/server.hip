@@ -17,9 +17,10 @@
 // phase_i + (k + 1) T_i / compression, T_i the chunk's duration.  Worker
 // threads take released chunks in arrival order (a stream's chunks strictly
 // in sequence), each on its own HIP stream with its own output planes and
-// plans: host-to-device copy behind the overlap, dedispersion, statistics +
-// boxcar S/N, overlap moved to the front of the ring, detection.  A chunk's
-// latency is its completion time minus its arrival time.
+// plans: host-to-device copy behind the overlap, then, holding the server's
+// compute lock, dedispersion, statistics + boxcar S/N, overlap moved to the
+// front of the ring and detection.  A chunk's latency is its completion time
+// minus its arrival time.
 #include <stdio.h>
 #include <string.h>
 
@@ -106,6 +107,11 @@ sps_status dev_fail(hipError_t e, const char *what) {
 struct sps_server_s {
   int device = 0;
   int64_t budget = 0, used = 0;
+  // One chunk's kernels at a time: the dedispersion kernel relies on the
+  // workgroups resident on an XCD sharing input windows in its L2, which
+  // concurrent launches from several workers would interleave away.  Uploads
+  // run outside the lock, so one worker's copy overlaps another's search.
+  std::mutex compute;
   std::vector<SetupKey> setups;
   std::vector<int64_t> setup_delay;  // D_max per set-up
   std::vector<StreamState> streams;
@@ -147,7 +153,9 @@ sps_status process_chunk(sps_server s, Worker &w, int sid, const uint8_t *src, i
   *n_found = 0;
   hipError_t e = hipMemcpy2DAsync(st.ring + st.overlap, (size_t)st.pitch, src, (size_t)src_pitch,
                                   (size_t)st.chunk, (size_t)st.nchan, hipMemcpyHostToDevice, hs);
+  if (e == hipSuccess) e = hipStreamSynchronize(hs);
   if (e != hipSuccess) return dev_fail(e, "chunk upload");
+  std::lock_guard<std::mutex> lk(s->compute);
   sps_status r =
       sps_dedisperse(plan, st.ring, st.pitch, st.overlap + st.chunk, w.Y, st.chunk, 0, hs);
   if (r != SPS_OK) return r;

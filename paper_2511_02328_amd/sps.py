@@ -75,6 +75,11 @@ class sps_chunk_record(ctypes.Structure):
                 ("end_s", ctypes.c_double), ("n_cand", ctypes.c_int32), ("status", ctypes.c_int32)]
 
 
+class sps_cnn_candidate(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_int32), ("cell_dm", ctypes.c_int32), ("cell_t", ctypes.c_int32),
+                ("prob", ctypes.c_float), ("row", ctypes.c_float), ("col", ctypes.c_float)]
+
+
 _lib = None
 
 
@@ -124,6 +129,28 @@ def library() -> ctypes.CDLL:
         lib.sps_server_run.argtypes = [P, ctypes.POINTER(sps_feed), ctypes.c_double,
                                        ctypes.c_double, ctypes.POINTER(sps_chunk_record), i32,
                                        ctypes.POINTER(i32)]
+        lib.sps_cnn_param_count.argtypes = []
+        lib.sps_cnn_param_count.restype = i64
+        lib.sps_cnn_create.argtypes = [i32, ctypes.POINTER(P)]
+        lib.sps_cnn_destroy.argtypes = [P]
+        for f in ("sps_cnn_set_params", "sps_cnn_get_params", "sps_cnn_set_grads",
+                  "sps_cnn_get_grads"):
+            getattr(lib, f).argtypes = [P, P]
+        lib.sps_cnn_activations.argtypes = [P, i32, i32, P]
+        lib.sps_cnn_pool_tiles.argtypes = [P, i64, i32, i64, ctypes.c_float, P, P]
+        lib.sps_cnn_forward.argtypes = [P, P, i32, P, P]
+        lib.sps_cnn_loss_grad.argtypes = [P, P, P, i32, P, P]
+        lib.sps_cnn_adam.argtypes = [P, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                     ctypes.c_float, P]
+        lib.sps_cnn_train_step.argtypes = [P, P, P, i32, ctypes.c_float, P, P]
+        lib.sps_cnn_detect.argtypes = [P, P, i32, ctypes.c_float,
+                                       ctypes.POINTER(sps_cnn_candidate), i32,
+                                       ctypes.POINTER(i32), P]
+        for f in ("sps_cnn_create", "sps_cnn_destroy", "sps_cnn_set_params", "sps_cnn_get_params",
+                  "sps_cnn_set_grads", "sps_cnn_get_grads", "sps_cnn_activations",
+                  "sps_cnn_pool_tiles", "sps_cnn_forward", "sps_cnn_loss_grad", "sps_cnn_adam",
+                  "sps_cnn_train_step", "sps_cnn_detect"):
+            getattr(lib, f).restype = ctypes.c_int
         for f in ("sps_server_create", "sps_server_destroy", "sps_server_add_stream",
                   "sps_server_memory", "sps_server_stream_info", "sps_server_push",
                   "sps_server_run"):
@@ -146,7 +173,7 @@ def header_functions() -> list:
     hdr = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
                        "include", "sps.h")
     text = open(hdr).read()
-    return sorted(set(re.findall(r"^\s*(?:sps_status|const char \*|int32_t)\s*(sps_\w+)\s*\(",
+    return sorted(set(re.findall(r"^\s*(?:sps_status|const char \*|int32_t|int64_t)\s*(sps_\w+)\s*\(",
                                  text, re.M)))
 
 
@@ -557,6 +584,152 @@ def sps_server_run(server: Server, feeds: Sequence[dict], run_s: float, compress
     k = min(int(n.value), cap)
     return np.frombuffer(bytes(recs)[:k * ctypes.sizeof(sps_chunk_record)],
                          dtype=RECORD_DTYPE).copy()
+
+
+class Cnn:
+    """Owns an sps_cnn handle."""
+
+    def __init__(self, handle, max_batch):
+        self.handle, self.max_batch = handle, max_batch
+
+    def close(self) -> None:
+        if self.handle:
+            sps_cnn_destroy(self)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+CNN_CANDIDATE_DTYPE = np.dtype([("tile", np.int32), ("cell_dm", np.int32), ("cell_t", np.int32),
+                                ("prob", np.float32), ("row", np.float32), ("col", np.float32)])
+CNN_LAYERS = ((1, 16, 2), (16, 32, 2), (32, 64, 2), (64, 128, 2), (128, 128, 2), (128, 128, 1))
+CNN_TILE = (256, 512)
+CNN_GRID = (8, 16)
+
+
+def sps_cnn_param_count() -> int:
+    return int(library().sps_cnn_param_count())
+
+
+def sps_cnn_create(max_batch: int) -> Cnn:
+    h = ctypes.c_void_p()
+    _check(library().sps_cnn_create(int(max_batch), ctypes.byref(h)), "sps_cnn_create")
+    return Cnn(h.value, int(max_batch))
+
+
+def sps_cnn_destroy(net: Cnn) -> None:
+    h, net.handle = net.handle, None
+    if h:
+        _check(library().sps_cnn_destroy(h), "sps_cnn_destroy")
+
+
+def _params_vec(a) -> np.ndarray:
+    v = np.ascontiguousarray(a, dtype=np.float32).ravel()
+    if v.size != sps_cnn_param_count():
+        raise ValueError(f"expected {sps_cnn_param_count()} parameters, got {v.size}")
+    return v
+
+
+def sps_cnn_set_params(net: Cnn, params) -> None:
+    v = _params_vec(params)
+    _check(library().sps_cnn_set_params(net.handle, v.ctypes.data), "sps_cnn_set_params")
+
+
+def sps_cnn_get_params(net: Cnn) -> np.ndarray:
+    v = np.empty(sps_cnn_param_count(), np.float32)
+    _check(library().sps_cnn_get_params(net.handle, v.ctypes.data), "sps_cnn_get_params")
+    return v
+
+
+def sps_cnn_set_grads(net: Cnn, grads) -> None:
+    v = _params_vec(grads)
+    _check(library().sps_cnn_set_grads(net.handle, v.ctypes.data), "sps_cnn_set_grads")
+
+
+def sps_cnn_get_grads(net: Cnn) -> np.ndarray:
+    v = np.empty(sps_cnn_param_count(), np.float32)
+    _check(library().sps_cnn_get_grads(net.handle, v.ctypes.data), "sps_cnn_get_grads")
+    return v
+
+
+def sps_cnn_activations(net: Cnn, layer: int, n: int) -> np.ndarray:
+    """bf16 bit patterns NHWC [n][h][w][cout] of 3x3 layer `layer`."""
+    size = 256 // 2 ** min(layer + 1, 5), 512 // 2 ** min(layer + 1, 5)
+    out = np.empty((n, size[0], size[1], CNN_LAYERS[layer][1]), np.uint16)
+    _check(library().sps_cnn_activations(net.handle, int(layer), int(n), out.ctypes.data),
+           "sps_cnn_activations")
+    return out
+
+
+def _tiles_ptr(tiles: torch.Tensor) -> int:
+    if (not isinstance(tiles, torch.Tensor) or tiles.device.type != "cuda"
+            or tiles.dtype not in (torch.uint16, torch.int16, torch.bfloat16)
+            or not tiles.is_contiguous() or tuple(tiles.shape[-2:]) != CNN_TILE):
+        raise TypeError("tiles must be a contiguous 16-bit [n][256][512] tensor on a GPU")
+    return tiles.data_ptr()
+
+
+def sps_cnn_pool_tiles(snr: torch.Tensor, nout: int, scale: float, tiles: torch.Tensor,
+                       stream=None) -> None:
+    if snr.dim() != 2 or snr.stride(1) != 1:
+        raise ValueError("snr must be [ndm][pitch] with unit stride")
+    if tiles.dtype not in (torch.uint16, torch.int16, torch.bfloat16) or not tiles.is_contiguous():
+        raise TypeError("tiles must be a contiguous 16-bit tensor")
+    _check(library().sps_cnn_pool_tiles(_dev(snr, torch.float32, "snr"), snr.stride(0),
+                                        snr.shape[0], int(nout), float(scale), tiles.data_ptr(),
+                                        _stream(stream)), "sps_cnn_pool_tiles")
+
+
+def sps_cnn_forward(net: Cnn, tiles: torch.Tensor, n: int, head: Optional[torch.Tensor] = None,
+                    stream=None) -> None:
+    hp = _dev(head, torch.float32, "head") if head is not None else None
+    _check(library().sps_cnn_forward(net.handle, _tiles_ptr(tiles), int(n), hp, _stream(stream)),
+           "sps_cnn_forward")
+
+
+def sps_cnn_loss_grad(net: Cnn, tiles: torch.Tensor, labels: torch.Tensor, n: int,
+                      loss: Optional[torch.Tensor] = None, stream=None) -> None:
+    lp = _dev(loss, torch.float32, "loss") if loss is not None else None
+    _check(library().sps_cnn_loss_grad(net.handle, _tiles_ptr(tiles),
+                                       _dev(labels, torch.float32, "labels"), int(n), lp,
+                                       _stream(stream)), "sps_cnn_loss_grad")
+
+
+def sps_cnn_adam(net: Cnn, lr: float, beta1: float = 0.9, beta2: float = 0.999,
+                 eps: float = 1e-8, stream=None) -> None:
+    _check(library().sps_cnn_adam(net.handle, float(lr), float(beta1), float(beta2), float(eps),
+                                  _stream(stream)), "sps_cnn_adam")
+
+
+def sps_cnn_train_step(net: Cnn, tiles: torch.Tensor, labels: torch.Tensor, n: int, lr: float,
+                       loss: Optional[torch.Tensor] = None, stream=None) -> None:
+    lp = _dev(loss, torch.float32, "loss") if loss is not None else None
+    _check(library().sps_cnn_train_step(net.handle, _tiles_ptr(tiles),
+                                        _dev(labels, torch.float32, "labels"), int(n), float(lr),
+                                        lp, _stream(stream)), "sps_cnn_train_step")
+
+
+def sps_cnn_detect(net: Cnn, tiles: torch.Tensor, n: int, threshold: float, cap: int = 65536,
+                   stream=None, allow_truncated: bool = False):
+    out = (sps_cnn_candidate * max(cap, 1))()
+    k = ctypes.c_int32()
+    rc = library().sps_cnn_detect(net.handle, _tiles_ptr(tiles), int(n), float(threshold), out,
+                                  int(cap), ctypes.byref(k), _stream(stream))
+    if not (rc == 6 and allow_truncated):
+        _check(rc, "sps_cnn_detect")
+    m = min(int(k.value), cap)
+    arr = np.frombuffer(bytes(out)[:m * ctypes.sizeof(sps_cnn_candidate)],
+                        dtype=CNN_CANDIDATE_DTYPE).copy()
+    return arr, int(k.value)
 
 
 def plan_for(wl) -> Plan:

@@ -167,6 +167,66 @@ def make_filterbank(wl: Workload, nsamp_in: int, seed: Optional[int] = None,
     return X, truth
 
 
+def render_filterbanks(wl: Workload, nsamp_in: int, truths, seed: int, device: str = "cuda",
+                       pitch: Optional[int] = None, out=None):
+    """Many filterbanks at once: truths[b] (events of filterbank b) rendered over
+    fresh Gaussian noise into uint8 [B][nchan][pitch] (torch, on `device`).
+    Same sky model as make_filterbank; the noise comes from one torch
+    generator seeded with `seed` for the whole batch."""
+    import torch
+    pitch = nsamp_in if pitch is None else pitch
+    B, nc = len(truths), wl.nchan
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed) & 0x7FFFFFFFFFFFFFFF)
+    blk = torch.randn((B * nc, nsamp_in), generator=gen, device=device, dtype=torch.float32)
+    blk.mul_(wl.noise_sigma).add_(wl.noise_mean)
+    flat_idx, flat_val = [], []
+    rows = np.arange(nc)[:, None]
+    for b, tr in enumerate(truths):
+        for p in tr.pulses:
+            idx, val, ok = _pulse_windows(wl, p, 0, nc, nsamp_in)
+            r = np.broadcast_to(rows, idx.shape)
+            flat_idx.append(((b * nc + r[ok]) * nsamp_in + idx[ok]).astype(np.int64))
+            flat_val.append(val[ok].astype(np.float32))
+    if flat_idx:
+        blk.view(-1).index_add_(0, torch.from_numpy(np.concatenate(flat_idx)).to(device),
+                                torch.from_numpy(np.concatenate(flat_val)).to(device))
+    srow, sper, sph, samp = [], [], [], []
+    for b, tr in enumerate(truths):
+        for sn in tr.sines:
+            srow.append(b * nc + sn.chan)
+            sper.append(sn.period_s)
+            sph.append(sn.phase)
+            samp.append(sn.amp)
+    if srow:
+        t_s = torch.arange(nsamp_in, device=device, dtype=torch.float64) * wl.tsamp_s
+        per = torch.tensor(sper, device=device, dtype=torch.float64)[:, None]
+        ph = torch.tensor(sph, device=device, dtype=torch.float64)[:, None]
+        amp = torch.tensor(samp, device=device, dtype=torch.float64)[:, None]
+        wave = (amp * torch.sin(2 * math.pi * t_s[None, :] / per + ph)).to(torch.float32)
+        blk.index_add_(0, torch.tensor(srow, device=device, dtype=torch.int64), wave)
+        del wave
+    for b, tr in enumerate(truths):
+        for im in tr.impulses:
+            blk[b * nc:(b + 1) * nc, im.start:im.start + im.length] += im.amp
+    if out is None:
+        out = torch.zeros((B, nc, pitch), dtype=torch.uint8, device=device)
+    out[:, :, :nsamp_in] = blk.round_().clamp_(0, 255).to(torch.uint8).view(B, nc, nsamp_in)
+    del blk
+    return out
+
+
+def seeded_weights(seed: int, specs) -> dict:
+    """Initial weights, an input of training: specs is a list of
+    (name, shape, std); each entry is drawn N(0, std^2) in order from one
+    numpy PCG64 stream (std 0 gives zeros).  float32 arrays."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = {}
+    for name, shape, std in specs:
+        out[name] = (rng.normal(0.0, std, shape) if std > 0 else np.zeros(shape)).astype(np.float32)
+    return out
+
+
 def random_bytes(nchan: int, nsamp_in: int, seed: int, pitch: Optional[int] = None,
                  lo: int = 0, hi: int = 256) -> np.ndarray:
     """Uniform random bytes [nchan][pitch] (first nsamp_in valid, rest 0)."""
