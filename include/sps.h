@@ -409,6 +409,10 @@ sps_status sps_cnn_get_grads(sps_cnn net, float *host);
 /* The bfloat16 ReLU output of 3x3 layer `layer` (0..5) for the first n tiles
  * of the last forward pass, NHWC [n][h][w][cout] (synchronous). */
 sps_status sps_cnn_activations(sps_cnn net, int32_t layer, int32_t n, uint16_t *host);
+/* The bfloat16 signal back-propagated to the output of 3x3 layer `layer`
+ * (gradient of the loss w.r.t. its pre-activation, masked by a > 0) for the
+ * first n tiles of the last sps_cnn_loss_grad, NHWC (synchronous). */
+sps_status sps_cnn_signals(sps_cnn net, int32_t layer, int32_t n, uint16_t *host);
 
 /* Pools the S/N plane snr (device FP32 [ndm][pitch], first nout used) into
  * tiles (device uint16 [ndm/2][nout/8]); only full windows.  Asynchronous. */

@@ -852,6 +852,16 @@ sps_status sps_cnn_activations(sps_cnn c, int32_t layer, int32_t n, uint16_t *ho
   return SPS_OK;
 }
 
+sps_status sps_cnn_signals(sps_cnn c, int32_t layer, int32_t n, uint16_t *host) {
+  if (!c || !host || layer < 0 || layer >= kNumLayers || n < 1 || n > c->max_batch)
+    return sps::set_error(SPS_ERR_INVALID_ARG, "bad network, layer, count or output");
+  hipError_t e = hipDeviceSynchronize();
+  const size_t bytes = sizeof(uint16_t) * (size_t)npix_out(layer, n) * kLayers[layer].cout;
+  if (e == hipSuccess) e = hipMemcpy(host, c->dz[layer], bytes, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return cnn_dev_fail(e, "reading back-propagated signals");
+  return SPS_OK;
+}
+
 sps_status sps_cnn_pool_tiles(const float *snr, int64_t pitch, int32_t ndm, int64_t nout,
                               float scale, uint16_t *tiles, void *stream) {
   if (!snr || !tiles) return sps::set_error(SPS_ERR_INVALID_ARG, "NULL plane or tiles");

@@ -137,6 +137,7 @@ def library() -> ctypes.CDLL:
                   "sps_cnn_get_grads"):
             getattr(lib, f).argtypes = [P, P]
         lib.sps_cnn_activations.argtypes = [P, i32, i32, P]
+        lib.sps_cnn_signals.argtypes = [P, i32, i32, P]
         lib.sps_cnn_pool_tiles.argtypes = [P, i64, i32, i64, ctypes.c_float, P, P]
         lib.sps_cnn_forward.argtypes = [P, P, i32, P, P]
         lib.sps_cnn_loss_grad.argtypes = [P, P, P, i32, P, P]
@@ -147,7 +148,7 @@ def library() -> ctypes.CDLL:
                                        ctypes.POINTER(sps_cnn_candidate), i32,
                                        ctypes.POINTER(i32), P]
         for f in ("sps_cnn_create", "sps_cnn_destroy", "sps_cnn_set_params", "sps_cnn_get_params",
-                  "sps_cnn_set_grads", "sps_cnn_get_grads", "sps_cnn_activations",
+                  "sps_cnn_set_grads", "sps_cnn_get_grads", "sps_cnn_activations", "sps_cnn_signals",
                   "sps_cnn_pool_tiles", "sps_cnn_forward", "sps_cnn_loss_grad", "sps_cnn_adam",
                   "sps_cnn_train_step", "sps_cnn_detect"):
             getattr(lib, f).restype = ctypes.c_int
@@ -667,6 +668,15 @@ def sps_cnn_activations(net: Cnn, layer: int, n: int) -> np.ndarray:
     out = np.empty((n, size[0], size[1], CNN_LAYERS[layer][1]), np.uint16)
     _check(library().sps_cnn_activations(net.handle, int(layer), int(n), out.ctypes.data),
            "sps_cnn_activations")
+    return out
+
+
+def sps_cnn_signals(net: Cnn, layer: int, n: int) -> np.ndarray:
+    """bf16 bit patterns NHWC [n][h][w][cout] of the signal at 3x3 layer `layer`."""
+    size = 256 // 2 ** min(layer + 1, 5), 512 // 2 ** min(layer + 1, 5)
+    out = np.empty((n, size[0], size[1], CNN_LAYERS[layer][1]), np.uint16)
+    _check(library().sps_cnn_signals(net.handle, int(layer), int(n), out.ctypes.data),
+           "sps_cnn_signals")
     return out
 
 

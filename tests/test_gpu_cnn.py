@@ -85,31 +85,128 @@ def case(sps):
     return params, tb, y
 
 
-def test_forward_layers_and_head(sps, case):
+U = 2.0 ** -24  # binary32 unit roundoff
+
+
+def _nchw(bits):
+    return np.transpose(cnn.from_bf16_bits(bits), (0, 3, 1, 2))
+
+
+def _justified_relu(g, z, delta):
+    """g is bf16(max(z', 0)) for some z' within delta of the exact z
+    (rounding and ReLU are monotone, so the attainable values are exactly
+    those between the two ends)."""
+    lo = cnn.bf16(np.maximum(z - delta, 0.0))
+    hi = cnn.bf16(np.maximum(z + delta, 0.0))
+    return (g >= lo) & (g <= hi)
+
+
+def _justified_masked(g, d, delta, mask):
+    """g is bf16(d') for some d' within delta of d where mask, else exactly 0."""
+    lo, hi = cnn.bf16(d - delta), cnn.bf16(d + delta)
+    return np.where(mask, (g >= lo) & (g <= hi), g == 0)
+
+
+def test_forward_layer_local(sps, case):
+    # each layer's GPU output against the exact layer applied to the GPU's
+    # own input: every difference must be a bfloat16 rounding decision that
+    # the FP32 accumulation error (at most K u sum|w x| for K terms) can flip
+    params, tb, y = case
+    n = tb.shape[0]
+    with sps.sps_cnn_create(4) as net:
+        sps.sps_cnn_set_params(net, _flat(params))
+        head = torch.zeros((n, 3, 8, 16), dtype=torch.float32, device="cuda")
+        sps.sps_cnn_forward(net, _to_dev_tiles(tb), n, head)
+        torch.cuda.synchronize()
+        acts = [_nchw(sps.sps_cnn_activations(net, li, n)) for li in range(len(cnn.LAYERS))]
+        h = head.cpu().numpy().astype(np.float64)
+    prev = tb[:, None]
+    for li, (ci, co, stride) in enumerate(cnn.LAYERS):
+        w = cnn.bf16(params[f"w{li}"])
+        b = params[f"b{li}"].astype(np.float64)
+        z = cnn.conv3x3(prev, w, b, stride)
+        mag = cnn.conv3x3(np.abs(prev), np.abs(w), np.abs(b), stride)
+        g = acts[li]
+        assert g.shape == z.shape
+        ok = _justified_relu(g, z, 2 * (9 * ci + 1) * U * mag)
+        assert ok.all(), (li, int((~ok).sum()))
+        flips = np.mean(g != cnn.bf16(np.maximum(z, 0.0)))
+        assert flips <= 2e-3, (li, flips)
+        prev = g
+    wh, bh = params["wh"].astype(np.float64), params["bh"].astype(np.float64)
+    ref = np.einsum("kc,nchw->nkhw", wh, prev) + bh[None, :, None, None]
+    mag = np.einsum("kc,nchw->nkhw", np.abs(wh), np.abs(prev)) + np.abs(bh)[None, :, None, None]
+    assert np.all(np.abs(h - ref) <= 2 * 129 * U * mag + 1e-30)
+
+
+def test_forward_end_to_end(sps, case):
+    # from the tiles alone: flipped roundings propagate, so the bar is a
+    # bound on the drift of the head outputs
     params, tb, y = case
     n = tb.shape[0]
     head_o, acts_o = cnn.forward(params, tb)
     with sps.sps_cnn_create(4) as net:
         sps.sps_cnn_set_params(net, _flat(params))
-        T = _to_dev_tiles(tb)
         head = torch.zeros((n, 3, 8, 16), dtype=torch.float32, device="cuda")
-        sps.sps_cnn_forward(net, T, n, head)
+        sps.sps_cnn_forward(net, _to_dev_tiles(tb), n, head)
         torch.cuda.synchronize()
         for li in range(len(cnn.LAYERS)):
-            g = sps.sps_cnn_activations(net, li, n)
-            o = np.transpose(acts_o[li + 1], (0, 2, 3, 1))  # NCHW -> NHWC
-            ulps, gv = _bf_ulp_diff(g, o)
-            same = np.mean(gv == o)
-            # a rounding decision can differ only where the FP32 sum lies within
-            # its accumulation error of a bfloat16 rounding boundary
-            assert same >= 0.99, (li, same)
-            assert np.all((ulps <= 2.0) | (np.abs(gv - o) <= 1e-2 * np.abs(o).max())), li
+            g = _nchw(sps.sps_cnn_activations(net, li, n))
+            assert np.mean(g == acts_o[li + 1]) >= 0.95, li
         h = head.cpu().numpy().astype(np.float64)
-        err = np.abs(h - head_o)
-        assert err.max() <= 1e-2 * np.abs(head_o).max() + 1e-4, err.max()
+    assert np.abs(h - head_o).max() <= 1e-2 * np.abs(head_o).max()
 
 
-def test_loss_and_gradients(sps, case):
+def test_backward_layer_local(sps, case):
+    # gradients and back-propagated signals against the exact backward of
+    # each layer applied to the GPU's own activations and signals
+    params, tb, y = case
+    n = tb.shape[0]
+    with sps.sps_cnn_create(4) as net:
+        sps.sps_cnn_set_params(net, _flat(params))
+        T = _to_dev_tiles(tb)
+        Y = torch.from_numpy(y.astype(np.float32)).cuda()
+        loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+        sps.sps_cnn_loss_grad(net, T, Y, n, loss)
+        torch.cuda.synchronize()
+        acts = [_nchw(sps.sps_cnn_activations(net, li, n)) for li in range(len(cnn.LAYERS))]
+        sig = [_nchw(sps.sps_cnn_signals(net, li, n)) for li in range(len(cnn.LAYERS))]
+        grads = _unflat(sps.sps_cnn_get_grads(net), params)
+        L_g = float(loss.cpu()[0])
+    # head, loss and the signal entering the last layer
+    a6 = acts[-1]
+    wh, bh = params["wh"].astype(np.float64), params["bh"].astype(np.float64)
+    h = np.einsum("kc,nchw->nkhw", wh, a6) + bh[None, :, None, None]
+    # binary32 per-cell terms (expf/log1pf a few ulps each) summed over the cells
+    assert abs(L_g - cnn.loss(h, y)) <= 1e-4 * abs(cnn.loss(h, y))
+    gh = cnn.loss_grad_head(h, y)
+    dwh = np.einsum("nkhw,nchw->kc", gh, a6)
+    dwh_mag = np.einsum("nkhw,nchw->kc", np.abs(gh), np.abs(a6))
+    ncell = n * cnn.GRID_DM * cnn.GRID_T
+    # the GPU's own head values carry binary32 error into gh: 1e-5 relative
+    assert np.all(np.abs(grads["wh"] - dwh) <= (2 * ncell * U + 1e-5) * dwh_mag + 1e-30)
+    gmag = np.abs(gh).sum(axis=(0, 2, 3))
+    assert np.all(np.abs(grads["bh"] - gh.sum(axis=(0, 2, 3))) <= (2 * ncell * U + 1e-5) * gmag)
+    d = np.einsum("kc,nkhw->nchw", wh, gh)
+    dmag = np.einsum("kc,nkhw->nchw", np.abs(wh), np.abs(gh))
+    ok = _justified_masked(sig[5], d, (8 * U + 1e-5) * dmag, a6 > 0)
+    assert ok.all(), int((~ok).sum())
+    for li in range(len(cnn.LAYERS) - 1, -1, -1):
+        ci, co, stride = cnn.LAYERS[li]
+        x = tb[:, None] if li == 0 else acts[li - 1]
+        w = cnn.bf16(params[f"w{li}"])
+        dx, dw, db = cnn.conv3x3_backward(x, w, sig[li], stride)
+        mx, mw, mb = cnn.conv3x3_backward(np.abs(x), np.abs(w), np.abs(sig[li]), stride)
+        kw = sig[li].shape[0] * sig[li].shape[2] * sig[li].shape[3]
+        ew = np.abs(grads[f"w{li}"] - dw)
+        assert np.all(ew <= 2 * kw * U * mw + 1e-30), (li, float((ew / (mw + 1e-30)).max()))
+        assert np.all(np.abs(grads[f"b{li}"] - db) <= 2 * kw * U * mb + 1e-30), li
+        if li > 0:
+            ok = _justified_masked(sig[li - 1], dx, 2 * 9 * co * U * mx, acts[li - 1] > 0)
+            assert ok.all(), (li, int((~ok).sum()))
+
+
+def test_loss_and_gradients_end_to_end(sps, case):
     params, tb, y = case
     n = tb.shape[0]
     L_o, g_o = cnn.backward(params, tb, y)
