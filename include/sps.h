@@ -342,6 +342,8 @@ typedef struct {
   int64_t index;    /* chunk number within the run */
   double arrival_s; /* scheduled arrival */
   double start_s;   /* a worker took it */
+  double upload_s;  /* its samples were in the device ring */
+  double compute_s; /* it held the compute lock (kernels start) */
   double end_s;     /* candidates on the host */
   int32_t n_cand;   /* candidates found (true count) */
   int32_t status;   /* sps_status of the chunk */

@@ -145,8 +145,14 @@ sps_status grow_planes(sps_server s, int64_t elems, int64_t rows) {
 // [nchan][src_pitch].  Y_copy (optional, device [ndm][chunk]) receives the
 // dedispersed plane; out/cap/n_found as in sps_detect.  Synchronises the
 // worker's stream.
+// Wall-clock marks of one chunk's phases (seconds on the caller's clock).
+struct Marks {
+  std::chrono::steady_clock::time_point uploaded, locked;
+};
+
 sps_status process_chunk(sps_server s, Worker &w, int sid, const uint8_t *src, int64_t src_pitch,
-                         uint32_t *Y_copy, sps_candidate *out, int32_t cap, int32_t *n_found) {
+                         uint32_t *Y_copy, sps_candidate *out, int32_t cap, int32_t *n_found,
+                         Marks *marks = nullptr) {
   StreamState &st = s->streams[(size_t)sid];
   sps_plan plan = w.plans[(size_t)st.setup];
   hipStream_t hs = w.stream;
@@ -155,7 +161,9 @@ sps_status process_chunk(sps_server s, Worker &w, int sid, const uint8_t *src, i
                                   (size_t)st.chunk, (size_t)st.nchan, hipMemcpyHostToDevice, hs);
   if (e == hipSuccess) e = hipStreamSynchronize(hs);
   if (e != hipSuccess) return dev_fail(e, "chunk upload");
+  if (marks) marks->uploaded = std::chrono::steady_clock::now();
   std::lock_guard<std::mutex> lk(s->compute);
+  if (marks) marks->locked = std::chrono::steady_clock::now();
   sps_status r =
       sps_dedisperse(plan, st.ring, st.pitch, st.overlap + st.chunk, w.Y, st.chunk, 0, hs);
   if (r != SPS_OK) return r;
@@ -441,9 +449,14 @@ sps_status sps_server_run(sps_server s, const sps_feed *feeds, double run_s, dou
       const int64_t src_idx = (f.first + job.index) % f.nsrc;
       const uint8_t *src = f.host + (size_t)src_idx * (size_t)st.nchan * (size_t)f.src_pitch;
       int32_t nc = 0;
-      sps_status r = process_chunk(s, w, job.stream, src, f.src_pitch, nullptr, nullptr, 0, &nc);
+      Marks mk;
+      mk.uploaded = mk.locked = std::chrono::steady_clock::now();
+      sps_status r =
+          process_chunk(s, w, job.stream, src, f.src_pitch, nullptr, nullptr, 0, &nc, &mk);
       if (r == SPS_ERR_TRUNCATED) r = SPS_OK;  // only the count is kept
       const double end = now_s();
+      const double up = std::chrono::duration<double>(mk.uploaded - t0).count();
+      const double lk_s = std::chrono::duration<double>(mk.locked - t0).count();
       {
         std::lock_guard<std::mutex> lk(mu);
         StreamState &sm = s->streams[(size_t)job.stream];
@@ -453,7 +466,7 @@ sps_status sps_server_run(sps_server s, const sps_feed *feeds, double run_s, dou
           err = r;
           err_msg = sps_last_error();
         }
-        recs.push_back({job.stream, wi, job.index, job.t, start, end, nc, (int32_t)r});
+        recs.push_back({job.stream, wi, job.index, job.t, start, up, lk_s, end, nc, (int32_t)r});
       }
       cv.notify_all();
     }

@@ -234,6 +234,8 @@ def train(net, tiles, labels, epochs: int, batch: int, lr: float, stream=None,
                                    labels[s * batch:(s + 1) * batch], batch, lr_k,
                                    losses[k:k + 1], stream=stream)
             k += 1
+    if stream is not None:
+        stream.synchronize()
     return losses.cpu().numpy()
 
 
@@ -247,6 +249,8 @@ def cnn_scores(net, tiles, batch: int, stream=None):
     for b0 in range(0, n, batch):
         nb = min(batch, n - b0)
         sps.sps_cnn_forward(net, tiles[b0:b0 + nb], nb, out[b0:b0 + nb], stream=stream)
+    if stream is not None:
+        stream.synchronize()
     return out.cpu().numpy()
 
 

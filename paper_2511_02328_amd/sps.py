@@ -72,6 +72,7 @@ class sps_feed(ctypes.Structure):
 class sps_chunk_record(ctypes.Structure):
     _fields_ = [("stream", ctypes.c_int32), ("worker", ctypes.c_int32), ("index", ctypes.c_int64),
                 ("arrival_s", ctypes.c_double), ("start_s", ctypes.c_double),
+                ("upload_s", ctypes.c_double), ("compute_s", ctypes.c_double),
                 ("end_s", ctypes.c_double), ("n_cand", ctypes.c_int32), ("status", ctypes.c_int32)]
 
 
@@ -488,6 +489,7 @@ class Server:
 
 RECORD_DTYPE = np.dtype([("stream", np.int32), ("worker", np.int32), ("index", np.int64),
                          ("arrival_s", np.float64), ("start_s", np.float64),
+                         ("upload_s", np.float64), ("compute_s", np.float64),
                          ("end_s", np.float64), ("n_cand", np.int32), ("status", np.int32)])
 
 

@@ -151,6 +151,8 @@ def test_timed_run_then_continue(sps):
             assert len(r) == nexp and list(r["index"]) == list(range(nexp))
             assert np.allclose(r["arrival_s"], phase + (np.arange(nexp) + 1) * T)
             assert np.all(r["start_s"] >= r["arrival_s"]) and np.all(r["end_s"] > r["start_s"])
+            assert np.all(r["upload_s"] >= r["start_s"]) and np.all(r["compute_s"] >= r["upload_s"])
+            assert np.all(r["end_s"] >= r["compute_s"])
             assert np.all(np.diff(r["start_s"]) > 0)
         # continue: the run searched chunks first, first+1, ... of the sources
         for sid, wl, L, Xs in ((ia, wa, La, srcs[0]), (ib, wb, Lb, srcs[1])):
