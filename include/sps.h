@@ -288,13 +288,15 @@ sps_status sps_tiling_describe(int32_t index, int32_t *m, int32_t *dpw, int32_t 
 /* ---- Streaming: many real-time filterbank streams on one GPU ---- */
 
 /* A server searches admitted streams chunk by chunk.  Each stream keeps a
- * device ring of nchan x (D_max + chunk_len) bytes: the last D_max samples of
- * the previous chunk (the dispersion overlap of the time blocking in
- * Sec. 2.3), then the new chunk, so chunk k's outputs are the dedispersed
- * series at absolute samples [k chunk_len - D_max, (k+1) chunk_len - D_max)
- * of the stream (the overlap is zero before chunk 0).  Worker w owns a HIP
- * stream, one plan per observing set-up and output planes sized for the
- * largest stream; streams of one set-up share its plans. */
+ * device ring of nchan x (O + chunk_len) bytes: the last O samples of the
+ * previous chunk (the dispersion overlap of the time blocking in Sec. 2.3;
+ * O = D_max rounded up to a multiple of 16), then the new chunk, so chunk k's
+ * outputs are the dedispersed series at absolute samples
+ * [k chunk_len - O, (k+1) chunk_len - O) of the stream (the overlap is zero
+ * before chunk 0).  Worker w owns a HIP stream, a staging buffer for one
+ * chunk, one plan per observing set-up and output planes sized for the
+ * largest stream; streams of one set-up share its plans.  One chunk's
+ * kernels run at a time; uploads of other chunks overlap them. */
 typedef struct sps_server_s *sps_server;
 
 /* hbm_budget: device bytes the server may hold (rings, plans, planes);
@@ -312,13 +314,13 @@ sps_status sps_server_add_stream(sps_server server, const sps_obs_desc *desc,
                                  int64_t chunk_len, int32_t *stream_id);
 /* Device bytes accounted so far and the budget. */
 sps_status sps_server_memory(sps_server server, int64_t *used, int64_t *budget);
-/* Chunk length, overlap D_max (samples) and chunk duration (s) of a stream. */
+/* Chunk length, overlap O (samples) and chunk duration (s) of a stream. */
 sps_status sps_server_stream_info(sps_server server, int32_t stream_id, int64_t *chunk_len,
                                   int64_t *overlap, double *duration_s);
 
 /* Searches the stream's next chunk now, on worker 0, and waits for it.
- * host: [nchan][src_pitch] bytes (pinned memory for speed), first chunk_len
- * of each row used.  Y_copy (optional): device [ndm][chunk_len] that receives
+ * host: [nchan][src_pitch] bytes, first chunk_len of each row used (pinned
+ * memory with src_pitch == chunk_len takes the fast linear upload).  Y_copy (optional): device [ndm][chunk_len] that receives
  * the dedispersed plane.  out/cap/n_found and TRUNCATED as in sps_detect.
  * Must not overlap sps_server_run. */
 sps_status sps_server_push(sps_server server, int32_t stream_id, const uint8_t *host,

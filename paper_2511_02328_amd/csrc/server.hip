@@ -1,14 +1,16 @@
 // server.hip -- native streaming runtime: many real-time filterbank streams
 // searched on one GPU.
 //
-// Each admitted stream keeps a device ring of nchan x (D_max + chunk)
-// samples: the last D_max samples of the previous chunk (the dispersion
-// overlap of the time blocking in Sec. 2.3, L1 = L + R_max, here with the
-// full channel delay D_max) followed by the new chunk.  Consecutive chunks
-// therefore dedisperse into one gap-free series without the host resending
-// data: chunk k's outputs are the dedispersed series at absolute samples
-// [k L - D_max, (k + 1) L - D_max), the ring's overlap being zero before the
-// first chunk.  Admission is by device-memory budget: a stream is refused
+// Each admitted stream keeps a device ring of nchan x (O + chunk) samples:
+// the last O samples of the previous chunk (the dispersion overlap of the
+// time blocking in Sec. 2.3, L1 = L + R_max, here with the full channel delay:
+// O = D_max rounded up to a multiple of 16) followed by the new chunk.
+// Consecutive chunks therefore dedisperse into one gap-free series without
+// the host resending data: chunk k's outputs are the dedispersed series at
+// absolute samples [k L - O, (k + 1) L - O), the ring's overlap being zero
+// before the first chunk.  A chunk travels host -> contiguous staging buffer
+// (one linear DMA copy) -> ring row by row (a copy kernel); the overlap moves
+// to the front of the ring with the same kernel.  Admission is by device-memory budget: a stream is refused
 // when its ring, the plans of a new observing set-up and any growth of the
 // shared per-worker planes do not fit.
 //
@@ -17,9 +19,9 @@
 // phase_i + (k + 1) T_i / compression, T_i the chunk's duration.  Worker
 // threads take released chunks in arrival order (a stream's chunks strictly
 // in sequence), each on its own HIP stream with its own output planes and
-// plans: host-to-device copy behind the overlap, then, holding the server's
-// compute lock, dedispersion, statistics + boxcar S/N, overlap moved to the
-// front of the ring and detection.  A chunk's latency is its completion time
+// plans: host-to-device copy into its staging buffer, then, holding the
+// server's compute lock, staging -> ring, dedispersion, statistics + boxcar
+// S/N, overlap moved to the front of the ring and detection.  A chunk's latency is its completion time
 // minus its arrival time.
 #include <stdio.h>
 #include <string.h>
@@ -61,6 +63,8 @@ struct StreamState {
 
 struct Worker {
   hipStream_t stream = nullptr;
+  uint8_t *staging = nullptr;   // contiguous [nchan][chunk] upload target
+  int64_t staging_cap = 0;      // bytes
   uint32_t *Y = nullptr;
   float *snr = nullptr;
   uint8_t *best = nullptr;
@@ -97,6 +101,40 @@ void free_planes(Worker &w) {
   w.stats_cap = 0;
 }
 
+// dst[c][dst_off + i] = src[c][src_off + i] for i < len, c < nchan.  Each
+// thread moves 16 bytes: one vector load and store when every row start is
+// 16-byte aligned (vec), byte by byte otherwise.  Rows may overlap between
+// src and dst only if dst_off + len <= src_off or src_off + len <= dst_off
+// within a row (the caller splits longer moves).
+__global__ __launch_bounds__(256) void copy_rows_kernel(const uint8_t *__restrict__ src,
+                                                        int64_t src_pitch, int64_t src_off,
+                                                        uint8_t *__restrict__ dst,
+                                                        int64_t dst_pitch, int64_t dst_off,
+                                                        int64_t len, int vec) {
+  const int64_t i = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 16;
+  if (i >= len) return;
+  const uint8_t *s = src + (int64_t)blockIdx.y * src_pitch + src_off + i;
+  uint8_t *d = dst + (int64_t)blockIdx.y * dst_pitch + dst_off + i;
+  if (vec && i + 16 <= len) {
+    *reinterpret_cast<uint4 *>(d) = *reinterpret_cast<const uint4 *>(s);
+  } else {
+    const int64_t n = len - i < 16 ? len - i : 16;
+    for (int64_t k = 0; k < n; ++k) d[k] = s[k];
+  }
+}
+
+hipError_t copy_rows(const uint8_t *src, int64_t src_pitch, int64_t src_off, uint8_t *dst,
+                     int64_t dst_pitch, int64_t dst_off, int64_t len, int nchan, hipStream_t s) {
+  if (len <= 0) return hipSuccess;
+  const int64_t gx = (len + 256 * 16 - 1) / (256 * 16);
+  if (gx > 0x7FFFFFFF || nchan > 65535) return hipErrorInvalidValue;
+  const int vec = ((((uintptr_t)src + (uint64_t)src_off) | ((uintptr_t)dst + (uint64_t)dst_off) |
+                    (uint64_t)src_pitch | (uint64_t)dst_pitch) & 15u) == 0;
+  hipLaunchKernelGGL(copy_rows_kernel, dim3((unsigned)gx, (unsigned)nchan), dim3(256), 0, s, src,
+                     src_pitch, src_off, dst, dst_pitch, dst_off, len, vec);
+  return hipGetLastError();
+}
+
 sps_status dev_fail(hipError_t e, const char *what) {
   std::string m = std::string(what) + ": " + hipGetErrorString(e);
   return sps::set_error(SPS_ERR_DEVICE, m.c_str());
@@ -119,6 +157,22 @@ struct sps_server_s {
 };
 
 namespace {
+
+// Grows every worker's staging buffer to hold bytes.
+sps_status grow_staging(sps_server s, int64_t bytes) {
+  for (Worker &w : s->workers) {
+    if (w.staging_cap >= bytes) continue;
+    if (w.staging) (void)hipFree(w.staging);
+    w.staging = nullptr;
+    w.staging_cap = 0;
+    if (hipMalloc(&w.staging, (size_t)bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return sps::set_error(SPS_ERR_NOMEM, "device allocation of a staging buffer failed");
+    }
+    w.staging_cap = bytes;
+  }
+  return SPS_OK;
+}
 
 // Grows every worker's planes to hold elems samples and rows statistics.
 sps_status grow_planes(sps_server s, int64_t elems, int64_t rows) {
@@ -157,13 +211,22 @@ sps_status process_chunk(sps_server s, Worker &w, int sid, const uint8_t *src, i
   sps_plan plan = w.plans[(size_t)st.setup];
   hipStream_t hs = w.stream;
   *n_found = 0;
-  hipError_t e = hipMemcpy2DAsync(st.ring + st.overlap, (size_t)st.pitch, src, (size_t)src_pitch,
-                                  (size_t)st.chunk, (size_t)st.nchan, hipMemcpyHostToDevice, hs);
+  const int64_t bytes = st.chunk * (int64_t)st.nchan;
+  if (bytes > w.staging_cap) return sps::set_error(SPS_ERR_RANGE, "chunk exceeds the staging buffer");
+  // Upload to the contiguous staging buffer: one linear copy (a DMA engine,
+  // no compute units) when the host rows are back to back.
+  hipError_t e = src_pitch == st.chunk
+                     ? hipMemcpyAsync(w.staging, src, (size_t)bytes, hipMemcpyHostToDevice, hs)
+                     : hipMemcpy2DAsync(w.staging, (size_t)st.chunk, src, (size_t)src_pitch,
+                                        (size_t)st.chunk, (size_t)st.nchan,
+                                        hipMemcpyHostToDevice, hs);
   if (e == hipSuccess) e = hipStreamSynchronize(hs);
   if (e != hipSuccess) return dev_fail(e, "chunk upload");
   if (marks) marks->uploaded = std::chrono::steady_clock::now();
   std::lock_guard<std::mutex> lk(s->compute);
   if (marks) marks->locked = std::chrono::steady_clock::now();
+  e = copy_rows(w.staging, st.chunk, 0, st.ring, st.pitch, st.overlap, st.chunk, st.nchan, hs);
+  if (e != hipSuccess) return dev_fail(e, "ring fill");
   sps_status r =
       sps_dedisperse(plan, st.ring, st.pitch, st.overlap + st.chunk, w.Y, st.chunk, 0, hs);
   if (r != SPS_OK) return r;
@@ -181,9 +244,7 @@ sps_status process_chunk(sps_server s, Worker &w, int sid, const uint8_t *src, i
   // later piece overwrites it.
   for (int64_t off = 0; off < st.overlap; off += st.chunk) {
     const int64_t len = std::min(st.chunk, st.overlap - off);
-    e = hipMemcpy2DAsync(st.ring + off, (size_t)st.pitch, st.ring + st.chunk + off,
-                         (size_t)st.pitch, (size_t)len, (size_t)st.nchan, hipMemcpyDeviceToDevice,
-                         hs);
+    e = copy_rows(st.ring, st.pitch, st.chunk + off, st.ring, st.pitch, off, len, st.nchan, hs);
     if (e != hipSuccess) return dev_fail(e, "overlap move");
   }
   return sps_detect(plan, w.snr, w.best, st.chunk, st.widths.data(), (int32_t)st.widths.size(),
@@ -226,6 +287,7 @@ sps_status sps_server_destroy(sps_server s) {
   for (Worker &w : s->workers) {
     for (sps_plan p : w.plans) sps_plan_destroy(p);
     free_planes(w);
+    if (w.staging) (void)hipFree(w.staging);
     if (w.stream) (void)hipStreamDestroy(w.stream);
   }
   for (StreamState &st : s->streams)
@@ -281,13 +343,17 @@ sps_status sps_server_add_stream(sps_server s, const sps_obs_desc *desc, const i
   } else {
     dmax = s->setup_delay[(size_t)setup];
   }
-  const int64_t pitch = (dmax + chunk_len + 255) / 256 * 256;
+  // The overlap keeps D_max samples rounded up to 16, so that the chunk's
+  // region of every ring row starts 16-byte aligned.
+  const int64_t overlap = (dmax + 15) / 16 * 16;
+  const int64_t pitch = (overlap + chunk_len + 255) / 256 * 256;
   const int64_t ring = pitch * desc->nchan;
   const int64_t elems = (int64_t)desc->ndm * chunk_len;
+  const int64_t stage = chunk_len * (int64_t)desc->nchan;
   int64_t grow = 0;
   for (const Worker &w : s->workers)
     grow += plane_bytes(std::max(w.cap, elems), std::max<int64_t>(w.stats_cap, desc->ndm)) -
-            plane_bytes(w.cap, w.stats_cap);
+            plane_bytes(w.cap, w.stats_cap) + std::max<int64_t>(0, stage - w.staging_cap);
   const int64_t plans = new_setup ? (int64_t)s->workers.size() *
                                         plan_bytes(desc->ndm, desc->nchan, chunk_len, *det)
                                   : 0;
@@ -300,6 +366,7 @@ sps_status sps_server_add_stream(sps_server s, const sps_obs_desc *desc, const i
     return sps::set_error(SPS_ERR_NOMEM, m);
   }
   sps_status r = grow_planes(s, elems, desc->ndm);
+  if (r == SPS_OK) r = grow_staging(s, stage);
   if (r != SPS_OK) {
     drop();
     return r;
@@ -324,7 +391,7 @@ sps_status sps_server_add_stream(sps_server s, const sps_obs_desc *desc, const i
   st.nchan = desc->nchan;
   st.ndm = desc->ndm;
   st.chunk = chunk_len;
-  st.overlap = dmax;
+  st.overlap = overlap;
   st.pitch = pitch;
   st.widths.assign(widths, widths + nw);
   st.det = *det;

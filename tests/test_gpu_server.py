@@ -46,13 +46,13 @@ def _series(wl, nchunks, chunk):
     return X
 
 
-def _oracle_chunk(wl, Xs, dmax, k, chunk):
-    """Oracle search of chunk k: samples [k chunk - dmax, (k+1) chunk) of the series,
-    zeros before its start."""
+def _oracle_chunk(wl, Xs, overlap, k, chunk):
+    """Oracle search of chunk k: samples [k chunk - overlap, (k+1) chunk) of the
+    series, zeros before its start; the overlap is D_max rounded up to 16."""
     D = oracle.delays(wl.freqs_mhz(), wl.fref_mhz, wl.tsamp_s, wl.dms())
-    assert int(D.max()) == dmax
-    lo = k * chunk - dmax
-    win = np.zeros((wl.nchan, dmax + chunk), np.uint8)
+    assert overlap == (int(D.max()) + 15) // 16 * 16
+    lo = k * chunk - overlap
+    win = np.zeros((wl.nchan, overlap + chunk), np.uint8)
     a = max(lo, 0)
     win[:, a - lo:] = Xs[:, a:(k + 1) * chunk]
     return oracle.pipeline(win, D, chunk, wl.widths)
