@@ -3,10 +3,10 @@ made by the search itself, the training loop and the judgement against the
 plain boxcar search.
 
 Tiles come from the single-beam set-up (256 channels, 98.304 us, 512 trial
-DMs 0-1000, 4096 output samples): seeded synthetic filterbanks, each with
-persistent narrow-band sinusoids, for half of them broadband impulses, and
-for the positive half one dispersed pulse whose amplitude aims at a boxcar
-S/N drawn from 5-50.  The library dedisperses them, forms the S/N planes,
+DMs 0-1000, 4096 output samples): seeded synthetic filterbanks, half of them
+with persistent narrow-band sinusoids, half (independently) with broadband
+impulses, and for the positive half one dispersed pulse whose amplitude aims
+at a boxcar S/N drawn from 5-50.  The library dedisperses them, forms the S/N planes,
 runs the boxcar search (the judge) and pools the planes into bfloat16 tiles;
 the labels are the injected pulses' positions.  Python only draws the
 events, marshals buffers and keeps the books.
@@ -39,8 +39,15 @@ class TileSpec:
     snr_range: tuple = (5.0, 50.0)
     fwhm_range_s: tuple = (0.5e-3, 10e-3)     # log-uniform
     dm_range: tuple = (50.0, 950.0)
+    sine_prob: float = 0.5
     impulse_prob: float = 0.5
     pos_frac: float = 0.5
+
+
+# A detection matches an injected pulse when it lies within MATCH_DM trials
+# and within MATCH_T + 3 FWHM samples of it (the same rule for both searches).
+MATCH_DM = 16
+MATCH_T = 64
 
 
 def _boxcar_gain(sigma: float, widths) -> float:
@@ -60,13 +67,13 @@ def _boxcar_gain(sigma: float, widths) -> float:
 
 def draw_truth(rng: np.random.Generator, wl: Workload, nsamp_in: int, positive: bool,
                spec: TileSpec):
-    """Events of one tile (numpy PCG64): sinusoids on 5% of channels, impulses
-    with probability impulse_prob, and for a positive tile one pulse.
-    Returns (Truth, pulse parameters or None)."""
+    """Events of one tile (numpy PCG64): with probability sine_prob sinusoids
+    on 5% of channels, with probability impulse_prob broadband impulses, and
+    for a positive tile one pulse.  Returns (Truth, pulse parameters or None)."""
     sig = wl.noise_sigma
     rm = wl.rfi
     sines = []
-    n_rfi = int(round(rm.chan_fraction * wl.nchan))
+    n_rfi = int(round(rm.chan_fraction * wl.nchan)) if rng.random() < spec.sine_prob else 0
     for c in np.sort(rng.choice(wl.nchan, size=n_rfi, replace=False)):
         per = math.exp(rng.uniform(math.log(rm.sine_period_range_s[0]),
                                    math.log(rm.sine_period_range_s[1])))
@@ -139,7 +146,7 @@ class TileFactory:
                             device=self.device)
         labels = np.zeros((n, 3, 8, 16), np.float32)
         meta = {k: np.full(n, np.nan) for k in ("dm", "toa_s", "fwhm_s", "target_snr",
-                                                "pulse_snr", "row", "col")}
+                                                "pulse_snr", "row", "col", "d_star", "t_star")}
         meta["positive"] = np.zeros(n, bool)
         meta["boxcar_any"] = np.zeros(n, bool)
         meta["boxcar_hit"] = np.zeros(n, bool)
@@ -177,7 +184,7 @@ class TileFactory:
                 row, col = d_star / POOL[0], t_star / POOL[1]
                 meta["positive"][j] = True
                 for k, v in (("dm", dm), ("toa_s", toa), ("fwhm_s", fw), ("target_snr", target),
-                             ("row", row), ("col", col)):
+                             ("row", row), ("col", col), ("d_star", d_star), ("t_star", t_star)):
                     meta[k][j] = v
                 gy, gx = int(row // CELL[0]), int(col // CELL[1])
                 labels[j, 0, gy, gx] = 1.0
@@ -190,8 +197,9 @@ class TileFactory:
                 t1 = min(wl.nout, int(t_star + 3 * fws) + 8)
                 with torch.cuda.stream(self.stream):
                     meta["pulse_snr"][j] = float(self.snr[i, d0:d1, t0:t1].max().cpu())
-                near = (np.abs(cands["dm_idx"] - d_star) <= 12) & (cands["t_idx"] >= t0) & \
-                       (cands["t_idx"] < t1)
+                tol_t = MATCH_T + 3 * fws
+                near = (np.abs(cands["dm_idx"] - d_star) <= MATCH_DM) & \
+                       (np.abs(cands["t_idx"] - t_star) <= tol_t)
                 meta["boxcar_hit"][j] = bool(near.any())
         self.stream.synchronize()
         return tiles, torch.from_numpy(labels).to(self.device), meta
@@ -257,18 +265,25 @@ def cnn_scores(net, tiles, batch: int, stream=None):
 def judge(head: np.ndarray, meta: dict, threshold: float, snr_min: float = 8.0) -> dict:
     """Recall on positive tiles whose injected pulse reaches snr_min in the
     boxcar plane, and false-alarm rate on pulse-free tiles, for the network
-    (a cell at or above the probability threshold within one cell of the
-    pulse; any such cell) and for the boxcar search (a detection near the
-    pulse; any detection)."""
+    and for the boxcar search.  A network detection is a cell at or above
+    the probability threshold, placed where its offset heads put it; it
+    matches the pulse under the same rule as a boxcar candidate (within
+    MATCH_DM trials and MATCH_T + 3 FWHM samples).  A false alarm is any
+    detection on a pulse-free tile."""
     logit = math.log(threshold / (1 - threshold))
-    obj = head[:, 0]
-    fire = obj >= logit
+    fire = head[:, 0] >= logit
     pos = meta["positive"]
     strong = pos & (meta["pulse_snr"] >= snr_min)
+    gy = np.arange(head.shape[2])[:, None]
+    gx = np.arange(head.shape[3])[None, :]
     hit = np.zeros(len(pos), bool)
     for j in np.flatnonzero(pos):
-        gy, gx = int(meta["row"][j] // CELL[0]), int(meta["col"][j] // CELL[1])
-        hit[j] = fire[j, max(0, gy - 1):gy + 2, max(0, gx - 1):gx + 2].any()
+        d_pred = (gy + head[j, 1]) * CELL[0] * POOL[0]
+        t_pred = (gx + head[j, 2]) * CELL[1] * POOL[1]
+        fws = meta["fwhm_s"][j] / TILE_WORKLOAD.tsamp_s
+        ok = fire[j] & (np.abs(d_pred - meta["d_star"][j]) <= MATCH_DM) & \
+             (np.abs(t_pred - meta["t_star"][j]) <= MATCH_T + 3 * fws)
+        hit[j] = bool(ok.any())
     neg = ~pos
     return {
         "threshold": threshold,
@@ -278,4 +293,6 @@ def judge(head: np.ndarray, meta: dict, threshold: float, snr_min: float = 8.0) 
         "cnn_false_alarm_rate": float(fire[neg].any(axis=(1, 2)).mean()) if neg.any() else None,
         "boxcar_false_alarm_rate": float(meta["boxcar_any"][neg].mean()) if neg.any() else None,
         "cnn_recall_below_min": float(hit[pos & ~strong].mean()) if (pos & ~strong).any() else None,
+        "boxcar_recall_below_min": (float(meta["boxcar_hit"][pos & ~strong].mean())
+                                    if (pos & ~strong).any() else None),
     }

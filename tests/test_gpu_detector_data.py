@@ -41,7 +41,8 @@ def test_tiles_labels_and_search(factory):
         assert int(meta["row"][j] // 32) == gy and int(meta["col"][j] // 32) == gx
         assert 0 <= lab[j, 1, gy, gx] < 1 and 0 <= lab[j, 2, gy, gx] < 1
         r, c = int(meta["row"][j]), int(meta["col"][j])
-        if meta["pulse_snr"][j] >= 10:
+        assert abs(meta["d_star"][j] - 2 * meta["row"][j]) < 1e-9
+        if meta["pulse_snr"][j] >= 15:
             # the tile is bright near the pulse (S/N / 8 after pooling)
             win = tb[j, max(0, r - 4):r + 5, max(0, c - 12):c + 5]
             assert win.max() >= 0.8 * meta["pulse_snr"][j] / 8, (j, win.max(), meta["pulse_snr"][j])
