@@ -383,8 +383,9 @@ sps_status sps_server_run(sps_server server, const sps_feed *feeds, double run_s
  * weights [3][128] and biases [3].
  *
  * Loss (mean over tiles): per cell, binary cross-entropy of the objectness
- * logit against the label (positive cells weighted 32), averaged over the
- * 128 cells, plus the squared errors of both offsets at positive cells.
+ * logit against the label (positive cells weighted pos_weight, default 32),
+ * averaged over the 128 cells, plus lambda_box (default 1) times the squared
+ * errors of both offsets at positive cells.
  * Labels: FP32 [n][3][8][16]: objectness (0/1), row offset, column offset.
  *
  * A network may be used from one stream at a time. */
@@ -408,6 +409,8 @@ sps_status sps_cnn_destroy(sps_cnn net);
  * resets the Adam state and step count. */
 sps_status sps_cnn_set_params(sps_cnn net, const float *host);
 sps_status sps_cnn_get_params(sps_cnn net, float *host);
+/* Loss weights for the following loss_grad / train_step calls. */
+sps_status sps_cnn_set_loss_weights(sps_cnn net, float pos_weight, float lambda_box);
 sps_status sps_cnn_set_grads(sps_cnn net, const float *host);
 sps_status sps_cnn_get_grads(sps_cnn net, float *host);
 /* The bfloat16 ReLU output of 3x3 layer `layer` (0..5) for the first n tiles

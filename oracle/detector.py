@@ -161,26 +161,28 @@ def labels_for(n: int, pulses) -> np.ndarray:
     return y
 
 
-def loss(head: np.ndarray, y: np.ndarray) -> float:
+def loss(head: np.ndarray, y: np.ndarray, pos_weight: float = POS_WEIGHT,
+         lambda_box: float = LAMBDA_BOX) -> float:
     o = head[:, 0]
     pos = y[:, 0]
-    wgt = np.where(pos > 0, POS_WEIGHT, 1.0)
+    wgt = np.where(pos > 0, pos_weight, 1.0)
     bce = np.maximum(o, 0.0) - pos * o + np.log1p(np.exp(-np.abs(o)))
     ncell = GRID_DM * GRID_T
     box = ((head[:, 1] - y[:, 1]) ** 2 + (head[:, 2] - y[:, 2]) ** 2) * pos
-    per_tile = (wgt * bce).sum(axis=(1, 2)) / ncell + LAMBDA_BOX * box.sum(axis=(1, 2))
+    per_tile = (wgt * bce).sum(axis=(1, 2)) / ncell + lambda_box * box.sum(axis=(1, 2))
     return float(per_tile.mean())
 
 
-def loss_grad_head(head: np.ndarray, y: np.ndarray) -> np.ndarray:
+def loss_grad_head(head: np.ndarray, y: np.ndarray, pos_weight: float = POS_WEIGHT,
+                   lambda_box: float = LAMBDA_BOX) -> np.ndarray:
     n = head.shape[0]
     o = head[:, 0]
     pos = y[:, 0]
-    wgt = np.where(pos > 0, POS_WEIGHT, 1.0)
+    wgt = np.where(pos > 0, pos_weight, 1.0)
     g = np.zeros_like(head)
     g[:, 0] = wgt * (1.0 / (1.0 + np.exp(-o)) - pos) / (GRID_DM * GRID_T) / n
-    g[:, 1] = 2.0 * LAMBDA_BOX * (head[:, 1] - y[:, 1]) * pos / n
-    g[:, 2] = 2.0 * LAMBDA_BOX * (head[:, 2] - y[:, 2]) * pos / n
+    g[:, 1] = 2.0 * lambda_box * (head[:, 1] - y[:, 1]) * pos / n
+    g[:, 2] = 2.0 * lambda_box * (head[:, 2] - y[:, 2]) * pos / n
     return g
 
 

@@ -8,8 +8,9 @@
 // channels 1->16->32->64->128->128->128), each with bias and ReLU, and a
 // 1x1 head giving, per cell of the final 8 x 16 grid, an objectness logit and
 // the pulse's DM and time offsets inside the cell.  Loss: per cell binary
-// cross-entropy of the objectness (positives weighted 32) averaged over the
-// cells, plus the squared offset errors at positive cells; mean over tiles.
+// cross-entropy of the objectness (positives weighted, 32 by default)
+// averaged over the cells, plus the squared offset errors at positive cells
+// (weight 1 by default); mean over tiles.
 // Optimiser: Adam with bias correction on FP32 master weights.
 //
 // Precision: 3x3 weights are used as bfloat16, activations are stored as
@@ -45,7 +46,7 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kTileDm = 256, kTileT = 512, kPoolDm = 2, kPoolT = 8;
 constexpr int kGridDm = 8, kGridT = 16, kCells = kGridDm * kGridT, kHead = 3;
-constexpr float kPosWeight = 32.0f, kLambdaBox = 1.0f;
+constexpr float kPosWeight = 32.0f, kLambdaBox = 1.0f;  // default loss weights
 constexpr int kNumLayers = 6;
 
 struct Layer {
@@ -201,7 +202,7 @@ __global__ __launch_bounds__(128) void head_loss_kernel(
     const uint16_t *__restrict__ a6, const float *__restrict__ wh, const float *__restrict__ bh,
     const float *__restrict__ labels, int64_t ncell, float inv_n, float *__restrict__ head,
     uint16_t *__restrict__ dz6, float *__restrict__ part_wh, float *__restrict__ part_bh,
-    float *__restrict__ part_loss, int train) {
+    float *__restrict__ part_loss, int train, float pos_weight, float lambda_box) {
   __shared__ float w_s[kHead][kFeat];
   __shared__ float g_s[128][kHead];
   __shared__ uint16_t a_s[128][kFeat + 2];
@@ -238,14 +239,14 @@ __global__ __launch_bounds__(128) void head_loss_kernel(
       const float y1 = labels[(tile * kHead + 1) * kCells + cidx];
       const float y2 = labels[(tile * kHead + 2) * kCells + cidx];
       const float o = h[0];
-      const float wgt = y0 > 0.f ? kPosWeight : 1.0f;
+      const float wgt = y0 > 0.f ? pos_weight : 1.0f;
       const float bce = fmaxf(o, 0.f) - y0 * o + log1pf(expf(-fabsf(o)));
       const float e1 = h[1] - y1, e2 = h[2] - y2;
-      lc = (wgt * bce / (float)kCells + kLambdaBox * y0 * (e1 * e1 + e2 * e2)) * inv_n;
+      lc = (wgt * bce / (float)kCells + lambda_box * y0 * (e1 * e1 + e2 * e2)) * inv_n;
       const float sig = 1.0f / (1.0f + expf(-o));
       gk[0] = wgt * (sig - y0) / (float)kCells * inv_n;
-      gk[1] = 2.0f * kLambdaBox * e1 * y0 * inv_n;
-      gk[2] = 2.0f * kLambdaBox * e2 * y0 * inv_n;
+      gk[1] = 2.0f * lambda_box * e1 * y0 * inv_n;
+      gk[2] = 2.0f * lambda_box * e2 * y0 * inv_n;
     }
   }
   if (!train) return;
@@ -600,6 +601,7 @@ struct sps_cnn_s {
   float *head_part = nullptr; // per head block: [3][128] + [3] + [1]
   float *loss = nullptr;      // device scalar of the last loss_grad
   float *head = nullptr;      // head outputs of the last forward
+  float pos_weight = kPosWeight, lambda_box = kLambdaBox;
   int64_t partial_cap = 0, bpart_cap = 0;
 };
 
@@ -671,7 +673,8 @@ sps_status run_head(sps_cnn c, const float *labels, int32_t n, bool train, hipSt
   const int64_t hoff = head_param_offset();
   hipLaunchKernelGGL(head_loss_kernel, dim3((unsigned)nblk), dim3(128), 0, s, c->act[5],
                      c->params + hoff, c->params + hoff + kHead * kFeat, labels, ncell,
-                     1.0f / (float)n, c->head, c->dz[5], part_wh, part_bh, part_loss, train ? 1 : 0);
+                     1.0f / (float)n, c->head, c->dz[5], part_wh, part_bh, part_loss, train ? 1 : 0,
+                     c->pos_weight, c->lambda_box);
   if (train) {
     hipLaunchKernelGGL(reduce_rows_kernel, dim3((kHead * kFeat + 255) / 256), dim3(256), 0, s,
                        part_wh, nblk, kHead * kFeat, c->grads + hoff);
@@ -816,6 +819,15 @@ sps_status sps_cnn_set_params(sps_cnn c, const float *host) {
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) return cnn_dev_fail(e, "setting parameters");
   c->step = 0;
+  return SPS_OK;
+}
+
+sps_status sps_cnn_set_loss_weights(sps_cnn c, float pos_weight, float lambda_box) {
+  if (!c) return sps::set_error(SPS_ERR_INVALID_ARG, "NULL network");
+  if (!(pos_weight > 0.0f) || !(lambda_box >= 0.0f) || !isfinite(pos_weight) || !isfinite(lambda_box))
+    return sps::set_error(SPS_ERR_INVALID_ARG, "loss weights must be finite, pos_weight > 0");
+  c->pos_weight = pos_weight;
+  c->lambda_box = lambda_box;
   return SPS_OK;
 }
 

@@ -138,6 +138,7 @@ def library() -> ctypes.CDLL:
                   "sps_cnn_get_grads"):
             getattr(lib, f).argtypes = [P, P]
         lib.sps_cnn_activations.argtypes = [P, i32, i32, P]
+        lib.sps_cnn_set_loss_weights.argtypes = [P, ctypes.c_float, ctypes.c_float]
         lib.sps_cnn_signals.argtypes = [P, i32, i32, P]
         lib.sps_cnn_pool_tiles.argtypes = [P, i64, i32, i64, ctypes.c_float, P, P]
         lib.sps_cnn_forward.argtypes = [P, P, i32, P, P]
@@ -150,6 +151,7 @@ def library() -> ctypes.CDLL:
                                        ctypes.POINTER(i32), P]
         for f in ("sps_cnn_create", "sps_cnn_destroy", "sps_cnn_set_params", "sps_cnn_get_params",
                   "sps_cnn_set_grads", "sps_cnn_get_grads", "sps_cnn_activations", "sps_cnn_signals",
+                  "sps_cnn_set_loss_weights",
                   "sps_cnn_pool_tiles", "sps_cnn_forward", "sps_cnn_loss_grad", "sps_cnn_adam",
                   "sps_cnn_train_step", "sps_cnn_detect"):
             getattr(lib, f).restype = ctypes.c_int
@@ -645,6 +647,11 @@ def _params_vec(a) -> np.ndarray:
 def sps_cnn_set_params(net: Cnn, params) -> None:
     v = _params_vec(params)
     _check(library().sps_cnn_set_params(net.handle, v.ctypes.data), "sps_cnn_set_params")
+
+
+def sps_cnn_set_loss_weights(net: Cnn, pos_weight: float = 32.0, lambda_box: float = 1.0) -> None:
+    _check(library().sps_cnn_set_loss_weights(net.handle, float(pos_weight), float(lambda_box)),
+           "sps_cnn_set_loss_weights")
 
 
 def sps_cnn_get_params(net: Cnn) -> np.ndarray:

@@ -292,3 +292,31 @@ def test_argument_errors(sps):
             sps.sps_cnn_set_params(net, np.zeros(10, np.float32))
     with pytest.raises(sps.SpsError):
         sps.sps_cnn_create(0)
+
+
+def test_loss_weights(sps, case):
+    # non-default positive weight and offset weight: loss and head gradients
+    # against the oracle's formula on the GPU's own last-layer activations
+    params, tb, y = case
+    n = tb.shape[0]
+    pw, lb = 8.0, 3.0
+    with sps.sps_cnn_create(4) as net:
+        sps.sps_cnn_set_params(net, _flat(params))
+        sps.sps_cnn_set_loss_weights(net, pw, lb)
+        Y = torch.from_numpy(y.astype(np.float32)).cuda()
+        loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+        sps.sps_cnn_loss_grad(net, _to_dev_tiles(tb), Y, n, loss)
+        torch.cuda.synchronize()
+        a6 = _nchw(sps.sps_cnn_activations(net, 5, n))
+        grads = _unflat(sps.sps_cnn_get_grads(net), params)
+        L_g = float(loss.cpu()[0])
+        with pytest.raises(sps.SpsError):
+            sps.sps_cnn_set_loss_weights(net, 0.0, 1.0)
+    wh, bh = params["wh"].astype(np.float64), params["bh"].astype(np.float64)
+    h = np.einsum("kc,nchw->nkhw", wh, a6) + bh[None, :, None, None]
+    L_o = cnn.loss(h, y, pw, lb)
+    assert abs(L_g - L_o) <= 1e-4 * abs(L_o)
+    gh = cnn.loss_grad_head(h, y, pw, lb)
+    gmag = np.abs(gh).sum(axis=(0, 2, 3))
+    ncell = n * cnn.GRID_DM * cnn.GRID_T
+    assert np.all(np.abs(grads["bh"] - gh.sum(axis=(0, 2, 3))) <= (2 * ncell * U + 1e-5) * gmag)
