@@ -148,6 +148,8 @@ class TileFactory:
         meta = {k: np.full(n, np.nan) for k in ("dm", "toa_s", "fwhm_s", "target_snr",
                                                 "pulse_snr", "row", "col", "d_star", "t_star")}
         meta["positive"] = np.zeros(n, bool)
+        meta["sines"] = np.zeros(n, bool)
+        meta["impulses"] = np.zeros(n, bool)
         meta["boxcar_any"] = np.zeros(n, bool)
         meta["boxcar_hit"] = np.zeros(n, bool)
         meta["plane_max_snr"] = np.zeros(n)
@@ -172,6 +174,8 @@ class TileFactory:
             for i in range(nb):
                 j = b0 + i
                 meta["plane_max_snr"][j] = pmax[i]
+                meta["sines"][j] = len(truths[i].sines) > 0
+                meta["impulses"][j] = len(truths[i].impulses) > 0
                 cands, _ = sps.sps_batch_candidates(self.handle, i, cap=4096, stream=self.stream,
                                                     allow_truncated=True)
                 meta["boxcar_any"][j] = len(cands) > 0
@@ -260,6 +264,20 @@ def cnn_scores(net, tiles, batch: int, stream=None):
     if stream is not None:
         stream.synchronize()
     return out.cpu().numpy()
+
+
+def judge_by_rfi(head: np.ndarray, meta: dict, threshold: float, snr_min: float = 8.0) -> dict:
+    """judge() on all tiles and separately on tiles without RFI, with
+    sinusoids only and with impulses (any)."""
+    groups = {"all": np.ones(len(meta["positive"]), bool),
+              "clean": ~meta["sines"] & ~meta["impulses"],
+              "sines_only": meta["sines"] & ~meta["impulses"],
+              "impulses": meta["impulses"]}
+    out = {}
+    for g, m in groups.items():
+        sub = {k: v[m] for k, v in meta.items()}
+        out[g] = judge(head[m], sub, threshold, snr_min)
+    return out
 
 
 def judge(head: np.ndarray, meta: dict, threshold: float, snr_min: float = 8.0) -> dict:
