@@ -164,6 +164,7 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(const uint16_t *__restric
 #pragma unroll
   for (int b = 0; b < NB; ++b) acc[b] = floatx4{0.f, 0.f, 0.f, 0.f};
   const uint16_t *wrow = wp + (int64_t)(lane & 15) * KPAD + 8 * g;
+#pragma unroll 3
   for (int k0 = 0; k0 < KPAD; k0 += 32) {
     const int k = k0 + 8 * g;
     const int tap = k / CIN, ci = k % CIN;
@@ -299,43 +300,59 @@ __global__ __launch_bounds__(128) void head_loss_kernel(
 // dx[p][ci] = bf16(mask(x[p][ci]) * sum_{tap, co} W[co][ci][tap] dz[q(p, tap)][co])
 // for layers 1..5, where q(p, tap) is the output pixel that reads input p
 // through tap (if any).  M = input pixels, N = CIN, K = taps x COUT.
+// With stride 2 an input pixel is read only through the taps whose offset
+// has its parity (1, 2 or 4 of the 9), so the input pixels are taken in
+// four parity classes (blockIdx.y) and every workgroup loops over its
+// class's taps only.  With stride 1 there is one class with all 9 taps.
 template <int LI>
 __global__ __launch_bounds__(256) void conv_bwd_data_kernel(const uint16_t *__restrict__ dz,
                                                             const uint16_t *__restrict__ wt,
                                                             const uint16_t *__restrict__ x,
-                                                            uint16_t *__restrict__ dx,
-                                                            int64_t npix_in) {
+                                                            uint16_t *__restrict__ dx, int n) {
   constexpr Layer L = kLayers[LI];
   constexpr int CIN = L.cin, COUT = L.cout, S = L.stride, NB = CIN / 16, K = 9 * COUT;
+  // class geometry: rows/columns of input pixels with parity (py, px)
+  const int py = S == 2 ? (int)(blockIdx.y >> 1) : 0, px = S == 2 ? (int)(blockIdx.y & 1) : 0;
+  constexpr int CH = S == 2 ? L.hin / 2 : L.hin, CW = S == 2 ? L.win / 2 : L.win;
+  const int64_t ncls = (int64_t)n * CH * CW;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4;
-  const int64_t pbase = (int64_t)blockIdx.x * 64 + wave * 16;
-  const int64_t p = pbase + (lane & 15);
-  const bool valid = p < npix_in;
-  int64_t n = 0;
+  const int64_t cbase = (int64_t)blockIdx.x * 64 + wave * 16;
+  // the taps of this class: ky with (iy + 1 - ky) divisible by S, same for kx
+  int kys[3], kxs[3], nky = 0, nkx = 0;
+  for (int k = 0; k < 3; ++k) {
+    if (S == 1 || ((py + 1 - k) & 1) == 0) kys[nky++] = k;
+    if (S == 1 || ((px + 1 - k) & 1) == 0) kxs[nkx++] = k;
+  }
+  const int64_t cidx = cbase + (lane & 15);
+  const bool valid = cidx < ncls;
+  int64_t nn = 0;
   int iy = 0, ix = 0;
   if (valid) {
-    n = p / (L.hin * L.win);
-    const int r = (int)(p - n * L.hin * L.win);
-    iy = r / L.win;
-    ix = r % L.win;
+    nn = cidx / (CH * CW);
+    const int r = (int)(cidx - nn * CH * CW);
+    iy = (r / CW) * S + py;
+    ix = (r % CW) * S + px;
   }
   floatx4 acc[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b) acc[b] = floatx4{0.f, 0.f, 0.f, 0.f};
   const uint16_t *wrow = wt + (int64_t)(lane & 15) * K + 8 * g;
-  for (int tap = 0; tap < 9; ++tap) {
-    const int ty = iy + 1 - tap / 3, tx = ix + 1 - tap % 3;
-    const bool ok = valid && ty >= 0 && tx >= 0 && ty % S == 0 && tx % S == 0 &&
-                    ty / S < L.hout && tx / S < L.wout;
-    const int64_t src = ok ? ((n * L.hout + ty / S) * L.wout + tx / S) * COUT + 8 * g : 0;
-    for (int co0 = 0; co0 < COUT; co0 += 32) {
-      u32x4 av = {0u, 0u, 0u, 0u};
-      if (ok) av = *reinterpret_cast<const u32x4 *>(dz + src + co0);
+  for (int a = 0; a < nky; ++a) {
+    for (int bq = 0; bq < nkx; ++bq) {
+      const int tap = kys[a] * 3 + kxs[bq];
+      const int ty = iy + 1 - kys[a], tx = ix + 1 - kxs[bq];
+      const bool ok = valid && ty >= 0 && tx >= 0 && ty / S < L.hout && tx / S < L.wout;
+      const int64_t src = ok ? ((nn * L.hout + ty / S) * L.wout + tx / S) * COUT + 8 * g : 0;
 #pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        const u32x4 bv =
-            *reinterpret_cast<const u32x4 *>(wrow + (int64_t)b * 16 * K + tap * COUT + co0);
-        acc[b] = mfma(av, bv, acc[b]);
+      for (int co0 = 0; co0 < COUT; co0 += 32) {
+        u32x4 av = {0u, 0u, 0u, 0u};
+        if (ok) av = *reinterpret_cast<const u32x4 *>(dz + src + co0);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          const u32x4 bv =
+              *reinterpret_cast<const u32x4 *>(wrow + (int64_t)b * 16 * K + tap * COUT + co0);
+          acc[b] = mfma(av, bv, acc[b]);
+        }
       }
     }
   }
@@ -344,9 +361,12 @@ __global__ __launch_bounds__(256) void conv_bwd_data_kernel(const uint16_t *__re
     const int ci = b * 16 + (lane & 15);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int64_t q = pbase + 4 * g + j;
-      if (q < npix_in) {
-        const int64_t o = q * CIN + ci;
+      const int64_t q = cbase + 4 * g + j;
+      if (q < ncls) {
+        const int64_t qn = q / (CH * CW);
+        const int r = (int)(q - qn * CH * CW);
+        const int qy = (r / CW) * S + py, qx = (r % CW) * S + px;
+        const int64_t o = ((qn * L.hin + qy) * L.win + qx) * CIN + ci;
         dx[o] = bf_positive(x[o]) ? f2bf(acc[b][j]) : (uint16_t)0;
       }
     }
@@ -361,21 +381,24 @@ constexpr int kKP = 32;       // pixels per staged K-step
 constexpr int kLdsRow = 40;   // bf16 per LDS row (32 + 8 padding)
 
 // partial[split][co][tap][ci] = sum over the split's output pixels q of
-// dz[q][co] * x[input of q through tap][ci], layers 1..5.  Grid (9, nsplit);
-// M = COUT, N = CIN, K = pixels, staged 32 pixels at a time through LDS in
-// transposed form so that each lane's 8 K-values are one 16-byte read.
-template <int LI>
+// dz[q][co] * x[input of q through tap][ci], layers 1..5.  M = COUT,
+// N = CIN, K = pixels, staged 32 pixels at a time through LDS in transposed
+// form so that each lane's 8 K-values are one 16-byte read.  A workgroup
+// handles TAPS taps (grid (9 / TAPS, nsplit)): all 9 for the narrow layers,
+// where the staged signal tile is then shared by every tap, one for the
+// wide layers, whose accumulators would not fit nine times.
+template <int LI, int TAPS>
 __global__ __launch_bounds__(256) void conv_bwd_weight_kernel(const uint16_t *__restrict__ dz,
                                                               const uint16_t *__restrict__ x,
                                                               float *__restrict__ partial,
                                                               int64_t npix_out, int64_t chunk) {
   constexpr Layer L = kLayers[LI];
   constexpr int CIN = L.cin, COUT = L.cout, S = L.stride;
-  constexpr int MB = COUT / 16, NB = CIN / 16, NBLK = MB * NB;
+  constexpr int MB = COUT / 16, NB = CIN / 16, NBLK = MB * NB * TAPS;
   constexpr int PER_WAVE = (NBLK + 3) / 4;
   __shared__ __attribute__((aligned(16))) uint16_t dzT[COUT][kLdsRow];
-  __shared__ __attribute__((aligned(16))) uint16_t xT[CIN][kLdsRow];
-  const int tap = blockIdx.x, ky = tap / 3, kx = tap % 3;
+  __shared__ __attribute__((aligned(16))) uint16_t xT[TAPS][CIN][kLdsRow];
+  const int tap0 = blockIdx.x * TAPS;
   const int64_t split = blockIdx.y;
   const int64_t pbeg = split * chunk;
   const int64_t pend = pbeg + chunk < npix_out ? pbeg + chunk : npix_out;
@@ -393,29 +416,33 @@ __global__ __launch_bounds__(256) void conv_bwd_weight_kernel(const uint16_t *__
 #pragma unroll
       for (int i = 0; i < 8; ++i) dzT[c8 + i][pix] = h[i];
     }
-    for (int v = threadIdx.x; v < kKP * CIN / 8; v += 256) {
-      const int pix = v / (CIN / 8), c8 = (v % (CIN / 8)) * 8;
+    for (int v = threadIdx.x; v < TAPS * kKP * CIN / 8; v += 256) {
+      const int tt = v / (kKP * CIN / 8);
+      const int rem = v - tt * (kKP * CIN / 8);
+      const int pix = rem / (CIN / 8), c8 = (rem % (CIN / 8)) * 8;
+      const int tap = tap0 + tt;
       const int64_t q = p0 + pix;
       u32x4 d = {0u, 0u, 0u, 0u};
       if (q < pend) {
         const int64_t n = q / (L.hout * L.wout);
         const int r = (int)(q - n * L.hout * L.wout);
-        const int iy = S * (r / L.wout) + ky - 1, ix = S * (r % L.wout) + kx - 1;
+        const int iy = S * (r / L.wout) + tap / 3 - 1, ix = S * (r % L.wout) + tap % 3 - 1;
         if (iy >= 0 && iy < L.hin && ix >= 0 && ix < L.win)
           d = *reinterpret_cast<const u32x4 *>(x + ((n * L.hin + iy) * L.win + ix) * CIN + c8);
       }
       const uint16_t *h = reinterpret_cast<const uint16_t *>(&d);
 #pragma unroll
-      for (int i = 0; i < 8; ++i) xT[c8 + i][pix] = h[i];
+      for (int i = 0; i < 8; ++i) xT[tt][c8 + i][pix] = h[i];
     }
     __syncthreads();
 #pragma unroll
     for (int b = 0; b < PER_WAVE; ++b) {
       const int blk = wave * PER_WAVE + b;
       if (blk < NBLK) {
-        const int mb = blk / NB, nb = blk % NB;
+        const int tt = blk / (MB * NB), rb = blk % (MB * NB);
+        const int mb = rb / NB, nb = rb % NB;
         const u32x4 av = *reinterpret_cast<const u32x4 *>(&dzT[mb * 16 + (lane & 15)][8 * g]);
-        const u32x4 bv = *reinterpret_cast<const u32x4 *>(&xT[nb * 16 + (lane & 15)][8 * g]);
+        const u32x4 bv = *reinterpret_cast<const u32x4 *>(&xT[tt][nb * 16 + (lane & 15)][8 * g]);
         acc[b] = mfma(av, bv, acc[b]);
       }
     }
@@ -425,105 +452,158 @@ __global__ __launch_bounds__(256) void conv_bwd_weight_kernel(const uint16_t *__
   for (int b = 0; b < PER_WAVE; ++b) {
     const int blk = wave * PER_WAVE + b;
     if (blk < NBLK) {
-      const int mb = blk / NB, nb = blk % NB;
+      const int tt = blk / (MB * NB), rb = blk % (MB * NB);
+      const int mb = rb / NB, nb = rb % NB;
       const int ci = nb * 16 + (lane & 15);
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int co = mb * 16 + 4 * g + j;
-        partial[((split * COUT + co) * 9 + tap) * CIN + ci] = acc[b][j];
+        partial[((split * COUT + co) * 9 + tap0 + tt) * CIN + ci] = acc[b][j];
       }
     }
   }
 }
 
-// First layer's weight gradient on the vector ALU: grid (9, nsplit), each
-// thread accumulates 16 output channels over its pixels, then the block
-// reduces.  partial[split][co][tap] (CIN = 1).
+// First layer's weight gradient on the vector ALU: grid (2, nsplit), the
+// x index picking 8 of the 16 output channels.  Each thread reads a pixel's
+// 8 signals once and its 9 inputs, accumulates 8 x 9 products, and the
+// block reduces.  partial[split][co][tap] (CIN = 1).
 __global__ __launch_bounds__(256) void conv0_bwd_weight_kernel(const uint16_t *__restrict__ dz,
                                                                const uint16_t *__restrict__ x,
                                                                float *__restrict__ partial,
                                                                int64_t npix_out, int64_t chunk) {
   constexpr Layer L = kLayers[0];
-  __shared__ float red[256][17];
-  const int tap = blockIdx.x, ky = tap / 3, kx = tap % 3;
+  __shared__ float red[72][65];
+  const int half = blockIdx.x;
   const int64_t split = blockIdx.y;
   const int64_t pbeg = split * chunk;
   const int64_t pend = pbeg + chunk < npix_out ? pbeg + chunk : npix_out;
-  float acc[16];
+  float acc[8][9];
 #pragma unroll
-  for (int c = 0; c < 16; ++c) acc[c] = 0.f;
+  for (int c = 0; c < 8; ++c)
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[c][t] = 0.f;
   for (int64_t q = pbeg + threadIdx.x; q < pend; q += 256) {
     const int64_t n = q / (L.hout * L.wout);
     const int r = (int)(q - n * L.hout * L.wout);
-    const int iy = 2 * (r / L.wout) + ky - 1, ix = 2 * (r % L.wout) + kx - 1;
-    if (iy < 0 || iy >= L.hin || ix < 0 || ix >= L.win) continue;
-    const float xv = bf2f(x[(n * L.hin + iy) * L.win + ix]);
-    const u32x4 *d = reinterpret_cast<const u32x4 *>(dz + q * 16);
-    const u32x4 d0 = d[0], d1 = d[1];
-    const uint16_t *h0 = reinterpret_cast<const uint16_t *>(&d0);
-    const uint16_t *h1 = reinterpret_cast<const uint16_t *>(&d1);
+    const int oy = r / L.wout, ox = r % L.wout;
+    const u32x4 d = *reinterpret_cast<const u32x4 *>(dz + q * 16 + half * 8);
+    const uint16_t *h = reinterpret_cast<const uint16_t *>(&d);
+    float dv[8];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      acc[c] += bf2f(h0[c]) * xv;
-      acc[c + 8] += bf2f(h1[c]) * xv;
+    for (int c = 0; c < 8; ++c) dv[c] = bf2f(h[c]);
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int iy = 2 * oy + t / 3 - 1, ix = 2 * ox + t % 3 - 1;
+      const float xv = (iy >= 0 && iy < L.hin && ix >= 0 && ix < L.win)
+                           ? bf2f(x[(n * L.hin + iy) * L.win + ix])
+                           : 0.0f;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) acc[c][t] += dv[c] * xv;
     }
   }
+  // waves add their lanes' sums into LDS one after another (fixed order)
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
 #pragma unroll
-  for (int c = 0; c < 16; ++c) red[threadIdx.x][c] = acc[c];
-  __syncthreads();
-  if (threadIdx.x < 16) {
+      for (int c = 0; c < 8; ++c)
+#pragma unroll
+        for (int t = 0; t < 9; ++t)
+          red[c * 9 + t][lane] = (w == 0 ? 0.f : red[c * 9 + t][lane]) + acc[c][t];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 72) {
     float s = 0.f;
-    for (int t = 0; t < 256; ++t) s += red[t][threadIdx.x];
-    partial[(split * 16 + threadIdx.x) * 9 + tap] = s;
+    for (int k = 0; k < 64; ++k) s += red[threadIdx.x][k];
+    const int c = threadIdx.x / 9, t = threadIdx.x % 9;
+    partial[(split * 16 + half * 8 + c) * 9 + t] = s;
   }
 }
 
-// part[split][co] = sum over the split's pixels of dz[q][co].
+// part[block][co] = sum over the block's pixels of dz[q][co].  A thread owns
+// one 16-byte group of 8 channels and strides over pixels (the stride is a
+// multiple of the groups per pixel, so its group never changes); the block
+// then reduces the threads of each group.
+template <int COUT>
 __global__ __launch_bounds__(256) void bias_partial_kernel(const uint16_t *__restrict__ dz,
-                                                           int cout, int64_t npix,
-                                                           int64_t chunk,
+                                                           int64_t npix,
                                                            float *__restrict__ part) {
-  __shared__ float red[256];
-  const int64_t split = blockIdx.x;
-  const int64_t pbeg = split * chunk;
-  const int64_t pend = pbeg + chunk < npix ? pbeg + chunk : npix;
-  const int lanes = 256 / cout;  // pixels in flight per step (cout divides 256)
-  const int c = threadIdx.x % cout, r = threadIdx.x / cout;
-  float s = 0.f;
-  for (int64_t q = pbeg + r; q < pend; q += lanes) s += bf2f(dz[q * cout + c]);
-  red[threadIdx.x] = s;
+  constexpr int V = COUT / 8;  // 16-byte groups per pixel
+  __shared__ float red[256][9];
+  const int64_t nvec = npix * V;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < nvec; v += stride) {
+    const u32x4 d = *reinterpret_cast<const u32x4 *>(dz + v * 8);
+    const uint16_t *h = reinterpret_cast<const uint16_t *>(&d);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc[i] += bf2f(h[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < 8; ++i) red[threadIdx.x][i] = acc[i];
   __syncthreads();
-  if (threadIdx.x < cout) {
+  if (threadIdx.x < COUT) {
+    const int g = threadIdx.x / 8, i = threadIdx.x % 8;
     float t = 0.f;
-    for (int k = 0; k < lanes; ++k) t += red[k * cout + threadIdx.x];
-    part[split * cout + threadIdx.x] = t;
+    for (int k = g; k < 256; k += V) t += red[k][i];
+    part[(int64_t)blockIdx.x * COUT + threadIdx.x] = t;
   }
 }
 
-// grads[co][ci][tap] = sum_s partial[s][co][tap][ci] (fixed order).
-__global__ __launch_bounds__(256) void reduce_weight_kernel(const float *__restrict__ partial,
-                                                            int nsplit, int cout, int cin,
-                                                            float *__restrict__ grad) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t total = (int64_t)cout * cin * 9;
-  if (e >= total) return;
-  const int co = (int)(e / (cin * 9));
-  const int rem = (int)(e - (int64_t)co * cin * 9);
-  const int ci = rem / 9, tap = rem % 9;
+constexpr int kBiasBlocks = 1024;
+
+// Two-level sum of the weight-gradient partials, in a fixed order.  Level
+// one: tmp[g][i] = sum of partial[k][i] over the g-th of kWGroups contiguous
+// ranges of splits (grid (ceil(W / 256), kWGroups)); threads walk the
+// partials in their own layout so that the loads coalesce.  Level two:
+// grads[co][ci][tap] = sum_g tmp[g][i].
+constexpr int kWGroups = 32;
+
+__global__ __launch_bounds__(256) void reduce_weight_partial_kernel(
+    const float *__restrict__ partial, int nsplit, int64_t total, float *__restrict__ tmp) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= total) return;
+  const int per = (nsplit + kWGroups - 1) / kWGroups;
+  const int k0 = blockIdx.y * per;
+  const int k1 = k0 + per < nsplit ? k0 + per : nsplit;
   float s = 0.f;
-  for (int k = 0; k < nsplit; ++k) s += partial[(((int64_t)k * cout + co) * 9 + tap) * cin + ci];
-  grad[e] = s;
+  for (int k = k0; k < k1; ++k) s += partial[(int64_t)k * total + i];
+  tmp[(int64_t)blockIdx.y * total + i] = s;
 }
 
-// out[i] = sum_s part[s][i] for i < count (fixed order).
+__global__ __launch_bounds__(256) void reduce_weight_kernel(const float *__restrict__ tmp,
+                                                            int cout, int cin,
+                                                            float *__restrict__ grad) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t total = (int64_t)cout * cin * 9;
+  if (i >= total) return;
+  const int co = (int)(i / (9 * cin));
+  const int rem = (int)(i - (int64_t)co * 9 * cin);
+  const int tap = rem / cin, ci = rem % cin;
+  float s = 0.f;
+  for (int g = 0; g < kWGroups; ++g) s += tmp[(int64_t)g * total + i];
+  grad[((int64_t)co * cin + ci) * 9 + tap] = s;
+}
+
+// out[i] = sum_s part[s][i], one workgroup per output i: thread t adds rows
+// t, t + 256, ... and a fixed-order tree in LDS combines the 256 partial
+// sums (the result does not depend on scheduling).
 __global__ __launch_bounds__(256) void reduce_rows_kernel(const float *__restrict__ part,
                                                           int nrows, int count,
                                                           float *__restrict__ out) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= count) return;
+  __shared__ float red[256];
+  const int i = blockIdx.x;
   float s = 0.f;
-  for (int k = 0; k < nrows; ++k) s += part[(int64_t)k * count + i];
-  out[i] = s;
+  for (int k = threadIdx.x; k < nrows; k += 256) s += part[(int64_t)k * count + i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[i] = red[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -579,10 +659,19 @@ constexpr int64_t kParams = head_param_offset() + kHead * kFeat + kHead;
 int64_t npix_out(int li, int n) { return (int64_t)n * kLayers[li].hout * kLayers[li].wout; }
 int64_t npix_in(int li, int n) { return (int64_t)n * kLayers[li].hin * kLayers[li].win; }
 
-// Splits of the weight-gradient reduction: about 64-128 per layer, chunks a
-// multiple of the staged K-step.
-int64_t split_chunk(int64_t npix) {
-  int64_t c = (npix + 95) / 96;
+// Workgroups of a layer's weight-gradient kernel along its other grid
+// dimension (taps or channel halves): 9 / taps per workgroup for layers
+// 1..5, 2 for the first layer.
+int wgrad_groups(int li) {
+  static const int g[kNumLayers] = {2, 1, 1, 9, 9, 9};
+  return g[li];
+}
+
+// Pixel splits of the weight-gradient reduction: about 864 workgroups in
+// total per layer, chunks a multiple of the staged K-step.
+int64_t split_chunk(int64_t npix, int li) {
+  const int64_t target = 864 / wgrad_groups(li);
+  int64_t c = (npix + target - 1) / target;
   c = (c + kKP - 1) / kKP * kKP;
   return c < kKP ? kKP : c;
 }
@@ -598,6 +687,7 @@ struct sps_cnn_s {
   uint16_t *act[kNumLayers] = {}, *dz[kNumLayers] = {};
   float *partial = nullptr;   // weight-gradient partials (largest layer)
   float *bpart = nullptr;     // bias partials
+  float *wtmp = nullptr;      // second level of the weight-gradient sum
   float *head_part = nullptr; // per head block: [3][128] + [3] + [1]
   float *loss = nullptr;      // device scalar of the last loss_grad
   float *head = nullptr;      // head outputs of the last forward
@@ -615,7 +705,7 @@ sps_status cnn_dev_fail(hipError_t e, const char *what) {
 
 void cnn_free(sps_cnn c) {
   void *ptrs[] = {c->params, c->grads, c->m, c->v, c->partial, c->bpart, c->head_part, c->loss,
-                  c->head};
+                  c->head, c->wtmp};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (int i = 0; i < kNumLayers; ++i) {
@@ -676,9 +766,9 @@ sps_status run_head(sps_cnn c, const float *labels, int32_t n, bool train, hipSt
                      1.0f / (float)n, c->head, c->dz[5], part_wh, part_bh, part_loss, train ? 1 : 0,
                      c->pos_weight, c->lambda_box);
   if (train) {
-    hipLaunchKernelGGL(reduce_rows_kernel, dim3((kHead * kFeat + 255) / 256), dim3(256), 0, s,
+    hipLaunchKernelGGL(reduce_rows_kernel, dim3(kHead * kFeat), dim3(256), 0, s,
                        part_wh, nblk, kHead * kFeat, c->grads + hoff);
-    hipLaunchKernelGGL(reduce_rows_kernel, dim3(1), dim3(256), 0, s, part_bh, nblk, kHead,
+    hipLaunchKernelGGL(reduce_rows_kernel, dim3(kHead), dim3(256), 0, s, part_bh, nblk, kHead,
                        c->grads + hoff + kHead * kFeat);
     hipLaunchKernelGGL(reduce_rows_kernel, dim3(1), dim3(256), 0, s, part_loss, nblk, 1, c->loss);
   }
@@ -690,37 +780,50 @@ sps_status run_backward(sps_cnn c, const uint16_t *tiles, int32_t n, hipStream_t
   for (int li = kNumLayers - 1; li >= 0; --li) {
     const Layer &L = kLayers[li];
     const int64_t np = npix_out(li, n);
-    const int64_t chunk = split_chunk(np);
+    const int64_t chunk = split_chunk(np, li);
     const int64_t nsplit = (np + chunk - 1) / chunk;
     const uint16_t *xin = li == 0 ? tiles : c->act[li - 1];
     float *gw = c->grads + layer_param_offset(li);
     switch (li) {
       case 0:
-        hipLaunchKernelGGL(conv0_bwd_weight_kernel, dim3(9, (unsigned)nsplit), dim3(256), 0, s,
+        hipLaunchKernelGGL(conv0_bwd_weight_kernel, dim3(2, (unsigned)nsplit), dim3(256), 0, s,
                            c->dz[0], xin, c->partial, np, chunk);
         break;
-#define SPS_BWDW(LI)                                                                       \
-  case LI:                                                                                 \
-    hipLaunchKernelGGL(conv_bwd_weight_kernel<LI>, dim3(9, (unsigned)nsplit), dim3(256), 0, s, \
-                       c->dz[LI], xin, c->partial, np, chunk);                             \
+#define SPS_BWDW(LI, TAPS)                                                                   \
+  case LI:                                                                                   \
+    hipLaunchKernelGGL((conv_bwd_weight_kernel<LI, TAPS>), dim3(9 / TAPS, (unsigned)nsplit),  \
+                       dim3(256), 0, s, c->dz[LI], xin, c->partial, np, chunk);              \
     break;
-        SPS_BWDW(1) SPS_BWDW(2) SPS_BWDW(3) SPS_BWDW(4) SPS_BWDW(5)
+        SPS_BWDW(1, 9) SPS_BWDW(2, 9) SPS_BWDW(3, 1) SPS_BWDW(4, 1) SPS_BWDW(5, 1)
 #undef SPS_BWDW
     }
+    hipLaunchKernelGGL(reduce_weight_partial_kernel,
+                       dim3((unsigned)((L.wcount() + 255) / 256), kWGroups), dim3(256), 0, s,
+                       c->partial, (int)nsplit, L.wcount(), c->wtmp);
     hipLaunchKernelGGL(reduce_weight_kernel, dim3((unsigned)((L.wcount() + 255) / 256)), dim3(256),
-                       0, s, c->partial, (int)nsplit, L.cout, L.cin, gw);
-    hipLaunchKernelGGL(bias_partial_kernel, dim3((unsigned)nsplit), dim3(256), 0, s, c->dz[li],
-                       L.cout, np, chunk, c->bpart);
-    hipLaunchKernelGGL(reduce_rows_kernel, dim3(1), dim3(256), 0, s, c->bpart, (int)nsplit, L.cout,
-                       gw + L.wcount());
+                       0, s, c->wtmp, L.cout, L.cin, gw);
+    {
+      const int64_t nvec = np * (L.cout / 8);
+      int64_t nb = (nvec + 255) / 256;
+      nb = nb < kBiasBlocks ? nb : kBiasBlocks;
+      switch (L.cout) {
+        case 16: hipLaunchKernelGGL(bias_partial_kernel<16>, dim3((unsigned)nb), dim3(256), 0, s, c->dz[li], np, c->bpart); break;
+        case 32: hipLaunchKernelGGL(bias_partial_kernel<32>, dim3((unsigned)nb), dim3(256), 0, s, c->dz[li], np, c->bpart); break;
+        case 64: hipLaunchKernelGGL(bias_partial_kernel<64>, dim3((unsigned)nb), dim3(256), 0, s, c->dz[li], np, c->bpart); break;
+        default: hipLaunchKernelGGL(bias_partial_kernel<128>, dim3((unsigned)nb), dim3(256), 0, s, c->dz[li], np, c->bpart); break;
+      }
+      hipLaunchKernelGGL(reduce_rows_kernel, dim3((unsigned)L.cout), dim3(256), 0, s, c->bpart, (int)nb, L.cout,
+                         gw + L.wcount());
+    }
     if (li > 0) {
-      const int64_t ni = npix_in(li, n);
-      const unsigned grid = (unsigned)((ni + 63) / 64);
+      const int classes = L.stride == 2 ? 4 : 1;
+      const int64_t ncls = npix_in(li, n) / classes;
+      const dim3 grid((unsigned)((ncls + 63) / 64), (unsigned)classes);
       switch (li) {
 #define SPS_BWDD(LI)                                                                          \
   case LI:                                                                                    \
-    hipLaunchKernelGGL(conv_bwd_data_kernel<LI>, dim3(grid), dim3(256), 0, s, c->dz[LI],      \
-                       c->wt[LI], c->act[LI - 1], c->dz[LI - 1], ni);                         \
+    hipLaunchKernelGGL(conv_bwd_data_kernel<LI>, grid, dim3(256), 0, s, c->dz[LI],            \
+                       c->wt[LI], c->act[LI - 1], c->dz[LI - 1], n);                          \
     break;
         SPS_BWDD(1) SPS_BWDD(2) SPS_BWDD(3) SPS_BWDD(4) SPS_BWDD(5)
 #undef SPS_BWDD
@@ -757,11 +860,12 @@ sps_status sps_cnn_create(int32_t max_batch, sps_cnn *out) {
   int64_t pmax = 0;
   for (int i = 0; i < kNumLayers; ++i) {
     const int64_t np = npix_out(i, max_batch);
-    const int64_t ns = (np + split_chunk(np) - 1) / split_chunk(np);
+    const int64_t ns = (np + split_chunk(np, i) - 1) / split_chunk(np, i);
     pmax = ns * kLayers[i].wcount() > pmax ? ns * kLayers[i].wcount() : pmax;
     c->bpart_cap = ns * kLayers[i].cout > c->bpart_cap ? ns * kLayers[i].cout : c->bpart_cap;
   }
   c->partial_cap = pmax;
+  c->bpart_cap = (int64_t)kBiasBlocks * 128;
   const int64_t nblk = ((int64_t)max_batch * kCells + 127) / 128;
   auto alloc = [&](void **p, size_t bytes) {
     if (e == hipSuccess) e = hipMalloc(p, bytes);
@@ -772,6 +876,7 @@ sps_status sps_cnn_create(int32_t max_batch, sps_cnn *out) {
   alloc((void **)&c->v, sizeof(float) * kParams);
   alloc((void **)&c->partial, sizeof(float) * (size_t)pmax);
   alloc((void **)&c->bpart, sizeof(float) * (size_t)c->bpart_cap);
+  alloc((void **)&c->wtmp, sizeof(float) * (size_t)kWGroups * (size_t)kLayers[5].wcount());
   alloc((void **)&c->head_part, sizeof(float) * (size_t)(nblk * (kHead * kFeat + kHead + 1)));
   alloc((void **)&c->loss, sizeof(float) * 4);
   alloc((void **)&c->head, sizeof(float) * (size_t)max_batch * kHead * kCells);

@@ -18,6 +18,8 @@ constexpr int kS2Out = 4;  // consecutive outputs per thread
 // Y[m][t] = sum_s I[s][j(m)][t + R[m][s]].  One workgroup covers one coarse
 // group j and 1024 output samples, for every fine DM of the group, so the
 // subband rows it reads are shared through L1/L2 by the group's n0 trials.
+// Thread i owns outputs t0 + i + 256 b (b < 4): for a given (m, s) the shift
+// is uniform, so every load instruction reads 256 consecutive words.
 __global__ __launch_bounds__(kS2Threads) void subband_stage2_kernel(
     const uint32_t *__restrict__ I, int64_t len1, int ncoarse, int nsub,
     const int32_t *__restrict__ R, int ndm, int n0, uint32_t *__restrict__ Y, int64_t nout,
@@ -25,7 +27,7 @@ __global__ __launch_bounds__(kS2Threads) void subband_stage2_kernel(
   const int64_t blk = blockIdx.x;
   const int j = (int)(blk / nchunks);
   const int64_t chunk = blk - (int64_t)j * nchunks;
-  const int64_t t = (chunk * kS2Threads + threadIdx.x) * kS2Out;
+  const int64_t t = chunk * kS2Threads * kS2Out + threadIdx.x;
   if (t >= nout) return;
   const int m1 = min((j + 1) * n0, ndm);
   const int64_t plane = (int64_t)ncoarse * len1;
@@ -36,12 +38,12 @@ __global__ __launch_bounds__(kS2Threads) void subband_stage2_kernel(
       const uint32_t *row = I + (int64_t)s * plane + (int64_t)j * len1 + Rm[s] + t;
 #pragma unroll
       for (int b = 0; b < kS2Out; ++b)
-        if (t + b < nout) acc[b] += row[b];
+        if (t + b * kS2Threads < nout) acc[b] += row[b * kS2Threads];
     }
-    uint32_t *Ym = Y + (int64_t)m * nout;
+    uint32_t *Ym = Y + (int64_t)m * nout + t;
 #pragma unroll
     for (int b = 0; b < kS2Out; ++b)
-      if (t + b < nout) Ym[t + b] = acc[b];
+      if (t + b * kS2Threads < nout) Ym[b * kS2Threads] = acc[b];
   }
 }
 
