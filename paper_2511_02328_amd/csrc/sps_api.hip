@@ -618,7 +618,8 @@ sps_status sps_dedisperse_subband(sps_plan plan, const uint8_t *X, int64_t pitch
     if (e != hipSuccess) return hip_fail(e, "subband stage 1 launch");
   }
   hipError_t e = sps::launch_subband_stage2(plan->d_I, len1, plan->ncoarse, plan->nsub,
-                                            plan->d_resid, plan->ndm, plan->n0, Y, nout, s);
+                                            plan->d_resid, plan->rmax, plan->ndm, plan->n0, Y,
+                                            nout, s);
   if (e != hipSuccess) return hip_fail(e, "subband stage 2 launch");
   return SPS_OK;
 }

@@ -15,35 +15,51 @@ namespace {
 constexpr int kS2Threads = 256;
 constexpr int kS2Out = 4;  // consecutive outputs per thread
 
-// Y[m][t] = sum_s I[s][j(m)][t + R[m][s]].  One workgroup covers one coarse
-// group j and 1024 output samples, for every fine DM of the group, so the
-// subband rows it reads are shared through L1/L2 by the group's n0 trials.
-// Thread i owns outputs t0 + i + 256 b (b < 4): for a given (m, s) the shift
-// is uniform, so every load instruction reads 256 consecutive words.
-__global__ __launch_bounds__(kS2Threads) void subband_stage2_kernel(
+// Stage 2, Y[m][t] = sum_s I[s][j(m)][t + R[m][s]], one workgroup per coarse
+// group j and 1024 output samples.  The subband loop is outside and up to
+// GM fine DMs of the group are accumulated together, so the GM overlapping
+// windows of one subband row (a few KB) are read back to back and served
+// from L1, and each word of I leaves L2 about once per tile.  Thread i owns
+// outputs t0 + i + 256 b (b < 4).
+template <int GM>
+__global__ __launch_bounds__(kS2Threads) void subband_stage2_blocked_kernel(
     const uint32_t *__restrict__ I, int64_t len1, int ncoarse, int nsub,
     const int32_t *__restrict__ R, int ndm, int n0, uint32_t *__restrict__ Y, int64_t nout,
     int64_t nchunks) {
   const int64_t blk = blockIdx.x;
   const int j = (int)(blk / nchunks);
-  const int64_t chunk = blk - (int64_t)j * nchunks;
-  const int64_t t = chunk * kS2Threads * kS2Out + threadIdx.x;
+  const int64_t t = (blk - (int64_t)j * nchunks) * kS2Threads * kS2Out + threadIdx.x;
   if (t >= nout) return;
-  const int m1 = min((j + 1) * n0, ndm);
+  const int mend = min((j + 1) * n0, ndm);
   const int64_t plane = (int64_t)ncoarse * len1;
-  for (int m = j * n0; m < m1; ++m) {
-    uint32_t acc[kS2Out] = {0u, 0u, 0u, 0u};
-    const int32_t *Rm = R + (int64_t)m * nsub;
-    for (int s = 0; s < nsub; ++s) {
-      const uint32_t *row = I + (int64_t)s * plane + (int64_t)j * len1 + Rm[s] + t;
+  for (int m0 = j * n0; m0 < mend; m0 += GM) {
+    const int gm = min(GM, mend - m0);
+    uint32_t acc[GM][kS2Out];
 #pragma unroll
-      for (int b = 0; b < kS2Out; ++b)
-        if (t + b * kS2Threads < nout) acc[b] += row[b * kS2Threads];
+    for (int a = 0; a < GM; ++a)
+#pragma unroll
+      for (int b = 0; b < kS2Out; ++b) acc[a][b] = 0u;
+    for (int sb = 0; sb < nsub; ++sb) {
+      const uint32_t *row = I + (int64_t)sb * plane + (int64_t)j * len1 + t;
+#pragma unroll
+      for (int a = 0; a < GM; ++a) {
+        if (a < gm) {
+          const uint32_t *w = row + R[(int64_t)(m0 + a) * nsub + sb];
+#pragma unroll
+          for (int b = 0; b < kS2Out; ++b)
+            if (t + b * kS2Threads < nout) acc[a][b] += w[b * kS2Threads];
+        }
+      }
     }
-    uint32_t *Ym = Y + (int64_t)m * nout + t;
 #pragma unroll
-    for (int b = 0; b < kS2Out; ++b)
-      if (t + b * kS2Threads < nout) Ym[b * kS2Threads] = acc[b];
+    for (int a = 0; a < GM; ++a) {
+      if (a < gm) {
+        uint32_t *Ym = Y + (int64_t)(m0 + a) * nout + t;
+#pragma unroll
+        for (int b = 0; b < kS2Out; ++b)
+          if (t + b * kS2Threads < nout) Ym[b * kS2Threads] = acc[a][b];
+      }
+    }
   }
 }
 
@@ -117,14 +133,15 @@ __global__ __launch_bounds__(256) void downsample_sqrt_kernel(
 }  // namespace
 
 hipError_t launch_subband_stage2(const uint32_t *I, int64_t len1, int ncoarse, int nsub,
-                                 const int32_t *R, int ndm, int n0, uint32_t *Y, int64_t nout,
-                                 hipStream_t stream) {
+                                 const int32_t *R, int rmax, int ndm, int n0, uint32_t *Y,
+                                 int64_t nout, hipStream_t stream) {
   const int64_t per_block = (int64_t)kS2Threads * kS2Out;
   const int64_t nchunks = (nout + per_block - 1) / per_block;
   const int64_t grid = nchunks * ncoarse;
   if (grid > 0x7FFFFFFF) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(subband_stage2_kernel, dim3((unsigned)grid), dim3(kS2Threads), 0, stream, I,
-                     len1, ncoarse, nsub, R, ndm, n0, Y, nout, nchunks);
+  (void)rmax;
+  hipLaunchKernelGGL(subband_stage2_blocked_kernel<8>, dim3((unsigned)grid), dim3(kS2Threads), 0,
+                     stream, I, len1, ncoarse, nsub, R, ndm, n0, Y, nout, nchunks);
   return hipGetLastError();
 }
 

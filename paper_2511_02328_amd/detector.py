@@ -1,5 +1,5 @@
 """The learned candidate detector around the HIP library: its training set
-made by the search itself, the training loop and the judgement against the
+made by the search itself, the training loop and the comparison with the
 plain boxcar search.
 
 Tiles come from the single-beam set-up (256 channels, 98.304 us, 512 trial
@@ -7,7 +7,7 @@ DMs 0-1000, 4096 output samples): seeded synthetic filterbanks, half of them
 with persistent narrow-band sinusoids, half (independently) with broadband
 impulses, and for the positive half one dispersed pulse whose amplitude aims
 at a boxcar S/N drawn from 5-50.  The library dedisperses them, forms the S/N planes,
-runs the boxcar search (the judge) and pools the planes into bfloat16 tiles;
+runs the boxcar search (the yardstick) and pools the planes into bfloat16 tiles;
 the labels are the injected pulses' positions.  Python only draws the
 events, marshals buffers and keeps the books.
 """
@@ -266,8 +266,8 @@ def cnn_scores(net, tiles, batch: int, stream=None):
     return out.cpu().numpy()
 
 
-def judge_by_rfi(head: np.ndarray, meta: dict, threshold: float, snr_min: float = 8.0) -> dict:
-    """judge() on all tiles and separately on tiles without RFI, with
+def compare_by_rfi(head: np.ndarray, meta: dict, threshold: float, snr_min: float = 8.0) -> dict:
+    """compare_with_boxcar() on all tiles and separately on tiles without RFI, with
     sinusoids only and with impulses (any)."""
     groups = {"all": np.ones(len(meta["positive"]), bool),
               "clean": ~meta["sines"] & ~meta["impulses"],
@@ -276,11 +276,12 @@ def judge_by_rfi(head: np.ndarray, meta: dict, threshold: float, snr_min: float 
     out = {}
     for g, m in groups.items():
         sub = {k: v[m] for k, v in meta.items()}
-        out[g] = judge(head[m], sub, threshold, snr_min)
+        out[g] = compare_with_boxcar(head[m], sub, threshold, snr_min)
     return out
 
 
-def judge(head: np.ndarray, meta: dict, threshold: float, snr_min: float = 8.0) -> dict:
+def compare_with_boxcar(head: np.ndarray, meta: dict, threshold: float,
+                        snr_min: float = 8.0) -> dict:
     """Recall on positive tiles whose injected pulse reaches snr_min in the
     boxcar plane, and false-alarm rate on pulse-free tiles, for the network
     and for the boxcar search.  A network detection is a cell at or above
