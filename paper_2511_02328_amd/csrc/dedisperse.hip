@@ -163,14 +163,44 @@ __device__ __forceinline__ int uniform_offset(int row_base_dw, int off) {
   return s;
 }
 
+// Writes the accumulators of trials dw0 .. dw0 + DPW - 1 at outputs
+// t0 + 4 (lane m + j) + b of plane Y.
+template <int M, int DPW>
+__device__ __forceinline__ void store_acc(const uint32_t (&acc)[DPW][M][4], uint32_t *__restrict__ Y,
+                                          int64_t nout, int ndm, int dw0, int lane, int64_t t0,
+                                          int vec_store) {
+#pragma unroll
+  for (int k = 0; k < DPW; ++k) {
+    const int d = dw0 + k;
+    if (d >= ndm) continue;
+    uint32_t *Yd = Y + (int64_t)d * nout;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      const int64_t t = t0 + 4 * (int64_t)(lane * M + j);
+      if (vec_store && t + 4 <= nout) {
+        *reinterpret_cast<uint4 *>(Yd + t) =
+            make_uint4(acc[k][j][0], acc[k][j][1], acc[k][j][2], acc[k][j][3]);
+      } else {
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          if (t + b < nout) Yd[t + b] = acc[k][j][b];
+      }
+    }
+  }
+}
+
 // One workgroup's share: trials [d_lo, d_lo + nw dpw) x outputs
-// [t0, t0 + 256 m) of one filterbank.  Ends with a barrier, so the caller may
-// reuse the LDS buffers right away.
-template <int M, int DPW, int NW, int CS, int KMAX>
+// [t0, t0 + 256 m) of one filterbank.  With seg > 0 (a multiple of CS) the
+// channels form consecutive groups of seg and group g's partial sums go to
+// plane Y + g seg_stride instead of one total (the first stage of subband
+// dedispersion in one pass over all channels).  Ends with a barrier, so the
+// caller may reuse the LDS buffers right away.
+template <int M, int DPW, int NW, int CS, int KMAX, bool SEG = false>
 __device__ __forceinline__ void dedisperse_block(
     const uint8_t *__restrict__ X, int64_t pitch, int64_t nsamp_in,
     const int32_t *__restrict__ D, int nchan, int ndm, uint32_t *__restrict__ Y, int64_t nout,
-    int lds_pitch, int vec_store, int64_t t0, int d_lo, uint4 *smem) {
+    int lds_pitch, int vec_store, int64_t t0, int d_lo, uint4 *smem, int seg = 0,
+    int64_t seg_stride = 0) {
   static_assert(M % 2 == 1, "lane stride must be odd for conflict-free LDS reads");
   static_assert(CS % 2 == 0 && 256 % CS == 0, "slab must be even and divide 256");
   static_assert(CS % NW == 0, "every wave stages the same number of rows");
@@ -240,7 +270,8 @@ __device__ __forceinline__ void dedisperse_block(
       }
     }
 
-    if ((c1 & 255) == 0 || !more) {
+    const bool seg_end = SEG && (c1 % seg == 0 || !more);
+    if ((c1 & 255) == 0 || !more || seg_end) {
 #pragma unroll
       for (int k = 0; k < DPW; ++k)
 #pragma unroll
@@ -253,45 +284,41 @@ __device__ __forceinline__ void dedisperse_block(
           od[k][j] = 0u;
         }
     }
+    if constexpr (SEG) {
+      if (seg_end) {
+        store_acc<M, DPW>(acc, Y + (int64_t)(c0 / seg) * seg_stride, nout, ndm, dw0, lane, t0,
+                          vec_store);
+#pragma unroll
+        for (int k = 0; k < DPW; ++k)
+#pragma unroll
+          for (int j = 0; j < M; ++j)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[k][j][b] = 0u;
+      }
+    }
     if (more) slab_store(st, smem + (parity ^ 1) * (buf_dw >> 2), ncs1, vpr, wave, lane);
     __syncthreads();
     parity ^= 1;
   }
 
-#pragma unroll
-  for (int k = 0; k < DPW; ++k) {
-    const int d = dw0 + k;
-    if (d >= ndm) continue;
-    uint32_t *Yd = Y + (int64_t)d * nout;
-#pragma unroll
-    for (int j = 0; j < M; ++j) {
-      const int64_t t = t0 + 4 * (int64_t)(lane * M + j);
-      if (vec_store && t + 4 <= nout) {
-        *reinterpret_cast<uint4 *>(Yd + t) =
-            make_uint4(acc[k][j][0], acc[k][j][1], acc[k][j][2], acc[k][j][3]);
-      } else {
-#pragma unroll
-        for (int b = 0; b < 4; ++b)
-          if (t + b < nout) Yd[t + b] = acc[k][j][b];
-      }
-    }
-  }
+  if constexpr (!SEG) store_acc<M, DPW>(acc, Y, nout, ndm, dw0, lane, t0, vec_store);
 }
 
-template <int M, int DPW, int NW, int CS, int KMAX, int WPE>
+template <int M, int DPW, int NW, int CS, int KMAX, int WPE, bool SEG>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) void
 dedisperse_kernel(const uint8_t *__restrict__ X, int64_t pitch, int64_t nsamp_in,
                   const int32_t *__restrict__ D, int nchan, int ndm, uint32_t *__restrict__ Y,
-                  int64_t nout, int lds_pitch, int ntiles, int ndmb, int per_xcd, int vec_store) {
+                  int64_t nout, int lds_pitch, int ntiles, int ndmb, int per_xcd, int vec_store,
+                  int seg, int64_t seg_stride) {
   extern __shared__ uint4 smem[];  // two slab buffers of CS rows x lds_pitch bytes
   const int blk = blockIdx.x;
   const int logical = (blk & 7) * per_xcd + (blk >> 3);
   if (logical >= ntiles * ndmb) return;
   const int dblk = logical % ndmb;
   const int tile = logical / ndmb;
-  dedisperse_block<M, DPW, NW, CS, KMAX>(X, pitch, nsamp_in, D, nchan, ndm, Y, nout, lds_pitch,
-                                         vec_store, (int64_t)tile * (256 * M), dblk * (NW * DPW),
-                                         smem);
+  dedisperse_block<M, DPW, NW, CS, KMAX, SEG>(X, pitch, nsamp_in, D, nchan, ndm, Y, nout,
+                                              lds_pitch, vec_store, (int64_t)tile * (256 * M),
+                                              dblk * (NW * DPW), smem, seg, seg_stride);
 }
 
 // Persistent kernel over many filterbanks that share a plan (beams of one
@@ -343,13 +370,15 @@ __global__ __launch_bounds__(256) void dedisperse_direct_kernel(
   }
 }
 
-template <int M, int DPW, int NW, int CS, int KMAX, int WPE>
+template <int M, int DPW, int NW, int CS, int KMAX, int WPE, bool SEG>
 hipError_t launch_cfg(int lds_pitch, const uint8_t *X, int64_t pitch, int64_t nsamp_in,
                       const int32_t *D, int nchan, int ndm, uint32_t *Y, int64_t nout,
-                      hipStream_t stream) {
+                      hipStream_t stream, int seg, int64_t seg_stride) {
   constexpr int NT = 256 * M;
   constexpr int ND = NW * DPW;
   if (lds_pitch > 16 * 64 * KMAX || lds_pitch % 16 != 0) return hipErrorInvalidValue;
+  if (SEG != (seg > 0) || (SEG && (seg % CS != 0 || nchan % seg != 0)))
+    return hipErrorInvalidValue;
   const int64_t ntiles64 = (nout + NT - 1) / NT;
   const int ndmb = (ndm + ND - 1) / ND;
   const int64_t total = ntiles64 * ndmb;
@@ -357,15 +386,17 @@ hipError_t launch_cfg(int lds_pitch, const uint8_t *X, int64_t pitch, int64_t ns
   const int per_xcd = (int)((total + 7) / 8);
   const int grid = per_xcd * 8;
   const size_t lds = 2 * (size_t)CS * (size_t)lds_pitch;
-  const int vec_store = (nout % 4 == 0) && ((reinterpret_cast<uintptr_t>(Y) & 15) == 0);
-  auto kern = dedisperse_kernel<M, DPW, NW, CS, KMAX, WPE>;
+  const int vec_store = (nout % 4 == 0) && ((reinterpret_cast<uintptr_t>(Y) & 15) == 0) &&
+                        (seg == 0 || seg_stride % 4 == 0);
+  auto kern = dedisperse_kernel<M, DPW, NW, CS, KMAX, WPE, SEG>;
   if (lds > 64 * 1024) {
     const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(kern, dim3(grid), dim3(NW * 64), lds, stream, X, pitch, nsamp_in, D, nchan,
-                     ndm, Y, nout, lds_pitch, (int)ntiles64, ndmb, per_xcd, vec_store);
+                     ndm, Y, nout, lds_pitch, (int)ntiles64, ndmb, per_xcd, vec_store, seg,
+                     seg_stride);
   return hipGetLastError();
 }
 
@@ -452,8 +483,10 @@ hipError_t launch_dedisperse_batch(const DedispConfig &c, int lds_pitch, const B
 
 hipError_t launch_dedisperse(const DedispConfig &c, int lds_pitch, const uint8_t *X,
                              int64_t pitch, int64_t nsamp_in, const int32_t *D, int nchan,
-                             int ndm, uint32_t *Y, int64_t nout, hipStream_t stream) {
+                             int ndm, uint32_t *Y, int64_t nout, hipStream_t stream, int seg,
+                             int64_t seg_stride) {
   if (c.m == 0) {
+    if (seg != 0) return hipErrorInvalidValue;
     const int64_t nthreads = (nout + 3) / 4;
     const int64_t gx = (nthreads + 255) / 256;
     if (gx > 0x7FFFFFFF) return hipErrorInvalidValue;
@@ -465,8 +498,11 @@ hipError_t launch_dedisperse(const DedispConfig &c, int lds_pitch, const uint8_t
 #define SPS_LAUNCH(m_, dpw_, nw_, cs_, kmax_, wpe_)                                     \
   if (c.m == m_ && c.dpw == dpw_ && c.nw == nw_ && c.cs == cs_ && c.kmax == kmax_ &&    \
       c.wpe == wpe_)                                                                     \
-    return launch_cfg<m_, dpw_, nw_, cs_, kmax_, wpe_>(lds_pitch, X, pitch, nsamp_in, D, \
-                                                       nchan, ndm, Y, nout, stream);
+    return seg > 0 ? launch_cfg<m_, dpw_, nw_, cs_, kmax_, wpe_, true>(                 \
+                         lds_pitch, X, pitch, nsamp_in, D, nchan, ndm, Y, nout, stream, seg, \
+                         seg_stride)                                                        \
+                   : launch_cfg<m_, dpw_, nw_, cs_, kmax_, wpe_, false>(                    \
+                         lds_pitch, X, pitch, nsamp_in, D, nchan, ndm, Y, nout, stream, 0, 0);
   SPS_DEDISP_CONFIGS(SPS_LAUNCH)
 #undef SPS_LAUNCH
   return hipErrorInvalidValue;

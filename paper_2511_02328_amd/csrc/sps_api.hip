@@ -82,6 +82,12 @@ struct sps_plan_s {
   std::vector<int32_t *> d_coarse_sub;  // per subband: [ncoarse][channels of s]
   std::vector<sps::DedispConfig> sub_cfg;
   std::vector<int> sub_pitch;
+  // stage 1 in one launch over all channels (equal subbands that are a
+  // multiple of the tiling's slab): the whole coarse table and its tiling
+  bool fused = false;
+  sps::DedispConfig fused_cfg{0, 0, 0, 0, 0, 0};
+  int fused_pitch = 0;
+  int32_t *d_coarse_full = nullptr;
   int32_t *d_resid = nullptr;
   uint32_t *d_I = nullptr;
   size_t I_bytes = 0;
@@ -105,6 +111,7 @@ void free_plan(sps_plan p) {
     if (q) (void)hipFree(q);
   if (p->d_resid) (void)hipFree(p->d_resid);
   if (p->d_I) (void)hipFree(p->d_I);
+  if (p->d_coarse_full) (void)hipFree(p->d_coarse_full);
   delete p;
 }
 
@@ -129,9 +136,14 @@ int64_t fitted_pitch(sps_plan p, const sps::DedispConfig &c, int64_t lds_budget)
 // Picks the first preferred tiling whose double-buffered slab fits the LDS
 // budget (64 KiB keeps two workgroups per CU; up to 160 KiB is allowed
 // next); otherwise the plain global-memory kernel (m = 0) is used.
-void pick_tiling(const int32_t *D, int nchan, int ndm, sps::DedispConfig *cfg, int *pitch) {
+// seg > 0 restricts the choice to slabs that divide seg (segmented output)
+// and to the 4-waves-per-SIMD tilings, whose register budget holds the
+// segment stores without spilling.
+void pick_tiling(const int32_t *D, int nchan, int ndm, sps::DedispConfig *cfg, int *pitch,
+                 int seg = 0) {
   for (int64_t budget : {(int64_t)64 * 1024, (int64_t)160 * 1024}) {
     for (const auto &c : kPrefs) {
+      if (seg > 0 && (seg % c.cs != 0 || c.wpe != 4)) continue;
       const int64_t pp = fitted_pitch(D, nchan, ndm, c, budget);
       if (pp > 0) {
         *cfg = c;
@@ -551,6 +563,23 @@ sps_status sps_subband_plan_create(const sps_subband_desc *desc, sps_plan *out) 
       return fail(SPS_ERR_NOMEM, "device allocation of subband tables failed");
     }
   }
+  // One stage-1 launch over all channels when the subbands are equal.
+  if (nchan % nsub == 0) {
+    const int seg = nchan / nsub;
+    pick_tiling(p->coarse_delays.data(), nchan, ncoarse, &p->fused_cfg, &p->fused_pitch, seg);
+    if (p->fused_cfg.m != 0) {
+      hipError_t e = hipMalloc(&p->d_coarse_full, p->coarse_delays.size() * sizeof(int32_t));
+      if (e == hipSuccess)
+        e = hipMemcpy(p->d_coarse_full, p->coarse_delays.data(),
+                      p->coarse_delays.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+      if (e != hipSuccess) {
+        free_plan(p);
+        (void)hipGetLastError();
+        return fail(SPS_ERR_NOMEM, "device allocation of the coarse table failed");
+      }
+      p->fused = true;
+    }
+  }
   hipError_t e = hipMalloc(&p->d_resid, p->residuals.size() * sizeof(int32_t));
   if (e == hipSuccess)
     e = hipMemcpy(p->d_resid, p->residuals.data(), p->residuals.size() * sizeof(int32_t),
@@ -595,7 +624,9 @@ sps_status sps_dedisperse_subband(sps_plan plan, const uint8_t *X, int64_t pitch
                 (long long)nsamp_in, (long long)nout, plan->eff_max_delay);
   DeviceScope scope(plan->device);
   if (scope.err != hipSuccess) return hip_fail(scope.err, "selecting the plan's device");
-  const int64_t len1 = nout + plan->rmax;
+  // Subband series rows: nout + R_max samples, padded to a multiple of 4 so
+  // that stage 1 stores 16-byte vectors.
+  const int64_t len1 = (nout + plan->rmax + 3) / 4 * 4;
   const size_t need = (size_t)plan->nsub * plan->ncoarse * (size_t)len1 * sizeof(uint32_t);
   if (plan->I_bytes < need) {
     if (plan->d_I) (void)hipFree(plan->d_I);
@@ -609,13 +640,21 @@ sps_status sps_dedisperse_subband(sps_plan plan, const uint8_t *X, int64_t pitch
     plan->I_bytes = need;
   }
   hipStream_t s = (hipStream_t)stream;
-  for (int b = 0; b < plan->nsub; ++b) {
-    const int c0 = plan->sub[(size_t)b], ns = plan->sub[(size_t)b + 1] - c0;
-    hipError_t e = sps::launch_dedisperse(
-        plan->sub_cfg[(size_t)b], plan->sub_pitch[(size_t)b], X + (int64_t)c0 * pitch, pitch,
-        nsamp_in, plan->d_coarse_sub[(size_t)b], ns, plan->ncoarse,
-        plan->d_I + (size_t)b * plan->ncoarse * (size_t)len1, len1, s);
+  if (plan->fused) {
+    hipError_t e = sps::launch_dedisperse(plan->fused_cfg, plan->fused_pitch, X, pitch, nsamp_in,
+                                          plan->d_coarse_full, plan->nchan, plan->ncoarse,
+                                          plan->d_I, len1, s, plan->nchan / plan->nsub,
+                                          (int64_t)plan->ncoarse * len1);
     if (e != hipSuccess) return hip_fail(e, "subband stage 1 launch");
+  } else {
+    for (int b = 0; b < plan->nsub; ++b) {
+      const int c0 = plan->sub[(size_t)b], ns = plan->sub[(size_t)b + 1] - c0;
+      hipError_t e = sps::launch_dedisperse(
+          plan->sub_cfg[(size_t)b], plan->sub_pitch[(size_t)b], X + (int64_t)c0 * pitch, pitch,
+          nsamp_in, plan->d_coarse_sub[(size_t)b], ns, plan->ncoarse,
+          plan->d_I + (size_t)b * plan->ncoarse * (size_t)len1, len1, s);
+      if (e != hipSuccess) return hip_fail(e, "subband stage 1 launch");
+    }
   }
   hipError_t e = sps::launch_subband_stage2(plan->d_I, len1, plan->ncoarse, plan->nsub,
                                             plan->d_resid, plan->rmax, plan->ndm, plan->n0, Y,

@@ -61,9 +61,12 @@ hipError_t launch_dedisperse_batch(const DedispConfig &c, int lds_pitch, const B
                                    int nbeams, int64_t total_items, const int32_t *D, int nchan,
                                    int ndm, int grid, hipStream_t stream);
 
+// seg > 0: channel groups of seg (a multiple of the slab, dividing nchan)
+// write their partial sums to planes Y + g seg_stride (m > 0 tilings only).
 hipError_t launch_dedisperse(const DedispConfig &cfg, int lds_pitch, const uint8_t *X,
                              int64_t pitch, int64_t nsamp_in, const int32_t *D, int nchan,
-                             int ndm, uint32_t *Y, int64_t nout, hipStream_t stream);
+                             int ndm, uint32_t *Y, int64_t nout, hipStream_t stream, int seg = 0,
+                             int64_t seg_stride = 0);
 
 hipError_t launch_row_stats(const uint32_t *Y, int ndm, int64_t nout, uint32_t vmax,
                             int32_t *stats, hipStream_t stream);
