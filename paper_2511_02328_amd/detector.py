@@ -153,6 +153,12 @@ class TileFactory:
         meta["boxcar_any"] = np.zeros(n, bool)
         meta["boxcar_hit"] = np.zeros(n, bool)
         meta["plane_max_snr"] = np.zeros(n)
+        # a pseudo pulse per pulse-free tile, drawn like the real ones from a
+        # separate stream: how often a search "finds" a pulse by chance
+        for k in ("pseudo_d", "pseudo_t", "pseudo_fws"):
+            meta[k] = np.full(n, np.nan)
+        meta["boxcar_chance"] = np.zeros(n, bool)
+        prng = np.random.Generator(np.random.PCG64([seed, 7]))
         ddm = (wl.dm_hi - wl.dm_lo) / (wl.ndm - 1)
         for b0 in range(0, n, self.batch):
             nb = min(self.batch, n - b0)
@@ -181,6 +187,15 @@ class TileFactory:
                 meta["boxcar_any"][j] = len(cands) > 0
                 info = infos[i]
                 if info is None:
+                    pdm = prng.uniform(*spec.dm_range)
+                    pfw = math.exp(prng.uniform(math.log(spec.fwhm_range_s[0]),
+                                                math.log(spec.fwhm_range_s[1])))
+                    ptoa = prng.uniform(3 * pfw + 0.01, wl.nout * wl.tsamp_s - 3 * pfw - 0.01)
+                    pd, pt, pf = (pdm - wl.dm_lo) / ddm, ptoa / wl.tsamp_s, pfw / wl.tsamp_s
+                    meta["pseudo_d"][j], meta["pseudo_t"][j], meta["pseudo_fws"][j] = pd, pt, pf
+                    meta["boxcar_chance"][j] = bool(
+                        ((np.abs(cands["dm_idx"] - pd) <= MATCH_DM) &
+                         (np.abs(cands["t_idx"] - pt) <= MATCH_T + 3 * pf)).any())
                     continue
                 dm, toa, fw, target = info
                 d_star = (dm - wl.dm_lo) / ddm
@@ -288,7 +303,9 @@ def compare_with_boxcar(head: np.ndarray, meta: dict, threshold: float,
     the probability threshold, placed where its offset heads put it; it
     matches the pulse under the same rule as a boxcar candidate (within
     MATCH_DM trials and MATCH_T + 3 FWHM samples).  A false alarm is any
-    detection on a pulse-free tile."""
+    detection on a pulse-free tile; the chance-match rate is how often a
+    pulse-free tile has a detection matching a pseudo pulse drawn like the
+    real ones (the part of a recall that coincidence alone would give)."""
     logit = math.log(threshold / (1 - threshold))
     fire = head[:, 0] >= logit
     pos = meta["positive"]
@@ -304,8 +321,17 @@ def compare_with_boxcar(head: np.ndarray, meta: dict, threshold: float,
              (np.abs(t_pred - meta["t_star"][j]) <= MATCH_T + 3 * fws)
         hit[j] = bool(ok.any())
     neg = ~pos
+    chance = np.zeros(len(pos), bool)
+    for j in np.flatnonzero(neg):
+        d_pred = (gy + head[j, 1]) * CELL[0] * POOL[0]
+        t_pred = (gx + head[j, 2]) * CELL[1] * POOL[1]
+        ok = fire[j] & (np.abs(d_pred - meta["pseudo_d"][j]) <= MATCH_DM) & \
+             (np.abs(t_pred - meta["pseudo_t"][j]) <= MATCH_T + 3 * meta["pseudo_fws"][j])
+        chance[j] = bool(ok.any())
     return {
         "threshold": threshold,
+        "cnn_chance_match_rate": float(chance[neg].mean()) if neg.any() else None,
+        "boxcar_chance_match_rate": float(meta["boxcar_chance"][neg].mean()) if neg.any() else None,
         "n_positive_snr_ge_min": int(strong.sum()), "n_negative": int(neg.sum()),
         "cnn_recall": float(hit[strong].mean()) if strong.any() else None,
         "boxcar_recall": float(meta["boxcar_hit"][strong].mean()) if strong.any() else None,
