@@ -320,3 +320,33 @@ def test_loss_weights(sps, case):
     gmag = np.abs(gh).sum(axis=(0, 2, 3))
     ncell = n * cnn.GRID_DM * cnn.GRID_T
     assert np.all(np.abs(grads["bh"] - gh.sum(axis=(0, 2, 3))) <= (2 * ncell * U + 1e-5) * gmag)
+
+
+def test_forward_full_batch_sampled_tiles(sps):
+    # the benchmark's batch of 256 tiles; two sampled tiles checked layer by
+    # layer on the GPU's own inputs (the rounding bound of the layer-local test)
+    params = cnn.init_params(41)
+    n = 256
+    tb, _ = _tiles(n, 42, positive=(5, 200))
+    with sps.sps_cnn_create(n) as net:
+        sps.sps_cnn_set_params(net, _flat(params))
+        head = torch.zeros((n, 3, 8, 16), dtype=torch.float32, device="cuda")
+        sps.sps_cnn_forward(net, _to_dev_tiles(tb), n, head)
+        torch.cuda.synchronize()
+        acts = [_nchw(sps.sps_cnn_activations(net, li, n)) for li in range(len(cnn.LAYERS))]
+        h = head.cpu().numpy().astype(np.float64)
+    for k in (5, 255):
+        prev = tb[k:k + 1, None]
+        for li, (ci, co, stride) in enumerate(cnn.LAYERS):
+            w = cnn.bf16(params[f"w{li}"])
+            b = params[f"b{li}"].astype(np.float64)
+            z = cnn.conv3x3(prev, w, b, stride)
+            mag = cnn.conv3x3(np.abs(prev), np.abs(w), np.abs(b), stride)
+            g = acts[li][k:k + 1]
+            ok = _justified_relu(g, z, 2 * (9 * ci + 1) * U * mag)
+            assert ok.all(), (k, li, int((~ok).sum()))
+            prev = g
+        wh, bh = params["wh"].astype(np.float64), params["bh"].astype(np.float64)
+        ref = np.einsum("kc,nchw->nkhw", wh, prev) + bh[None, :, None, None]
+        mag = np.einsum("kc,nchw->nkhw", np.abs(wh), np.abs(prev)) + np.abs(bh)[None, :, None, None]
+        assert np.all(np.abs(h[k:k + 1] - ref) <= 2 * 129 * U * mag + 1e-30), k
