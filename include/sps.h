@@ -320,12 +320,14 @@ sps_status sps_server_stream_info(sps_server server, int32_t stream_id, int64_t 
 
 /* Searches the stream's next chunk now, on worker 0, and waits for it.
  * host: [nchan][src_pitch] bytes, first chunk_len of each row used (pinned
- * memory with src_pitch == chunk_len takes the fast linear upload).  Y_copy (optional): device [ndm][chunk_len] that receives
- * the dedispersed plane.  out/cap/n_found and TRUNCATED as in sps_detect.
- * Must not overlap sps_server_run. */
+ * memory with src_pitch == chunk_len takes the fast linear upload).  Y_copy
+ * (optional): device [ndm][chunk_len] that receives the dedispersed plane.
+ * out/cap/n_found and TRUNCATED as in sps_detect.  n_cnn (optional, host)
+ * receives the attached detector's count (sps_server_set_detector; 0 without
+ * one).  Must not overlap sps_server_run. */
 sps_status sps_server_push(sps_server server, int32_t stream_id, const uint8_t *host,
                            int64_t src_pitch, uint32_t *Y_copy, sps_candidate *out, int32_t cap,
-                           int32_t *n_found);
+                           int32_t *n_found, int32_t *n_cnn);
 
 /* Source of a stream's chunks in sps_server_run: nsrc chunks of
  * [nchan][src_pitch] bytes back to back at host; chunk k of the run reads
@@ -349,6 +351,8 @@ typedef struct {
   double end_s;     /* candidates on the host */
   int32_t n_cand;   /* candidates found (true count) */
   int32_t status;   /* sps_status of the chunk */
+  int32_t n_cnn;    /* cells the attached detector flagged (0 without one) */
+  int32_t reserved;
 } sps_chunk_record;
 
 /* Serves every admitted stream for run_s seconds of wall clock: stream i's
@@ -425,6 +429,26 @@ sps_status sps_cnn_signals(sps_cnn net, int32_t layer, int32_t n, uint16_t *host
  * tiles (device uint16 [ndm/2][nout/8]); only full windows.  Asynchronous. */
 sps_status sps_cnn_pool_tiles(const float *snr, int64_t pitch, int32_t ndm, int64_t nout,
                               float scale, uint16_t *tiles, void *stream);
+/* The whole plane cut into tiles (tile (i, j): trials [512 i, 512 i + 512),
+ * samples [4096 j, 4096 j + 4096), pooled as sps_cnn_pool_tiles), written back
+ * to back in row-major tile order to tiles (device; may be NULL when the count
+ * is 0).  *ntiles = (ndm / 512) (nout / 4096): only whole tiles.
+ * Asynchronous. */
+sps_status sps_cnn_pool_tile_grid(const float *snr, int64_t pitch, int32_t ndm, int64_t nout,
+                                  float scale, uint16_t *tiles, int64_t *ntiles, void *stream);
+/* The batch size the network was created for (0 for NULL). */
+int32_t sps_cnn_max_batch(sps_cnn net);
+
+/* Attaches the learned detector (NULL detaches): after the boxcar S/N, every
+ * chunk's plane is cut into whole tiles (sps_cnn_pool_tile_grid with scale)
+ * and run through net; the number of cells with probability >= threshold is
+ * reported (n_cnn of push and of the chunk records).  The tile buffer counts
+ * against the budget (NOMEM if it does not fit).  The server uses net only
+ * while it holds its compute lock; net must outlive the attachment and must
+ * not be used elsewhere meanwhile.  Must not overlap sps_server_run or
+ * sps_server_push. */
+sps_status sps_server_set_detector(sps_server server, sps_cnn net, float threshold, float scale);
+
 /* Forward pass of n tiles (device, 16-byte aligned); head (optional, device
  * FP32 [n][3][8][16]) receives the head outputs.  Asynchronous. */
 sps_status sps_cnn_forward(sps_cnn net, const uint16_t *tiles, int32_t n, float *head,

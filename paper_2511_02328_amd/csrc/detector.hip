@@ -92,6 +92,45 @@ __global__ __launch_bounds__(256) void pool_tiles_kernel(const float *__restrict
   out[idx] = f2bf(m * scale);
 }
 
+// A whole plane cut into tiles: tile (ti, tj) covers trials
+// [512 ti, 512 ti + 512) and samples [4096 tj, 4096 tj + 4096); tiles are
+// written back to back in row-major tile order.  Only whole tiles.
+__global__ __launch_bounds__(256) void pool_tile_grid_kernel(const float *__restrict__ snr,
+                                                             int64_t pitch, int ncols,
+                                                             int64_t ntiles, float scale,
+                                                             uint16_t *__restrict__ out) {
+  constexpr int64_t kTilePix = (int64_t)kTileDm * kTileT;
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= ntiles * kTilePix) return;
+  const int64_t tile = idx / kTilePix;
+  const int pix = (int)(idx - tile * kTilePix);
+  const int i = pix / kTileT, j = pix % kTileT;
+  const int64_t ti = tile / ncols, tj = tile - ti * ncols;
+  const int64_t r0 = ti * (kTileDm * kPoolDm) + (int64_t)i * kPoolDm;
+  const int64_t c0 = tj * (kTileT * kPoolT) + (int64_t)j * kPoolT;
+  float m = -INFINITY;
+  for (int a = 0; a < kPoolDm; ++a) {
+    const float *row = snr + (r0 + a) * pitch + c0;
+    for (int b = 0; b < kPoolT; ++b) m = fmaxf(m, row[b]);
+  }
+  out[idx] = f2bf(m * scale);
+}
+
+// Adds to *count the number of cells among n tiles whose objectness logit
+// (head channel 0) is at least logit; one atomic per wave.
+__global__ __launch_bounds__(256) void count_cells_kernel(const float *__restrict__ head, int32_t n,
+                                                          float logit, int32_t *count) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  bool hit = false;
+  if (i < (int64_t)n * kCells) {
+    const int64_t t = i / kCells;
+    const int cell = (int)(i - t * kCells);
+    hit = head[t * kHead * kCells + cell] >= logit;
+  }
+  const unsigned long long b = __ballot(hit);
+  if ((threadIdx.x & 63) == 0 && b) atomicAdd(count, (int32_t)__popcll(b));
+}
+
 // ---------------------------------------------------------------------------
 // Forward
 // ---------------------------------------------------------------------------
@@ -994,6 +1033,27 @@ sps_status sps_cnn_pool_tiles(const float *snr, int64_t pitch, int32_t ndm, int6
   return SPS_OK;
 }
 
+sps_status sps_cnn_pool_tile_grid(const float *snr, int64_t pitch, int32_t ndm, int64_t nout,
+                                  float scale, uint16_t *tiles, int64_t *ntiles, void *stream) {
+  if (!snr || !ntiles) return sps::set_error(SPS_ERR_INVALID_ARG, "NULL plane or count");
+  if (ndm < 0 || nout < 0 || pitch < nout)
+    return sps::set_error(SPS_ERR_INVALID_ARG, "bad plane shape");
+  const int64_t nrows = ndm / (kTileDm * kPoolDm), ncols = nout / (kTileT * kPoolT);
+  *ntiles = nrows * ncols;
+  if (*ntiles == 0) return SPS_OK;
+  if (!tiles) return sps::set_error(SPS_ERR_INVALID_ARG, "NULL tiles");
+  const int64_t total = *ntiles * kTileDm * kTileT;
+  if ((total + 255) / 256 > 0x7FFFFFFF || ncols > 0x7FFFFFFF)
+    return sps::set_error(SPS_ERR_RANGE, "plane too large");
+  hipLaunchKernelGGL(pool_tile_grid_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
+                     (hipStream_t)stream, snr, pitch, (int)ncols, *ntiles, scale, tiles);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return cnn_dev_fail(e, "tile-grid pooling launch");
+  return SPS_OK;
+}
+
+int32_t sps_cnn_max_batch(sps_cnn c) { return c ? c->max_batch : 0; }
+
 sps_status sps_cnn_forward(sps_cnn c, const uint16_t *tiles, int32_t n, float *head,
                            void *stream) {
   sps_status r = check_batch(c, tiles, n);
@@ -1090,3 +1150,28 @@ sps_status sps_cnn_detect(sps_cnn c, const uint16_t *tiles, int32_t n, float thr
 }
 
 }  // extern "C"
+
+namespace sps {
+
+sps_status cnn_count_cells(sps_cnn c, const uint16_t *tiles, int32_t n, float threshold,
+                           int32_t *count, hipStream_t s) {
+  sps_status r = check_batch(c, tiles, n);
+  if (r != SPS_OK) return r;
+  if (!count) return set_error(SPS_ERR_INVALID_ARG, "NULL count");
+  if (!(threshold > 0.0f && threshold < 1.0f))
+    return set_error(SPS_ERR_INVALID_ARG, "threshold must be a probability in (0, 1)");
+  r = run_forward(c, tiles, n, s);
+  if (r != SPS_OK) return r;
+  r = run_head(c, nullptr, n, false, s);
+  if (r != SPS_OK) return r;
+  // the same FP32 logit and comparison as sps_cnn_detect, so counts agree
+  const float logit = logf(threshold / (1.0f - threshold));
+  const int64_t cells = (int64_t)n * kCells;
+  hipLaunchKernelGGL(count_cells_kernel, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, s,
+                     c->head, n, logit, count);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return cnn_dev_fail(e, "cell count launch");
+  return SPS_OK;
+}
+
+}  // namespace sps

@@ -21,7 +21,8 @@
 // in sequence), each on its own HIP stream with its own output planes and
 // plans: host-to-device copy into its staging buffer, then, holding the
 // server's compute lock, staging -> ring, dedispersion, statistics + boxcar
-// S/N, overlap moved to the front of the ring and detection.  A chunk's latency is its completion time
+// S/N, the learned detector on the S/N plane (if one is attached), overlap
+// moved to the front of the ring and detection.  A chunk's latency is its completion time
 // minus its arrival time.
 #include <stdio.h>
 #include <string.h>
@@ -71,6 +72,8 @@ struct Worker {
   int32_t *stats = nullptr;
   int64_t cap = 0;              // elements of each plane
   int64_t stats_cap = 0;        // rows of the statistics array
+  int32_t *d_cnn = nullptr;     // device count of the detector's flagged cells
+  int32_t *h_cnn = nullptr;     // pinned host copy of it
   std::vector<sps_plan> plans;  // one per observing set-up
 };
 
@@ -150,6 +153,12 @@ struct sps_server_s {
   // concurrent launches from several workers would interleave away.  Uploads
   // run outside the lock, so one worker's copy overlaps another's search.
   std::mutex compute;
+  // optional learned detector run on every chunk's S/N plane (under the
+  // compute lock, so one network and one tile buffer serve every worker)
+  sps_cnn detector = nullptr;
+  float det_threshold = 0.9f, det_scale = 0.125f;
+  uint16_t *tiles = nullptr;
+  int64_t tiles_cap = 0;  // tiles
   std::vector<SetupKey> setups;
   std::vector<int64_t> setup_delay;  // D_max per set-up
   std::vector<StreamState> streams;
@@ -195,10 +204,52 @@ sps_status grow_planes(sps_server s, int64_t elems, int64_t rows) {
   return SPS_OK;
 }
 
+constexpr int64_t kTileBytes = 256 * 512 * 2;  // one bfloat16 detector tile
+
+int64_t grid_tiles(int ndm, int64_t chunk) { return (int64_t)(ndm / 512) * (chunk / 4096); }
+
+// Grows the shared detector tile buffer to hold n tiles.
+sps_status grow_tiles(sps_server s, int64_t n) {
+  if (s->tiles_cap >= n) return SPS_OK;
+  if (s->tiles) (void)hipFree(s->tiles);
+  s->tiles = nullptr;
+  s->tiles_cap = 0;
+  if (hipMalloc(&s->tiles, (size_t)(n * kTileBytes)) != hipSuccess) {
+    (void)hipGetLastError();
+    return sps::set_error(SPS_ERR_NOMEM, "device allocation of detector tiles failed");
+  }
+  s->tiles_cap = n;
+  return SPS_OK;
+}
+
+// Runs the attached detector on the S/N plane of worker w: the plane cut
+// into whole tiles, the network over them in batches, the cells at or above
+// the threshold counted on the device and the count copied to w.h_cnn.
+// Asynchronous on the worker's stream: no host round trip per batch.
+sps_status run_detector(sps_server s, Worker &w, const StreamState &st) {
+  hipError_t e = hipMemsetAsync(w.d_cnn, 0, sizeof(int32_t), w.stream);
+  if (e != hipSuccess) return dev_fail(e, "detector count reset");
+  int64_t nt = 0;
+  sps_status r = sps_cnn_pool_tile_grid(w.snr, st.chunk, st.ndm, st.chunk, s->det_scale, s->tiles,
+                                        &nt, w.stream);
+  if (r != SPS_OK) return r;
+  const int32_t mb = sps_cnn_max_batch(s->detector);
+  for (int64_t b0 = 0; b0 < nt; b0 += mb) {
+    const int32_t nb = (int32_t)(nt - b0 < mb ? nt - b0 : mb);
+    r = sps::cnn_count_cells(s->detector, s->tiles + b0 * (kTileBytes / 2), nb, s->det_threshold,
+                             w.d_cnn, w.stream);
+    if (r != SPS_OK) return r;
+  }
+  e = hipMemcpyAsync(w.h_cnn, w.d_cnn, sizeof(int32_t), hipMemcpyDeviceToHost, w.stream);
+  if (e != hipSuccess) return dev_fail(e, "detector count copy");
+  return SPS_OK;
+}
+
 // Searches the next chunk of stream sid on worker w.  src: host
 // [nchan][src_pitch].  Y_copy (optional, device [ndm][chunk]) receives the
-// dedispersed plane; out/cap/n_found as in sps_detect.  Synchronises the
-// worker's stream.
+// dedispersed plane; out/cap/n_found as in sps_detect; n_cnn receives the
+// attached detector's count (0 without one).  Synchronises the worker's
+// stream.
 // Wall-clock marks of one chunk's phases (seconds on the caller's clock).
 struct Marks {
   std::chrono::steady_clock::time_point uploaded, locked;
@@ -206,11 +257,12 @@ struct Marks {
 
 sps_status process_chunk(sps_server s, Worker &w, int sid, const uint8_t *src, int64_t src_pitch,
                          uint32_t *Y_copy, sps_candidate *out, int32_t cap, int32_t *n_found,
-                         Marks *marks = nullptr) {
+                         int32_t *n_cnn, Marks *marks = nullptr) {
   StreamState &st = s->streams[(size_t)sid];
   sps_plan plan = w.plans[(size_t)st.setup];
   hipStream_t hs = w.stream;
   *n_found = 0;
+  *n_cnn = 0;
   const int64_t bytes = st.chunk * (int64_t)st.nchan;
   if (bytes > w.staging_cap) return sps::set_error(SPS_ERR_RANGE, "chunk exceeds the staging buffer");
   // Upload to the contiguous staging buffer: one linear copy (a DMA engine,
@@ -238,6 +290,11 @@ sps_status process_chunk(sps_server s, Worker &w, int sid, const uint8_t *src, i
   r = sps_boxcar_snr(plan, w.Y, st.chunk, st.widths.data(), (int32_t)st.widths.size(), w.snr,
                      w.best, w.stats, hs);
   if (r != SPS_OK) return r;
+  const bool learned = s->detector != nullptr;
+  if (learned) {
+    r = run_detector(s, w, st);
+    if (r != SPS_OK) return r;
+  }
   // The last D_max samples move to the front of the ring, in pieces no
   // longer than the chunk, so that no piece's source overlaps its
   // destination; in stream order every piece reads its source before a
@@ -247,8 +304,14 @@ sps_status process_chunk(sps_server s, Worker &w, int sid, const uint8_t *src, i
     e = copy_rows(st.ring, st.pitch, st.chunk + off, st.ring, st.pitch, off, len, st.nchan, hs);
     if (e != hipSuccess) return dev_fail(e, "overlap move");
   }
-  return sps_detect(plan, w.snr, w.best, st.chunk, st.widths.data(), (int32_t)st.widths.size(),
-                    &st.det, out, cap, n_found, hs);
+  r = sps_detect(plan, w.snr, w.best, st.chunk, st.widths.data(), (int32_t)st.widths.size(),
+                 &st.det, out, cap, n_found, hs);
+  if (learned && (r == SPS_OK || r == SPS_ERR_TRUNCATED)) {
+    e = hipStreamSynchronize(hs);  // normally idle already: detection waits for its outputs
+    if (e != hipSuccess) return dev_fail(e, "detector count");
+    *n_cnn = *w.h_cnn;
+  }
+  return r;
 }
 
 }  // namespace
@@ -271,9 +334,11 @@ sps_status sps_server_create(int64_t hbm_budget, int32_t nworkers, sps_server *o
   s->workers.resize((size_t)nworkers);
   for (Worker &w : s->workers) {
     e = hipStreamCreateWithFlags(&w.stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipMalloc(&w.d_cnn, sizeof(int32_t));
+    if (e == hipSuccess) e = hipHostMalloc(&w.h_cnn, sizeof(int32_t), hipHostMallocDefault);
     if (e != hipSuccess) {
       (void)sps_server_destroy(s);
-      return dev_fail(e, "stream creation");
+      return dev_fail(e, "worker set-up");
     }
   }
   *out = s;
@@ -288,11 +353,34 @@ sps_status sps_server_destroy(sps_server s) {
     for (sps_plan p : w.plans) sps_plan_destroy(p);
     free_planes(w);
     if (w.staging) (void)hipFree(w.staging);
+    if (w.d_cnn) (void)hipFree(w.d_cnn);
+    if (w.h_cnn) (void)hipHostFree(w.h_cnn);
     if (w.stream) (void)hipStreamDestroy(w.stream);
   }
   for (StreamState &st : s->streams)
     if (st.ring) (void)hipFree(st.ring);
+  if (s->tiles) (void)hipFree(s->tiles);
   delete s;
+  return SPS_OK;
+}
+
+sps_status sps_server_set_detector(sps_server s, sps_cnn net, float threshold, float scale) {
+  if (!s) return sps::set_error(SPS_ERR_INVALID_ARG, "NULL server");
+  if (net && (!(threshold > 0.0f && threshold < 1.0f) || !(scale > 0.0f)))
+    return sps::set_error(SPS_ERR_INVALID_ARG, "need 0 < threshold < 1 and scale > 0");
+  if (net) {
+    int64_t need = 0;
+    for (const StreamState &st : s->streams) need = std::max(need, grid_tiles(st.ndm, st.chunk));
+    const int64_t grow = std::max<int64_t>(0, need - s->tiles_cap) * kTileBytes;
+    if (s->used + grow > s->budget)
+      return sps::set_error(SPS_ERR_NOMEM, "refused: detector tiles do not fit the budget");
+    const sps_status r = grow_tiles(s, need);
+    if (r != SPS_OK) return r;
+    s->used += grow;
+  }
+  s->detector = net;
+  s->det_threshold = threshold;
+  s->det_scale = scale;
   return SPS_OK;
 }
 
@@ -357,7 +445,10 @@ sps_status sps_server_add_stream(sps_server s, const sps_obs_desc *desc, const i
   const int64_t plans = new_setup ? (int64_t)s->workers.size() *
                                         plan_bytes(desc->ndm, desc->nchan, chunk_len, *det)
                                   : 0;
-  const int64_t need = ring + grow + plans;
+  const int64_t tile_grow =
+      s->detector ? std::max<int64_t>(0, grid_tiles(desc->ndm, chunk_len) - s->tiles_cap) * kTileBytes
+                  : 0;
+  const int64_t need = ring + grow + plans + tile_grow;
   if (s->used + need > s->budget) {
     drop();
     char m[192];
@@ -367,6 +458,7 @@ sps_status sps_server_add_stream(sps_server s, const sps_obs_desc *desc, const i
   }
   sps_status r = grow_planes(s, elems, desc->ndm);
   if (r == SPS_OK) r = grow_staging(s, stage);
+  if (r == SPS_OK && s->detector) r = grow_tiles(s, grid_tiles(desc->ndm, chunk_len));
   if (r != SPS_OK) {
     drop();
     return r;
@@ -421,7 +513,8 @@ sps_status sps_server_stream_info(sps_server s, int32_t stream_id, int64_t *chun
 }
 
 sps_status sps_server_push(sps_server s, int32_t stream_id, const uint8_t *host, int64_t src_pitch,
-                           uint32_t *Y_copy, sps_candidate *out, int32_t cap, int32_t *n_found) {
+                           uint32_t *Y_copy, sps_candidate *out, int32_t cap, int32_t *n_found,
+                           int32_t *n_cnn) {
   if (!s || !host || !n_found) return sps::set_error(SPS_ERR_INVALID_ARG, "NULL argument");
   if (stream_id < 0 || stream_id >= (int32_t)s->streams.size())
     return sps::set_error(SPS_ERR_INVALID_ARG, "bad stream id");
@@ -430,8 +523,10 @@ sps_status sps_server_push(sps_server s, int32_t stream_id, const uint8_t *host,
   if (cap < 0 || (cap > 0 && !out)) return sps::set_error(SPS_ERR_INVALID_ARG, "bad output array");
   hipError_t e = hipSetDevice(s->device);
   if (e != hipSuccess) return dev_fail(e, "hipSetDevice");
-  const sps_status r =
-      process_chunk(s, s->workers[0], stream_id, host, src_pitch, Y_copy, out, cap, n_found);
+  int32_t ncnn = 0;
+  const sps_status r = process_chunk(s, s->workers[0], stream_id, host, src_pitch, Y_copy, out,
+                                     cap, n_found, &ncnn);
+  if (n_cnn) *n_cnn = ncnn;
   if (r == SPS_OK || r == SPS_ERR_TRUNCATED) st.next_chunk += 1;
   return r;
 }
@@ -515,11 +610,11 @@ sps_status sps_server_run(sps_server s, const sps_feed *feeds, double run_s, dou
       const StreamState &st = s->streams[(size_t)job.stream];
       const int64_t src_idx = (f.first + job.index) % f.nsrc;
       const uint8_t *src = f.host + (size_t)src_idx * (size_t)st.nchan * (size_t)f.src_pitch;
-      int32_t nc = 0;
+      int32_t nc = 0, ncnn = 0;
       Marks mk;
       mk.uploaded = mk.locked = std::chrono::steady_clock::now();
-      sps_status r =
-          process_chunk(s, w, job.stream, src, f.src_pitch, nullptr, nullptr, 0, &nc, &mk);
+      sps_status r = process_chunk(s, w, job.stream, src, f.src_pitch, nullptr, nullptr, 0, &nc,
+                                   &ncnn, &mk);
       if (r == SPS_ERR_TRUNCATED) r = SPS_OK;  // only the count is kept
       const double end = now_s();
       const double up = std::chrono::duration<double>(mk.uploaded - t0).count();
@@ -533,7 +628,8 @@ sps_status sps_server_run(sps_server s, const sps_feed *feeds, double run_s, dou
           err = r;
           err_msg = sps_last_error();
         }
-        recs.push_back({job.stream, wi, job.index, job.t, start, up, lk_s, end, nc, (int32_t)r});
+        recs.push_back({job.stream, wi, job.index, job.t, start, up, lk_s, end, nc, (int32_t)r,
+                        ncnn, 0});
       }
       cv.notify_all();
     }

@@ -127,4 +127,10 @@ hipError_t launch_detect_batch(const BeamWork *beams, int nbeams, int ndm, int64
                                int64_t nms_t, TilePeak *peaks, TilePeak *out, int32_t *status,
                                hipStream_t stream);
 
+// Forward pass of n tiles (device) through net; adds to *count (device int32)
+// the number of cells whose objectness probability is >= threshold, decided
+// exactly as sps_cnn_detect decides it.  Asynchronous on s.
+sps_status cnn_count_cells(sps_cnn net, const uint16_t *tiles, int32_t n, float threshold,
+                           int32_t *count, hipStream_t s);
+
 }  // namespace sps

@@ -73,7 +73,8 @@ class sps_chunk_record(ctypes.Structure):
     _fields_ = [("stream", ctypes.c_int32), ("worker", ctypes.c_int32), ("index", ctypes.c_int64),
                 ("arrival_s", ctypes.c_double), ("start_s", ctypes.c_double),
                 ("upload_s", ctypes.c_double), ("compute_s", ctypes.c_double),
-                ("end_s", ctypes.c_double), ("n_cand", ctypes.c_int32), ("status", ctypes.c_int32)]
+                ("end_s", ctypes.c_double), ("n_cand", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("n_cnn", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class sps_cnn_candidate(ctypes.Structure):
@@ -126,7 +127,8 @@ def library() -> ctypes.CDLL:
         lib.sps_server_stream_info.argtypes = [P, i32, ctypes.POINTER(i64), ctypes.POINTER(i64),
                                                ctypes.POINTER(ctypes.c_double)]
         lib.sps_server_push.argtypes = [P, i32, P, i64, P, ctypes.POINTER(sps_candidate), i32,
-                                        ctypes.POINTER(i32)]
+                                        ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        lib.sps_server_set_detector.argtypes = [P, P, ctypes.c_float, ctypes.c_float]
         lib.sps_server_run.argtypes = [P, ctypes.POINTER(sps_feed), ctypes.c_double,
                                        ctypes.c_double, ctypes.POINTER(sps_chunk_record), i32,
                                        ctypes.POINTER(i32)]
@@ -141,6 +143,10 @@ def library() -> ctypes.CDLL:
         lib.sps_cnn_set_loss_weights.argtypes = [P, ctypes.c_float, ctypes.c_float]
         lib.sps_cnn_signals.argtypes = [P, i32, i32, P]
         lib.sps_cnn_pool_tiles.argtypes = [P, i64, i32, i64, ctypes.c_float, P, P]
+        lib.sps_cnn_pool_tile_grid.argtypes = [P, i64, i32, i64, ctypes.c_float, P,
+                                               ctypes.POINTER(i64), P]
+        lib.sps_cnn_max_batch.argtypes = [P]
+        lib.sps_cnn_max_batch.restype = i32
         lib.sps_cnn_forward.argtypes = [P, P, i32, P, P]
         lib.sps_cnn_loss_grad.argtypes = [P, P, P, i32, P, P]
         lib.sps_cnn_adam.argtypes = [P, ctypes.c_float, ctypes.c_float, ctypes.c_float,
@@ -152,12 +158,12 @@ def library() -> ctypes.CDLL:
         for f in ("sps_cnn_create", "sps_cnn_destroy", "sps_cnn_set_params", "sps_cnn_get_params",
                   "sps_cnn_set_grads", "sps_cnn_get_grads", "sps_cnn_activations", "sps_cnn_signals",
                   "sps_cnn_set_loss_weights",
-                  "sps_cnn_pool_tiles", "sps_cnn_forward", "sps_cnn_loss_grad", "sps_cnn_adam",
+                  "sps_cnn_pool_tiles", "sps_cnn_pool_tile_grid", "sps_cnn_forward", "sps_cnn_loss_grad", "sps_cnn_adam",
                   "sps_cnn_train_step", "sps_cnn_detect"):
             getattr(lib, f).restype = ctypes.c_int
         for f in ("sps_server_create", "sps_server_destroy", "sps_server_add_stream",
                   "sps_server_memory", "sps_server_stream_info", "sps_server_push",
-                  "sps_server_run"):
+                  "sps_server_run", "sps_server_set_detector"):
             getattr(lib, f).restype = ctypes.c_int
         for f in ("sps_plan_create", "sps_plan_destroy", "sps_plan_delays", "sps_dedisperse",
                   "sps_boxcar_snr", "sps_detect", "sps_plan_set_tiling", "sps_plan_get_tiling",
@@ -471,6 +477,7 @@ class Server:
     def __init__(self, handle):
         self.handle = handle
         self.widths = {}
+        self.detector = None
 
     def close(self) -> None:
         if self.handle:
@@ -492,7 +499,8 @@ class Server:
 RECORD_DTYPE = np.dtype([("stream", np.int32), ("worker", np.int32), ("index", np.int64),
                          ("arrival_s", np.float64), ("start_s", np.float64),
                          ("upload_s", np.float64), ("compute_s", np.float64),
-                         ("end_s", np.float64), ("n_cand", np.int32), ("status", np.int32)])
+                         ("end_s", np.float64), ("n_cand", np.int32), ("status", np.int32),
+                         ("n_cnn", np.int32), ("reserved", np.int32)])
 
 
 def sps_server_create(hbm_budget: int, nworkers: int) -> Server:
@@ -553,23 +561,34 @@ def _host_ptr(a, name: str):
 
 
 def sps_server_push(server: Server, stream_id: int, chunk, Y_copy: Optional[torch.Tensor] = None,
-                    cap: int = 4096, allow_truncated: bool = False):
+                    cap: int = 4096, allow_truncated: bool = False, with_cnn: bool = False):
     """Searches the stream's next chunk (host uint8 [nchan][>= chunk_len]); returns
-    (candidates, number found)."""
+    (candidates, number found), plus the attached detector's count if with_cnn."""
     hp, pitch = _host_ptr(chunk, "chunk")
     yp = None
     if Y_copy is not None:
         yp = (_dev(Y_copy, torch.int32, "Y_copy") if Y_copy.dtype == torch.int32
               else _dev(Y_copy, torch.uint32, "Y_copy"))
     out = (sps_candidate * max(cap, 1))()
-    n = ctypes.c_int32()
+    n, ncnn = ctypes.c_int32(), ctypes.c_int32()
     rc = library().sps_server_push(server.handle, int(stream_id), hp, int(pitch), yp, out,
-                                   int(cap), ctypes.byref(n))
+                                   int(cap), ctypes.byref(n), ctypes.byref(ncnn))
     if not (rc == 6 and allow_truncated):
         _check(rc, "sps_server_push")
     k = min(int(n.value), cap)
     arr = np.frombuffer(bytes(out)[:k * ctypes.sizeof(sps_candidate)], dtype=CANDIDATE_DTYPE).copy()
+    if with_cnn:
+        return arr, int(n.value), int(ncnn.value)
     return arr, int(n.value)
+
+
+def sps_server_set_detector(server: Server, net, threshold: float = 0.9,
+                            scale: float = 0.125) -> None:
+    """Attaches net (a Cnn, or None to detach) to every chunk the server searches."""
+    _check(library().sps_server_set_detector(server.handle, net.handle if net else None,
+                                             float(threshold), float(scale)),
+           "sps_server_set_detector")
+    server.detector = net  # keeps the network alive while attached
 
 
 def sps_server_run(server: Server, feeds: Sequence[dict], run_s: float, compression: float,
@@ -706,6 +725,33 @@ def sps_cnn_pool_tiles(snr: torch.Tensor, nout: int, scale: float, tiles: torch.
     _check(library().sps_cnn_pool_tiles(_dev(snr, torch.float32, "snr"), snr.stride(0),
                                         snr.shape[0], int(nout), float(scale), tiles.data_ptr(),
                                         _stream(stream)), "sps_cnn_pool_tiles")
+
+
+def sps_cnn_pool_tile_grid(snr: torch.Tensor, nout: int, scale: float,
+                           tiles: Optional[torch.Tensor], stream=None) -> int:
+    """Cuts the plane into whole 512-trial x 4096-sample tiles, pooled; returns
+    their number."""
+    if snr.dim() != 2 or snr.stride(1) != 1:
+        raise ValueError("snr must be [ndm][pitch] with unit stride")
+    need = (snr.shape[0] // 512) * (int(nout) // 4096)
+    tp = None
+    if tiles is not None:
+        if (tiles.dtype not in (torch.uint16, torch.int16, torch.bfloat16)
+                or not tiles.is_contiguous() or tiles.numel() < need * 256 * 512):
+            raise TypeError("tiles must be a contiguous 16-bit tensor of >= n x 256 x 512")
+        tp = tiles.data_ptr()
+    elif need:
+        raise TypeError("tiles needed for a plane of whole tiles")
+    nt = ctypes.c_int64()
+    _check(library().sps_cnn_pool_tile_grid(_dev(snr, torch.float32, "snr"), snr.stride(0),
+                                            snr.shape[0], int(nout), float(scale), tp,
+                                            ctypes.byref(nt), _stream(stream)),
+           "sps_cnn_pool_tile_grid")
+    return int(nt.value)
+
+
+def sps_cnn_max_batch(net: Cnn) -> int:
+    return int(library().sps_cnn_max_batch(net.handle))
 
 
 def sps_cnn_forward(net: Cnn, tiles: torch.Tensor, n: int, head: Optional[torch.Tensor] = None,

@@ -75,6 +75,27 @@ def test_pool_tiles_bitexact(sps):
         assert np.array_equal(got, want), (nd, nt)
 
 
+def test_pool_tile_grid_bitexact(sps):
+    # a plane of 2 x 2 whole tiles plus ragged trials and samples: tile (i, j)
+    # is the oracle's pooling of trials [512 i, +512), samples [4096 j, +4096)
+    rng = np.random.Generator(np.random.PCG64(5))
+    nd, nt, pitch = 1100, 9000, 9216
+    snr = rng.normal(0, 3, (nd, pitch)).astype(np.float32)
+    s = torch.from_numpy(snr).cuda()
+    out = torch.zeros((5, cnn.TILE_DM, cnn.TILE_T), dtype=torch.int16, device="cuda")
+    n = sps.sps_cnn_pool_tile_grid(s, nt, 0.125, out)
+    torch.cuda.synchronize()
+    assert n == 4
+    got = cnn.from_bf16_bits(out.cpu().numpy().view(np.uint16))
+    for k in range(4):
+        i, j = divmod(k, 2)
+        want = cnn.pool_tiles(snr[512 * i:512 * (i + 1), 4096 * j:4096 * (j + 1)], 0.125)
+        assert np.array_equal(got[k], want), k
+    assert np.all(got[4] == 0)  # nothing written past the whole tiles
+    assert sps.sps_cnn_pool_tile_grid(s[:511], nt, 0.125, None) == 0
+    assert sps.sps_cnn_pool_tile_grid(s, 4095, 0.125, None) == 0
+
+
 @pytest.fixture(scope="module")
 def case(sps):
     params = cnn.init_params(11)

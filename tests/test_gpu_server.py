@@ -2,7 +2,9 @@
 dispersion overlap kept on the device must equal the oracle's search of the
 whole concatenated series (bit-exact dedispersion, candidates as in the
 single-call path), admission must respect the memory budget, and a timed run
-must search every scheduled chunk in order."""
+must search every scheduled chunk in order.  With the learned detector
+attached, each chunk's count of flagged cells must equal the network run
+directly on the same S/N plane."""
 import numpy as np
 import pytest
 
@@ -165,3 +167,84 @@ def test_timed_run_then_continue(sps):
             info = sps.sps_server_stream_info(server, sid)
             ref = _oracle_chunk(wl, full, info["overlap"], nrun, L)
             _check_chunk(Y.cpu().numpy().view(np.uint32), cands, n, ref, wl.widths)
+
+
+def _net(sps, max_batch, seed):
+    from paper_2511_02328_amd import detector
+    p = detector.init_params(seed)
+    p[-3] = 0.0  # objectness bias 0: a fair share of cells near the threshold
+    net = sps.sps_cnn_create(max_batch)
+    sps.sps_cnn_set_params(net, p)
+    return net, p
+
+
+def test_detector_in_server(sps):
+    # 1024 trials x 8192 samples per chunk = 2 x 2 tiles; the server's network
+    # takes 3 tiles a batch, so each chunk needs two batches
+    wl = _wl(64, 1024, 400.0, 196.608e-6, 41)
+    L, nchunks, thr = 8192, 3, 0.6
+    Xs = _series(wl, nchunks, L)
+    net, p = _net(sps, 3, 7)
+    ref_net = sps.sps_cnn_create(4)
+    sps.sps_cnn_set_params(ref_net, p)
+    plan = sps.plan_for(wl)
+    with sps.sps_server_create(8 << 30, 1) as server:
+        sid = _add(sps, server, wl, L)
+        before = sps.sps_server_memory(server)["used"]
+        sps.sps_server_set_detector(server, net, thr)
+        assert sps.sps_server_memory(server)["used"] == before + 4 * 256 * 512 * 2
+        counts = []
+        for k in range(nchunks):
+            Y = torch.zeros((wl.ndm, L), dtype=torch.int32, device="cuda")
+            host = np.ascontiguousarray(Xs[:, k * L:(k + 1) * L])
+            cands, n, ncnn = sps.sps_server_push(server, sid, host, Y_copy=Y, with_cnn=True)
+            snr = torch.empty((wl.ndm, L), dtype=torch.float32, device="cuda")
+            best = torch.empty((wl.ndm, L), dtype=torch.uint8, device="cuda")
+            st = torch.empty((wl.ndm, 2), dtype=torch.int32, device="cuda")
+            sps.sps_boxcar_snr(plan, Y, L, wl.widths, snr, best, st)
+            tiles = torch.empty((4, 256, 512), dtype=torch.int16, device="cuda")
+            assert sps.sps_cnn_pool_tile_grid(snr, L, 0.125, tiles) == 4
+            _, want = sps.sps_cnn_detect(ref_net, tiles, 4, thr, cap=0, allow_truncated=True)
+            torch.cuda.synchronize()
+            assert ncnn == want, k
+            counts.append(ncnn)
+            info = sps.sps_server_stream_info(server, sid)
+            ref = _oracle_chunk(wl, Xs, info["overlap"], k, L)
+            _check_chunk(Y.cpu().numpy().view(np.uint32), cands, n, ref, wl.widths)
+        assert 0 < sum(counts) < nchunks * 4 * 128
+        # a timed run carries the counts in its records
+        feed = dict(host=torch.from_numpy(np.ascontiguousarray(Xs[:, :L])).pin_memory(), nsrc=1)
+        recs = sps.sps_server_run(server, [feed], 0.5, 4.0)
+        assert len(recs) > 0 and np.all(recs["status"] == 0)
+        assert np.all((recs["n_cnn"] >= 0) & (recs["n_cnn"] <= 4 * 128))
+        sps.sps_server_set_detector(server, None)
+        _, _, ncnn = sps.sps_server_push(server, sid, np.ascontiguousarray(Xs[:, :L]),
+                                         with_cnn=True)
+        assert ncnn == 0
+    net.close()
+    ref_net.close()
+    plan.close()
+
+
+def test_detector_budget(sps):
+    wl = _wl(64, 1024, 400.0, 196.608e-6, 42)
+    with sps.sps_server_create(1 << 40, 1) as probe:
+        _add(sps, probe, wl, 8192)
+        one = sps.sps_server_memory(probe)["used"]
+    net, _ = _net(sps, 2, 8)
+    with sps.sps_server_create(one + 4 * 256 * 512 * 2 - 1, 1) as server:
+        _add(sps, server, wl, 8192)
+        with pytest.raises(sps.SpsError) as e:
+            sps.sps_server_set_detector(server, net, 0.9)
+        assert e.value.name == "SPS_ERR_NOMEM"
+        assert sps.sps_server_memory(server)["used"] == one
+        with pytest.raises(sps.SpsError):
+            sps.sps_server_set_detector(server, net, 1.5)
+    with sps.sps_server_create(one + 4 * 256 * 512 * 2, 1) as server:
+        sps.sps_server_set_detector(server, net, 0.9)   # no streams yet: no tiles
+        assert sps.sps_server_memory(server)["used"] == 0
+        _add(sps, server, wl, 8192)                     # the stream brings its tiles
+        assert sps.sps_server_memory(server)["used"] == one + 4 * 256 * 512 * 2
+        with pytest.raises(sps.SpsError):
+            _add(sps, server, _wl(64, 2048, 400.0, 196.608e-6, 43), 8192)
+    net.close()
