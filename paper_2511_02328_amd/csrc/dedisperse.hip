@@ -23,6 +23,13 @@
 //    u32 accumulators.  Cost: about 3 VALU ops per 8 sample-adds plus one
 //    address add per (trial, channel), against 1 op per add for a plain
 //    byte-extract-and-add loop.
+//  * The delay table is read in a staged form built once per tiling
+//    (stage_delays): per (trial, channel) the LDS dword offset of its window
+//    inside a slab buffer and its perm selector, per (DM block, channel) the
+//    16-aligned first staged sample.  A wave loads a slab's entries with
+//    wide scalar loads and spends two scalar ops per channel on them, so the
+//    scalar unit, which issues at the same rate as the vector unit, stays
+//    well below it.
 //  * Workgroups are dealt to the 8 XCDs round-robin by the hardware; the
 //    logical index is remapped so that each XCD walks a contiguous range with
 //    the DM block fastest, so the workgroups resident on one XCD share most
@@ -36,25 +43,28 @@ __device__ __forceinline__ uint32_t perm_bytes(uint32_t hi, uint32_t lo, uint32_
   return __builtin_amdgcn_perm(hi, lo, sel);
 }
 
-// Selector that takes bytes (r, r+2) of the 8-byte window {hi:lo} into the
-// low bytes of the two u16 halves and zeroes the high bytes; +0x00010001
-// gives bytes (r+1, r+3).
-__device__ __forceinline__ uint32_t even_selector(int off) {
-  const uint32_t r = (uint32_t)off & 3u;
-  return 0x0C000C00u | r | ((r + 2u) << 16);
+// Uniform LDS dword offset of a window: slab buffer base + staged offset,
+// kept opaque so that the compiler forms each lane address with one add
+// instead of holding a register per staged row.
+__device__ __forceinline__ int uniform_offset(int buf_dw, int staged) {
+  int s = buf_dw + staged;
+  asm volatile("" : "+s"(s));
+  return s;
 }
 
-// Adds two channels' windows into the packed accumulators of one trial.  sa,
-// sb: uniform LDS dword offsets of the windows (row base + delay / 4); offa,
-// offb: the byte offsets, whose low two bits pick the perm selectors.
+// Adds two channels' windows into the packed accumulators of one trial.
+// ea, eb: staged entries (LDS dword offset within the slab buffer, selector
+// that takes bytes (r, r+2) of the 8-byte window {hi:lo} into the low bytes
+// of the two u16 halves, r the delay mod 4); + 0x00010001 selects bytes
+// (r+1, r+3).
 template <int M>
 __device__ __forceinline__ void add_pair(uint32_t (&ev)[M], uint32_t (&od)[M],
-                                         const uint32_t *lds32, int lane_m, int sa, int offa,
-                                         int sb, int offb) {
-  const uint32_t sea = even_selector(offa), soa = sea + 0x00010001u;
-  const uint32_t seb = even_selector(offb), sob = seb + 0x00010001u;
-  const uint32_t *pa = lds32 + (lane_m + sa);
-  const uint32_t *pb = lds32 + (lane_m + sb);
+                                         const uint32_t *lds32, int lane_m, int bo, int2 ea,
+                                         int2 eb) {
+  const uint32_t sea = (uint32_t)ea.y, soa = sea + 0x00010001u;
+  const uint32_t seb = (uint32_t)eb.y, sob = seb + 0x00010001u;
+  const uint32_t *pa = lds32 + (lane_m + uniform_offset(bo, ea.x));
+  const uint32_t *pb = lds32 + (lane_m + uniform_offset(bo, eb.x));
   uint32_t wa[M + 1], wb[M + 1];
 #pragma unroll
   for (int j = 0; j <= M; ++j) {
@@ -68,34 +78,22 @@ __device__ __forceinline__ void add_pair(uint32_t (&ev)[M], uint32_t (&od)[M],
   }
 }
 
-template <int M>
-__device__ __forceinline__ void add_one(uint32_t (&ev)[M], uint32_t (&od)[M],
-                                        const uint32_t *lds32, int lane_m, int sa, int offa) {
-  const uint32_t sea = even_selector(offa), soa = sea + 0x00010001u;
-  const uint32_t *pa = lds32 + (lane_m + sa);
-  uint32_t wa[M + 1];
-#pragma unroll
-  for (int j = 0; j <= M; ++j) wa[j] = pa[j];
-#pragma unroll
-  for (int j = 0; j < M; ++j) {
-    ev[j] += perm_bytes(wa[j + 1], wa[j], sea);
-    od[j] += perm_bytes(wa[j + 1], wa[j], soa);
-  }
-}
-
 template <int CS, int NW, int KMAX>
 struct SlabRegs {
   static constexpr int RPW = CS / NW;
   uint4 v[RPW][KMAX];
 };
 
-// Global -> registers for the slab starting at channel c0.  Rows whose whole
-// window lies below nsamp_in take a guard-free path; the others zero-fill
-// every byte at or past nsamp_in.
+// Global -> registers for the slab starting at channel c0; Bb: first staged
+// sample (16-aligned) of each channel's row for this DM block.  Rows whose
+// whole window lies below nsamp_in take a guard-free path; the others
+// zero-fill every byte at or past nsamp_in.  Rows >= ncs (past the last
+// channel) are zero.  The registers are cleared first and loaded in place,
+// so that the loads stay in flight while the current slab is summed.
 template <int CS, int NW, int KMAX>
 __device__ __forceinline__ void slab_load(SlabRegs<CS, NW, KMAX> &st, const uint8_t *__restrict__ X,
                                           int64_t pitch, int64_t nsamp_in,
-                                          const int32_t *__restrict__ Dlo, int c0, int ncs,
+                                          const int32_t *__restrict__ Bb, int c0, int ncs,
                                           int64_t t0, int vpr, int wave, int lane) {
 #pragma unroll
   for (int i = 0; i < SlabRegs<CS, NW, KMAX>::RPW; ++i) {
@@ -103,7 +101,7 @@ __device__ __forceinline__ void slab_load(SlabRegs<CS, NW, KMAX> &st, const uint
 #pragma unroll
     for (int u = 0; u < KMAX; ++u) st.v[i][u] = make_uint4(0u, 0u, 0u, 0u);
     if (r < ncs) {
-      const int64_t base = t0 + (int64_t)(Dlo[c0 + r] & ~15);
+      const int64_t base = t0 + (int64_t)Bb[c0 + r];
       const uint8_t *rowp = X + (int64_t)(c0 + r) * pitch;
       if (base + 16 * (int64_t)vpr <= nsamp_in) {
         const uint4 *src = reinterpret_cast<const uint4 *>(rowp + base);
@@ -139,28 +137,17 @@ __device__ __forceinline__ void slab_load(SlabRegs<CS, NW, KMAX> &st, const uint
 }
 
 template <int CS, int NW, int KMAX>
-__device__ __forceinline__ void slab_store(const SlabRegs<CS, NW, KMAX> &st, uint4 *buf, int ncs,
-                                           int vpr, int wave, int lane) {
+__device__ __forceinline__ void slab_store(const SlabRegs<CS, NW, KMAX> &st, uint4 *buf, int vpr,
+                                           int wave, int lane) {
 #pragma unroll
   for (int i = 0; i < SlabRegs<CS, NW, KMAX>::RPW; ++i) {
     const int r = wave + NW * i;
-    if (r < ncs) {
 #pragma unroll
-      for (int u = 0; u < KMAX; ++u) {
-        const int k = lane + 64 * u;
-        if (k < vpr) buf[r * vpr + k] = st.v[i][u];
-      }
+    for (int u = 0; u < KMAX; ++u) {
+      const int k = lane + 64 * u;
+      if (k < vpr) buf[r * vpr + k] = st.v[i][u];
     }
   }
-}
-
-// Uniform LDS dword offset of a (row, delay) pair, kept opaque so that the
-// compiler forms each lane address with one add instead of holding a
-// register per staged row.
-__device__ __forceinline__ int uniform_offset(int row_base_dw, int off) {
-  int s = row_base_dw + (off >> 2);
-  asm volatile("" : "+s"(s));
-  return s;
 }
 
 // Writes the accumulators of trials dw0 .. dw0 + DPW - 1 at outputs
@@ -189,27 +176,33 @@ __device__ __forceinline__ void store_acc(const uint32_t (&acc)[DPW][M][4], uint
   }
 }
 
-// One workgroup's share: trials [d_lo, d_lo + nw dpw) x outputs
-// [t0, t0 + 256 m) of one filterbank.  With seg > 0 (a multiple of CS) the
-// channels form consecutive groups of seg and group g's partial sums go to
-// plane Y + g seg_stride instead of one total (the first stage of subband
-// dedispersion in one pass over all channels).  Ends with a barrier, so the
-// caller may reuse the LDS buffers right away.
+// One workgroup's share: trials [d_lo, d_lo + nw dpw) of DM block dblk x
+// outputs [t0, t0 + 256 m) of one filterbank.  P (pcols entries per trial,
+// channels padded to a multiple of CS), B: the staged delay table of this
+// tiling.  With seg > 0 (a multiple of CS) the channels form consecutive
+// groups of seg and group g's partial sums go to plane Y + g seg_stride
+// instead of one total (the first stage of subband dedispersion in one pass
+// over all channels).  Ends with a barrier, so the caller may reuse the LDS
+// buffers right away.
+//
+// The channel loop is two nested loops: slabs inside a fold group (at most
+// 256 channels, ending at a segment end), the fold of the u16 halves after
+// each group, so the slab loop carries the packed accumulators without
+// branches.  Padded channels of a last partial slab point at zeroed rows.
 template <int M, int DPW, int NW, int CS, int KMAX, bool SEG = false>
 __device__ __forceinline__ void dedisperse_block(
-    const uint8_t *__restrict__ X, int64_t pitch, int64_t nsamp_in,
-    const int32_t *__restrict__ D, int nchan, int ndm, uint32_t *__restrict__ Y, int64_t nout,
-    int lds_pitch, int vec_store, int64_t t0, int d_lo, uint4 *smem, int seg = 0,
+    const uint8_t *__restrict__ X, int64_t pitch, int64_t nsamp_in, const int2 *__restrict__ P,
+    int pcols, const int32_t *__restrict__ B, int nchan, int ndm, uint32_t *__restrict__ Y,
+    int64_t nout, int lds_pitch, int vec_store, int64_t t0, int dblk, uint4 *smem, int seg = 0,
     int64_t seg_stride = 0) {
   static_assert(M % 2 == 1, "lane stride must be odd for conflict-free LDS reads");
-  static_assert(CS % 2 == 0 && 256 % CS == 0, "slab must be even and divide 256");
+  static_assert(CS % 8 == 0 && 256 % CS == 0, "slab must be a multiple of 8 dividing 256");
   static_assert(CS % NW == 0, "every wave stages the same number of rows");
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int dw0 = d_lo + wave * DPW;
+  const int dw0 = dblk * (NW * DPW) + wave * DPW;
   const int vpr = lds_pitch >> 4;
-  const int row_dw = lds_pitch >> 2;
-  const int buf_dw = CS * row_dw;
+  const int buf_dw = CS * (lds_pitch >> 2);
   const int lane_m = lane * M;
 
   uint32_t acc[DPW][M][4];
@@ -224,69 +217,67 @@ __device__ __forceinline__ void dedisperse_block(
       for (int b = 0; b < 4; ++b) acc[k][j][b] = 0u;
     }
 
-  const int32_t *Dlo = D + (int64_t)d_lo * nchan;
+  // Trials past the last one (a partial DM block) repeat the last trial's
+  // entries, so the channel loop has no per-trial branch; store_acc drops
+  // them.
+  const int2 *Pk[DPW];
+#pragma unroll
+  for (int k = 0; k < DPW; ++k) Pk[k] = P + (int64_t)min(dw0 + k, ndm - 1) * pcols;
+  const int32_t *Bb = B + (int64_t)dblk * nchan;
   const uint32_t *lds32 = reinterpret_cast<const uint32_t *>(smem);
   SlabRegs<CS, NW, KMAX> st;
 
-  slab_load(st, X, pitch, nsamp_in, Dlo, 0, min(CS, nchan), t0, vpr, wave, lane);
-  slab_store(st, smem, min(CS, nchan), vpr, wave, lane);
+  slab_load(st, X, pitch, nsamp_in, Bb, 0, min(CS, nchan), t0, vpr, wave, lane);
+  slab_store(st, smem, vpr, wave, lane);
   __syncthreads();
 
   int parity = 0;
-  for (int c0 = 0; c0 < nchan; c0 += CS) {
-    const int ncs = min(CS, nchan - c0);
-    const int c1 = c0 + CS;
-    const bool more = c1 < nchan;
-    const int ncs1 = more ? min(CS, nchan - c1) : 0;
-    if (more) slab_load(st, X, pitch, nsamp_in, Dlo, c1, ncs1, t0, vpr, wave, lane);
-
-    const int bo = parity * buf_dw;
+#pragma unroll 1
+  for (int g0 = 0; g0 < nchan;) {
+    int g1 = min(nchan, (g0 + 256) & ~255);
+    if constexpr (SEG) g1 = min(g1, (g0 / seg + 1) * seg);
+#pragma unroll 1
+    for (int c0 = g0; c0 < g1; c0 += CS) {
+      const int c1 = c0 + CS;
+      const bool more = c1 < nchan;
+      if (more) slab_load(st, X, pitch, nsamp_in, Bb, c1, min(CS, nchan - c1), t0, vpr, wave, lane);
+      const int bo = parity * buf_dw;
 #pragma unroll
-    for (int k = 0; k < DPW; ++k) {
-      const int d = dw0 + k;
-      if (d < ndm) {
-        const int32_t *Dd = D + (int64_t)d * nchan + c0;
-        if (ncs == CS) {
+      for (int k = 0; k < DPW; ++k) {
+        const int2 *Pc = Pk[k] + c0;
 #pragma unroll
-          for (int r = 0; r < CS; r += 2)
-            add_pair<M>(ev[k], od[k], lds32, lane_m,
-                        uniform_offset(bo + r * row_dw, Dd[r] - (Dlo[c0 + r] & ~15)),
-                        Dd[r] - (Dlo[c0 + r] & ~15),
-                        uniform_offset(bo + (r + 1) * row_dw, Dd[r + 1] - (Dlo[c0 + r + 1] & ~15)),
-                        Dd[r + 1] - (Dlo[c0 + r + 1] & ~15));
-        } else {
-          int r = 0;
-          for (; r + 1 < ncs; r += 2)
-            add_pair<M>(ev[k], od[k], lds32, lane_m,
-                        uniform_offset(bo + r * row_dw, Dd[r] - (Dlo[c0 + r] & ~15)),
-                        Dd[r] - (Dlo[c0 + r] & ~15),
-                        uniform_offset(bo + (r + 1) * row_dw, Dd[r + 1] - (Dlo[c0 + r + 1] & ~15)),
-                        Dd[r + 1] - (Dlo[c0 + r + 1] & ~15));
-          if (r < ncs)
-            add_one<M>(ev[k], od[k], lds32, lane_m,
-                       uniform_offset(bo + r * row_dw, Dd[r] - (Dlo[c0 + r] & ~15)),
-                       Dd[r] - (Dlo[c0 + r] & ~15));
+        for (int r0 = 0; r0 < CS; r0 += 8) {
+          int2 e[8];
+#pragma unroll
+          for (int r = 0; r < 8; ++r) e[r] = Pc[r0 + r];
+#pragma unroll
+          for (int r = 0; r < 8; r += 2) {
+            add_pair<M>(ev[k], od[k], lds32, lane_m, bo, e[r], e[r + 1]);
+            // the sums stay a chain, one pair at a time: regrouped, they
+            // would keep a slab's perms live at once
+#pragma unroll
+            for (int j = 0; j < M; ++j) asm volatile("" : "+v"(ev[k][j]), "+v"(od[k][j]));
+          }
         }
       }
+      if (more) slab_store(st, smem + (parity ^ 1) * (buf_dw >> 2), vpr, wave, lane);
+      __syncthreads();
+      parity ^= 1;
     }
-
-    const bool seg_end = SEG && (c1 % seg == 0 || !more);
-    if ((c1 & 255) == 0 || !more || seg_end) {
 #pragma unroll
-      for (int k = 0; k < DPW; ++k)
+    for (int k = 0; k < DPW; ++k)
 #pragma unroll
-        for (int j = 0; j < M; ++j) {
-          acc[k][j][0] += ev[k][j] & 0xFFFFu;
-          acc[k][j][2] += ev[k][j] >> 16;
-          acc[k][j][1] += od[k][j] & 0xFFFFu;
-          acc[k][j][3] += od[k][j] >> 16;
-          ev[k][j] = 0u;
-          od[k][j] = 0u;
-        }
-    }
+      for (int j = 0; j < M; ++j) {
+        acc[k][j][0] += ev[k][j] & 0xFFFFu;
+        acc[k][j][2] += ev[k][j] >> 16;
+        acc[k][j][1] += od[k][j] & 0xFFFFu;
+        acc[k][j][3] += od[k][j] >> 16;
+        ev[k][j] = 0u;
+        od[k][j] = 0u;
+      }
     if constexpr (SEG) {
-      if (seg_end) {
-        store_acc<M, DPW>(acc, Y + (int64_t)(c0 / seg) * seg_stride, nout, ndm, dw0, lane, t0,
+      if (g1 % seg == 0) {
+        store_acc<M, DPW>(acc, Y + (int64_t)(g0 / seg) * seg_stride, nout, ndm, dw0, lane, t0,
                           vec_store);
 #pragma unroll
         for (int k = 0; k < DPW; ++k)
@@ -296,9 +287,7 @@ __device__ __forceinline__ void dedisperse_block(
             for (int b = 0; b < 4; ++b) acc[k][j][b] = 0u;
       }
     }
-    if (more) slab_store(st, smem + (parity ^ 1) * (buf_dw >> 2), ncs1, vpr, wave, lane);
-    __syncthreads();
-    parity ^= 1;
+    g0 = g1;
   }
 
   if constexpr (!SEG) store_acc<M, DPW>(acc, Y, nout, ndm, dw0, lane, t0, vec_store);
@@ -307,18 +296,18 @@ __device__ __forceinline__ void dedisperse_block(
 template <int M, int DPW, int NW, int CS, int KMAX, int WPE, bool SEG>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) void
 dedisperse_kernel(const uint8_t *__restrict__ X, int64_t pitch, int64_t nsamp_in,
-                  const int32_t *__restrict__ D, int nchan, int ndm, uint32_t *__restrict__ Y,
-                  int64_t nout, int lds_pitch, int ntiles, int ndmb, int per_xcd, int vec_store,
-                  int seg, int64_t seg_stride) {
+                  const int2 *__restrict__ P, int pcols, const int32_t *__restrict__ B, int nchan,
+                  int ndm, uint32_t *__restrict__ Y, int64_t nout, int lds_pitch, int ntiles,
+                  int ndmb, int per_xcd, int vec_store, int seg, int64_t seg_stride) {
   extern __shared__ uint4 smem[];  // two slab buffers of CS rows x lds_pitch bytes
   const int blk = blockIdx.x;
   const int logical = (blk & 7) * per_xcd + (blk >> 3);
   if (logical >= ntiles * ndmb) return;
   const int dblk = logical % ndmb;
   const int tile = logical / ndmb;
-  dedisperse_block<M, DPW, NW, CS, KMAX, SEG>(X, pitch, nsamp_in, D, nchan, ndm, Y, nout,
+  dedisperse_block<M, DPW, NW, CS, KMAX, SEG>(X, pitch, nsamp_in, P, pcols, B, nchan, ndm, Y, nout,
                                               lds_pitch, vec_store, (int64_t)tile * (256 * M),
-                                              dblk * (NW * DPW), smem, seg, seg_stride);
+                                              dblk, smem, seg, seg_stride);
 }
 
 // Persistent kernel over many filterbanks that share a plan (beams of one
@@ -328,8 +317,8 @@ dedisperse_kernel(const uint8_t *__restrict__ X, int64_t pitch, int64_t nsamp_in
 template <int M, int DPW, int NW, int CS, int KMAX, int WPE>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) void
 dedisperse_batch_kernel(const BeamWork *__restrict__ beams, int nbeams, int64_t total_items,
-                        const int32_t *__restrict__ D, int nchan, int ndm, int lds_pitch,
-                        int ndmb) {
+                        const int2 *__restrict__ P, int pcols, const int32_t *__restrict__ B,
+                        int nchan, int ndm, int lds_pitch, int ndmb) {
   extern __shared__ uint4 smem[];
   const int G = gridDim.x;
   const int w = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
@@ -340,10 +329,38 @@ dedisperse_batch_kernel(const BeamWork *__restrict__ beams, int nbeams, int64_t 
     const int64_t local = item - bw.dd_begin;
     const int dblk = (int)(local % ndmb);
     const int64_t tile = local / ndmb;
-    dedisperse_block<M, DPW, NW, CS, KMAX>(bw.X, bw.pitch, bw.nsamp_in, D, nchan, ndm, bw.Y,
-                                           bw.nout, lds_pitch, bw.vec_store,
-                                           tile * (256 * M), dblk * (NW * DPW), smem);
+    dedisperse_block<M, DPW, NW, CS, KMAX>(bw.X, bw.pitch, bw.nsamp_in, P, pcols, B, nchan, ndm,
+                                           bw.Y,
+                                           bw.nout, lds_pitch, bw.vec_store, tile * (256 * M),
+                                           dblk, smem);
   }
+}
+
+// Staged form of the delay table for blocks of nd trials, slabs of cs rows
+// and rows of row_dw dwords (see StagedDelays).  One thread per (trial,
+// column); columns past the last channel (up to pcols, a multiple of cs)
+// point at the start of their zeroed slab row.  Delays are non-decreasing in
+// the trial, so a trial's offset from its block's first staged sample is
+// >= 0.
+__global__ __launch_bounds__(256) void stage_delays_kernel(const int32_t *__restrict__ D,
+                                                           int nchan, int ndm, int pcols, int nd,
+                                                           int cs, int row_dw,
+                                                           int2 *__restrict__ P,
+                                                           int32_t *__restrict__ B) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (int64_t)ndm * pcols) return;
+  const int d = (int)(i / pcols);
+  const int c = (int)(i - (int64_t)d * pcols);
+  if (c >= nchan) {
+    P[i] = make_int2((c % cs) * row_dw, 0x0C020C00);
+    return;
+  }
+  const int dlo = d - d % nd;
+  const int32_t base = D[(int64_t)dlo * nchan + c] & ~15;
+  const int32_t v = D[(int64_t)d * nchan + c];
+  P[i] = make_int2((c % cs) * row_dw + ((v - base) >> 2),
+                   (int32_t)(0x0C020C00u + (uint32_t)(v & 3) * 0x00010001u));
+  if (d == dlo) B[(int64_t)(d / nd) * nchan + c] = base;
 }
 
 // Plain fallback for delay spreads too wide to stage in LDS: one thread sums
@@ -372,7 +389,7 @@ __global__ __launch_bounds__(256) void dedisperse_direct_kernel(
 
 template <int M, int DPW, int NW, int CS, int KMAX, int WPE, bool SEG>
 hipError_t launch_cfg(int lds_pitch, const uint8_t *X, int64_t pitch, int64_t nsamp_in,
-                      const int32_t *D, int nchan, int ndm, uint32_t *Y, int64_t nout,
+                      const StagedDelays &sd, int nchan, int ndm, uint32_t *Y, int64_t nout,
                       hipStream_t stream, int seg, int64_t seg_stride) {
   constexpr int NT = 256 * M;
   constexpr int ND = NW * DPW;
@@ -394,15 +411,16 @@ hipError_t launch_cfg(int lds_pitch, const uint8_t *X, int64_t pitch, int64_t ns
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(NW * 64), lds, stream, X, pitch, nsamp_in, D, nchan,
-                     ndm, Y, nout, lds_pitch, (int)ntiles64, ndmb, per_xcd, vec_store, seg,
-                     seg_stride);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(NW * 64), lds, stream, X, pitch, nsamp_in, sd.P,
+                     sd.pcols, sd.B, nchan, ndm, Y, nout, lds_pitch, (int)ntiles64, ndmb, per_xcd,
+                     vec_store, seg, seg_stride);
   return hipGetLastError();
 }
 
 template <int M, int DPW, int NW, int CS, int KMAX, int WPE>
 hipError_t launch_batch_cfg(int lds_pitch, const BeamWork *beams, int nbeams, int64_t total,
-                            const int32_t *D, int nchan, int ndm, int grid, hipStream_t stream) {
+                            const StagedDelays &sd, int nchan, int ndm, int grid,
+                            hipStream_t stream) {
   constexpr int ND = NW * DPW;
   if (lds_pitch > 16 * 64 * KMAX || lds_pitch % 16 != 0 || grid % 8 != 0)
     return hipErrorInvalidValue;
@@ -414,8 +432,8 @@ hipError_t launch_batch_cfg(int lds_pitch, const BeamWork *beams, int nbeams, in
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(NW * 64), lds, stream, beams, nbeams, total, D, nchan,
-                     ndm, lds_pitch, ndmb);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(NW * 64), lds, stream, beams, nbeams, total, sd.P,
+                     sd.pcols, sd.B, nchan, ndm, lds_pitch, ndmb);
   return hipGetLastError();
 }
 
@@ -468,13 +486,14 @@ int64_t dedisp_batch_items(const DedispConfig &c, int ndm, int64_t nout) {
 }
 
 hipError_t launch_dedisperse_batch(const DedispConfig &c, int lds_pitch, const BeamWork *beams,
-                                   int nbeams, int64_t total_items, const int32_t *D, int nchan,
-                                   int ndm, int grid, hipStream_t stream) {
+                                   int nbeams, int64_t total_items, const StagedDelays &sd,
+                                   int nchan, int ndm, int grid, hipStream_t stream) {
+  if (!sd.matches(c, lds_pitch, nchan, ndm)) return hipErrorInvalidValue;
 #define SPS_BLAUNCH(m_, dpw_, nw_, cs_, kmax_, wpe_)                                          \
   if (c.m == m_ && c.dpw == dpw_ && c.nw == nw_ && c.cs == cs_ && c.kmax == kmax_ &&         \
       c.wpe == wpe_)                                                                          \
     return launch_batch_cfg<m_, dpw_, nw_, cs_, kmax_, wpe_>(lds_pitch, beams, nbeams,        \
-                                                             total_items, D, nchan, ndm, grid, \
+                                                             total_items, sd, nchan, ndm, grid, \
                                                              stream);
   SPS_DEDISP_CONFIGS(SPS_BLAUNCH)
 #undef SPS_BLAUNCH
@@ -482,9 +501,9 @@ hipError_t launch_dedisperse_batch(const DedispConfig &c, int lds_pitch, const B
 }
 
 hipError_t launch_dedisperse(const DedispConfig &c, int lds_pitch, const uint8_t *X,
-                             int64_t pitch, int64_t nsamp_in, const int32_t *D, int nchan,
-                             int ndm, uint32_t *Y, int64_t nout, hipStream_t stream, int seg,
-                             int64_t seg_stride) {
+                             int64_t pitch, int64_t nsamp_in, const int32_t *D,
+                             const StagedDelays *sd, int nchan, int ndm, uint32_t *Y,
+                             int64_t nout, hipStream_t stream, int seg, int64_t seg_stride) {
   if (c.m == 0) {
     if (seg != 0) return hipErrorInvalidValue;
     const int64_t nthreads = (nout + 3) / 4;
@@ -495,17 +514,62 @@ hipError_t launch_dedisperse(const DedispConfig &c, int lds_pitch, const uint8_t
                        stream, X, pitch, nsamp_in, D, nchan, ndm, Y, nout);
     return hipGetLastError();
   }
-#define SPS_LAUNCH(m_, dpw_, nw_, cs_, kmax_, wpe_)                                     \
-  if (c.m == m_ && c.dpw == dpw_ && c.nw == nw_ && c.cs == cs_ && c.kmax == kmax_ &&    \
-      c.wpe == wpe_)                                                                     \
-    return seg > 0 ? launch_cfg<m_, dpw_, nw_, cs_, kmax_, wpe_, true>(                 \
-                         lds_pitch, X, pitch, nsamp_in, D, nchan, ndm, Y, nout, stream, seg, \
-                         seg_stride)                                                        \
-                   : launch_cfg<m_, dpw_, nw_, cs_, kmax_, wpe_, false>(                    \
-                         lds_pitch, X, pitch, nsamp_in, D, nchan, ndm, Y, nout, stream, 0, 0);
+  if (!sd || !sd->matches(c, lds_pitch, nchan, ndm)) return hipErrorInvalidValue;
+#define SPS_LAUNCH(m_, dpw_, nw_, cs_, kmax_, wpe_)                                      \
+  if (c.m == m_ && c.dpw == dpw_ && c.nw == nw_ && c.cs == cs_ && c.kmax == kmax_ &&     \
+      c.wpe == wpe_)                                                                      \
+    return seg > 0 ? launch_cfg<m_, dpw_, nw_, cs_, kmax_, wpe_, true>(                  \
+                         lds_pitch, X, pitch, nsamp_in, *sd, nchan, ndm, Y, nout, stream, seg, \
+                         seg_stride)                                                         \
+                   : launch_cfg<m_, dpw_, nw_, cs_, kmax_, wpe_, false>(                     \
+                         lds_pitch, X, pitch, nsamp_in, *sd, nchan, ndm, Y, nout, stream, 0, 0);
   SPS_DEDISP_CONFIGS(SPS_LAUNCH)
 #undef SPS_LAUNCH
   return hipErrorInvalidValue;
+}
+
+void free_staged(StagedDelays &sd) {
+  if (sd.P) (void)hipFree(sd.P);
+  if (sd.B) (void)hipFree(sd.B);
+  sd = StagedDelays{};
+}
+
+hipError_t stage_delays(StagedDelays &sd, const DedispConfig &c, int lds_pitch, const int32_t *D,
+                        int nchan, int ndm) {
+  if (c.m == 0) {
+    free_staged(sd);
+    return hipSuccess;
+  }
+  if (sd.matches(c, lds_pitch, nchan, ndm)) return hipSuccess;
+  if (nchan < 1 || ndm < 1 || lds_pitch % 16 != 0 || c.nd() < 1 || c.cs < 1)
+    return hipErrorInvalidValue;
+  const int pcols = (nchan + c.cs - 1) / c.cs * c.cs;
+  const int64_t n = (int64_t)ndm * pcols;
+  const int64_t nb = (int64_t)((ndm + c.nd() - 1) / c.nd()) * nchan;
+  if ((n + 255) / 256 > 0x7FFFFFFF) return hipErrorInvalidValue;
+  free_staged(sd);
+  hipError_t e = hipMalloc(&sd.P, sizeof(int2) * (size_t)n);
+  if (e == hipSuccess) e = hipMalloc(&sd.B, sizeof(int32_t) * (size_t)nb);
+  if (e != hipSuccess) {
+    free_staged(sd);
+    return e;
+  }
+  // null stream, waited for: callers may launch on any stream afterwards
+  hipLaunchKernelGGL(stage_delays_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, nullptr,
+                     D, nchan, ndm, pcols, c.nd(), c.cs, lds_pitch / 4, sd.P, sd.B);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+  if (e != hipSuccess) {
+    free_staged(sd);
+    return e;
+  }
+  sd.nchan = nchan;
+  sd.pcols = pcols;
+  sd.ndm = ndm;
+  sd.nd = c.nd();
+  sd.cs = c.cs;
+  sd.pitch = lds_pitch;
+  return hipSuccess;
 }
 
 }  // namespace sps

@@ -71,6 +71,7 @@ struct sps_plan_s {
   int32_t *d_stats = nullptr;  // [ndm][2] used when the caller passes none
   sps::DedispConfig cfg{5, 1, 16, 16, 2, 8};
   int lds_pitch = 0;
+  sps::StagedDelays staged;  // d_delays in the form the tiling cfg reads
   // subband method (sps_subband_plan_create)
   bool subband = false;
   int n0 = 0, nsub = 0, ncoarse = 0;
@@ -82,12 +83,14 @@ struct sps_plan_s {
   std::vector<int32_t *> d_coarse_sub;  // per subband: [ncoarse][channels of s]
   std::vector<sps::DedispConfig> sub_cfg;
   std::vector<int> sub_pitch;
+  std::vector<sps::StagedDelays> sub_staged;
   // stage 1 in one launch over all channels (equal subbands that are a
   // multiple of the tiling's slab): the whole coarse table and its tiling
   bool fused = false;
   sps::DedispConfig fused_cfg{0, 0, 0, 0, 0, 0};
   int fused_pitch = 0;
   int32_t *d_coarse_full = nullptr;
+  sps::StagedDelays fused_staged;
   int32_t *d_resid = nullptr;
   uint32_t *d_I = nullptr;
   size_t I_bytes = 0;
@@ -112,6 +115,9 @@ void free_plan(sps_plan p) {
   if (p->d_resid) (void)hipFree(p->d_resid);
   if (p->d_I) (void)hipFree(p->d_I);
   if (p->d_coarse_full) (void)hipFree(p->d_coarse_full);
+  sps::free_staged(p->staged);
+  for (sps::StagedDelays &q : p->sub_staged) sps::free_staged(q);
+  sps::free_staged(p->fused_staged);
   delete p;
 }
 
@@ -158,6 +164,20 @@ void pick_tiling(const int32_t *D, int nchan, int ndm, sps::DedispConfig *cfg, i
 
 sps_status choose_tiling(sps_plan p) {
   pick_tiling(p->delays.data(), p->nchan, p->ndm, &p->cfg, &p->lds_pitch);
+  return SPS_OK;
+}
+
+// Rebuilds the staged delay table for the plan's current tiling.
+sps_status restage(sps_plan p) {
+  DeviceScope scope(p->device);
+  if (scope.err != hipSuccess) return hip_fail(scope.err, "selecting the plan's device");
+  const hipError_t e =
+      sps::stage_delays(p->staged, p->cfg, p->lds_pitch, p->d_delays, p->nchan, p->ndm);
+  if (e == hipErrorOutOfMemory) {
+    (void)hipGetLastError();
+    return fail(SPS_ERR_NOMEM, "device allocation of the staged delay table failed");
+  }
+  if (e != hipSuccess) return hip_fail(e, "staging the delay table");
   return SPS_OK;
 }
 
@@ -247,6 +267,11 @@ sps_status sps_plan_create(const sps_obs_desc *desc, sps_plan *out) {
     free_plan(p);
     return hip_fail(e, "uploading the delay table");
   }
+  st = restage(p);
+  if (st != SPS_OK) {
+    free_plan(p);
+    return st;
+  }
   *out = p;
   return SPS_OK;
 }
@@ -274,7 +299,7 @@ sps_status sps_plan_set_tiling(sps_plan plan, int32_t m, int32_t dpw, int32_t nw
   if (m == 0) {
     plan->cfg = sps::DedispConfig{0, 0, 0, 0, 0, 0};
     plan->lds_pitch = 0;
-    return SPS_OK;
+    return restage(plan);
   }
   bool known = false;
   for (const auto &c : kPrefs) {
@@ -283,9 +308,17 @@ sps_status sps_plan_set_tiling(sps_plan plan, int32_t m, int32_t dpw, int32_t nw
     known = true;
     const int64_t pitch = fitted_pitch(plan, c, 160 * 1024);
     if (pitch > 0) {
+      const sps::DedispConfig old_cfg = plan->cfg;
+      const int old_pitch = plan->lds_pitch;
       plan->cfg = c;
       plan->lds_pitch = (int)pitch;
-      return SPS_OK;
+      const sps_status r = restage(plan);
+      if (r != SPS_OK) {  // keep the previous tiling usable
+        plan->cfg = old_cfg;
+        plan->lds_pitch = old_pitch;
+        (void)restage(plan);
+      }
+      return r;
     }
   }
   if (!known)
@@ -325,8 +358,8 @@ sps_status sps_dedisperse(sps_plan plan, const uint8_t *X, int64_t pitch, int64_
   DeviceScope scope(plan->device);
   if (scope.err != hipSuccess) return hip_fail(scope.err, "selecting the plan's device");
   hipError_t e = sps::launch_dedisperse(plan->cfg, plan->lds_pitch, X, pitch, nsamp_in,
-                                        plan->d_delays, plan->nchan, plan->ndm, Y, nout,
-                                        (hipStream_t)stream);
+                                        plan->d_delays, &plan->staged, plan->nchan, plan->ndm, Y,
+                                        nout, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "dedispersion launch");
   return SPS_OK;
 }
@@ -485,6 +518,7 @@ sps_status sps_subband_plan_create(const sps_subband_desc *desc, sps_plan *out) 
     p->residuals.resize((size_t)ndm * nsub);
     p->d_coarse_sub.assign((size_t)nsub, nullptr);
     p->sub_cfg.resize((size_t)nsub);
+    p->sub_staged.resize((size_t)nsub);
     p->sub_pitch.resize((size_t)nsub);
   } catch (...) {
     free_plan(p);
@@ -557,6 +591,9 @@ sps_status sps_subband_plan_create(const sps_subband_desc *desc, sps_plan *out) 
     if (e == hipSuccess)
       e = hipMemcpy(p->d_coarse_sub[(size_t)s], tab.data(), tab.size() * sizeof(int32_t),
                     hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = sps::stage_delays(p->sub_staged[(size_t)s], p->sub_cfg[(size_t)s],
+                            p->sub_pitch[(size_t)s], p->d_coarse_sub[(size_t)s], ns, ncoarse);
     if (e != hipSuccess) {
       free_plan(p);
       (void)hipGetLastError();
@@ -572,6 +609,9 @@ sps_status sps_subband_plan_create(const sps_subband_desc *desc, sps_plan *out) 
       if (e == hipSuccess)
         e = hipMemcpy(p->d_coarse_full, p->coarse_delays.data(),
                       p->coarse_delays.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+      if (e == hipSuccess)
+        e = sps::stage_delays(p->fused_staged, p->fused_cfg, p->fused_pitch, p->d_coarse_full,
+                              nchan, ncoarse);
       if (e != hipSuccess) {
         free_plan(p);
         (void)hipGetLastError();
@@ -642,17 +682,17 @@ sps_status sps_dedisperse_subband(sps_plan plan, const uint8_t *X, int64_t pitch
   hipStream_t s = (hipStream_t)stream;
   if (plan->fused) {
     hipError_t e = sps::launch_dedisperse(plan->fused_cfg, plan->fused_pitch, X, pitch, nsamp_in,
-                                          plan->d_coarse_full, plan->nchan, plan->ncoarse,
-                                          plan->d_I, len1, s, plan->nchan / plan->nsub,
-                                          (int64_t)plan->ncoarse * len1);
+                                          plan->d_coarse_full, &plan->fused_staged, plan->nchan,
+                                          plan->ncoarse, plan->d_I, len1, s,
+                                          plan->nchan / plan->nsub, (int64_t)plan->ncoarse * len1);
     if (e != hipSuccess) return hip_fail(e, "subband stage 1 launch");
   } else {
     for (int b = 0; b < plan->nsub; ++b) {
       const int c0 = plan->sub[(size_t)b], ns = plan->sub[(size_t)b + 1] - c0;
       hipError_t e = sps::launch_dedisperse(
           plan->sub_cfg[(size_t)b], plan->sub_pitch[(size_t)b], X + (int64_t)c0 * pitch, pitch,
-          nsamp_in, plan->d_coarse_sub[(size_t)b], ns, plan->ncoarse,
-          plan->d_I + (size_t)b * plan->ncoarse * (size_t)len1, len1, s);
+          nsamp_in, plan->d_coarse_sub[(size_t)b], &plan->sub_staged[(size_t)b], ns,
+          plan->ncoarse, plan->d_I + (size_t)b * plan->ncoarse * (size_t)len1, len1, s);
       if (e != hipSuccess) return hip_fail(e, "subband stage 1 launch");
     }
   }
@@ -708,6 +748,7 @@ struct sps_batch_s {
   sps_detect_params prm{};
   sps::DedispConfig cfg{};
   int lds_pitch = 0;
+  sps::StagedDelays staged;  // the plan's table for cfg, owned by the batch
   int grid_dd = 0;
   sps::TilePeak *d_peaks = nullptr, *d_out = nullptr;
   int32_t *d_status = nullptr;
@@ -726,13 +767,14 @@ void free_batch(sps_batch b) {
   if (b->d_peaks) (void)hipFree(b->d_peaks);
   if (b->d_out) (void)hipFree(b->d_out);
   if (b->d_status) (void)hipFree(b->d_status);
+  sps::free_staged(b->staged);
   delete b;
 }
 
 sps_status batch_enqueue(sps_batch b, hipStream_t s) {
   sps_plan p = b->plan;
   hipError_t e = sps::launch_dedisperse_batch(b->cfg, b->lds_pitch, b->d_beams, b->nbeams,
-                                              b->dd_items, p->d_delays, p->nchan, p->ndm,
+                                              b->dd_items, b->staged, p->nchan, p->ndm,
                                               b->grid_dd, s);
   if (e != hipSuccess) return hip_fail(e, "batched dedispersion launch");
   e = sps::launch_row_stats_batch(b->d_beams, b->nbeams, p->ndm, 255u * (uint32_t)p->nchan, s);
@@ -844,6 +886,9 @@ sps_status sps_batch_create(sps_plan plan, int32_t nbeams, const sps_beam *beams
   if (e == hipSuccess)
     e = hipMemcpy(b->d_beams, b->beams.data(), sizeof(sps::BeamWork) * (size_t)nbeams,
                   hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = sps::stage_delays(b->staged, b->cfg, b->lds_pitch, plan->d_delays, plan->nchan,
+                          plan->ndm);
   if (e != hipSuccess) {
     free_batch(b);
     (void)hipGetLastError();
@@ -980,13 +1025,16 @@ sps_status sps_plan_autotune(sps_plan plan, int64_t nout_probe, int32_t iters, v
     const int64_t lp = fitted_pitch(plan, c, 160 * 1024);
     if (ms_out) ms_out[i] = -1.0f;
     if (lp <= 0) continue;
-    e = sps::launch_dedisperse(c, (int)lp, X, pitch, nsamp, plan->d_delays, plan->nchan, plan->ndm,
-                               Y, nout_probe, s);  // warm-up
+    sps::StagedDelays sd;
+    e = sps::stage_delays(sd, c, (int)lp, plan->d_delays, plan->nchan, plan->ndm);
+    if (e == hipSuccess)
+      e = sps::launch_dedisperse(c, (int)lp, X, pitch, nsamp, plan->d_delays, &sd, plan->nchan,
+                                 plan->ndm, Y, nout_probe, s);  // warm-up
     float total = 0.0f;
     for (int it = 0; it < iters && e == hipSuccess; ++it) {
       e = hipEventRecord(ev0, s);
       if (e == hipSuccess)
-        e = sps::launch_dedisperse(c, (int)lp, X, pitch, nsamp, plan->d_delays, plan->nchan,
+        e = sps::launch_dedisperse(c, (int)lp, X, pitch, nsamp, plan->d_delays, &sd, plan->nchan,
                                    plan->ndm, Y, nout_probe, s);
       if (e == hipSuccess) e = hipEventRecord(ev1, s);
       if (e == hipSuccess) e = hipEventSynchronize(ev1);
@@ -994,6 +1042,8 @@ sps_status sps_plan_autotune(sps_plan plan, int64_t nout_probe, int32_t iters, v
       if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
       total += ms;
     }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);  // before its table is freed
+    sps::free_staged(sd);
     if (e != hipSuccess) break;
     const float mean = total / (float)iters;
     if (ms_out) ms_out[i] = mean;
@@ -1013,7 +1063,7 @@ sps_status sps_plan_autotune(sps_plan plan, int64_t nout_probe, int32_t iters, v
   if (tried == 0) return fail(SPS_ERR_RANGE, "no compiled tiling fits this plan");
   plan->cfg = best_cfg;
   plan->lds_pitch = best_pitch;
-  return SPS_OK;
+  return restage(plan);
 }
 
 int32_t sps_tiling_count(void) { return (int32_t)(sizeof(kPrefs) / sizeof(kPrefs[0])); }

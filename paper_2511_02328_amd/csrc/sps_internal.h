@@ -56,16 +56,47 @@ struct BeamWork {
   int32_t pad;
 };
 
+// The delay table D [ndm][nchan] in the form the staged kernels of one
+// tiling read (blocks of nd = nw dpw trials, slabs of cs rows, staged rows of
+// `pitch` bytes):
+//   P[d][c] = {(c mod cs) pitch/4 + (D[d][c] - B[d/nd][c]) / 4,
+//              perm selector of bytes (r, r+2), r = D[d][c] mod 4}
+//     with pcols columns (nchan rounded up to a multiple of cs; the padding
+//     columns point at the start of their zeroed slab row)
+//   B[j][c] = D[j nd][c] rounded down to a multiple of 16 (first staged
+//             sample of channel c's row for DM block j).
+// Device memory owned by the struct's holder (free_staged).
+struct StagedDelays {
+  int2 *P = nullptr;
+  int32_t *B = nullptr;
+  int nchan = 0, pcols = 0, ndm = 0, nd = 0, cs = 0, pitch = 0;
+  bool matches(const DedispConfig &c, int lds_pitch, int nc, int nd_trials) const {
+    return P && nchan == nc && ndm == nd_trials && nd == c.nd() && cs == c.cs &&
+           pitch == lds_pitch;
+  }
+};
+
+// (Re)builds sd for tiling c from the device table D unless it already
+// matches; frees it for the plain kernel (m = 0).  Allocates, and waits for
+// its own kernel, so it is never called inside a launch sequence that a
+// caller may capture.
+hipError_t stage_delays(StagedDelays &sd, const DedispConfig &c, int lds_pitch, const int32_t *D,
+                        int nchan, int ndm);
+void free_staged(StagedDelays &sd);
+
 int64_t dedisp_batch_items(const DedispConfig &c, int ndm, int64_t nout);
 hipError_t launch_dedisperse_batch(const DedispConfig &c, int lds_pitch, const BeamWork *beams,
-                                   int nbeams, int64_t total_items, const int32_t *D, int nchan,
-                                   int ndm, int grid, hipStream_t stream);
+                                   int nbeams, int64_t total_items, const StagedDelays &sd,
+                                   int nchan, int ndm, int grid, hipStream_t stream);
 
-// seg > 0: channel groups of seg (a multiple of the slab, dividing nchan)
-// write their partial sums to planes Y + g seg_stride (m > 0 tilings only).
+// D: raw table (plain kernel, m = 0); sd: its staged form for tiling cfg
+// (m > 0).  seg > 0: channel groups of seg (a multiple of the slab, dividing
+// nchan) write their partial sums to planes Y + g seg_stride (m > 0 tilings
+// only).
 hipError_t launch_dedisperse(const DedispConfig &cfg, int lds_pitch, const uint8_t *X,
-                             int64_t pitch, int64_t nsamp_in, const int32_t *D, int nchan,
-                             int ndm, uint32_t *Y, int64_t nout, hipStream_t stream, int seg = 0,
+                             int64_t pitch, int64_t nsamp_in, const int32_t *D,
+                             const StagedDelays *sd, int nchan, int ndm, uint32_t *Y,
+                             int64_t nout, hipStream_t stream, int seg = 0,
                              int64_t seg_stride = 0);
 
 hipError_t launch_row_stats(const uint32_t *Y, int ndm, int64_t nout, uint32_t vmax,
