@@ -31,9 +31,10 @@
 //    scalar unit, which issues at the same rate as the vector unit, stays
 //    well below it.
 //  * Workgroups are dealt to the 8 XCDs round-robin by the hardware; the
-//    logical index is remapped so that each XCD walks a contiguous range with
-//    the DM block fastest, so the workgroups resident on one XCD share most
-//    of their input windows in that XCD's L2.
+//    logical index is remapped so that each XCD walks a contiguous range in
+//    panels of a few DM blocks (DM block fastest inside a panel, then time),
+//    so the workgroups resident on one XCD share their staged delay rows and
+//    most of their input windows in that XCD's L2.
 #include "sps_internal.h"
 
 namespace sps {
@@ -293,6 +294,14 @@ __device__ __forceinline__ void dedisperse_block(
   if constexpr (!SEG) store_acc<M, DPW>(acc, Y, nout, ndm, dw0, lane, t0, vec_store);
 }
 
+// DM blocks per panel of the workgroup order.  The 64 workgroups resident on
+// an XCD then cover about 8 DM blocks x 8 time tiles: the staged delay rows
+// of 8 blocks (8 x 16 trials x nchan entries) stay in the XCD's L2 and the
+// input windows of neighbouring blocks and tiles overlap.  Measured on the
+// full-scale chunk: 3x less fetched from memory than the DM block running
+// fastest over all blocks, and 4-6% faster; panels of 4 or 16 fall between.
+constexpr int kPanel = 8;
+
 template <int M, int DPW, int NW, int CS, int KMAX, int WPE, bool SEG>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) void
 dedisperse_kernel(const uint8_t *__restrict__ X, int64_t pitch, int64_t nsamp_in,
@@ -303,8 +312,13 @@ dedisperse_kernel(const uint8_t *__restrict__ X, int64_t pitch, int64_t nsamp_in
   const int blk = blockIdx.x;
   const int logical = (blk & 7) * per_xcd + (blk >> 3);
   if (logical >= ntiles * ndmb) return;
-  const int dblk = logical % ndmb;
-  const int tile = logical / ndmb;
+  // panels of kPanel DM blocks: DM block fastest inside a panel, then the
+  // time tile, then the next panel
+  const int panel = logical / (ntiles * kPanel);
+  const int pd = min(kPanel, ndmb - panel * kPanel);
+  const int rem = logical - panel * (ntiles * kPanel);
+  const int tile = rem / pd;
+  const int dblk = panel * kPanel + rem % pd;
   dedisperse_block<M, DPW, NW, CS, KMAX, SEG>(X, pitch, nsamp_in, P, pcols, B, nchan, ndm, Y, nout,
                                               lds_pitch, vec_store, (int64_t)tile * (256 * M),
                                               dblk, smem, seg, seg_stride);
