@@ -91,7 +91,7 @@ struct sps_plan_s {
   int fused_pitch = 0;
   int32_t *d_coarse_full = nullptr;
   sps::StagedDelays fused_staged;
-  int32_t *d_resid = nullptr;
+  int32_t *d_resid = nullptr;  // residuals transposed, [nsub][ndm]
   uint32_t *d_I = nullptr;
   size_t I_bytes = 0;
   // detection scratch
@@ -620,10 +620,14 @@ sps_status sps_subband_plan_create(const sps_subband_desc *desc, sps_plan *out) 
       p->fused = true;
     }
   }
-  hipError_t e = hipMalloc(&p->d_resid, p->residuals.size() * sizeof(int32_t));
+  // stage 2 reads the residuals transposed, [nsub][ndm]
+  std::vector<int32_t> rt(p->residuals.size());
+  for (int m = 0; m < ndm; ++m)
+    for (int s = 0; s < nsub; ++s)
+      rt[(size_t)s * ndm + m] = p->residuals[(size_t)m * nsub + s];
+  hipError_t e = hipMalloc(&p->d_resid, rt.size() * sizeof(int32_t));
   if (e == hipSuccess)
-    e = hipMemcpy(p->d_resid, p->residuals.data(), p->residuals.size() * sizeof(int32_t),
-                  hipMemcpyHostToDevice);
+    e = hipMemcpy(p->d_resid, rt.data(), rt.size() * sizeof(int32_t), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     free_plan(p);
     (void)hipGetLastError();

@@ -135,8 +135,9 @@ hipError_t launch_select_nms(const TilePeak *peaks, int ndm, int64_t nout, int t
                              int64_t tile_t, float threshold, int nms_dm, int64_t nms_t,
                              TilePeak *out, int32_t *status, hipStream_t stream);
 
+// Rt: residual table transposed, [nsub][ndm].
 hipError_t launch_subband_stage2(const uint32_t *I, int64_t len1, int ncoarse, int nsub,
-                                 const int32_t *R, int rmax, int ndm, int n0, uint32_t *Y,
+                                 const int32_t *Rt, int rmax, int ndm, int n0, uint32_t *Y,
                                  int64_t nout, hipStream_t stream);
 hipError_t launch_zero_dm(const uint8_t *X, int64_t pitch, int64_t nsamp, int nchan, uint8_t *Xo,
                           int64_t pitch_out, hipStream_t stream);

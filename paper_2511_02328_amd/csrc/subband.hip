@@ -20,18 +20,25 @@ constexpr int kS2Out = 4;  // consecutive outputs per thread
 // GM fine DMs of the group are accumulated together, so the GM overlapping
 // windows of one subband row (a few KB) are read back to back and served
 // from L1, and each word of I leaves L2 about once per tile.  Thread i owns
-// outputs t0 + i + 256 b (b < 4).
+// outputs t0 + i + 256 b (b < 4).  Rt: the residual table transposed,
+// [nsub][ndm], so the GM shifts of one subband are one scalar load.
+//
+// Whole groups of GM trials on whole tiles take a branch-free path: all
+// GM x 4 loads of a subband are issued before the first add, and two
+// subbands are in flight.  Group and tile edges take the guarded loop.
 template <int GM>
 __global__ __launch_bounds__(kS2Threads) void subband_stage2_blocked_kernel(
     const uint32_t *__restrict__ I, int64_t len1, int ncoarse, int nsub,
-    const int32_t *__restrict__ R, int ndm, int n0, uint32_t *__restrict__ Y, int64_t nout,
+    const int32_t *__restrict__ Rt, int ndm, int n0, uint32_t *__restrict__ Y, int64_t nout,
     int64_t nchunks) {
   const int64_t blk = blockIdx.x;
   const int j = (int)(blk / nchunks);
-  const int64_t t = (blk - (int64_t)j * nchunks) * kS2Threads * kS2Out + threadIdx.x;
-  if (t >= nout) return;
+  const int64_t t0 = (blk - (int64_t)j * nchunks) * kS2Threads * kS2Out;
+  const int64_t t = t0 + threadIdx.x;
+  const bool full_tile = t0 + kS2Threads * kS2Out <= nout;
   const int mend = min((j + 1) * n0, ndm);
   const int64_t plane = (int64_t)ncoarse * len1;
+  const uint32_t *base = I + (int64_t)j * len1 + t;
   for (int m0 = j * n0; m0 < mend; m0 += GM) {
     const int gm = min(GM, mend - m0);
     uint32_t acc[GM][kS2Out];
@@ -39,25 +46,43 @@ __global__ __launch_bounds__(kS2Threads) void subband_stage2_blocked_kernel(
     for (int a = 0; a < GM; ++a)
 #pragma unroll
       for (int b = 0; b < kS2Out; ++b) acc[a][b] = 0u;
-    for (int sb = 0; sb < nsub; ++sb) {
-      const uint32_t *row = I + (int64_t)sb * plane + (int64_t)j * len1 + t;
+    if (gm == GM && full_tile) {
+#pragma unroll 2
+      for (int sb = 0; sb < nsub; ++sb) {
+        const uint32_t *row = base + (int64_t)sb * plane;
+        const int32_t *Rs = Rt + (int64_t)sb * ndm + m0;
+        uint32_t v[GM][kS2Out];
 #pragma unroll
-      for (int a = 0; a < GM; ++a) {
-        if (a < gm) {
-          const uint32_t *w = row + R[(int64_t)(m0 + a) * nsub + sb];
+        for (int a = 0; a < GM; ++a) {
+          const uint32_t *w = row + Rs[a];
+#pragma unroll
+          for (int b = 0; b < kS2Out; ++b) v[a][b] = w[b * kS2Threads];
+        }
+#pragma unroll
+        for (int a = 0; a < GM; ++a)
+#pragma unroll
+          for (int b = 0; b < kS2Out; ++b) acc[a][b] += v[a][b];
+      }
+    } else if (t < nout) {
+      for (int sb = 0; sb < nsub; ++sb) {
+        const uint32_t *row = base + (int64_t)sb * plane;
+        for (int a = 0; a < gm; ++a) {
+          const uint32_t *w = row + Rt[(int64_t)sb * ndm + m0 + a];
 #pragma unroll
           for (int b = 0; b < kS2Out; ++b)
             if (t + b * kS2Threads < nout) acc[a][b] += w[b * kS2Threads];
         }
       }
     }
+    if (t < nout) {
 #pragma unroll
-    for (int a = 0; a < GM; ++a) {
-      if (a < gm) {
-        uint32_t *Ym = Y + (int64_t)(m0 + a) * nout + t;
+      for (int a = 0; a < GM; ++a) {
+        if (a < gm) {
+          uint32_t *Ym = Y + (int64_t)(m0 + a) * nout + t;
 #pragma unroll
-        for (int b = 0; b < kS2Out; ++b)
-          if (t + b * kS2Threads < nout) Ym[b * kS2Threads] = acc[a][b];
+          for (int b = 0; b < kS2Out; ++b)
+            if (t + b * kS2Threads < nout) Ym[b * kS2Threads] = acc[a][b];
+        }
       }
     }
   }
@@ -133,7 +158,7 @@ __global__ __launch_bounds__(256) void downsample_sqrt_kernel(
 }  // namespace
 
 hipError_t launch_subband_stage2(const uint32_t *I, int64_t len1, int ncoarse, int nsub,
-                                 const int32_t *R, int rmax, int ndm, int n0, uint32_t *Y,
+                                 const int32_t *Rt, int rmax, int ndm, int n0, uint32_t *Y,
                                  int64_t nout, hipStream_t stream) {
   const int64_t per_block = (int64_t)kS2Threads * kS2Out;
   const int64_t nchunks = (nout + per_block - 1) / per_block;
@@ -141,7 +166,7 @@ hipError_t launch_subband_stage2(const uint32_t *I, int64_t len1, int ncoarse, i
   if (grid > 0x7FFFFFFF) return hipErrorInvalidValue;
   (void)rmax;
   hipLaunchKernelGGL(subband_stage2_blocked_kernel<8>, dim3((unsigned)grid), dim3(kS2Threads), 0,
-                     stream, I, len1, ncoarse, nsub, R, ndm, n0, Y, nout, nchunks);
+                     stream, I, len1, ncoarse, nsub, Rt, ndm, n0, Y, nout, nchunks);
   return hipGetLastError();
 }
 
