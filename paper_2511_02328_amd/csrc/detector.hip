@@ -177,9 +177,12 @@ __global__ __launch_bounds__(256) void conv0_fwd_kernel(const uint16_t *__restri
 }
 
 // Layers 1..5: implicit GEMM, M = output pixels, N = COUT, K = taps x CIN.
-// A workgroup of 4 waves covers 64 output pixels (16 per wave) and all
-// output channels.
-template <int LI>
+// A workgroup of 4 waves covers 64 MB output pixels (16 MB per wave, in MB
+// blocks of 16) and all output channels.  Per 32-wide K step a wave loads
+// the NB weight fragments once and reuses them for its MB pixel blocks, so
+// the weight reads per MFMA fall MB-fold.  Each output's K steps are summed
+// in the same order whatever MB is.
+template <int LI, int MB>
 __global__ __launch_bounds__(256) void conv_fwd_kernel(const uint16_t *__restrict__ x,
                                                        const uint16_t *__restrict__ wp,
                                                        const float *__restrict__ bias,
@@ -188,35 +191,47 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(const uint16_t *__restric
   constexpr int CIN = L.cin, COUT = L.cout, S = L.stride, NB = COUT / 16;
   constexpr int KPAD = (9 * CIN + 31) / 32 * 32;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4;
-  const int64_t pbase = (int64_t)blockIdx.x * 64 + wave * 16;
-  const int64_t p = pbase + (lane & 15);
-  const bool valid = p < npix;
-  int64_t n = 0;
-  int oy = 0, ox = 0;
-  if (valid) {
-    n = p / (L.hout * L.wout);
-    const int r = (int)(p - n * L.hout * L.wout);
-    oy = r / L.wout;
-    ox = r % L.wout;
-  }
-  floatx4 acc[NB];
+  const int64_t pbase = (int64_t)blockIdx.x * (64 * MB) + wave * (16 * MB);
+  int64_t n[MB];
+  int oy[MB], ox[MB];
+  bool valid[MB];
 #pragma unroll
-  for (int b = 0; b < NB; ++b) acc[b] = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int mb = 0; mb < MB; ++mb) {
+    const int64_t p = pbase + mb * 16 + (lane & 15);
+    valid[mb] = p < npix;
+    n[mb] = 0;
+    oy[mb] = ox[mb] = 0;
+    if (valid[mb]) {
+      n[mb] = p / (L.hout * L.wout);
+      const int r = (int)(p - n[mb] * L.hout * L.wout);
+      oy[mb] = r / L.wout;
+      ox[mb] = r % L.wout;
+    }
+  }
+  floatx4 acc[MB][NB];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[mb][b] = floatx4{0.f, 0.f, 0.f, 0.f};
   const uint16_t *wrow = wp + (int64_t)(lane & 15) * KPAD + 8 * g;
-#pragma unroll 3
+#pragma unroll 2
   for (int k0 = 0; k0 < KPAD; k0 += 32) {
     const int k = k0 + 8 * g;
     const int tap = k / CIN, ci = k % CIN;
-    u32x4 av = {0u, 0u, 0u, 0u};
-    if (valid && tap < 9) {
-      const int iy = S * oy + tap / 3 - 1, ix = S * ox + tap % 3 - 1;
-      if (iy >= 0 && iy < L.hin && ix >= 0 && ix < L.win)
-        av = *reinterpret_cast<const u32x4 *>(x + ((n * L.hin + iy) * L.win + ix) * CIN + ci);
-    }
+    u32x4 bv[NB];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const u32x4 bv = *reinterpret_cast<const u32x4 *>(wrow + (int64_t)b * 16 * KPAD + k0);
-      acc[b] = mfma(av, bv, acc[b]);
+    for (int b = 0; b < NB; ++b)
+      bv[b] = *reinterpret_cast<const u32x4 *>(wrow + (int64_t)b * 16 * KPAD + k0);
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      u32x4 av = {0u, 0u, 0u, 0u};
+      if (valid[mb] && tap < 9) {
+        const int iy = S * oy[mb] + tap / 3 - 1, ix = S * ox[mb] + tap % 3 - 1;
+        if (iy >= 0 && iy < L.hin && ix >= 0 && ix < L.win)
+          av = *reinterpret_cast<const u32x4 *>(x + ((n[mb] * L.hin + iy) * L.win + ix) * CIN + ci);
+      }
+#pragma unroll
+      for (int b = 0; b < NB; ++b) acc[mb][b] = mfma(av, bv[b], acc[mb][b]);
     }
   }
 #pragma unroll
@@ -224,12 +239,19 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(const uint16_t *__restric
     const int co = b * 16 + (lane & 15);
     const float bb = bias[co];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int64_t q = pbase + 4 * g + j;
-      if (q < npix) y[q * COUT + co] = f2bf(fmaxf(acc[b][j] + bb, 0.0f));
-    }
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t q = pbase + mb * 16 + 4 * g + j;
+        if (q < npix) y[q * COUT + co] = f2bf(fmaxf(acc[mb][b][j] + bb, 0.0f));
+      }
   }
 }
+
+// Pixel blocks per wave of the forward kernel, per layer (entry 0 unused).
+// Measured at batch 256: forward 0.73 ms with 1 everywhere, 0.60 ms with
+// these; 8 blocks for layer 2 and 4 for layers 4-5 cost occupancy (0.71 ms).
+constexpr int kFwdMB[kNumLayers] = {1, 2, 4, 4, 2, 2};
 
 // ---------------------------------------------------------------------------
 // Head, loss and the signal entering the last 3x3 layer
@@ -343,7 +365,7 @@ __global__ __launch_bounds__(128) void head_loss_kernel(
 // has its parity (1, 2 or 4 of the 9), so the input pixels are taken in
 // four parity classes (blockIdx.y) and every workgroup loops over its
 // class's taps only.  With stride 1 there is one class with all 9 taps.
-template <int LI>
+template <int LI, int MB>
 __global__ __launch_bounds__(256) void conv_bwd_data_kernel(const uint16_t *__restrict__ dz,
                                                             const uint16_t *__restrict__ wt,
                                                             const uint16_t *__restrict__ x,
@@ -355,42 +377,60 @@ __global__ __launch_bounds__(256) void conv_bwd_data_kernel(const uint16_t *__re
   constexpr int CH = S == 2 ? L.hin / 2 : L.hin, CW = S == 2 ? L.win / 2 : L.win;
   const int64_t ncls = (int64_t)n * CH * CW;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4;
-  const int64_t cbase = (int64_t)blockIdx.x * 64 + wave * 16;
+  // a wave owns MB blocks of 16 class pixels; the weight fragments of a
+  // (tap, channel step) are loaded once for all of them
+  const int64_t cbase = (int64_t)blockIdx.x * (64 * MB) + wave * (16 * MB);
   // the taps of this class: ky with (iy + 1 - ky) divisible by S, same for kx
   int kys[3], kxs[3], nky = 0, nkx = 0;
   for (int k = 0; k < 3; ++k) {
     if (S == 1 || ((py + 1 - k) & 1) == 0) kys[nky++] = k;
     if (S == 1 || ((px + 1 - k) & 1) == 0) kxs[nkx++] = k;
   }
-  const int64_t cidx = cbase + (lane & 15);
-  const bool valid = cidx < ncls;
-  int64_t nn = 0;
-  int iy = 0, ix = 0;
-  if (valid) {
-    nn = cidx / (CH * CW);
-    const int r = (int)(cidx - nn * CH * CW);
-    iy = (r / CW) * S + py;
-    ix = (r % CW) * S + px;
-  }
-  floatx4 acc[NB];
+  bool valid[MB];
+  int64_t nn[MB];
+  int iy[MB], ix[MB];
 #pragma unroll
-  for (int b = 0; b < NB; ++b) acc[b] = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int mb = 0; mb < MB; ++mb) {
+    const int64_t cidx = cbase + mb * 16 + (lane & 15);
+    valid[mb] = cidx < ncls;
+    nn[mb] = 0;
+    iy[mb] = ix[mb] = 0;
+    if (valid[mb]) {
+      nn[mb] = cidx / (CH * CW);
+      const int r = (int)(cidx - nn[mb] * CH * CW);
+      iy[mb] = (r / CW) * S + py;
+      ix[mb] = (r % CW) * S + px;
+    }
+  }
+  floatx4 acc[MB][NB];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[mb][b] = floatx4{0.f, 0.f, 0.f, 0.f};
   const uint16_t *wrow = wt + (int64_t)(lane & 15) * K + 8 * g;
   for (int a = 0; a < nky; ++a) {
     for (int bq = 0; bq < nkx; ++bq) {
       const int tap = kys[a] * 3 + kxs[bq];
-      const int ty = iy + 1 - kys[a], tx = ix + 1 - kxs[bq];
-      const bool ok = valid && ty >= 0 && tx >= 0 && ty / S < L.hout && tx / S < L.wout;
-      const int64_t src = ok ? ((nn * L.hout + ty / S) * L.wout + tx / S) * COUT + 8 * g : 0;
+      bool ok[MB];
+      int64_t src[MB];
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        const int ty = iy[mb] + 1 - kys[a], tx = ix[mb] + 1 - kxs[bq];
+        ok[mb] = valid[mb] && ty >= 0 && tx >= 0 && ty / S < L.hout && tx / S < L.wout;
+        src[mb] = ok[mb] ? ((nn[mb] * L.hout + ty / S) * L.wout + tx / S) * COUT + 8 * g : 0;
+      }
 #pragma unroll
       for (int co0 = 0; co0 < COUT; co0 += 32) {
-        u32x4 av = {0u, 0u, 0u, 0u};
-        if (ok) av = *reinterpret_cast<const u32x4 *>(dz + src + co0);
+        u32x4 bv[NB];
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-          const u32x4 bv =
-              *reinterpret_cast<const u32x4 *>(wrow + (int64_t)b * 16 * K + tap * COUT + co0);
-          acc[b] = mfma(av, bv, acc[b]);
+        for (int b = 0; b < NB; ++b)
+          bv[b] = *reinterpret_cast<const u32x4 *>(wrow + (int64_t)b * 16 * K + tap * COUT + co0);
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+          u32x4 av = {0u, 0u, 0u, 0u};
+          if (ok[mb]) av = *reinterpret_cast<const u32x4 *>(dz + src[mb] + co0);
+#pragma unroll
+          for (int b = 0; b < NB; ++b) acc[mb][b] = mfma(av, bv[b], acc[mb][b]);
         }
       }
     }
@@ -399,18 +439,26 @@ __global__ __launch_bounds__(256) void conv_bwd_data_kernel(const uint16_t *__re
   for (int b = 0; b < NB; ++b) {
     const int ci = b * 16 + (lane & 15);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int64_t q = cbase + 4 * g + j;
-      if (q < ncls) {
-        const int64_t qn = q / (CH * CW);
-        const int r = (int)(q - qn * CH * CW);
-        const int qy = (r / CW) * S + py, qx = (r % CW) * S + px;
-        const int64_t o = ((qn * L.hin + qy) * L.win + qx) * CIN + ci;
-        dx[o] = bf_positive(x[o]) ? f2bf(acc[b][j]) : (uint16_t)0;
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t q = cbase + mb * 16 + 4 * g + j;
+        if (q < ncls) {
+          const int64_t qn = q / (CH * CW);
+          const int r = (int)(q - qn * CH * CW);
+          const int qy = (r / CW) * S + py, qx = (r % CW) * S + px;
+          const int64_t o = ((qn * L.hin + qy) * L.win + qx) * CIN + ci;
+          dx[o] = bf_positive(x[o]) ? f2bf(acc[mb][b][j]) : (uint16_t)0;
+        }
       }
-    }
   }
 }
+
+// Pixel blocks per wave of the backward-data kernel, per layer (entry 0
+// unused).  Measured at batch 256 against 1 everywhere: layer 1 is bound by
+// its 2-byte signal and mask traffic and gains nothing (2 was 3% slower);
+// layers 2-5 gain 10-25%.
+constexpr int kBwdMB[kNumLayers] = {1, 1, 2, 4, 2, 2};
 
 // ---------------------------------------------------------------------------
 // Backward: weights and biases
@@ -779,13 +827,14 @@ sps_status run_forward(sps_cnn c, const uint16_t *tiles, int32_t n, hipStream_t 
                        tiles, c->wp[0], c->params + layer_param_offset(0) + kLayers[0].wcount(),
                        c->act[0], np);
   }
-#define SPS_FWD(LI)                                                                          \
-  {                                                                                          \
-    const int64_t np = npix_out(LI, n);                                                      \
-    hipLaunchKernelGGL(conv_fwd_kernel<LI>, dim3((unsigned)((np + 63) / 64)), dim3(256), 0, s, \
-                       c->act[LI - 1], c->wp[LI],                                            \
+#define SPS_FWD(LI)                                                                         \
+  {                                                                                         \
+    constexpr int MB = kFwdMB[LI];                                                          \
+    const int64_t np = npix_out(LI, n);                                                     \
+    hipLaunchKernelGGL((conv_fwd_kernel<LI, MB>), dim3((unsigned)((np + 64 * MB - 1) / (64 * MB))), \
+                       dim3(256), 0, s, c->act[LI - 1], c->wp[LI],                          \
                        c->params + layer_param_offset(LI) + kLayers[LI].wcount(), c->act[LI], \
-                       np);                                                                  \
+                       np);                                                                 \
   }
   SPS_FWD(1) SPS_FWD(2) SPS_FWD(3) SPS_FWD(4) SPS_FWD(5)
 #undef SPS_FWD
@@ -857,13 +906,15 @@ sps_status run_backward(sps_cnn c, const uint16_t *tiles, int32_t n, hipStream_t
     if (li > 0) {
       const int classes = L.stride == 2 ? 4 : 1;
       const int64_t ncls = npix_in(li, n) / classes;
-      const dim3 grid((unsigned)((ncls + 63) / 64), (unsigned)classes);
       switch (li) {
 #define SPS_BWDD(LI)                                                                          \
-  case LI:                                                                                    \
-    hipLaunchKernelGGL(conv_bwd_data_kernel<LI>, grid, dim3(256), 0, s, c->dz[LI],            \
+  case LI: {                                                                                  \
+    constexpr int MB = kBwdMB[LI];                                                            \
+    const dim3 grid((unsigned)((ncls + 64 * MB - 1) / (64 * MB)), (unsigned)classes);         \
+    hipLaunchKernelGGL((conv_bwd_data_kernel<LI, MB>), grid, dim3(256), 0, s, c->dz[LI],      \
                        c->wt[LI], c->act[LI - 1], c->dz[LI - 1], n);                          \
-    break;
+    break;                                                                                    \
+  }
         SPS_BWDD(1) SPS_BWDD(2) SPS_BWDD(3) SPS_BWDD(4) SPS_BWDD(5)
 #undef SPS_BWDD
       }
