@@ -141,6 +141,44 @@ def test_dedisperse_random_shapes_bitexact(sps, seed):
     assert np.array_equal(Yg, Yo)
 
 
+@pytest.mark.parametrize("seed", range(6))
+def test_dedisperse_every_tiling_bitexact(sps, seed):
+    # every compiled tiling on shapes with partial slabs (channel counts off
+    # the 8- and 16-channel slabs), partial DM blocks and ragged time tiles;
+    # the staged delay table is rebuilt for each tiling
+    rng = np.random.Generator(np.random.PCG64(1000 + seed))
+    nchan = int([7, 17, 40, 129, 263, 9][seed])
+    ndm = int(rng.choice([3, 9, 17, 23]))
+    nout = int(rng.choice([700, 1281, 3001, 4099]))
+    # small delay spreads fit the short staged rows; larger ones need the
+    # tilings with longer rows (4, 5 and 8 KB)
+    dm_hi = [12.0, 150.0, 10.0, 250.0, 7.0, 420.0][seed]
+    wl = Workload("tiles", nchan, 1100.0, 1500.0, 98.304e-6, nout, ndm, 0.0, dm_hi, (1,))
+    Do = oracle.delays(wl.freqs_mhz(), wl.fref_mhz, wl.tsamp_s, wl.dms())
+    nsamp = nout + int(Do.max()) - (int(rng.integers(0, 50)) if seed % 2 else 0)
+    X = synth.random_bytes(nchan, nsamp, seed=seed + 500)
+    Yo = oracle.dedisperse(X, Do, nout, nsamp)
+    Xd = to_device_pitched(X, nsamp, pad=1)
+    tried = set()
+    with sps.plan_for(wl) as plan:
+        for i in range(sps.sps_tiling_count()):
+            t = sps.sps_tiling_describe(i)
+            try:
+                sps.sps_plan_set_tiling(plan, t["m"], t["dpw"], t["nw"], t["cs"],
+                                        t["waves_per_eu"])
+            except sps.SpsError as e:
+                assert e.name == "SPS_ERR_RANGE"  # rows too long for this tiling
+                continue
+            got = sps.sps_plan_get_tiling(plan)
+            assert (got["m"], got["cs"], got["waves_per_eu"]) == (t["m"], t["cs"], t["waves_per_eu"])
+            Yg = gpu_dedisperse(sps, plan, Xd, nsamp, nout, sps.SPS_ZERO_PAD)
+            assert np.array_equal(Yg, Yo), got
+            tried.add(tuple(sorted(got.items())))
+        sps.sps_plan_set_tiling(plan, 0, 0, 0, 0, 0)  # the plain kernel
+        assert np.array_equal(gpu_dedisperse(sps, plan, Xd, nsamp, nout, sps.SPS_ZERO_PAD), Yo)
+    assert tried
+
+
 def test_dedisperse_strict_mode_rejects_short_input(sps):
     wl = SINGLE_BEAM
     with sps.plan_for(wl) as plan:
