@@ -268,6 +268,17 @@ sps_status sps_batch_enqueue(sps_batch batch, void *stream);
  * (and re-captured if the stream changes).  stream must not be NULL. */
 sps_status sps_batch_launch_graph(sps_batch batch, void *stream);
 
+/* Batch autotuner: times the batch's own persistent dedispersion launch
+ * over its beams with every compiled tiling that fits the plan (iters timed
+ * launches each, HIP events, after one warm-up) and keeps the fastest for
+ * this batch (the plan's tiling is unchanged).  Overwrites the beams' Y.
+ * ms_out (optional) receives the mean time per tiling index (-1 where it
+ * does not fit); *n_tried the number timed.  Allocates and frees the staged
+ * tables it times; synchronises the stream; the next sps_batch_launch_graph
+ * captures a new graph. */
+sps_status sps_batch_autotune(sps_batch batch, int32_t iters, void *stream, float *ms_out,
+                              int32_t *n_tried);
+
 /* Synchronises the stream and returns beam's candidates as sps_detect does
  * (same order, TRUNCATED / RANGE rules). */
 sps_status sps_batch_candidates(sps_batch batch, int32_t beam, sps_candidate *out, int32_t cap,

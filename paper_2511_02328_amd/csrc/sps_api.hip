@@ -775,6 +775,20 @@ void free_batch(sps_batch b) {
   delete b;
 }
 
+// Dedispersion item ranges of the beams (and the persistent grid) for
+// tiling c; host side only.
+void layout_dedisp(sps_batch b, const sps::DedispConfig &c) {
+  int64_t items = 0;
+  for (int i = 0; i < b->nbeams; ++i) {
+    b->beams[(size_t)i].dd_begin = items;
+    items += sps::dedisp_batch_items(c, b->plan->ndm, b->nout[(size_t)i]);
+  }
+  b->dd_items = items;
+  const int64_t persistent = 256 * 2;
+  const int64_t g = items < persistent ? items : persistent;
+  b->grid_dd = (int)(((g + 7) / 8) * 8);
+}
+
 sps_status batch_enqueue(sps_batch b, hipStream_t s) {
   sps_plan p = b->plan;
   hipError_t e = sps::launch_dedisperse_batch(b->cfg, b->lds_pitch, b->d_beams, b->nbeams,
@@ -858,14 +872,12 @@ sps_status sps_batch_create(sps_plan plan, int32_t nbeams, const sps_beam *beams
     w.snr = q.snr;
     w.best = q.best_w;
     w.stats = q.stats;
-    w.dd_begin = b->dd_items;
     w.bx_begin = b->bx_blocks;
     w.tp_begin = b->tp_tiles;
     w.nseg = sps::boxcar_segments(q.nout);
     w.ntt = (q.nout + prm->tile_t - 1) / prm->tile_t;
     w.vec_store = (q.nout % 4 == 0) && aligned16(q.Y);
     w.pad = 0;
-    b->dd_items += sps::dedisp_batch_items(b->cfg, plan->ndm, q.nout);
     b->bx_blocks += w.nseg * plan->ndm;
     b->tp_tiles += w.ntt * ntd;
     b->nout[(size_t)i] = q.nout;
@@ -878,9 +890,7 @@ sps_status sps_batch_create(sps_plan plan, int32_t nbeams, const sps_beam *beams
     free_batch(b);
     return fail(SPS_ERR_RANGE, "batch too large");
   }
-  const int64_t persistent = 256 * 2;
-  const int64_t g = b->dd_items < persistent ? b->dd_items : persistent;
-  b->grid_dd = (int)(((g + 7) / 8) * 8);
+  layout_dedisp(b, b->cfg);
   DeviceScope scope(plan->device);
   hipError_t e = hipMalloc(&b->d_beams, sizeof(sps::BeamWork) * (size_t)nbeams);
   if (e == hipSuccess) e = hipMalloc(&b->d_peaks, sizeof(sps::TilePeak) * (size_t)b->tp_tiles);
@@ -950,6 +960,80 @@ sps_status sps_batch_launch_graph(sps_batch batch, void *stream) {
   }
   hipError_t e = hipGraphLaunch(batch->exec, s);
   if (e != hipSuccess) return hip_fail(e, "launching the graph");
+  return SPS_OK;
+}
+
+sps_status sps_batch_autotune(sps_batch batch, int32_t iters, void *stream, float *ms_out,
+                              int32_t *n_tried) {
+  g_error.clear();
+  if (!batch) return fail(SPS_ERR_INVALID_ARG, "batch is NULL");
+  if (iters < 1 || iters > 100) return fail(SPS_ERR_INVALID_ARG, "need 1 <= iters <= 100");
+  sps_plan p = batch->plan;
+  DeviceScope scope(p->device);
+  if (scope.err != hipSuccess) return hip_fail(scope.err, "selecting the plan's device");
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipError_t e = hipEventCreate(&ev0);
+  if (e == hipSuccess) e = hipEventCreate(&ev1);
+  float best_ms = 1e30f;
+  int best = -1;
+  int64_t best_pitch = 0;
+  int tried = 0;
+  const int nprefs = (int)(sizeof(kPrefs) / sizeof(kPrefs[0]));
+  for (int i = 0; i < nprefs && e == hipSuccess; ++i) {
+    const sps::DedispConfig &c = kPrefs[i];
+    if (ms_out) ms_out[i] = -1.0f;
+    const int64_t lp = fitted_pitch(p, c, 160 * 1024);
+    if (lp <= 0) continue;
+    layout_dedisp(batch, c);
+    e = hipMemcpy(batch->d_beams, batch->beams.data(),
+                  sizeof(sps::BeamWork) * (size_t)batch->nbeams, hipMemcpyHostToDevice);
+    sps::StagedDelays sd;
+    if (e == hipSuccess) e = sps::stage_delays(sd, c, (int)lp, p->d_delays, p->nchan, p->ndm);
+    if (e == hipSuccess)  // warm-up
+      e = sps::launch_dedisperse_batch(c, (int)lp, batch->d_beams, batch->nbeams,
+                                       batch->dd_items, sd, p->nchan, p->ndm, batch->grid_dd, s);
+    if (e == hipSuccess) e = hipEventRecord(ev0, s);
+    for (int it = 0; it < iters && e == hipSuccess; ++it)
+      e = sps::launch_dedisperse_batch(c, (int)lp, batch->d_beams, batch->nbeams,
+                                       batch->dd_items, sd, p->nchan, p->ndm, batch->grid_dd, s);
+    if (e == hipSuccess) e = hipEventRecord(ev1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(ev1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);  // before its table is freed
+    sps::free_staged(sd);
+    if (e != hipSuccess) break;
+    ms /= (float)iters;
+    if (ms_out) ms_out[i] = ms;
+    ++tried;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = i;
+      best_pitch = lp;
+    }
+  }
+  if (ev0) (void)hipEventDestroy(ev0);
+  if (ev1) (void)hipEventDestroy(ev1);
+  if (n_tried) *n_tried = tried;
+  // keep the fastest (or restore the batch's tiling after a failure)
+  const sps::DedispConfig keep = best >= 0 && e == hipSuccess ? kPrefs[best] : batch->cfg;
+  const int keep_pitch = best >= 0 && e == hipSuccess ? (int)best_pitch : batch->lds_pitch;
+  layout_dedisp(batch, keep);
+  hipError_t e2 = hipMemcpy(batch->d_beams, batch->beams.data(),
+                            sizeof(sps::BeamWork) * (size_t)batch->nbeams, hipMemcpyHostToDevice);
+  if (e2 == hipSuccess)
+    e2 = sps::stage_delays(batch->staged, keep, keep_pitch, p->d_delays, p->nchan, p->ndm);
+  batch->cfg = keep;
+  batch->lds_pitch = keep_pitch;
+  // the captured graph holds the old tiling's launch
+  if (batch->exec) (void)hipGraphExecDestroy(batch->exec);
+  if (batch->graph) (void)hipGraphDestroy(batch->graph);
+  batch->exec = nullptr;
+  batch->graph = nullptr;
+  if (e != hipSuccess) return hip_fail(e, "batch autotuning");
+  if (e2 != hipSuccess) return hip_fail(e2, "restaging the batch");
+  if (tried == 0) return fail(SPS_ERR_RANGE, "no compiled tiling fits this plan");
   return SPS_OK;
 }
 

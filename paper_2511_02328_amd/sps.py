@@ -115,6 +115,7 @@ def library() -> ctypes.CDLL:
         lib.sps_batch_candidates.argtypes = [P, i32, ctypes.POINTER(sps_candidate), i32,
                                              ctypes.POINTER(i32), P]
         lib.sps_plan_autotune.argtypes = [P, i64, i32, P, P, ctypes.POINTER(i32)]
+        lib.sps_batch_autotune.argtypes = [P, i32, P, P, ctypes.POINTER(i32)]
         lib.sps_tiling_count.argtypes = []
         lib.sps_tiling_count.restype = i32
         lib.sps_tiling_describe.argtypes = [i32] + [ctypes.POINTER(i32)] * 5
@@ -170,7 +171,7 @@ def library() -> ctypes.CDLL:
                   "sps_subband_plan_create", "sps_subband_tables", "sps_dedisperse_subband",
                   "sps_zero_dm", "sps_downsample_sqrt", "sps_batch_create", "sps_batch_destroy",
                   "sps_batch_enqueue", "sps_batch_launch_graph", "sps_batch_candidates",
-                  "sps_plan_autotune", "sps_tiling_describe"):
+                  "sps_plan_autotune", "sps_batch_autotune", "sps_tiling_describe"):
             getattr(lib, f).restype = ctypes.c_int
         lib.sps_last_error.argtypes = []
         lib.sps_last_error.restype = ctypes.c_char_p
@@ -459,6 +460,17 @@ def sps_tiling_describe(index: int) -> dict:
     _check(library().sps_tiling_describe(int(index), *[ctypes.byref(x) for x in v]),
            "sps_tiling_describe")
     return dict(zip(("m", "dpw", "nw", "cs", "waves_per_eu"), (x.value for x in v)))
+
+
+def sps_batch_autotune(batch: Batch, iters: int = 3, stream=None) -> list:
+    """Mean ms of the batch's dedispersion launch per compiled tiling (-1 where
+    it does not fit); the batch keeps the fastest."""
+    n = sps_tiling_count()
+    ms = np.full(n, -1.0, dtype=np.float32)
+    tried = ctypes.c_int32()
+    _check(library().sps_batch_autotune(batch.handle, int(iters), _stream(stream),
+                                        ms.ctypes.data, ctypes.byref(tried)), "sps_batch_autotune")
+    return [float(x) for x in ms]
 
 
 def sps_plan_autotune(plan: Plan, nout_probe: int, iters: int = 3, stream=None) -> list:

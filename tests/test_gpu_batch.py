@@ -125,3 +125,30 @@ def test_autotune_keeps_results(sps):
         sps.sps_dedisperse(plan, Xd, wl.nout + dmax, Y1, wl.nout)
         torch.cuda.synchronize()
         assert torch.equal(Y0, Y1)
+
+
+def test_batch_autotune_keeps_results(sps):
+    # the batch times its own persistent launch per tiling, keeps the
+    # fastest, and a graph captured before the autotuning is replaced
+    nouts = [3000, 9000, 1281, 5000]
+    wl = _wl(nouts[0], 0)
+    widths = list(wl.widths)
+    stream = torch.cuda.Stream()
+    with sps.plan_for(wl) as plan:
+        _, dmax = sps.sps_plan_delays(plan)
+        plan_tiling = sps.sps_plan_get_tiling(plan)
+        beams = _beams(sps, plan, nouts, dmax, pad=1)
+        with sps.sps_batch_create(plan, beams, widths, **DET) as batch:
+            sps.sps_batch_launch_graph(batch, stream)
+            stream.synchronize()
+            ms = sps.sps_batch_autotune(batch, 2, stream)
+            assert sum(m > 0 for m in ms) >= 2
+            assert sps.sps_plan_get_tiling(plan) == plan_tiling  # the plan is untouched
+            for b in beams:
+                b["Y"].zero_()
+            sps.sps_batch_launch_graph(batch, stream)
+            stream.synchronize()
+            _check_beams(sps, plan, batch, beams, widths)
+            D = oracle.delays(wl.freqs_mhz(), wl.fref_mhz, wl.tsamp_s, wl.dms())
+            Yo = oracle.dedisperse(beams[1]["Xh"], D, nouts[1])
+            assert np.array_equal(beams[1]["Y"].cpu().numpy().view(np.uint32), Yo)
