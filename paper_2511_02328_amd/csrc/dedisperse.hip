@@ -79,6 +79,8 @@ __device__ __forceinline__ void add_pair(uint32_t (&ev)[M], uint32_t (&od)[M],
   }
 }
 
+typedef unsigned int vu4 __attribute__((ext_vector_type(4)));
+
 template <int CS, int NW, int KMAX>
 struct SlabRegs {
   static constexpr int RPW = CS / NW;
@@ -137,6 +139,29 @@ __device__ __forceinline__ void slab_load(SlabRegs<CS, NW, KMAX> &st, const uint
   }
 }
 
+// Interior form of slab_load, for workgroups whose every staged window lies
+// below nsamp_in and whose slabs are all whole (nchan a multiple of CS): no
+// guards and no clearing.  Every lane loads; lanes past the row repeat its
+// last vector, which slab_store skips.
+template <int CS, int NW, int KMAX>
+__device__ __forceinline__ void slab_load_interior(SlabRegs<CS, NW, KMAX> &st,
+                                                   const uint8_t *__restrict__ X, int64_t pitch,
+                                                   const int32_t *__restrict__ Bb, int c0,
+                                                   int64_t t0, int vpr, int wave, int lane) {
+#pragma unroll
+  for (int i = 0; i < SlabRegs<CS, NW, KMAX>::RPW; ++i) {
+    const int c = c0 + wave + NW * i;
+    // native 4-vector loads: a struct copy of uint4 becomes a memcpy that
+    // the compiler keeps in scratch memory
+    const vu4 *src = reinterpret_cast<const vu4 *>(X + (int64_t)c * pitch + t0 + (int64_t)Bb[c]);
+#pragma unroll
+    for (int u = 0; u < KMAX; ++u) {
+      const vu4 v = src[min(lane + 64 * u, vpr - 1)];
+      st.v[i][u] = make_uint4(v.x, v.y, v.z, v.w);
+    }
+  }
+}
+
 template <int CS, int NW, int KMAX>
 __device__ __forceinline__ void slab_store(const SlabRegs<CS, NW, KMAX> &st, uint4 *buf, int vpr,
                                            int wave, int lane) {
@@ -190,7 +215,7 @@ __device__ __forceinline__ void store_acc(const uint32_t (&acc)[DPW][M][4], uint
 // 256 channels, ending at a segment end), the fold of the u16 halves after
 // each group, so the slab loop carries the packed accumulators without
 // branches.  Padded channels of a last partial slab point at zeroed rows.
-template <int M, int DPW, int NW, int CS, int KMAX, bool SEG = false>
+template <int M, int DPW, int NW, int CS, int KMAX, bool SEG = false, bool INTERIOR = false>
 __device__ __forceinline__ void dedisperse_block(
     const uint8_t *__restrict__ X, int64_t pitch, int64_t nsamp_in, const int2 *__restrict__ P,
     int pcols, const int32_t *__restrict__ B, int nchan, int ndm, uint32_t *__restrict__ Y,
@@ -228,7 +253,10 @@ __device__ __forceinline__ void dedisperse_block(
   const uint32_t *lds32 = reinterpret_cast<const uint32_t *>(smem);
   SlabRegs<CS, NW, KMAX> st;
 
-  slab_load(st, X, pitch, nsamp_in, Bb, 0, min(CS, nchan), t0, vpr, wave, lane);
+  if constexpr (INTERIOR)
+    slab_load_interior(st, X, pitch, Bb, 0, t0, vpr, wave, lane);
+  else
+    slab_load(st, X, pitch, nsamp_in, Bb, 0, min(CS, nchan), t0, vpr, wave, lane);
   slab_store(st, smem, vpr, wave, lane);
   __syncthreads();
 
@@ -241,7 +269,12 @@ __device__ __forceinline__ void dedisperse_block(
     for (int c0 = g0; c0 < g1; c0 += CS) {
       const int c1 = c0 + CS;
       const bool more = c1 < nchan;
-      if (more) slab_load(st, X, pitch, nsamp_in, Bb, c1, min(CS, nchan - c1), t0, vpr, wave, lane);
+      if (more) {
+        if constexpr (INTERIOR)
+          slab_load_interior(st, X, pitch, Bb, c1, t0, vpr, wave, lane);
+        else
+          slab_load(st, X, pitch, nsamp_in, Bb, c1, min(CS, nchan - c1), t0, vpr, wave, lane);
+      }
       const int bo = parity * buf_dw;
 #pragma unroll
       for (int k = 0; k < DPW; ++k) {
@@ -307,7 +340,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) 
 dedisperse_kernel(const uint8_t *__restrict__ X, int64_t pitch, int64_t nsamp_in,
                   const int2 *__restrict__ P, int pcols, const int32_t *__restrict__ B, int nchan,
                   int ndm, uint32_t *__restrict__ Y, int64_t nout, int lds_pitch, int ntiles,
-                  int ndmb, int per_xcd, int vec_store, int seg, int64_t seg_stride) {
+                  int ndmb, int per_xcd, int vec_store, int seg, int64_t seg_stride, int dmax) {
   extern __shared__ uint4 smem[];  // two slab buffers of CS rows x lds_pitch bytes
   const int blk = blockIdx.x;
   const int logical = (blk & 7) * per_xcd + (blk >> 3);
@@ -319,9 +352,16 @@ dedisperse_kernel(const uint8_t *__restrict__ X, int64_t pitch, int64_t nsamp_in
   const int rem = logical - panel * (ntiles * kPanel);
   const int tile = rem / pd;
   const int dblk = panel * kPanel + rem % pd;
-  dedisperse_block<M, DPW, NW, CS, KMAX, SEG>(X, pitch, nsamp_in, P, pcols, B, nchan, ndm, Y, nout,
-                                              lds_pitch, vec_store, (int64_t)tile * (256 * M),
-                                              dblk, smem, seg, seg_stride);
+  const int64_t t0 = (int64_t)tile * (256 * M);
+  // every staged row starts at or below t0 + dmax and spans lds_pitch bytes
+  if (nchan % CS == 0 && t0 + dmax + lds_pitch <= nsamp_in)
+    dedisperse_block<M, DPW, NW, CS, KMAX, SEG, true>(X, pitch, nsamp_in, P, pcols, B, nchan, ndm,
+                                                      Y, nout, lds_pitch, vec_store, t0, dblk,
+                                                      smem, seg, seg_stride);
+  else
+    dedisperse_block<M, DPW, NW, CS, KMAX, SEG, false>(X, pitch, nsamp_in, P, pcols, B, nchan,
+                                                       ndm, Y, nout, lds_pitch, vec_store, t0,
+                                                       dblk, smem, seg, seg_stride);
 }
 
 // Persistent kernel over many filterbanks that share a plan (beams of one
@@ -332,7 +372,7 @@ template <int M, int DPW, int NW, int CS, int KMAX, int WPE>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) void
 dedisperse_batch_kernel(const BeamWork *__restrict__ beams, int nbeams, int64_t total_items,
                         const int2 *__restrict__ P, int pcols, const int32_t *__restrict__ B,
-                        int nchan, int ndm, int lds_pitch, int ndmb) {
+                        int nchan, int ndm, int lds_pitch, int ndmb, int dmax) {
   extern __shared__ uint4 smem[];
   const int G = gridDim.x;
   const int w = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
@@ -343,10 +383,16 @@ dedisperse_batch_kernel(const BeamWork *__restrict__ beams, int nbeams, int64_t 
     const int64_t local = item - bw.dd_begin;
     const int dblk = (int)(local % ndmb);
     const int64_t tile = local / ndmb;
-    dedisperse_block<M, DPW, NW, CS, KMAX>(bw.X, bw.pitch, bw.nsamp_in, P, pcols, B, nchan, ndm,
-                                           bw.Y,
-                                           bw.nout, lds_pitch, bw.vec_store, tile * (256 * M),
-                                           dblk, smem);
+    const int64_t t0 = tile * (256 * M);
+    if (nchan % CS == 0 && t0 + dmax + lds_pitch <= bw.nsamp_in)
+      dedisperse_block<M, DPW, NW, CS, KMAX, false, true>(bw.X, bw.pitch, bw.nsamp_in, P, pcols, B,
+                                                          nchan, ndm, bw.Y, bw.nout, lds_pitch,
+                                                          bw.vec_store, t0, dblk, smem);
+    else
+      dedisperse_block<M, DPW, NW, CS, KMAX, false, false>(bw.X, bw.pitch, bw.nsamp_in, P, pcols,
+                                                           B, nchan, ndm, bw.Y, bw.nout,
+                                                           lds_pitch, bw.vec_store, t0, dblk,
+                                                           smem);
   }
 }
 
@@ -427,7 +473,7 @@ hipError_t launch_cfg(int lds_pitch, const uint8_t *X, int64_t pitch, int64_t ns
   }
   hipLaunchKernelGGL(kern, dim3(grid), dim3(NW * 64), lds, stream, X, pitch, nsamp_in, sd.P,
                      sd.pcols, sd.B, nchan, ndm, Y, nout, lds_pitch, (int)ntiles64, ndmb, per_xcd,
-                     vec_store, seg, seg_stride);
+                     vec_store, seg, seg_stride, sd.dmax);
   return hipGetLastError();
 }
 
@@ -447,7 +493,7 @@ hipError_t launch_batch_cfg(int lds_pitch, const BeamWork *beams, int nbeams, in
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(kern, dim3(grid), dim3(NW * 64), lds, stream, beams, nbeams, total, sd.P,
-                     sd.pcols, sd.B, nchan, ndm, lds_pitch, ndmb);
+                     sd.pcols, sd.B, nchan, ndm, lds_pitch, ndmb, sd.dmax);
   return hipGetLastError();
 }
 
@@ -549,12 +595,12 @@ void free_staged(StagedDelays &sd) {
 }
 
 hipError_t stage_delays(StagedDelays &sd, const DedispConfig &c, int lds_pitch, const int32_t *D,
-                        int nchan, int ndm) {
+                        int nchan, int ndm, int32_t dmax) {
   if (c.m == 0) {
     free_staged(sd);
     return hipSuccess;
   }
-  if (sd.matches(c, lds_pitch, nchan, ndm)) return hipSuccess;
+  if (sd.matches(c, lds_pitch, nchan, ndm) && sd.dmax == dmax) return hipSuccess;
   if (nchan < 1 || ndm < 1 || lds_pitch % 16 != 0 || c.nd() < 1 || c.cs < 1)
     return hipErrorInvalidValue;
   const int pcols = (nchan + c.cs - 1) / c.cs * c.cs;
@@ -578,6 +624,7 @@ hipError_t stage_delays(StagedDelays &sd, const DedispConfig &c, int lds_pitch, 
     return e;
   }
   sd.nchan = nchan;
+  sd.dmax = dmax;
   sd.pcols = pcols;
   sd.ndm = ndm;
   sd.nd = c.nd();

@@ -5,6 +5,7 @@
 // plan in IEEE double and uploaded, argument validation before anything is
 // enqueued, and turning the detection kernels' output into candidate
 // records.  Every step of the search itself runs in the HIP kernels.
+#include <algorithm>
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
@@ -172,7 +173,8 @@ sps_status restage(sps_plan p) {
   DeviceScope scope(p->device);
   if (scope.err != hipSuccess) return hip_fail(scope.err, "selecting the plan's device");
   const hipError_t e =
-      sps::stage_delays(p->staged, p->cfg, p->lds_pitch, p->d_delays, p->nchan, p->ndm);
+      sps::stage_delays(p->staged, p->cfg, p->lds_pitch, p->d_delays, p->nchan, p->ndm,
+                        p->max_delay);
   if (e == hipErrorOutOfMemory) {
     (void)hipGetLastError();
     return fail(SPS_ERR_NOMEM, "device allocation of the staged delay table failed");
@@ -593,7 +595,8 @@ sps_status sps_subband_plan_create(const sps_subband_desc *desc, sps_plan *out) 
                     hipMemcpyHostToDevice);
     if (e == hipSuccess)
       e = sps::stage_delays(p->sub_staged[(size_t)s], p->sub_cfg[(size_t)s],
-                            p->sub_pitch[(size_t)s], p->d_coarse_sub[(size_t)s], ns, ncoarse);
+                            p->sub_pitch[(size_t)s], p->d_coarse_sub[(size_t)s], ns, ncoarse,
+                            *std::max_element(tab.begin(), tab.end()));
     if (e != hipSuccess) {
       free_plan(p);
       (void)hipGetLastError();
@@ -611,7 +614,8 @@ sps_status sps_subband_plan_create(const sps_subband_desc *desc, sps_plan *out) 
                       p->coarse_delays.size() * sizeof(int32_t), hipMemcpyHostToDevice);
       if (e == hipSuccess)
         e = sps::stage_delays(p->fused_staged, p->fused_cfg, p->fused_pitch, p->d_coarse_full,
-                              nchan, ncoarse);
+                              nchan, ncoarse,
+                              *std::max_element(p->coarse_delays.begin(), p->coarse_delays.end()));
       if (e != hipSuccess) {
         free_plan(p);
         (void)hipGetLastError();
@@ -902,7 +906,7 @@ sps_status sps_batch_create(sps_plan plan, int32_t nbeams, const sps_beam *beams
                   hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = sps::stage_delays(b->staged, b->cfg, b->lds_pitch, plan->d_delays, plan->nchan,
-                          plan->ndm);
+                          plan->ndm, plan->max_delay);
   if (e != hipSuccess) {
     free_batch(b);
     (void)hipGetLastError();
@@ -989,7 +993,8 @@ sps_status sps_batch_autotune(sps_batch batch, int32_t iters, void *stream, floa
     e = hipMemcpy(batch->d_beams, batch->beams.data(),
                   sizeof(sps::BeamWork) * (size_t)batch->nbeams, hipMemcpyHostToDevice);
     sps::StagedDelays sd;
-    if (e == hipSuccess) e = sps::stage_delays(sd, c, (int)lp, p->d_delays, p->nchan, p->ndm);
+    if (e == hipSuccess)
+      e = sps::stage_delays(sd, c, (int)lp, p->d_delays, p->nchan, p->ndm, p->max_delay);
     if (e == hipSuccess)  // warm-up
       e = sps::launch_dedisperse_batch(c, (int)lp, batch->d_beams, batch->nbeams,
                                        batch->dd_items, sd, p->nchan, p->ndm, batch->grid_dd, s);
@@ -1023,7 +1028,8 @@ sps_status sps_batch_autotune(sps_batch batch, int32_t iters, void *stream, floa
   hipError_t e2 = hipMemcpy(batch->d_beams, batch->beams.data(),
                             sizeof(sps::BeamWork) * (size_t)batch->nbeams, hipMemcpyHostToDevice);
   if (e2 == hipSuccess)
-    e2 = sps::stage_delays(batch->staged, keep, keep_pitch, p->d_delays, p->nchan, p->ndm);
+    e2 = sps::stage_delays(batch->staged, keep, keep_pitch, p->d_delays, p->nchan, p->ndm,
+                           p->max_delay);
   batch->cfg = keep;
   batch->lds_pitch = keep_pitch;
   // the captured graph holds the old tiling's launch
@@ -1114,7 +1120,8 @@ sps_status sps_plan_autotune(sps_plan plan, int64_t nout_probe, int32_t iters, v
     if (ms_out) ms_out[i] = -1.0f;
     if (lp <= 0) continue;
     sps::StagedDelays sd;
-    e = sps::stage_delays(sd, c, (int)lp, plan->d_delays, plan->nchan, plan->ndm);
+    e = sps::stage_delays(sd, c, (int)lp, plan->d_delays, plan->nchan, plan->ndm,
+                          plan->max_delay);
     if (e == hipSuccess)
       e = sps::launch_dedisperse(c, (int)lp, X, pitch, nsamp, plan->d_delays, &sd, plan->nchan,
                                  plan->ndm, Y, nout_probe, s);  // warm-up

@@ -70,18 +70,19 @@ struct StagedDelays {
   int2 *P = nullptr;
   int32_t *B = nullptr;
   int nchan = 0, pcols = 0, ndm = 0, nd = 0, cs = 0, pitch = 0;
+  int32_t dmax = 0;  // largest delay of the table
   bool matches(const DedispConfig &c, int lds_pitch, int nc, int nd_trials) const {
     return P && nchan == nc && ndm == nd_trials && nd == c.nd() && cs == c.cs &&
            pitch == lds_pitch;
   }
 };
 
-// (Re)builds sd for tiling c from the device table D unless it already
-// matches; frees it for the plain kernel (m = 0).  Allocates, and waits for
+// (Re)builds sd for tiling c from the device table D (largest entry dmax)
+// unless it already matches; frees it for the plain kernel (m = 0).  Allocates, and waits for
 // its own kernel, so it is never called inside a launch sequence that a
 // caller may capture.
 hipError_t stage_delays(StagedDelays &sd, const DedispConfig &c, int lds_pitch, const int32_t *D,
-                        int nchan, int ndm);
+                        int nchan, int ndm, int32_t dmax);
 void free_staged(StagedDelays &sd);
 
 int64_t dedisp_batch_items(const DedispConfig &c, int ndm, int64_t nout);
