@@ -84,10 +84,12 @@ int64_t plane_bytes(int64_t elems, int64_t rows) {
 
 // Device memory of one plan: delay table, statistics, detection scratch for
 // the stream's tile grid.
-int64_t plan_bytes(int ndm, int nchan, int64_t chunk, const sps_detect_params &det) {
+// Device bytes of one worker's plan: its tables (as held now) plus the
+// detection scratch that its first chunk will allocate.
+int64_t plan_bytes(sps_plan plan, int ndm, int64_t chunk, const sps_detect_params &det) {
   const int64_t ntiles = ((ndm + det.tile_dm - 1) / det.tile_dm) *
                          ((chunk + det.tile_t - 1) / det.tile_t);
-  return (int64_t)ndm * nchan * 4 + (int64_t)ndm * 8 +
+  return sps::plan_device_bytes(plan) +
          (int64_t)(ntiles + sps::kMaxOffers) * (int64_t)sizeof(sps::TilePeak) + 16;
 }
 
@@ -442,9 +444,8 @@ sps_status sps_server_add_stream(sps_server s, const sps_obs_desc *desc, const i
   for (const Worker &w : s->workers)
     grow += plane_bytes(std::max(w.cap, elems), std::max<int64_t>(w.stats_cap, desc->ndm)) -
             plane_bytes(w.cap, w.stats_cap) + std::max<int64_t>(0, stage - w.staging_cap);
-  const int64_t plans = new_setup ? (int64_t)s->workers.size() *
-                                        plan_bytes(desc->ndm, desc->nchan, chunk_len, *det)
-                                  : 0;
+  int64_t plans = 0;
+  for (sps_plan q : new_plans) plans += plan_bytes(q, desc->ndm, chunk_len, *det);
   const int64_t tile_grow =
       s->detector ? std::max<int64_t>(0, grid_tiles(desc->ndm, chunk_len) - s->tiles_cap) * kTileBytes
                   : 0;

@@ -187,6 +187,34 @@ bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 
 
 }  // namespace
 
+namespace sps {
+
+int64_t plan_device_bytes(sps_plan p) {
+  if (!p) return 0;
+  auto staged = [](const sps::StagedDelays &sd) -> int64_t {
+    if (!sd.P) return 0;
+    const int64_t nb = (int64_t)((sd.ndm + sd.nd - 1) / sd.nd) * sd.nchan;
+    return (int64_t)sd.ndm * sd.pcols * (int64_t)sizeof(int2) + nb * (int64_t)sizeof(int32_t);
+  };
+  int64_t b = 0;
+  if (p->d_delays) b += (int64_t)p->delays.size() * (int64_t)sizeof(int32_t);
+  if (p->d_stats) b += (int64_t)p->ndm * 2 * (int64_t)sizeof(int32_t);
+  b += staged(p->staged) + staged(p->fused_staged);
+  for (const sps::StagedDelays &q : p->sub_staged) b += staged(q);
+  if (p->d_peaks) b += p->peaks_cap * (int64_t)sizeof(sps::TilePeak);
+  if (p->d_accepted) b += (int64_t)sps::kMaxOffers * (int64_t)sizeof(sps::TilePeak);
+  if (p->d_status) b += 4 * (int64_t)sizeof(int32_t);
+  if (p->d_coarse_full) b += (int64_t)p->coarse_delays.size() * (int64_t)sizeof(int32_t);
+  for (size_t s = 0; s < p->d_coarse_sub.size(); ++s)
+    if (p->d_coarse_sub[s])
+      b += (int64_t)p->ncoarse * (p->sub[s + 1] - p->sub[s]) * (int64_t)sizeof(int32_t);
+  if (p->d_resid) b += (int64_t)p->residuals.size() * (int64_t)sizeof(int32_t);
+  b += (int64_t)p->I_bytes;
+  return b;
+}
+
+}  // namespace sps
+
 extern "C" {
 
 const char *sps_last_error(void) { return g_error.c_str(); }

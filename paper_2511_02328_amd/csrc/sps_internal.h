@@ -146,6 +146,10 @@ hipError_t launch_downsample_sqrt(const uint8_t *X, int64_t pitch, int64_t nsamp
                                   int factor, uint8_t *Xo, int64_t pitch_out,
                                   hipStream_t stream);
 
+// Device bytes a plan holds now: delay table, staged tables, statistics
+// scratch and whatever detection / subband scratch it has grown.
+int64_t plan_device_bytes(sps_plan plan);
+
 // Records msg as the calling thread's last error (sps_last_error) and
 // returns s.
 sps_status set_error(sps_status s, const char *msg);
