@@ -41,9 +41,26 @@ __device__ __forceinline__ void tile_peak(const float *__restrict__ snr,
   const int64_t t1 = t0 + tile_t < nout ? t0 + tile_t : nout;
 
   uint64_t key = 0;
+  // 16-byte loads when every row segment of the tile is 16-byte aligned:
+  // four keys per load, four loads of a row in flight per thread
+  const bool vec = ((reinterpret_cast<uintptr_t>(snr) & 15) == 0) && nout % 4 == 0 &&
+                   tile_t % 4 == 0;
+  const int64_t nq = vec ? (t1 - t0) / 4 : 0;
+#pragma unroll 2
   for (int d = d0; d < d1; ++d) {
     const float *row = snr + (int64_t)d * nout;
-    for (int64_t t = t0 + threadIdx.x; t < t1; t += kTileThreads) {
+    const uint32_t dl = (uint32_t)(d - d0);
+    const float4 *rv = reinterpret_cast<const float4 *>(row + t0);
+#pragma unroll 4
+    for (int64_t q = threadIdx.x; q < nq; q += kTileThreads) {
+      const float4 v = rv[q];
+      const uint32_t p0 = (uint32_t)(4 * q) * (uint32_t)tile_dm + dl;
+      key = max_u64(key, ((uint64_t)ordered_bits(v.x) << 32) | (uint64_t)(~p0));
+      key = max_u64(key, ((uint64_t)ordered_bits(v.y) << 32) | (uint64_t)(~(p0 + tile_dm)));
+      key = max_u64(key, ((uint64_t)ordered_bits(v.z) << 32) | (uint64_t)(~(p0 + 2 * tile_dm)));
+      key = max_u64(key, ((uint64_t)ordered_bits(v.w) << 32) | (uint64_t)(~(p0 + 3 * tile_dm)));
+    }
+    for (int64_t t = t0 + 4 * nq + threadIdx.x; t < t1; t += kTileThreads) {
       const uint32_t pos = (uint32_t)((t - t0) * tile_dm + (d - d0));
       const uint64_t k = ((uint64_t)ordered_bits(row[t]) << 32) | (uint64_t)(~pos);
       key = max_u64(key, k);
