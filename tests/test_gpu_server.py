@@ -248,3 +248,25 @@ def test_detector_budget(sps):
         with pytest.raises(sps.SpsError):
             _add(sps, server, _wl(64, 2048, 400.0, 196.608e-6, 43), 8192)
     net.close()
+
+
+def test_detector_on_planes_without_whole_tiles(sps):
+    # fewer than 512 trials: no whole tile, so the network never runs and the
+    # count is 0; the search itself is unchanged
+    wl = _wl(128, 96, 150.0, 98.304e-6, 44)
+    L = 4096
+    Xs = _series(wl, 2, L)
+    net, _ = _net(sps, 2, 9)
+    with sps.sps_server_create(8 << 30, 1) as server:
+        sps.sps_server_set_detector(server, net, 0.5)
+        sid = _add(sps, server, wl, L)
+        for k in range(2):
+            Y = torch.zeros((wl.ndm, L), dtype=torch.int32, device="cuda")
+            cands, n, ncnn = sps.sps_server_push(server, sid, np.ascontiguousarray(Xs[:, k * L:(k + 1) * L]),
+                                                 Y_copy=Y, with_cnn=True)
+            torch.cuda.synchronize()
+            assert ncnn == 0
+            info = sps.sps_server_stream_info(server, sid)
+            ref = _oracle_chunk(wl, Xs, info["overlap"], k, L)
+            _check_chunk(Y.cpu().numpy().view(np.uint32), cands, n, ref, wl.widths)
+    net.close()
