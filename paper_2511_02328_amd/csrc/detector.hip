@@ -138,15 +138,10 @@ __global__ __launch_bounds__(256) void count_cells_kernel(const float *__restric
 // First layer (one input channel): per output pixel, 9 taps x 16 channels on
 // the vector ALU.  x: tiles [n][256][512]; w: packed [16][32] (k = tap).
 __global__ __launch_bounds__(256) void conv0_fwd_kernel(const uint16_t *__restrict__ x,
-                                                        const uint16_t *__restrict__ wp,
+                                                        const float *__restrict__ w0f,
                                                         const float *__restrict__ bias,
                                                         uint16_t *__restrict__ y, int64_t npix) {
   constexpr Layer L = kLayers[0];
-  __shared__ float ws[16][9];
-  __shared__ float bs[16];
-  if (threadIdx.x < 144) ws[threadIdx.x / 9][threadIdx.x % 9] = bf2f(wp[(threadIdx.x / 9) * 32 + threadIdx.x % 9]);
-  if (threadIdx.x < 16) bs[threadIdx.x] = bias[threadIdx.x];
-  __syncthreads();
   const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (p >= npix) return;
   const int64_t n = p / (L.hout * L.wout);
@@ -160,14 +155,16 @@ __global__ __launch_bounds__(256) void conv0_fwd_kernel(const uint16_t *__restri
                 ? bf2f(x[(n * L.hin + iy) * L.win + ix])
                 : 0.0f;
   }
+  // weights and biases are wave-uniform: scalar loads, one fused
+  // multiply-add per tap and channel
   uint32_t packed[8];
 #pragma unroll
   for (int c = 0; c < 16; c += 2) {
-    float s0 = bs[c], s1 = bs[c + 1];
+    float s0 = bias[c], s1 = bias[c + 1];
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
-      s0 += ws[c][t] * xv[t];
-      s1 += ws[c + 1][t] * xv[t];
+      s0 = fmaf(w0f[c * 9 + t], xv[t], s0);
+      s1 = fmaf(w0f[(c + 1) * 9 + t], xv[t], s1);
     }
     packed[c / 2] = (uint32_t)f2bf(fmaxf(s0, 0.0f)) | ((uint32_t)f2bf(fmaxf(s1, 0.0f)) << 16);
   }
@@ -586,7 +583,7 @@ __global__ __launch_bounds__(256) void conv0_bwd_weight_kernel(const uint16_t *_
                            ? bf2f(x[(n * L.hin + iy) * L.win + ix])
                            : 0.0f;
 #pragma unroll
-      for (int c = 0; c < 8; ++c) acc[c][t] += dv[c] * xv;
+      for (int c = 0; c < 8; ++c) acc[c][t] = fmaf(dv[c], xv, acc[c][t]);
     }
   }
   // waves add their lanes' sums into LDS one after another (fixed order)
@@ -731,6 +728,13 @@ __global__ __launch_bounds__(256) void pack_weights_kernel(const float *__restri
   if (wt) wt[(int64_t)ci * 9 * cout + tap * cout + co] = b;
 }
 
+// Layer-0 weights (params [16][1][3][3], FP32 master copy) rounded to
+// bfloat16 and kept as FP32, for the forward kernel's scalar loads.
+__global__ __launch_bounds__(256) void round_w0_kernel(const float *__restrict__ w,
+                                                       float *__restrict__ w0f) {
+  if (threadIdx.x < 16 * 9) w0f[threadIdx.x] = bf2f(f2bf(w[threadIdx.x]));
+}
+
 int64_t layer_param_offset(int li) {
   int64_t off = 0;
   for (int i = 0; i < li; ++i) off += kLayers[i].wcount() + kLayers[i].cout;
@@ -778,6 +782,7 @@ struct sps_cnn_s {
   float *head_part = nullptr; // per head block: [3][128] + [3] + [1]
   float *loss = nullptr;      // device scalar of the last loss_grad
   float *head = nullptr;      // head outputs of the last forward
+  float *w0f = nullptr;       // layer-0 weights rounded to bfloat16, as FP32 [16][9]
   float pos_weight = kPosWeight, lambda_box = kLambdaBox;
   int64_t partial_cap = 0, bpart_cap = 0;
 };
@@ -792,7 +797,7 @@ sps_status cnn_dev_fail(hipError_t e, const char *what) {
 
 void cnn_free(sps_cnn c) {
   void *ptrs[] = {c->params, c->grads, c->m, c->v, c->partial, c->bpart, c->head_part, c->loss,
-                  c->head, c->wtmp};
+                  c->head, c->wtmp, c->w0f};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (int i = 0; i < kNumLayers; ++i) {
@@ -811,6 +816,7 @@ hipError_t pack_all(sps_cnn c, hipStream_t s) {
                        c->params + layer_param_offset(i), L.cin, L.cout, L.kpad(), c->wp[i],
                        c->wt[i]);
   }
+  hipLaunchKernelGGL(round_w0_kernel, dim3(1), dim3(256), 0, s, c->params, c->w0f);
   return hipGetLastError();
 }
 
@@ -824,7 +830,7 @@ sps_status run_forward(sps_cnn c, const uint16_t *tiles, int32_t n, hipStream_t 
   {
     const int64_t np = npix_out(0, n);
     hipLaunchKernelGGL(conv0_fwd_kernel, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s,
-                       tiles, c->wp[0], c->params + layer_param_offset(0) + kLayers[0].wcount(),
+                       tiles, c->w0f, c->params + layer_param_offset(0) + kLayers[0].wcount(),
                        c->act[0], np);
   }
 #define SPS_FWD(LI)                                                                         \
@@ -970,6 +976,7 @@ sps_status sps_cnn_create(int32_t max_batch, sps_cnn *out) {
   alloc((void **)&c->head_part, sizeof(float) * (size_t)(nblk * (kHead * kFeat + kHead + 1)));
   alloc((void **)&c->loss, sizeof(float) * 4);
   alloc((void **)&c->head, sizeof(float) * (size_t)max_batch * kHead * kCells);
+  alloc((void **)&c->w0f, sizeof(float) * 16 * 9);
   for (int i = 0; i < kNumLayers; ++i) {
     const Layer &L = kLayers[i];
     alloc((void **)&c->wp[i], sizeof(uint16_t) * (size_t)L.cout * L.kpad());
