@@ -288,8 +288,11 @@ sps_status sps_batch_candidates(sps_batch batch, int32_t beam, sps_candidate *ou
  * a probe of nout_probe output samples (iters timed runs each, HIP events,
  * after one warm-up) and keeps the fastest.  ms_out (optional) receives the
  * mean time per tiling index (-1 for tilings that do not fit), see
- * sps_tiling_describe; *n_tried the number timed.  Allocates and frees its
- * probe buffers; synchronises the stream. */
+ * sps_tiling_describe; *n_tried the number timed.  For a subband plan whose
+ * subbands are equal it also times stage 1 in one segmented launch against
+ * one launch per subband on the same probe and keeps the faster form for
+ * sps_dedisperse_subband (results are identical either way).  Allocates and
+ * frees its probe buffers; synchronises the stream. */
 sps_status sps_plan_autotune(sps_plan plan, int64_t nout_probe, int32_t iters, void *stream,
                              float *ms_out, int32_t *n_tried);
 int32_t sps_tiling_count(void);

@@ -87,7 +87,8 @@ struct sps_plan_s {
   std::vector<sps::StagedDelays> sub_staged;
   // stage 1 in one launch over all channels (equal subbands that are a
   // multiple of the tiling's slab): the whole coarse table and its tiling
-  bool fused = false;
+  bool fused = false;      // the one-launch form exists
+  bool use_fused = true;   // and is used (sps_plan_autotune may switch it off)
   sps::DedispConfig fused_cfg{0, 0, 0, 0, 0, 0};
   int fused_pitch = 0;
   int32_t *d_coarse_full = nullptr;
@@ -716,7 +717,7 @@ sps_status sps_dedisperse_subband(sps_plan plan, const uint8_t *X, int64_t pitch
     plan->I_bytes = need;
   }
   hipStream_t s = (hipStream_t)stream;
-  if (plan->fused) {
+  if (plan->fused && plan->use_fused) {
     hipError_t e = sps::launch_dedisperse(plan->fused_cfg, plan->fused_pitch, X, pitch, nsamp_in,
                                           plan->d_coarse_full, &plan->fused_staged, plan->nchan,
                                           plan->ncoarse, plan->d_I, len1, s,
@@ -1127,7 +1128,7 @@ sps_status sps_plan_autotune(sps_plan plan, int64_t nout_probe, int32_t iters, v
   DeviceScope scope(plan->device);
   if (scope.err != hipSuccess) return hip_fail(scope.err, "selecting the plan's device");
   hipStream_t s = (hipStream_t)stream;
-  const int64_t nsamp = nout_probe + plan->max_delay;
+  const int64_t nsamp = nout_probe + std::max(plan->max_delay, plan->eff_max_delay);
   const int64_t pitch = (nsamp + 255) / 256 * 256;
   uint8_t *X = nullptr;
   uint32_t *Y = nullptr;
@@ -1177,12 +1178,30 @@ sps_status sps_plan_autotune(sps_plan plan, int64_t nout_probe, int32_t iters, v
       best_pitch = (int)lp;
     }
   }
+  // Subband plans: stage 1 in one segmented launch against one launch per
+  // subband (each with its own tiling), on the same probe; the faster stays.
+  sps_status sub_st = SPS_OK;
+  if (e == hipSuccess && plan->subband && plan->fused) {
+    float t_form[2] = {0.0f, 0.0f};
+    for (int f = 0; f < 2 && e == hipSuccess && sub_st == SPS_OK; ++f) {
+      plan->use_fused = f == 0;
+      sub_st = sps_dedisperse_subband(plan, X, pitch, nsamp, Y, nout_probe, 0, stream);  // warm-up
+      if (sub_st == SPS_OK) e = hipEventRecord(ev0, s);
+      for (int it = 0; it < iters && e == hipSuccess && sub_st == SPS_OK; ++it)
+        sub_st = sps_dedisperse_subband(plan, X, pitch, nsamp, Y, nout_probe, 0, stream);
+      if (e == hipSuccess && sub_st == SPS_OK) e = hipEventRecord(ev1, s);
+      if (e == hipSuccess && sub_st == SPS_OK) e = hipEventSynchronize(ev1);
+      if (e == hipSuccess && sub_st == SPS_OK) e = hipEventElapsedTime(&t_form[f], ev0, ev1);
+    }
+    plan->use_fused = !(e == hipSuccess && sub_st == SPS_OK) || t_form[0] <= t_form[1];
+  }
   if (ev0) (void)hipEventDestroy(ev0);
   if (ev1) (void)hipEventDestroy(ev1);
   if (X) (void)hipFree(X);
   if (Y) (void)hipFree(Y);
   if (n_tried) *n_tried = tried;
   if (e != hipSuccess) return hip_fail(e, "autotuning");
+  if (sub_st != SPS_OK) return sub_st;  // the subband call recorded its message
   if (tried == 0) return fail(SPS_ERR_RANGE, "no compiled tiling fits this plan");
   plan->cfg = best_cfg;
   plan->lds_pitch = best_pitch;

@@ -121,6 +121,7 @@ def test_fullscale_subband_rows(sps, full):
     with sps.sps_subband_plan_create(wl.freqs_mhz(), wl.fref_mhz, wl.tsamp_s, wl.ndm, wl.dm_lo,
                                      ddm, n0, nsub) as plan:
         Dc, R, F, mx = sps.sps_subband_tables(plan)
+        sps.sps_plan_autotune(plan, 1 << 18, 2)  # picks the stage-1 form, as the benchmark does
         Y = torch.empty((wl.ndm, wl.nout), dtype=torch.int32, device="cuda")
         sps.sps_dedisperse_subband(plan, X, nsamp, Y, wl.nout)
         torch.cuda.synchronize()

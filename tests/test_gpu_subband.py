@@ -106,3 +106,23 @@ def test_downsample(sps, factor, nsamp):
     sps.sps_downsample_sqrt(Xd, nsamp, factor, Xo)
     torch.cuda.synchronize()
     assert np.array_equal(Xo[:, :nb].cpu().numpy(), oracle.downsample_sqrt(X, factor, nsamp))
+
+
+@pytest.mark.parametrize("nsub", [32, 8])
+def test_autotuned_stage1_form_identical(sps, nsub):
+    # the autotuner times both stage-1 forms and keeps the faster; the output
+    # is the same either way
+    wl = SINGLE_BEAM
+    plan, _ = _plan(sps, wl, wl.ndm, 8, nsub)
+    with plan:
+        _, _, _, mx = sps.sps_subband_tables(plan)
+        nsamp = wl.nout + mx
+        X = synth.random_bytes(wl.nchan, nsamp, seed=77)
+        Xd = pitched(X, nsamp)
+        Y0 = torch.empty((wl.ndm, wl.nout), dtype=torch.int32, device="cuda")
+        sps.sps_dedisperse_subband(plan, Xd, nsamp, Y0, wl.nout)
+        sps.sps_plan_autotune(plan, 4096, 2)
+        Y1 = torch.empty_like(Y0)
+        sps.sps_dedisperse_subband(plan, Xd, nsamp, Y1, wl.nout)
+        torch.cuda.synchronize()
+        assert torch.equal(Y0, Y1)
