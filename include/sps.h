@@ -257,7 +257,7 @@ sps_status sps_batch_create(sps_plan plan, int32_t nbeams, const sps_beam *beams
                             uint32_t flags, sps_batch *out);
 sps_status sps_batch_destroy(sps_batch batch);
 
-/* Enqueues the whole search for every beam: one persistent dedispersion
+/* Enqueues the whole search for every beam: one batched dedispersion
  * launch over all (beam, time tile, DM block) items, then batched row
  * statistics, boxcar S/N and detection (4 + 1 launches in total).  Makes no
  * allocation and no host synchronisation, so it may be captured into a HIP
@@ -268,7 +268,7 @@ sps_status sps_batch_enqueue(sps_batch batch, void *stream);
  * (and re-captured if the stream changes).  stream must not be NULL. */
 sps_status sps_batch_launch_graph(sps_batch batch, void *stream);
 
-/* Batch autotuner: times the batch's own persistent dedispersion launch
+/* Batch autotuner: times the batch's own batched dedispersion launch
  * over its beams with every compiled tiling that fits the plan (iters timed
  * launches each, HIP events, after one warm-up) and keeps the fastest for
  * this batch (the plan's tiling is unchanged).  Overwrites the beams' Y.

@@ -41,8 +41,105 @@ __device__ uint32_t block_exclusive_scan256(uint32_t v, uint32_t *tmp /* >= 4 */
   return off + inc - v;
 }
 
-// NPOW > 0: the widths are exactly 1, 2, 4, ..., 2^(NPOW-1), so window
-// offsets are immediates of the LDS reads and width indices are constants.
+// a + b + c (mod 2^32) in one instruction; left to itself the compiler
+// splits the numerator below into a subtract and an add.
+__device__ __forceinline__ uint32_t add3_u32(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t r;
+  asm("v_add3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+
+// Widths 1, 2, 4, ..., 2^(NPOW-1): window offsets are immediates of the LDS
+// reads and width indices are constants, and the window length kLen is a
+// compile-time constant, so each thread issues all of its loads before the
+// first wait and reads and writes its scan chunk at immediate LDS offsets
+// (an odd chunk length puts the chunk starts of a wave in distinct banks).
+// TAIL: the row ends inside the window (n_left < kLen samples remain); the
+// missing samples read as zero, widths that run past the row end are left
+// out of the maximum (as -inf; width 1 always fits), and outputs past the
+// row end are not written.
+template <int NPOW, bool TAIL>
+__device__ __forceinline__ void pow2_segment(const SPS_GLOBAL uint32_t *src, int n_left,
+                                             int32_t med, int32_t mad, const WidthList &widths,
+                                             float *scale, uint32_t *tmp, SPS_GLOBAL float *srow,
+                                             SPS_GLOBAL uint8_t *brow, uint32_t *P) {
+  constexpr int kLen = kSeg + (1 << (NPOW - 1)) - 1;
+  constexpr int kLd = (kLen + kThreads - 1) / kThreads;
+  constexpr int kCh = kLd | 1;
+  uint32_t v[kLd];
+#pragma unroll
+  for (int k = 0; k < kLd; ++k) {
+    const int i = threadIdx.x + kThreads * k;
+    const bool in = TAIL ? i < n_left : (k + 1 < kLd || i < kLen);
+    v[k] = in ? src[i] : 0u;
+  }
+  if (threadIdx.x < NPOW) {
+    const double w = (double)widths.w[threadIdx.x];
+    scale[threadIdx.x] = mad > 0 ? (float)(1.0 / (1.4826 * (double)mad * sqrt(w))) : 0.0f;
+  }
+#pragma unroll
+  for (int k = 0; k < kLd; ++k) {
+    const int i = threadIdx.x + kThreads * k;
+    if (k + 1 < kLd || i < kLen) P[i + 1] = v[k];
+  }
+  __syncthreads();
+
+  // Exclusive prefix over [0, kLen): thread chunks of kCh samples.
+  const int lo = threadIdx.x * kCh;
+  uint32_t c[kCh];
+  uint32_t part = 0;
+#pragma unroll
+  for (int j = 0; j < kCh; ++j) {
+    c[j] = lo + j < kLen ? P[lo + j + 1] : 0u;
+    part += c[j];
+  }
+  uint32_t run = block_exclusive_scan256(part, tmp);
+#pragma unroll
+  for (int j = 0; j < kCh; ++j) {
+    run += c[j];
+    if (lo + j < kLen) P[lo + j + 1] = run;
+  }
+  if (threadIdx.x == 0) P[0] = 0u;
+  __syncthreads();
+
+  // The maximum first (three-input max), then the smallest width that
+  // attains it: equal to the strict running comparison, since S/N values are
+  // never NaN and never -0 (the numerator is an integer, the scale positive;
+  // with MAD = 0 every value is +-0 and width index 0 is chosen, as there).
+  // cw[i] = -w med (wrapping), wave-uniform.
+  const bool live = mad > 0;
+  const int seg_len = TAIL ? (n_left < kSeg ? n_left : kSeg) : kSeg;
+  float sc[NPOW];
+  uint32_t cw[NPOW];
+#pragma unroll
+  for (int i = 0; i < NPOW; ++i) {
+    sc[i] = scale[i];
+    cw[i] = 0u - (uint32_t)((1 << i) * med);
+  }
+#pragma unroll 2
+  for (int m = 0; m < kPer; ++m) {
+    const int tl = threadIdx.x + kThreads * m;
+    if (TAIL && tl >= seg_len) break;
+    const uint32_t *pt = P + tl;
+    const uint32_t neg_p0 = 0u - pt[0];
+    float s[NPOW];
+#pragma unroll
+    for (int i = 0; i < NPOW; ++i) {
+      s[i] = (float)(int32_t)add3_u32(pt[1 << i], neg_p0, cw[i]) * sc[i];
+      if (TAIL && tl + (1 << i) > n_left) s[i] = -INFINITY;
+    }
+    float mx = s[0];
+#pragma unroll
+    for (int i = 1; i < NPOW; ++i) mx = fmaxf(mx, s[i]);
+    int bi = NPOW - 1;
+#pragma unroll
+    for (int i = NPOW - 2; i >= 0; --i) bi = s[i] == mx ? i : bi;
+    srow[tl] = live ? mx : 0.0f;
+    brow[tl] = (uint8_t)bi;
+  }
+}
+
+// NPOW > 0: power-of-two widths (pow2_segment); NPOW = 0: any width list.
 template <int NPOW>
 __device__ __forceinline__ void boxcar_segment(const uint32_t *__restrict__ Y, int64_t nout, int d,
                                                int seg, const int32_t *__restrict__ stats,
@@ -51,19 +148,33 @@ __device__ __forceinline__ void boxcar_segment(const uint32_t *__restrict__ Y, i
   __shared__ float scale[kMaxWidths];
   __shared__ uint32_t tmp[4];
   const int64_t t0 = (int64_t)seg * kSeg;
-  const uint32_t *row = Y + (int64_t)d * nout;
+  const SPS_GLOBAL uint32_t *row = gmem(Y + (int64_t)d * nout);
   const int nw = widths.n;
   const int wmax = widths.w[nw - 1];
-  const int32_t med = stats[2 * (int64_t)d];
-  const int32_t mad = stats[2 * (int64_t)d + 1];
-
-  if (threadIdx.x < nw) {
-    const double w = (double)widths.w[threadIdx.x];
-    scale[threadIdx.x] = mad > 0 ? (float)(1.0 / (1.4826 * (double)mad * sqrt(w))) : 0.0f;
-  }
+  const int32_t med = gmem(stats)[2 * (int64_t)d];
+  const int32_t mad = gmem(stats)[2 * (int64_t)d + 1];
+  auto set_scales = [&]() {
+    if (threadIdx.x < nw) {
+      const double w = (double)widths.w[threadIdx.x];
+      scale[threadIdx.x] = mad > 0 ? (float)(1.0 / (1.4826 * (double)mad * sqrt(w))) : 0.0f;
+    }
+  };
 
   // Samples this segment needs: [t0, t0 + len), len <= kSeg + wmax - 1.
   const int64_t avail = nout - t0;
+
+  if constexpr (NPOW > 0) {
+    constexpr int kLen = kSeg + (1 << (NPOW - 1)) - 1;
+    SPS_GLOBAL float *srow = gmem(snr + (int64_t)d * nout + t0);
+    SPS_GLOBAL uint8_t *brow = gmem(best + (int64_t)d * nout + t0);
+    if (avail >= (int64_t)kLen)
+      pow2_segment<NPOW, false>(row + t0, kLen, med, mad, widths, scale, tmp, srow, brow, P);
+    else
+      pow2_segment<NPOW, true>(row + t0, (int)avail, med, mad, widths, scale, tmp, srow, brow, P);
+    return;
+  }
+
+  set_scales();
   const int len = (int)(avail < (int64_t)(kSeg + wmax - 1) ? avail : (int64_t)(kSeg + wmax - 1));
   for (int i = threadIdx.x; i < len; i += kThreads) P[i + 1] = row[t0 + i];
   __syncthreads();
@@ -83,35 +194,9 @@ __device__ __forceinline__ void boxcar_segment(const uint32_t *__restrict__ Y, i
   __syncthreads();
 
   const int seg_len = avail < kSeg ? (int)avail : kSeg;
-  float *srow = snr + (int64_t)d * nout + t0;
-  uint8_t *brow = best + (int64_t)d * nout + t0;
+  SPS_GLOBAL float *srow = gmem(snr + (int64_t)d * nout + t0);
+  SPS_GLOBAL uint8_t *brow = gmem(best + (int64_t)d * nout + t0);
   const bool live = mad > 0;
-
-  if (NPOW > 0 && avail >= (int64_t)(kSeg + wmax - 1)) {
-    float sc[NPOW > 0 ? NPOW : 1];
-#pragma unroll
-    for (int i = 0; i < NPOW; ++i) sc[i] = scale[i];
-#pragma unroll 2
-    for (int m = 0; m < kPer; ++m) {
-      const int tl = threadIdx.x + kThreads * m;
-      const uint32_t *pt = P + tl;
-      const uint32_t neg_p0 = 0u - pt[0];
-      float bs = -INFINITY;
-      int bi = 0;
-#pragma unroll
-      for (int i = 0; i < NPOW; ++i) {
-        const int32_t num = (int32_t)(pt[1 << i] + neg_p0 - (uint32_t)((1 << i) * med));
-        const float s = (float)num * sc[i];
-        if (s > bs) {
-          bs = s;
-          bi = i;
-        }
-      }
-      srow[tl] = live ? bs : 0.0f;
-      brow[tl] = (uint8_t)bi;
-    }
-    return;
-  }
 
   if (avail >= (int64_t)(kSeg + wmax - 1)) {
     // Every width fits at every output of this segment: no per-width guard.
@@ -181,9 +266,7 @@ __global__ __launch_bounds__(kThreads) void boxcar_batch_kernel(
     const BeamWork *__restrict__ beams, int nbeams, WidthList widths) {
   extern __shared__ uint32_t P[];
   const int64_t blk = blockIdx.x;
-  int b = 0;
-  while (b + 1 < nbeams && beams[b + 1].bx_begin <= blk) ++b;
-  const BeamWork &bw = beams[b];
+  const BeamWork &bw = beams[find_beam<&BeamWork::bx_begin>(beams, nbeams, blk)];
   const int64_t local = blk - bw.bx_begin;
   const int d = (int)(local / bw.nseg);
   const int seg = (int)(local - (int64_t)d * bw.nseg);

@@ -79,8 +79,6 @@ __device__ __forceinline__ void add_pair(uint32_t (&ev)[M], uint32_t (&od)[M],
   }
 }
 
-typedef unsigned int vu4 __attribute__((ext_vector_type(4)));
-
 template <int CS, int NW, int KMAX>
 struct SlabRegs {
   static constexpr int RPW = CS / NW;
@@ -105,13 +103,16 @@ __device__ __forceinline__ void slab_load(SlabRegs<CS, NW, KMAX> &st, const uint
     for (int u = 0; u < KMAX; ++u) st.v[i][u] = make_uint4(0u, 0u, 0u, 0u);
     if (r < ncs) {
       const int64_t base = t0 + (int64_t)Bb[c0 + r];
-      const uint8_t *rowp = X + (int64_t)(c0 + r) * pitch;
+      const SPS_GLOBAL uint8_t *rowp = gmem(X + (int64_t)(c0 + r) * pitch);
       if (base + 16 * (int64_t)vpr <= nsamp_in) {
-        const uint4 *src = reinterpret_cast<const uint4 *>(rowp + base);
+        const SPS_GLOBAL u32x4 *src = (const SPS_GLOBAL u32x4 *)(rowp + base);
 #pragma unroll
         for (int u = 0; u < KMAX; ++u) {
           const int k = lane + 64 * u;
-          if (k < vpr) st.v[i][u] = src[k];
+          if (k < vpr) {
+            const u32x4 v = src[k];
+            st.v[i][u] = make_uint4(v.x, v.y, v.z, v.w);
+          }
         }
       } else {
 #pragma unroll
@@ -119,19 +120,18 @@ __device__ __forceinline__ void slab_load(SlabRegs<CS, NW, KMAX> &st, const uint
           const int k = lane + 64 * u;
           const int64_t s0 = base + 16 * (int64_t)k;
           if (k < vpr && s0 < nsamp_in) {
-            uint4 v = *reinterpret_cast<const uint4 *>(rowp + s0);
+            const u32x4 v = *(const SPS_GLOBAL u32x4 *)(rowp + s0);
+            uint32_t w4[4] = {v.x, v.y, v.z, v.w};
             const int64_t nv = nsamp_in - s0;
             if (nv < 16) {
-              uint32_t w4[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
               for (int q = 0; q < 4; ++q) {
                 const int64_t keep = nv - 4 * q;
                 w4[q] = keep >= 4 ? w4[q]
                                   : (keep <= 0 ? 0u : (w4[q] & ((1u << (8 * keep)) - 1u)));
               }
-              v = make_uint4(w4[0], w4[1], w4[2], w4[3]);
             }
-            st.v[i][u] = v;
+            st.v[i][u] = make_uint4(w4[0], w4[1], w4[2], w4[3]);
           }
         }
       }
@@ -153,10 +153,11 @@ __device__ __forceinline__ void slab_load_interior(SlabRegs<CS, NW, KMAX> &st,
     const int c = c0 + wave + NW * i;
     // native 4-vector loads: a struct copy of uint4 becomes a memcpy that
     // the compiler keeps in scratch memory
-    const vu4 *src = reinterpret_cast<const vu4 *>(X + (int64_t)c * pitch + t0 + (int64_t)Bb[c]);
+    const SPS_GLOBAL u32x4 *src =
+        (const SPS_GLOBAL u32x4 *)gmem(X + (int64_t)c * pitch + t0 + (int64_t)Bb[c]);
 #pragma unroll
     for (int u = 0; u < KMAX; ++u) {
-      const vu4 v = src[min(lane + 64 * u, vpr - 1)];
+      const u32x4 v = src[min(lane + 64 * u, vpr - 1)];
       st.v[i][u] = make_uint4(v.x, v.y, v.z, v.w);
     }
   }
@@ -186,13 +187,12 @@ __device__ __forceinline__ void store_acc(const uint32_t (&acc)[DPW][M][4], uint
   for (int k = 0; k < DPW; ++k) {
     const int d = dw0 + k;
     if (d >= ndm) continue;
-    uint32_t *Yd = Y + (int64_t)d * nout;
+    SPS_GLOBAL uint32_t *Yd = gmem(Y + (int64_t)d * nout);
 #pragma unroll
     for (int j = 0; j < M; ++j) {
       const int64_t t = t0 + 4 * (int64_t)(lane * M + j);
       if (vec_store && t + 4 <= nout) {
-        *reinterpret_cast<uint4 *>(Yd + t) =
-            make_uint4(acc[k][j][0], acc[k][j][1], acc[k][j][2], acc[k][j][3]);
+        *(SPS_GLOBAL u32x4 *)(Yd + t) = u32x4{acc[k][j][0], acc[k][j][1], acc[k][j][2], acc[k][j][3]};
       } else {
 #pragma unroll
         for (int b = 0; b < 4; ++b)
@@ -364,36 +364,36 @@ dedisperse_kernel(const uint8_t *__restrict__ X, int64_t pitch, int64_t nsamp_in
                                                        dblk, smem, seg, seg_stride);
 }
 
-// Persistent kernel over many filterbanks that share a plan (beams of one
-// receiver, chunks of different lengths): the work items (beam, time tile,
-// DM block) form one flat range; workgroup w takes items w', w' + G, ...,
-// with w' the XCD-contiguous renumbering of w, until the range is done.
+// Many filterbanks that share a plan (beams of one receiver, chunks of
+// different lengths): the work items (beam, time tile, DM block) form one
+// flat range, DM block fastest, and each workgroup takes one item.  The item
+// numbering gives each XCD a contiguous share, so the workgroups resident on
+// an XCD cover neighbouring time tiles of all DM blocks of a beam.  One item
+// per workgroup (rather than a persistent loop over items) keeps no state
+// across items, so the tilings fit their register budget as in the
+// single-filterbank kernel.
 template <int M, int DPW, int NW, int CS, int KMAX, int WPE>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) void
 dedisperse_batch_kernel(const BeamWork *__restrict__ beams, int nbeams, int64_t total_items,
-                        const int2 *__restrict__ P, int pcols, const int32_t *__restrict__ B,
-                        int nchan, int ndm, int lds_pitch, int ndmb, int dmax) {
+                        int64_t per_xcd, const int2 *__restrict__ P, int pcols,
+                        const int32_t *__restrict__ B, int nchan, int ndm, int lds_pitch,
+                        int ndmb, int dmax) {
   extern __shared__ uint4 smem[];
-  const int G = gridDim.x;
-  const int w = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
-  for (int64_t item = w; item < total_items; item += G) {
-    int b = 0;
-    while (b + 1 < nbeams && beams[b + 1].dd_begin <= item) ++b;
-    const BeamWork &bw = beams[b];
-    const int64_t local = item - bw.dd_begin;
-    const int dblk = (int)(local % ndmb);
-    const int64_t tile = local / ndmb;
-    const int64_t t0 = tile * (256 * M);
-    if (nchan % CS == 0 && t0 + dmax + lds_pitch <= bw.nsamp_in)
-      dedisperse_block<M, DPW, NW, CS, KMAX, false, true>(bw.X, bw.pitch, bw.nsamp_in, P, pcols, B,
-                                                          nchan, ndm, bw.Y, bw.nout, lds_pitch,
-                                                          bw.vec_store, t0, dblk, smem);
-    else
-      dedisperse_block<M, DPW, NW, CS, KMAX, false, false>(bw.X, bw.pitch, bw.nsamp_in, P, pcols,
-                                                           B, nchan, ndm, bw.Y, bw.nout,
-                                                           lds_pitch, bw.vec_store, t0, dblk,
-                                                           smem);
-  }
+  const int64_t item = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (item >= total_items) return;
+  const BeamWork &bw = beams[find_beam<&BeamWork::dd_begin>(beams, nbeams, item)];
+  const int64_t local = item - bw.dd_begin;
+  const int dblk = (int)(local % ndmb);
+  const int64_t tile = local / ndmb;
+  const int64_t t0 = tile * (256 * M);
+  if (nchan % CS == 0 && t0 + dmax + lds_pitch <= bw.nsamp_in)
+    dedisperse_block<M, DPW, NW, CS, KMAX, false, true>(bw.X, bw.pitch, bw.nsamp_in, P, pcols, B,
+                                                        nchan, ndm, bw.Y, bw.nout, lds_pitch,
+                                                        bw.vec_store, t0, dblk, smem);
+  else
+    dedisperse_block<M, DPW, NW, CS, KMAX, false, false>(bw.X, bw.pitch, bw.nsamp_in, P, pcols,
+                                                         B, nchan, ndm, bw.Y, bw.nout, lds_pitch,
+                                                         bw.vec_store, t0, dblk, smem);
 }
 
 // Staged form of the delay table for blocks of nd trials, slabs of cs rows
@@ -482,7 +482,9 @@ hipError_t launch_batch_cfg(int lds_pitch, const BeamWork *beams, int nbeams, in
                             const StagedDelays &sd, int nchan, int ndm, int grid,
                             hipStream_t stream) {
   constexpr int ND = NW * DPW;
-  if (lds_pitch > 16 * 64 * KMAX || lds_pitch % 16 != 0 || grid % 8 != 0)
+  // one workgroup per item: grid = 8 ceil(total / 8)
+  if (lds_pitch > 16 * 64 * KMAX || lds_pitch % 16 != 0 || grid % 8 != 0 ||
+      (int64_t)grid < total)
     return hipErrorInvalidValue;
   const int ndmb = (ndm + ND - 1) / ND;
   const size_t lds = 2 * (size_t)CS * (size_t)lds_pitch;
@@ -492,8 +494,9 @@ hipError_t launch_batch_cfg(int lds_pitch, const BeamWork *beams, int nbeams, in
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(NW * 64), lds, stream, beams, nbeams, total, sd.P,
-                     sd.pcols, sd.B, nchan, ndm, lds_pitch, ndmb, sd.dmax);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(NW * 64), lds, stream, beams, nbeams, total,
+                     (int64_t)(grid / 8), sd.P, sd.pcols, sd.B, nchan, ndm, lds_pitch, ndmb,
+                     sd.dmax);
   return hipGetLastError();
 }
 

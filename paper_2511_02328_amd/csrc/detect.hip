@@ -48,12 +48,12 @@ __device__ __forceinline__ void tile_peak(const float *__restrict__ snr,
   const int64_t nq = vec ? (t1 - t0) / 4 : 0;
 #pragma unroll 2
   for (int d = d0; d < d1; ++d) {
-    const float *row = snr + (int64_t)d * nout;
+    const SPS_GLOBAL float *row = gmem(snr + (int64_t)d * nout);
     const uint32_t dl = (uint32_t)(d - d0);
-    const float4 *rv = reinterpret_cast<const float4 *>(row + t0);
+    const SPS_GLOBAL f32x4 *rv = (const SPS_GLOBAL f32x4 *)(row + t0);
 #pragma unroll 4
     for (int64_t q = threadIdx.x; q < nq; q += kTileThreads) {
-      const float4 v = rv[q];
+      const f32x4 v = rv[q];
       const uint32_t p0 = (uint32_t)(4 * q) * (uint32_t)tile_dm + dl;
       key = max_u64(key, ((uint64_t)ordered_bits(v.x) << 32) | (uint64_t)(~p0));
       key = max_u64(key, ((uint64_t)ordered_bits(v.y) << 32) | (uint64_t)(~(p0 + tile_dm)));
@@ -86,10 +86,10 @@ __device__ __forceinline__ void tile_peak(const float *__restrict__ snr,
     const int d = d0 + dl;
     const int64_t t = t0 + tl;
     TilePeak p;
-    p.snr = snr[(int64_t)d * nout + t];
+    p.snr = gmem(snr)[(int64_t)d * nout + t];
     p.d = d;
     p.t = (int32_t)t;
-    p.w = best[(int64_t)d * nout + t];
+    p.w = gmem(best)[(int64_t)d * nout + t];
     *out = p;
   }
 }
@@ -104,9 +104,7 @@ __global__ __launch_bounds__(kTileThreads) void tile_peaks_batch_kernel(
     const BeamWork *__restrict__ beams, int nbeams, int ndm, int tile_dm, int64_t tile_t,
     TilePeak *__restrict__ peaks) {
   const int64_t blk = blockIdx.x;
-  int b = 0;
-  while (b + 1 < nbeams && beams[b + 1].tp_begin <= blk) ++b;
-  const BeamWork &bw = beams[b];
+  const BeamWork &bw = beams[find_beam<&BeamWork::tp_begin>(beams, nbeams, blk)];
   tile_peak(bw.snr, bw.best, ndm, bw.nout, tile_dm, tile_t, bw.ntt, blk - bw.tp_begin,
             peaks + blk);
 }

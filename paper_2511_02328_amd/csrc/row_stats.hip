@@ -94,12 +94,13 @@ __device__ void locate_rank_n(const uint32_t *hist, int n, uint32_t k, uint32_t 
 }
 
 template <typename F>
-__device__ __forceinline__ void for_each_value(const uint32_t *row, int64_t n, bool vec, F f) {
+__device__ __forceinline__ void for_each_value(const uint32_t *row_in, int64_t n, bool vec, F f) {
+  const SPS_GLOBAL uint32_t *row = gmem(row_in);
   if (vec) {
-    const uint4 *r4 = reinterpret_cast<const uint4 *>(row);
+    const SPS_GLOBAL u32x4 *r4 = (const SPS_GLOBAL u32x4 *)row;
     const int64_t n4 = n >> 2;
     for (int64_t i = threadIdx.x; i < n4; i += kThreads) {
-      const uint4 v = r4[i];
+      const u32x4 v = r4[i];
       f(v.x);
       f(v.y);
       f(v.z);

@@ -808,18 +808,22 @@ void free_batch(sps_batch b) {
   delete b;
 }
 
-// Dedispersion item ranges of the beams (and the persistent grid) for
-// tiling c; host side only.
-void layout_dedisp(sps_batch b, const sps::DedispConfig &c) {
+// Dedispersion item ranges of the beams (and the grid: one workgroup per
+// item, rounded up to whole XCD shares) for tiling c; host side only.
+// False (and nothing changed) if the grid would pass 2^31 - 1 workgroups.
+bool layout_dedisp(sps_batch b, const sps::DedispConfig &c) {
   int64_t items = 0;
+  for (int i = 0; i < b->nbeams; ++i)
+    items += sps::dedisp_batch_items(c, b->plan->ndm, b->nout[(size_t)i]);
+  if (items > 0x7FFFFFF8) return false;
+  items = 0;
   for (int i = 0; i < b->nbeams; ++i) {
     b->beams[(size_t)i].dd_begin = items;
     items += sps::dedisp_batch_items(c, b->plan->ndm, b->nout[(size_t)i]);
   }
   b->dd_items = items;
-  const int64_t persistent = 256 * 2;
-  const int64_t g = items < persistent ? items : persistent;
-  b->grid_dd = (int)(((g + 7) / 8) * 8);
+  b->grid_dd = (int)(((items + 7) / 8) * 8);
+  return true;
 }
 
 sps_status batch_enqueue(sps_batch b, hipStream_t s) {
@@ -919,11 +923,10 @@ sps_status sps_batch_create(sps_plan plan, int32_t nbeams, const sps_beam *beams
       return fail(SPS_ERR_RANGE, "beam %d has more than %d detection tiles", i, sps::kMaxOffers);
     }
   }
-  if (b->bx_blocks > 0x7FFFFFFF || b->tp_tiles > 0x7FFFFFFF) {
+  if (b->bx_blocks > 0x7FFFFFFF || b->tp_tiles > 0x7FFFFFFF || !layout_dedisp(b, b->cfg)) {
     free_batch(b);
     return fail(SPS_ERR_RANGE, "batch too large");
   }
-  layout_dedisp(b, b->cfg);
   DeviceScope scope(plan->device);
   hipError_t e = hipMalloc(&b->d_beams, sizeof(sps::BeamWork) * (size_t)nbeams);
   if (e == hipSuccess) e = hipMalloc(&b->d_peaks, sizeof(sps::TilePeak) * (size_t)b->tp_tiles);
@@ -1017,8 +1020,7 @@ sps_status sps_batch_autotune(sps_batch batch, int32_t iters, void *stream, floa
     const sps::DedispConfig &c = kPrefs[i];
     if (ms_out) ms_out[i] = -1.0f;
     const int64_t lp = fitted_pitch(p, c, 160 * 1024);
-    if (lp <= 0) continue;
-    layout_dedisp(batch, c);
+    if (lp <= 0 || !layout_dedisp(batch, c)) continue;
     e = hipMemcpy(batch->d_beams, batch->beams.data(),
                   sizeof(sps::BeamWork) * (size_t)batch->nbeams, hipMemcpyHostToDevice);
     sps::StagedDelays sd;
@@ -1053,7 +1055,7 @@ sps_status sps_batch_autotune(sps_batch batch, int32_t iters, void *stream, floa
   // keep the fastest (or restore the batch's tiling after a failure)
   const sps::DedispConfig keep = best >= 0 && e == hipSuccess ? kPrefs[best] : batch->cfg;
   const int keep_pitch = best >= 0 && e == hipSuccess ? (int)best_pitch : batch->lds_pitch;
-  layout_dedisp(batch, keep);
+  (void)layout_dedisp(batch, keep);  // laid out before, so it fits
   hipError_t e2 = hipMemcpy(batch->d_beams, batch->beams.data(),
                             sizeof(sps::BeamWork) * (size_t)batch->nbeams, hipMemcpyHostToDevice);
   if (e2 == hipSuccess)

@@ -35,6 +35,25 @@ int dedisp_block_spread(const int32_t *delays_host, int nchan, int ndm, int nd);
 // True if the config is one the library instantiates.
 bool dedisp_config_supported(const DedispConfig &cfg);
 
+// Every buffer the kernels touch is in device memory.  Pointers are cast to
+// the global address space where they are dereferenced: a pointer that a
+// kernel reads from memory (a BeamWork field) or receives in a non-inlined
+// function is generic to the compiler, which then emits flat loads and
+// stores, and flat operations also count against the LDS wait counter, so
+// every LDS wait would wait for them too.
+#define SPS_GLOBAL __attribute__((address_space(1)))
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+__device__ __forceinline__ const SPS_GLOBAL T *gmem(const T *p) {
+  return (const SPS_GLOBAL T *)p;
+}
+template <typename T>
+__device__ __forceinline__ SPS_GLOBAL T *gmem(T *p) {
+  return (SPS_GLOBAL T *)p;
+}
+
 // Per-filterbank work description of a batched call (device memory).  The
 // *_begin fields are exclusive prefix sums of each kernel's work items over
 // the preceding beams.
@@ -55,6 +74,23 @@ struct BeamWork {
   int32_t vec_store;
   int32_t pad;
 };
+
+// The beam whose work range holds `item`: the last b with beams[b].*F <=
+// item (the ranges are exclusive prefix sums from 0, so an empty beam never
+// wins over the beam after it).  Binary search: log2(nbeams) dependent
+// scalar loads.
+template <int64_t BeamWork::*F>
+__device__ __forceinline__ int find_beam(const BeamWork *beams, int nbeams, int64_t item) {
+  int lo = 0, hi = nbeams - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (beams[mid].*F <= item)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
 
 // The delay table D [ndm][nchan] in the form the staged kernels of one
 // tiling read (blocks of nd = nw dpw trials, slabs of cs rows, staged rows of

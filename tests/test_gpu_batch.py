@@ -1,4 +1,4 @@
-"""GPU parity of the batched path (many beams of one plan in persistent
+"""GPU parity of the batched path (many beams of one plan in batched
 launches, optionally replayed from a HIP graph) against the single-beam calls
 and the oracle, and of the autotuner's choice."""
 import numpy as np
@@ -128,7 +128,7 @@ def test_autotune_keeps_results(sps):
 
 
 def test_batch_autotune_keeps_results(sps):
-    # the batch times its own persistent launch per tiling, keeps the
+    # the batch times its own batched launch per tiling, keeps the
     # fastest, and a graph captured before the autotuning is replaced
     nouts = [3000, 9000, 1281, 5000]
     wl = _wl(nouts[0], 0)

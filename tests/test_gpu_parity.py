@@ -222,6 +222,34 @@ def test_stats_and_boxcar_random(sps, seed):
         check_snr(snr.cpu().numpy(), best.cpu().numpy(), snro, besto, all_width_snr(Y, sto, widths))
 
 
+@pytest.mark.parametrize("npow,nout", [(1, 4096), (1, 4100), (3, 4), (3, 7), (7, 4096),
+                                       (7, 4096 + 62), (7, 4096 + 63), (9, 4096 + 256),
+                                       (9, 3 * 4096 - 1), (13, 4097), (13, 2 * 4096 + 4095),
+                                       (13, 3 * 4096)])
+def test_boxcar_pow2_segment_tails(sps, npow, nout):
+    """Power-of-two width lists 1 .. 2^(npow-1) on rows whose last segment
+    ends inside, at, or just past the widest window; with a row of ties and
+    a row of MAD 0."""
+    rng = np.random.Generator(np.random.PCG64(100 * npow + nout % 97))
+    ndm, nchan = 4, 256
+    widths = [2 ** i for i in range(npow)]
+    Y = rng.integers(0, 255 * nchan + 1, size=(ndm, nout)).astype(np.uint32)
+    Y[1] = rng.integers(1000, 1003, size=nout)
+    Y[2] = 77
+    sto = oracle.stats(Y)
+    snro, besto = oracle.boxcar(Y, sto, widths)
+    wl = Workload("s", nchan, 1000.0, 1500.0, 1e-4, nout, ndm, 0.0, 1.0, tuple(widths))
+    with sps.plan_for(wl) as plan:
+        Yd = torch.from_numpy(Y.view(np.int32)).cuda()
+        snr = torch.empty((ndm, nout), dtype=torch.float32, device="cuda")
+        best = torch.empty((ndm, nout), dtype=torch.uint8, device="cuda")
+        st = torch.empty((ndm, 2), dtype=torch.int32, device="cuda")
+        sps.sps_boxcar_snr(plan, Yd, nout, widths, snr, best, st)
+        torch.cuda.synchronize()
+        assert np.array_equal(st.cpu().numpy().astype(np.int64), sto)
+        check_snr(snr.cpu().numpy(), best.cpu().numpy(), snro, besto, all_width_snr(Y, sto, widths))
+
+
 @pytest.mark.parametrize("seed", range(6))
 def test_detect_same_plane(sps, seed):
     rng = np.random.Generator(np.random.PCG64(seed))
