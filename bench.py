@@ -59,6 +59,33 @@ def measured_counters(wl, tiling):
             "ops_per_add": float(vals["dedisperse_valu_lane_ops_per_sample_add"])}
 
 
+# Vector instructions per 16-channel slab of the dedispersion kernel's inner
+# loop, per lane (320 sample-adds: 20 outputs x 16 channels), read from its
+# ISA: byte permutes, three-input adds and address adds.
+SLAB_PERMS, SLAB_ADD3S, SLAB_ADDS, SLAB_SAMPLE_ADDS = 160, 80, 18, 320
+
+
+def measured_peaks(sps, achieved_tops, lds_bytes_per_add=None):
+    """The device's sustained instruction and LDS read rates from the
+    library's probes (run after the timed region), the sample-add rate the
+    dedispersion slab loop's instruction mix would reach at them with every
+    issue slot used, and the kernel's fraction of each."""
+    p = sps.sps_probe_peaks(0)
+    mix = SLAB_SAMPLE_ADDS / (SLAB_PERMS / p["valu_perm_ops_per_s"]
+                              + SLAB_ADD3S / p["valu_add3_ops_per_s"]
+                              + SLAB_ADDS / p["valu_add_ops_per_s"])
+    out = {"valu_add_tops": p["valu_add_ops_per_s"] / 1e12,
+           "valu_add3_tops": p["valu_add3_ops_per_s"] / 1e12,
+           "valu_perm_tops": p["valu_perm_ops_per_s"] / 1e12,
+           "lds_read_tbps": p["lds_read_bytes_per_s"] / 1e12,
+           "slab_mix_tops": mix / 1e12,
+           "frac_of_valu_add": achieved_tops * 1e12 / p["valu_add_ops_per_s"],
+           "frac_of_slab_mix": achieved_tops * 1e12 / mix}
+    if lds_bytes_per_add:
+        out["lds_read_frac"] = achieved_tops * 1e12 * lds_bytes_per_add / p["lds_read_bytes_per_s"]
+    return out
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -249,7 +276,9 @@ def main():
                      "valu_issue_frac": (achieved * counters["ops_per_add"] / ALU_PEAK_TOPS
                                          if counters else None),
                      "lds_read_frac": (achieved * 1e12 * (tiling["m"] + 1) / tiling["m"]
-                                       / LDS_PEAK_BPS if tiling["m"] else None)},
+                                       / LDS_PEAK_BPS if tiling["m"] else None),
+                     "measured_peaks": measured_peaks(
+                         sps, achieved, (tiling["m"] + 1) / tiling["m"] if tiling["m"] else None)},
     }
 
     if args.cpu_rows > 0:
@@ -343,7 +372,8 @@ def bench_batched(args, bw):
                      "frac": adds / (t_dd / 1e3) / 1e12 / ALU_PEAK_TOPS, "traffic": None,
                      "kernel_ms": t_dd, "graph_ms": t_graph * 1e3,
                      "step_frac": adds / t_graph / 1e12 / ALU_PEAK_TOPS,
-                     "work_per_launch": f"{adds} sample-adds (sum over beams of ndm x nout x nchan)"},
+                     "work_per_launch": f"{adds} sample-adds (sum over beams of ndm x nout x nchan)",
+                     "measured_peaks": measured_peaks(sps, adds / (t_dd / 1e3) / 1e12)},
     }
     print(json.dumps(rec), flush=True)
     batch.close()

@@ -299,6 +299,24 @@ int32_t sps_tiling_count(void);
 sps_status sps_tiling_describe(int32_t index, int32_t *m, int32_t *dpw, int32_t *nw, int32_t *cs,
                                int32_t *waves_per_eu);
 
+/* Device microbenchmarks for the rates the kernels are measured against, on
+ * HIP device `device`, written to rates[0 .. SPS_PROBE_COUNT-1]:
+ *   rates[SPS_PROBE_VALU_ADD]  sustained v_add_u32 lane-ops per second,
+ *   rates[SPS_PROBE_VALU_ADD3] sustained three-input adds (v_add3_u32) per second,
+ *   rates[SPS_PROBE_VALU_PERM] sustained byte permutes (v_perm_b32) per second,
+ *   rates[SPS_PROBE_LDS_READ]  sustained LDS read bytes per second
+ *                              (16-byte lane-consecutive reads, no bank conflicts).
+ * The vector rates come from eight independent chains of the instruction on
+ * every lane of 8192 workgroups of 256 threads.  The figure derived from
+ * unit counts for one lane-op per lane per 4-cycle pass is 256 CUs x 64 x
+ * 2.4 GHz = 39.3e12/s; for LDS, 128 B/clk/CU x 256 x 2.4 GHz = 78.6e12 B/s.
+ * Synchronous (own stream); allocates and frees 8 MB of device memory; about
+ * 30 ms.  INVALID_ARG: rates NULL, n < SPS_PROBE_COUNT, or no such device;
+ * DEVICE on a HIP error. */
+enum { SPS_PROBE_VALU_ADD = 0, SPS_PROBE_VALU_ADD3 = 1, SPS_PROBE_VALU_PERM = 2,
+       SPS_PROBE_LDS_READ = 3, SPS_PROBE_COUNT = 4 };
+sps_status sps_probe_peaks(int32_t device, double *rates, int32_t n);
+
 /* ---- Streaming: many real-time filterbank streams on one GPU ---- */
 
 /* A server searches admitted streams chunk by chunk.  Each stream keeps a

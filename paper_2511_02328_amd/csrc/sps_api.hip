@@ -1225,4 +1225,22 @@ sps_status sps_tiling_describe(int32_t index, int32_t *m, int32_t *dpw, int32_t 
   return SPS_OK;
 }
 
+sps_status sps_probe_peaks(int32_t device, double *rates, int32_t n) {
+  g_error.clear();
+  if (!rates) return fail(SPS_ERR_INVALID_ARG, "rates is NULL");
+  if (n < SPS_PROBE_COUNT) return fail(SPS_ERR_INVALID_ARG, "rates needs %d entries", SPS_PROBE_COUNT);
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess) return hip_fail(e, "counting devices");
+  if (device < 0 || device >= ndev) return fail(SPS_ERR_INVALID_ARG, "no device %d", device);
+  DeviceScope scope(device);
+  if (scope.err != hipSuccess) return hip_fail(scope.err, "selecting the device");
+  hipStream_t s = nullptr;
+  e = hipStreamCreate(&s);
+  if (e == hipSuccess) e = sps::probe_device_peaks(rates, s);
+  if (s) (void)hipStreamDestroy(s);
+  if (e != hipSuccess) return hip_fail(e, "device probes");
+  return SPS_OK;
+}
+
 }  // extern "C"

@@ -119,6 +119,7 @@ def library() -> ctypes.CDLL:
         lib.sps_tiling_count.argtypes = []
         lib.sps_tiling_count.restype = i32
         lib.sps_tiling_describe.argtypes = [i32] + [ctypes.POINTER(i32)] * 5
+        lib.sps_probe_peaks.argtypes = [i32, ctypes.POINTER(ctypes.c_double), i32]
         lib.sps_server_create.argtypes = [i64, i32, ctypes.POINTER(P)]
         lib.sps_server_destroy.argtypes = [P]
         lib.sps_server_add_stream.argtypes = [P, ctypes.POINTER(sps_obs_desc), P, i32,
@@ -171,7 +172,8 @@ def library() -> ctypes.CDLL:
                   "sps_subband_plan_create", "sps_subband_tables", "sps_dedisperse_subband",
                   "sps_zero_dm", "sps_downsample_sqrt", "sps_batch_create", "sps_batch_destroy",
                   "sps_batch_enqueue", "sps_batch_launch_graph", "sps_batch_candidates",
-                  "sps_plan_autotune", "sps_batch_autotune", "sps_tiling_describe"):
+                  "sps_plan_autotune", "sps_batch_autotune", "sps_tiling_describe",
+                  "sps_probe_peaks"):
             getattr(lib, f).restype = ctypes.c_int
         lib.sps_last_error.argtypes = []
         lib.sps_last_error.restype = ctypes.c_char_p
@@ -460,6 +462,15 @@ def sps_tiling_describe(index: int) -> dict:
     _check(library().sps_tiling_describe(int(index), *[ctypes.byref(x) for x in v]),
            "sps_tiling_describe")
     return dict(zip(("m", "dpw", "nw", "cs", "waves_per_eu"), (x.value for x in v)))
+
+
+def sps_probe_peaks(device: int = 0) -> dict:
+    """Sustained lane-ops/s of v_add_u32, v_add3_u32, v_perm_b32 and LDS read
+    bytes/s of the device."""
+    rates = (ctypes.c_double * 4)()
+    _check(library().sps_probe_peaks(int(device), rates, 4), "sps_probe_peaks")
+    return {"valu_add_ops_per_s": rates[0], "valu_add3_ops_per_s": rates[1],
+            "valu_perm_ops_per_s": rates[2], "lds_read_bytes_per_s": rates[3]}
 
 
 def sps_batch_autotune(batch: Batch, iters: int = 3, stream=None) -> list:

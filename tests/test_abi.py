@@ -57,6 +57,10 @@ def test_null_arguments_fail_before_touching_a_device(lib):
     assert lib.sps_dedisperse(None, None, 16, 16, None, 1, 0, None) == 1
     lib.sps_plan_destroy.argtypes = [ctypes.c_void_p]
     assert lib.sps_plan_destroy(None) == 0
+    lib.sps_probe_peaks.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32]
+    assert lib.sps_probe_peaks(0, None, 4) == 1
+    rates = (ctypes.c_double * 3)()
+    assert lib.sps_probe_peaks(0, rates, 3) == 1
 
 
 def test_no_cpu_fallback_in_the_product_package():

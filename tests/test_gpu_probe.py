@@ -1,0 +1,38 @@
+"""The device probes behind the bench's measured peaks: both rates land near
+the figures derived from MI355X's unit counts and clock (256 CUs x 64 lanes
+x 2.4 GHz of 32-bit adds; 128 B/clk/CU of LDS reads), and bad arguments are
+refused."""
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+DERIVED_ADDS = 256 * 64 * 2.4e9
+DERIVED_LDS = 256 * 128 * 2.4e9
+
+
+@pytest.fixture(scope="module")
+def sps():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2511_02328_amd import sps as mod
+    mod.library()
+    return mod
+
+
+def test_probe_rates_plausible(sps):
+    p = sps.sps_probe_peaks(0)
+    print(" ".join(f"{k} {v:.4e}" for k, v in p.items()))
+    # one lane-op per lane per 4-cycle pass is the floor of any VALU rate;
+    # two passes' worth per cycle would be twice that
+    for k in ("valu_add_ops_per_s", "valu_add3_ops_per_s", "valu_perm_ops_per_s"):
+        assert 0.5 * DERIVED_ADDS < p[k] < 2.2 * DERIVED_ADDS, k
+    # CDNA3's 128 B/clk/CU is the derived figure; CDNA4 may read more
+    assert 0.5 * DERIVED_LDS < p["lds_read_bytes_per_s"] < 3.0 * DERIVED_LDS
+
+
+def test_probe_rejects_missing_device(sps):
+    with pytest.raises(sps.SpsError) as ei:
+        sps.sps_probe_peaks(torch.cuda.device_count() + 3)
+    assert ei.value.name == "SPS_ERR_INVALID_ARG"
