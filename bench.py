@@ -24,10 +24,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# MI355X: 256 CUs x 64 lanes x 2.4 GHz of 32-bit integer adds.
-ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
-# LDS reads: 128 B per clock per CU.
-LDS_PEAK_BPS = 256 * 128 * 2.4e9
+# MI355X vector ALU: 256 CUs x 64 lanes x 2.4 GHz, two 32-bit lane-ops per
+# lane per clock -- the rate behind the published 157.3 TFLOP/s FP32 vector
+# peak (two FMAs = four flops per lane per clock).  Two-operand integer ops
+# (v_add_u32) reach it; three-operand ops (v_add3_u32, v_perm_b32) issue at
+# half of it (sps_probe_peaks measures both on the device).
+ALU_PEAK_TOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+# LDS reads: 256 B per clock per CU (CDNA4 doubled CDNA3's 128 B; the probe
+# sustains about 0.92 of this).
+LDS_PEAK_BPS = 256 * 256 * 2.4e9
 # Dense BF16 matrix cores.
 BF16_PEAK_TFLOPS = 2500.0
 # HBM3E.
@@ -61,8 +66,10 @@ def measured_counters(wl, tiling):
 
 # Vector instructions per 16-channel slab of the dedispersion kernel's inner
 # loop, per lane (320 sample-adds: 20 outputs x 16 channels), read from its
-# ISA: byte permutes, three-input adds and address adds.
+# ISA: byte permutes, three-input adds and address adds.  The first two are
+# three-operand ops, which take two of the ALU's lane-op issue slots.
 SLAB_PERMS, SLAB_ADD3S, SLAB_ADDS, SLAB_SAMPLE_ADDS = 160, 80, 18, 320
+SLAB_SLOTS_PER_ADD = (2 * SLAB_PERMS + 2 * SLAB_ADD3S + SLAB_ADDS) / SLAB_SAMPLE_ADDS
 
 
 def measured_peaks(sps, achieved_tops, lds_bytes_per_add=None):
@@ -269,12 +276,14 @@ def main():
                      "traffic_unit": "bytes per launch (FETCH_SIZE x2.0 + WRITE_SIZE x1.0, "
                                      "scaled by a 1 GiB copy)",
                      "work_per_launch": f"{adds} sample-adds (ndm x nout x nchan)",
-                     # the packed (SWAR) kernel spends < 1 VALU op per sample-add:
-                     # its own ceilings are the VALU issue rate at the measured
-                     # ops per add, and the LDS read rate at (m+1)/m bytes per add
+                     # the packed (SWAR) kernel spends 0.82 VALU lane-ops per
+                     # sample-add, mostly three-operand ops that take two issue
+                     # slots each: its own ceilings are the ALU's issue slots at
+                     # the slab loop's slots per add, and the LDS read rate at
+                     # (m+1)/m bytes per add
                      "valu_lane_ops_per_add": counters["ops_per_add"] if counters else None,
-                     "valu_issue_frac": (achieved * counters["ops_per_add"] / ALU_PEAK_TOPS
-                                         if counters else None),
+                     "issue_slots_per_add": SLAB_SLOTS_PER_ADD,
+                     "valu_issue_frac": achieved * SLAB_SLOTS_PER_ADD / ALU_PEAK_TOPS,
                      "lds_read_frac": (achieved * 1e12 * (tiling["m"] + 1) / tiling["m"]
                                        / LDS_PEAK_BPS if tiling["m"] else None),
                      "measured_peaks": measured_peaks(

@@ -307,9 +307,11 @@ sps_status sps_tiling_describe(int32_t index, int32_t *m, int32_t *dpw, int32_t 
  *   rates[SPS_PROBE_LDS_READ]  sustained LDS read bytes per second
  *                              (16-byte lane-consecutive reads, no bank conflicts).
  * The vector rates come from eight independent chains of the instruction on
- * every lane of 8192 workgroups of 256 threads.  The figure derived from
- * unit counts for one lane-op per lane per 4-cycle pass is 256 CUs x 64 x
- * 2.4 GHz = 39.3e12/s; for LDS, 128 B/clk/CU x 256 x 2.4 GHz = 78.6e12 B/s.
+ * every lane of 8192 workgroups of 256 threads.  The figures derived from
+ * unit counts: 256 CUs x 64 lanes x 2 lane-ops per clock x 2.4 GHz =
+ * 78.6e12/s (the lane rate behind the 157.3 TFLOP/s FP32 vector peak), which
+ * two-operand ops approach and three-operand ops reach half of; LDS reads,
+ * 256 B/clk/CU x 256 x 2.4 GHz = 157.3e12 B/s.
  * Synchronous (own stream); allocates and frees 8 MB of device memory; about
  * 30 ms.  INVALID_ARG: rates NULL, n < SPS_PROBE_COUNT, or no such device;
  * DEVICE on a HIP error. */

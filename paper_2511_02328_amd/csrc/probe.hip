@@ -3,7 +3,9 @@
 // three-input add, byte permute) and LDS reads.  Each rate is what the
 // device sustains at its actual clock, in lane-operations (or bytes) per
 // second, so a kernel's fraction can be stated against the instruction mix
-// it issues as well as against the figures derived from unit counts.
+// it issues as well as against the figures derived from unit counts.  On
+// MI355X two-operand 32-bit ops issue at two lane-ops per lane per clock and
+// three-operand ops (v_add3_u32, v_perm_b32) at one.
 #include "sps_internal.h"
 
 namespace sps {
