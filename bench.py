@@ -30,8 +30,9 @@ if ROOT not in sys.path:
 # (v_add_u32) reach it; three-operand ops (v_add3_u32, v_perm_b32) issue at
 # half of it (sps_probe_peaks measures both on the device).
 ALU_PEAK_TOPS = 256 * 64 * 2 * 2.4e9 / 1e12
-# LDS reads: 256 B per clock per CU (CDNA4 doubled CDNA3's 128 B; the probe
-# sustains about 0.92 of this).
+# LDS reads: 256 B per clock per CU with 16-byte reads (CDNA4 doubled CDNA3's
+# 128 B; the probe sustains about 0.92 of this).  The dedispersion kernel's
+# window reads are 4-byte, for which the probe finds about half of it.
 LDS_PEAK_BPS = 256 * 256 * 2.4e9
 # Dense BF16 matrix cores.
 BF16_PEAK_TFLOPS = 2500.0
@@ -85,11 +86,13 @@ def measured_peaks(sps, achieved_tops, lds_bytes_per_add=None):
            "valu_add3_tops": p["valu_add3_ops_per_s"] / 1e12,
            "valu_perm_tops": p["valu_perm_ops_per_s"] / 1e12,
            "lds_read_tbps": p["lds_read_bytes_per_s"] / 1e12,
+           "lds_read32_tbps": p["lds_read32_bytes_per_s"] / 1e12,
            "slab_mix_tops": mix / 1e12,
            "frac_of_valu_add": achieved_tops * 1e12 / p["valu_add_ops_per_s"],
            "frac_of_slab_mix": achieved_tops * 1e12 / mix}
-    if lds_bytes_per_add:
-        out["lds_read_frac"] = achieved_tops * 1e12 * lds_bytes_per_add / p["lds_read_bytes_per_s"]
+    if lds_bytes_per_add:  # against the 4-byte read rate, the kernel's access width
+        out["lds_read_frac"] = (achieved_tops * 1e12 * lds_bytes_per_add
+                                / p["lds_read32_bytes_per_s"])
     return out
 
 

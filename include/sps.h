@@ -305,18 +305,20 @@ sps_status sps_tiling_describe(int32_t index, int32_t *m, int32_t *dpw, int32_t 
  *   rates[SPS_PROBE_VALU_ADD3] sustained three-input adds (v_add3_u32) per second,
  *   rates[SPS_PROBE_VALU_PERM] sustained byte permutes (v_perm_b32) per second,
  *   rates[SPS_PROBE_LDS_READ]  sustained LDS read bytes per second
- *                              (16-byte lane-consecutive reads, no bank conflicts).
+ *                              (16-byte lane-consecutive reads, no bank conflicts),
+ *   rates[SPS_PROBE_LDS_READ32] the same with 4-byte reads.
  * The vector rates come from eight independent chains of the instruction on
  * every lane of 8192 workgroups of 256 threads.  The figures derived from
  * unit counts: 256 CUs x 64 lanes x 2 lane-ops per clock x 2.4 GHz =
  * 78.6e12/s (the lane rate behind the 157.3 TFLOP/s FP32 vector peak), which
  * two-operand ops approach and three-operand ops reach half of; LDS reads,
- * 256 B/clk/CU x 256 x 2.4 GHz = 157.3e12 B/s.
+ * 256 B/clk/CU x 256 x 2.4 GHz = 157.3e12 B/s with 16-byte reads, half of
+ * that with 4-byte reads.
  * Synchronous (own stream); allocates and frees 8 MB of device memory; about
  * 30 ms.  INVALID_ARG: rates NULL, n < SPS_PROBE_COUNT, or no such device;
  * DEVICE on a HIP error. */
 enum { SPS_PROBE_VALU_ADD = 0, SPS_PROBE_VALU_ADD3 = 1, SPS_PROBE_VALU_PERM = 2,
-       SPS_PROBE_LDS_READ = 3, SPS_PROBE_COUNT = 4 };
+       SPS_PROBE_LDS_READ = 3, SPS_PROBE_LDS_READ32 = 4, SPS_PROBE_COUNT = 5 };
 sps_status sps_probe_peaks(int32_t device, double *rates, int32_t n);
 
 /* ---- Streaming: many real-time filterbank streams on one GPU ---- */

@@ -1,6 +1,6 @@
 // probe.hip -- microbenchmarks of the device rates the dedispersion kernel
 // is measured against: the vector instructions it is made of (32-bit add,
-// three-input add, byte permute) and LDS reads.  Each rate is what the
+// three-input add, byte permute) and LDS reads (16-byte and 4-byte).  Each rate is what the
 // device sustains at its actual clock, in lane-operations (or bytes) per
 // second, so a kernel's fraction can be stated against the instruction mix
 // it issues as well as against the figures derived from unit counts.  On
@@ -70,6 +70,28 @@ __global__ __launch_bounds__(kProbeThreads) void lds_read_probe_kernel(uint32_t 
   out[(int64_t)blockIdx.x * kProbeThreads + threadIdx.x] = acc.x ^ acc.y ^ acc.z ^ acc.w;
 }
 
+// 4-byte LDS reads, lane-consecutive (conflict-free), eight per iteration:
+// the access width of the dedispersion kernel's window reads.  The address
+// depends on the running sum as above.
+__global__ __launch_bounds__(kProbeThreads) void lds_read32_probe_kernel(uint32_t *__restrict__ out,
+                                                                         int iters) {
+  __shared__ uint32_t buf[16 * kProbeThreads];  // 16 KB
+  for (int i = threadIdx.x; i < 16 * kProbeThreads; i += kProbeThreads) buf[i] = (uint32_t)i;
+  __syncthreads();
+  uint32_t acc = 0u, acc2 = 0u;
+  for (int i = 0; i < iters; ++i) {
+    const uint32_t *p = buf + (acc & 1u) * (8 * kProbeThreads) + threadIdx.x;
+    const uint32_t v0 = p[0], v1 = p[kProbeThreads], v2 = p[2 * kProbeThreads],
+                   v3 = p[3 * kProbeThreads], v4 = p[4 * kProbeThreads], v5 = p[5 * kProbeThreads],
+                   v6 = p[6 * kProbeThreads], v7 = p[7 * kProbeThreads];
+    acc = acc + v0 + v1;
+    acc2 = acc2 + v2 + v3;
+    acc = acc + v4 + v5;
+    acc2 = acc2 + v6 + v7;
+  }
+  out[(int64_t)blockIdx.x * kProbeThreads + threadIdx.x] = acc ^ acc2;
+}
+
 // Mean duration of one launch (ms), after an untimed shorter one.
 template <typename F>
 hipError_t time_launch(F launch, hipEvent_t e0, hipEvent_t e1, hipStream_t stream, float *ms) {
@@ -115,6 +137,13 @@ hipError_t probe_device_peaks(double *rates, hipStream_t stream) {
                          warm ? kLdsIters / 10 : kLdsIters);
     }, e0, e1, stream, &ms);
     if (e == hipSuccess) rates[3] = threads * kLdsIters * 4.0 * 16.0 / (ms * 1e-3);
+  }
+  if (e == hipSuccess) {
+    e = time_launch([&](bool warm) {
+      hipLaunchKernelGGL(lds_read32_probe_kernel, grid, block, 0, stream, out,
+                         warm ? kLdsIters / 10 : kLdsIters);
+    }, e0, e1, stream, &ms);
+    if (e == hipSuccess) rates[4] = threads * kLdsIters * 8.0 * 4.0 / (ms * 1e-3);
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);

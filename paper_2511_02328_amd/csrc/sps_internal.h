@@ -207,7 +207,8 @@ sps_status cnn_count_cells(sps_cnn net, const uint16_t *tiles, int32_t n, float 
                            int32_t *count, hipStream_t s);
 
 // Device microbenchmarks (probe.hip): rates[0..2] = sustained lane-ops/s of
-// v_add_u32, v_add3_u32 and v_perm_b32; rates[3] = LDS read bytes/s.
+// v_add_u32, v_add3_u32 and v_perm_b32; rates[3], rates[4] = LDS read
+// bytes/s with 16-byte and 4-byte reads.
 // Synchronous on `stream`; allocates and frees 8 MB.
 hipError_t probe_device_peaks(double *rates, hipStream_t stream);
 

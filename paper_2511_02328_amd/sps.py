@@ -466,11 +466,12 @@ def sps_tiling_describe(index: int) -> dict:
 
 def sps_probe_peaks(device: int = 0) -> dict:
     """Sustained lane-ops/s of v_add_u32, v_add3_u32, v_perm_b32 and LDS read
-    bytes/s of the device."""
-    rates = (ctypes.c_double * 4)()
-    _check(library().sps_probe_peaks(int(device), rates, 4), "sps_probe_peaks")
+    bytes/s (16-byte and 4-byte reads) of the device."""
+    rates = (ctypes.c_double * 5)()
+    _check(library().sps_probe_peaks(int(device), rates, 5), "sps_probe_peaks")
     return {"valu_add_ops_per_s": rates[0], "valu_add3_ops_per_s": rates[1],
-            "valu_perm_ops_per_s": rates[2], "lds_read_bytes_per_s": rates[3]}
+            "valu_perm_ops_per_s": rates[2], "lds_read_bytes_per_s": rates[3],
+            "lds_read32_bytes_per_s": rates[4]}
 
 
 def sps_batch_autotune(batch: Batch, iters: int = 3, stream=None) -> list:

@@ -59,8 +59,8 @@ def test_null_arguments_fail_before_touching_a_device(lib):
     assert lib.sps_plan_destroy(None) == 0
     lib.sps_probe_peaks.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32]
     assert lib.sps_probe_peaks(0, None, 4) == 1
-    rates = (ctypes.c_double * 3)()
-    assert lib.sps_probe_peaks(0, rates, 3) == 1
+    rates = (ctypes.c_double * 4)()
+    assert lib.sps_probe_peaks(0, rates, 4) == 1
 
 
 def test_no_cpu_fallback_in_the_product_package():

@@ -30,6 +30,8 @@ def test_probe_rates_plausible(sps):
     for k in ("valu_add3_ops_per_s", "valu_perm_ops_per_s"):
         assert 0.3 * DERIVED_OPS < p[k] < 0.55 * DERIVED_OPS, k
     assert 0.5 * DERIVED_LDS < p["lds_read_bytes_per_s"] < 1.05 * DERIVED_LDS
+    # 4-byte reads move at most as much per clock as 16-byte ones
+    assert 0.2 * DERIVED_LDS < p["lds_read32_bytes_per_s"] <= 1.05 * p["lds_read_bytes_per_s"]
 
 
 def test_probe_rejects_missing_device(sps):
