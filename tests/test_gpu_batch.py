@@ -67,7 +67,11 @@ def _check_beams(sps, plan, batch, beams, widths):
         assert nb == n and np.array_equal(cb, c), f"beam {i} candidates"
 
 
-@pytest.mark.parametrize("nouts", [[3000, 5000, 1281, 7777, 4096], [16], [20000] * 3])
+# the last case: 40 beams, so the kernels' beam lookup (a binary search over
+# the beams' first work items) takes several levels, with tiny, ragged and
+# segment-edge lengths side by side
+@pytest.mark.parametrize("nouts", [[3000, 5000, 1281, 7777, 4096], [16], [20000] * 3,
+                                   [16, 17, 1000, 4095, 4096, 4097, 333, 8191] * 5])
 def test_batch_equals_single_calls(sps, nouts):
     wl = _wl(nouts[0], 0)
     widths = list(wl.widths)
