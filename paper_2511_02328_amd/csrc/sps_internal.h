@@ -44,6 +44,8 @@ bool dedisp_config_supported(const DedispConfig &cfg);
 #define SPS_GLOBAL __attribute__((address_space(1)))
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+// four dwords at any dword-aligned address (one 16-byte load on gfx950)
+typedef unsigned int u32x4_a4 __attribute__((ext_vector_type(4), aligned(4)));
 
 template <typename T>
 __device__ __forceinline__ const SPS_GLOBAL T *gmem(const T *p) {
