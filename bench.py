@@ -143,8 +143,10 @@ def main():
 
     import torch
 
-    from paper_2511_02328_amd import sps, synth
-    from paper_2511_02328_amd.workloads import BATCH_WORKLOADS, STREAMING_WORKLOADS, WORKLOADS
+    from paper_2511_02328_amd import sps
+
+    from sps_inputs import synth
+    from sps_inputs.workloads import BATCH_WORKLOADS, STREAMING_WORKLOADS, WORKLOADS
 
     if args.workload == "detector":
         return bench_detector(args)
@@ -303,7 +305,9 @@ def bench_batched(args, bw):
     """Many beams of one receiver, one chunk each, replayed from a HIP graph."""
     import torch
 
-    from paper_2511_02328_amd import sps, synth
+    from paper_2511_02328_amd import sps
+
+    from sps_inputs import synth
     wl0 = bw.base
     torch.cuda.set_device(0)
     plan = sps.plan_for(wl0)
@@ -400,7 +404,9 @@ def bench_streaming(args, sw):
     and every chunk's latency (search finished minus arrival) is recorded."""
     import torch
 
-    from paper_2511_02328_amd import sps, synth
+    from paper_2511_02328_amd import sps
+
+    from sps_inputs import synth
     torch.cuda.set_device(0)
     streams = sw.streams()
     setups = []
@@ -637,7 +643,9 @@ def bench_subband(args, wl):
     brute force: time per chunk and S/N kept at the injected pulses."""
     import torch
 
-    from paper_2511_02328_amd import sps, synth
+    from paper_2511_02328_amd import sps
+
+    from sps_inputs import synth
     torch.cuda.set_device(0)
     ddm = (wl.dm_hi - wl.dm_lo) / (wl.ndm - 1)
     plan = sps.sps_subband_plan_create(wl.freqs_mhz(), wl.fref_mhz, wl.tsamp_s, wl.ndm, wl.dm_lo,
@@ -708,6 +716,31 @@ def bench_subband(args, wl):
     plan.close()
 
 
+def host_cpu():
+    """The host the CPU baseline ran on: CPU model (lscpu / /proc/cpuinfo),
+    nproc (CPUs this process may use) and the logical CPU count."""
+    model = None
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except (OSError, subprocess.SubprocessError):
+        pass
+    if model is None:
+        try:
+            with open("/proc/cpuinfo") as f:
+                for line in f:
+                    if line.startswith("model name"):
+                        model = line.split(":", 1)[1].strip()
+                        break
+        except OSError:
+            pass
+    return {"model": model, "nproc": len(os.sched_getaffinity(0)), "logical_cpus": os.cpu_count()}
+
+
 def cpu_baseline(wl, X, nsamp, Y, nrows, det):
     """The oracle on a bounded sample: every (ndm / nrows)-th DM row of the same
     chunk at full length, through dedispersion, statistics, boxcar and
@@ -729,6 +762,7 @@ def cpu_baseline(wl, X, nsamp, Y, nrows, det):
     print(f"[bench] cpu baseline: {sec:.1f} s, sampled rows bit-exact: {ok}", flush=True)
     return {"value": nrows * wl.nout / sec, "unit": "DM-time samples/s",
             "cores": oracle.threads(), "kind": "oracle",
+            "host": host_cpu(),
             "sample": f"{nrows} of {wl.ndm} DM rows (evenly spaced) of one chunk at full length "
                       f"({wl.nout} samples): dedisperse + stats + boxcar + detect; {sec:.1f} s",
             "sampled_rows_match_gpu": ok}

@@ -149,8 +149,10 @@ typedef struct {
  *   out:         host array of cap records (may be NULL when cap == 0),
  *                receiving the first min(n, cap) accepted in that order.
  *   n_found:     host, receives n, the number accepted.
- * Returns SPS_ERR_TRUNCATED (after filling out) if n > cap.  RANGE if more
- * than 8192 tiles reach the threshold (raise the threshold or the tile size).
+ * Any number of tiles may reach the threshold.  Suppression radii larger
+ * than the plane act as the plane's extent.  The plan keeps device scratch
+ * of about 56 bytes per tile (allocated on first use, grown with the tile
+ * count).  Returns SPS_ERR_TRUNCATED (after filling out) if n > cap.
  * Synchronises the stream. */
 sps_status sps_detect(sps_plan plan, const float *snr, const uint8_t *best_w, int64_t nout,
                       const int32_t *widths, int32_t nw, const sps_detect_params *params,
@@ -250,8 +252,8 @@ typedef struct sps_batch_s *sps_batch;
  * uploads the work description and allocates all scratch, so that running
  * the batch allocates nothing and never waits on the host.  The plan's
  * current tiling is used (call sps_plan_autotune / sps_plan_set_tiling
- * first); the plan must outlive the batch.  RANGE if a beam has more than
- * 8192 detection tiles or the plan needs the plain kernel. */
+ * first); the plan must outlive the batch.  RANGE if the plan needs the
+ * plain kernel.  Every beam's candidates read "none" until its first run. */
 sps_status sps_batch_create(sps_plan plan, int32_t nbeams, const sps_beam *beams,
                             const int32_t *widths, int32_t nw, const sps_detect_params *params,
                             uint32_t flags, sps_batch *out);
@@ -342,8 +344,10 @@ sps_status sps_server_create(int64_t hbm_budget, int32_t nworkers, sps_server *o
 sps_status sps_server_destroy(sps_server server);
 
 /* Admits a stream: desc as for sps_plan_create, widths/nw and det as for
- * sps_boxcar_snr / sps_detect, chunk_len >= largest width.  NOMEM (nothing
- * allocated) when ring + new plans + plane growth would exceed the budget.
+ * sps_boxcar_snr / sps_detect (checked here exactly as those calls check
+ * them, so that no chunk fails for its parameters), chunk_len >= largest
+ * width.  NOMEM (nothing allocated) when ring + new plans (with their
+ * detection scratch) + plane growth would exceed the budget.
  * *stream_id numbers streams 0, 1, ... in admission order. */
 sps_status sps_server_add_stream(sps_server server, const sps_obs_desc *desc,
                                  const int32_t *widths, int32_t nw, const sps_detect_params *det,
@@ -397,8 +401,10 @@ typedef struct {
  * not issued, and the call returns when every issued chunk is searched.
  * Workers take chunks in arrival order, a stream's chunks in sequence.
  * records (cap entries) receive one record per chunk in arrival order;
- * *n_records is the true count (TRUNCATED if above cap).  A failing chunk
- * stops the run and its status is returned. */
+ * *n_records is the true count (TRUNCATED if above cap).  A chunk that fails
+ * with SPS_ERR_DEVICE or SPS_ERR_NOMEM stops the run and that status is
+ * returned; any other failure is kept in the chunk's record (status) and the
+ * run goes on. */
 sps_status sps_server_run(sps_server server, const sps_feed *feeds, double run_s,
                           double compression, sps_chunk_record *records, int32_t cap,
                           int32_t *n_records);

@@ -116,7 +116,7 @@ def conv3x3_backward(x: np.ndarray, w: np.ndarray, dout: np.ndarray, stride: int
 def init_params(seed: int) -> dict:
     """He-normal 3x3 weights, zero biases, head weights N(0, 1/128), head
     biases (-4, 0.5, 0.5), drawn by the shared seeded input generator."""
-    from paper_2511_02328_amd.synth import seeded_weights
+    from sps_inputs.synth import seeded_weights
     specs = []
     for i, (ci, co, _) in enumerate(LAYERS):
         specs += [(f"w{i}", (co, ci, 3, 3), np.sqrt(2.0 / (9 * ci))), (f"b{i}", (co,), 0.0)]

@@ -5,7 +5,7 @@ detection (ASTROFLOW, arXiv:2511.02328, Sec. 1 and Sec. 2.3).
 
 The computation lives in a HIP shared library behind a C ABI
 (``include/sps.h``); :mod:`paper_2511_02328_amd.sps` is its ctypes binding.
-Submodules are imported on demand so that the workload and generator modules
-work without a GPU.
+The workload descriptions and the seeded input generators live in the
+separate package ``sps_inputs``, which holds no step of the search.
 """
-__all__ = ["sps", "synth", "workloads"]
+__all__ = ["sps", "detector"]

@@ -6,10 +6,12 @@
 // order-preserving unsigned integer in the high word, the complement of the
 // in-tile position t_local * tile_dm + d_local in the low word.
 // Stage 2 (select_nms_kernel): one workgroup gathers the peaks at or above
-// the threshold into LDS, sorts them (bitonic) by S/N descending, then t,
-// then d, and accepts them greedily unless an accepted one lies within the
-// suppression radius.  The candidate record carries DM, arrival time at the
-// top of the band, width and S/N (ASTROFLOW Sec. 2).
+// the threshold, sorts them (bitonic) by S/N descending, then t, then d, and
+// accepts them greedily unless an accepted one lies within the suppression
+// radius.  Offers that fit stay in LDS; any larger number goes through the
+// global arrays of the plane's detection scratch.  The candidate record
+// carries DM, arrival time at the top of the band, width and S/N (ASTROFLOW
+// Sec. 2).
 #include <float.h>
 #include <limits.h>
 
@@ -100,13 +102,16 @@ __global__ __launch_bounds__(kTileThreads) void tile_peaks_kernel(
   tile_peak(snr, best, ndm, nout, tile_dm, tile_t, ntt, blockIdx.x, peaks + blockIdx.x);
 }
 
+// Beam b's tile peaks go to the peaks array of its scratch (scratch +
+// beams[b].det_begin).
 __global__ __launch_bounds__(kTileThreads) void tile_peaks_batch_kernel(
     const BeamWork *__restrict__ beams, int nbeams, int ndm, int tile_dm, int64_t tile_t,
-    TilePeak *__restrict__ peaks) {
+    uint8_t *__restrict__ scratch) {
   const int64_t blk = blockIdx.x;
   const BeamWork &bw = beams[find_beam<&BeamWork::tp_begin>(beams, nbeams, blk)];
-  tile_peak(bw.snr, bw.best, ndm, bw.nout, tile_dm, tile_t, bw.ntt, blk - bw.tp_begin,
-            peaks + blk);
+  TilePeak *peaks = reinterpret_cast<TilePeak *>(scratch + bw.det_begin);
+  const int64_t local = blk - bw.tp_begin;
+  tile_peak(bw.snr, bw.best, ndm, bw.nout, tile_dm, tile_t, bw.ntt, local, peaks + local);
 }
 
 // True if a comes before b: S/N descending, then t, then d.
@@ -122,85 +127,113 @@ __device__ __forceinline__ bool near(const TilePeak &a, const TilePeak &b, int n
   return (dd < 0 ? -dd : dd) <= nms_dm && (dt < 0 ? -dt : dt) <= nms_t;
 }
 
-// Selection and greedy suppression in one workgroup.  Offers (tile peaks at
-// or above the threshold) are gathered into LDS and bitonic-sorted into
-// "before" order.  Greedy acceptance in that order has a unique result; when
-// the suppression radius spans few tiles it is computed in parallel rounds:
-// an offer is rejected once an accepted, earlier, nearby offer exists, and
-// accepted once every earlier nearby offer is rejected.  Each round decides
-// at least the earliest undecided offer, and decisions are final, so reading
-// neighbours' states while they change is safe.  Otherwise the offers are
-// scanned one by one.
-__device__ void select_nms(const TilePeak *__restrict__ peaks, int64_t npeaks, int ntd,
-                           int64_t ntt, int tile_dm, int64_t tile_t, float threshold, int nms_dm,
-                           int64_t nms_t, TilePeak *__restrict__ out,
-                           int32_t *__restrict__ status) {
-  __shared__ TilePeak offer[kMaxOffers];
-  __shared__ int16_t aux[kMaxOffers];  // tile -> offer rank, or the accepted list
-  __shared__ uint8_t state[kMaxOffers];  // 0 undecided, 1 accepted, 2 rejected
-  __shared__ int count;
-  __shared__ int naccept;
-  __shared__ uint32_t tmp[kNmsThreads / 64];
+__device__ __forceinline__ TilePeak sentinel() {
+  TilePeak s;
+  s.snr = -FLT_MAX;
+  s.d = INT_MAX;
+  s.t = INT_MAX;
+  s.w = 0xFF;
+  return s;
+}
+
+// One compare-exchange step (k, j) of a bitonic sorting network into
+// "before" order over the pairs of a[0 .. n2 * 2); idx0: global index of
+// a[0] (the direction of a pair depends on its global index).
+__device__ __forceinline__ void bitonic_step(TilePeak *a, int64_t n2, int64_t idx0, int64_t k,
+                                             int64_t j) {
+  for (int64_t i = threadIdx.x; i < n2; i += kNmsThreads) {
+    const int64_t lo = 2 * i - (i & (j - 1));
+    const int64_t hi = lo + j;
+    const bool up = ((idx0 + lo) & k) == 0;
+    const TilePeak x = a[lo], y = a[hi];
+    if (up ? before(y, x) : before(x, y)) {
+      a[lo] = y;
+      a[hi] = x;
+    }
+  }
+}
+
+// Sorts a[0 .. npow) (npow a power of two) into "before" order with one
+// workgroup; lds: kMaxOffers records.  Up to kMaxOffers records the whole
+// network runs in LDS.  Beyond, blocks of kMaxOffers are sorted in LDS
+// (alternating directions, as the network's first log2(kMaxOffers) stages
+// leave them), then every merge stage takes its strides >= kMaxOffers on the
+// global array and its shorter strides block by block in LDS.
+__device__ void sort_offers(TilePeak *a, int64_t npow, TilePeak *lds) {
+  constexpr int64_t B = kMaxOffers;
   const int tid = threadIdx.x;
-  if (tid == 0) {
-    count = 0;
-    naccept = 0;
-  }
-  __syncthreads();
-  for (int64_t i = tid; i < npeaks; i += kNmsThreads) {
-    const TilePeak p = peaks[i];
-    if (p.snr >= threshold) {
-      const int slot = atomicAdd(&count, 1);
-      if (slot < kMaxOffers) offer[slot] = p;
-    }
-  }
-  __syncthreads();
-  const int n = count;
-  if (n > kMaxOffers) {
-    if (tid == 0) {
-      status[0] = n;
-      status[1] = 0;
-      status[2] = 1;
-    }
+  if (npow <= B) {
+    for (int64_t i = tid; i < npow; i += kNmsThreads) lds[i] = a[i];
+    __syncthreads();
+    for (int64_t k = 2; k <= npow; k <<= 1)
+      for (int64_t j = k >> 1; j > 0; j >>= 1) {
+        bitonic_step(lds, npow / 2, 0, k, j);
+        __syncthreads();
+      }
+    for (int64_t i = tid; i < npow; i += kNmsThreads) a[i] = lds[i];
+    __syncthreads();
     return;
   }
-  int npow = 1;
-  while (npow < n) npow <<= 1;
-  for (int i = n + tid; i < npow; i += kNmsThreads) {
-    TilePeak s;
-    s.snr = -FLT_MAX;
-    s.d = INT_MAX;
-    s.t = INT_MAX;
-    s.w = 0xFF;
-    offer[i] = s;
-  }
-  __syncthreads();
-  for (int size = 2; size <= npow; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int i = tid; i < npow / 2; i += kNmsThreads) {
-        const int lo = 2 * i - (i & (stride - 1));
-        const int hi = lo + stride;
-        const bool up = (lo & size) == 0;
-        const TilePeak x = offer[lo], y = offer[hi];
-        if (up ? before(y, x) : before(x, y)) {
-          offer[lo] = y;
-          offer[hi] = x;
-        }
+  // stages k <= B, block by block
+  for (int64_t base = 0; base < npow; base += B) {
+    for (int64_t i = tid; i < B; i += kNmsThreads) lds[i] = a[base + i];
+    __syncthreads();
+    for (int64_t k = 2; k <= B; k <<= 1)
+      for (int64_t j = k >> 1; j > 0; j >>= 1) {
+        bitonic_step(lds, B / 2, base, k, j);
+        __syncthreads();
       }
+    for (int64_t i = tid; i < B; i += kNmsThreads) a[base + i] = lds[i];
+    __syncthreads();
+  }
+  for (int64_t k = 2 * B; k <= npow; k <<= 1) {
+    for (int64_t j = k >> 1; j >= B; j >>= 1) {
+      bitonic_step(a, npow / 2, 0, k, j);
+      __syncthreads();
+    }
+    for (int64_t base = 0; base < npow; base += B) {
+      for (int64_t i = tid; i < B; i += kNmsThreads) lds[i] = a[base + i];
+      __syncthreads();
+      for (int64_t j = B >> 1; j > 0; j >>= 1) {
+        bitonic_step(lds, B / 2, base, k, j);
+        __syncthreads();
+      }
+      for (int64_t i = tid; i < B; i += kNmsThreads) a[base + i] = lds[i];
       __syncthreads();
     }
   }
+}
 
-  const int span_d = (nms_dm + tile_dm - 1) / tile_dm;
+// Greedy suppression of the sorted offers offer[0 .. n): an offer is
+// accepted unless an accepted, earlier offer lies within the radius.  The
+// result of greedy acceptance in a fixed order is unique.  When the radius
+// spans few tiles it is computed in parallel rounds over the tile grid (aux:
+// tile -> rank): an offer is rejected once an accepted, earlier, nearby
+// offer exists, and accepted once every earlier nearby offer is rejected.
+// Each round decides at least the earliest undecided offer, and decisions
+// are final, so reading neighbours' states while they change is safe.
+// Otherwise the offers are scanned one by one against the accepted list
+// (aux).  Writes the accepted offers in order to out; returns their number.
+// AUX is int16_t (LDS, ntiles <= kMaxOffers) or int32_t (global).
+template <typename AUX>
+__device__ __forceinline__ int suppress(const TilePeak *offer, int n, int64_t ntiles, int ntd, int64_t ntt,
+                        int tile_dm, int64_t tile_t, int nms_dm, int64_t nms_t, AUX *aux,
+                        uint8_t *state, TilePeak *__restrict__ out, int *naccept,
+                        uint32_t *tmp) {
+  const int tid = threadIdx.x;
+  // spans in tiles, from radii already clamped to the plane
+  const int64_t span_d = ((int64_t)nms_dm + tile_dm - 1) / tile_dm;
   const int64_t span_t = (nms_t + tile_t - 1) / tile_t;
-  const bool grid = npeaks <= kMaxOffers && (2 * span_d + 1) * (2 * span_t + 1) <= 49;
+  const bool grid = (2 * span_d + 1) * (2 * span_t + 1) <= 49;
+  if (tid == 0) *naccept = 0;
+  __syncthreads();
   if (grid) {
-    for (int i = tid; i < (int)npeaks; i += kNmsThreads) aux[i] = -1;
+    for (int64_t i = tid; i < ntiles; i += kNmsThreads) aux[i] = (AUX)-1;
     for (int i = tid; i < n; i += kNmsThreads) state[i] = 0;
     __syncthreads();
     for (int i = tid; i < n; i += kNmsThreads) {
       const TilePeak c = offer[i];
-      aux[(int64_t)(c.d / tile_dm) * ntt + c.t / tile_t] = (int16_t)i;
+      aux[(int64_t)(c.d / tile_dm) * ntt + c.t / tile_t] = (AUX)i;
     }
     __syncthreads();
     int undecided = 1;
@@ -209,16 +242,16 @@ __device__ void select_nms(const TilePeak *__restrict__ peaks, int64_t npeaks, i
       for (int i = tid; i < n; i += kNmsThreads) {
         if (state[i] != 0) continue;
         const TilePeak c = offer[i];
-        const int a = c.d / tile_dm;
+        const int64_t a = c.d / tile_dm;
         const int64_t b = c.t / tile_t;
         bool blocked = false, rejected = false;
-        for (int da = -span_d; da <= span_d && !rejected; ++da) {
-          const int aa = a + da;
+        for (int64_t da = -span_d; da <= span_d && !rejected; ++da) {
+          const int64_t aa = a + da;
           if (aa < 0 || aa >= ntd) continue;
           for (int64_t db = -span_t; db <= span_t; ++db) {
             const int64_t bb = b + db;
             if (bb < 0 || bb >= ntt) continue;
-            const int j = aux[(int64_t)aa * ntt + bb];
+            const int j = (int)aux[aa * ntt + bb];
             if (j < 0 || j >= i) continue;
             if (!near(c, offer[j], nms_dm, nms_t)) continue;
             const uint8_t sj = *(volatile uint8_t *)&state[j];
@@ -238,6 +271,7 @@ __device__ void select_nms(const TilePeak *__restrict__ peaks, int64_t npeaks, i
       }
       undecided = __syncthreads_or(mine);
     }
+    __syncthreads();  // every state written (they may be in global memory)
     // Accepted offers in order: block-wide exclusive scan of per-thread counts
     // over contiguous runs.
     const int per = (n + kNmsThreads - 1) / kNmsThreads;
@@ -256,50 +290,120 @@ __device__ void select_nms(const TilePeak *__restrict__ peaks, int64_t npeaks, i
     for (int w = 0; w < wave; ++w) pos += tmp[w];
     for (int i = lo; i < hi; ++i)
       if (state[i] == 1) out[pos++] = offer[i];
-    if (tid == kNmsThreads - 1) naccept = (int)pos;
+    if (tid == kNmsThreads - 1) *naccept = (int)pos;
     __syncthreads();
   } else {
     for (int i = 0; i < n; ++i) {
       const TilePeak c = offer[i];
-      const int na = naccept;
+      const int na = *naccept;
       bool hit = false;
       for (int j = tid; j < na; j += kNmsThreads)
-        if (near(c, offer[(uint16_t)aux[j]], nms_dm, nms_t)) hit = true;
+        if (near(c, offer[(int)aux[j]], nms_dm, nms_t)) hit = true;
       const int any = __syncthreads_or(hit);
       if (!any && tid == 0) {
-        aux[na] = (int16_t)i;
-        naccept = na + 1;
+        aux[na] = (AUX)i;
+        *naccept = na + 1;
       }
       __syncthreads();
     }
-    const int na = naccept;
-    for (int j = tid; j < na; j += kNmsThreads) out[j] = offer[(uint16_t)aux[j]];
+    const int na = *naccept;
+    for (int j = tid; j < na; j += kNmsThreads) out[j] = offer[(int)aux[j]];
+  }
+  __syncthreads();
+  return *naccept;
+}
+
+// Selection and greedy suppression of one plane in one workgroup.  The
+// offers (tile peaks at or above the threshold) are counted first.  When
+// they and the tile grid fit in LDS, the offers are gathered, sorted and
+// suppressed there.  Otherwise the global arrays of the scratch hold the
+// offers (sorted with LDS blocks), the tile -> rank map and the states.
+// Either way there is no limit on the number of offers.
+__device__ void select_nms(uint8_t *__restrict__ scratch, int64_t ntiles, int ntd, int64_t ntt,
+                           int tile_dm, int64_t tile_t, float threshold, int nms_dm,
+                           int64_t nms_t) {
+  __shared__ TilePeak offer[kMaxOffers];
+  __shared__ int16_t aux[kMaxOffers];
+  __shared__ uint8_t state[kMaxOffers];
+  __shared__ int count;
+  __shared__ int naccept;
+  __shared__ uint32_t tmp[kNmsThreads / 64];
+  const int tid = threadIdx.x;
+  const DetectLayout L = detect_layout(ntiles);
+  const TilePeak *peaks = reinterpret_cast<const TilePeak *>(scratch + L.peaks);
+  TilePeak *out = reinterpret_cast<TilePeak *>(scratch + L.out);
+  int32_t *status = reinterpret_cast<int32_t *>(scratch + L.status);
+  if (tid == 0) count = 0;
+  __syncthreads();
+  int mine = 0;
+  for (int64_t i = tid; i < ntiles; i += kNmsThreads) mine += peaks[i].snr >= threshold;
+  atomicAdd(&count, mine);
+  __syncthreads();
+  const int n = count;
+  int na = 0;
+  if (n == 0) {
+    na = 0;
+  } else if (ntiles <= kMaxOffers) {
+    if (tid == 0) count = 0;
+    __syncthreads();
+    for (int64_t i = tid; i < ntiles; i += kNmsThreads) {
+      const TilePeak p = peaks[i];
+      if (p.snr >= threshold) offer[atomicAdd(&count, 1)] = p;
+    }
+    __syncthreads();
+    int npow = 1;
+    while (npow < n) npow <<= 1;
+    for (int i = n + tid; i < npow; i += kNmsThreads) offer[i] = sentinel();
+    __syncthreads();
+    for (int k = 2; k <= npow; k <<= 1)
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        bitonic_step(offer, npow / 2, 0, k, j);
+        __syncthreads();
+      }
+    na = suppress<int16_t>(offer, n, ntiles, ntd, ntt, tile_dm, tile_t, nms_dm, nms_t, aux,
+                           state, out, &naccept, tmp);
+  } else {
+    TilePeak *g_offer = reinterpret_cast<TilePeak *>(scratch + L.offer);
+    int32_t *g_aux = reinterpret_cast<int32_t *>(scratch + L.aux);
+    uint8_t *g_state = scratch + L.state;
+    if (tid == 0) count = 0;
+    __syncthreads();
+    for (int64_t i = tid; i < ntiles; i += kNmsThreads) {
+      const TilePeak p = peaks[i];
+      if (p.snr >= threshold) g_offer[atomicAdd(&count, 1)] = p;
+    }
+    int64_t npow = 1;
+    while (npow < n) npow <<= 1;
+    for (int64_t i = n + tid; i < npow; i += kNmsThreads) g_offer[i] = sentinel();
+    __syncthreads();
+    sort_offers(g_offer, npow, offer);
+    na = suppress<int32_t>(g_offer, n, ntiles, ntd, ntt, tile_dm, tile_t, nms_dm, nms_t, g_aux,
+                           g_state, out, &naccept, tmp);
   }
   if (tid == 0) {
     status[0] = n;
-    status[1] = naccept;
+    status[1] = na;
     status[2] = 0;
+    status[3] = 0;
   }
 }
 
 __global__ __launch_bounds__(kNmsThreads) void select_nms_kernel(
-    const TilePeak *__restrict__ peaks, int64_t npeaks, int ntd, int64_t ntt, int tile_dm,
-    int64_t tile_t, float threshold, int nms_dm, int64_t nms_t, TilePeak *__restrict__ out,
-    int32_t *__restrict__ status) {
-  select_nms(peaks, npeaks, ntd, ntt, tile_dm, tile_t, threshold, nms_dm, nms_t, out, status);
+    uint8_t *__restrict__ scratch, int64_t ntiles, int ntd, int64_t ntt, int tile_dm,
+    int64_t tile_t, float threshold, int nms_dm, int64_t nms_t) {
+  select_nms(scratch, ntiles, ntd, ntt, tile_dm, tile_t, threshold, nms_dm, nms_t);
 }
 
-// One workgroup per beam: accepted peaks of beam b go to out[b * kMaxOffers ...]
-// and its status to status[4 b ...].
+// One workgroup per beam, on the beam's own scratch.
 __global__ __launch_bounds__(kNmsThreads) void select_nms_batch_kernel(
     const BeamWork *__restrict__ beams, int ndm, int tile_dm, int64_t tile_t, float threshold,
-    int nms_dm, int64_t nms_t, const TilePeak *__restrict__ peaks, TilePeak *__restrict__ out,
-    int32_t *__restrict__ status) {
-  const int b = blockIdx.x;
-  const BeamWork &bw = beams[b];
+    int nms_dm, int64_t nms_t, uint8_t *__restrict__ scratch) {
+  const BeamWork &bw = beams[blockIdx.x];
   const int ntd = (ndm + tile_dm - 1) / tile_dm;
-  select_nms(peaks + bw.tp_begin, (int64_t)ntd * bw.ntt, ntd, bw.ntt, tile_dm, tile_t, threshold,
-             nms_dm, nms_t, out + (int64_t)b * kMaxOffers, status + 4 * (int64_t)b);
+  // radii clamped to this beam's plane (they are clamped to the largest on the host)
+  const int64_t nt = nms_t < bw.nout ? nms_t : bw.nout;
+  select_nms(scratch + bw.det_begin, (int64_t)ntd * bw.ntt, ntd, bw.ntt, tile_dm, tile_t,
+             threshold, nms_dm, nt);
 }
 
 }  // namespace
@@ -315,28 +419,25 @@ hipError_t launch_tile_peaks(const float *snr, const uint8_t *best, int ndm, int
   return hipGetLastError();
 }
 
-hipError_t launch_select_nms(const TilePeak *peaks, int ndm, int64_t nout, int tile_dm,
-                             int64_t tile_t, float threshold, int nms_dm, int64_t nms_t,
-                             TilePeak *out, int32_t *status, hipStream_t stream) {
+hipError_t launch_select_nms(uint8_t *scratch, int ndm, int64_t nout, int tile_dm, int64_t tile_t,
+                             float threshold, int nms_dm, int64_t nms_t, hipStream_t stream) {
   const int ntd = (ndm + tile_dm - 1) / tile_dm;
   const int64_t ntt = (nout + tile_t - 1) / tile_t;
-  hipLaunchKernelGGL(select_nms_kernel, dim3(1), dim3(kNmsThreads), 0, stream, peaks,
-                     (int64_t)ntd * ntt, ntd, ntt, tile_dm, tile_t, threshold, nms_dm, nms_t, out,
-                     status);
+  hipLaunchKernelGGL(select_nms_kernel, dim3(1), dim3(kNmsThreads), 0, stream, scratch,
+                     (int64_t)ntd * ntt, ntd, ntt, tile_dm, tile_t, threshold, nms_dm, nms_t);
   return hipGetLastError();
 }
 
 hipError_t launch_detect_batch(const BeamWork *beams, int nbeams, int ndm, int64_t total_tiles,
                                int tile_dm, int64_t tile_t, float threshold, int nms_dm,
-                               int64_t nms_t, TilePeak *peaks, TilePeak *out, int32_t *status,
-                               hipStream_t stream) {
+                               int64_t nms_t, uint8_t *scratch, hipStream_t stream) {
   if (total_tiles > 0x7FFFFFFF) return hipErrorInvalidValue;
   hipLaunchKernelGGL(tile_peaks_batch_kernel, dim3((unsigned)total_tiles), dim3(kTileThreads), 0,
-                     stream, beams, nbeams, ndm, tile_dm, tile_t, peaks);
+                     stream, beams, nbeams, ndm, tile_dm, tile_t, scratch);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(select_nms_batch_kernel, dim3(nbeams), dim3(kNmsThreads), 0, stream, beams,
-                     ndm, tile_dm, tile_t, threshold, nms_dm, nms_t, peaks, out, status);
+                     ndm, tile_dm, tile_t, threshold, nms_dm, nms_t, scratch);
   return hipGetLastError();
 }
 

@@ -24,6 +24,7 @@
 // S/N, the learned detector on the S/N plane (if one is attached), overlap
 // moved to the front of the ring and detection.  A chunk's latency is its completion time
 // minus its arrival time.
+#include <math.h>
 #include <stdio.h>
 #include <string.h>
 
@@ -89,8 +90,7 @@ int64_t plane_bytes(int64_t elems, int64_t rows) {
 int64_t plan_bytes(sps_plan plan, int ndm, int64_t chunk, const sps_detect_params &det) {
   const int64_t ntiles = ((ndm + det.tile_dm - 1) / det.tile_dm) *
                          ((chunk + det.tile_t - 1) / det.tile_t);
-  return sps::plan_device_bytes(plan) +
-         (int64_t)(ntiles + sps::kMaxOffers) * (int64_t)sizeof(sps::TilePeak) + 16;
+  return sps::plan_device_bytes(plan) + sps::detect_layout(ntiles).bytes;
 }
 
 void free_planes(Worker &w) {
@@ -392,14 +392,29 @@ sps_status sps_server_add_stream(sps_server s, const sps_obs_desc *desc, const i
   if (!s || !desc || !widths || !det || !stream_id)
     return sps::set_error(SPS_ERR_INVALID_ARG, "NULL argument");
   *stream_id = -1;
+  // Everything the chunk's boxcar and detection calls would check, so that
+  // an admitted stream never fails on its first chunk for its parameters.
   if (nw < 1 || nw > sps::kMaxWidths)
     return sps::set_error(SPS_ERR_INVALID_ARG, "bad width count");
+  for (int i = 0; i < nw; ++i)
+    if (widths[i] < 1 || (i > 0 && widths[i] <= widths[i - 1]))
+      return sps::set_error(SPS_ERR_INVALID_ARG, "widths must be >= 1 and strictly ascending");
+  if (widths[nw - 1] > sps::kMaxWidth)
+    return sps::set_error(SPS_ERR_RANGE, "largest width above the supported maximum");
   if (chunk_len < widths[nw - 1] || chunk_len > 0x7FFFFFFF)
     return sps::set_error(SPS_ERR_INVALID_ARG, "chunk length must be in [largest width, 2^31-1]");
-  if (det->tile_dm < 1 || det->tile_t < 1)
-    return sps::set_error(SPS_ERR_INVALID_ARG, "bad detection tile");
+  if (!(det->threshold > 0.0f) || !isfinite(det->threshold) || det->tile_dm < 1 ||
+      det->tile_t < 1 || det->nms_dm < 0 || det->nms_t < 0)
+    return sps::set_error(SPS_ERR_INVALID_ARG, "bad detection parameters");
+  if ((uint64_t)det->tile_dm * (uint64_t)det->tile_t >= (1ull << 32))
+    return sps::set_error(SPS_ERR_RANGE, "tile_dm * tile_t must be below 2^32");
   if (!desc->freq_mhz || !desc->dm || desc->nchan < 1 || desc->ndm < 1)
     return sps::set_error(SPS_ERR_INVALID_ARG, "bad observing description");
+  if ((uint64_t)widths[nw - 1] * 255u * (uint64_t)desc->nchan >= (1ull << 31))
+    return sps::set_error(SPS_ERR_OVERFLOW, "largest width x 255 x nchan reaches 2^31");
+  if (((int64_t)desc->ndm + det->tile_dm - 1) / det->tile_dm *
+          ((chunk_len + det->tile_t - 1) / det->tile_t) > 0x7FFFFFFF)
+    return sps::set_error(SPS_ERR_RANGE, "too many detection tiles");
   SetupKey key;
   key.freq.assign(desc->freq_mhz, desc->freq_mhz + desc->nchan);
   key.dm.assign(desc->dm, desc->dm + desc->ndm);
@@ -625,7 +640,9 @@ sps_status sps_server_run(sps_server s, const sps_feed *feeds, double run_s, dou
         StreamState &sm = s->streams[(size_t)job.stream];
         sm.busy = false;
         sm.next_chunk += 1;
-        if (r != SPS_OK && err == SPS_OK) {
+        // a device or memory failure stops the run; any other failure stays
+        // in the chunk's record and the run goes on
+        if ((r == SPS_ERR_DEVICE || r == SPS_ERR_NOMEM) && err == SPS_OK) {
           err = r;
           err_msg = sps_last_error();
         }

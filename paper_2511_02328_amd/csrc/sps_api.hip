@@ -96,11 +96,9 @@ struct sps_plan_s {
   int32_t *d_resid = nullptr;  // residuals transposed, [nsub][ndm]
   uint32_t *d_I = nullptr;
   size_t I_bytes = 0;
-  // detection scratch
-  sps::TilePeak *d_peaks = nullptr;
-  int64_t peaks_cap = 0;
-  sps::TilePeak *d_accepted = nullptr;
-  int32_t *d_status = nullptr;
+  // detection scratch (sps::detect_layout of the last plane's tile count)
+  uint8_t *d_det = nullptr;
+  int64_t det_bytes = 0;
 };
 
 namespace {
@@ -109,9 +107,7 @@ void free_plan(sps_plan p) {
   if (!p) return;
   if (p->d_delays) (void)hipFree(p->d_delays);
   if (p->d_stats) (void)hipFree(p->d_stats);
-  if (p->d_peaks) (void)hipFree(p->d_peaks);
-  if (p->d_accepted) (void)hipFree(p->d_accepted);
-  if (p->d_status) (void)hipFree(p->d_status);
+  if (p->d_det) (void)hipFree(p->d_det);
   for (int32_t *q : p->d_coarse_sub)
     if (q) (void)hipFree(q);
   if (p->d_resid) (void)hipFree(p->d_resid);
@@ -186,6 +182,52 @@ sps_status restage(sps_plan p) {
 
 bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
+// Reads the result of the selection kernel from a plane's detection scratch
+// (d_scratch, laid out by sps::detect_layout(ntiles)) and converts the first
+// min(n, cap) accepted offers into candidate records (Sec. 2: DM, TOA at the
+// top of the band, width, S/N).  Synchronises the stream.  Allocates nothing:
+// the records pass through a fixed host buffer.
+sps_status read_candidates(const uint8_t *d_scratch, int64_t ntiles, const int32_t *widths,
+                           int nw, const double *dm, int ndm, double tsamp_s, sps_candidate *out,
+                           int32_t cap, int32_t *n_found, hipStream_t s) {
+  const sps::DetectLayout L = sps::detect_layout(ntiles);
+  int32_t status[4] = {0, 0, 0, 0};
+  hipError_t e = hipMemcpyAsync(status, d_scratch + L.status, sizeof status, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "reading detection status");
+  const int32_t na = status[1];
+  if (na < 0 || (int64_t)na > ntiles || status[0] < na) {
+    *n_found = 0;
+    return fail(SPS_ERR_DEVICE, "detection status is inconsistent (%d offers, %d accepted, %lld tiles)",
+                status[0], na, (long long)ntiles);
+  }
+  const int32_t ncopy = na < cap ? na : cap;
+  constexpr int kChunk = 256;
+  sps::TilePeak buf[kChunk];
+  const sps::TilePeak *src = reinterpret_cast<const sps::TilePeak *>(d_scratch + L.out);
+  for (int32_t i0 = 0; i0 < ncopy; i0 += kChunk) {
+    const int32_t m = ncopy - i0 < kChunk ? ncopy - i0 : kChunk;
+    e = hipMemcpyAsync(buf, src + i0, sizeof(sps::TilePeak) * (size_t)m, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "reading candidates");
+    for (int32_t k = 0; k < m; ++k) {
+      const sps::TilePeak &q = buf[k];
+      sps_candidate c;
+      c.dm_idx = q.d;
+      c.t_idx = q.t;
+      c.width = (q.w >= 0 && q.w < nw) ? widths[q.w] : 0;
+      c.snr = q.snr;
+      c.reserved = 0.0f;
+      c.dm = (q.d >= 0 && q.d < ndm) ? dm[q.d] : 0.0;
+      c.toa_s = ((double)q.t + 0.5 * (double)c.width) * tsamp_s;
+      out[i0 + k] = c;
+    }
+  }
+  *n_found = na;
+  if (na > cap) return fail(SPS_ERR_TRUNCATED, "%d candidates found, %d returned", na, cap);
+  return SPS_OK;
+}
+
 }  // namespace
 
 namespace sps {
@@ -202,9 +244,7 @@ int64_t plan_device_bytes(sps_plan p) {
   if (p->d_stats) b += (int64_t)p->ndm * 2 * (int64_t)sizeof(int32_t);
   b += staged(p->staged) + staged(p->fused_staged);
   for (const sps::StagedDelays &q : p->sub_staged) b += staged(q);
-  if (p->d_peaks) b += p->peaks_cap * (int64_t)sizeof(sps::TilePeak);
-  if (p->d_accepted) b += (int64_t)sps::kMaxOffers * (int64_t)sizeof(sps::TilePeak);
-  if (p->d_status) b += 4 * (int64_t)sizeof(int32_t);
+  if (p->d_det) b += p->det_bytes;
   if (p->d_coarse_full) b += (int64_t)p->coarse_delays.size() * (int64_t)sizeof(int32_t);
   for (size_t s = 0; s < p->d_coarse_sub.size(); ++s)
     if (p->d_coarse_sub[s])
@@ -451,67 +491,31 @@ sps_status sps_detect(sps_plan plan, const float *snr, const uint8_t *best_w, in
   if (ntiles > 0x7FFFFFFF) return fail(SPS_ERR_RANGE, "too many tiles");
   DeviceScope scope(plan->device);
   if (scope.err != hipSuccess) return hip_fail(scope.err, "selecting the plan's device");
+  // radii past the plane's extent suppress the same offers as the extent
+  const int32_t nms_dm = prm->nms_dm < plan->ndm ? prm->nms_dm : plan->ndm;
+  const int64_t nms_t = prm->nms_t < nout ? prm->nms_t : nout;
+  const sps::DetectLayout L = sps::detect_layout(ntiles);
   hipError_t e = hipSuccess;
-  if (!plan->d_accepted) {
-    e = hipMalloc(&plan->d_accepted, sizeof(sps::TilePeak) * sps::kMaxOffers);
-    if (e == hipSuccess) e = hipMalloc(&plan->d_status, 4 * sizeof(int32_t));
+  if (plan->det_bytes < L.bytes) {
+    if (plan->d_det) (void)hipFree(plan->d_det);
+    plan->d_det = nullptr;
+    plan->det_bytes = 0;
+    e = hipMalloc(&plan->d_det, (size_t)L.bytes);
     if (e != hipSuccess) {
       (void)hipGetLastError();
       return fail(SPS_ERR_NOMEM, "device allocation of detection scratch failed");
     }
-  }
-  if (plan->peaks_cap < ntiles) {
-    if (plan->d_peaks) (void)hipFree(plan->d_peaks);
-    plan->d_peaks = nullptr;
-    plan->peaks_cap = 0;
-    e = hipMalloc(&plan->d_peaks, sizeof(sps::TilePeak) * (size_t)ntiles);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(SPS_ERR_NOMEM, "device allocation of tile peaks failed");
-    }
-    plan->peaks_cap = ntiles;
+    plan->det_bytes = L.bytes;
   }
   hipStream_t s = (hipStream_t)stream;
   e = sps::launch_tile_peaks(snr, best_w, plan->ndm, nout, prm->tile_dm, prm->tile_t,
-                             plan->d_peaks, s);
+                             reinterpret_cast<sps::TilePeak *>(plan->d_det + L.peaks), s);
   if (e != hipSuccess) return hip_fail(e, "tile peak launch");
-  e = sps::launch_select_nms(plan->d_peaks, plan->ndm, nout, prm->tile_dm, prm->tile_t,
-                             prm->threshold, prm->nms_dm, prm->nms_t, plan->d_accepted,
-                             plan->d_status, s);
+  e = sps::launch_select_nms(plan->d_det, plan->ndm, nout, prm->tile_dm, prm->tile_t,
+                             prm->threshold, nms_dm, nms_t, s);
   if (e != hipSuccess) return hip_fail(e, "selection launch");
-  int32_t status[4] = {0, 0, 0, 0};
-  e = hipMemcpyAsync(status, plan->d_status, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess) return hip_fail(e, "reading detection status");
-  if (status[2]) {
-    *n_found = 0;
-    return fail(SPS_ERR_RANGE, "%d tiles reach the threshold; at most %d are supported", status[0],
-                sps::kMaxOffers);
-  }
-  const int32_t na = status[1];
-  const int32_t ncopy = na < cap ? na : cap;
-  std::vector<sps::TilePeak> acc((size_t)ncopy);
-  if (ncopy > 0) {
-    e = hipMemcpyAsync(acc.data(), plan->d_accepted, sizeof(sps::TilePeak) * (size_t)ncopy,
-                       hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_fail(e, "reading candidates");
-  }
-  for (int32_t i = 0; i < ncopy; ++i) {
-    const sps::TilePeak &q = acc[(size_t)i];
-    sps_candidate c;
-    c.dm_idx = q.d;
-    c.t_idx = q.t;
-    c.width = (q.w >= 0 && q.w < nw) ? widths[q.w] : 0;
-    c.snr = q.snr;
-    c.reserved = 0.0f;
-    c.dm = (q.d >= 0 && q.d < plan->ndm) ? plan->dm[(size_t)q.d] : 0.0;
-    c.toa_s = ((double)q.t + 0.5 * (double)c.width) * plan->tsamp_s;
-    out[i] = c;
-  }
-  *n_found = na;
-  if (na > cap) return fail(SPS_ERR_TRUNCATED, "%d candidates found, %d returned", na, cap);
-  return SPS_OK;
+  return read_candidates(plan->d_det, ntiles, widths, nw, plan->dm.data(), plan->ndm,
+                         plan->tsamp_s, out, cap, n_found, s);
 }
 
 sps_status sps_subband_plan_create(const sps_subband_desc *desc, sps_plan *out) {
@@ -787,8 +791,8 @@ struct sps_batch_s {
   int lds_pitch = 0;
   sps::StagedDelays staged;  // the plan's table for cfg, owned by the batch
   int grid_dd = 0;
-  sps::TilePeak *d_peaks = nullptr, *d_out = nullptr;
-  int32_t *d_status = nullptr;
+  uint8_t *d_det = nullptr;  // detection scratch of every beam (BeamWork::det_begin)
+  int64_t det_bytes = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipStream_t graph_stream = nullptr;
@@ -801,9 +805,7 @@ void free_batch(sps_batch b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->d_beams) (void)hipFree(b->d_beams);
-  if (b->d_peaks) (void)hipFree(b->d_peaks);
-  if (b->d_out) (void)hipFree(b->d_out);
-  if (b->d_status) (void)hipFree(b->d_status);
+  if (b->d_det) (void)hipFree(b->d_det);
   sps::free_staged(b->staged);
   delete b;
 }
@@ -838,7 +840,7 @@ sps_status batch_enqueue(sps_batch b, hipStream_t s) {
   if (e != hipSuccess) return hip_fail(e, "batched boxcar launch");
   e = sps::launch_detect_batch(b->d_beams, b->nbeams, p->ndm, b->tp_tiles, b->prm.tile_dm,
                                b->prm.tile_t, b->prm.threshold, b->prm.nms_dm, b->prm.nms_t,
-                               b->d_peaks, b->d_out, b->d_status, s);
+                               b->d_det, s);
   if (e != hipSuccess) return hip_fail(e, "batched detection launch");
   return SPS_OK;
 }
@@ -874,6 +876,10 @@ sps_status sps_batch_create(sps_plan plan, int32_t nbeams, const sps_beam *beams
   b->plan = plan;
   b->nbeams = nbeams;
   b->prm = *prm;
+  // radii past the plane's extent suppress the same offers as the extent
+  // (the kernel clamps nms_t to each beam's length)
+  if (b->prm.nms_dm > plan->ndm) b->prm.nms_dm = plan->ndm;
+  if (b->prm.nms_t > 0x7FFFFFFF) b->prm.nms_t = 0x7FFFFFFF;
   b->cfg = plan->cfg;
   b->lds_pitch = plan->lds_pitch;
   b->widths.n = nw;
@@ -915,13 +921,11 @@ sps_status sps_batch_create(sps_plan plan, int32_t nbeams, const sps_beam *beams
     w.ntt = (q.nout + prm->tile_t - 1) / prm->tile_t;
     w.vec_store = (q.nout % 4 == 0) && aligned16(q.Y);
     w.pad = 0;
+    w.det_begin = b->det_bytes;
     b->bx_blocks += w.nseg * plan->ndm;
     b->tp_tiles += w.ntt * ntd;
+    b->det_bytes += sps::detect_layout(w.ntt * ntd).bytes;
     b->nout[(size_t)i] = q.nout;
-    if (w.ntt * ntd > sps::kMaxOffers) {
-      free_batch(b);
-      return fail(SPS_ERR_RANGE, "beam %d has more than %d detection tiles", i, sps::kMaxOffers);
-    }
   }
   if (b->bx_blocks > 0x7FFFFFFF || b->tp_tiles > 0x7FFFFFFF || !layout_dedisp(b, b->cfg)) {
     free_batch(b);
@@ -929,10 +933,9 @@ sps_status sps_batch_create(sps_plan plan, int32_t nbeams, const sps_beam *beams
   }
   DeviceScope scope(plan->device);
   hipError_t e = hipMalloc(&b->d_beams, sizeof(sps::BeamWork) * (size_t)nbeams);
-  if (e == hipSuccess) e = hipMalloc(&b->d_peaks, sizeof(sps::TilePeak) * (size_t)b->tp_tiles);
-  if (e == hipSuccess)
-    e = hipMalloc(&b->d_out, sizeof(sps::TilePeak) * (size_t)sps::kMaxOffers * nbeams);
-  if (e == hipSuccess) e = hipMalloc(&b->d_status, sizeof(int32_t) * 4 * (size_t)nbeams);
+  if (e == hipSuccess) e = hipMalloc(&b->d_det, (size_t)b->det_bytes);
+  // zero statuses: candidates read before the first run are none
+  if (e == hipSuccess) e = hipMemset(b->d_det, 0, (size_t)b->det_bytes);
   if (e == hipSuccess)
     e = hipMemcpy(b->d_beams, b->beams.data(), sizeof(sps::BeamWork) * (size_t)nbeams,
                   hipMemcpyHostToDevice);
@@ -1082,43 +1085,12 @@ sps_status sps_batch_candidates(sps_batch batch, int32_t beam, sps_candidate *ou
   if (cap < 0 || (cap > 0 && !out)) return fail(SPS_ERR_INVALID_ARG, "bad output array");
   DeviceScope scope(batch->plan->device);
   if (scope.err != hipSuccess) return hip_fail(scope.err, "selecting the plan's device");
-  hipStream_t s = (hipStream_t)stream;
-  int32_t status[4] = {0, 0, 0, 0};
-  hipError_t e = hipMemcpyAsync(status, batch->d_status + 4 * (size_t)beam, 3 * sizeof(int32_t),
-                                hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess) return hip_fail(e, "reading detection status");
-  if (status[2]) {
-    *n_found = 0;
-    return fail(SPS_ERR_RANGE, "%d tiles reach the threshold; at most %d are supported", status[0],
-                sps::kMaxOffers);
-  }
-  const int32_t na = status[1];
-  const int32_t ncopy = na < cap ? na : cap;
-  std::vector<sps::TilePeak> acc((size_t)ncopy);
-  if (ncopy > 0) {
-    e = hipMemcpyAsync(acc.data(), batch->d_out + (size_t)beam * sps::kMaxOffers,
-                       sizeof(sps::TilePeak) * (size_t)ncopy, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_fail(e, "reading candidates");
-  }
-  const sps_plan p = batch->plan;
-  const int nw = (int)batch->widths_host.size();
-  for (int32_t i = 0; i < ncopy; ++i) {
-    const sps::TilePeak &q = acc[(size_t)i];
-    sps_candidate c;
-    c.dm_idx = q.d;
-    c.t_idx = q.t;
-    c.width = (q.w >= 0 && q.w < nw) ? batch->widths_host[(size_t)q.w] : 0;
-    c.snr = q.snr;
-    c.reserved = 0.0f;
-    c.dm = (q.d >= 0 && q.d < p->ndm) ? p->dm[(size_t)q.d] : 0.0;
-    c.toa_s = ((double)q.t + 0.5 * (double)c.width) * p->tsamp_s;
-    out[i] = c;
-  }
-  *n_found = na;
-  if (na > cap) return fail(SPS_ERR_TRUNCATED, "%d candidates found, %d returned", na, cap);
-  return SPS_OK;
+  const sps::BeamWork &w = batch->beams[(size_t)beam];
+  const int64_t ntd = (batch->plan->ndm + batch->prm.tile_dm - 1) / batch->prm.tile_dm;
+  return read_candidates(batch->d_det + w.det_begin, ntd * w.ntt, batch->widths_host.data(),
+                         (int)batch->widths_host.size(), batch->plan->dm.data(),
+                         batch->plan->ndm, batch->plan->tsamp_s, out, cap, n_found,
+                         (hipStream_t)stream);
 }
 
 sps_status sps_plan_autotune(sps_plan plan, int64_t nout_probe, int32_t iters, void *stream,

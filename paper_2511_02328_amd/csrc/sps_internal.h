@@ -73,6 +73,7 @@ struct BeamWork {
   int64_t tp_begin;     // detection tiles
   int64_t nseg;         // boxcar segments per row
   int64_t ntt;          // detection tiles along time
+  int64_t det_begin;    // byte offset of the beam's detection scratch
   int32_t vec_store;
   int32_t pad;
 };
@@ -161,18 +162,58 @@ struct TilePeak {
   int32_t w;
 };
 
+// Offers that the selection kernel keeps in LDS; larger offer sets (and tile
+// grids larger than this) use the global arrays of the detection scratch.
 constexpr int kMaxOffers = 8192;
+
+// Detection scratch of one plane of ntiles tiles, as byte offsets from one
+// base (each a multiple of 256):
+//   peaks  [ntiles] TilePeak  the tile maxima
+//   out    [ntiles] TilePeak  accepted offers, in candidate order
+//   status [4] int32          offers, accepted, 0, 0
+// and, when ntiles > kMaxOffers (offers that may not fit in LDS):
+//   offer  [npow] TilePeak    offers, sorted in place (npow = ntiles rounded
+//                             up to a power of two)
+//   aux    [ntiles] int32     tile -> offer rank, or the accepted list
+//   state  [npow] uint8       per offer: undecided, accepted, rejected
+struct DetectLayout {
+  int64_t peaks, out, status, offer, aux, state, bytes, npow;
+};
+
+__host__ __device__ inline DetectLayout detect_layout(int64_t ntiles) {
+  auto up = [](int64_t b) { return (b + 255) & ~(int64_t)255; };
+  DetectLayout L{};
+  int64_t npow = 1;
+  while (npow < ntiles) npow <<= 1;
+  L.npow = npow;
+  L.peaks = 0;
+  L.out = up(L.peaks + 16 * ntiles);
+  L.status = up(L.out + 16 * ntiles);
+  int64_t end = up(L.status + 16);
+  if (ntiles > kMaxOffers) {
+    L.offer = end;
+    L.aux = up(L.offer + 16 * npow);
+    L.state = up(L.aux + 4 * ntiles);
+    end = up(L.state + npow);
+  } else {
+    L.offer = L.aux = L.state = -1;
+  }
+  L.bytes = end;
+  return L;
+}
 
 hipError_t launch_tile_peaks(const float *snr, const uint8_t *best, int ndm, int64_t nout,
                              int tile_dm, int64_t tile_t, TilePeak *peaks,
                              hipStream_t stream);
 
-// Selects tile peaks >= threshold, orders them and applies greedy
-// suppression; writes accepted peaks (in order) to out and, to status[0..2]:
-// number of offers, number accepted, overflow flag.
-hipError_t launch_select_nms(const TilePeak *peaks, int ndm, int64_t nout, int tile_dm,
-                             int64_t tile_t, float threshold, int nms_dm, int64_t nms_t,
-                             TilePeak *out, int32_t *status, hipStream_t stream);
+// Selects the tile peaks of scratch (laid out by detect_layout for the
+// plane's tile count) at or above the threshold, orders them (S/N
+// descending, then t, then d) and applies greedy suppression; writes the
+// accepted offers in that order to the scratch's out array and to its status
+// the number of offers and the number accepted.  Any number of offers.
+// nms_dm and nms_t must already be clamped to ndm and nout.
+hipError_t launch_select_nms(uint8_t *scratch, int ndm, int64_t nout, int tile_dm, int64_t tile_t,
+                             float threshold, int nms_dm, int64_t nms_t, hipStream_t stream);
 
 // Rt: residual table transposed, [nsub][ndm].
 hipError_t launch_subband_stage2(const uint32_t *I, int64_t len1, int ncoarse, int nsub,
@@ -197,10 +238,11 @@ hipError_t launch_row_stats_batch(const BeamWork *beams, int nbeams, int ndm, ui
 hipError_t launch_boxcar_batch(const BeamWork *beams, int nbeams, int64_t total_blocks,
                                const WidthList &widths, hipStream_t stream);
 int64_t boxcar_segments(int64_t nout);
+// Batched detection: beam b's scratch (detect_layout of its tile count)
+// starts at scratch + beams[b].det_begin.
 hipError_t launch_detect_batch(const BeamWork *beams, int nbeams, int ndm, int64_t total_tiles,
                                int tile_dm, int64_t tile_t, float threshold, int nms_dm,
-                               int64_t nms_t, TilePeak *peaks, TilePeak *out, int32_t *status,
-                               hipStream_t stream);
+                               int64_t nms_t, uint8_t *scratch, hipStream_t stream);
 
 // Forward pass of n tiles (device) through net; adds to *count (device int32)
 // the number of cells whose objectness probability is >= threshold, decided

@@ -19,8 +19,8 @@ from typing import Optional
 
 import numpy as np
 
-from . import synth
-from .workloads import PulseModel, RfiModel, Workload
+from sps_inputs import synth
+from sps_inputs.workloads import PulseModel, RfiModel, Workload
 
 TILE_WORKLOAD = Workload(
     name="detector_tiles_256ch_4096t_512dm", nchan=256, f_lo_mhz=1000.0, f_hi_mhz=1500.0,

@@ -73,3 +73,18 @@ def test_no_cpu_fallback_in_the_product_package():
                 text = open(os.path.join(root, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "sps_oracle" not in text, f
+
+
+def test_oracle_and_inputs_never_import_the_product_package():
+    # the oracle shares no code with the HIP path, and the shared seeded-input
+    # package imports neither side
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    for sub in ("oracle", "sps_inputs"):
+        for dirpath, _, files in os.walk(os.path.join(root, sub)):
+            for f in files:
+                if f.endswith((".py", ".c", ".h")):
+                    text = open(os.path.join(dirpath, f)).read()
+                    assert "paper_2511_02328_amd" not in text.replace(
+                        "(``paper_2511_02328_amd``)", ""), os.path.join(sub, f)
+                    if sub == "sps_inputs":
+                        assert "import oracle" not in text and "from oracle" not in text, f

@@ -14,8 +14,9 @@ import pytest
 torch = pytest.importorskip("torch")
 
 import oracle  # noqa: E402
-from paper_2511_02328_amd import synth  # noqa: E402
-from paper_2511_02328_amd.workloads import BATCHED, FULL_SCALE, STREAMING  # noqa: E402
+from _checks import check_candidates_exact, check_snr  # noqa: E402
+from sps_inputs import synth  # noqa: E402
+from sps_inputs.workloads import BATCHED, FULL_SCALE, STREAMING  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -171,8 +172,19 @@ def test_batched_19_beams_full_size(sps):
             sums_o = oracle.row_checksums(Xh, D, b["nout"], b["nsamp_in"])
             sums_g = b["Y"].sum(dim=1, dtype=torch.int64).cpu().numpy().astype(np.uint64)
             assert np.array_equal(sums_g, sums_o), f"beam {i} row sums"
-            st = b["stats"][torch.from_numpy(rows).cuda()].cpu().numpy().astype(np.int64)
-            assert np.array_equal(st, oracle.stats(Yo)), f"beam {i} stats"
+            idx = torch.from_numpy(rows).cuda()
+            st = b["stats"][idx].cpu().numpy().astype(np.int64)
+            sto = oracle.stats(Yo)
+            assert np.array_equal(st, sto), f"beam {i} stats"
+            check_snr(Yo, sto, wl0.widths, b["snr"][idx].cpu().numpy(),
+                      b["best_w"][idx].cpu().numpy(), f"beam {i}")
+            # candidates: the oracle's rule on the beam's whole GPU plane
+            snr_full, best_full = b["snr"].cpu().numpy(), b["best_w"].cpu().numpy()
+            co = oracle.detect(snr_full, best_full, DET["threshold"], DET["tile_dm"],
+                               DET["tile_t"], DET["nms_dm"], DET["nms_t"], cap=1 << 16)
+            del snr_full, best_full
+            cb, nb = sps.sps_batch_candidates(batch, i, cap=1 << 16)
+            check_candidates_exact(cb, nb, co, list(wl0.widths), f"beam {i}")
     plan.close()
 
 

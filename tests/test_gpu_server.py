@@ -11,8 +11,8 @@ import pytest
 torch = pytest.importorskip("torch")
 
 import oracle  # noqa: E402
-from paper_2511_02328_amd import synth  # noqa: E402
-from paper_2511_02328_amd.workloads import PulseModel, Workload  # noqa: E402
+from sps_inputs import synth  # noqa: E402
+from sps_inputs.workloads import PulseModel, Workload  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -178,6 +178,26 @@ def _net(sps, max_batch, seed):
     return net, p
 
 
+def _oracle_cell_count(ncnn, snr, p, thr):
+    """The server's count of flagged cells against the detector oracle on the
+    same S/N plane (pooled by the oracle, network in the oracle's rounding
+    points): every cell whose oracle logit clears the threshold by more than
+    the FP32-accumulation drift bound of the head (1e-2 of its largest value)
+    must be counted, and none below it by that margin."""
+    cnn = oracle.cnn()
+    params = cnn.init_params(7)
+    params["bh"][0] = 0.0
+    assert np.array_equal(np.concatenate([params[k].ravel() for k in cnn.param_names()]), p)
+    tiles = np.stack([cnn.pool_tiles(snr[512 * i:512 * (i + 1), 4096 * j:4096 * (j + 1)], 0.125)
+                      for i in range(snr.shape[0] // 512) for j in range(snr.shape[1] // 4096)])
+    head, _ = cnn.forward(params, tiles)
+    logit = head[:, 0]
+    lt = np.log(thr / (1.0 - thr))
+    delta = 1e-2 * np.abs(head).max()
+    sure, maybe = int((logit >= lt + delta).sum()), int((logit >= lt - delta).sum())
+    assert sure <= ncnn <= maybe, (sure, ncnn, maybe)
+
+
 def test_detector_in_server(sps):
     # 1024 trials x 8192 samples per chunk = 2 x 2 tiles; the server's network
     # takes 3 tiles a batch, so each chunk needs two batches
@@ -207,6 +227,8 @@ def test_detector_in_server(sps):
             _, want = sps.sps_cnn_detect(ref_net, tiles, 4, thr, cap=0, allow_truncated=True)
             torch.cuda.synchronize()
             assert ncnn == want, k
+            if k == 0:
+                _oracle_cell_count(ncnn, snr.cpu().numpy(), p, thr)
             counts.append(ncnn)
             info = sps.sps_server_stream_info(server, sid)
             ref = _oracle_chunk(wl, Xs, info["overlap"], k, L)

@@ -8,8 +8,8 @@ import pytest
 torch = pytest.importorskip("torch")
 
 import oracle  # noqa: E402
-from paper_2511_02328_amd import synth  # noqa: E402
-from paper_2511_02328_amd.workloads import SINGLE_BEAM  # noqa: E402
+from sps_inputs import synth  # noqa: E402
+from sps_inputs.workloads import SINGLE_BEAM  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 

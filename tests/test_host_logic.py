@@ -13,7 +13,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 
-from paper_2511_02328_amd import workloads  # noqa: E402
+from sps_inputs import workloads  # noqa: E402
 
 
 def test_bench_refuses_more_than_one_gpu():

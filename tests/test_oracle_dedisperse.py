@@ -10,8 +10,8 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_2511_02328_amd import synth
-from paper_2511_02328_amd.workloads import SINGLE_BEAM
+from sps_inputs import synth
+from sps_inputs.workloads import SINGLE_BEAM
 
 
 def _brute_python(X, D, nout, nsamp_in):

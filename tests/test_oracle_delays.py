@@ -14,7 +14,7 @@ import pytest
 import scipy.constants as sc
 
 import oracle
-from paper_2511_02328_amd.workloads import FULL_SCALE, SINGLE_BEAM
+from sps_inputs.workloads import FULL_SCALE, SINGLE_BEAM
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")
 
