@@ -158,6 +158,22 @@ sps_status sps_detect(sps_plan plan, const float *snr, const uint8_t *best_w, in
                       const int32_t *widths, int32_t nw, const sps_detect_params *params,
                       sps_candidate *out, int32_t cap, int32_t *n_found, void *stream);
 
+/* sps_detect for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments, checks, kernels and results, but the detection
+ * scratch is a fixed 4 MiB array in the library's device image, one copy
+ * per device, held until the process ends, instead of plan memory grown
+ * with hipMalloc.  It calls no hipMalloc, hipFree or other allocating
+ * routine.  Holds at least 65,536 tiles (the scratch of ntiles tiles takes
+ * about 56 bytes per tile); a plane that needs more returns SPS_ERR_RANGE
+ * before anything is enqueued.  Every call on one device uses that device's
+ * one copy: calls that overlap on a device (other streams, other threads)
+ * race and must be serialised by the caller.  Synchronises the stream. */
+sps_status sps_detect_noalloc(sps_plan plan, const float *snr, const uint8_t *best_w,
+                              int64_t nout, const int32_t *widths, int32_t nw,
+                              const sps_detect_params *params, sps_candidate *out, int32_t cap,
+                              int32_t *n_found, void *stream);
+
 /* Tiling of the dedispersion kernel, for tuning (sps_plan_create picks a
  * default).  m: output dwords per lane (odd), dpw: trials per wave, nw: waves
  * per workgroup, cs: channels per LDS slab, waves_per_eu: register budget

@@ -11,6 +11,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -226,6 +227,103 @@ sps_status read_candidates(const uint8_t *d_scratch, int64_t ntiles, const int32
   *n_found = na;
   if (na > cap) return fail(SPS_ERR_TRUNCATED, "%d candidates found, %d returned", na, cap);
   return SPS_OK;
+}
+
+// Fixed detection scratch of sps_detect_noalloc: one copy on every device
+// the library runs on, held until the process ends.  Host code never uses
+// the array's name as an address: on each device, with that device current,
+// the first call looks up the device address of that device's copy once and
+// keeps it in g_fixed_scratch.  Calls that overlap on one device share the
+// copy and race.  Every byte a call reads is first written by its own
+// kernels (tile peaks, status, and the tile map and states the selection
+// kernel clears), so nothing carries over between calls.
+constexpr int64_t kFixedScratchBytes = 4ll << 20;
+constexpr int64_t kFixedScratchTiles = 65536;
+static_assert(sps::detect_layout(kFixedScratchTiles).bytes <= kFixedScratchBytes,
+              "the fixed detection scratch must hold the stated tile count");
+static __device__ __align__(256) uint8_t scratch[kFixedScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_fixed_mu;
+uint8_t *g_fixed_scratch[kMaxDevices] = {};
+
+// Device address of the current device's copy of the fixed scratch.
+sps_status fixed_scratch(int device, uint8_t **ptr) {
+  if (device < 0 || device >= kMaxDevices)
+    return fail(SPS_ERR_DEVICE, "device %d is beyond the %d the fixed scratch serves", device,
+                kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_fixed_mu);
+  if (!g_fixed_scratch[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e, "looking up the fixed detection scratch");
+    g_fixed_scratch[device] = static_cast<uint8_t *>(p);
+  }
+  *ptr = g_fixed_scratch[device];
+  return SPS_OK;
+}
+
+// sps_detect and sps_detect_noalloc: the same checks and kernels; the
+// scratch is the plan's (grown with hipMalloc on demand) or the fixed one.
+sps_status run_detect(sps_plan plan, const float *snr, const uint8_t *best_w, int64_t nout,
+                      const int32_t *widths, int32_t nw, const sps_detect_params *prm,
+                      sps_candidate *out, int32_t cap, int32_t *n_found, void *stream,
+                      bool fixed) {
+  g_error.clear();
+  if (!plan || !snr || !best_w || !widths || !prm || !n_found)
+    return fail(SPS_ERR_INVALID_ARG, "NULL plan, buffer or parameter");
+  if (cap < 0 || (cap > 0 && !out)) return fail(SPS_ERR_INVALID_ARG, "bad output array");
+  if (nout < 1 || nout > 0x7FFFFFFF) return fail(SPS_ERR_RANGE, "nout must be in [1, 2^31-1]");
+  if (nw < 1 || nw > sps::kMaxWidths) return fail(SPS_ERR_INVALID_ARG, "bad width count");
+  if (!(prm->threshold > 0.0f) || !isfinite(prm->threshold))
+    return fail(SPS_ERR_INVALID_ARG, "threshold must be positive");
+  if (prm->tile_dm < 1 || prm->tile_t < 1 || prm->nms_dm < 0 || prm->nms_t < 0)
+    return fail(SPS_ERR_INVALID_ARG, "bad tile or suppression sizes");
+  if ((uint64_t)prm->tile_dm * (uint64_t)prm->tile_t >= (1ull << 32))
+    return fail(SPS_ERR_RANGE, "tile_dm * tile_t must be below 2^32");
+  const int64_t ntd = (plan->ndm + prm->tile_dm - 1) / prm->tile_dm;
+  const int64_t ntt = (nout + prm->tile_t - 1) / prm->tile_t;
+  const int64_t ntiles = ntd * ntt;
+  if (ntiles > 0x7FFFFFFF) return fail(SPS_ERR_RANGE, "too many tiles");
+  const sps::DetectLayout L = sps::detect_layout(ntiles);
+  if (fixed && L.bytes > kFixedScratchBytes)
+    return fail(SPS_ERR_RANGE,
+                "%lld tiles need %lld bytes of detection scratch; the fixed scratch holds %lld "
+                "(at least %lld tiles)",
+                (long long)ntiles, (long long)L.bytes, (long long)kFixedScratchBytes,
+                (long long)kFixedScratchTiles);
+  DeviceScope scope(plan->device);
+  if (scope.err != hipSuccess) return hip_fail(scope.err, "selecting the plan's device");
+  // radii past the plane's extent suppress the same offers as the extent
+  const int32_t nms_dm = prm->nms_dm < plan->ndm ? prm->nms_dm : plan->ndm;
+  const int64_t nms_t = prm->nms_t < nout ? prm->nms_t : nout;
+  uint8_t *det = nullptr;
+  if (fixed) {
+    const sps_status st = fixed_scratch(plan->device, &det);
+    if (st != SPS_OK) return st;
+  } else {
+    if (plan->det_bytes < L.bytes) {
+      if (plan->d_det) (void)hipFree(plan->d_det);
+      plan->d_det = nullptr;
+      plan->det_bytes = 0;
+      const hipError_t e = hipMalloc(&plan->d_det, (size_t)L.bytes);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SPS_ERR_NOMEM, "device allocation of detection scratch failed");
+      }
+      plan->det_bytes = L.bytes;
+    }
+    det = plan->d_det;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = sps::launch_tile_peaks(snr, best_w, plan->ndm, nout, prm->tile_dm, prm->tile_t,
+                                        reinterpret_cast<sps::TilePeak *>(det + L.peaks), s);
+  if (e != hipSuccess) return hip_fail(e, "tile peak launch");
+  e = sps::launch_select_nms(det, plan->ndm, nout, prm->tile_dm, prm->tile_t, prm->threshold,
+                             nms_dm, nms_t, s);
+  if (e != hipSuccess) return hip_fail(e, "selection launch");
+  return read_candidates(det, ntiles, widths, nw, plan->dm.data(), plan->ndm, plan->tsamp_s, out,
+                         cap, n_found, s);
 }
 
 }  // namespace
@@ -473,49 +571,14 @@ sps_status sps_boxcar_snr(sps_plan plan, const uint32_t *Y, int64_t nout, const 
 sps_status sps_detect(sps_plan plan, const float *snr, const uint8_t *best_w, int64_t nout,
                       const int32_t *widths, int32_t nw, const sps_detect_params *prm,
                       sps_candidate *out, int32_t cap, int32_t *n_found, void *stream) {
-  g_error.clear();
-  if (!plan || !snr || !best_w || !widths || !prm || !n_found)
-    return fail(SPS_ERR_INVALID_ARG, "NULL plan, buffer or parameter");
-  if (cap < 0 || (cap > 0 && !out)) return fail(SPS_ERR_INVALID_ARG, "bad output array");
-  if (nout < 1 || nout > 0x7FFFFFFF) return fail(SPS_ERR_RANGE, "nout must be in [1, 2^31-1]");
-  if (nw < 1 || nw > sps::kMaxWidths) return fail(SPS_ERR_INVALID_ARG, "bad width count");
-  if (!(prm->threshold > 0.0f) || !isfinite(prm->threshold))
-    return fail(SPS_ERR_INVALID_ARG, "threshold must be positive");
-  if (prm->tile_dm < 1 || prm->tile_t < 1 || prm->nms_dm < 0 || prm->nms_t < 0)
-    return fail(SPS_ERR_INVALID_ARG, "bad tile or suppression sizes");
-  if ((uint64_t)prm->tile_dm * (uint64_t)prm->tile_t >= (1ull << 32))
-    return fail(SPS_ERR_RANGE, "tile_dm * tile_t must be below 2^32");
-  const int64_t ntd = (plan->ndm + prm->tile_dm - 1) / prm->tile_dm;
-  const int64_t ntt = (nout + prm->tile_t - 1) / prm->tile_t;
-  const int64_t ntiles = ntd * ntt;
-  if (ntiles > 0x7FFFFFFF) return fail(SPS_ERR_RANGE, "too many tiles");
-  DeviceScope scope(plan->device);
-  if (scope.err != hipSuccess) return hip_fail(scope.err, "selecting the plan's device");
-  // radii past the plane's extent suppress the same offers as the extent
-  const int32_t nms_dm = prm->nms_dm < plan->ndm ? prm->nms_dm : plan->ndm;
-  const int64_t nms_t = prm->nms_t < nout ? prm->nms_t : nout;
-  const sps::DetectLayout L = sps::detect_layout(ntiles);
-  hipError_t e = hipSuccess;
-  if (plan->det_bytes < L.bytes) {
-    if (plan->d_det) (void)hipFree(plan->d_det);
-    plan->d_det = nullptr;
-    plan->det_bytes = 0;
-    e = hipMalloc(&plan->d_det, (size_t)L.bytes);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(SPS_ERR_NOMEM, "device allocation of detection scratch failed");
-    }
-    plan->det_bytes = L.bytes;
-  }
-  hipStream_t s = (hipStream_t)stream;
-  e = sps::launch_tile_peaks(snr, best_w, plan->ndm, nout, prm->tile_dm, prm->tile_t,
-                             reinterpret_cast<sps::TilePeak *>(plan->d_det + L.peaks), s);
-  if (e != hipSuccess) return hip_fail(e, "tile peak launch");
-  e = sps::launch_select_nms(plan->d_det, plan->ndm, nout, prm->tile_dm, prm->tile_t,
-                             prm->threshold, nms_dm, nms_t, s);
-  if (e != hipSuccess) return hip_fail(e, "selection launch");
-  return read_candidates(plan->d_det, ntiles, widths, nw, plan->dm.data(), plan->ndm,
-                         plan->tsamp_s, out, cap, n_found, s);
+  return run_detect(plan, snr, best_w, nout, widths, nw, prm, out, cap, n_found, stream, false);
+}
+
+sps_status sps_detect_noalloc(sps_plan plan, const float *snr, const uint8_t *best_w,
+                              int64_t nout, const int32_t *widths, int32_t nw,
+                              const sps_detect_params *prm, sps_candidate *out, int32_t cap,
+                              int32_t *n_found, void *stream) {
+  return run_detect(plan, snr, best_w, nout, widths, nw, prm, out, cap, n_found, stream, true);
 }
 
 sps_status sps_subband_plan_create(const sps_subband_desc *desc, sps_plan *out) {

@@ -180,7 +180,7 @@ struct DetectLayout {
   int64_t peaks, out, status, offer, aux, state, bytes, npow;
 };
 
-__host__ __device__ inline DetectLayout detect_layout(int64_t ntiles) {
+__host__ __device__ constexpr inline DetectLayout detect_layout(int64_t ntiles) {
   auto up = [](int64_t b) { return (b + 255) & ~(int64_t)255; };
   DetectLayout L{};
   int64_t npow = 1;

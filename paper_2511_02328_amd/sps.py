@@ -100,6 +100,10 @@ def library() -> ctypes.CDLL:
         lib.sps_boxcar_snr.argtypes = [P, P, i64, P, i32, P, P, P, P]
         lib.sps_detect.argtypes = [P, P, P, i64, P, i32, ctypes.POINTER(sps_detect_params),
                                    ctypes.POINTER(sps_candidate), i32, ctypes.POINTER(i32), P]
+        lib.sps_detect_noalloc.argtypes = [P, P, P, i64, P, i32,
+                                           ctypes.POINTER(sps_detect_params),
+                                           ctypes.POINTER(sps_candidate), i32,
+                                           ctypes.POINTER(i32), P]
         lib.sps_plan_set_tiling.argtypes = [P, i32, i32, i32, i32, i32]
         lib.sps_plan_get_tiling.argtypes = [P] + [ctypes.POINTER(i32)] * 6
         lib.sps_subband_plan_create.argtypes = [ctypes.POINTER(sps_subband_desc), ctypes.POINTER(P)]
@@ -168,7 +172,8 @@ def library() -> ctypes.CDLL:
                   "sps_server_run", "sps_server_set_detector"):
             getattr(lib, f).restype = ctypes.c_int
         for f in ("sps_plan_create", "sps_plan_destroy", "sps_plan_delays", "sps_dedisperse",
-                  "sps_boxcar_snr", "sps_detect", "sps_plan_set_tiling", "sps_plan_get_tiling",
+                  "sps_boxcar_snr", "sps_detect", "sps_detect_noalloc", "sps_plan_set_tiling",
+                  "sps_plan_get_tiling",
                   "sps_subband_plan_create", "sps_subband_tables", "sps_dedisperse_subband",
                   "sps_zero_dm", "sps_downsample_sqrt", "sps_batch_create", "sps_batch_destroy",
                   "sps_batch_enqueue", "sps_batch_launch_graph", "sps_batch_candidates",
@@ -308,16 +313,31 @@ def sps_detect(plan: Plan, snr: torch.Tensor, best_w: torch.Tensor, nout: int,
                widths: Sequence[int], threshold: float, tile_dm: int, tile_t: int, nms_dm: int,
                nms_t: int, cap: int = 4096, stream=None, allow_truncated: bool = False):
     """Returns (structured array of candidates, number found)."""
+    return _detect("sps_detect", plan, snr, best_w, nout, widths, threshold, tile_dm, tile_t,
+                   nms_dm, nms_t, cap, stream, allow_truncated)
+
+
+def sps_detect_noalloc(plan: Plan, snr: torch.Tensor, best_w: torch.Tensor, nout: int,
+                       widths: Sequence[int], threshold: float, tile_dm: int, tile_t: int,
+                       nms_dm: int, nms_t: int, cap: int = 4096, stream=None,
+                       allow_truncated: bool = False):
+    """sps_detect on the library's fixed device scratch (no device allocation)."""
+    return _detect("sps_detect_noalloc", plan, snr, best_w, nout, widths, threshold, tile_dm,
+                   tile_t, nms_dm, nms_t, cap, stream, allow_truncated)
+
+
+def _detect(name, plan, snr, best_w, nout, widths, threshold, tile_dm, tile_t, nms_dm, nms_t,
+            cap, stream, allow_truncated):
     w = np.ascontiguousarray(widths, dtype=np.int32)
     prm = sps_detect_params(float(threshold), int(tile_dm), int(tile_t), int(nms_dm), int(nms_t))
     out = (sps_candidate * max(cap, 1))()
     n = ctypes.c_int32()
-    rc = library().sps_detect(plan.handle, _dev(snr, torch.float32, "snr"),
+    rc = getattr(library(), name)(plan.handle, _dev(snr, torch.float32, "snr"),
                               _dev(best_w, torch.uint8, "best_w"), int(nout), w.ctypes.data,
                               w.size, ctypes.byref(prm), out, int(cap), ctypes.byref(n),
                               _stream(stream))
     if not (rc == 6 and allow_truncated):
-        _check(rc, "sps_detect")
+        _check(rc, name)
     k = min(int(n.value), cap)
     arr = np.frombuffer(bytes(out)[:k * ctypes.sizeof(sps_candidate)], dtype=CANDIDATE_DTYPE).copy()
     return arr, int(n.value)
