@@ -158,6 +158,20 @@ sps_status sps_detect(sps_plan plan, const float *snr, const uint8_t *best_w, in
                       const int32_t *widths, int32_t nw, const sps_detect_params *params,
                       sps_candidate *out, int32_t cap, int32_t *n_found, void *stream);
 
+/* The search of one plane in one call: row statistics and boxcar S/N as in
+ * sps_boxcar_snr, then candidates as in sps_detect, with the tile maxima
+ * gathered by the boxcar pass itself (each boxcar workgroup reduces its
+ * outputs to one key per tile and merges it atomically) instead of a
+ * second pass over the S/N plane.  Same arguments, checks, results and
+ * errors as sps_boxcar_snr followed by sps_detect on the same plan (Sec. 1
+ * step iii; Sec. 2, candidate record); snr, best_w and stats receive the
+ * same planes.  Uses the plan's detection scratch (grown on demand).
+ * Synchronises the stream. */
+sps_status sps_search(sps_plan plan, const uint32_t *Y, int64_t nout, const int32_t *widths,
+                      int32_t nw, float *snr, uint8_t *best_w, int32_t *stats,
+                      const sps_detect_params *params, sps_candidate *out, int32_t cap,
+                      int32_t *n_found, void *stream);
+
 /* sps_detect for callers that cannot allocate device memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc):
  * the same arguments, checks, kernels and results, but the detection

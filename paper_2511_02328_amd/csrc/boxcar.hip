@@ -49,6 +49,76 @@ __device__ __forceinline__ uint32_t add3_u32(uint32_t a, uint32_t b, uint32_t c)
   return r;
 }
 
+// Running tile maximum of one thread's outputs of a segment (row d, first
+// output t0).  TILES = 0: none.  TILES = 1: the segment lies in one tile
+// column; each thread keeps its largest S/N and the first output holding it
+// (outputs arrive in increasing t), and finish() reduces the workgroup to
+// one key and one atomic.  TILES = 2: any tiling; a thread flushes its
+// maximum with an atomic whenever its outputs enter the next tile column.
+template <int TILES>
+struct TileTrack {
+  float s = -INFINITY;
+  int tl = 0;
+  int64_t col = 0, col_end = 0;
+
+  __device__ __forceinline__ void begin(const TileSink &k, int64_t t0) {
+    if constexpr (TILES != 0) {
+      col = t0 / k.tile_t;
+      col_end = (col + 1) * k.tile_t;
+    }
+  }
+  __device__ __forceinline__ unsigned long long key(const TileSink &k, int d, int64_t t0) const {
+    const int64_t t = t0 + tl;
+    const int a = d / k.tile_dm;
+    const uint32_t pos =
+        (uint32_t)((t - col * k.tile_t) * k.tile_dm + (int64_t)(d - a * k.tile_dm));
+    return ((unsigned long long)snr_key_bits(s) << 32) | (unsigned long long)(~pos);
+  }
+  __device__ __forceinline__ void flush(const TileSink &k, int d, int64_t t0) {
+    if (s != -INFINITY)
+      atomicMax(k.keys + (int64_t)(d / k.tile_dm) * k.ntt + col, key(k, d, t0));
+  }
+  __device__ __forceinline__ void add(const TileSink &k, int d, int64_t t0, float v, int t_local) {
+    if constexpr (TILES == 2) {
+      if (t0 + t_local >= col_end) {
+        flush(k, d, t0);
+        col = (t0 + t_local) / k.tile_t;
+        col_end = (col + 1) * k.tile_t;
+        s = -INFINITY;
+      }
+    }
+    if constexpr (TILES != 0) {
+      if (v > s) {
+        s = v;
+        tl = t_local;
+      }
+    }
+  }
+  // Every thread of the workgroup calls this once, after its last add.
+  __device__ __forceinline__ void finish(const TileSink &k, int d, int64_t t0,
+                                         unsigned long long *red) {
+    if constexpr (TILES == 1) {
+      unsigned long long v = s == -INFINITY ? 0ull : key(k, d, t0);
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t lo = __shfl_xor((uint32_t)v, o, 64);
+        const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), o, 64);
+        const unsigned long long u = ((unsigned long long)hi << 32) | lo;
+        v = u > v ? u : v;
+      }
+      if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+#pragma unroll
+        for (int w = 1; w < kThreads / 64; ++w) v = red[w] > v ? red[w] : v;
+        if (v != 0ull) atomicMax(k.keys + (int64_t)(d / k.tile_dm) * k.ntt + col, v);
+      }
+    } else if constexpr (TILES == 2) {
+      flush(k, d, t0);
+    }
+  }
+};
+
 // Widths 1, 2, 4, ..., 2^(NPOW-1): window offsets are immediates of the LDS
 // reads and width indices are constants, and the window length kLen is a
 // compile-time constant, so each thread issues all of its loads before the
@@ -58,11 +128,13 @@ __device__ __forceinline__ uint32_t add3_u32(uint32_t a, uint32_t b, uint32_t c)
 // missing samples read as zero, widths that run past the row end are left
 // out of the maximum (as -inf; width 1 always fits), and outputs past the
 // row end are not written.
-template <int NPOW, bool TAIL>
+template <int NPOW, bool TAIL, int TILES>
 __device__ __forceinline__ void pow2_segment(const SPS_GLOBAL uint32_t *src, int n_left,
                                              int32_t med, int32_t mad, const WidthList &widths,
                                              float *scale, uint32_t *tmp, SPS_GLOBAL float *srow,
-                                             SPS_GLOBAL uint8_t *brow, uint32_t *P) {
+                                             SPS_GLOBAL uint8_t *brow, uint32_t *P,
+                                             TileTrack<TILES> &tr, const TileSink &sink, int d,
+                                             int64_t t0) {
   constexpr int kLen = kSeg + (1 << (NPOW - 1)) - 1;
   constexpr int kLd = (kLen + kThreads - 1) / kThreads;
   constexpr int kCh = kLd | 1;
@@ -134,20 +206,26 @@ __device__ __forceinline__ void pow2_segment(const SPS_GLOBAL uint32_t *src, int
     int bi = NPOW - 1;
 #pragma unroll
     for (int i = NPOW - 2; i >= 0; --i) bi = s[i] == mx ? i : bi;
-    srow[tl] = live ? mx : 0.0f;
+    const float out = live ? mx : 0.0f;
+    srow[tl] = out;
     brow[tl] = (uint8_t)bi;
+    tr.add(sink, d, t0, out, tl);
   }
 }
 
 // NPOW > 0: power-of-two widths (pow2_segment); NPOW = 0: any width list.
-template <int NPOW>
+template <int NPOW, int TILES>
 __device__ __forceinline__ void boxcar_segment(const uint32_t *__restrict__ Y, int64_t nout, int d,
                                                int seg, const int32_t *__restrict__ stats,
                                                const WidthList &widths, float *__restrict__ snr,
-                                               uint8_t *__restrict__ best, uint32_t *P) {
+                                               uint8_t *__restrict__ best, uint32_t *P,
+                                               const TileSink &sink) {
   __shared__ float scale[kMaxWidths];
   __shared__ uint32_t tmp[4];
+  __shared__ unsigned long long red[kThreads / 64];
   const int64_t t0 = (int64_t)seg * kSeg;
+  TileTrack<TILES> tr;
+  tr.begin(sink, t0);
   const SPS_GLOBAL uint32_t *row = gmem(Y + (int64_t)d * nout);
   const int nw = widths.n;
   const int wmax = widths.w[nw - 1];
@@ -168,9 +246,12 @@ __device__ __forceinline__ void boxcar_segment(const uint32_t *__restrict__ Y, i
     SPS_GLOBAL float *srow = gmem(snr + (int64_t)d * nout + t0);
     SPS_GLOBAL uint8_t *brow = gmem(best + (int64_t)d * nout + t0);
     if (avail >= (int64_t)kLen)
-      pow2_segment<NPOW, false>(row + t0, kLen, med, mad, widths, scale, tmp, srow, brow, P);
+      pow2_segment<NPOW, false, TILES>(row + t0, kLen, med, mad, widths, scale, tmp, srow, brow,
+                                       P, tr, sink, d, t0);
     else
-      pow2_segment<NPOW, true>(row + t0, (int)avail, med, mad, widths, scale, tmp, srow, brow, P);
+      pow2_segment<NPOW, true, TILES>(row + t0, (int)avail, med, mad, widths, scale, tmp, srow,
+                                      brow, P, tr, sink, d, t0);
+    tr.finish(sink, d, t0, red);
     return;
   }
 
@@ -220,9 +301,12 @@ __device__ __forceinline__ void boxcar_segment(const uint32_t *__restrict__ Y, i
           bi = i;
         }
       }
-      srow[tl] = live ? bs : 0.0f;
+      const float out = live ? bs : 0.0f;
+      srow[tl] = out;
       brow[tl] = (uint8_t)bi;
+      tr.add(sink, d, t0, out, tl);
     }
+    tr.finish(sink, d, t0, red);
     return;
   }
 
@@ -244,80 +328,196 @@ __device__ __forceinline__ void boxcar_segment(const uint32_t *__restrict__ Y, i
         bi = i;
       }
     }
-    srow[tl] = bi == 0xFF ? 0.0f : bs;
+    const float out = bi == 0xFF ? 0.0f : bs;
+    srow[tl] = out;
     brow[tl] = (uint8_t)bi;
+    tr.add(sink, d, t0, out, tl);
   }
+  tr.finish(sink, d, t0, red);
 }
 
-template <int NPOW>
+template <int NPOW, int TILES>
 __global__ __launch_bounds__(kThreads) void boxcar_kernel(
     const uint32_t *__restrict__ Y, int64_t nout, int nseg, const int32_t *__restrict__ stats,
-    WidthList widths, float *__restrict__ snr, uint8_t *__restrict__ best) {
+    WidthList widths, float *__restrict__ snr, uint8_t *__restrict__ best, TileSink sink) {
   extern __shared__ uint32_t P[];  // [kSeg + w_max]
   const int64_t blk = blockIdx.x;
   const int d = (int)(blk / nseg);
   const int seg = (int)(blk - (int64_t)d * nseg);
-  boxcar_segment<NPOW>(Y, nout, d, seg, stats, widths, snr, best, P);
+  boxcar_segment<NPOW, TILES>(Y, nout, d, seg, stats, widths, snr, best, P, sink);
 }
 
-// One workgroup per (beam, DM row, segment) of a batch.
-template <int NPOW>
+// One workgroup per (beam, DM row, segment) of a batch.  With TILES, the
+// beam's tile keys are the out array of its detection scratch.
+template <int NPOW, int TILES>
 __global__ __launch_bounds__(kThreads) void boxcar_batch_kernel(
-    const BeamWork *__restrict__ beams, int nbeams, WidthList widths) {
+    const BeamWork *__restrict__ beams, int nbeams, WidthList widths, uint8_t *scratch, int ndm,
+    int tile_dm, int64_t tile_t) {
   extern __shared__ uint32_t P[];
   const int64_t blk = blockIdx.x;
   const BeamWork &bw = beams[find_beam<&BeamWork::bx_begin>(beams, nbeams, blk)];
   const int64_t local = blk - bw.bx_begin;
   const int d = (int)(local / bw.nseg);
   const int seg = (int)(local - (int64_t)d * bw.nseg);
-  boxcar_segment<NPOW>(bw.Y, bw.nout, d, seg, bw.stats, widths, bw.snr, bw.best, P);
+  TileSink sink{};
+  if constexpr (TILES != 0) {
+    const int64_t ntd = (ndm + tile_dm - 1) / tile_dm;
+    sink.keys = reinterpret_cast<unsigned long long *>(scratch + bw.det_begin +
+                                                       detect_layout(ntd * bw.ntt).out);
+    sink.tile_dm = tile_dm;
+    sink.tile_t = tile_t;
+    sink.ntt = bw.ntt;
+  }
+  boxcar_segment<NPOW, TILES>(bw.Y, bw.nout, d, seg, bw.stats, widths, bw.snr, bw.best, P, sink);
+}
+
+// Tile keys: zeroed (DECODE false) or turned into tile peak records.
+__device__ __forceinline__ void tile_key(const TileSink &k, int ndm, int64_t nout,
+                                         const uint8_t *best, TilePeak *peaks, int64_t i,
+                                         bool decode) {
+  if (!decode) {
+    k.keys[i] = 0ull;
+    return;
+  }
+  const unsigned long long v = k.keys[i];
+  const int a = (int)(i / k.ntt);
+  const int64_t b = i - (int64_t)a * k.ntt;
+  const uint32_t pos = ~(uint32_t)v;
+  int64_t tl = pos / (uint32_t)k.tile_dm;
+  int dl = (int)(pos - (uint32_t)tl * (uint32_t)k.tile_dm);
+  const int d0 = a * k.tile_dm;
+  const int64_t t0 = b * k.tile_t;
+  if (v == 0ull || d0 + dl >= ndm || t0 + tl >= nout) {  // no output reached the tile
+    tl = 0;
+    dl = 0;
+  }
+  TilePeak p;
+  p.snr = v == 0ull ? 0.0f : snr_from_key_bits((uint32_t)(v >> 32));
+  p.d = d0 + dl;
+  p.t = (int32_t)(t0 + tl);
+  p.w = gmem(best)[(int64_t)p.d * nout + p.t];
+  peaks[i] = p;
+}
+
+__global__ __launch_bounds__(kThreads) void tile_keys_kernel(TileSink k, int64_t ntiles, int ndm,
+                                                             int64_t nout,
+                                                             const uint8_t *__restrict__ best,
+                                                             TilePeak *__restrict__ peaks,
+                                                             int decode) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i < ntiles) tile_key(k, ndm, nout, best, peaks, i, decode != 0);
+}
+
+// One thread per (beam, tile) of a batch.
+__global__ __launch_bounds__(kThreads) void tile_keys_batch_kernel(
+    const BeamWork *__restrict__ beams, int nbeams, int ndm, int64_t total_tiles, int tile_dm,
+    int64_t tile_t, uint8_t *scratch, int decode) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= total_tiles) return;
+  const BeamWork &bw = beams[find_beam<&BeamWork::tp_begin>(beams, nbeams, i)];
+  const int64_t ntd = (ndm + tile_dm - 1) / tile_dm;
+  const DetectLayout L = detect_layout(ntd * bw.ntt);
+  TileSink k{};
+  k.keys = reinterpret_cast<unsigned long long *>(scratch + bw.det_begin + L.out);
+  k.tile_dm = tile_dm;
+  k.tile_t = tile_t;
+  k.ntt = bw.ntt;
+  tile_key(k, ndm, bw.nout, bw.best, reinterpret_cast<TilePeak *>(scratch + bw.det_begin + L.peaks),
+           i - bw.tp_begin, decode != 0);
+}
+
+// 0: no tile maxima; 1: every segment inside one tile column (tile_t a
+// multiple of the segment length); 2: any tiling.
+int tile_mode(const void *keys, int64_t tile_t) {
+  if (!keys) return 0;
+  return tile_t % kSeg == 0 ? 1 : 2;
 }
 
 }  // namespace
 
 hipError_t launch_boxcar(const uint32_t *Y, int ndm, int64_t nout, const int32_t *stats,
-                         const WidthList &widths, float *snr, uint8_t *best,
-                         hipStream_t stream) {
+                         const WidthList &widths, float *snr, uint8_t *best, hipStream_t stream,
+                         const TileSink &sink) {
   const int64_t nseg = (nout + kSeg - 1) / kSeg;
   const int64_t grid = nseg * ndm;
   if (grid > 0x7FFFFFFF || nseg > 0x7FFFFFFF) return hipErrorInvalidValue;
+  if (sink.keys && (sink.tile_dm < 1 || sink.tile_t < 1)) return hipErrorInvalidValue;
   const size_t lds = (size_t)(kSeg + widths.w[widths.n - 1] + 1) * sizeof(uint32_t);
   bool pow2 = widths.n <= 13;
   for (int i = 0; i < widths.n && pow2; ++i) pow2 = widths.w[i] == (1 << i);
-#define SPS_BOXCAR_CASE(n_)                                                                    \
-  if (pow2 && widths.n == n_) {                                                                \
-    hipLaunchKernelGGL(boxcar_kernel<n_>, dim3((unsigned)grid), dim3(kThreads), lds, stream, Y, \
-                       nout, (int)nseg, stats, widths, snr, best);                             \
-    return hipGetLastError();                                                                  \
+  const int tm = tile_mode(sink.keys, sink.tile_t);
+#define SPS_BOXCAR_LAUNCH(n_, t_)                                                          \
+  hipLaunchKernelGGL((boxcar_kernel<n_, t_>), dim3((unsigned)grid), dim3(kThreads), lds, stream, \
+                     Y, nout, (int)nseg, stats, widths, snr, best, sink)
+#define SPS_BOXCAR_CASE(n_)                                 \
+  if (pow2 && widths.n == n_) {                             \
+    if (tm == 0) SPS_BOXCAR_LAUNCH(n_, 0);                  \
+    else if (tm == 1) SPS_BOXCAR_LAUNCH(n_, 1);             \
+    else SPS_BOXCAR_LAUNCH(n_, 2);                          \
+    return hipGetLastError();                               \
   }
   SPS_BOXCAR_CASE(1) SPS_BOXCAR_CASE(2) SPS_BOXCAR_CASE(3) SPS_BOXCAR_CASE(4) SPS_BOXCAR_CASE(5)
   SPS_BOXCAR_CASE(6) SPS_BOXCAR_CASE(7) SPS_BOXCAR_CASE(8) SPS_BOXCAR_CASE(9) SPS_BOXCAR_CASE(10)
   SPS_BOXCAR_CASE(11) SPS_BOXCAR_CASE(12) SPS_BOXCAR_CASE(13)
+  if (tm == 0) SPS_BOXCAR_LAUNCH(0, 0);
+  else if (tm == 1) SPS_BOXCAR_LAUNCH(0, 1);
+  else SPS_BOXCAR_LAUNCH(0, 2);
 #undef SPS_BOXCAR_CASE
-  hipLaunchKernelGGL(boxcar_kernel<0>, dim3((unsigned)grid), dim3(kThreads), lds, stream, Y, nout,
-                     (int)nseg, stats, widths, snr, best);
+#undef SPS_BOXCAR_LAUNCH
   return hipGetLastError();
 }
 
 hipError_t launch_boxcar_batch(const BeamWork *beams, int nbeams, int64_t total_blocks,
-                               const WidthList &widths, hipStream_t stream) {
+                               const WidthList &widths, hipStream_t stream, uint8_t *scratch,
+                               int ndm, int tile_dm, int64_t tile_t) {
   if (total_blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
+  if (scratch && (tile_dm < 1 || tile_t < 1 || ndm < 1)) return hipErrorInvalidValue;
   const size_t lds = (size_t)(kSeg + widths.w[widths.n - 1] + 1) * sizeof(uint32_t);
   bool pow2 = widths.n <= 13;
   for (int i = 0; i < widths.n && pow2; ++i) pow2 = widths.w[i] == (1 << i);
-#define SPS_BOXCAR_BCASE(n_)                                                                 \
-  if (pow2 && widths.n == n_) {                                                              \
-    hipLaunchKernelGGL(boxcar_batch_kernel<n_>, dim3((unsigned)total_blocks), dim3(kThreads), \
-                       lds, stream, beams, nbeams, widths);                                  \
-    return hipGetLastError();                                                                \
+  const int tm = tile_mode(scratch, tile_t);
+#define SPS_BOXCAR_BLAUNCH(n_, t_)                                                           \
+  hipLaunchKernelGGL((boxcar_batch_kernel<n_, t_>), dim3((unsigned)total_blocks), dim3(kThreads), \
+                     lds, stream, beams, nbeams, widths, scratch, ndm, tile_dm, tile_t)
+#define SPS_BOXCAR_BCASE(n_)                                \
+  if (pow2 && widths.n == n_) {                             \
+    if (tm == 0) SPS_BOXCAR_BLAUNCH(n_, 0);                 \
+    else if (tm == 1) SPS_BOXCAR_BLAUNCH(n_, 1);            \
+    else SPS_BOXCAR_BLAUNCH(n_, 2);                         \
+    return hipGetLastError();                               \
   }
   SPS_BOXCAR_BCASE(1) SPS_BOXCAR_BCASE(2) SPS_BOXCAR_BCASE(3) SPS_BOXCAR_BCASE(4)
   SPS_BOXCAR_BCASE(5) SPS_BOXCAR_BCASE(6) SPS_BOXCAR_BCASE(7) SPS_BOXCAR_BCASE(8)
   SPS_BOXCAR_BCASE(9) SPS_BOXCAR_BCASE(10) SPS_BOXCAR_BCASE(11) SPS_BOXCAR_BCASE(12)
   SPS_BOXCAR_BCASE(13)
+  if (tm == 0) SPS_BOXCAR_BLAUNCH(0, 0);
+  else if (tm == 1) SPS_BOXCAR_BLAUNCH(0, 1);
+  else SPS_BOXCAR_BLAUNCH(0, 2);
 #undef SPS_BOXCAR_BCASE
-  hipLaunchKernelGGL(boxcar_batch_kernel<0>, dim3((unsigned)total_blocks), dim3(kThreads), lds,
-                     stream, beams, nbeams, widths);
+#undef SPS_BOXCAR_BLAUNCH
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_keys(const TileSink &sink, int ndm, int64_t nout, const uint8_t *best,
+                            TilePeak *peaks, bool decode, hipStream_t stream) {
+  if (!sink.keys || sink.tile_dm < 1 || sink.tile_t < 1) return hipErrorInvalidValue;
+  const int64_t ntiles = (int64_t)((ndm + sink.tile_dm - 1) / sink.tile_dm) * sink.ntt;
+  const int64_t grid = (ntiles + kThreads - 1) / kThreads;
+  if (grid > 0x7FFFFFFF) return hipErrorInvalidValue;
+  if (grid == 0) return hipSuccess;
+  hipLaunchKernelGGL(tile_keys_kernel, dim3((unsigned)grid), dim3(kThreads), 0, stream, sink,
+                     ntiles, ndm, nout, best, peaks, decode ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_keys_batch(const BeamWork *beams, int nbeams, int ndm, int64_t total_tiles,
+                                  int tile_dm, int64_t tile_t, uint8_t *scratch, bool decode,
+                                  hipStream_t stream) {
+  const int64_t grid = (total_tiles + kThreads - 1) / kThreads;
+  if (grid > 0x7FFFFFFF || tile_dm < 1 || tile_t < 1) return hipErrorInvalidValue;
+  if (grid == 0) return hipSuccess;
+  hipLaunchKernelGGL(tile_keys_batch_kernel, dim3((unsigned)grid), dim3(kThreads), 0, stream,
+                     beams, nbeams, ndm, total_tiles, tile_dm, tile_t, scratch, decode ? 1 : 0);
   return hipGetLastError();
 }
 

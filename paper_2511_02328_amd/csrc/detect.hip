@@ -23,11 +23,6 @@ namespace {
 constexpr int kTileThreads = 256;
 constexpr int kNmsThreads = 1024;
 
-__device__ __forceinline__ uint32_t ordered_bits(float v) {
-  const uint32_t u = __float_as_uint(v);
-  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-}
-
 __device__ __forceinline__ uint64_t max_u64(uint64_t a, uint64_t b) { return a > b ? a : b; }
 
 __device__ __forceinline__ void tile_peak(const float *__restrict__ snr,
@@ -57,14 +52,14 @@ __device__ __forceinline__ void tile_peak(const float *__restrict__ snr,
     for (int64_t q = threadIdx.x; q < nq; q += kTileThreads) {
       const f32x4 v = rv[q];
       const uint32_t p0 = (uint32_t)(4 * q) * (uint32_t)tile_dm + dl;
-      key = max_u64(key, ((uint64_t)ordered_bits(v.x) << 32) | (uint64_t)(~p0));
-      key = max_u64(key, ((uint64_t)ordered_bits(v.y) << 32) | (uint64_t)(~(p0 + tile_dm)));
-      key = max_u64(key, ((uint64_t)ordered_bits(v.z) << 32) | (uint64_t)(~(p0 + 2 * tile_dm)));
-      key = max_u64(key, ((uint64_t)ordered_bits(v.w) << 32) | (uint64_t)(~(p0 + 3 * tile_dm)));
+      key = max_u64(key, ((uint64_t)snr_key_bits(v.x) << 32) | (uint64_t)(~p0));
+      key = max_u64(key, ((uint64_t)snr_key_bits(v.y) << 32) | (uint64_t)(~(p0 + tile_dm)));
+      key = max_u64(key, ((uint64_t)snr_key_bits(v.z) << 32) | (uint64_t)(~(p0 + 2 * tile_dm)));
+      key = max_u64(key, ((uint64_t)snr_key_bits(v.w) << 32) | (uint64_t)(~(p0 + 3 * tile_dm)));
     }
     for (int64_t t = t0 + 4 * nq + threadIdx.x; t < t1; t += kTileThreads) {
       const uint32_t pos = (uint32_t)((t - t0) * tile_dm + (d - d0));
-      const uint64_t k = ((uint64_t)ordered_bits(row[t]) << 32) | (uint64_t)(~pos);
+      const uint64_t k = ((uint64_t)snr_key_bits(row[t]) << 32) | (uint64_t)(~pos);
       key = max_u64(key, k);
     }
   }
@@ -436,6 +431,13 @@ hipError_t launch_detect_batch(const BeamWork *beams, int nbeams, int ndm, int64
                      stream, beams, nbeams, ndm, tile_dm, tile_t, scratch);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  return launch_select_nms_batch(beams, nbeams, ndm, tile_dm, tile_t, threshold, nms_dm, nms_t,
+                                 scratch, stream);
+}
+
+hipError_t launch_select_nms_batch(const BeamWork *beams, int nbeams, int ndm, int tile_dm,
+                                   int64_t tile_t, float threshold, int nms_dm, int64_t nms_t,
+                                   uint8_t *scratch, hipStream_t stream) {
   hipLaunchKernelGGL(select_nms_batch_kernel, dim3(nbeams), dim3(kNmsThreads), 0, stream, beams,
                      ndm, tile_dm, tile_t, threshold, nms_dm, nms_t, scratch);
   return hipGetLastError();

@@ -263,15 +263,18 @@ sps_status fixed_scratch(int device, uint8_t **ptr) {
   return SPS_OK;
 }
 
-// sps_detect and sps_detect_noalloc: the same checks and kernels; the
-// scratch is the plan's (grown with hipMalloc on demand) or the fixed one.
-sps_status run_detect(sps_plan plan, const float *snr, const uint8_t *best_w, int64_t nout,
-                      const int32_t *widths, int32_t nw, const sps_detect_params *prm,
-                      sps_candidate *out, int32_t cap, int32_t *n_found, void *stream,
-                      bool fixed) {
-  g_error.clear();
-  if (!plan || !snr || !best_w || !widths || !prm || !n_found)
-    return fail(SPS_ERR_INVALID_ARG, "NULL plan, buffer or parameter");
+// Checks shared by the calls that detect candidates; fills the tile count,
+// the scratch layout and the suppression radii clamped to the plane.
+struct DetectArgs {
+  int64_t ntiles = 0, ntt = 0;
+  int32_t nms_dm = 0;
+  int64_t nms_t = 0;
+  sps::DetectLayout L{};
+};
+
+sps_status check_detect(sps_plan plan, int64_t nout, int32_t nw, const sps_detect_params *prm,
+                        sps_candidate *out, int32_t cap, const int32_t *n_found, DetectArgs *a) {
+  if (!prm || !n_found) return fail(SPS_ERR_INVALID_ARG, "NULL parameter or count");
   if (cap < 0 || (cap > 0 && !out)) return fail(SPS_ERR_INVALID_ARG, "bad output array");
   if (nout < 1 || nout > 0x7FFFFFFF) return fail(SPS_ERR_RANGE, "nout must be in [1, 2^31-1]");
   if (nw < 1 || nw > sps::kMaxWidths) return fail(SPS_ERR_INVALID_ARG, "bad width count");
@@ -282,48 +285,89 @@ sps_status run_detect(sps_plan plan, const float *snr, const uint8_t *best_w, in
   if ((uint64_t)prm->tile_dm * (uint64_t)prm->tile_t >= (1ull << 32))
     return fail(SPS_ERR_RANGE, "tile_dm * tile_t must be below 2^32");
   const int64_t ntd = (plan->ndm + prm->tile_dm - 1) / prm->tile_dm;
-  const int64_t ntt = (nout + prm->tile_t - 1) / prm->tile_t;
-  const int64_t ntiles = ntd * ntt;
-  if (ntiles > 0x7FFFFFFF) return fail(SPS_ERR_RANGE, "too many tiles");
-  const sps::DetectLayout L = sps::detect_layout(ntiles);
-  if (fixed && L.bytes > kFixedScratchBytes)
+  a->ntt = (nout + prm->tile_t - 1) / prm->tile_t;
+  a->ntiles = ntd * a->ntt;
+  if (a->ntiles > 0x7FFFFFFF) return fail(SPS_ERR_RANGE, "too many tiles");
+  a->L = sps::detect_layout(a->ntiles);
+  // radii past the plane's extent suppress the same offers as the extent
+  a->nms_dm = prm->nms_dm < plan->ndm ? prm->nms_dm : plan->ndm;
+  a->nms_t = prm->nms_t < nout ? prm->nms_t : nout;
+  return SPS_OK;
+}
+
+// The plan's detection scratch, grown with hipMalloc to at least `bytes`.
+sps_status plan_scratch(sps_plan plan, int64_t bytes, uint8_t **det) {
+  if (plan->det_bytes < bytes) {
+    if (plan->d_det) (void)hipFree(plan->d_det);
+    plan->d_det = nullptr;
+    plan->det_bytes = 0;
+    const hipError_t e = hipMalloc(&plan->d_det, (size_t)bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(SPS_ERR_NOMEM, "device allocation of detection scratch failed");
+    }
+    plan->det_bytes = bytes;
+  }
+  *det = plan->d_det;
+  return SPS_OK;
+}
+
+// Checks of the boxcar calls; fills the width list and 255 nchan.
+sps_status check_boxcar(sps_plan plan, int64_t nout, const int32_t *widths, int32_t nw,
+                        sps::WidthList *wl, uint32_t *vmax) {
+  if (nout < 1 || nout > 0x7FFFFFFF) return fail(SPS_ERR_RANGE, "nout must be in [1, 2^31-1]");
+  if (nw < 1 || nw > sps::kMaxWidths)
+    return fail(SPS_ERR_INVALID_ARG, "nw must be in [1, %d]", sps::kMaxWidths);
+  wl->n = nw;
+  for (int i = 0; i < nw; ++i) {
+    wl->w[i] = widths[i];
+    if (widths[i] < 1) return fail(SPS_ERR_INVALID_ARG, "widths must be >= 1");
+    if (i > 0 && widths[i] <= widths[i - 1])
+      return fail(SPS_ERR_INVALID_ARG, "widths must be strictly ascending");
+  }
+  for (int i = nw; i < sps::kMaxWidths; ++i) wl->w[i] = 0;
+  const int64_t wmax = widths[nw - 1];
+  if (wmax > nout || wmax > sps::kMaxWidth)
+    return fail(SPS_ERR_RANGE, "largest width %lld exceeds nout or %d", (long long)wmax,
+                sps::kMaxWidth);
+  *vmax = 255u * (uint32_t)plan->nchan;
+  if ((uint64_t)wmax * *vmax >= (1ull << 31))
+    return fail(SPS_ERR_OVERFLOW, "width %lld x 255 x nchan reaches 2^31", (long long)wmax);
+  return SPS_OK;
+}
+
+// sps_detect and sps_detect_noalloc: the same checks and kernels; the
+// scratch is the plan's (grown with hipMalloc on demand) or the fixed one.
+sps_status run_detect(sps_plan plan, const float *snr, const uint8_t *best_w, int64_t nout,
+                      const int32_t *widths, int32_t nw, const sps_detect_params *prm,
+                      sps_candidate *out, int32_t cap, int32_t *n_found, void *stream,
+                      bool fixed) {
+  g_error.clear();
+  if (!plan || !snr || !best_w || !widths)
+    return fail(SPS_ERR_INVALID_ARG, "NULL plan, buffer or parameter");
+  DetectArgs a;
+  sps_status st = check_detect(plan, nout, nw, prm, out, cap, n_found, &a);
+  if (st != SPS_OK) return st;
+  if (fixed && a.L.bytes > kFixedScratchBytes)
     return fail(SPS_ERR_RANGE,
                 "%lld tiles need %lld bytes of detection scratch; the fixed scratch holds %lld "
                 "(at least %lld tiles)",
-                (long long)ntiles, (long long)L.bytes, (long long)kFixedScratchBytes,
+                (long long)a.ntiles, (long long)a.L.bytes, (long long)kFixedScratchBytes,
                 (long long)kFixedScratchTiles);
   DeviceScope scope(plan->device);
   if (scope.err != hipSuccess) return hip_fail(scope.err, "selecting the plan's device");
-  // radii past the plane's extent suppress the same offers as the extent
-  const int32_t nms_dm = prm->nms_dm < plan->ndm ? prm->nms_dm : plan->ndm;
-  const int64_t nms_t = prm->nms_t < nout ? prm->nms_t : nout;
   uint8_t *det = nullptr;
-  if (fixed) {
-    const sps_status st = fixed_scratch(plan->device, &det);
-    if (st != SPS_OK) return st;
-  } else {
-    if (plan->det_bytes < L.bytes) {
-      if (plan->d_det) (void)hipFree(plan->d_det);
-      plan->d_det = nullptr;
-      plan->det_bytes = 0;
-      const hipError_t e = hipMalloc(&plan->d_det, (size_t)L.bytes);
-      if (e != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(SPS_ERR_NOMEM, "device allocation of detection scratch failed");
-      }
-      plan->det_bytes = L.bytes;
-    }
-    det = plan->d_det;
-  }
+  st = fixed ? fixed_scratch(plan->device, &det) : plan_scratch(plan, a.L.bytes, &det);
+  if (st != SPS_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = sps::launch_tile_peaks(snr, best_w, plan->ndm, nout, prm->tile_dm, prm->tile_t,
-                                        reinterpret_cast<sps::TilePeak *>(det + L.peaks), s);
+                                        reinterpret_cast<sps::TilePeak *>(det + a.L.peaks), s);
   if (e != hipSuccess) return hip_fail(e, "tile peak launch");
   e = sps::launch_select_nms(det, plan->ndm, nout, prm->tile_dm, prm->tile_t, prm->threshold,
-                             nms_dm, nms_t, s);
+                             a.nms_dm, a.nms_t, s);
   if (e != hipSuccess) return hip_fail(e, "selection launch");
-  return read_candidates(det, ntiles, widths, nw, plan->dm.data(), plan->ndm, plan->tsamp_s, out,
-                         cap, n_found, s);
+  return read_candidates(det, a.ntiles, widths, nw, plan->dm.data(), plan->ndm, plan->tsamp_s,
+                         out, cap, n_found, s);
 }
 
 }  // namespace
@@ -539,33 +583,61 @@ sps_status sps_boxcar_snr(sps_plan plan, const uint32_t *Y, int64_t nout, const 
   g_error.clear();
   if (!plan || !Y || !widths || !snr || !best_w)
     return fail(SPS_ERR_INVALID_ARG, "NULL plan or buffer");
-  if (nout < 1 || nout > 0x7FFFFFFF) return fail(SPS_ERR_RANGE, "nout must be in [1, 2^31-1]");
-  if (nw < 1 || nw > sps::kMaxWidths)
-    return fail(SPS_ERR_INVALID_ARG, "nw must be in [1, %d]", sps::kMaxWidths);
   sps::WidthList wl;
-  wl.n = nw;
-  for (int i = 0; i < nw; ++i) {
-    wl.w[i] = widths[i];
-    if (widths[i] < 1) return fail(SPS_ERR_INVALID_ARG, "widths must be >= 1");
-    if (i > 0 && widths[i] <= widths[i - 1])
-      return fail(SPS_ERR_INVALID_ARG, "widths must be strictly ascending");
-  }
-  for (int i = nw; i < sps::kMaxWidths; ++i) wl.w[i] = 0;
-  const int64_t wmax = widths[nw - 1];
-  if (wmax > nout || wmax > sps::kMaxWidth)
-    return fail(SPS_ERR_RANGE, "largest width %lld exceeds nout or %d", (long long)wmax,
-                sps::kMaxWidth);
-  const uint32_t vmax = 255u * (uint32_t)plan->nchan;
-  if ((uint64_t)wmax * vmax >= (1ull << 31))
-    return fail(SPS_ERR_OVERFLOW, "width %lld x 255 x nchan reaches 2^31", (long long)wmax);
+  uint32_t vmax = 0;
+  const sps_status st = check_boxcar(plan, nout, widths, nw, &wl, &vmax);
+  if (st != SPS_OK) return st;
   DeviceScope scope(plan->device);
   if (scope.err != hipSuccess) return hip_fail(scope.err, "selecting the plan's device");
-  int32_t *st = stats ? stats : plan->d_stats;
-  hipError_t e = sps::launch_row_stats(Y, plan->ndm, nout, vmax, st, (hipStream_t)stream);
+  int32_t *sts = stats ? stats : plan->d_stats;
+  hipError_t e = sps::launch_row_stats(Y, plan->ndm, nout, vmax, sts, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "row statistics launch");
-  e = sps::launch_boxcar(Y, plan->ndm, nout, st, wl, snr, best_w, (hipStream_t)stream);
+  e = sps::launch_boxcar(Y, plan->ndm, nout, sts, wl, snr, best_w, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "boxcar launch");
   return SPS_OK;
+}
+
+sps_status sps_search(sps_plan plan, const uint32_t *Y, int64_t nout, const int32_t *widths,
+                      int32_t nw, float *snr, uint8_t *best_w, int32_t *stats,
+                      const sps_detect_params *prm, sps_candidate *out, int32_t cap,
+                      int32_t *n_found, void *stream) {
+  g_error.clear();
+  if (!plan || !Y || !widths || !snr || !best_w)
+    return fail(SPS_ERR_INVALID_ARG, "NULL plan or buffer");
+  sps::WidthList wl;
+  uint32_t vmax = 0;
+  sps_status st = check_boxcar(plan, nout, widths, nw, &wl, &vmax);
+  if (st != SPS_OK) return st;
+  DetectArgs a;
+  st = check_detect(plan, nout, nw, prm, out, cap, n_found, &a);
+  if (st != SPS_OK) return st;
+  DeviceScope scope(plan->device);
+  if (scope.err != hipSuccess) return hip_fail(scope.err, "selecting the plan's device");
+  uint8_t *det = nullptr;
+  st = plan_scratch(plan, a.L.bytes, &det);
+  if (st != SPS_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  // tile keys in the out array of the scratch (16 bytes per tile), zeroed
+  sps::TileSink sink{};
+  sink.keys = reinterpret_cast<unsigned long long *>(det + a.L.out);
+  sink.tile_dm = prm->tile_dm;
+  sink.tile_t = prm->tile_t;
+  sink.ntt = a.ntt;
+  sps::TilePeak *peaks = reinterpret_cast<sps::TilePeak *>(det + a.L.peaks);
+  hipError_t e = sps::launch_tile_keys(sink, plan->ndm, nout, best_w, peaks, false, s);
+  if (e != hipSuccess) return hip_fail(e, "tile key clearing launch");
+  int32_t *sts = stats ? stats : plan->d_stats;
+  e = sps::launch_row_stats(Y, plan->ndm, nout, vmax, sts, s);
+  if (e != hipSuccess) return hip_fail(e, "row statistics launch");
+  e = sps::launch_boxcar(Y, plan->ndm, nout, sts, wl, snr, best_w, s, sink);
+  if (e != hipSuccess) return hip_fail(e, "boxcar launch");
+  e = sps::launch_tile_keys(sink, plan->ndm, nout, best_w, peaks, true, s);
+  if (e != hipSuccess) return hip_fail(e, "tile key decoding launch");
+  e = sps::launch_select_nms(det, plan->ndm, nout, prm->tile_dm, prm->tile_t, prm->threshold,
+                             a.nms_dm, a.nms_t, s);
+  if (e != hipSuccess) return hip_fail(e, "selection launch");
+  return read_candidates(det, a.ntiles, widths, nw, plan->dm.data(), plan->ndm, plan->tsamp_s,
+                         out, cap, n_found, s);
 }
 
 sps_status sps_detect(sps_plan plan, const float *snr, const uint8_t *best_w, int64_t nout,
@@ -899,12 +971,19 @@ sps_status batch_enqueue(sps_batch b, hipStream_t s) {
   if (e != hipSuccess) return hip_fail(e, "batched dedispersion launch");
   e = sps::launch_row_stats_batch(b->d_beams, b->nbeams, p->ndm, 255u * (uint32_t)p->nchan, s);
   if (e != hipSuccess) return hip_fail(e, "batched statistics launch");
-  e = sps::launch_boxcar_batch(b->d_beams, b->nbeams, b->bx_blocks, b->widths, s);
+  // tile maxima taken inside the boxcar pass: keys zeroed, gathered, decoded
+  e = sps::launch_tile_keys_batch(b->d_beams, b->nbeams, p->ndm, b->tp_tiles, b->prm.tile_dm,
+                                  b->prm.tile_t, b->d_det, false, s);
+  if (e != hipSuccess) return hip_fail(e, "batched tile key clearing launch");
+  e = sps::launch_boxcar_batch(b->d_beams, b->nbeams, b->bx_blocks, b->widths, s, b->d_det,
+                               p->ndm, b->prm.tile_dm, b->prm.tile_t);
   if (e != hipSuccess) return hip_fail(e, "batched boxcar launch");
-  e = sps::launch_detect_batch(b->d_beams, b->nbeams, p->ndm, b->tp_tiles, b->prm.tile_dm,
-                               b->prm.tile_t, b->prm.threshold, b->prm.nms_dm, b->prm.nms_t,
-                               b->d_det, s);
-  if (e != hipSuccess) return hip_fail(e, "batched detection launch");
+  e = sps::launch_tile_keys_batch(b->d_beams, b->nbeams, p->ndm, b->tp_tiles, b->prm.tile_dm,
+                                  b->prm.tile_t, b->d_det, true, s);
+  if (e != hipSuccess) return hip_fail(e, "batched tile key decoding launch");
+  e = sps::launch_select_nms_batch(b->d_beams, b->nbeams, p->ndm, b->prm.tile_dm, b->prm.tile_t,
+                                   b->prm.threshold, b->prm.nms_dm, b->prm.nms_t, b->d_det, s);
+  if (e != hipSuccess) return hip_fail(e, "batched selection launch");
   return SPS_OK;
 }
 

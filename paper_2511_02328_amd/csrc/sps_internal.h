@@ -150,9 +150,34 @@ struct WidthList {
   int32_t w[kMaxWidths];
 };
 
+// Order-preserving map of a binary32 S/N to an unsigned integer (a larger
+// value maps to a larger integer, -0 just below +0), and its inverse.
+__device__ __forceinline__ uint32_t snr_key_bits(float v) {
+  const uint32_t u = __float_as_uint(v);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float snr_from_key_bits(uint32_t k) {
+  return __uint_as_float((k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k);
+}
+
+// Tile maxima of a plane gathered by the boxcar pass itself.  Detection
+// tiles are tile_dm trials x tile_t samples (ntt of them along time); each
+// tile has one 64-bit key: snr_key_bits(S/N) in the high word, the
+// complement of the in-tile position (t - t_tile) * tile_dm + (d - d_tile)
+// in the low word, so the largest key is the tile's largest S/N at the
+// smallest t, then the smallest d (the order the tile peak kernel uses).
+// keys == nullptr: no tile maxima.  The keys must be zero before the pass.
+struct TileSink {
+  unsigned long long *keys;  // [ntd][ntt]
+  int32_t tile_dm;
+  int32_t pad;
+  int64_t tile_t;
+  int64_t ntt;
+};
+
 hipError_t launch_boxcar(const uint32_t *Y, int ndm, int64_t nout, const int32_t *stats,
                          const WidthList &widths, float *snr, uint8_t *best,
-                         hipStream_t stream);
+                         hipStream_t stream, const TileSink &sink = TileSink{});
 
 // Tile peak record written by the first detection kernel.
 struct TilePeak {
@@ -235,14 +260,35 @@ sps_status set_error(sps_status s, const char *msg);
 
 hipError_t launch_row_stats_batch(const BeamWork *beams, int nbeams, int ndm, uint32_t vmax,
                                   hipStream_t stream);
+// scratch != nullptr: every beam's tile maxima go to the key array of its
+// detection scratch (the out array of detect_layout, at scratch +
+// det_begin), which must be zero.
 hipError_t launch_boxcar_batch(const BeamWork *beams, int nbeams, int64_t total_blocks,
-                               const WidthList &widths, hipStream_t stream);
+                               const WidthList &widths, hipStream_t stream,
+                               uint8_t *scratch = nullptr, int ndm = 0, int tile_dm = 1,
+                               int64_t tile_t = 1);
 int64_t boxcar_segments(int64_t nout);
 // Batched detection: beam b's scratch (detect_layout of its tile count)
 // starts at scratch + beams[b].det_begin.
 hipError_t launch_detect_batch(const BeamWork *beams, int nbeams, int ndm, int64_t total_tiles,
                                int tile_dm, int64_t tile_t, float threshold, int nms_dm,
                                int64_t nms_t, uint8_t *scratch, hipStream_t stream);
+
+// Tile keys of a plane (TileSink): decode == false zeroes them; decode ==
+// true turns them into the tile peak records (S/N, d, t and the width index
+// best[d][t]) that the selection kernel reads, as the tile peak kernel would
+// have written them.
+hipError_t launch_tile_keys(const TileSink &sink, int ndm, int64_t nout, const uint8_t *best,
+                            TilePeak *peaks, bool decode, hipStream_t stream);
+// The same over every beam of a batch: keys in the out array of each beam's
+// detection scratch, peaks in its peaks array.
+hipError_t launch_tile_keys_batch(const BeamWork *beams, int nbeams, int ndm, int64_t total_tiles,
+                                  int tile_dm, int64_t tile_t, uint8_t *scratch, bool decode,
+                                  hipStream_t stream);
+// Selection and suppression of every beam of a batch from its tile peaks.
+hipError_t launch_select_nms_batch(const BeamWork *beams, int nbeams, int ndm, int tile_dm,
+                                   int64_t tile_t, float threshold, int nms_dm, int64_t nms_t,
+                                   uint8_t *scratch, hipStream_t stream);
 
 // Forward pass of n tiles (device) through net; adds to *count (device int32)
 // the number of cells whose objectness probability is >= threshold, decided

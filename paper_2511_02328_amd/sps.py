@@ -100,6 +100,8 @@ def library() -> ctypes.CDLL:
         lib.sps_boxcar_snr.argtypes = [P, P, i64, P, i32, P, P, P, P]
         lib.sps_detect.argtypes = [P, P, P, i64, P, i32, ctypes.POINTER(sps_detect_params),
                                    ctypes.POINTER(sps_candidate), i32, ctypes.POINTER(i32), P]
+        lib.sps_search.argtypes = [P, P, i64, P, i32, P, P, P, ctypes.POINTER(sps_detect_params),
+                                   ctypes.POINTER(sps_candidate), i32, ctypes.POINTER(i32), P]
         lib.sps_detect_noalloc.argtypes = [P, P, P, i64, P, i32,
                                            ctypes.POINTER(sps_detect_params),
                                            ctypes.POINTER(sps_candidate), i32,
@@ -172,7 +174,8 @@ def library() -> ctypes.CDLL:
                   "sps_server_run", "sps_server_set_detector"):
             getattr(lib, f).restype = ctypes.c_int
         for f in ("sps_plan_create", "sps_plan_destroy", "sps_plan_delays", "sps_dedisperse",
-                  "sps_boxcar_snr", "sps_detect", "sps_detect_noalloc", "sps_plan_set_tiling",
+                  "sps_boxcar_snr", "sps_search", "sps_detect", "sps_detect_noalloc",
+                  "sps_plan_set_tiling",
                   "sps_plan_get_tiling",
                   "sps_subband_plan_create", "sps_subband_tables", "sps_dedisperse_subband",
                   "sps_zero_dm", "sps_downsample_sqrt", "sps_batch_create", "sps_batch_destroy",
@@ -302,6 +305,28 @@ def sps_boxcar_snr(plan: Plan, Y: torch.Tensor, nout: int, widths: Sequence[int]
                                     _dev(snr, torch.float32, "snr"),
                                     _dev(best_w, torch.uint8, "best_w"), sp, _stream(stream)),
            "sps_boxcar_snr")
+
+
+def sps_search(plan: Plan, Y: torch.Tensor, nout: int, widths: Sequence[int], snr: torch.Tensor,
+               best_w: torch.Tensor, stats: Optional[torch.Tensor], threshold: float,
+               tile_dm: int, tile_t: int, nms_dm: int, nms_t: int, cap: int = 4096,
+               stream=None, allow_truncated: bool = False):
+    """Statistics, boxcar S/N and detection in one call; returns (candidates, number found)."""
+    w = np.ascontiguousarray(widths, dtype=np.int32)
+    yp = _dev(Y, torch.int32, "Y") if Y.dtype == torch.int32 else _dev(Y, torch.uint32, "Y")
+    sp = _dev(stats, torch.int32, "stats") if stats is not None else None
+    prm = sps_detect_params(float(threshold), int(tile_dm), int(tile_t), int(nms_dm), int(nms_t))
+    out = (sps_candidate * max(cap, 1))()
+    n = ctypes.c_int32()
+    rc = library().sps_search(plan.handle, yp, int(nout), w.ctypes.data, w.size,
+                              _dev(snr, torch.float32, "snr"), _dev(best_w, torch.uint8, "best_w"),
+                              sp, ctypes.byref(prm), out, int(cap), ctypes.byref(n),
+                              _stream(stream))
+    if not (rc == 6 and allow_truncated):
+        _check(rc, "sps_search")
+    k = min(int(n.value), cap)
+    arr = np.frombuffer(bytes(out)[:k * ctypes.sizeof(sps_candidate)], dtype=CANDIDATE_DTYPE).copy()
+    return arr, int(n.value)
 
 
 CANDIDATE_DTYPE = np.dtype([("dm_idx", np.int32), ("width", np.int32), ("t_idx", np.int64),
