@@ -522,9 +522,15 @@ int32_t sps_cnn_max_batch(sps_cnn net);
 sps_status sps_server_set_detector(sps_server server, sps_cnn net, float threshold, float scale);
 
 /* Forward pass of n tiles (device, 16-byte aligned); head (optional, device
- * FP32 [n][3][8][16]) receives the head outputs.  Asynchronous. */
+ * FP32 [n][3][8][16]) receives the head outputs.  Every layer's activation
+ * is kept (sps_cnn_activations reads them back).  Asynchronous. */
 sps_status sps_cnn_forward(sps_cnn net, const uint16_t *tiles, int32_t n, float *head,
                            void *stream);
+/* The same forward pass for inference: identical head outputs and layer
+ * 1-5 activations, but layer 0 is computed inside layer 1's workgroups and
+ * its activation (1 MB per tile) is not kept.  Asynchronous. */
+sps_status sps_cnn_infer(sps_cnn net, const uint16_t *tiles, int32_t n, float *head,
+                         void *stream);
 /* Forward, loss and backward: gradients of the mean loss into the network's
  * gradient buffer; loss (optional, device FP32) receives the loss.
  * Asynchronous. */

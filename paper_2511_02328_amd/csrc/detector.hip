@@ -33,6 +33,7 @@
 #include <string.h>
 
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "sps.h"
@@ -67,6 +68,14 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 }
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 __device__ __forceinline__ bool bf_positive(uint16_t b) { return b != 0 && !(b & 0x8000u); }
+
+typedef float floatx2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+// bf16(lo) | bf16(hi) << 16, nearest even (one v_cvt_pk_bf16_f32); the same
+// values as f2bf for every non-NaN input.
+__device__ __forceinline__ uint32_t f2bf2(float lo, float hi) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(floatx2{lo, hi}, bf16x2));
+}
 
 __device__ __forceinline__ floatx4 mfma(u32x4 a, u32x4 b, floatx4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
@@ -135,120 +144,364 @@ __global__ __launch_bounds__(256) void count_cells_kernel(const float *__restric
 // Forward
 // ---------------------------------------------------------------------------
 
-// First layer (one input channel): per output pixel, 9 taps x 16 channels on
-// the vector ALU.  x: tiles [n][256][512]; w: packed [16][32] (k = tap).
-__global__ __launch_bounds__(256) void conv0_fwd_kernel(const uint16_t *__restrict__ x,
-                                                        const float *__restrict__ w0f,
-                                                        const float *__restrict__ bias,
-                                                        uint16_t *__restrict__ y, int64_t npix) {
-  constexpr Layer L = kLayers[0];
-  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (p >= npix) return;
-  const int64_t n = p / (L.hout * L.wout);
-  const int r = (int)(p - n * L.hout * L.wout);
-  const int oy = r / L.wout, ox = r % L.wout;
-  float xv[9];
-#pragma unroll
-  for (int t = 0; t < 9; ++t) {
-    const int iy = 2 * oy + t / 3 - 1, ix = 2 * ox + t % 3 - 1;
-    xv[t] = (iy >= 0 && iy < L.hin && ix >= 0 && ix < L.win)
-                ? bf2f(x[(n * L.hin + iy) * L.win + ix])
-                : 0.0f;
+// Forward of layers 1..5 as an implicit GEMM with the input staged in LDS
+// (M = output pixels, N = COUT, K = taps x CIN, the same K order as
+// conv_fwd_kernel, so every output sums the same products in the same
+// order).  A workgroup of 4 waves computes a BH x BW block (BW a multiple
+// of 16: one row of 16 pixels per A row block) of one tile for all COUT
+// channels.  Its input region ((BH-1)S+3) x ((BW-1)S+3), zero outside the
+// image, is loaded once into LDS as S*S stride-parity planes with CIN+8
+// bf16 per pixel: the 16 pixels of an A row block then read consecutive
+// pixels of one plane, 16 bytes each at a stride of CIN+8 bf16, which puts
+// them on distinct banks.  Waves split the block into WM x WN (row blocks x
+// channel blocks); each wave loads its weight fragments from global memory
+// (L2) one K step ahead of their use.  The output block is staged in LDS
+// and written with 16-byte stores.
+// FUSE0 (layer 1 only): the staged region is layer 0's output, computed in
+// the workgroup from the tile (one 16x16x32 product per 16 pixels, K = the
+// 9 taps), so layer 0's activation never leaves the chip; STORE0 also
+// writes the block's own layer-0 pixels (the training pass needs them).
+// Weight fragments the forward kernel keeps in flight per wave (K steps
+// ahead = this / fragments per step).
+constexpr int kFwdPrefetch = 16;
+
+template <int LI, int BH, int BW>
+struct FwdGeom {
+  static constexpr Layer L = kLayers[LI];
+  static constexpr int CIN = L.cin, COUT = L.cout, S = L.stride;
+  static constexpr int KPAD = (9 * CIN + 31) / 32 * 32;
+  static constexpr int IH = (BH - 1) * S + 3, IW = (BW - 1) * S + 3;
+  static constexpr int PH = (IH + S - 1) / S, PW = (IW + S - 1) / S;
+  static constexpr int CP = CIN + 8;
+  static constexpr int PLANE = PH * PW * CP;
+  static constexpr int HALO = S * S * PLANE;
+  static constexpr int OUTP = COUT + 8;
+  static constexpr int OUT = BH * BW * OUTP;
+  // Tile region of a fused layer 0: TH x TW values, staged from an even
+  // column as pairs (dwords), TP of them holding data per row.  Layer 0
+  // reads a pixel's taps as rows of dword pairs with JB blocks of 16 lanes
+  // per region row, so staged rows are TPP dwords long and one zero row
+  // follows the region: every read stays inside the staged tile.
+  static constexpr int TH = 2 * IH + 1, TW = 2 * IW + 1;
+  static constexpr int TP = (TW + 2) / 2, JB = (IW + 15) / 16;
+  static constexpr int TPP = TP > 16 * JB + 2 ? TP : 16 * JB + 2;
+  static constexpr int TROWS = TH + 1;
+  static constexpr int TILE = 2 * TROWS * TPP;  // bf16
+  // LDS (bf16 elements): the halo, or with FUSE0 the halo and the tile
+  // region; the output staging reuses the same space
+  static constexpr int lds(bool fuse0) {
+    const int a = HALO + (fuse0 ? TILE : 0);
+    return a > OUT ? a : OUT;
   }
-  // weights and biases are wave-uniform: scalar loads, one fused
-  // multiply-add per tap and channel
-  uint32_t packed[8];
+  // LDS offset (bf16) of staged input pixel (hy, hx) of the region
+  __device__ static constexpr int at(int hy, int hx) {
+    return ((hy % S) * S + (hx % S)) * PLANE + ((hy / S) * PW + hx / S) * CP;
+  }
+};
+
+template <int LI, int BH, int BW, int WM, int WN, bool FUSE0, bool STORE0>
+__global__ __launch_bounds__(256) void conv_fwd_lds_kernel(
+    const uint16_t *__restrict__ x, const uint16_t *__restrict__ wp,
+    const float *__restrict__ bias, uint16_t *__restrict__ y, const float *__restrict__ w0f,
+    const float *__restrict__ b0, uint16_t *__restrict__ y0, int n) {
+  using G = FwdGeom<LI, BH, BW>;
+  constexpr Layer L = G::L;
+  constexpr Layer L0 = kLayers[0];
+  constexpr int CIN = G::CIN, COUT = G::COUT, S = G::S, KPAD = G::KPAD;
+  constexpr int IH = G::IH, IW = G::IW;
+  constexpr int MBLK = BH * BW / 16, NBLK = COUT / 16;
+  constexpr int MB = MBLK / WM, NB = NBLK / WN;
+  static_assert(WM * WN == 4 && MBLK % WM == 0 && NBLK % WN == 0, "four waves, even split");
+  static_assert(BW == 16 && L.hout % BH == 0 && L.wout % BW == 0, "whole blocks, 16 wide");
+  static_assert(!FUSE0 || LI == 1, "layer 0 fuses into layer 1 only");
+  extern __shared__ __attribute__((aligned(16))) uint16_t lds[];
+  constexpr int BX = L.wout / BW, BPT = (L.hout / BH) * BX;  // blocks per tile
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, px = lane & 15;
+  const int wv = __builtin_amdgcn_readfirstlane(wave);
+  const int total = n * BPT;
+
+  // ---- staging: the next block's loads go to registers while the current
+  // block is computed; every load is issued (outside pixels read a pixel of
+  // the tile and are zeroed), so none waits behind a branch ----
+  // fused layer 0: tile pixels (2 (iy0 + hy) + ky - 1, 2 (ix0 + hx) + kx - 1),
+  // staged from column 2 ix0 - 2 (even) as pairs: a pair is wholly inside or
+  // wholly outside the tile, whose width is even
+  constexpr int TP = G::TP, TPP = G::TPP;
+  constexpr int NSV = FUSE0 ? G::TROWS * TPP : IH * IW * (CIN / 8);  // staged items
+  constexpr int PER = (NSV + 255) / 256;
+  using Item = typename std::conditional<FUSE0, uint32_t, u32x4>::type;
+  Item sv[PER];
+  auto stage_load = [&](int blk) {
+    const int64_t tile = blk / BPT;
+    const int bi = blk - (int)tile * BPT;
+    const int iy0 = (bi / BX) * BH * S - 1, ix0 = (bi % BX) * BW * S - 1;
 #pragma unroll
-  for (int c = 0; c < 16; c += 2) {
-    float s0 = bias[c], s1 = bias[c + 1];
-#pragma unroll
-    for (int t = 0; t < 9; ++t) {
-      s0 = fmaf(w0f[c * 9 + t], xv[t], s0);
-      s1 = fmaf(w0f[(c + 1) * 9 + t], xv[t], s1);
+    for (int r = 0; r < PER; ++r) {
+      const int i = threadIdx.x + 256 * r;
+      if constexpr (FUSE0) {
+        const int row = i / TPP, pc = i - row * TPP;
+        const int ty = 2 * iy0 - 1 + row, tx = 2 * ix0 - 2 + 2 * pc;
+        const bool in = i < NSV && row < G::TH && pc < TP && ty >= 0 && ty < L0.hin && tx >= 0 &&
+                        tx < L0.win;
+        const int64_t o = in ? (tile * L0.hin + ty) * L0.win + tx : tile * L0.hin * L0.win;
+        sv[r] = *reinterpret_cast<const uint32_t *>(x + o);
+        if (!in) sv[r] = 0u;
+      } else {
+        constexpr int V = CIN / 8;  // 16-byte vectors per pixel
+        const int pix = i / V, v = i - pix * V;
+        const int hy = pix / IW, hx = pix - hy * IW;
+        const int yy = iy0 + hy, xx = ix0 + hx;
+        const bool in = i < NSV && yy >= 0 && yy < L.hin && xx >= 0 && xx < L.win;
+        const int64_t o = in ? ((tile * L.hin + yy) * L.win + xx) * CIN + 8 * v
+                             : tile * L.hin * L.win * CIN;
+        sv[r] = *reinterpret_cast<const u32x4 *>(x + o);
+        if (!in) sv[r] = u32x4{0u, 0u, 0u, 0u};
+      }
     }
-    packed[c / 2] = (uint32_t)f2bf(fmaxf(s0, 0.0f)) | ((uint32_t)f2bf(fmaxf(s1, 0.0f)) << 16);
+  };
+  auto stage_store = [&]() {
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int i = threadIdx.x + 256 * r;
+      if (i < NSV) {
+        if constexpr (FUSE0) {
+          reinterpret_cast<uint32_t *>(lds + G::HALO)[i] = sv[r];
+        } else {
+          constexpr int V = CIN / 8;
+          const int pix = i / V, v = i - pix * V;
+          const int hy = pix / IW, hx = pix - hy * IW;
+          *reinterpret_cast<u32x4 *>(lds + G::at(hy, hx) + 8 * v) = sv[r];
+        }
+      }
+    }
+  };
+
+  // ---- fused layer 0 constants: per 16 region pixels one 16x16x32 product
+  // with M = the 16 channels, N = the pixels, K = (tap row ky, staged column
+  // c) as 4 ky + c for ky < 3, c < 4, where staged columns 2 hx .. 2 hx + 3
+  // of a pixel are its taps kx = c - 1 (c = 0 has weight 0), so a pixel's K
+  // values are two aligned dword pairs of the staged tile ----
+  u32x4 wa = {0u, 0u, 0u, 0u};  // A: row px = channel, K values 8g .. 8g + 7
+  float bch[4] = {0.f, 0.f, 0.f, 0.f};
+  if constexpr (FUSE0) {
+    float wvv[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = 8 * g + j, ky = k >> 2, c = k & 3;
+      const bool use = ky < 3 && c > 0;
+      wvv[j] = w0f[px * 9 + (use ? ky * 3 + c - 1 : 0)];
+      if (!use) wvv[j] = 0.0f;
+    }
+    uint32_t h[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) h[j] = (uint32_t)f2bf(wvv[j]);
+    wa = u32x4{h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16)};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) bch[j] = b0[4 * g + j];
   }
-  u32x4 *dst = reinterpret_cast<u32x4 *>(y + p * 16);
-  dst[0] = u32x4{packed[0], packed[1], packed[2], packed[3]};
-  dst[1] = u32x4{packed[4], packed[5], packed[6], packed[7]};
+
+  // ---- main product constants: M = output channels (weights), N = pixels,
+  // so that a lane ends with 4 consecutive channels of one pixel ----
+  const int wm = wave / WN, wn = wave % WN;
+  const uint16_t *wrow = wp + (int64_t)(wn * NB * 16 + px) * KPAD + 8 * g;
+  const uint16_t *abase = lds + G::at(S * (wm * MB), S * px) + 8 * g;
+  constexpr int ROWSTEP = G::PW * G::CP;  // next output row: one plane row further
+  auto tap_off = [](int t) {
+    const int ky = t / 3, kx = t % 3;
+    return ((ky % S) * S + (kx % S)) * G::PLANE + ((ky / S) * G::PW + kx / S) * G::CP;
+  };
+  constexpr int NSTEP = KPAD / 32;
+  constexpr int PFW = kFwdPrefetch / NB > 1 ? kFwdPrefetch / NB : 1;
+  constexpr int PF = NSTEP < PFW ? NSTEP : PFW;
+  auto load_a = [&](int st, u32x4 (&a)[MB]) {
+    const int k0 = 32 * st;
+    int off;
+    bool live = true;
+    if constexpr (CIN >= 32) {
+      off = tap_off(k0 / CIN) + k0 % CIN;  // one tap for the whole step
+    } else {
+      // CIN == 16: lanes g < 2 take tap k0 / 16, lanes g >= 2 the next one
+      const int t0 = k0 / CIN, t1 = t0 + 1;
+      live = g < 2 || t1 < 9;
+      off = g < 2 ? tap_off(t0) : (t1 < 9 ? tap_off(t1) : 0) - 16;
+    }
+#pragma unroll
+    for (int i = 0; i < MB; ++i) {
+      a[i] = *reinterpret_cast<const u32x4 *>(abase + off + i * ROWSTEP);
+      if constexpr (CIN < 32) {
+        if (!live) a[i] = u32x4{0u, 0u, 0u, 0u};
+      }
+    }
+  };
+
+  // one block: stage it (its loads were issued before), compute, write
+  auto process = [&](int blk) {
+    const int64_t tile = blk / BPT;
+    const int bi = blk - (int)tile * BPT;
+    const int oy0 = (bi / BX) * BH, ox0 = (bi % BX) * BW;
+    const int iy0 = oy0 * S - 1, ix0 = ox0 * S - 1;  // input pixel of region (0, 0)
+    stage_store();
+    __syncthreads();
+    // persistent (fused layer 0, whose staging is a few registers): the
+    // next block's loads are in flight meanwhile
+    if constexpr (FUSE0)
+      if (blk + (int)gridDim.x < total) stage_load(blk + gridDim.x);
+
+    if constexpr (FUSE0) {
+      // Layer 0 on the matrix cores.  Region rows are dealt to the waves
+      // (row hy is wave-uniform); a row's IW pixels are JB blocks of 16
+      // lanes, the lanes past IW idle.  K positions without a tap (groups
+      // 2, 3 and the upper half of group 1) meet zero weights; the values
+      // read there are staged tile values (finite), so they add exact
+      // zeros.  Lanes past the row read inside the staged row (TPP >= 16 JB
+      // + 2 dwords) and their columns are not stored; group 1's second row,
+      // 2 hy + 3, is at most the zero row.  Pixels outside layer 0's output
+      // (the next layer's zero padding) are stored as zeros.
+      constexpr int JB = G::JB;
+      const uint32_t *t32 =
+          reinterpret_cast<const uint32_t *>(lds + G::HALO) + 2 * (g & 1) * TPP + px;
+      uint16_t *dcol = lds + (px & 1) * G::PLANE + (px >> 1) * G::CP + 4 * g;
+      bool xin[JB], lane_on[JB];
+#pragma unroll
+      for (int j = 0; j < JB; ++j) {
+        const int hx = 16 * j + px, xx = ix0 + hx;
+        lane_on[j] = hx < IW;
+        xin[j] = hx < IW && xx >= 0 && xx < L0.wout;
+      }
+      for (int hy = wv; hy < IH; hy += 4) {
+        const int yy = iy0 + hy;
+        const bool row_in = yy >= 0 && yy < L0.hout;
+        const uint32_t *rrow = t32 + 2 * hy * TPP;  // staged rows 2 hy + 2 (g & 1), + 1
+        u32x4 tb[JB];
+#pragma unroll
+        for (int j = 0; j < JB; ++j)
+          tb[j] = u32x4{rrow[16 * j], rrow[16 * j + 1], rrow[TPP + 16 * j], rrow[TPP + 16 * j + 1]};
+        floatx4 dl[JB];  // every product first, then the stores
+#pragma unroll
+        for (int j = 0; j < JB; ++j) dl[j] = mfma(wa, tb[j], floatx4{0.f, 0.f, 0.f, 0.f});
+        uint16_t *drow = dcol + (hy & 1) * S * G::PLANE + (hy >> 1) * G::PW * G::CP;
+#pragma unroll
+        for (int j = 0; j < JB; ++j) {
+          if (lane_on[j]) {
+            const floatx4 d = dl[j];
+            uint32_t pk[2] = {0u, 0u};
+            if (row_in && xin[j]) {
+              pk[0] = f2bf2(fmaxf(d[0] + bch[0], 0.0f), fmaxf(d[1] + bch[1], 0.0f));
+              pk[1] = f2bf2(fmaxf(d[2] + bch[2], 0.0f), fmaxf(d[3] + bch[3], 0.0f));
+            }
+            uint32_t *dst = reinterpret_cast<uint32_t *>(drow + 8 * j * G::CP);
+            dst[0] = pk[0];
+            dst[1] = pk[1];
+          }
+        }
+      }
+      __syncthreads();
+      if constexpr (STORE0) {
+        // the block's own layer-0 pixels (the region without its first row
+        // and column), copied out of the staged region with 16-byte stores
+        constexpr int OWN = (IH - 1) * (IW - 1);
+        for (int i = threadIdx.x; i < OWN * 2; i += 256) {
+          const int pix = i >> 1, half = i & 1;
+          const int hy = 1 + pix / (IW - 1), hx = 1 + pix % (IW - 1);
+          const int yy = iy0 + hy, xx = ix0 + hx;
+          if (yy < L0.hout && xx < L0.wout)
+            reinterpret_cast<u32x4 *>(y0 + ((tile * L0.hout + yy) * L0.wout + xx) * 16)[half] =
+                reinterpret_cast<const u32x4 *>(lds + G::at(hy, hx))[half];
+        }
+      }
+    }
+
+    // ---- the main product, fully unrolled (tap and channel of every K step
+    // are constants; LDS reads take immediate offsets from one base per
+    // lane), as a software pipeline pinned with scheduling barriers (left
+    // alone, the compiler moves each load next to its use): weight fragments
+    // PF K steps ahead in a ring of registers, A fragments one step ahead ----
+    floatx4 acc[MB][NB];
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) acc[i][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+    u32x4 ring[PF][NB];
+#pragma unroll
+    for (int u = 0; u < PF; ++u)
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+        ring[u][b] = *reinterpret_cast<const u32x4 *>(wrow + (int64_t)b * 16 * KPAD + 32 * u);
+    u32x4 acur[MB];
+    load_a(0, acur);
+#pragma unroll
+    for (int st = 0; st < NSTEP; ++st) {
+      u32x4 bv[NB];
+#pragma unroll
+      for (int b = 0; b < NB; ++b) bv[b] = ring[st % PF][b];
+      if (st + PF < NSTEP) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+          ring[st % PF][b] =
+              *reinterpret_cast<const u32x4 *>(wrow + (int64_t)b * 16 * KPAD + 32 * (st + PF));
+      }
+      u32x4 anext[MB];
+      if (st + 1 < NSTEP) load_a(st + 1, anext);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[i][b] = mfma(bv[b], acur[i], acc[i][b]);
+      __builtin_amdgcn_sched_barrier(0);
+      if (st + 1 < NSTEP) {
+#pragma unroll
+        for (int i = 0; i < MB; ++i) acur[i] = anext[i];
+      }
+    }
+
+    // ---- bias, ReLU, bf16 (8 bytes per lane and block pair); staged in
+    // LDS, written with 16-byte stores ----
+    __syncthreads();  // every wave is done with the staged input
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int co = (wn * NB + b) * 16 + 4 * g;  // channels co .. co + 3
+      const float b0v = bias[co], b1v = bias[co + 1], b2v = bias[co + 2], b3v = bias[co + 3];
+#pragma unroll
+      for (int i = 0; i < MB; ++i) {
+        const int m = (wm * MB + i) * 16 + px;  // pixel of the block (row-major)
+        const floatx4 a = acc[i][b];
+        uint32_t *dst = reinterpret_cast<uint32_t *>(lds + m * G::OUTP + co);
+        dst[0] = f2bf2(fmaxf(a[0] + b0v, 0.0f), fmaxf(a[1] + b1v, 0.0f));
+        dst[1] = f2bf2(fmaxf(a[2] + b2v, 0.0f), fmaxf(a[3] + b3v, 0.0f));
+      }
+    }
+    __syncthreads();
+    constexpr int V = COUT / 8;
+    for (int i = threadIdx.x; i < BH * BW * V; i += 256) {
+      const int m = i / V, v = i % V;
+      const int oy = oy0 + m / BW, ox = ox0 + m % BW;
+      *reinterpret_cast<u32x4 *>(y + ((tile * L.hout + oy) * L.wout + ox) * COUT + 8 * v) =
+          *reinterpret_cast<const u32x4 *>(lds + m * G::OUTP + 8 * v);
+    }
+    __syncthreads();  // the staging of the next block overwrites this space
+  };
+
+  if constexpr (FUSE0) {
+    for (int blk = blockIdx.x; blk < total; blk += gridDim.x) {
+      if (blk == (int)blockIdx.x) stage_load(blk);
+      process(blk);
+    }
+  } else {
+    if ((int)blockIdx.x < total) {
+      stage_load(blockIdx.x);
+      process(blockIdx.x);
+    }
+  }
 }
 
-// Layers 1..5: implicit GEMM, M = output pixels, N = COUT, K = taps x CIN.
-// A workgroup of 4 waves covers 64 MB output pixels (16 MB per wave, in MB
-// blocks of 16) and all output channels.  Per 32-wide K step a wave loads
-// the NB weight fragments once and reuses them for its MB pixel blocks, so
-// the weight reads per MFMA fall MB-fold.  Each output's K steps are summed
-// in the same order whatever MB is.
-template <int LI, int MB>
-__global__ __launch_bounds__(256) void conv_fwd_kernel(const uint16_t *__restrict__ x,
-                                                       const uint16_t *__restrict__ wp,
-                                                       const float *__restrict__ bias,
-                                                       uint16_t *__restrict__ y, int64_t npix) {
-  constexpr Layer L = kLayers[LI];
-  constexpr int CIN = L.cin, COUT = L.cout, S = L.stride, NB = COUT / 16;
-  constexpr int KPAD = (9 * CIN + 31) / 32 * 32;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4;
-  const int64_t pbase = (int64_t)blockIdx.x * (64 * MB) + wave * (16 * MB);
-  int64_t n[MB];
-  int oy[MB], ox[MB];
-  bool valid[MB];
-#pragma unroll
-  for (int mb = 0; mb < MB; ++mb) {
-    const int64_t p = pbase + mb * 16 + (lane & 15);
-    valid[mb] = p < npix;
-    n[mb] = 0;
-    oy[mb] = ox[mb] = 0;
-    if (valid[mb]) {
-      n[mb] = p / (L.hout * L.wout);
-      const int r = (int)(p - n[mb] * L.hout * L.wout);
-      oy[mb] = r / L.wout;
-      ox[mb] = r % L.wout;
-    }
-  }
-  floatx4 acc[MB][NB];
-#pragma unroll
-  for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-    for (int b = 0; b < NB; ++b) acc[mb][b] = floatx4{0.f, 0.f, 0.f, 0.f};
-  const uint16_t *wrow = wp + (int64_t)(lane & 15) * KPAD + 8 * g;
-#pragma unroll 2
-  for (int k0 = 0; k0 < KPAD; k0 += 32) {
-    const int k = k0 + 8 * g;
-    const int tap = k / CIN, ci = k % CIN;
-    u32x4 bv[NB];
-#pragma unroll
-    for (int b = 0; b < NB; ++b)
-      bv[b] = *reinterpret_cast<const u32x4 *>(wrow + (int64_t)b * 16 * KPAD + k0);
-#pragma unroll
-    for (int mb = 0; mb < MB; ++mb) {
-      u32x4 av = {0u, 0u, 0u, 0u};
-      if (valid[mb] && tap < 9) {
-        const int iy = S * oy[mb] + tap / 3 - 1, ix = S * ox[mb] + tap % 3 - 1;
-        if (iy >= 0 && iy < L.hin && ix >= 0 && ix < L.win)
-          av = *reinterpret_cast<const u32x4 *>(x + ((n[mb] * L.hin + iy) * L.win + ix) * CIN + ci);
-      }
-#pragma unroll
-      for (int b = 0; b < NB; ++b) acc[mb][b] = mfma(av, bv[b], acc[mb][b]);
-    }
-  }
-#pragma unroll
-  for (int b = 0; b < NB; ++b) {
-    const int co = b * 16 + (lane & 15);
-    const float bb = bias[co];
-#pragma unroll
-    for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int64_t q = pbase + mb * 16 + 4 * g + j;
-        if (q < npix) y[q * COUT + co] = f2bf(fmaxf(acc[mb][b][j] + bb, 0.0f));
-      }
-  }
-}
-
-// Pixel blocks per wave of the forward kernel, per layer (entry 0 unused).
-// Measured at batch 256: forward 0.73 ms with 1 everywhere, 0.60 ms with
-// these; 8 blocks for layer 2 and 4 for layers 4-5 cost occupancy (0.71 ms).
-constexpr int kFwdMB[kNumLayers] = {1, 2, 4, 4, 2, 2};
+// Blocks and wave splits of the LDS-staged forward, per layer:
+// (BH, BW, WM, WN).
+#define SPS_FWD_LDS_CONFIGS(X) \
+  X(1, 16, 16, 4, 1)           \
+  X(2, 8, 16, 4, 1)            \
+  X(3, 4, 16, 1, 4)            \
+  X(4, 2, 16, 1, 4)            \
+  X(5, 4, 16, 1, 4)
 
 // ---------------------------------------------------------------------------
 // Head, loss and the signal entering the last 3x3 layer
@@ -826,25 +1079,54 @@ hipError_t pack_all(sps_cnn c, hipStream_t s) {
     if (e_ != hipSuccess) return cnn_dev_fail(e_, what); \
   } while (0)
 
-sps_status run_forward(sps_cnn c, const uint16_t *tiles, int32_t n, hipStream_t s) {
-  {
-    const int64_t np = npix_out(0, n);
-    hipLaunchKernelGGL(conv0_fwd_kernel, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s,
-                       tiles, c->w0f, c->params + layer_param_offset(0) + kLayers[0].wcount(),
-                       c->act[0], np);
+template <int LI, int BH, int BW, int WM, int WN, bool FUSE0, bool STORE0>
+hipError_t launch_fwd_lds(const uint16_t *x, const uint16_t *wp, const float *bias, uint16_t *y,
+                          const float *w0f, const float *b0, uint16_t *y0, int n, hipStream_t s) {
+  using G = FwdGeom<LI, BH, BW>;
+  const size_t lds = sizeof(uint16_t) * (size_t)G::lds(FUSE0);
+  auto kern = conv_fwd_lds_kernel<LI, BH, BW, WM, WN, FUSE0, STORE0>;
+  if (lds > 64 * 1024) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
   }
-#define SPS_FWD(LI)                                                                         \
-  {                                                                                         \
-    constexpr int MB = kFwdMB[LI];                                                          \
-    const int64_t np = npix_out(LI, n);                                                     \
-    hipLaunchKernelGGL((conv_fwd_kernel<LI, MB>), dim3((unsigned)((np + 64 * MB - 1) / (64 * MB))), \
-                       dim3(256), 0, s, c->act[LI - 1], c->wp[LI],                          \
-                       c->params + layer_param_offset(LI) + kLayers[LI].wcount(), c->act[LI], \
-                       np);                                                                 \
+  // fused layer 0: persistent, as many workgroups as are resident at once,
+  // each looping over blocks (the next block's loads overlap the current
+  // one's work); other layers: one block per workgroup
+  static int resident = FUSE0 ? 0 : 0x7FFFFFFF;  // per kernel instance
+  if (resident == 0) {
+    int per_cu = 0, dev = 0, cus = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, reinterpret_cast<const void *>(kern), 256, lds);
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    resident = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
   }
-  SPS_FWD(1) SPS_FWD(2) SPS_FWD(3) SPS_FWD(4) SPS_FWD(5)
-#undef SPS_FWD
-  SPS_LAUNCH_CHECK("forward launch");
+  const int64_t blocks = (int64_t)(G::L.hout / BH) * (G::L.wout / BW) * n;
+  const int grid = (int)(blocks < resident ? blocks : resident);
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), lds, s, x, wp, bias, y, w0f, b0, y0, n);
+  return hipGetLastError();
+}
+
+// Layers 0..5.  Layer 0 runs inside layer 1's workgroups; keep0: also
+// store layer 0's activation (training and read-back need it).
+sps_status run_forward(sps_cnn c, const uint16_t *tiles, int32_t n, hipStream_t s, bool keep0) {
+  const float *w0f = c->w0f, *b0 = c->params + layer_param_offset(0) + kLayers[0].wcount();
+  hipError_t e = hipSuccess;
+#define SPS_FWD_LAUNCH(LI, BH, BW, WM, WN)                                                   \
+  if (e == hipSuccess) {                                                                     \
+    const float *bias = c->params + layer_param_offset(LI) + kLayers[LI].wcount();          \
+    if (LI == 1 && keep0)                                                                    \
+      e = launch_fwd_lds<LI, BH, BW, WM, WN, LI == 1, true>(tiles, c->wp[LI], bias,          \
+                                                              c->act[LI], w0f, b0, c->act[0], n, s); \
+    else                                                                                     \
+      e = launch_fwd_lds<LI, BH, BW, WM, WN, LI == 1, false>(                                \
+          LI == 1 ? tiles : c->act[LI - 1], c->wp[LI], bias, c->act[LI], w0f, b0, c->act[0], n, s); \
+  }
+  SPS_FWD_LDS_CONFIGS(SPS_FWD_LAUNCH)
+#undef SPS_FWD_LAUNCH
+  if (e != hipSuccess) return cnn_dev_fail(e, "forward launch");
   return SPS_OK;
 }
 
@@ -1117,7 +1399,23 @@ sps_status sps_cnn_forward(sps_cnn c, const uint16_t *tiles, int32_t n, float *h
   sps_status r = check_batch(c, tiles, n);
   if (r != SPS_OK) return r;
   hipStream_t s = (hipStream_t)stream;
-  r = run_forward(c, tiles, n, s);
+  r = run_forward(c, tiles, n, s, true);
+  if (r != SPS_OK) return r;
+  r = run_head(c, nullptr, n, false, s);
+  if (r != SPS_OK) return r;
+  if (head) {
+    hipError_t e = hipMemcpyAsync(head, c->head, sizeof(float) * (size_t)n * kHead * kCells,
+                                  hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return cnn_dev_fail(e, "head copy");
+  }
+  return SPS_OK;
+}
+
+sps_status sps_cnn_infer(sps_cnn c, const uint16_t *tiles, int32_t n, float *head, void *stream) {
+  sps_status r = check_batch(c, tiles, n);
+  if (r != SPS_OK) return r;
+  hipStream_t s = (hipStream_t)stream;
+  r = run_forward(c, tiles, n, s, false);
   if (r != SPS_OK) return r;
   r = run_head(c, nullptr, n, false, s);
   if (r != SPS_OK) return r;
@@ -1135,7 +1433,7 @@ sps_status sps_cnn_loss_grad(sps_cnn c, const uint16_t *tiles, const float *labe
   if (r != SPS_OK) return r;
   if (!labels) return sps::set_error(SPS_ERR_INVALID_ARG, "NULL labels");
   hipStream_t s = (hipStream_t)stream;
-  r = run_forward(c, tiles, n, s);
+  r = run_forward(c, tiles, n, s, true);
   if (r == SPS_OK) r = run_head(c, labels, n, true, s);
   if (r == SPS_OK) r = run_backward(c, tiles, n, s);
   if (r != SPS_OK) return r;
@@ -1177,7 +1475,7 @@ sps_status sps_cnn_detect(sps_cnn c, const uint16_t *tiles, int32_t n, float thr
   if (cap < 0 || (cap > 0 && !out)) return sps::set_error(SPS_ERR_INVALID_ARG, "bad output array");
   if (!(threshold > 0.0f && threshold < 1.0f))
     return sps::set_error(SPS_ERR_INVALID_ARG, "threshold must be a probability in (0, 1)");
-  sps_status r = sps_cnn_forward(c, tiles, n, nullptr, stream);
+  sps_status r = sps_cnn_infer(c, tiles, n, nullptr, stream);
   if (r != SPS_OK) return r;
   std::vector<float> h((size_t)n * kHead * kCells);
   hipStream_t s = (hipStream_t)stream;
@@ -1218,7 +1516,7 @@ sps_status cnn_count_cells(sps_cnn c, const uint16_t *tiles, int32_t n, float th
   if (!count) return set_error(SPS_ERR_INVALID_ARG, "NULL count");
   if (!(threshold > 0.0f && threshold < 1.0f))
     return set_error(SPS_ERR_INVALID_ARG, "threshold must be a probability in (0, 1)");
-  r = run_forward(c, tiles, n, s);
+  r = run_forward(c, tiles, n, s, false);
   if (r != SPS_OK) return r;
   r = run_head(c, nullptr, n, false, s);
   if (r != SPS_OK) return r;

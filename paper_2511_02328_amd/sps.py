@@ -156,6 +156,7 @@ def library() -> ctypes.CDLL:
         lib.sps_cnn_max_batch.argtypes = [P]
         lib.sps_cnn_max_batch.restype = i32
         lib.sps_cnn_forward.argtypes = [P, P, i32, P, P]
+        lib.sps_cnn_infer.argtypes = [P, P, i32, P, P]
         lib.sps_cnn_loss_grad.argtypes = [P, P, P, i32, P, P]
         lib.sps_cnn_adam.argtypes = [P, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                      ctypes.c_float, P]
@@ -166,7 +167,7 @@ def library() -> ctypes.CDLL:
         for f in ("sps_cnn_create", "sps_cnn_destroy", "sps_cnn_set_params", "sps_cnn_get_params",
                   "sps_cnn_set_grads", "sps_cnn_get_grads", "sps_cnn_activations", "sps_cnn_signals",
                   "sps_cnn_set_loss_weights",
-                  "sps_cnn_pool_tiles", "sps_cnn_pool_tile_grid", "sps_cnn_forward", "sps_cnn_loss_grad", "sps_cnn_adam",
+                  "sps_cnn_pool_tiles", "sps_cnn_pool_tile_grid", "sps_cnn_forward", "sps_cnn_infer", "sps_cnn_loss_grad", "sps_cnn_adam",
                   "sps_cnn_train_step", "sps_cnn_detect"):
             getattr(lib, f).restype = ctypes.c_int
         for f in ("sps_server_create", "sps_server_destroy", "sps_server_add_stream",
@@ -828,6 +829,13 @@ def sps_cnn_forward(net: Cnn, tiles: torch.Tensor, n: int, head: Optional[torch.
     hp = _dev(head, torch.float32, "head") if head is not None else None
     _check(library().sps_cnn_forward(net.handle, _tiles_ptr(tiles), int(n), hp, _stream(stream)),
            "sps_cnn_forward")
+
+
+def sps_cnn_infer(net: Cnn, tiles: torch.Tensor, n: int, head: Optional[torch.Tensor] = None,
+                  stream=None) -> None:
+    hp = _dev(head, torch.float32, "head") if head is not None else None
+    _check(library().sps_cnn_infer(net.handle, _tiles_ptr(tiles), int(n), hp, _stream(stream)),
+           "sps_cnn_infer")
 
 
 def sps_cnn_loss_grad(net: Cnn, tiles: torch.Tensor, labels: torch.Tensor, n: int,

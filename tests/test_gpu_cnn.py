@@ -371,3 +371,26 @@ def test_forward_full_batch_sampled_tiles(sps):
         ref = np.einsum("kc,nchw->nkhw", wh, prev) + bh[None, :, None, None]
         mag = np.einsum("kc,nchw->nkhw", np.abs(wh), np.abs(prev)) + np.abs(bh)[None, :, None, None]
         assert np.all(np.abs(h[k:k + 1] - ref) <= 2 * 129 * U * mag + 1e-30), k
+
+
+def test_inference_path_matches_forward(sps, case):
+    # sps_cnn_infer computes layer 0 inside layer 1's workgroups without
+    # keeping it: head outputs and layer 1-5 activations must be identical
+    # to sps_cnn_forward's, on a batch with several tiles and workgroups
+    params, _, _ = case
+    tb, _ = _tiles(5, 31, positive=(1, 3))
+    n = tb.shape[0]
+    with sps.sps_cnn_create(8) as net:
+        sps.sps_cnn_set_params(net, _flat(params))
+        d = _to_dev_tiles(tb)
+        h1 = torch.zeros((n, 3, 8, 16), dtype=torch.float32, device="cuda")
+        h2 = torch.zeros_like(h1)
+        sps.sps_cnn_forward(net, d, n, h1)
+        torch.cuda.synchronize()
+        a1 = [sps.sps_cnn_activations(net, li, n) for li in range(1, len(cnn.LAYERS))]
+        sps.sps_cnn_infer(net, d, n, h2)
+        torch.cuda.synchronize()
+        a2 = [sps.sps_cnn_activations(net, li, n) for li in range(1, len(cnn.LAYERS))]
+    assert torch.equal(h1, h2)
+    for li, (x, y) in enumerate(zip(a1, a2), start=1):
+        assert np.array_equal(x, y), li
