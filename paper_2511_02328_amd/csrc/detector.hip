@@ -145,22 +145,23 @@ __global__ __launch_bounds__(256) void count_cells_kernel(const float *__restric
 // ---------------------------------------------------------------------------
 
 // Forward of layers 1..5 as an implicit GEMM with the input staged in LDS
-// (M = output pixels, N = COUT, K = taps x CIN, the same K order as
-// conv_fwd_kernel, so every output sums the same products in the same
-// order).  A workgroup of 4 waves computes a BH x BW block (BW a multiple
-// of 16: one row of 16 pixels per A row block) of one tile for all COUT
-// channels.  Its input region ((BH-1)S+3) x ((BW-1)S+3), zero outside the
+// (M = COUT, N = output pixels, K = taps x CIN in tap-major order, the
+// order of the packed weights).  A workgroup of 4 waves computes a BH x 16
+// block (one row of 16 pixels per N block) of one tile for all COUT
+// channels.  Its input region ((BH-1)S+3) x (15S+3), zero outside the
 // image, is loaded once into LDS as S*S stride-parity planes with CIN+8
-// bf16 per pixel: the 16 pixels of an A row block then read consecutive
-// pixels of one plane, 16 bytes each at a stride of CIN+8 bf16, which puts
-// them on distinct banks.  Waves split the block into WM x WN (row blocks x
-// channel blocks); each wave loads its weight fragments from global memory
-// (L2) one K step ahead of their use.  The output block is staged in LDS
-// and written with 16-byte stores.
+// bf16 per pixel: the 16 pixels of a block then read consecutive pixels of
+// one plane, 16 bytes each at a stride of CIN+8 bf16.  Waves split the block
+// into WM x WN (row blocks x channel blocks).  A lane ends with 4
+// consecutive channels of one pixel: bias, ReLU and bfloat16 are one packed
+// conversion pair and an 8-byte LDS store, and the block leaves through LDS
+// with 16-byte stores.
 // FUSE0 (layer 1 only): the staged region is layer 0's output, computed in
 // the workgroup from the tile (one 16x16x32 product per 16 pixels, K = the
 // 9 taps), so layer 0's activation never leaves the chip; STORE0 also
 // writes the block's own layer-0 pixels (the training pass needs them).
+// The fused kernel is persistent: each workgroup loops over blocks and
+// issues the next block's tile loads before working on the current one.
 // Weight fragments the forward kernel keeps in flight per wave (K steps
 // ahead = this / fragments per step).
 constexpr int kFwdPrefetch = 16;
