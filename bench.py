@@ -641,6 +641,39 @@ def bench_detector(args):
     e1.record(stream)
     e1.synchronize()
     search_ms = e0.elapsed_time(e1) / reps / fac.batch
+    # the detector path on the same batch: dedispersion, statistics and the
+    # boxcar pass writing the network's tiles directly (no S/N or width
+    # planes, no threshold search), then the network on those tiles
+    det_tiles = torch.empty((fac.batch, 256, 512), dtype=torch.int16, device="cuda")
+    ntl = sps.sps_batch_set_tiles(fac.handle, det_tiles, detector.TILE_SCALE)
+    assert ntl == fac.batch
+
+    def detector_path():
+        sps.sps_batch_launch_graph(fac.handle, stream)
+        sps.sps_cnn_infer(net, det_tiles, fac.batch, stream=stream)
+
+    for _ in range(2):
+        detector_path()
+    e0.record(stream)
+    for _ in range(reps):
+        detector_path()
+    e1.record(stream)
+    e1.synchronize()
+    det_path_ms = e0.elapsed_time(e1) / reps / fac.batch
+    # the same tiles as the search mode's planes pooled (what the network was
+    # trained and judged on)
+    sps.sps_batch_set_tiles(fac.handle, None)
+    sps.sps_batch_launch_graph(fac.handle, stream)
+    ref = torch.empty_like(det_tiles)
+    for i in range(fac.batch):
+        sps.sps_cnn_pool_tiles(fac.snr[i], fac.wl.nout, detector.TILE_SCALE, ref[i], stream=stream)
+    stream.synchronize()
+    sps.sps_batch_set_tiles(fac.handle, det_tiles, detector.TILE_SCALE)
+    sps.sps_batch_launch_graph(fac.handle, stream)
+    stream.synchronize()
+    tiles_identical = bool(torch.equal(ref, det_tiles))
+    sps.sps_batch_set_tiles(fac.handle, None)
+    dm_t_per_tile = fac.wl.ndm * fac.wl.nout
     flops = cnn_flops_per_tile()
     rec = {
         "metric": "detector training tiles/s", "value": tiles_trained / (train_ms / 1e3),
@@ -662,6 +695,14 @@ def bench_detector(args):
                      "traffic": None,
                      "work_per_launch": f"{flops * args.batch} FLOP per batch of {args.batch} tiles"},
         "search_ms_per_tile": search_ms, "cnn_ms_per_tile": fwd_ms / args.batch,
+        # end to end, one 64-beam batch of single-beam filterbanks per step
+        "end_to_end": {
+            "plain_search": {"ms_per_tile": search_ms, "tiles_per_s": 1e3 / search_ms,
+                             "dm_time_samples_per_s": dm_t_per_tile * 1e3 / search_ms},
+            "detector_path": {"ms_per_tile": det_path_ms, "tiles_per_s": 1e3 / det_path_ms,
+                              "dm_time_samples_per_s": dm_t_per_tile * 1e3 / det_path_ms},
+            "detector_path_over_plain": search_ms / det_path_ms,
+            "tiles_identical_to_pooled_planes": tiles_identical},
         "operating_point": operating,
         "vs_boxcar_by_rfi": {str(th): {g: {k: (round(v, 4) if isinstance(v, float) else v)
                                         for k, v in r.items()}

@@ -172,6 +172,19 @@ sps_status sps_search(sps_plan plan, const uint32_t *Y, int64_t nout, const int3
                       const sps_detect_params *params, sps_candidate *out, int32_t cap,
                       int32_t *n_found, void *stream);
 
+/* Statistics and boxcar S/N as in sps_boxcar_snr, but instead of the S/N
+ * and width planes the pass writes the learned detector's input tiles
+ * directly: the S/N of each whole tile of 512 trials x 4096 samples,
+ * max-pooled over 2 trials x 8 samples, times scale, rounded to bfloat16
+ * (nearest, ties to even) -- the tiles sps_cnn_pool_tile_grid makes from
+ * the S/N plane, bit for bit.  tiles: device bf16 [ntiles][256][512] in
+ * row-major tile order, ntiles = (ndm / 512) * (nout / 4096) (returned in
+ * *ntiles if not NULL); a ragged rest of the plane makes no tile.  stats
+ * as in sps_boxcar_snr.  Asynchronous. */
+sps_status sps_boxcar_pool(sps_plan plan, const uint32_t *Y, int64_t nout, const int32_t *widths,
+                           int32_t nw, int32_t *stats, float scale, uint16_t *tiles,
+                           int64_t *ntiles, void *stream);
+
 /* sps_detect for callers that cannot allocate device memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc):
  * the same arguments, checks, kernels and results, but the detection
@@ -311,8 +324,19 @@ sps_status sps_batch_launch_graph(sps_batch batch, void *stream);
 sps_status sps_batch_autotune(sps_batch batch, int32_t iters, void *stream, float *ms_out,
                               int32_t *n_tried);
 
+/* Tile mode: with tiles not NULL, every later enqueue or graph replay of
+ * the batch runs dedispersion and statistics as before, then writes the
+ * learned detector's input tiles straight from the boxcar pass (as
+ * sps_boxcar_pool does for one plane) instead of the beams' S/N and width
+ * planes and candidates: beam b's whole tiles follow those of beams < b in
+ * tiles (device bf16 [ntiles][256][512]).  *ntiles (if not NULL) receives
+ * the batch's tile count.  tiles NULL returns to the search mode.  A
+ * change of mode discards the captured graph.  Must not overlap a run of
+ * the batch. */
+sps_status sps_batch_set_tiles(sps_batch batch, uint16_t *tiles, float scale, int64_t *ntiles);
+
 /* Synchronises the stream and returns beam's candidates as sps_detect does
- * (same order, TRUNCATED / RANGE rules). */
+ * (same order, TRUNCATED / RANGE rules); INVALID_ARG in tile mode. */
 sps_status sps_batch_candidates(sps_batch batch, int32_t beam, sps_candidate *out, int32_t cap,
                                 int32_t *n_found, void *stream);
 

@@ -55,6 +55,10 @@ __device__ __forceinline__ uint32_t add3_u32(uint32_t a, uint32_t b, uint32_t c)
 // (outputs arrive in increasing t), and finish() reduces the workgroup to
 // one key and one atomic.  TILES = 2: any tiling; a thread flushes its
 // maximum with an atomic whenever its outputs enter the next tile column.
+// TILES = 3: tile_t and the row length multiples of 64, so the 64
+// consecutive outputs a wave handles at a time share one column, and its
+// lanes change column, and leave the last segment's loop, together: a
+// flush reduces the wave's keys and issues one atomic.
 template <int TILES>
 struct TileTrack {
   float s = -INFINITY;
@@ -75,11 +79,24 @@ struct TileTrack {
     return ((unsigned long long)snr_key_bits(s) << 32) | (unsigned long long)(~pos);
   }
   __device__ __forceinline__ void flush(const TileSink &k, int d, int64_t t0) {
-    if (s != -INFINITY)
-      atomicMax(k.keys + (int64_t)(d / k.tile_dm) * k.ntt + col, key(k, d, t0));
+    if constexpr (TILES == 3) {
+      unsigned long long v = s == -INFINITY ? 0ull : key(k, d, t0);
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t lo = __shfl_xor((uint32_t)v, o, 64);
+        const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), o, 64);
+        const unsigned long long u = ((unsigned long long)hi << 32) | lo;
+        v = u > v ? u : v;
+      }
+      if ((threadIdx.x & 63) == 0 && v != 0ull)
+        atomicMax(k.keys + (int64_t)(d / k.tile_dm) * k.ntt + col, v);
+    } else {
+      if (s != -INFINITY)
+        atomicMax(k.keys + (int64_t)(d / k.tile_dm) * k.ntt + col, key(k, d, t0));
+    }
   }
   __device__ __forceinline__ void add(const TileSink &k, int d, int64_t t0, float v, int t_local) {
-    if constexpr (TILES == 2) {
+    if constexpr (TILES >= 2) {
       if (t0 + t_local >= col_end) {
         flush(k, d, t0);
         col = (t0 + t_local) / k.tile_t;
@@ -113,10 +130,39 @@ struct TileTrack {
         for (int w = 1; w < kThreads / 64; ++w) v = red[w] > v ? red[w] : v;
         if (v != 0ull) atomicMax(k.keys + (int64_t)(d / k.tile_dm) * k.ntt + col, v);
       }
-    } else if constexpr (TILES == 2) {
+    } else if constexpr (TILES >= 2) {
       flush(k, d, t0);
     }
   }
+};
+
+// Where a segment's outputs go.  PlaneSink: the S/N and width planes, and
+// the tile maxima (TileTrack).  PoolSink: an LDS row of S/N values, for the
+// max-pooled detector tiles (first row of a pair stored, second maxed in).
+template <int TILES>
+struct PlaneSink {
+  SPS_GLOBAL float *srow;
+  SPS_GLOBAL uint8_t *brow;
+  const TileSink *tiles;
+  unsigned long long *red;
+  int d;
+  int64_t t0;
+  TileTrack<TILES> tr;
+  __device__ __forceinline__ void put(int tl, float v, int bi) {
+    srow[tl] = v;
+    brow[tl] = (uint8_t)bi;
+    tr.add(*tiles, d, t0, v, tl);
+  }
+  __device__ __forceinline__ void finish() { tr.finish(*tiles, d, t0, red); }
+};
+
+struct PoolSink {
+  float *pv;
+  bool first;
+  __device__ __forceinline__ void put(int tl, float v, int) {
+    pv[tl] = first ? v : fmaxf(pv[tl], v);
+  }
+  __device__ __forceinline__ void finish() {}
 };
 
 // Widths 1, 2, 4, ..., 2^(NPOW-1): window offsets are immediates of the LDS
@@ -128,13 +174,11 @@ struct TileTrack {
 // missing samples read as zero, widths that run past the row end are left
 // out of the maximum (as -inf; width 1 always fits), and outputs past the
 // row end are not written.
-template <int NPOW, bool TAIL, int TILES>
+template <int NPOW, bool TAIL, class Sink>
 __device__ __forceinline__ void pow2_segment(const SPS_GLOBAL uint32_t *src, int n_left,
                                              int32_t med, int32_t mad, const WidthList &widths,
-                                             float *scale, uint32_t *tmp, SPS_GLOBAL float *srow,
-                                             SPS_GLOBAL uint8_t *brow, uint32_t *P,
-                                             TileTrack<TILES> &tr, const TileSink &sink, int d,
-                                             int64_t t0) {
+                                             float *scale, uint32_t *tmp, uint32_t *P,
+                                             Sink &out) {
   constexpr int kLen = kSeg + (1 << (NPOW - 1)) - 1;
   constexpr int kLd = (kLen + kThreads - 1) / kThreads;
   constexpr int kCh = kLd | 1;
@@ -206,26 +250,20 @@ __device__ __forceinline__ void pow2_segment(const SPS_GLOBAL uint32_t *src, int
     int bi = NPOW - 1;
 #pragma unroll
     for (int i = NPOW - 2; i >= 0; --i) bi = s[i] == mx ? i : bi;
-    const float out = live ? mx : 0.0f;
-    srow[tl] = out;
-    brow[tl] = (uint8_t)bi;
-    tr.add(sink, d, t0, out, tl);
+    out.put(tl, live ? mx : 0.0f, bi);
   }
 }
 
 // NPOW > 0: power-of-two widths (pow2_segment); NPOW = 0: any width list.
-template <int NPOW, int TILES>
-__device__ __forceinline__ void boxcar_segment(const uint32_t *__restrict__ Y, int64_t nout, int d,
-                                               int seg, const int32_t *__restrict__ stats,
-                                               const WidthList &widths, float *__restrict__ snr,
-                                               uint8_t *__restrict__ best, uint32_t *P,
-                                               const TileSink &sink) {
+// One segment of row d: outputs [seg kSeg, seg kSeg + kSeg) go to `out`
+// (out.put(t - seg kSeg, S/N, width index)), then out.finish().
+template <int NPOW, class Sink>
+__device__ __forceinline__ void boxcar_core(const uint32_t *__restrict__ Y, int64_t nout, int d,
+                                            int seg, const int32_t *__restrict__ stats,
+                                            const WidthList &widths, uint32_t *P, Sink &out) {
   __shared__ float scale[kMaxWidths];
   __shared__ uint32_t tmp[4];
-  __shared__ unsigned long long red[kThreads / 64];
   const int64_t t0 = (int64_t)seg * kSeg;
-  TileTrack<TILES> tr;
-  tr.begin(sink, t0);
   const SPS_GLOBAL uint32_t *row = gmem(Y + (int64_t)d * nout);
   const int nw = widths.n;
   const int wmax = widths.w[nw - 1];
@@ -243,15 +281,11 @@ __device__ __forceinline__ void boxcar_segment(const uint32_t *__restrict__ Y, i
 
   if constexpr (NPOW > 0) {
     constexpr int kLen = kSeg + (1 << (NPOW - 1)) - 1;
-    SPS_GLOBAL float *srow = gmem(snr + (int64_t)d * nout + t0);
-    SPS_GLOBAL uint8_t *brow = gmem(best + (int64_t)d * nout + t0);
     if (avail >= (int64_t)kLen)
-      pow2_segment<NPOW, false, TILES>(row + t0, kLen, med, mad, widths, scale, tmp, srow, brow,
-                                       P, tr, sink, d, t0);
+      pow2_segment<NPOW, false>(row + t0, kLen, med, mad, widths, scale, tmp, P, out);
     else
-      pow2_segment<NPOW, true, TILES>(row + t0, (int)avail, med, mad, widths, scale, tmp, srow,
-                                      brow, P, tr, sink, d, t0);
-    tr.finish(sink, d, t0, red);
+      pow2_segment<NPOW, true>(row + t0, (int)avail, med, mad, widths, scale, tmp, P, out);
+    out.finish();
     return;
   }
 
@@ -275,8 +309,6 @@ __device__ __forceinline__ void boxcar_segment(const uint32_t *__restrict__ Y, i
   __syncthreads();
 
   const int seg_len = avail < kSeg ? (int)avail : kSeg;
-  SPS_GLOBAL float *srow = gmem(snr + (int64_t)d * nout + t0);
-  SPS_GLOBAL uint8_t *brow = gmem(best + (int64_t)d * nout + t0);
   const bool live = mad > 0;
 
   if (avail >= (int64_t)(kSeg + wmax - 1)) {
@@ -301,12 +333,9 @@ __device__ __forceinline__ void boxcar_segment(const uint32_t *__restrict__ Y, i
           bi = i;
         }
       }
-      const float out = live ? bs : 0.0f;
-      srow[tl] = out;
-      brow[tl] = (uint8_t)bi;
-      tr.add(sink, d, t0, out, tl);
+      out.put(tl, live ? bs : 0.0f, bi);
     }
-    tr.finish(sink, d, t0, red);
+    out.finish();
     return;
   }
 
@@ -328,12 +357,47 @@ __device__ __forceinline__ void boxcar_segment(const uint32_t *__restrict__ Y, i
         bi = i;
       }
     }
-    const float out = bi == 0xFF ? 0.0f : bs;
-    srow[tl] = out;
-    brow[tl] = (uint8_t)bi;
-    tr.add(sink, d, t0, out, tl);
+    out.put(tl, bi == 0xFF ? 0.0f : bs, bi);
   }
-  tr.finish(sink, d, t0, red);
+  out.finish();
+}
+
+// The S/N and width planes of one segment, with the tile maxima.
+template <int NPOW, int TILES>
+__device__ __forceinline__ void boxcar_segment(const uint32_t *__restrict__ Y, int64_t nout, int d,
+                                               int seg, const int32_t *__restrict__ stats,
+                                               const WidthList &widths, float *__restrict__ snr,
+                                               uint8_t *__restrict__ best, uint32_t *P,
+                                               const TileSink &sink) {
+  __shared__ unsigned long long red[kThreads / 64];
+  const int64_t t0 = (int64_t)seg * kSeg;
+  PlaneSink<TILES> out{gmem(snr + (int64_t)d * nout + t0), gmem(best + (int64_t)d * nout + t0),
+                       &sink, red, d, t0, TileTrack<TILES>{}};
+  out.tr.begin(sink, t0);
+  boxcar_core<NPOW>(Y, nout, d, seg, stats, widths, P, out);
+}
+
+// Trials d, d + 1 of one segment pooled over 2 trials x 8 samples, scaled
+// and rounded to bfloat16: pooled[t / 8] of the segment, 512 values (the
+// same S/N values the planes would hold; pooling as the tile kernels do).
+template <int NPOW>
+__device__ __forceinline__ void boxcar_pool_pair(const uint32_t *__restrict__ Y, int64_t nout,
+                                                 int d, int seg, const int32_t *__restrict__ stats,
+                                                 const WidthList &widths, uint32_t *P, float *pv,
+                                                 float scale, uint16_t *__restrict__ pooled) {
+  PoolSink first{pv, true};
+  boxcar_core<NPOW>(Y, nout, d, seg, stats, widths, P, first);
+  __syncthreads();  // P is refilled for the second trial
+  PoolSink second{pv, false};
+  boxcar_core<NPOW>(Y, nout, d + 1, seg, stats, widths, P, second);
+  __syncthreads();
+  for (int j = threadIdx.x; j < kSeg / 8; j += kThreads) {
+    float m = pv[8 * j];
+#pragma unroll
+    for (int b = 1; b < 8; ++b) m = fmaxf(m, pv[8 * j + b]);
+    const uint32_t u = __float_as_uint(m * scale);
+    pooled[j] = (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);  // nearest even
+  }
 }
 
 template <int NPOW, int TILES>
@@ -426,11 +490,45 @@ __global__ __launch_bounds__(kThreads) void tile_keys_batch_kernel(
            i - bw.tp_begin, decode != 0);
 }
 
+// Detector tiles straight from the boxcar: one workgroup per (trial pair,
+// segment) of the whole tiles (512 trials x 4096 samples) of a plane; tile
+// (ti, tj) is tiles[ti * ncols + tj], pooled row i of a tile from trials
+// 512 ti + 2i, + 1.
+template <int NPOW>
+__global__ __launch_bounds__(kThreads) void boxcar_pool_kernel(
+    const uint32_t *__restrict__ Y, int64_t nout, int ncols, const int32_t *__restrict__ stats,
+    WidthList widths, float scale, uint16_t *__restrict__ tiles) {
+  extern __shared__ uint32_t P[];  // [kSeg + w_max]
+  __shared__ float pv[kSeg];
+  const int64_t blk = blockIdx.x;
+  const int pair = (int)(blk / ncols), tj = (int)(blk - (int64_t)pair * ncols);
+  const int d = 2 * pair, ti = d / kPoolTileDm, i = (d % kPoolTileDm) / 2;
+  uint16_t *pooled = tiles + (((int64_t)ti * ncols + tj) * (kPoolTileDm / 2) + i) * (kSeg / 8);
+  boxcar_pool_pair<NPOW>(Y, nout, d, tj, stats, widths, P, pv, scale, pooled);
+}
+
+template <int NPOW>
+__global__ __launch_bounds__(kThreads) void boxcar_pool_batch_kernel(
+    const BeamWork *__restrict__ beams, int nbeams, WidthList widths, float scale,
+    uint16_t *__restrict__ tiles) {
+  extern __shared__ uint32_t P[];
+  __shared__ float pv[kSeg];
+  const int64_t blk = blockIdx.x;
+  const BeamWork &bw = beams[find_beam<&BeamWork::pl_begin>(beams, nbeams, blk)];
+  const int64_t local = blk - bw.pl_begin;
+  const int ncols = (int)bw.pcols;
+  const int pair = (int)(local / ncols), tj = (int)(local - (int64_t)pair * ncols);
+  const int d = 2 * pair, ti = d / kPoolTileDm, i = (d % kPoolTileDm) / 2;
+  uint16_t *pooled = tiles + ((bw.tile_begin + (int64_t)ti * ncols + tj) * (kPoolTileDm / 2) + i) *
+                                 (kSeg / 8);
+  boxcar_pool_pair<NPOW>(bw.Y, bw.nout, d, tj, bw.stats, widths, P, pv, scale, pooled);
+}
+
 // 0: no tile maxima; 1: every segment inside one tile column (tile_t a
 // multiple of the segment length); 2: any tiling.
-int tile_mode(const void *keys, int64_t tile_t) {
+int tile_mode(const void *keys, int64_t tile_t, bool rows_of_64) {
   if (!keys) return 0;
-  return tile_t % kSeg == 0 ? 1 : 2;
+  return tile_t % kSeg == 0 ? 1 : (tile_t % 64 == 0 && rows_of_64 ? 3 : 2);
 }
 
 }  // namespace
@@ -445,7 +543,7 @@ hipError_t launch_boxcar(const uint32_t *Y, int ndm, int64_t nout, const int32_t
   const size_t lds = (size_t)(kSeg + widths.w[widths.n - 1] + 1) * sizeof(uint32_t);
   bool pow2 = widths.n <= 13;
   for (int i = 0; i < widths.n && pow2; ++i) pow2 = widths.w[i] == (1 << i);
-  const int tm = tile_mode(sink.keys, sink.tile_t);
+  const int tm = tile_mode(sink.keys, sink.tile_t, nout % 64 == 0);
 #define SPS_BOXCAR_LAUNCH(n_, t_)                                                          \
   hipLaunchKernelGGL((boxcar_kernel<n_, t_>), dim3((unsigned)grid), dim3(kThreads), lds, stream, \
                      Y, nout, (int)nseg, stats, widths, snr, best, sink)
@@ -453,6 +551,7 @@ hipError_t launch_boxcar(const uint32_t *Y, int ndm, int64_t nout, const int32_t
   if (pow2 && widths.n == n_) {                             \
     if (tm == 0) SPS_BOXCAR_LAUNCH(n_, 0);                  \
     else if (tm == 1) SPS_BOXCAR_LAUNCH(n_, 1);             \
+    else if (tm == 3) SPS_BOXCAR_LAUNCH(n_, 3);             \
     else SPS_BOXCAR_LAUNCH(n_, 2);                          \
     return hipGetLastError();                               \
   }
@@ -461,6 +560,7 @@ hipError_t launch_boxcar(const uint32_t *Y, int ndm, int64_t nout, const int32_t
   SPS_BOXCAR_CASE(11) SPS_BOXCAR_CASE(12) SPS_BOXCAR_CASE(13)
   if (tm == 0) SPS_BOXCAR_LAUNCH(0, 0);
   else if (tm == 1) SPS_BOXCAR_LAUNCH(0, 1);
+  else if (tm == 3) SPS_BOXCAR_LAUNCH(0, 3);
   else SPS_BOXCAR_LAUNCH(0, 2);
 #undef SPS_BOXCAR_CASE
 #undef SPS_BOXCAR_LAUNCH
@@ -469,13 +569,13 @@ hipError_t launch_boxcar(const uint32_t *Y, int ndm, int64_t nout, const int32_t
 
 hipError_t launch_boxcar_batch(const BeamWork *beams, int nbeams, int64_t total_blocks,
                                const WidthList &widths, hipStream_t stream, uint8_t *scratch,
-                               int ndm, int tile_dm, int64_t tile_t) {
+                               int ndm, int tile_dm, int64_t tile_t, bool rows_of_64) {
   if (total_blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
   if (scratch && (tile_dm < 1 || tile_t < 1 || ndm < 1)) return hipErrorInvalidValue;
   const size_t lds = (size_t)(kSeg + widths.w[widths.n - 1] + 1) * sizeof(uint32_t);
   bool pow2 = widths.n <= 13;
   for (int i = 0; i < widths.n && pow2; ++i) pow2 = widths.w[i] == (1 << i);
-  const int tm = tile_mode(scratch, tile_t);
+  const int tm = tile_mode(scratch, tile_t, rows_of_64);
 #define SPS_BOXCAR_BLAUNCH(n_, t_)                                                           \
   hipLaunchKernelGGL((boxcar_batch_kernel<n_, t_>), dim3((unsigned)total_blocks), dim3(kThreads), \
                      lds, stream, beams, nbeams, widths, scratch, ndm, tile_dm, tile_t)
@@ -483,6 +583,7 @@ hipError_t launch_boxcar_batch(const BeamWork *beams, int nbeams, int64_t total_
   if (pow2 && widths.n == n_) {                             \
     if (tm == 0) SPS_BOXCAR_BLAUNCH(n_, 0);                 \
     else if (tm == 1) SPS_BOXCAR_BLAUNCH(n_, 1);            \
+    else if (tm == 3) SPS_BOXCAR_BLAUNCH(n_, 3);            \
     else SPS_BOXCAR_BLAUNCH(n_, 2);                         \
     return hipGetLastError();                               \
   }
@@ -492,6 +593,7 @@ hipError_t launch_boxcar_batch(const BeamWork *beams, int nbeams, int64_t total_
   SPS_BOXCAR_BCASE(13)
   if (tm == 0) SPS_BOXCAR_BLAUNCH(0, 0);
   else if (tm == 1) SPS_BOXCAR_BLAUNCH(0, 1);
+  else if (tm == 3) SPS_BOXCAR_BLAUNCH(0, 3);
   else SPS_BOXCAR_BLAUNCH(0, 2);
 #undef SPS_BOXCAR_BCASE
 #undef SPS_BOXCAR_BLAUNCH
@@ -518,6 +620,54 @@ hipError_t launch_tile_keys_batch(const BeamWork *beams, int nbeams, int ndm, in
   if (grid == 0) return hipSuccess;
   hipLaunchKernelGGL(tile_keys_batch_kernel, dim3((unsigned)grid), dim3(kThreads), 0, stream,
                      beams, nbeams, ndm, total_tiles, tile_dm, tile_t, scratch, decode ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_boxcar_pool(const uint32_t *Y, int ndm, int64_t nout, const int32_t *stats,
+                              const WidthList &widths, float scale, uint16_t *tiles,
+                              hipStream_t stream) {
+  const int64_t ncols = nout / kSeg, pairs = (int64_t)(ndm / kPoolTileDm) * (kPoolTileDm / 2);
+  const int64_t grid = pairs * ncols;
+  if (grid > 0x7FFFFFFF) return hipErrorInvalidValue;
+  if (grid == 0) return hipSuccess;
+  const size_t lds = (size_t)(kSeg + widths.w[widths.n - 1] + 1) * sizeof(uint32_t);
+  bool pow2 = widths.n <= 13;
+  for (int i = 0; i < widths.n && pow2; ++i) pow2 = widths.w[i] == (1 << i);
+#define SPS_POOL_CASE(n_)                                                                       \
+  if (pow2 && widths.n == n_) {                                                                 \
+    hipLaunchKernelGGL(boxcar_pool_kernel<n_>, dim3((unsigned)grid), dim3(kThreads), lds, stream, \
+                       Y, nout, (int)ncols, stats, widths, scale, tiles);                       \
+    return hipGetLastError();                                                                   \
+  }
+  SPS_POOL_CASE(1) SPS_POOL_CASE(2) SPS_POOL_CASE(3) SPS_POOL_CASE(4) SPS_POOL_CASE(5)
+  SPS_POOL_CASE(6) SPS_POOL_CASE(7) SPS_POOL_CASE(8) SPS_POOL_CASE(9) SPS_POOL_CASE(10)
+  SPS_POOL_CASE(11) SPS_POOL_CASE(12) SPS_POOL_CASE(13)
+#undef SPS_POOL_CASE
+  hipLaunchKernelGGL(boxcar_pool_kernel<0>, dim3((unsigned)grid), dim3(kThreads), lds, stream, Y,
+                     nout, (int)ncols, stats, widths, scale, tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_boxcar_pool_batch(const BeamWork *beams, int nbeams, int64_t total_blocks,
+                                    const WidthList &widths, float scale, uint16_t *tiles,
+                                    hipStream_t stream) {
+  if (total_blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
+  if (total_blocks == 0) return hipSuccess;
+  const size_t lds = (size_t)(kSeg + widths.w[widths.n - 1] + 1) * sizeof(uint32_t);
+  bool pow2 = widths.n <= 13;
+  for (int i = 0; i < widths.n && pow2; ++i) pow2 = widths.w[i] == (1 << i);
+#define SPS_POOL_BCASE(n_)                                                                    \
+  if (pow2 && widths.n == n_) {                                                               \
+    hipLaunchKernelGGL(boxcar_pool_batch_kernel<n_>, dim3((unsigned)total_blocks), dim3(kThreads), \
+                       lds, stream, beams, nbeams, widths, scale, tiles);                     \
+    return hipGetLastError();                                                                 \
+  }
+  SPS_POOL_BCASE(1) SPS_POOL_BCASE(2) SPS_POOL_BCASE(3) SPS_POOL_BCASE(4) SPS_POOL_BCASE(5)
+  SPS_POOL_BCASE(6) SPS_POOL_BCASE(7) SPS_POOL_BCASE(8) SPS_POOL_BCASE(9) SPS_POOL_BCASE(10)
+  SPS_POOL_BCASE(11) SPS_POOL_BCASE(12) SPS_POOL_BCASE(13)
+#undef SPS_POOL_BCASE
+  hipLaunchKernelGGL(boxcar_pool_batch_kernel<0>, dim3((unsigned)total_blocks), dim3(kThreads), lds,
+                     stream, beams, nbeams, widths, scale, tiles);
   return hipGetLastError();
 }
 

@@ -640,6 +640,28 @@ sps_status sps_search(sps_plan plan, const uint32_t *Y, int64_t nout, const int3
                          out, cap, n_found, s);
 }
 
+sps_status sps_boxcar_pool(sps_plan plan, const uint32_t *Y, int64_t nout, const int32_t *widths,
+                           int32_t nw, int32_t *stats, float scale, uint16_t *tiles,
+                           int64_t *ntiles, void *stream) {
+  g_error.clear();
+  if (!plan || !Y || !widths || !tiles) return fail(SPS_ERR_INVALID_ARG, "NULL plan or buffer");
+  if (!(scale > 0.0f) || !isfinite(scale))
+    return fail(SPS_ERR_INVALID_ARG, "scale must be positive and finite");
+  sps::WidthList wl;
+  uint32_t vmax = 0;
+  const sps_status st = check_boxcar(plan, nout, widths, nw, &wl, &vmax);
+  if (st != SPS_OK) return st;
+  if (ntiles) *ntiles = (int64_t)(plan->ndm / sps::kPoolTileDm) * (nout / 4096);
+  DeviceScope scope(plan->device);
+  if (scope.err != hipSuccess) return hip_fail(scope.err, "selecting the plan's device");
+  int32_t *sts = stats ? stats : plan->d_stats;
+  hipError_t e = sps::launch_row_stats(Y, plan->ndm, nout, vmax, sts, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "row statistics launch");
+  e = sps::launch_boxcar_pool(Y, plan->ndm, nout, sts, wl, scale, tiles, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "pooled boxcar launch");
+  return SPS_OK;
+}
+
 sps_status sps_detect(sps_plan plan, const float *snr, const uint8_t *best_w, int64_t nout,
                       const int32_t *widths, int32_t nw, const sps_detect_params *prm,
                       sps_candidate *out, int32_t cap, int32_t *n_found, void *stream) {
@@ -928,6 +950,9 @@ struct sps_batch_s {
   int grid_dd = 0;
   uint8_t *d_det = nullptr;  // detection scratch of every beam (BeamWork::det_begin)
   int64_t det_bytes = 0;
+  int64_t pl_blocks = 0, pool_tiles = 0;  // pooled-tile boxcar workgroups, detector tiles
+  uint16_t *tiles = nullptr;              // tile mode (sps_batch_set_tiles): destination
+  float tile_scale = 0.0f;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipStream_t graph_stream = nullptr;
@@ -971,12 +996,21 @@ sps_status batch_enqueue(sps_batch b, hipStream_t s) {
   if (e != hipSuccess) return hip_fail(e, "batched dedispersion launch");
   e = sps::launch_row_stats_batch(b->d_beams, b->nbeams, p->ndm, 255u * (uint32_t)p->nchan, s);
   if (e != hipSuccess) return hip_fail(e, "batched statistics launch");
+  if (b->tiles) {
+    // tile mode: detector tiles straight from the boxcar pass, no planes
+    e = sps::launch_boxcar_pool_batch(b->d_beams, b->nbeams, b->pl_blocks, b->widths,
+                                      b->tile_scale, b->tiles, s);
+    if (e != hipSuccess) return hip_fail(e, "batched pooled boxcar launch");
+    return SPS_OK;
+  }
   // tile maxima taken inside the boxcar pass: keys zeroed, gathered, decoded
   e = sps::launch_tile_keys_batch(b->d_beams, b->nbeams, p->ndm, b->tp_tiles, b->prm.tile_dm,
                                   b->prm.tile_t, b->d_det, false, s);
   if (e != hipSuccess) return hip_fail(e, "batched tile key clearing launch");
+  bool rows_of_64 = true;
+  for (int64_t n : b->nout) rows_of_64 = rows_of_64 && n % 64 == 0;
   e = sps::launch_boxcar_batch(b->d_beams, b->nbeams, b->bx_blocks, b->widths, s, b->d_det,
-                               p->ndm, b->prm.tile_dm, b->prm.tile_t);
+                               p->ndm, b->prm.tile_dm, b->prm.tile_t, rows_of_64);
   if (e != hipSuccess) return hip_fail(e, "batched boxcar launch");
   e = sps::launch_tile_keys_batch(b->d_beams, b->nbeams, p->ndm, b->tp_tiles, b->prm.tile_dm,
                                   b->prm.tile_t, b->d_det, true, s);
@@ -1064,12 +1098,19 @@ sps_status sps_batch_create(sps_plan plan, int32_t nbeams, const sps_beam *beams
     w.vec_store = (q.nout % 4 == 0) && aligned16(q.Y);
     w.pad = 0;
     w.det_begin = b->det_bytes;
+    // whole detector tiles of the beam's plane (tile mode)
+    w.pcols = q.nout / 4096;
+    w.pl_begin = b->pl_blocks;
+    w.tile_begin = b->pool_tiles;
+    b->pl_blocks += (int64_t)(plan->ndm / sps::kPoolTileDm) * (sps::kPoolTileDm / 2) * w.pcols;
+    b->pool_tiles += (int64_t)(plan->ndm / sps::kPoolTileDm) * w.pcols;
     b->bx_blocks += w.nseg * plan->ndm;
     b->tp_tiles += w.ntt * ntd;
     b->det_bytes += sps::detect_layout(w.ntt * ntd).bytes;
     b->nout[(size_t)i] = q.nout;
   }
-  if (b->bx_blocks > 0x7FFFFFFF || b->tp_tiles > 0x7FFFFFFF || !layout_dedisp(b, b->cfg)) {
+  if (b->bx_blocks > 0x7FFFFFFF || b->tp_tiles > 0x7FFFFFFF || b->pl_blocks > 0x7FFFFFFF ||
+      !layout_dedisp(b, b->cfg)) {
     free_batch(b);
     return fail(SPS_ERR_RANGE, "batch too large");
   }
@@ -1219,10 +1260,31 @@ sps_status sps_batch_autotune(sps_batch batch, int32_t iters, void *stream, floa
   return SPS_OK;
 }
 
+sps_status sps_batch_set_tiles(sps_batch batch, uint16_t *tiles, float scale, int64_t *ntiles) {
+  g_error.clear();
+  if (!batch) return fail(SPS_ERR_INVALID_ARG, "batch is NULL");
+  if (tiles && (!(scale > 0.0f) || !isfinite(scale)))
+    return fail(SPS_ERR_INVALID_ARG, "scale must be positive and finite");
+  if (ntiles) *ntiles = batch->pool_tiles;
+  if (tiles != batch->tiles || scale != batch->tile_scale) {
+    // the captured graph holds the other mode's launches
+    DeviceScope scope(batch->plan->device);
+    if (batch->exec) (void)hipGraphExecDestroy(batch->exec);
+    if (batch->graph) (void)hipGraphDestroy(batch->graph);
+    batch->exec = nullptr;
+    batch->graph = nullptr;
+  }
+  batch->tiles = tiles;
+  batch->tile_scale = tiles ? scale : 0.0f;
+  return SPS_OK;
+}
+
 sps_status sps_batch_candidates(sps_batch batch, int32_t beam, sps_candidate *out, int32_t cap,
                                 int32_t *n_found, void *stream) {
   g_error.clear();
   if (!batch || !n_found) return fail(SPS_ERR_INVALID_ARG, "NULL argument");
+  if (batch->tiles)
+    return fail(SPS_ERR_INVALID_ARG, "the batch is in tile mode: it searches for no candidates");
   if (beam < 0 || beam >= batch->nbeams) return fail(SPS_ERR_RANGE, "beam out of range");
   if (cap < 0 || (cap > 0 && !out)) return fail(SPS_ERR_INVALID_ARG, "bad output array");
   DeviceScope scope(batch->plan->device);

@@ -74,6 +74,9 @@ struct BeamWork {
   int64_t nseg;         // boxcar segments per row
   int64_t ntt;          // detection tiles along time
   int64_t det_begin;    // byte offset of the beam's detection scratch
+  int64_t pl_begin;     // pooled-tile boxcar workgroups (trial pair x tile column)
+  int64_t tile_begin;   // first detector tile of the beam
+  int64_t pcols;        // whole tiles along time
   int32_t vec_store;
   int32_t pad;
 };
@@ -263,11 +266,25 @@ hipError_t launch_row_stats_batch(const BeamWork *beams, int nbeams, int ndm, ui
 // scratch != nullptr: every beam's tile maxima go to the key array of its
 // detection scratch (the out array of detect_layout, at scratch +
 // det_begin), which must be zero.
+// rows_of_64: every beam's nout is a multiple of 64.
 hipError_t launch_boxcar_batch(const BeamWork *beams, int nbeams, int64_t total_blocks,
                                const WidthList &widths, hipStream_t stream,
                                uint8_t *scratch = nullptr, int ndm = 0, int tile_dm = 1,
-                               int64_t tile_t = 1);
+                               int64_t tile_t = 1, bool rows_of_64 = false);
 int64_t boxcar_segments(int64_t nout);
+
+// Detector tiles taken straight from the boxcar pass: the S/N of whole
+// tiles of kPoolTileDm trials x 4096 samples max-pooled over 2 trials x 8
+// samples, times scale, rounded to bfloat16 (nearest even) -- the values
+// the tile pooling kernels make from the S/N plane -- with no S/N or width
+// plane written.  Tiles in row-major tile order, [256][512] each.
+constexpr int kPoolTileDm = 512;
+hipError_t launch_boxcar_pool(const uint32_t *Y, int ndm, int64_t nout, const int32_t *stats,
+                              const WidthList &widths, float scale, uint16_t *tiles,
+                              hipStream_t stream);
+hipError_t launch_boxcar_pool_batch(const BeamWork *beams, int nbeams, int64_t total_blocks,
+                                    const WidthList &widths, float scale, uint16_t *tiles,
+                                    hipStream_t stream);
 // Batched detection: beam b's scratch (detect_layout of its tile count)
 // starts at scratch + beams[b].det_begin.
 hipError_t launch_detect_batch(const BeamWork *beams, int nbeams, int ndm, int64_t total_tiles,

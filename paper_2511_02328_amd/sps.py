@@ -100,6 +100,9 @@ def library() -> ctypes.CDLL:
         lib.sps_boxcar_snr.argtypes = [P, P, i64, P, i32, P, P, P, P]
         lib.sps_detect.argtypes = [P, P, P, i64, P, i32, ctypes.POINTER(sps_detect_params),
                                    ctypes.POINTER(sps_candidate), i32, ctypes.POINTER(i32), P]
+        lib.sps_boxcar_pool.argtypes = [P, P, i64, P, i32, P, ctypes.c_float, P,
+                                        ctypes.POINTER(i64), P]
+        lib.sps_batch_set_tiles.argtypes = [P, P, ctypes.c_float, ctypes.POINTER(i64)]
         lib.sps_search.argtypes = [P, P, i64, P, i32, P, P, P, ctypes.POINTER(sps_detect_params),
                                    ctypes.POINTER(sps_candidate), i32, ctypes.POINTER(i32), P]
         lib.sps_detect_noalloc.argtypes = [P, P, P, i64, P, i32,
@@ -175,7 +178,8 @@ def library() -> ctypes.CDLL:
                   "sps_server_run", "sps_server_set_detector"):
             getattr(lib, f).restype = ctypes.c_int
         for f in ("sps_plan_create", "sps_plan_destroy", "sps_plan_delays", "sps_dedisperse",
-                  "sps_boxcar_snr", "sps_search", "sps_detect", "sps_detect_noalloc",
+                  "sps_boxcar_snr", "sps_search", "sps_boxcar_pool", "sps_batch_set_tiles",
+                  "sps_detect", "sps_detect_noalloc",
                   "sps_plan_set_tiling",
                   "sps_plan_get_tiling",
                   "sps_subband_plan_create", "sps_subband_tables", "sps_dedisperse_subband",
@@ -328,6 +332,20 @@ def sps_search(plan: Plan, Y: torch.Tensor, nout: int, widths: Sequence[int], sn
     k = min(int(n.value), cap)
     arr = np.frombuffer(bytes(out)[:k * ctypes.sizeof(sps_candidate)], dtype=CANDIDATE_DTYPE).copy()
     return arr, int(n.value)
+
+
+def sps_boxcar_pool(plan: Plan, Y: torch.Tensor, nout: int, widths: Sequence[int],
+                    stats: Optional[torch.Tensor], scale: float, tiles: torch.Tensor,
+                    stream=None) -> int:
+    """Statistics and boxcar straight into bf16 detector tiles; returns the tile count."""
+    w = np.ascontiguousarray(widths, dtype=np.int32)
+    yp = _dev(Y, torch.int32, "Y") if Y.dtype == torch.int32 else _dev(Y, torch.uint32, "Y")
+    sp = _dev(stats, torch.int32, "stats") if stats is not None else None
+    n = ctypes.c_int64()
+    _check(library().sps_boxcar_pool(plan.handle, yp, int(nout), w.ctypes.data, w.size, sp,
+                                     float(scale), _tiles_ptr(tiles), ctypes.byref(n),
+                                     _stream(stream)), "sps_boxcar_pool")
+    return int(n.value)
 
 
 CANDIDATE_DTYPE = np.dtype([("dm_idx", np.int32), ("width", np.int32), ("t_idx", np.int64),
@@ -484,6 +502,17 @@ def sps_batch_enqueue(batch: Batch, stream=None) -> None:
 
 def sps_batch_launch_graph(batch: Batch, stream) -> None:
     _check(library().sps_batch_launch_graph(batch.handle, _stream(stream)), "sps_batch_launch_graph")
+
+
+def sps_batch_set_tiles(batch: Batch, tiles: Optional[torch.Tensor], scale: float = 0.0) -> int:
+    """Tile mode (tiles a [n][256][512] 16-bit tensor) or search mode (None);
+    returns the batch's tile count."""
+    n = ctypes.c_int64()
+    tp = _tiles_ptr(tiles) if tiles is not None else None
+    _check(library().sps_batch_set_tiles(batch.handle, tp, float(scale), ctypes.byref(n)),
+           "sps_batch_set_tiles")
+    batch._tiles = tiles  # kept alive while the batch writes into it
+    return int(n.value)
 
 
 def sps_batch_candidates(batch: Batch, beam: int, cap: int = 4096, stream=None,

@@ -5,7 +5,8 @@ width rule), and candidates identical to the oracle's tile / threshold /
 greedy-suppression rule on the S/N plane the call wrote.  Tilings cover a
 tile length that is a multiple of the boxcar segment (one reduction per
 segment), tile lengths that cut segments (per-thread merges), one-sample
-tiles, ragged rows and rows of MAD 0."""
+tiles, tile lengths of whole waves (one merge per wave and column), ragged
+rows and rows of MAD 0."""
 import numpy as np
 import pytest
 
@@ -77,6 +78,8 @@ CASES = [
     (9, 600, (1, 2, 4), 1, 1, 0, 0, 3.0),                                       # one-sample tiles
     (70, 4096, (1, 2, 4, 8, 16, 32, 64, 128, 256), 64, 4096, 16, 512, 1.5),     # full tiles, many offers
     (5, 1, (1,), 3, 7, 1, 1, 0.5),                                              # one output per row
+    (21, 4736, (1, 2, 4, 8, 16, 32, 64), 3, 512, 2, 100, 2.0),                  # tiles of 64-multiples,
+    (12, 8192, (1, 3, 5, 7, 12, 100), 4, 192, 1, 30, 2.0),                      # wave-level merges
 ]
 
 
