@@ -41,19 +41,12 @@ __device__ uint32_t block_exclusive_scan256(uint32_t v, uint32_t *tmp /* >= 4 */
   return off + inc - v;
 }
 
-// a + b + c (mod 2^32) in one instruction; left to itself the compiler
-// splits the numerator below into a subtract and an add.
-__device__ __forceinline__ uint32_t add3_u32(uint32_t a, uint32_t b, uint32_t c) {
-  uint32_t r;
-  asm("v_add3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
-  return r;
-}
-
 // Running tile maximum of one thread's outputs of a segment (row d, first
 // output t0).  TILES = 0: none.  TILES = 1: the segment lies in one tile
-// column; each thread keeps its largest S/N and the first output holding it
-// (outputs arrive in increasing t), and finish() reduces the workgroup to
-// one key and one atomic.  TILES = 2: any tiling; a thread flushes its
+// column; each thread keeps only its largest S/N (one max per output), and
+// finish() reduces the workgroup to its maximum, whose first output the
+// threads holding it find again in the S/N row they wrote (one atomic per
+// such thread; the key orders equal S/N by position).  TILES = 2: any tiling; a thread flushes its
 // maximum with an atomic whenever its outputs enter the next tile column.
 // TILES = 3: tile_t and the row length multiples of 64, so the 64
 // consecutive outputs a wave handles at a time share one column, and its
@@ -96,6 +89,10 @@ struct TileTrack {
     }
   }
   __device__ __forceinline__ void add(const TileSink &k, int d, int64_t t0, float v, int t_local) {
+    if constexpr (TILES == 1) {
+      s = fmaxf(s, v);
+      return;
+    }
     if constexpr (TILES >= 2) {
       if (t0 + t_local >= col_end) {
         flush(k, d, t0);
@@ -111,24 +108,35 @@ struct TileTrack {
       }
     }
   }
-  // Every thread of the workgroup calls this once, after its last add.
+  // Every thread of the workgroup calls this once, after its last add;
+  // srow[0, len) are the S/N values this segment wrote (TILES = 1 reads
+  // back its own outputs).
   __device__ __forceinline__ void finish(const TileSink &k, int d, int64_t t0,
-                                         unsigned long long *red) {
+                                         unsigned long long *red, const SPS_GLOBAL float *srow,
+                                         int len) {
     if constexpr (TILES == 1) {
-      unsigned long long v = s == -INFINITY ? 0ull : key(k, d, t0);
+      float m = s;
 #pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        const uint32_t lo = __shfl_xor((uint32_t)v, o, 64);
-        const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), o, 64);
-        const unsigned long long u = ((unsigned long long)hi << 32) | lo;
-        v = u > v ? u : v;
-      }
-      if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+      for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+      float *redf = reinterpret_cast<float *>(red);
+      if ((threadIdx.x & 63) == 0) redf[threadIdx.x >> 6] = m;
       __syncthreads();
-      if (threadIdx.x == 0) {
 #pragma unroll
-        for (int w = 1; w < kThreads / 64; ++w) v = red[w] > v ? red[w] : v;
-        if (v != 0ull) atomicMax(k.keys + (int64_t)(d / k.tile_dm) * k.ntt + col, v);
+      for (int w = 0; w < kThreads / 64; ++w) m = fmaxf(m, redf[w]);
+      if (s == m && m != -INFINITY) {
+        // this thread's outputs are threadIdx.x + kThreads j, in order; all
+        // of them are read at once, the first equal to m wins
+        float v[kPer];
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+          const int t = threadIdx.x + kThreads * j;
+          v[j] = t < len ? srow[t] : -INFINITY;
+        }
+        int first = kPer - 1;
+#pragma unroll
+        for (int j = kPer - 2; j >= 0; --j) first = v[j] == m ? j : first;
+        tl = threadIdx.x + kThreads * first;
+        atomicMax(k.keys + (int64_t)(d / k.tile_dm) * k.ntt + col, key(k, d, t0));
       }
     } else if constexpr (TILES >= 2) {
       flush(k, d, t0);
@@ -146,6 +154,7 @@ struct PlaneSink {
   const TileSink *tiles;
   unsigned long long *red;
   int d;
+  int len;  // outputs of the segment
   int64_t t0;
   TileTrack<TILES> tr;
   __device__ __forceinline__ void put(int tl, float v, int bi) {
@@ -153,7 +162,7 @@ struct PlaneSink {
     brow[tl] = (uint8_t)bi;
     tr.add(*tiles, d, t0, v, tl);
   }
-  __device__ __forceinline__ void finish() { tr.finish(*tiles, d, t0, red); }
+  __device__ __forceinline__ void finish() { tr.finish(*tiles, d, t0, red, srow, len); }
 };
 
 struct PoolSink {
@@ -170,50 +179,75 @@ struct PoolSink {
 // compile-time constant, so each thread issues all of its loads before the
 // first wait and reads and writes its scan chunk at immediate LDS offsets
 // (an odd chunk length puts the chunk starts of a wave in distinct banks).
+// A segment is fetched into registers (pow2_fetch), staged into LDS
+// (pow2_stage) and filtered (pow2_filter).
 // TAIL: the row ends inside the window (n_left < kLen samples remain); the
 // missing samples read as zero, widths that run past the row end are left
 // out of the maximum (as -inf; width 1 always fits), and outputs past the
 // row end are not written.
-template <int NPOW, bool TAIL, class Sink>
-__device__ __forceinline__ void pow2_segment(const SPS_GLOBAL uint32_t *src, int n_left,
-                                             int32_t med, int32_t mad, const WidthList &widths,
-                                             float *scale, uint32_t *tmp, uint32_t *P,
-                                             Sink &out) {
-  constexpr int kLen = kSeg + (1 << (NPOW - 1)) - 1;
-  constexpr int kLd = (kLen + kThreads - 1) / kThreads;
-  constexpr int kCh = kLd | 1;
-  uint32_t v[kLd];
+template <int NPOW>
+struct Pow2 {
+  static constexpr int kLen = kSeg + (1 << (NPOW - 1)) - 1;
+  static constexpr int kLd = (kLen + kThreads - 1) / kThreads;
+  static constexpr int kCh = kLd | 1;
+  static constexpr int kWords = kThreads * kCh + 1;  // P, scan chunks padded
+};
+
+template <int NPOW, bool TAIL>
+__device__ __forceinline__ void pow2_fetch(const SPS_GLOBAL uint32_t *src, int n_left,
+                                           uint32_t (&v)[Pow2<NPOW>::kLd]) {
+  constexpr int kLen = Pow2<NPOW>::kLen, kLd = Pow2<NPOW>::kLd;
 #pragma unroll
   for (int k = 0; k < kLd; ++k) {
     const int i = threadIdx.x + kThreads * k;
     const bool in = TAIL ? i < n_left : (k + 1 < kLd || i < kLen);
     v[k] = in ? src[i] : 0u;
   }
-  if (threadIdx.x < NPOW) {
+}
+
+// P[i + 1] = sample i of the window minus the median (wrapping), for i
+// up to the padded scan extent (zero samples past the window); the caller
+// has made sure that every reader of the previous segment's P is done.  The
+// prefix of Y - med makes each numerator B_w - w med one subtraction.
+template <int NPOW>
+__device__ __forceinline__ void pow2_stage(const uint32_t (&v)[Pow2<NPOW>::kLd], int32_t med,
+                                           uint32_t *P) {
+  constexpr int kLd = Pow2<NPOW>::kLd, kCh = Pow2<NPOW>::kCh;
+#pragma unroll
+  for (int k = 0; k < kCh; ++k) P[threadIdx.x + kThreads * k + 1] = (k < kLd ? v[k] : 0u) - (uint32_t)med;
+}
+
+// Width scales 1 / (1.4826 MAD sqrt(w)) into LDS (0 when MAD = 0); read
+// after the next barrier.
+__device__ __forceinline__ void set_scales(const WidthList &widths, int32_t mad, float *scale) {
+  if (threadIdx.x < widths.n) {
     const double w = (double)widths.w[threadIdx.x];
     scale[threadIdx.x] = mad > 0 ? (float)(1.0 / (1.4826 * (double)mad * sqrt(w))) : 0.0f;
   }
-#pragma unroll
-  for (int k = 0; k < kLd; ++k) {
-    const int i = threadIdx.x + kThreads * k;
-    if (k + 1 < kLd || i < kLen) P[i + 1] = v[k];
-  }
+}
+
+template <int NPOW, bool TAIL, class Sink>
+__device__ __forceinline__ void pow2_filter(int n_left, int32_t med, int32_t mad,
+                                            const float *scale, uint32_t *tmp, uint32_t *P,
+                                            Sink &out) {
+  constexpr int kCh = Pow2<NPOW>::kCh;
   __syncthreads();
 
-  // Exclusive prefix over [0, kLen): thread chunks of kCh samples.
+  // Exclusive prefix over the padded extent: thread chunks of kCh samples
+  // (entries past the window are never read).
   const int lo = threadIdx.x * kCh;
   uint32_t c[kCh];
   uint32_t part = 0;
 #pragma unroll
   for (int j = 0; j < kCh; ++j) {
-    c[j] = lo + j < kLen ? P[lo + j + 1] : 0u;
+    c[j] = P[lo + j + 1];
     part += c[j];
   }
   uint32_t run = block_exclusive_scan256(part, tmp);
 #pragma unroll
   for (int j = 0; j < kCh; ++j) {
     run += c[j];
-    if (lo + j < kLen) P[lo + j + 1] = run;
+    P[lo + j + 1] = run;
   }
   if (threadIdx.x == 0) P[0] = 0u;
   __syncthreads();
@@ -222,26 +256,21 @@ __device__ __forceinline__ void pow2_segment(const SPS_GLOBAL uint32_t *src, int
   // attains it: equal to the strict running comparison, since S/N values are
   // never NaN and never -0 (the numerator is an integer, the scale positive;
   // with MAD = 0 every value is +-0 and width index 0 is chosen, as there).
-  // cw[i] = -w med (wrapping), wave-uniform.
   const bool live = mad > 0;
   const int seg_len = TAIL ? (n_left < kSeg ? n_left : kSeg) : kSeg;
   float sc[NPOW];
-  uint32_t cw[NPOW];
 #pragma unroll
-  for (int i = 0; i < NPOW; ++i) {
-    sc[i] = scale[i];
-    cw[i] = 0u - (uint32_t)((1 << i) * med);
-  }
+  for (int i = 0; i < NPOW; ++i) sc[i] = scale[i];
 #pragma unroll 2
   for (int m = 0; m < kPer; ++m) {
     const int tl = threadIdx.x + kThreads * m;
     if (TAIL && tl >= seg_len) break;
     const uint32_t *pt = P + tl;
-    const uint32_t neg_p0 = 0u - pt[0];
+    const uint32_t p0 = pt[0];
     float s[NPOW];
 #pragma unroll
     for (int i = 0; i < NPOW; ++i) {
-      s[i] = (float)(int32_t)add3_u32(pt[1 << i], neg_p0, cw[i]) * sc[i];
+      s[i] = (float)(int32_t)(pt[1 << i] - p0) * sc[i];
       if (TAIL && tl + (1 << i) > n_left) s[i] = -INFINITY;
     }
     float mx = s[0];
@@ -252,6 +281,18 @@ __device__ __forceinline__ void pow2_segment(const SPS_GLOBAL uint32_t *src, int
     for (int i = NPOW - 2; i >= 0; --i) bi = s[i] == mx ? i : bi;
     out.put(tl, live ? mx : 0.0f, bi);
   }
+}
+
+template <int NPOW, bool TAIL, class Sink>
+__device__ __forceinline__ void pow2_segment(const SPS_GLOBAL uint32_t *src, int n_left,
+                                             int32_t med, int32_t mad, const WidthList &widths,
+                                             float *scale, uint32_t *tmp, uint32_t *P,
+                                             Sink &out) {
+  uint32_t v[Pow2<NPOW>::kLd];
+  pow2_fetch<NPOW, TAIL>(src, n_left, v);
+  set_scales(widths, mad, scale);
+  pow2_stage<NPOW>(v, med, P);
+  pow2_filter<NPOW, TAIL>(n_left, med, mad, scale, tmp, P, out);
 }
 
 // NPOW > 0: power-of-two widths (pow2_segment); NPOW = 0: any width list.
@@ -269,18 +310,12 @@ __device__ __forceinline__ void boxcar_core(const uint32_t *__restrict__ Y, int6
   const int wmax = widths.w[nw - 1];
   const int32_t med = gmem(stats)[2 * (int64_t)d];
   const int32_t mad = gmem(stats)[2 * (int64_t)d + 1];
-  auto set_scales = [&]() {
-    if (threadIdx.x < nw) {
-      const double w = (double)widths.w[threadIdx.x];
-      scale[threadIdx.x] = mad > 0 ? (float)(1.0 / (1.4826 * (double)mad * sqrt(w))) : 0.0f;
-    }
-  };
 
   // Samples this segment needs: [t0, t0 + len), len <= kSeg + wmax - 1.
   const int64_t avail = nout - t0;
 
   if constexpr (NPOW > 0) {
-    constexpr int kLen = kSeg + (1 << (NPOW - 1)) - 1;
+    constexpr int kLen = Pow2<NPOW>::kLen;
     if (avail >= (int64_t)kLen)
       pow2_segment<NPOW, false>(row + t0, kLen, med, mad, widths, scale, tmp, P, out);
     else
@@ -289,7 +324,7 @@ __device__ __forceinline__ void boxcar_core(const uint32_t *__restrict__ Y, int6
     return;
   }
 
-  set_scales();
+  set_scales(widths, mad, scale);
   const int len = (int)(avail < (int64_t)(kSeg + wmax - 1) ? avail : (int64_t)(kSeg + wmax - 1));
   for (int i = threadIdx.x; i < len; i += kThreads) P[i + 1] = row[t0 + i];
   __syncthreads();
@@ -372,9 +407,49 @@ __device__ __forceinline__ void boxcar_segment(const uint32_t *__restrict__ Y, i
   __shared__ unsigned long long red[kThreads / 64];
   const int64_t t0 = (int64_t)seg * kSeg;
   PlaneSink<TILES> out{gmem(snr + (int64_t)d * nout + t0), gmem(best + (int64_t)d * nout + t0),
-                       &sink, red, d, t0, TileTrack<TILES>{}};
+                       &sink, red, d, (int)(nout - t0 < kSeg ? nout - t0 : kSeg), t0,
+                       TileTrack<TILES>{}};
   out.tr.begin(sink, t0);
   boxcar_core<NPOW>(Y, nout, d, seg, stats, widths, P, out);
+}
+
+// One segment of row d into the S/N and width planes, with the tile maxima.
+template <int NPOW, int TILES>
+__device__ __forceinline__ void boxcar_plane_segment(const uint32_t *__restrict__ Y, int64_t nout,
+                                                     int d, int seg,
+                                                     const int32_t *__restrict__ stats,
+                                                     const WidthList &widths,
+                                                     float *__restrict__ snr,
+                                                     uint8_t *__restrict__ best, uint32_t *P,
+                                                     const TileSink &sink) {
+  if constexpr (NPOW == 0) {
+    boxcar_segment<0, TILES>(Y, nout, d, seg, stats, widths, snr, best, P, sink);
+  } else {
+    __shared__ float scale[kMaxWidths];
+    __shared__ uint32_t tmp[4];
+    __shared__ unsigned long long red[kThreads / 64];
+    constexpr int kLen = Pow2<NPOW>::kLen;
+    const int64_t t0 = (int64_t)seg * kSeg, avail = nout - t0;
+    const SPS_GLOBAL uint32_t *src = gmem(Y + (int64_t)d * nout + t0);
+    const int32_t med = gmem(stats)[2 * (int64_t)d];
+    const int32_t mad = gmem(stats)[2 * (int64_t)d + 1];
+    uint32_t v[Pow2<NPOW>::kLd];
+    if (avail >= (int64_t)kLen)
+      pow2_fetch<NPOW, false>(src, kLen, v);
+    else
+      pow2_fetch<NPOW, true>(src, (int)avail, v);
+    set_scales(widths, mad, scale);
+    pow2_stage<NPOW>(v, med, P);
+    PlaneSink<TILES> out{gmem(snr + (int64_t)d * nout + t0), gmem(best + (int64_t)d * nout + t0),
+                         &sink, red, d, (int)(avail < kSeg ? avail : kSeg), t0,
+                         TileTrack<TILES>{}};
+    out.tr.begin(sink, t0);
+    if (avail >= (int64_t)kLen)
+      pow2_filter<NPOW, false>(kLen, med, mad, scale, tmp, P, out);
+    else
+      pow2_filter<NPOW, true>((int)avail, med, mad, scale, tmp, P, out);
+    out.finish();
+  }
 }
 
 // Trials d, d + 1 of one segment pooled over 2 trials x 8 samples, scaled
@@ -400,15 +475,16 @@ __device__ __forceinline__ void boxcar_pool_pair(const uint32_t *__restrict__ Y,
   }
 }
 
+// One workgroup per (DM row, segment).
 template <int NPOW, int TILES>
 __global__ __launch_bounds__(kThreads) void boxcar_kernel(
     const uint32_t *__restrict__ Y, int64_t nout, int nseg, const int32_t *__restrict__ stats,
     WidthList widths, float *__restrict__ snr, uint8_t *__restrict__ best, TileSink sink) {
-  extern __shared__ uint32_t P[];  // [kSeg + w_max]
+  extern __shared__ uint32_t P[];  // boxcar_lds_bytes
   const int64_t blk = blockIdx.x;
   const int d = (int)(blk / nseg);
   const int seg = (int)(blk - (int64_t)d * nseg);
-  boxcar_segment<NPOW, TILES>(Y, nout, d, seg, stats, widths, snr, best, P, sink);
+  boxcar_plane_segment<NPOW, TILES>(Y, nout, d, seg, stats, widths, snr, best, P, sink);
 }
 
 // One workgroup per (beam, DM row, segment) of a batch.  With TILES, the
@@ -432,7 +508,8 @@ __global__ __launch_bounds__(kThreads) void boxcar_batch_kernel(
     sink.tile_t = tile_t;
     sink.ntt = bw.ntt;
   }
-  boxcar_segment<NPOW, TILES>(bw.Y, bw.nout, d, seg, bw.stats, widths, bw.snr, bw.best, P, sink);
+  boxcar_plane_segment<NPOW, TILES>(bw.Y, bw.nout, d, seg, bw.stats, widths, bw.snr, bw.best, P,
+                                    sink);
 }
 
 // Tile keys: zeroed (DECODE false) or turned into tile peak records.
@@ -524,6 +601,16 @@ __global__ __launch_bounds__(kThreads) void boxcar_pool_batch_kernel(
   boxcar_pool_pair<NPOW>(bw.Y, bw.nout, d, tj, bw.stats, widths, P, pv, scale, pooled);
 }
 
+// Dynamic LDS of the boxcar kernels: the window's prefix (kSeg + w_max words)
+// and, for power-of-two widths, the padded scan extent.
+size_t boxcar_lds_bytes(const WidthList &widths) {
+  const int wmax = widths.w[widths.n - 1];
+  size_t words = (size_t)kSeg + wmax + 1;
+  const int ld = (kSeg + wmax - 1 + kThreads - 1) / kThreads;
+  const size_t padded = (size_t)kThreads * (ld | 1) + 1;
+  return (words > padded ? words : padded) * sizeof(uint32_t);
+}
+
 // 0: no tile maxima; 1: every segment inside one tile column (tile_t a
 // multiple of the segment length); 2: any tiling.
 int tile_mode(const void *keys, int64_t tile_t, bool rows_of_64) {
@@ -540,9 +627,9 @@ hipError_t launch_boxcar(const uint32_t *Y, int ndm, int64_t nout, const int32_t
   const int64_t grid = nseg * ndm;
   if (grid > 0x7FFFFFFF || nseg > 0x7FFFFFFF) return hipErrorInvalidValue;
   if (sink.keys && (sink.tile_dm < 1 || sink.tile_t < 1)) return hipErrorInvalidValue;
-  const size_t lds = (size_t)(kSeg + widths.w[widths.n - 1] + 1) * sizeof(uint32_t);
   bool pow2 = widths.n <= 13;
   for (int i = 0; i < widths.n && pow2; ++i) pow2 = widths.w[i] == (1 << i);
+  const size_t lds = boxcar_lds_bytes(widths);
   const int tm = tile_mode(sink.keys, sink.tile_t, nout % 64 == 0);
 #define SPS_BOXCAR_LAUNCH(n_, t_)                                                          \
   hipLaunchKernelGGL((boxcar_kernel<n_, t_>), dim3((unsigned)grid), dim3(kThreads), lds, stream, \
@@ -572,9 +659,9 @@ hipError_t launch_boxcar_batch(const BeamWork *beams, int nbeams, int64_t total_
                                int ndm, int tile_dm, int64_t tile_t, bool rows_of_64) {
   if (total_blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
   if (scratch && (tile_dm < 1 || tile_t < 1 || ndm < 1)) return hipErrorInvalidValue;
-  const size_t lds = (size_t)(kSeg + widths.w[widths.n - 1] + 1) * sizeof(uint32_t);
   bool pow2 = widths.n <= 13;
   for (int i = 0; i < widths.n && pow2; ++i) pow2 = widths.w[i] == (1 << i);
+  const size_t lds = boxcar_lds_bytes(widths);
   const int tm = tile_mode(scratch, tile_t, rows_of_64);
 #define SPS_BOXCAR_BLAUNCH(n_, t_)                                                           \
   hipLaunchKernelGGL((boxcar_batch_kernel<n_, t_>), dim3((unsigned)total_blocks), dim3(kThreads), \
@@ -630,9 +717,9 @@ hipError_t launch_boxcar_pool(const uint32_t *Y, int ndm, int64_t nout, const in
   const int64_t grid = pairs * ncols;
   if (grid > 0x7FFFFFFF) return hipErrorInvalidValue;
   if (grid == 0) return hipSuccess;
-  const size_t lds = (size_t)(kSeg + widths.w[widths.n - 1] + 1) * sizeof(uint32_t);
   bool pow2 = widths.n <= 13;
   for (int i = 0; i < widths.n && pow2; ++i) pow2 = widths.w[i] == (1 << i);
+  const size_t lds = boxcar_lds_bytes(widths);
 #define SPS_POOL_CASE(n_)                                                                       \
   if (pow2 && widths.n == n_) {                                                                 \
     hipLaunchKernelGGL(boxcar_pool_kernel<n_>, dim3((unsigned)grid), dim3(kThreads), lds, stream, \
@@ -653,9 +740,9 @@ hipError_t launch_boxcar_pool_batch(const BeamWork *beams, int nbeams, int64_t t
                                     hipStream_t stream) {
   if (total_blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
   if (total_blocks == 0) return hipSuccess;
-  const size_t lds = (size_t)(kSeg + widths.w[widths.n - 1] + 1) * sizeof(uint32_t);
   bool pow2 = widths.n <= 13;
   for (int i = 0; i < widths.n && pow2; ++i) pow2 = widths.w[i] == (1 << i);
+  const size_t lds = boxcar_lds_bytes(widths);
 #define SPS_POOL_BCASE(n_)                                                                    \
   if (pow2 && widths.n == n_) {                                                               \
     hipLaunchKernelGGL(boxcar_pool_batch_kernel<n_>, dim3((unsigned)total_blocks), dim3(kThreads), \

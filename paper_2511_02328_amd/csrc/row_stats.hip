@@ -3,12 +3,21 @@
 // The boxcar S/N is normalised by each dedispersed row's median and median
 // absolute deviation (sigma = 1.4826 MAD).  Both are order statistics of
 // integers no larger than 255 * nchan (< 2^24 for nchan <= 65536), so they
-// are found exactly from histograms: a 4096-bin histogram of the high bits
-// locates the bin holding rank floor((n-1)/2) and bounds the MAD; one exact
-// histogram over a window of values around that bin then yields both the
-// median and the MAD, in two reads of the row.  One workgroup of 1024
-// threads owns a row; histograms live in LDS (LDS atomics); the row is
-// streamed with 16-byte loads when its start is 16-byte aligned.
+// are found exactly from histograms.  One workgroup of 1024 threads owns a
+// row; histograms live in LDS (LDS atomics); the row is streamed with
+// 16-byte loads when its start is 16-byte aligned.
+//
+// One read of the row in the common case: a small sample of the row (8
+// runs of 512 samples spread over it) places a window of 16384 consecutive
+// values around its median; one pass then builds the exact histogram of the
+// window and counts the values below it.  The window's counts decide
+// exactly whether it holds the median and every deviation up to the MAD;
+// when it does, both follow from the window alone.  A row that fails the
+// test (a sample that misleads, a MAD too wide for the window) takes the
+// two-read path: a 4096-bin histogram of the high bits locates the median's
+// bin and bounds the MAD, and an exact histogram over the window of bins
+// around it yields both; rows wider than that window take two more reads
+// (radix selection of |Y - med|).
 #include "sps_internal.h"
 
 namespace sps {
@@ -18,6 +27,8 @@ constexpr int kThreads = 1024;
 constexpr int kBins = 4096;             // coarse histogram
 constexpr int kFine = 16384;            // exact window histogram (64 KiB of LDS)
 constexpr int kPerThread = kBins / kThreads;
+constexpr int kSampleRuns = 8;
+constexpr int kSampleRun = 4 * kThreads / kSampleRuns;  // 512: one 16-byte load per thread
 
 // Exclusive scan of one value per thread across the workgroup.
 __device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *tmp /* >= 16 */) {
@@ -93,39 +104,158 @@ __device__ void locate_rank_n(const uint32_t *hist, int n, uint32_t k, uint32_t 
   __syncthreads();
 }
 
+// f(v) for every value of the row, four 16-byte loads (or four words) per
+// thread in flight at a time.
 template <typename F>
 __device__ __forceinline__ void for_each_value(const uint32_t *row_in, int64_t n, bool vec, F f) {
   const SPS_GLOBAL uint32_t *row = gmem(row_in);
+  int64_t i = threadIdx.x;
   if (vec) {
     const SPS_GLOBAL u32x4 *r4 = (const SPS_GLOBAL u32x4 *)row;
     const int64_t n4 = n >> 2;
-    for (int64_t i = threadIdx.x; i < n4; i += kThreads) {
+    for (; i + 3 * kThreads < n4; i += 4 * kThreads) {
+      u32x4 v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = r4[i + u * kThreads];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        f(v[u].x);
+        f(v[u].y);
+        f(v[u].z);
+        f(v[u].w);
+      }
+    }
+    for (; i < n4; i += kThreads) {
       const u32x4 v = r4[i];
       f(v.x);
       f(v.y);
       f(v.z);
       f(v.w);
     }
-    for (int64_t i = (n4 << 2) + threadIdx.x; i < n; i += kThreads) f(row[i]);
+    for (i = (n4 << 2) + threadIdx.x; i < n; i += kThreads) f(row[i]);
   } else {
-    for (int64_t i = threadIdx.x; i < n; i += kThreads) f(row[i]);
+    for (; i + 3 * kThreads < n; i += 4 * kThreads) {
+      uint32_t v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = row[i + u * kThreads];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) f(v[u]);
+    }
+    for (; i < n; i += kThreads) f(row[i]);
   }
 }
 
-// Median and MAD of one row (the whole workgroup), written to out[0..1].
-__device__ void row_stats_row(const uint32_t *__restrict__ row, int64_t nout, int shift,
-                              int32_t *__restrict__ out) {
+// Workgroup sum of one value per thread, visible to all threads on return.
+__device__ uint32_t block_sum(uint32_t v, uint32_t *acc /* LDS word */) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if (threadIdx.x == 0) *acc = 0u;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) atomicAdd(acc, v);
+  __syncthreads();
+  const uint32_t r = *acc;
+  __syncthreads();
+  return r;
+}
+
+// The one-read path.  Returns false (every thread alike) when the window
+// does not hold the median or the deviations up to the MAD; hist is then
+// free for the caller.
+__device__ bool row_stats_one_pass(const uint32_t *__restrict__ row, int64_t nout, int shift,
+                                   bool vec, uint32_t *hist, uint32_t *tmp, uint32_t *sel,
+                                   uint32_t &med, uint32_t &mad) {
+  const uint32_t k = (uint32_t)((nout - 1) / 2);
+  // Sample: kSampleRuns runs of kSampleRun consecutive values, run j starting
+  // at j (nout - kSampleRun) / (kSampleRuns - 1) rounded down to a multiple
+  // of 4 (the whole row when it is no longer than the sample).
+  for (int i = threadIdx.x; i < kBins; i += kThreads) hist[i] = 0u;
+  __syncthreads();
+  const SPS_GLOBAL uint32_t *g = gmem(row);
+  const int64_t nsample = nout < (int64_t)(kSampleRuns * kSampleRun) ? nout
+                                                                      : kSampleRuns * kSampleRun;
+  auto bin = [&](uint32_t v) { atomicAdd(&hist[min(v >> shift, (uint32_t)(kBins - 1))], 1u); };
+  if (nsample < (int64_t)(kSampleRuns * kSampleRun)) {
+    for (int64_t i = threadIdx.x; i < nout; i += kThreads) bin(g[i]);
+  } else {
+    const int j = threadIdx.x / (kSampleRun / 4);
+    const int64_t start = ((int64_t)j * (nout - kSampleRun) / (kSampleRuns - 1)) & ~(int64_t)3;
+    const int64_t i = start + 4 * (threadIdx.x % (kSampleRun / 4));
+    if (vec) {
+      const u32x4 v = *(const SPS_GLOBAL u32x4 *)(g + i);
+      bin(v.x);
+      bin(v.y);
+      bin(v.z);
+      bin(v.w);
+    } else {
+      bin(g[i]);
+      bin(g[i + 1]);
+      bin(g[i + 2]);
+      bin(g[i + 3]);
+    }
+  }
+  __syncthreads();
+  locate_rank(hist, (uint32_t)((nsample - 1) / 2), tmp, sel);
+  // window [lo, lo + kFine) centred on the sample median's bin
+  const uint32_t centre = (sel[0] << shift) + ((1u << shift) >> 1);
+  const uint32_t lo = centre > (uint32_t)(kFine / 2) ? centre - (uint32_t)(kFine / 2) : 0u;
+  __syncthreads();
+
+  for (int i = threadIdx.x; i < kFine; i += kThreads) hist[i] = 0u;
+  __syncthreads();
+  uint32_t below = 0, inside = 0;
+  for_each_value(row, nout, vec, [&](uint32_t v) {
+    const uint32_t x = v - lo;
+    if (x < (uint32_t)kFine) {
+      atomicAdd(&hist[x], 1u);
+      ++inside;
+    }
+    below += v < lo ? 1u : 0u;
+  });
+  below = block_sum(below, &sel[2]);
+  inside = block_sum(inside, &sel[2]);
+  if (k < below || k - below >= inside) return false;
+  locate_rank_n(hist, kFine, k - below, tmp, sel);
+  const uint32_t mloc = sel[0];  // median - lo
+  __syncthreads();
+  // Deviations m < mspan have both med - m and med + m inside the window:
+  // dev[m] = #(|v - med| == m) there, formed in place after the window
+  // histogram is read into registers.
+  const int mspan = (int)min(mloc + 1u, (uint32_t)kFine - mloc);
+  uint32_t devc[kFine / kThreads];
+  uint32_t part = 0;
+#pragma unroll
+  for (int q = 0; q < kFine / kThreads; ++q) {
+    const int m = threadIdx.x + kThreads * q;
+    uint32_t c = 0;
+    if (m < mspan) {
+      c = hist[mloc - m];
+      if (m > 0) c += hist[mloc + m];
+    }
+    devc[q] = c;
+    part += c;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kFine / kThreads; ++q) hist[threadIdx.x + kThreads * q] = devc[q];
+  // #(|v - med| < mspan) must exceed k for the MAD to lie below mspan
+  if (block_sum(part, &sel[2]) < k + 1) return false;
+  locate_rank_n(hist, mspan, k, tmp, sel);
+  med = lo + mloc;
+  mad = sel[0];
+  return true;
+}
+
+// The two-read path (and the wide-row fallback beyond it).
+__device__ void row_stats_two_pass(const uint32_t *__restrict__ row, int64_t nout, int shift,
+                                   bool vec, uint32_t *hist, uint32_t *tmp, uint32_t *sel,
+                                   uint32_t &med, uint32_t &mad) {
   // Pass 1: histogram of the high bits (4096 bins of width 2^shift) gives the
   // bin b holding the median and, from the counts around b, a bound on the
   // MAD.  Pass 2: an exact histogram of the values in the window of coarse
   // bins [b - r - 1, b + r + 1] gives the median and then the MAD, whose
   // deviations all fall inside the window.  Rows whose window would not fit
   // in LDS fall back to two more passes over |Y - med|.
-  __shared__ uint32_t hist[kFine];
-  __shared__ uint32_t tmp[16];
-  __shared__ uint32_t sel[2];
   __shared__ int radius;
-  const bool vec = ((reinterpret_cast<uintptr_t>(row) & 15) == 0);
   const uint32_t k = (uint32_t)((nout - 1) / 2);
   const uint32_t width = 1u << shift;
 
@@ -168,7 +298,6 @@ __device__ void row_stats_row(const uint32_t *__restrict__ row, int64_t nout, in
   }
   __syncthreads();
 
-  uint32_t med, mad;
   if (nwin <= kFine) {
     const uint32_t lo = (uint32_t)lo_bin << shift;
     for (int i = threadIdx.x; i < kFine; i += kThreads) hist[i] = 0u;
@@ -236,6 +365,20 @@ __device__ void row_stats_row(const uint32_t *__restrict__ row, int64_t nout, in
     __syncthreads();
     locate_rank(hist, rank_in, tmp, sel);
     mad = (hb << shift) | sel[0];
+  }
+}
+
+// Median and MAD of one row (the whole workgroup), written to out[0..1].
+__device__ void row_stats_row(const uint32_t *__restrict__ row, int64_t nout, int shift,
+                              int32_t *__restrict__ out) {
+  __shared__ uint32_t hist[kFine];
+  __shared__ uint32_t tmp[16];
+  __shared__ uint32_t sel[3];
+  const bool vec = ((reinterpret_cast<uintptr_t>(row) & 15) == 0);
+  uint32_t med, mad;
+  if (!row_stats_one_pass(row, nout, shift, vec, hist, tmp, sel, med, mad)) {
+    __syncthreads();
+    row_stats_two_pass(row, nout, shift, vec, hist, tmp, sel, med, mad);
   }
   if (threadIdx.x == 0) {
     out[0] = (int32_t)med;

@@ -338,8 +338,14 @@ def test_detect_dense_chains(sps, radius):
     assert np.array_equal(cands["dm_idx"], co["d"]) and np.array_equal(cands["t_idx"], co["t"])
 
 
-@pytest.mark.parametrize("case", ["noise", "narrow", "near_zero", "near_top", "spiky"])
+@pytest.mark.parametrize("case", ["noise", "narrow", "near_zero", "near_top", "spiky", "step",
+                                  "trimodal", "short"])
 def test_stats_windowed_rows(sps, case):
+    """Rows whose sampled window holds the median and the MAD (noise, narrow,
+    windows clipped at 0 and past the top), a row whose sample misleads (a
+    step whose lower 45 % hold half the sampled runs) and one whose MAD lies
+    far outside the window (three narrow clusters): the last two are decided
+    by the exact fallback reads."""
     rng = np.random.Generator(np.random.PCG64(len(case)))
     nchan, ndm, nout = 4096, 6, 50000
     vmax = 255 * nchan
@@ -351,9 +357,18 @@ def test_stats_windowed_rows(sps, case):
         Y = np.abs(rng.normal(0, 700, (ndm, nout)))
     elif case == "near_top":
         Y = vmax - np.abs(rng.normal(0, 900, (ndm, nout)))
-    else:
+    elif case == "spiky":
         Y = rng.normal(500000, 800, (ndm, nout))
         Y[:, ::7] += rng.uniform(0, 200000, Y[:, ::7].shape)
+    elif case == "step":
+        Y = rng.normal(500000, 50, (ndm, nout))
+        Y[:, :nout * 45 // 100] = rng.normal(100000, 50, (ndm, nout * 45 // 100))
+    elif case == "trimodal":
+        centre = rng.choice([100000, 500000, 900000], p=[0.35, 0.3, 0.35], size=(ndm, nout))
+        Y = centre + rng.integers(-5, 6, size=(ndm, nout))
+    else:  # shorter than the sample: the whole row is the sample
+        nout = 3001
+        Y = rng.normal(400000, 2000, (ndm, nout))
     Y = np.clip(np.rint(Y), 0, vmax).astype(np.uint32)
     sto = oracle.stats(Y)
     wl = Workload("s", nchan, 1000.0, 1500.0, 1e-4, nout, ndm, 0.0, 1.0, (1, 2, 4))
