@@ -495,7 +495,7 @@ __global__ __launch_bounds__(kThreads) void boxcar_batch_kernel(
     int tile_dm, int64_t tile_t) {
   extern __shared__ uint32_t P[];
   const int64_t blk = blockIdx.x;
-  const BeamWork &bw = beams[find_beam<&BeamWork::bx_begin>(beams, nbeams, blk)];
+  const BeamWork &bw = beams[find_beam_wave<&BeamWork::bx_begin>(beams, nbeams, blk)];
   const int64_t local = blk - bw.bx_begin;
   const int d = (int)(local / bw.nseg);
   const int seg = (int)(local - (int64_t)d * bw.nseg);
@@ -591,7 +591,7 @@ __global__ __launch_bounds__(kThreads) void boxcar_pool_batch_kernel(
   extern __shared__ uint32_t P[];
   __shared__ float pv[kSeg];
   const int64_t blk = blockIdx.x;
-  const BeamWork &bw = beams[find_beam<&BeamWork::pl_begin>(beams, nbeams, blk)];
+  const BeamWork &bw = beams[find_beam_wave<&BeamWork::pl_begin>(beams, nbeams, blk)];
   const int64_t local = blk - bw.pl_begin;
   const int ncols = (int)bw.pcols;
   const int pair = (int)(local / ncols), tj = (int)(local - (int64_t)pair * ncols);

@@ -97,18 +97,6 @@ __global__ __launch_bounds__(kTileThreads) void tile_peaks_kernel(
   tile_peak(snr, best, ndm, nout, tile_dm, tile_t, ntt, blockIdx.x, peaks + blockIdx.x);
 }
 
-// Beam b's tile peaks go to the peaks array of its scratch (scratch +
-// beams[b].det_begin).
-__global__ __launch_bounds__(kTileThreads) void tile_peaks_batch_kernel(
-    const BeamWork *__restrict__ beams, int nbeams, int ndm, int tile_dm, int64_t tile_t,
-    uint8_t *__restrict__ scratch) {
-  const int64_t blk = blockIdx.x;
-  const BeamWork &bw = beams[find_beam<&BeamWork::tp_begin>(beams, nbeams, blk)];
-  TilePeak *peaks = reinterpret_cast<TilePeak *>(scratch + bw.det_begin);
-  const int64_t local = blk - bw.tp_begin;
-  tile_peak(bw.snr, bw.best, ndm, bw.nout, tile_dm, tile_t, bw.ntt, local, peaks + local);
-}
-
 // True if a comes before b: S/N descending, then t, then d.
 __device__ __forceinline__ bool before(const TilePeak &a, const TilePeak &b) {
   if (a.snr != b.snr) return a.snr > b.snr;
@@ -421,18 +409,6 @@ hipError_t launch_select_nms(uint8_t *scratch, int ndm, int64_t nout, int tile_d
   hipLaunchKernelGGL(select_nms_kernel, dim3(1), dim3(kNmsThreads), 0, stream, scratch,
                      (int64_t)ntd * ntt, ntd, ntt, tile_dm, tile_t, threshold, nms_dm, nms_t);
   return hipGetLastError();
-}
-
-hipError_t launch_detect_batch(const BeamWork *beams, int nbeams, int ndm, int64_t total_tiles,
-                               int tile_dm, int64_t tile_t, float threshold, int nms_dm,
-                               int64_t nms_t, uint8_t *scratch, hipStream_t stream) {
-  if (total_tiles > 0x7FFFFFFF) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(tile_peaks_batch_kernel, dim3((unsigned)total_tiles), dim3(kTileThreads), 0,
-                     stream, beams, nbeams, ndm, tile_dm, tile_t, scratch);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  return launch_select_nms_batch(beams, nbeams, ndm, tile_dm, tile_t, threshold, nms_dm, nms_t,
-                                 scratch, stream);
 }
 
 hipError_t launch_select_nms_batch(const BeamWork *beams, int nbeams, int ndm, int tile_dm,

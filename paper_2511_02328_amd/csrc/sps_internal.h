@@ -98,6 +98,20 @@ __device__ __forceinline__ int find_beam(const BeamWork *beams, int nbeams, int6
   return lo;
 }
 
+// As find_beam for an item that is the same in every lane of the wave (a
+// workgroup's own index): each lane compares one beam's start, 64 beams per
+// load, so the search costs one load latency instead of a chain of them.
+// Every lane of the wave must call it.
+template <int64_t BeamWork::*F>
+__device__ __forceinline__ int find_beam_wave(const BeamWork *beams, int nbeams, int64_t item) {
+  int count = 0;
+  for (int base = 0; base < nbeams; base += 64) {
+    const int b = base + (int)(threadIdx.x & 63);
+    count += __popcll(__ballot(b < nbeams && beams[b].*F <= item));
+  }
+  return count - 1;
+}
+
 // The delay table D [ndm][nchan] in the form the staged kernels of one
 // tiling read (blocks of nd = nw dpw trials, slabs of cs rows, staged rows of
 // `pitch` bytes):
@@ -285,11 +299,6 @@ hipError_t launch_boxcar_pool(const uint32_t *Y, int ndm, int64_t nout, const in
 hipError_t launch_boxcar_pool_batch(const BeamWork *beams, int nbeams, int64_t total_blocks,
                                     const WidthList &widths, float scale, uint16_t *tiles,
                                     hipStream_t stream);
-// Batched detection: beam b's scratch (detect_layout of its tile count)
-// starts at scratch + beams[b].det_begin.
-hipError_t launch_detect_batch(const BeamWork *beams, int nbeams, int ndm, int64_t total_tiles,
-                               int tile_dm, int64_t tile_t, float threshold, int nms_dm,
-                               int64_t nms_t, uint8_t *scratch, hipStream_t stream);
 
 // Tile keys of a plane (TileSink): decode == false zeroes them; decode ==
 // true turns them into the tile peak records (S/N, d, t and the width index
