@@ -4,15 +4,25 @@
 // requested widths come from one prefix sum P of the row segment held in LDS:
 // B_w(t) = P(t + w) - P(t).  P is kept in wrapping u32 arithmetic; every
 // window sum is below 2^31 (checked on the host), so the differences are
-// exact.  The S/N numerator B_w - w med is an exact integer; it is scaled by
-// 1 / (1.4826 MAD sqrt(w)) in binary32, and the maximum over widths (ties to
-// the smallest width) is written with the index of its width.
+// exact.  The S/N numerator B_w - w med is an exact integer (with power-of-two
+// widths the staged samples have the median subtracted, so it is P'(t + w) -
+// P'(t) of the prefix of Y - med); it is scaled by 1 / (1.4826 MAD sqrt(w)) in
+// binary32, and the maximum over widths (ties to the smallest width) is
+// written with the index of its width.
 //
 // One workgroup of 256 threads covers 4096 consecutive outputs of one row
 // plus a halo of w_max - 1 samples.  Lanes run along time, so the plane reads
 // and the S/N writes are fully coalesced and the LDS reads P[t + w] of a wave
-// are consecutive words (conflict-free).  HBM-bound: one read of Y, one write
-// of snr and best_w.
+// are consecutive words (conflict-free).  Traffic is one read of Y and one
+// write of snr and best_w (9 B per output), which runs at the device's
+// streaming rate with 7 widths; with 9 widths the vector work is close to
+// the same time and the part runs at its power limit (lower clock), so each
+// width's numerator is kept to one two-operand subtraction.
+//
+// The same pass can gather the tile maxima of the detection step (64-bit
+// key of order-preserving S/N bits and in-tile position, atomicMax per
+// tile), or write the detector's max-pooled bfloat16 tiles instead of the
+// planes.
 #include <math.h>
 
 #include "sps_internal.h"
