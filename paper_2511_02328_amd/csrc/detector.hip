@@ -705,10 +705,183 @@ __global__ __launch_bounds__(256) void conv_bwd_data_kernel(const uint16_t *__re
   }
 }
 
-// Pixel blocks per wave of the backward-data kernel, per layer (entry 0
-// unused).  Measured at batch 256 against 1 everywhere: layer 1 is bound by
-// its 2-byte signal and mask traffic and gains nothing (2 was 3% slower);
-// layers 2-5 gain 10-25%.
+// Layer 1's backward data product fused with layer 0's weight and bias
+// gradients.  A block is 8 x 32 layer-0 pixels of one tile: the signal of
+// layer 1 it reads ((4 + 1) x (16 + 1) pixels, 32 channels) and the tile
+// region layer 0 read for it (17 x 65 values) are staged in LDS once, and
+// the transposed layer-1 weights once per workgroup.  Each of the four
+// parity classes of the block's pixels is a product with M = 16 channels
+// (the transposed weights), N = 16 class pixels of one class row, K = the
+// class's taps x 32 (one 16x16x32 product per tap): a wave takes one class
+// row, and loads its pixels' ReLU masks before the products.  The lane's 4
+// channels of one pixel are masked by
+// the stored layer-0 activation, rounded to bfloat16 and stored (the
+// signal of layer 0), and then, as FP32, multiply the pixel's 9 tile values
+// into the lane's layer-0 weight-gradient sums (and its bias sums).  The
+// grid is fixed (kB01Grid workgroups, each taking blocks blockIdx.x,
+// + gridDim.x, ...), so every workgroup's partial sums, written to
+// partial[wg][co][tap] and partial[wg][144 + co], are in a fixed order.
+constexpr int kB01Rows = 4, kB01Cols = 16;  // class rows / columns of a block
+constexpr int kB01Grid = 2048;
+constexpr int kB01Part = 16 * 9 + 16;       // partial sums per workgroup
+constexpr int kB01ZW = kB01Cols + 1, kB01ZP = 40;   // staged signal: pixels per row, bf16 per pixel
+constexpr int kB01TH = 4 * kB01Rows + 1, kB01TW = 4 * kB01Cols + 8;  // staged tile region
+constexpr int kB01WP = 9 * 32 + 8;  // staged transposed weights: bf16 per input channel
+
+__global__ __launch_bounds__(256) void bwd01_kernel(const uint16_t *__restrict__ dz1,
+                                                    const uint16_t *__restrict__ wt1,
+                                                    const uint16_t *__restrict__ act0,
+                                                    const uint16_t *__restrict__ tiles,
+                                                    uint16_t *__restrict__ dz0,
+                                                    float *__restrict__ partial, int nblocks) {
+  constexpr Layer L0 = kLayers[0], L1 = kLayers[1];
+  static_assert(L1.cin == 16 && L1.cout == 32 && L1.stride == 2, "layer 1 shape");
+  constexpr int BY = L0.hout / (2 * kB01Rows), BX = L0.wout / (2 * kB01Cols);
+  static_assert(L0.hout % (2 * kB01Rows) == 0 && L0.wout % (2 * kB01Cols) == 0, "whole blocks");
+  __shared__ __attribute__((aligned(16))) uint16_t zs[(kB01Rows + 1) * kB01ZW * kB01ZP];
+  __shared__ __attribute__((aligned(16))) uint16_t ts[kB01TH * kB01TW];
+  __shared__ __attribute__((aligned(16))) uint16_t ws[16 * kB01WP];
+  __shared__ float red[4][4][40];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, c16 = lane & 15;
+  // transposed weights [ci][tap * 32 + co]; a lane's A fragment of a tap is
+  // row ci = c16, K = channels 8g .. 8g+7 of layer 1's signal
+  for (int v = threadIdx.x; v < 16 * 36; v += 256)
+    *reinterpret_cast<u32x4 *>(&ws[(v / 36) * kB01WP + 8 * (v % 36)]) =
+        *reinterpret_cast<const u32x4 *>(wt1 + 8 * v);
+  float accw[4][9], accb[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    accb[j] = 0.f;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) accw[j][t] = 0.f;
+  }
+  for (int blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
+    const int nn = blk / (BY * BX), r = blk % (BY * BX);
+    const int Y0 = (r / BX) * 2 * kB01Rows, X0 = (r % BX) * 2 * kB01Cols;
+    __syncthreads();  // the previous block's readers are done
+    // layer 1's signal at rows Y0/2 + i (i <= kB01Rows), columns X0/2 + j
+    // (j <= kB01Cols), zero outside the image
+    for (int v = threadIdx.x; v < (kB01Rows + 1) * kB01ZW * 4; v += 256) {
+      const int pix = v >> 2, q = v & 3;
+      const int oy = Y0 / 2 + pix / kB01ZW, ox = X0 / 2 + pix % kB01ZW;
+      u32x4 d = {0u, 0u, 0u, 0u};
+      if (oy < L1.hout && ox < L1.wout)
+        d = *reinterpret_cast<const u32x4 *>(dz1 + ((int64_t)(nn * L1.hout + oy) * L1.wout + ox) *
+                                                       32 + 8 * q);
+      *reinterpret_cast<u32x4 *>(&zs[pix * kB01ZP + 8 * q]) = d;
+    }
+    // tile rows 2 Y0 - 1 + i, columns from 2 X0 - 8 (16-byte chunks)
+    for (int v = threadIdx.x; v < kB01TH * (kB01TW / 8); v += 256) {
+      const int i = v / (kB01TW / 8), k = v % (kB01TW / 8);
+      const int ty = 2 * Y0 - 1 + i, tx = 2 * X0 - 8 + 8 * k;
+      u32x4 d = {0u, 0u, 0u, 0u};
+      if (ty >= 0 && ty < L0.hin && tx >= 0 && tx < L0.win)
+        d = *reinterpret_cast<const u32x4 *>(tiles + ((int64_t)nn * L0.hin + ty) * L0.win + tx);
+      *reinterpret_cast<u32x4 *>(&ts[i * kB01TW + 8 * k]) = d;
+    }
+    // the stored layer-0 activations of the lane's pixels (the ReLU masks),
+    // all loaded before the products so that their latency overlaps
+    uint2 am[kB01Rows / 4][4];
+#pragma unroll
+    for (int h = 0; h < kB01Rows / 4; ++h)
+#pragma unroll
+      for (int cls = 0; cls < 4; ++cls) {
+        const int iy = Y0 + 2 * (wave * (kB01Rows / 4) + h) + (cls >> 1);
+        const int ix = X0 + 2 * c16 + (cls & 1);
+        am[h][cls] = *reinterpret_cast<const uint2 *>(
+            act0 + (((int64_t)nn * L0.hout + iy) * L0.wout + ix) * 16 + 4 * g);
+      }
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < kB01Rows / 4; ++h) {
+      const int cy = wave * (kB01Rows / 4) + h;
+#pragma unroll
+      for (int cls = 0; cls < 4; ++cls) {
+        const int py = cls >> 1, px = cls & 1;
+        floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+        // taps (ky, kx) whose parity matches the class: an input pixel of
+        // parity p is read through ky = 1 (p = 0) or ky = 0, 2 (p = 1)
+#pragma unroll
+        for (int ky = 0; ky < 3; ++ky) {
+          if (((py + 1 - ky) & 1) != 0) continue;
+#pragma unroll
+          for (int kx = 0; kx < 3; ++kx) {
+            if (((px + 1 - kx) & 1) != 0) continue;
+            const int zr = cy + (py + 1 - ky) / 2, zc = c16 + (px + 1 - kx) / 2;
+            const u32x4 b = *reinterpret_cast<const u32x4 *>(&zs[(zr * kB01ZW + zc) * kB01ZP + 8 * g]);
+            const u32x4 a =
+                *reinterpret_cast<const u32x4 *>(&ws[c16 * kB01WP + (ky * 3 + kx) * 32 + 8 * g]);
+            acc = mfma(a, b, acc);
+          }
+        }
+        const int iy = Y0 + 2 * cy + py, ix = X0 + 2 * c16 + px;
+        const int64_t o = (((int64_t)nn * L0.hout + iy) * L0.wout + ix) * 16 + 4 * g;
+        const uint2 a = am[h][cls];
+        const uint16_t ah[4] = {(uint16_t)(a.x & 0xFFFFu), (uint16_t)(a.x >> 16),
+                                (uint16_t)(a.y & 0xFFFFu), (uint16_t)(a.y >> 16)};
+        uint16_t zq[4];
+        float zf[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          zq[j] = bf_positive(ah[j]) ? f2bf(acc[j]) : (uint16_t)0;
+          zf[j] = bf2f(zq[j]);
+          accb[j] += zf[j];
+        }
+        *reinterpret_cast<uint2 *>(dz0 + o) =
+            make_uint2((uint32_t)zq[0] | ((uint32_t)zq[1] << 16),
+                       (uint32_t)zq[2] | ((uint32_t)zq[3] << 16));
+        // the tile values layer 0 read for this pixel: (2 iy + ky - 1,
+        // 2 ix + kx - 1), staged at (2 (iy - Y0) + ky, 2 (ix - X0) + kx + 7)
+        const uint16_t *tp = ts + (2 * (iy - Y0)) * kB01TW + 2 * (ix - X0) + 7;
+#pragma unroll
+        for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+          for (int kx = 0; kx < 3; ++kx) {
+            const float tv = bf2f(tp[ky * kB01TW + kx]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) accw[j][ky * 3 + kx] = fmaf(zf[j], tv, accw[j][ky * 3 + kx]);
+          }
+        // one class at a time: its loads are not hoisted into the previous
+        // class's work (which would hold every class's temporaries live)
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+  }
+  // workgroup sums, fixed order: the 16 lanes of a channel group
+  // (butterfly), then the 4 waves
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) {
+      accb[j] += __shfl_xor(accb[j], o, 64);
+#pragma unroll
+      for (int t = 0; t < 9; ++t) accw[j][t] += __shfl_xor(accw[j][t], o, 64);
+    }
+  }
+  if (c16 == 0) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+#pragma unroll
+      for (int t = 0; t < 9; ++t) red[wave][g][j * 9 + t] = accw[j][t];
+      red[wave][g][36 + j] = accb[j];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < kB01Part) {
+    const int i = threadIdx.x;
+    // weights: co = i / 9, tap = i % 9; bias: co = i - 144
+    const int co = i < 144 ? i / 9 : i - 144;
+    const int slot = i < 144 ? (co % 4) * 9 + i % 9 : 36 + co % 4;
+    float s = 0.f;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) s += red[w][co / 4][slot];
+    partial[(int64_t)blockIdx.x * kB01Part + i] = s;
+  }
+}
+
+// Pixel blocks per wave of the backward-data kernel, per layer (entries 0
+// and 1 unused: layer 1 takes the fused kernel above).  Measured at batch
+// 256 against 1 everywhere: layers 2-5 gain 10-25%.
 constexpr int kBwdMB[kNumLayers] = {1, 1, 2, 4, 2, 2};
 
 // ---------------------------------------------------------------------------
@@ -802,64 +975,6 @@ __global__ __launch_bounds__(256) void conv_bwd_weight_kernel(const uint16_t *__
   }
 }
 
-// First layer's weight gradient on the vector ALU: grid (2, nsplit), the
-// x index picking 8 of the 16 output channels.  Each thread reads a pixel's
-// 8 signals once and its 9 inputs, accumulates 8 x 9 products, and the
-// block reduces.  partial[split][co][tap] (CIN = 1).
-__global__ __launch_bounds__(256) void conv0_bwd_weight_kernel(const uint16_t *__restrict__ dz,
-                                                               const uint16_t *__restrict__ x,
-                                                               float *__restrict__ partial,
-                                                               int64_t npix_out, int64_t chunk) {
-  constexpr Layer L = kLayers[0];
-  __shared__ float red[72][65];
-  const int half = blockIdx.x;
-  const int64_t split = blockIdx.y;
-  const int64_t pbeg = split * chunk;
-  const int64_t pend = pbeg + chunk < npix_out ? pbeg + chunk : npix_out;
-  float acc[8][9];
-#pragma unroll
-  for (int c = 0; c < 8; ++c)
-#pragma unroll
-    for (int t = 0; t < 9; ++t) acc[c][t] = 0.f;
-  for (int64_t q = pbeg + threadIdx.x; q < pend; q += 256) {
-    const int64_t n = q / (L.hout * L.wout);
-    const int r = (int)(q - n * L.hout * L.wout);
-    const int oy = r / L.wout, ox = r % L.wout;
-    const u32x4 d = *reinterpret_cast<const u32x4 *>(dz + q * 16 + half * 8);
-    const uint16_t *h = reinterpret_cast<const uint16_t *>(&d);
-    float dv[8];
-#pragma unroll
-    for (int c = 0; c < 8; ++c) dv[c] = bf2f(h[c]);
-#pragma unroll
-    for (int t = 0; t < 9; ++t) {
-      const int iy = 2 * oy + t / 3 - 1, ix = 2 * ox + t % 3 - 1;
-      const float xv = (iy >= 0 && iy < L.hin && ix >= 0 && ix < L.win)
-                           ? bf2f(x[(n * L.hin + iy) * L.win + ix])
-                           : 0.0f;
-#pragma unroll
-      for (int c = 0; c < 8; ++c) acc[c][t] = fmaf(dv[c], xv, acc[c][t]);
-    }
-  }
-  // waves add their lanes' sums into LDS one after another (fixed order)
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int w = 0; w < 4; ++w) {
-    if (wave == w) {
-#pragma unroll
-      for (int c = 0; c < 8; ++c)
-#pragma unroll
-        for (int t = 0; t < 9; ++t)
-          red[c * 9 + t][lane] = (w == 0 ? 0.f : red[c * 9 + t][lane]) + acc[c][t];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x < 72) {
-    float s = 0.f;
-    for (int k = 0; k < 64; ++k) s += red[threadIdx.x][k];
-    const int c = threadIdx.x / 9, t = threadIdx.x % 9;
-    partial[(split * 16 + half * 8 + c) * 9 + t] = s;
-  }
-}
-
 // part[block][co] = sum over the block's pixels of dz[q][co].  A thread owns
 // one 16-byte group of 8 channels and strides over pixels (the stride is a
 // multiple of the groups per pixel, so its group never changes); the block
@@ -896,7 +1011,7 @@ constexpr int kBiasBlocks = 1024;
 // one: tmp[g][i] = sum of partial[k][i] over the g-th of kWGroups contiguous
 // ranges of splits (grid (ceil(W / 256), kWGroups)); threads walk the
 // partials in their own layout so that the loads coalesce.  Level two:
-// grads[co][ci][tap] = sum_g tmp[g][i].
+// grads[co][ci][tap] = sum_g tmp[g][i] (tmp rows `stride` floats apart).
 constexpr int kWGroups = 32;
 
 __global__ __launch_bounds__(256) void reduce_weight_partial_kernel(
@@ -912,7 +1027,7 @@ __global__ __launch_bounds__(256) void reduce_weight_partial_kernel(
 }
 
 __global__ __launch_bounds__(256) void reduce_weight_kernel(const float *__restrict__ tmp,
-                                                            int cout, int cin,
+                                                            int64_t stride, int cout, int cin,
                                                             float *__restrict__ grad) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t total = (int64_t)cout * cin * 9;
@@ -921,7 +1036,7 @@ __global__ __launch_bounds__(256) void reduce_weight_kernel(const float *__restr
   const int rem = (int)(i - (int64_t)co * 9 * cin);
   const int tap = rem / cin, ci = rem % cin;
   float s = 0.f;
-  for (int g = 0; g < kWGroups; ++g) s += tmp[(int64_t)g * total + i];
+  for (int g = 0; g < kWGroups; ++g) s += tmp[(int64_t)g * stride + i];
   grad[((int64_t)co * cin + ci) * 9 + tap] = s;
 }
 
@@ -1003,12 +1118,17 @@ constexpr int64_t kParams = head_param_offset() + kHead * kFeat + kHead;
 
 int64_t npix_out(int li, int n) { return (int64_t)n * kLayers[li].hout * kLayers[li].wout; }
 int64_t npix_in(int li, int n) { return (int64_t)n * kLayers[li].hin * kLayers[li].win; }
+// Blocks and workgroups of the fused layer-1 / layer-0 backward kernel.
+int b01_blocks(int n) {
+  return n * (kLayers[0].hout / (2 * kB01Rows)) * (kLayers[0].wout / (2 * kB01Cols));
+}
+int b01_grid(int n) { return b01_blocks(n) < kB01Grid ? b01_blocks(n) : kB01Grid; }
 
 // Workgroups of a layer's weight-gradient kernel along its other grid
-// dimension (taps or channel halves): 9 / taps per workgroup for layers
-// 1..5, 2 for the first layer.
+// dimension (9 / taps per workgroup) for layers 1..5; layer 0's gradients
+// come from the fused kernel (entry unused).
 int wgrad_groups(int li) {
-  static const int g[kNumLayers] = {2, 1, 1, 9, 9, 9};
+  static const int g[kNumLayers] = {1, 1, 1, 9, 9, 9};
   return g[li];
 }
 
@@ -1161,11 +1281,19 @@ sps_status run_backward(sps_cnn c, const uint16_t *tiles, int32_t n, hipStream_t
     const int64_t nsplit = (np + chunk - 1) / chunk;
     const uint16_t *xin = li == 0 ? tiles : c->act[li - 1];
     float *gw = c->grads + layer_param_offset(li);
+    if (li == 0) {
+      // layer 0's gradients were summed by the fused kernel of layer 1
+      const int nwg = b01_grid(n);
+      hipLaunchKernelGGL(reduce_weight_partial_kernel, dim3(1, kWGroups), dim3(256), 0, s,
+                         c->partial, nwg, (int64_t)kB01Part, c->wtmp);
+      hipLaunchKernelGGL(reduce_weight_kernel, dim3(1), dim3(256), 0, s, c->wtmp,
+                         (int64_t)kB01Part, 16, 1, gw);
+      hipLaunchKernelGGL(reduce_rows_kernel, dim3(16), dim3(256), 0, s, c->wtmp + 144, kWGroups,
+                         kB01Part, gw + L.wcount());
+      SPS_LAUNCH_CHECK("backward launch");
+      continue;
+    }
     switch (li) {
-      case 0:
-        hipLaunchKernelGGL(conv0_bwd_weight_kernel, dim3(2, (unsigned)nsplit), dim3(256), 0, s,
-                           c->dz[0], xin, c->partial, np, chunk);
-        break;
 #define SPS_BWDW(LI, TAPS)                                                                   \
   case LI:                                                                                   \
     hipLaunchKernelGGL((conv_bwd_weight_kernel<LI, TAPS>), dim3(9 / TAPS, (unsigned)nsplit),  \
@@ -1178,13 +1306,12 @@ sps_status run_backward(sps_cnn c, const uint16_t *tiles, int32_t n, hipStream_t
                        dim3((unsigned)((L.wcount() + 255) / 256), kWGroups), dim3(256), 0, s,
                        c->partial, (int)nsplit, L.wcount(), c->wtmp);
     hipLaunchKernelGGL(reduce_weight_kernel, dim3((unsigned)((L.wcount() + 255) / 256)), dim3(256),
-                       0, s, c->wtmp, L.cout, L.cin, gw);
+                       0, s, c->wtmp, L.wcount(), L.cout, L.cin, gw);
     {
       const int64_t nvec = np * (L.cout / 8);
       int64_t nb = (nvec + 255) / 256;
       nb = nb < kBiasBlocks ? nb : kBiasBlocks;
       switch (L.cout) {
-        case 16: hipLaunchKernelGGL(bias_partial_kernel<16>, dim3((unsigned)nb), dim3(256), 0, s, c->dz[li], np, c->bpart); break;
         case 32: hipLaunchKernelGGL(bias_partial_kernel<32>, dim3((unsigned)nb), dim3(256), 0, s, c->dz[li], np, c->bpart); break;
         case 64: hipLaunchKernelGGL(bias_partial_kernel<64>, dim3((unsigned)nb), dim3(256), 0, s, c->dz[li], np, c->bpart); break;
         default: hipLaunchKernelGGL(bias_partial_kernel<128>, dim3((unsigned)nb), dim3(256), 0, s, c->dz[li], np, c->bpart); break;
@@ -1192,7 +1319,11 @@ sps_status run_backward(sps_cnn c, const uint16_t *tiles, int32_t n, hipStream_t
       hipLaunchKernelGGL(reduce_rows_kernel, dim3((unsigned)L.cout), dim3(256), 0, s, c->bpart, (int)nb, L.cout,
                          gw + L.wcount());
     }
-    if (li > 0) {
+    if (li == 1) {
+      const int nblocks = b01_blocks(n);
+      hipLaunchKernelGGL(bwd01_kernel, dim3((unsigned)b01_grid(n)), dim3(256), 0, s, c->dz[1],
+                         c->wt[1], c->act[0], tiles, c->dz[0], c->partial, nblocks);
+    } else if (li > 1) {
       const int classes = L.stride == 2 ? 4 : 1;
       const int64_t ncls = npix_in(li, n) / classes;
       switch (li) {
@@ -1204,7 +1335,7 @@ sps_status run_backward(sps_cnn c, const uint16_t *tiles, int32_t n, hipStream_t
                        c->wt[LI], c->act[LI - 1], c->dz[LI - 1], n);                          \
     break;                                                                                    \
   }
-        SPS_BWDD(1) SPS_BWDD(2) SPS_BWDD(3) SPS_BWDD(4) SPS_BWDD(5)
+        SPS_BWDD(2) SPS_BWDD(3) SPS_BWDD(4) SPS_BWDD(5)
 #undef SPS_BWDD
       }
     }
@@ -1243,6 +1374,7 @@ sps_status sps_cnn_create(int32_t max_batch, sps_cnn *out) {
     pmax = ns * kLayers[i].wcount() > pmax ? ns * kLayers[i].wcount() : pmax;
     c->bpart_cap = ns * kLayers[i].cout > c->bpart_cap ? ns * kLayers[i].cout : c->bpart_cap;
   }
+  pmax = (int64_t)kB01Grid * kB01Part > pmax ? (int64_t)kB01Grid * kB01Part : pmax;
   c->partial_cap = pmax;
   c->bpart_cap = (int64_t)kBiasBlocks * 128;
   const int64_t nblk = ((int64_t)max_batch * kCells + 127) / 128;
