@@ -888,16 +888,46 @@ constexpr int kBwdMB[kNumLayers] = {1, 1, 2, 4, 2, 2};
 // Backward: weights and biases
 // ---------------------------------------------------------------------------
 
-constexpr int kKP = 32;       // pixels per staged K-step
-constexpr int kLdsRow = 40;   // bf16 per LDS row (32 + 8 padding)
+constexpr int kKP = 32;  // pixels per staged K-step
+
+// bf16 per staged pixel row for C channels: the 4 rows that one group of 16
+// lanes reads in a transposed read then fall in disjoint LDS banks (row
+// strides of 8, 24, 40 or 72 dwords).
+constexpr int wg_row(int c) { return c >= 32 ? c + 16 : c; }
+
+typedef short i16x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) i16x4 lds_i16x4;
+
+// An MFMA operand with K = 8 consecutive staged pixels: the lane's 16-lane
+// group g reads pixels k0 + 8g .. + 7 of channel c0 + (lane % 16) from a
+// [pixel][channel] array with rows of `row` bf16.  A transposed read
+// (ds_read_b64_tr_b16) gives lane o of a 16-lane group, as its element k
+// (k < 4), element o & 3 of the 8 bytes that lane (o >> 2) + 4k of the
+// group addresses.  With lane s pointing at pixel k0 + 8g + (s >> 2) (+ 4
+// for the second read), channels c0 + 4 (s & 3) .. + 3, lane o therefore
+// receives channel c0 + o of 4 consecutive pixels.
+__device__ __forceinline__ u32x4 tr_operand(const uint16_t *base, int row, int k0, int c0,
+                                            int lane) {
+  const int g = lane >> 4, s = lane & 15;
+  const uint16_t *p = base + (k0 + 8 * g + (s >> 2)) * row + c0 + 4 * (s & 3);
+  const i16x4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_i16x4 *)p);
+  const i16x4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_i16x4 *)(p + 4 * row));
+  u32x4 r;
+  r.x = (uint32_t)(uint16_t)lo[0] | ((uint32_t)(uint16_t)lo[1] << 16);
+  r.y = (uint32_t)(uint16_t)lo[2] | ((uint32_t)(uint16_t)lo[3] << 16);
+  r.z = (uint32_t)(uint16_t)hi[0] | ((uint32_t)(uint16_t)hi[1] << 16);
+  r.w = (uint32_t)(uint16_t)hi[2] | ((uint32_t)(uint16_t)hi[3] << 16);
+  return r;
+}
 
 // partial[split][co][tap][ci] = sum over the split's output pixels q of
 // dz[q][co] * x[input of q through tap][ci], layers 1..5.  M = COUT,
-// N = CIN, K = pixels, staged 32 pixels at a time through LDS in transposed
-// form so that each lane's 8 K-values are one 16-byte read.  A workgroup
-// handles TAPS taps (grid (9 / TAPS, nsplit)): all 9 for the narrow layers,
-// where the staged signal tile is then shared by every tap, one for the
-// wide layers, whose accumulators would not fit nine times.
+// N = CIN, K = pixels, staged 32 pixels at a time through LDS in their
+// natural [pixel][channel] layout with 16-byte copies; each lane's 8
+// K-values come from two transposed LDS reads.  A workgroup handles TAPS
+// taps (grid (9 / TAPS, nsplit)): all 9 for the narrow layers, where the
+// staged signal tile is then shared by every tap, one for the wide layers,
+// whose accumulators would not fit nine times.
 template <int LI, int TAPS>
 __global__ __launch_bounds__(256) void conv_bwd_weight_kernel(const uint16_t *__restrict__ dz,
                                                               const uint16_t *__restrict__ x,
@@ -907,8 +937,9 @@ __global__ __launch_bounds__(256) void conv_bwd_weight_kernel(const uint16_t *__
   constexpr int CIN = L.cin, COUT = L.cout, S = L.stride;
   constexpr int MB = COUT / 16, NB = CIN / 16, NBLK = MB * NB * TAPS;
   constexpr int PER_WAVE = (NBLK + 3) / 4;
-  __shared__ __attribute__((aligned(16))) uint16_t dzT[COUT][kLdsRow];
-  __shared__ __attribute__((aligned(16))) uint16_t xT[TAPS][CIN][kLdsRow];
+  constexpr int ZR = wg_row(COUT), XR = wg_row(CIN);
+  __shared__ __attribute__((aligned(16))) uint16_t dzs[kKP * ZR];
+  __shared__ __attribute__((aligned(16))) uint16_t xs[TAPS][kKP * XR];
   const int tap0 = blockIdx.x * TAPS;
   const int64_t split = blockIdx.y;
   const int64_t pbeg = split * chunk;
@@ -923,9 +954,7 @@ __global__ __launch_bounds__(256) void conv_bwd_weight_kernel(const uint16_t *__
       const int64_t q = p0 + pix;
       u32x4 d = {0u, 0u, 0u, 0u};
       if (q < pend) d = *reinterpret_cast<const u32x4 *>(dz + q * COUT + c8);
-      const uint16_t *h = reinterpret_cast<const uint16_t *>(&d);
-#pragma unroll
-      for (int i = 0; i < 8; ++i) dzT[c8 + i][pix] = h[i];
+      *reinterpret_cast<u32x4 *>(&dzs[pix * ZR + c8]) = d;
     }
     for (int v = threadIdx.x; v < TAPS * kKP * CIN / 8; v += 256) {
       const int tt = v / (kKP * CIN / 8);
@@ -941,9 +970,7 @@ __global__ __launch_bounds__(256) void conv_bwd_weight_kernel(const uint16_t *__
         if (iy >= 0 && iy < L.hin && ix >= 0 && ix < L.win)
           d = *reinterpret_cast<const u32x4 *>(x + ((n * L.hin + iy) * L.win + ix) * CIN + c8);
       }
-      const uint16_t *h = reinterpret_cast<const uint16_t *>(&d);
-#pragma unroll
-      for (int i = 0; i < 8; ++i) xT[tt][c8 + i][pix] = h[i];
+      *reinterpret_cast<u32x4 *>(&xs[tt][pix * XR + c8]) = d;
     }
     __syncthreads();
 #pragma unroll
@@ -952,8 +979,8 @@ __global__ __launch_bounds__(256) void conv_bwd_weight_kernel(const uint16_t *__
       if (blk < NBLK) {
         const int tt = blk / (MB * NB), rb = blk % (MB * NB);
         const int mb = rb / NB, nb = rb % NB;
-        const u32x4 av = *reinterpret_cast<const u32x4 *>(&dzT[mb * 16 + (lane & 15)][8 * g]);
-        const u32x4 bv = *reinterpret_cast<const u32x4 *>(&xT[tt][nb * 16 + (lane & 15)][8 * g]);
+        const u32x4 av = tr_operand(dzs, ZR, 0, mb * 16, lane);
+        const u32x4 bv = tr_operand(xs[tt], XR, 0, nb * 16, lane);
         acc[b] = mfma(av, bv, acc[b]);
       }
     }
