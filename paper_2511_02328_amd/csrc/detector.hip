@@ -609,100 +609,128 @@ __global__ __launch_bounds__(128) void head_loss_kernel(
 // Backward: data
 // ---------------------------------------------------------------------------
 
-// dx[p][ci] = bf16(mask(x[p][ci]) * sum_{tap, co} W[co][ci][tap] dz[q(p, tap)][co])
-// for layers 1..5, where q(p, tap) is the output pixel that reads input p
-// through tap (if any).  M = input pixels, N = CIN, K = taps x COUT.
-// With stride 2 an input pixel is read only through the taps whose offset
-// has its parity (1, 2 or 4 of the 9), so the input pixels are taken in
-// four parity classes (blockIdx.y) and every workgroup loops over its
-// class's taps only.  With stride 1 there is one class with all 9 taps.
-template <int LI, int MB>
-__global__ __launch_bounds__(256) void conv_bwd_data_kernel(const uint16_t *__restrict__ dz,
-                                                            const uint16_t *__restrict__ wt,
-                                                            const uint16_t *__restrict__ x,
-                                                            uint16_t *__restrict__ dx, int n) {
+// Backward data of layers 2..5 as an implicit GEMM with the signal staged
+// in LDS: dx[p][ci] = bf16(mask(x[p][ci]) * sum_{tap, co} W[co][ci][tap]
+// dz[q(p, tap)][co]).  A workgroup owns RPW x 16 class pixels of each parity
+// class (stride 2: input pixels (Y0 + 2 cy + py, X0 + 2 cx + px); stride 1:
+// one class, (Y0 + cy, X0 + cx)) and stages the signal region they read,
+// zero outside the image.  Each class is a product with M = input channels
+// (the transposed weights, [ci][tap * COUT + co], straight from L2), N = 16
+// class pixels of a class row, K = the class's taps x COUT.  The 4 waves
+// split the M blocks (WMG groups) and the class rows (4 / WMG groups), so a
+// weight fragment serves every class row of the wave.  A lane ends with 4
+// consecutive channels of one pixel: 8-byte mask loads and signal stores.
+template <int LI, int WMG, int RPW>
+__global__ __launch_bounds__(256) void bwd_data_lds_kernel(const uint16_t *__restrict__ dz,
+                                                           const uint16_t *__restrict__ wt,
+                                                           const uint16_t *__restrict__ x,
+                                                           uint16_t *__restrict__ dx) {
   constexpr Layer L = kLayers[LI];
-  constexpr int CIN = L.cin, COUT = L.cout, S = L.stride, NB = CIN / 16, K = 9 * COUT;
-  // class geometry: rows/columns of input pixels with parity (py, px)
-  const int py = S == 2 ? (int)(blockIdx.y >> 1) : 0, px = S == 2 ? (int)(blockIdx.y & 1) : 0;
-  constexpr int CH = S == 2 ? L.hin / 2 : L.hin, CW = S == 2 ? L.win / 2 : L.win;
-  const int64_t ncls = (int64_t)n * CH * CW;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4;
-  // a wave owns MB blocks of 16 class pixels; the weight fragments of a
-  // (tap, channel step) are loaded once for all of them
-  const int64_t cbase = (int64_t)blockIdx.x * (64 * MB) + wave * (16 * MB);
-  // the taps of this class: ky with (iy + 1 - ky) divisible by S, same for kx
-  int kys[3], kxs[3], nky = 0, nkx = 0;
-  for (int k = 0; k < 3; ++k) {
-    if (S == 1 || ((py + 1 - k) & 1) == 0) kys[nky++] = k;
-    if (S == 1 || ((px + 1 - k) & 1) == 0) kxs[nkx++] = k;
+  constexpr int CIN = L.cin, COUT = L.cout, S = L.stride;
+  constexpr int WRG = 4 / WMG, CR = WRG * RPW;       // class rows of a block
+  constexpr int MBW = CIN / 16 / WMG;                 // M blocks of a wave
+  static_assert(CIN % (16 * WMG) == 0 && MBW >= 1, "M blocks split evenly");
+  constexpr int BH = S * CR, BW = S * 16;             // input pixels of a block
+  static_assert(L.hin % BH == 0 && L.win % BW == 0, "whole blocks");
+  constexpr int NBY = L.hin / BH, NBX = L.win / BW;
+  // staged signal region: stride 2 rows Y0/2 .. Y0/2 + CR, columns X0/2 ..
+  // X0/2 + 16; stride 1 rows Y0 - 1 .. Y0 + CR, columns X0 - 1 .. X0 + 16
+  constexpr int ZH = S == 2 ? CR + 1 : CR + 2, ZW = S == 2 ? 17 : 18, ZP = COUT + 8;
+  constexpr int K = 9 * COUT;
+  __shared__ __attribute__((aligned(16))) uint16_t zs[ZH * ZW * ZP];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, c16 = lane & 15;
+  const int wm = wave % WMG, wr = wave / WMG;
+  const int blk = blockIdx.x;
+  const int nn = blk / (NBY * NBX), rb = blk % (NBY * NBX);
+  const int Y0 = (rb / NBX) * BH, X0 = (rb % NBX) * BW;
+  const int zy0 = S == 2 ? Y0 / 2 : Y0 - 1, zx0 = S == 2 ? X0 / 2 : X0 - 1;
+  for (int v = threadIdx.x; v < ZH * ZW * (COUT / 8); v += 256) {
+    const int pix = v / (COUT / 8), c8 = (v % (COUT / 8)) * 8;
+    const int oy = zy0 + pix / ZW, ox = zx0 + pix % ZW;
+    u32x4 d = {0u, 0u, 0u, 0u};
+    if (oy >= 0 && oy < L.hout && ox >= 0 && ox < L.wout)
+      d = *reinterpret_cast<const u32x4 *>(dz + ((int64_t)(nn * L.hout + oy) * L.wout + ox) *
+                                                    COUT + c8);
+    *reinterpret_cast<u32x4 *>(&zs[pix * ZP + c8]) = d;
   }
-  bool valid[MB];
-  int64_t nn[MB];
-  int iy[MB], ix[MB];
+  __syncthreads();
+  // A fragments: row ci = (wm * MBW + m) * 16 + c16, K = channels 8g..8g+7
+  // of a 32-channel step
+  const uint16_t *wrow = wt + (int64_t)(wm * MBW * 16 + c16) * K + 8 * g;
 #pragma unroll
-  for (int mb = 0; mb < MB; ++mb) {
-    const int64_t cidx = cbase + mb * 16 + (lane & 15);
-    valid[mb] = cidx < ncls;
-    nn[mb] = 0;
-    iy[mb] = ix[mb] = 0;
-    if (valid[mb]) {
-      nn[mb] = cidx / (CH * CW);
-      const int r = (int)(cidx - nn[mb] * CH * CW);
-      iy[mb] = (r / CW) * S + py;
-      ix[mb] = (r % CW) * S + px;
+  for (int cls = 0; cls < S * S; ++cls) {
+    const int py = S == 2 ? cls >> 1 : 0, px = S == 2 ? cls & 1 : 0;
+    // masks of the lane's pixels, loaded before the products
+    uint2 am[RPW][MBW];
+    int64_t o[RPW];
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+      const int cy = wr * RPW + r;
+      const int iy = Y0 + S * cy + py, ix = X0 + S * c16 + px;
+      o[r] = (((int64_t)nn * L.hin + iy) * L.win + ix) * CIN + wm * MBW * 16 + 4 * g;
+#pragma unroll
+      for (int m = 0; m < MBW; ++m) am[r][m] = *reinterpret_cast<const uint2 *>(x + o[r] + 16 * m);
     }
-  }
-  floatx4 acc[MB][NB];
+    floatx4 acc[RPW][MBW];
 #pragma unroll
-  for (int mb = 0; mb < MB; ++mb)
+    for (int r = 0; r < RPW; ++r)
 #pragma unroll
-    for (int b = 0; b < NB; ++b) acc[mb][b] = floatx4{0.f, 0.f, 0.f, 0.f};
-  const uint16_t *wrow = wt + (int64_t)(lane & 15) * K + 8 * g;
-  for (int a = 0; a < nky; ++a) {
-    for (int bq = 0; bq < nkx; ++bq) {
-      const int tap = kys[a] * 3 + kxs[bq];
-      bool ok[MB];
-      int64_t src[MB];
+      for (int m = 0; m < MBW; ++m) acc[r][m] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int mb = 0; mb < MB; ++mb) {
-        const int ty = iy[mb] + 1 - kys[a], tx = ix[mb] + 1 - kxs[bq];
-        ok[mb] = valid[mb] && ty >= 0 && tx >= 0 && ty / S < L.hout && tx / S < L.wout;
-        src[mb] = ok[mb] ? ((nn[mb] * L.hout + ty / S) * L.wout + tx / S) * COUT + 8 * g : 0;
-      }
+    for (int ky = 0; ky < 3; ++ky) {
+      if (S == 2 && ((py + 1 - ky) & 1) != 0) continue;
 #pragma unroll
-      for (int co0 = 0; co0 < COUT; co0 += 32) {
-        u32x4 bv[NB];
+      for (int kx = 0; kx < 3; ++kx) {
+        if (S == 2 && ((px + 1 - kx) & 1) != 0) continue;
+        const int tap = ky * 3 + kx;
+        // staged signal pixel read by class pixel (cy, c16) through the tap
+        const int dr = S == 2 ? (py + 1 - ky) / 2 : 2 - ky;
+        const int dc = S == 2 ? (px + 1 - kx) / 2 : 2 - kx;
+#pragma unroll 2
+        for (int ks = 0; ks < COUT / 32; ++ks) {
+          u32x4 a[MBW];
 #pragma unroll
-        for (int b = 0; b < NB; ++b)
-          bv[b] = *reinterpret_cast<const u32x4 *>(wrow + (int64_t)b * 16 * K + tap * COUT + co0);
+          for (int m = 0; m < MBW; ++m)
+            a[m] = *reinterpret_cast<const u32x4 *>(wrow + (int64_t)m * 16 * K + tap * COUT +
+                                                    32 * ks);
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb) {
-          u32x4 av = {0u, 0u, 0u, 0u};
-          if (ok[mb]) av = *reinterpret_cast<const u32x4 *>(dz + src[mb] + co0);
+          for (int r = 0; r < RPW; ++r) {
+            const int cy = wr * RPW + r;
+            const u32x4 b = *reinterpret_cast<const u32x4 *>(
+                &zs[((cy + dr) * ZW + c16 + dc) * ZP + 32 * ks + 8 * g]);
 #pragma unroll
-          for (int b = 0; b < NB; ++b) acc[mb][b] = mfma(av, bv[b], acc[mb][b]);
+            for (int m = 0; m < MBW; ++m) acc[r][m] = mfma(a[m], b, acc[r][m]);
+          }
         }
       }
     }
-  }
 #pragma unroll
-  for (int b = 0; b < NB; ++b) {
-    const int ci = b * 16 + (lane & 15);
+    for (int r = 0; r < RPW; ++r)
 #pragma unroll
-    for (int mb = 0; mb < MB; ++mb)
+      for (int m = 0; m < MBW; ++m) {
+        const uint2 a = am[r][m];
+        const uint16_t ah[4] = {(uint16_t)(a.x & 0xFFFFu), (uint16_t)(a.x >> 16),
+                                (uint16_t)(a.y & 0xFFFFu), (uint16_t)(a.y >> 16)};
+        uint16_t zq[4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int64_t q = cbase + mb * 16 + 4 * g + j;
-        if (q < ncls) {
-          const int64_t qn = q / (CH * CW);
-          const int r = (int)(q - qn * CH * CW);
-          const int qy = (r / CW) * S + py, qx = (r % CW) * S + px;
-          const int64_t o = ((qn * L.hin + qy) * L.win + qx) * CIN + ci;
-          dx[o] = bf_positive(x[o]) ? f2bf(acc[mb][b][j]) : (uint16_t)0;
-        }
+        for (int j = 0; j < 4; ++j) zq[j] = bf_positive(ah[j]) ? f2bf(acc[r][m][j]) : (uint16_t)0;
+        *reinterpret_cast<uint2 *>(dx + o[r] + 16 * m) =
+            make_uint2((uint32_t)zq[0] | ((uint32_t)zq[1] << 16),
+                       (uint32_t)zq[2] | ((uint32_t)zq[3] << 16));
       }
+    __builtin_amdgcn_sched_barrier(0);
   }
+}
+
+// (WMG, RPW) of the backward-data kernel of layers 2..5 (entries 0 and 1
+// unused): M-block groups and class rows per wave.
+#define SPS_BWD_LDS_CONFIGS X(2, 2, 2) X(3, 4, 4) X(4, 4, 4) X(5, 4, 4)
+
+template <int LI, int WMG, int RPW>
+int64_t bwd_data_lds_grid(int n) {
+  constexpr Layer L = kLayers[LI];
+  constexpr int CR = (4 / WMG) * RPW;
+  return (int64_t)n * (L.hin / (L.stride * CR)) * (L.win / (L.stride * 16));
 }
 
 // Layer 1's backward data product fused with layer 0's weight and bias
@@ -879,10 +907,6 @@ __global__ __launch_bounds__(256) void bwd01_kernel(const uint16_t *__restrict__
   }
 }
 
-// Pixel blocks per wave of the backward-data kernel, per layer (entries 0
-// and 1 unused: layer 1 takes the fused kernel above).  Measured at batch
-// 256 against 1 everywhere: layers 2-5 gain 10-25%.
-constexpr int kBwdMB[kNumLayers] = {1, 1, 2, 4, 2, 2};
 
 // ---------------------------------------------------------------------------
 // Backward: weights and biases
@@ -1351,19 +1375,15 @@ sps_status run_backward(sps_cnn c, const uint16_t *tiles, int32_t n, hipStream_t
       hipLaunchKernelGGL(bwd01_kernel, dim3((unsigned)b01_grid(n)), dim3(256), 0, s, c->dz[1],
                          c->wt[1], c->act[0], tiles, c->dz[0], c->partial, nblocks);
     } else if (li > 1) {
-      const int classes = L.stride == 2 ? 4 : 1;
-      const int64_t ncls = npix_in(li, n) / classes;
       switch (li) {
-#define SPS_BWDD(LI)                                                                          \
-  case LI: {                                                                                  \
-    constexpr int MB = kBwdMB[LI];                                                            \
-    const dim3 grid((unsigned)((ncls + 64 * MB - 1) / (64 * MB)), (unsigned)classes);         \
-    hipLaunchKernelGGL((conv_bwd_data_kernel<LI, MB>), grid, dim3(256), 0, s, c->dz[LI],      \
-                       c->wt[LI], c->act[LI - 1], c->dz[LI - 1], n);                          \
-    break;                                                                                    \
-  }
-        SPS_BWDD(2) SPS_BWDD(3) SPS_BWDD(4) SPS_BWDD(5)
-#undef SPS_BWDD
+#define X(LI, WMG, RPW)                                                                       \
+  case LI:                                                                                    \
+    hipLaunchKernelGGL((bwd_data_lds_kernel<LI, WMG, RPW>),                                   \
+                       dim3((unsigned)bwd_data_lds_grid<LI, WMG, RPW>(n)), dim3(256), 0, s,   \
+                       c->dz[LI], c->wt[LI], c->act[LI - 1], c->dz[LI - 1]);                  \
+    break;
+        SPS_BWD_LDS_CONFIGS
+#undef X
       }
     }
     SPS_LAUNCH_CHECK("backward launch");
