@@ -609,6 +609,23 @@ __global__ __launch_bounds__(128) void head_loss_kernel(
 // Backward: data
 // ---------------------------------------------------------------------------
 
+typedef short i16x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) i16x4 lds_i16x4;
+
+// Two transposed LDS reads (4 pixels each) as one 8-value MFMA operand;
+// p: this lane's address for the first 4 pixels, next: element offset of
+// the second 4.
+__device__ __forceinline__ u32x4 tr_pair(const uint16_t *p, int next) {
+  const i16x4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_i16x4 *)p);
+  const i16x4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_i16x4 *)(p + next));
+  u32x4 r;
+  r.x = (uint32_t)(uint16_t)lo[0] | ((uint32_t)(uint16_t)lo[1] << 16);
+  r.y = (uint32_t)(uint16_t)lo[2] | ((uint32_t)(uint16_t)lo[3] << 16);
+  r.z = (uint32_t)(uint16_t)hi[0] | ((uint32_t)(uint16_t)hi[1] << 16);
+  r.w = (uint32_t)(uint16_t)hi[2] | ((uint32_t)(uint16_t)hi[3] << 16);
+  return r;
+}
+
 // Backward data of layers 2..5 as an implicit GEMM with the signal staged
 // in LDS: dx[p][ci] = bf16(mask(x[p][ci]) * sum_{tap, co} W[co][ci][tap]
 // dz[q(p, tap)][co]).  A workgroup owns RPW x 16 class pixels of each parity
@@ -733,30 +750,42 @@ int64_t bwd_data_lds_grid(int n) {
   return (int64_t)n * (L.hin / (L.stride * CR)) * (L.win / (L.stride * 16));
 }
 
-// Layer 1's backward data product fused with layer 0's weight and bias
-// gradients.  A block is 8 x 32 layer-0 pixels of one tile: the signal of
-// layer 1 it reads ((4 + 1) x (16 + 1) pixels, 32 channels) and the tile
-// region layer 0 read for it (17 x 65 values) are staged in LDS once, and
-// the transposed layer-1 weights once per workgroup.  Each of the four
-// parity classes of the block's pixels is a product with M = 16 channels
-// (the transposed weights), N = 16 class pixels of one class row, K = the
-// class's taps x 32 (one 16x16x32 product per tap): a wave takes one class
-// row, and loads its pixels' ReLU masks before the products.  The lane's 4
-// channels of one pixel are masked by
-// the stored layer-0 activation, rounded to bfloat16 and stored (the
-// signal of layer 0), and then, as FP32, multiply the pixel's 9 tile values
-// into the lane's layer-0 weight-gradient sums (and its bias sums).  The
-// grid is fixed (kB01Grid workgroups, each taking blocks blockIdx.x,
-// + gridDim.x, ...), so every workgroup's partial sums, written to
-// partial[wg][co][tap] and partial[wg][144 + co], are in a fixed order.
+// Layer 1's backward (data, weight and bias products) fused with layer 0's
+// weight and bias gradients.  A block is 8 x 32 layer-0 pixels of one tile
+// (layer 1's input), owning the 4 x 16 layer-1 output pixels whose
+// windows start in it.  Staged in LDS once per block: layer 1's signal over
+// (4 + 1) x (16 + 1) pixels, layer 0's stored activation over the block
+// with a one-pixel halo (9 x 33 pixels), and the tile region layer 0 read
+// for the block (17 x 65 values); the transposed layer-1 weights once per
+// workgroup.
+//  - Layer 0's signal: each of the four parity classes of the block's
+//    pixels is a product with M = 16 channels (the transposed weights),
+//    N = 16 class pixels of one class row, K = the class's taps x 32 (one
+//    16x16x32 product per tap); a wave takes one class row.  The lane's 4
+//    channels of one pixel are masked by the staged activation, rounded to
+//    bfloat16 and stored, and then, as FP32, multiply the pixel's 9 tile
+//    values into the lane's layer-0 weight-gradient sums (and bias sums).
+//  - Layer 1's weight gradient: M = 32 output channels, N = 16 input
+//    channels per tap, K = the 64 owned output pixels; both operands come
+//    from the staged signal and activation through transposed LDS reads,
+//    and the waves split the 9 taps.  Its bias gradient sums the owned
+//    pixels of the staged signal.
+// The grid is fixed (kB01Grid workgroups, each taking blocks blockIdx.x,
+// + gridDim.x, ...), so every workgroup's partial sums are in a fixed
+// order: partial[wg][0, 4608) layer 1's weights [co][tap][ci], then its 32
+// biases, layer 0's weights [co][tap] and its 16 biases.
 constexpr int kB01Rows = 4, kB01Cols = 16;  // class rows / columns of a block
-constexpr int kB01Grid = 2048;
-constexpr int kB01Part = 16 * 9 + 16;       // partial sums per workgroup
-constexpr int kB01ZW = kB01Cols + 1, kB01ZP = 40;   // staged signal: pixels per row, bf16 per pixel
+constexpr int kB01Grid = 1024;
+constexpr int kB01W1 = 32 * 9 * 16, kB01B1 = kB01W1, kB01W0 = kB01B1 + 32, kB01B0 = kB01W0 + 144;
+constexpr int kB01Part = kB01B0 + 16;               // partial sums per workgroup
+constexpr int kB01ZW = kB01Cols + 1, kB01ZP = 48;   // staged signal: pixels per row, bf16 per pixel
+constexpr int kB01XH = 2 * kB01Rows + 1, kB01XW = 2 * kB01Cols + 1;  // staged activation region
 constexpr int kB01TH = 4 * kB01Rows + 1, kB01TW = 4 * kB01Cols + 8;  // staged tile region
 constexpr int kB01WP = 9 * 32 + 8;  // staged transposed weights: bf16 per input channel
 
-__global__ __launch_bounds__(256) void bwd01_kernel(const uint16_t *__restrict__ dz1,
+// Four waves per SIMD: 128 registers hold it without spills (left alone,
+// the compiler takes 134 and three waves).
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) void bwd01_kernel(const uint16_t *__restrict__ dz1,
                                                     const uint16_t *__restrict__ wt1,
                                                     const uint16_t *__restrict__ act0,
                                                     const uint16_t *__restrict__ tiles,
@@ -767,9 +796,11 @@ __global__ __launch_bounds__(256) void bwd01_kernel(const uint16_t *__restrict__
   constexpr int BY = L0.hout / (2 * kB01Rows), BX = L0.wout / (2 * kB01Cols);
   static_assert(L0.hout % (2 * kB01Rows) == 0 && L0.wout % (2 * kB01Cols) == 0, "whole blocks");
   __shared__ __attribute__((aligned(16))) uint16_t zs[(kB01Rows + 1) * kB01ZW * kB01ZP];
+  __shared__ __attribute__((aligned(16))) uint16_t xs[kB01XH * kB01XW * 16];
   __shared__ __attribute__((aligned(16))) uint16_t ts[kB01TH * kB01TW];
   __shared__ __attribute__((aligned(16))) uint16_t ws[16 * kB01WP];
   __shared__ float red[4][4][40];
+  __shared__ float red1[8][32];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, c16 = lane & 15;
   // transposed weights [ci][tap * 32 + co]; a lane's A fragment of a tap is
   // row ci = c16, K = channels 8g .. 8g+7 of layer 1's signal
@@ -783,6 +814,13 @@ __global__ __launch_bounds__(256) void bwd01_kernel(const uint16_t *__restrict__
 #pragma unroll
     for (int t = 0; t < 9; ++t) accw[j][t] = 0.f;
   }
+  // layer 1's weight gradient: wave w takes taps w, w + 4 (and 8 for w = 0)
+  floatx4 acc1[3][2];
+#pragma unroll
+  for (int t = 0; t < 3; ++t)
+#pragma unroll
+    for (int m = 0; m < 2; ++m) acc1[t][m] = floatx4{0.f, 0.f, 0.f, 0.f};
+  float accb1 = 0.f;  // layer 1's bias: channel threadIdx.x % 32
   for (int blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
     const int nn = blk / (BY * BX), r = blk % (BY * BX);
     const int Y0 = (r / BX) * 2 * kB01Rows, X0 = (r % BX) * 2 * kB01Cols;
@@ -798,6 +836,16 @@ __global__ __launch_bounds__(256) void bwd01_kernel(const uint16_t *__restrict__
                                                        32 + 8 * q);
       *reinterpret_cast<u32x4 *>(&zs[pix * kB01ZP + 8 * q]) = d;
     }
+    // layer 0's activation at rows Y0 - 1 + i, columns X0 - 1 + j
+    for (int v = threadIdx.x; v < kB01XH * kB01XW * 2; v += 256) {
+      const int pix = v >> 1, q = v & 1;
+      const int iy = Y0 - 1 + pix / kB01XW, ix = X0 - 1 + pix % kB01XW;
+      u32x4 d = {0u, 0u, 0u, 0u};
+      if (iy >= 0 && iy < L0.hout && ix >= 0 && ix < L0.wout)
+        d = *reinterpret_cast<const u32x4 *>(act0 + ((int64_t)(nn * L0.hout + iy) * L0.wout + ix) *
+                                                        16 + 8 * q);
+      *reinterpret_cast<u32x4 *>(&xs[pix * 16 + 8 * q]) = d;
+    }
     // tile rows 2 Y0 - 1 + i, columns from 2 X0 - 8 (16-byte chunks)
     for (int v = threadIdx.x; v < kB01TH * (kB01TW / 8); v += 256) {
       const int i = v / (kB01TW / 8), k = v % (kB01TW / 8);
@@ -807,23 +855,43 @@ __global__ __launch_bounds__(256) void bwd01_kernel(const uint16_t *__restrict__
         d = *reinterpret_cast<const u32x4 *>(tiles + ((int64_t)nn * L0.hin + ty) * L0.win + tx);
       *reinterpret_cast<u32x4 *>(&ts[i * kB01TW + 8 * k]) = d;
     }
-    // the stored layer-0 activations of the lane's pixels (the ReLU masks),
-    // all loaded before the products so that their latency overlaps
-    uint2 am[kB01Rows / 4][4];
-#pragma unroll
-    for (int h = 0; h < kB01Rows / 4; ++h)
-#pragma unroll
-      for (int cls = 0; cls < 4; ++cls) {
-        const int iy = Y0 + 2 * (wave * (kB01Rows / 4) + h) + (cls >> 1);
-        const int ix = X0 + 2 * c16 + (cls & 1);
-        am[h][cls] = *reinterpret_cast<const uint2 *>(
-            act0 + (((int64_t)nn * L0.hout + iy) * L0.wout + ix) * 16 + 4 * g);
-      }
     __syncthreads();
+    // layer 1's bias: owned pixels p = m + 8k of the staged signal
+    {
+      const int co = threadIdx.x & 31, m = threadIdx.x >> 5;
 #pragma unroll
-    for (int h = 0; h < kB01Rows / 4; ++h) {
-      const int cy = wave * (kB01Rows / 4) + h;
+      for (int k = 0; k < 8; ++k) {
+        const int p = m + 8 * k;
+        accb1 += bf2f(zs[((p >> 4) * kB01ZW + (p & 15)) * kB01ZP + co]);
+      }
+    }
+    // layer 1's weight gradient over the 64 owned output pixels, K steps
+    // of 32: pixel p = 32 ks + 8 g + (s >> 2) (+ 4) for lane s of group g,
+    // at output (p >> 4, p & 15) of the block and input (2 (p >> 4) + ky,
+    // 2 (p & 15) + kx) of the staged activation
 #pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      const int s = c16, pr = 2 * ks + (g >> 1), pc = 8 * (g & 1) + (s >> 2);
+      u32x4 a[2];
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+        a[m] = tr_pair(&zs[(pr * kB01ZW + pc) * kB01ZP + 16 * m + 4 * (s & 3)], 4 * kB01ZP);
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        const int tap = wave + 4 * t;
+        if (tap < 9) {
+          const int ky = tap / 3, kx = tap % 3;
+          const u32x4 b =
+              tr_pair(&xs[((2 * pr + ky) * kB01XW + 2 * pc + kx) * 16 + 4 * (s & 3)], 8 * 16);
+#pragma unroll
+          for (int m = 0; m < 2; ++m) acc1[t][m] = mfma(a[m], b, acc1[t][m]);
+        }
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    {
+      const int cy = wave;
+#pragma unroll 1
       for (int cls = 0; cls < 4; ++cls) {
         const int py = cls >> 1, px = cls & 1;
         floatx4 acc = {0.f, 0.f, 0.f, 0.f};
@@ -844,7 +912,8 @@ __global__ __launch_bounds__(256) void bwd01_kernel(const uint16_t *__restrict__
         }
         const int iy = Y0 + 2 * cy + py, ix = X0 + 2 * c16 + px;
         const int64_t o = (((int64_t)nn * L0.hout + iy) * L0.wout + ix) * 16 + 4 * g;
-        const uint2 a = am[h][cls];
+        const uint2 a = *reinterpret_cast<const uint2 *>(
+            &xs[((iy - Y0 + 1) * kB01XW + ix - X0 + 1) * 16 + 4 * g]);
         const uint16_t ah[4] = {(uint16_t)(a.x & 0xFFFFu), (uint16_t)(a.x >> 16),
                                 (uint16_t)(a.y & 0xFFFFu), (uint16_t)(a.y >> 16)};
         uint16_t zq[4];
@@ -875,8 +944,22 @@ __global__ __launch_bounds__(256) void bwd01_kernel(const uint16_t *__restrict__
       }
     }
   }
+  float *pw = partial + (int64_t)blockIdx.x * kB01Part;
+  // layer 1's weights: the lane holds co = 16 m + 4 g + j, ci = c16 of tap
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    const int tap = wave + 4 * t;
+    if (tap < 9) {
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          pw[((16 * m + 4 * g + j) * 9 + tap) * 16 + c16] = acc1[t][m][j];
+    }
+  }
   // workgroup sums, fixed order: the 16 lanes of a channel group
-  // (butterfly), then the 4 waves
+  // (butterfly), then the 4 waves; layer 1's bias over the 8 threads of a
+  // channel
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
 #pragma unroll
@@ -894,18 +977,26 @@ __global__ __launch_bounds__(256) void bwd01_kernel(const uint16_t *__restrict__
       red[wave][g][36 + j] = accb[j];
     }
   }
+  red1[threadIdx.x >> 5][threadIdx.x & 31] = accb1;
   __syncthreads();
-  if (threadIdx.x < kB01Part) {
+  if (threadIdx.x < 160) {
     const int i = threadIdx.x;
-    // weights: co = i / 9, tap = i % 9; bias: co = i - 144
+    // layer 0: weights co = i / 9, tap = i % 9; bias co = i - 144
     const int co = i < 144 ? i / 9 : i - 144;
     const int slot = i < 144 ? (co % 4) * 9 + i % 9 : 36 + co % 4;
     float s = 0.f;
 #pragma unroll
     for (int w = 0; w < 4; ++w) s += red[w][co / 4][slot];
-    partial[(int64_t)blockIdx.x * kB01Part + i] = s;
+    pw[kB01W0 + i] = s;
+  } else if (threadIdx.x < 192) {
+    const int co = threadIdx.x - 160;
+    float s = 0.f;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) s += red1[m][co];
+    pw[kB01B1 + co] = s;
   }
 }
+
 
 
 // ---------------------------------------------------------------------------
@@ -919,9 +1010,6 @@ constexpr int kKP = 32;  // pixels per staged K-step
 // strides of 8, 24, 40 or 72 dwords).
 constexpr int wg_row(int c) { return c >= 32 ? c + 16 : c; }
 
-typedef short i16x4 __attribute__((ext_vector_type(4)));
-typedef __attribute__((address_space(3))) i16x4 lds_i16x4;
-
 // An MFMA operand with K = 8 consecutive staged pixels: the lane's 16-lane
 // group g reads pixels k0 + 8g .. + 7 of channel c0 + (lane % 16) from a
 // [pixel][channel] array with rows of `row` bf16.  A transposed read
@@ -933,15 +1021,7 @@ typedef __attribute__((address_space(3))) i16x4 lds_i16x4;
 __device__ __forceinline__ u32x4 tr_operand(const uint16_t *base, int row, int k0, int c0,
                                             int lane) {
   const int g = lane >> 4, s = lane & 15;
-  const uint16_t *p = base + (k0 + 8 * g + (s >> 2)) * row + c0 + 4 * (s & 3);
-  const i16x4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_i16x4 *)p);
-  const i16x4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_i16x4 *)(p + 4 * row));
-  u32x4 r;
-  r.x = (uint32_t)(uint16_t)lo[0] | ((uint32_t)(uint16_t)lo[1] << 16);
-  r.y = (uint32_t)(uint16_t)lo[2] | ((uint32_t)(uint16_t)lo[3] << 16);
-  r.z = (uint32_t)(uint16_t)hi[0] | ((uint32_t)(uint16_t)hi[1] << 16);
-  r.w = (uint32_t)(uint16_t)hi[2] | ((uint32_t)(uint16_t)hi[3] << 16);
-  return r;
+  return tr_pair(base + (k0 + 8 * g + (s >> 2)) * row + c0 + 4 * (s & 3), 4 * row);
 }
 
 // partial[split][co][tap][ci] = sum over the split's output pixels q of
@@ -1176,8 +1256,8 @@ int b01_blocks(int n) {
 int b01_grid(int n) { return b01_blocks(n) < kB01Grid ? b01_blocks(n) : kB01Grid; }
 
 // Workgroups of a layer's weight-gradient kernel along its other grid
-// dimension (9 / taps per workgroup) for layers 1..5; layer 0's gradients
-// come from the fused kernel (entry unused).
+// dimension (9 / taps per workgroup) for layers 2..5; layers 0 and 1 take
+// their gradients from the fused kernel (entries unused).
 int wgrad_groups(int li) {
   static const int g[kNumLayers] = {1, 1, 1, 9, 9, 9};
   return g[li];
@@ -1325,32 +1405,41 @@ sps_status run_head(sps_cnn c, const float *labels, int32_t n, bool train, hipSt
 }
 
 sps_status run_backward(sps_cnn c, const uint16_t *tiles, int32_t n, hipStream_t s) {
-  for (int li = kNumLayers - 1; li >= 0; --li) {
+  for (int li = kNumLayers - 1; li >= 1; --li) {
     const Layer &L = kLayers[li];
+    float *gw = c->grads + layer_param_offset(li);
+    if (li == 1) {
+      // layers 1 and 0: one fused kernel, then the two-level sums of its
+      // partials (weights of both layers, then the biases)
+      float *gw0 = c->grads + layer_param_offset(0);
+      const int nwg = b01_grid(n);
+      hipLaunchKernelGGL(bwd01_kernel, dim3((unsigned)nwg), dim3(256), 0, s, c->dz[1], c->wt[1],
+                         c->act[0], tiles, c->dz[0], c->partial, b01_blocks(n));
+      hipLaunchKernelGGL(reduce_weight_partial_kernel,
+                         dim3((unsigned)((kB01Part + 255) / 256), kWGroups), dim3(256), 0, s,
+                         c->partial, nwg, (int64_t)kB01Part, c->wtmp);
+      hipLaunchKernelGGL(reduce_weight_kernel, dim3((unsigned)((kB01W1 + 255) / 256)), dim3(256),
+                         0, s, c->wtmp, (int64_t)kB01Part, 32, 16, gw);
+      hipLaunchKernelGGL(reduce_rows_kernel, dim3(32), dim3(256), 0, s, c->wtmp + kB01B1, kWGroups,
+                         kB01Part, gw + L.wcount());
+      hipLaunchKernelGGL(reduce_weight_kernel, dim3(1), dim3(256), 0, s, c->wtmp + kB01W0,
+                         (int64_t)kB01Part, 16, 1, gw0);
+      hipLaunchKernelGGL(reduce_rows_kernel, dim3(16), dim3(256), 0, s, c->wtmp + kB01B0, kWGroups,
+                         kB01Part, gw0 + kLayers[0].wcount());
+      SPS_LAUNCH_CHECK("backward launch");
+      break;
+    }
     const int64_t np = npix_out(li, n);
     const int64_t chunk = split_chunk(np, li);
     const int64_t nsplit = (np + chunk - 1) / chunk;
-    const uint16_t *xin = li == 0 ? tiles : c->act[li - 1];
-    float *gw = c->grads + layer_param_offset(li);
-    if (li == 0) {
-      // layer 0's gradients were summed by the fused kernel of layer 1
-      const int nwg = b01_grid(n);
-      hipLaunchKernelGGL(reduce_weight_partial_kernel, dim3(1, kWGroups), dim3(256), 0, s,
-                         c->partial, nwg, (int64_t)kB01Part, c->wtmp);
-      hipLaunchKernelGGL(reduce_weight_kernel, dim3(1), dim3(256), 0, s, c->wtmp,
-                         (int64_t)kB01Part, 16, 1, gw);
-      hipLaunchKernelGGL(reduce_rows_kernel, dim3(16), dim3(256), 0, s, c->wtmp + 144, kWGroups,
-                         kB01Part, gw + L.wcount());
-      SPS_LAUNCH_CHECK("backward launch");
-      continue;
-    }
+    const uint16_t *xin = c->act[li - 1];
     switch (li) {
 #define SPS_BWDW(LI, TAPS)                                                                   \
   case LI:                                                                                   \
     hipLaunchKernelGGL((conv_bwd_weight_kernel<LI, TAPS>), dim3(9 / TAPS, (unsigned)nsplit),  \
                        dim3(256), 0, s, c->dz[LI], xin, c->partial, np, chunk);              \
     break;
-        SPS_BWDW(1, 9) SPS_BWDW(2, 9) SPS_BWDW(3, 1) SPS_BWDW(4, 1) SPS_BWDW(5, 1)
+      SPS_BWDW(2, 9) SPS_BWDW(3, 1) SPS_BWDW(4, 1) SPS_BWDW(5, 1)
 #undef SPS_BWDW
     }
     hipLaunchKernelGGL(reduce_weight_partial_kernel,
@@ -1362,29 +1451,24 @@ sps_status run_backward(sps_cnn c, const uint16_t *tiles, int32_t n, hipStream_t
       const int64_t nvec = np * (L.cout / 8);
       int64_t nb = (nvec + 255) / 256;
       nb = nb < kBiasBlocks ? nb : kBiasBlocks;
-      switch (L.cout) {
-        case 32: hipLaunchKernelGGL(bias_partial_kernel<32>, dim3((unsigned)nb), dim3(256), 0, s, c->dz[li], np, c->bpart); break;
-        case 64: hipLaunchKernelGGL(bias_partial_kernel<64>, dim3((unsigned)nb), dim3(256), 0, s, c->dz[li], np, c->bpart); break;
-        default: hipLaunchKernelGGL(bias_partial_kernel<128>, dim3((unsigned)nb), dim3(256), 0, s, c->dz[li], np, c->bpart); break;
-      }
-      hipLaunchKernelGGL(reduce_rows_kernel, dim3((unsigned)L.cout), dim3(256), 0, s, c->bpart, (int)nb, L.cout,
-                         gw + L.wcount());
+      if (L.cout == 64)
+        hipLaunchKernelGGL(bias_partial_kernel<64>, dim3((unsigned)nb), dim3(256), 0, s, c->dz[li],
+                           np, c->bpart);
+      else
+        hipLaunchKernelGGL(bias_partial_kernel<128>, dim3((unsigned)nb), dim3(256), 0, s,
+                           c->dz[li], np, c->bpart);
+      hipLaunchKernelGGL(reduce_rows_kernel, dim3((unsigned)L.cout), dim3(256), 0, s, c->bpart,
+                         (int)nb, L.cout, gw + L.wcount());
     }
-    if (li == 1) {
-      const int nblocks = b01_blocks(n);
-      hipLaunchKernelGGL(bwd01_kernel, dim3((unsigned)b01_grid(n)), dim3(256), 0, s, c->dz[1],
-                         c->wt[1], c->act[0], tiles, c->dz[0], c->partial, nblocks);
-    } else if (li > 1) {
-      switch (li) {
+    switch (li) {
 #define X(LI, WMG, RPW)                                                                       \
   case LI:                                                                                    \
     hipLaunchKernelGGL((bwd_data_lds_kernel<LI, WMG, RPW>),                                   \
                        dim3((unsigned)bwd_data_lds_grid<LI, WMG, RPW>(n)), dim3(256), 0, s,   \
                        c->dz[LI], c->wt[LI], c->act[LI - 1], c->dz[LI - 1]);                  \
     break;
-        SPS_BWD_LDS_CONFIGS
+      SPS_BWD_LDS_CONFIGS
 #undef X
-      }
     }
     SPS_LAUNCH_CHECK("backward launch");
   }
