@@ -1031,7 +1031,10 @@ __device__ __forceinline__ u32x4 tr_operand(const uint16_t *base, int row, int k
 // K-values come from two transposed LDS reads.  A workgroup handles TAPS
 // taps (grid (9 / TAPS, nsplit)): all 9 for the narrow layers, where the
 // staged signal tile is then shared by every tap, one for the wide layers,
-// whose accumulators would not fit nine times.
+// whose accumulators would not fit nine times.  With all 9 taps (stride
+// 2) the 32 pixels of a K step lie in one output row, and the input region
+// they read (3 rows x 65 pixels) is staged once for all taps; each lane
+// addresses its pixels' tap inputs inside it.
 template <int LI, int TAPS>
 __global__ __launch_bounds__(256) void conv_bwd_weight_kernel(const uint16_t *__restrict__ dz,
                                                               const uint16_t *__restrict__ x,
@@ -1042,8 +1045,11 @@ __global__ __launch_bounds__(256) void conv_bwd_weight_kernel(const uint16_t *__
   constexpr int MB = COUT / 16, NB = CIN / 16, NBLK = MB * NB * TAPS;
   constexpr int PER_WAVE = (NBLK + 3) / 4;
   constexpr int ZR = wg_row(COUT), XR = wg_row(CIN);
+  constexpr bool REGION = TAPS == 9;
+  static_assert(!REGION || (S == 2 && L.wout % kKP == 0), "region staging: whole K steps per row");
+  constexpr int RW = 2 * kKP + 1;  // region pixels per input row
   __shared__ __attribute__((aligned(16))) uint16_t dzs[kKP * ZR];
-  __shared__ __attribute__((aligned(16))) uint16_t xs[TAPS][kKP * XR];
+  __shared__ __attribute__((aligned(16))) uint16_t xs[REGION ? 1 : TAPS][(REGION ? 3 * RW : kKP) * XR];
   const int tap0 = blockIdx.x * TAPS;
   const int64_t split = blockIdx.y;
   const int64_t pbeg = split * chunk;
@@ -1052,31 +1058,83 @@ __global__ __launch_bounds__(256) void conv_bwd_weight_kernel(const uint16_t *__
   floatx4 acc[PER_WAVE];
 #pragma unroll
   for (int b = 0; b < PER_WAVE; ++b) acc[b] = floatx4{0.f, 0.f, 0.f, 0.f};
-  for (int64_t p0 = pbeg; p0 < pend; p0 += kKP) {
-    for (int v = threadIdx.x; v < kKP * COUT / 8; v += 256) {
+  // One K step's staging in registers: the signal's and the input's 16-byte
+  // chunks of this thread (fixed trip counts).  The next step's are loaded
+  // while the current one's products run.
+  constexpr int ZCH = kKP * COUT / 8;
+  constexpr int XCH = REGION ? 3 * RW * CIN / 8 : TAPS * kKP * CIN / 8;
+  constexpr int NZ = (ZCH + 255) / 256, NX = (XCH + 255) / 256;
+  u32x4 rz[NZ], rx[NX];
+  auto load = [&](int64_t p0) {
+#pragma unroll
+    for (int u = 0; u < NZ; ++u) {
+      const int v = threadIdx.x + 256 * u;
       const int pix = v / (COUT / 8), c8 = (v % (COUT / 8)) * 8;
       const int64_t q = p0 + pix;
-      u32x4 d = {0u, 0u, 0u, 0u};
-      if (q < pend) d = *reinterpret_cast<const u32x4 *>(dz + q * COUT + c8);
-      *reinterpret_cast<u32x4 *>(&dzs[pix * ZR + c8]) = d;
+      rz[u] = u32x4{0u, 0u, 0u, 0u};
+      if (v < ZCH && q < pend) rz[u] = *reinterpret_cast<const u32x4 *>(dz + q * COUT + c8);
     }
-    for (int v = threadIdx.x; v < TAPS * kKP * CIN / 8; v += 256) {
-      const int tt = v / (kKP * CIN / 8);
-      const int rem = v - tt * (kKP * CIN / 8);
-      const int pix = rem / (CIN / 8), c8 = (rem % (CIN / 8)) * 8;
-      const int tap = tap0 + tt;
-      const int64_t q = p0 + pix;
-      u32x4 d = {0u, 0u, 0u, 0u};
-      if (q < pend) {
-        const int64_t n = q / (L.hout * L.wout);
-        const int r = (int)(q - n * L.hout * L.wout);
-        const int iy = S * (r / L.wout) + tap / 3 - 1, ix = S * (r % L.wout) + tap % 3 - 1;
-        if (iy >= 0 && iy < L.hin && ix >= 0 && ix < L.win)
-          d = *reinterpret_cast<const u32x4 *>(x + ((n * L.hin + iy) * L.win + ix) * CIN + c8);
+    if constexpr (REGION) {
+      // input rows 2 oy - 1 .. + 2, columns 2 ox0 - 1 .. 2 ox0 + 2 kKP - 1
+      const int64_t n = p0 / (L.hout * L.wout);
+      const int r0 = (int)(p0 - n * L.hout * L.wout);
+      const int oy = r0 / L.wout, ox0 = r0 % L.wout;
+#pragma unroll
+      for (int u = 0; u < NX; ++u) {
+        const int v = threadIdx.x + 256 * u;
+        const int pix = v / (CIN / 8), c8 = (v % (CIN / 8)) * 8;
+        const int iy = 2 * oy - 1 + pix / RW, ix = 2 * ox0 - 1 + pix % RW;
+        rx[u] = u32x4{0u, 0u, 0u, 0u};
+        if (v < XCH && iy >= 0 && iy < L.hin && ix >= 0 && ix < L.win)
+          rx[u] = *reinterpret_cast<const u32x4 *>(x + ((n * L.hin + iy) * L.win + ix) * CIN + c8);
       }
-      *reinterpret_cast<u32x4 *>(&xs[tt][pix * XR + c8]) = d;
+    } else {
+#pragma unroll
+      for (int u = 0; u < NX; ++u) {
+        const int v = threadIdx.x + 256 * u;
+        const int tt = v / (kKP * CIN / 8);
+        const int rem = v - tt * (kKP * CIN / 8);
+        const int pix = rem / (CIN / 8), c8 = (rem % (CIN / 8)) * 8;
+        const int tap = tap0 + tt;
+        const int64_t q = p0 + pix;
+        rx[u] = u32x4{0u, 0u, 0u, 0u};
+        if (v < XCH && q < pend) {
+          const int64_t n = q / (L.hout * L.wout);
+          const int r = (int)(q - n * L.hout * L.wout);
+          const int iy = S * (r / L.wout) + tap / 3 - 1, ix = S * (r % L.wout) + tap % 3 - 1;
+          if (iy >= 0 && iy < L.hin && ix >= 0 && ix < L.win)
+            rx[u] = *reinterpret_cast<const u32x4 *>(x + ((n * L.hin + iy) * L.win + ix) * CIN + c8);
+        }
+      }
     }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int u = 0; u < NZ; ++u) {
+      const int v = threadIdx.x + 256 * u;
+      if (v < ZCH)
+        *reinterpret_cast<u32x4 *>(&dzs[(v / (COUT / 8)) * ZR + (v % (COUT / 8)) * 8]) = rz[u];
+    }
+#pragma unroll
+    for (int u = 0; u < NX; ++u) {
+      const int v = threadIdx.x + 256 * u;
+      if (v < XCH) {
+        if constexpr (REGION) {
+          *reinterpret_cast<u32x4 *>(&xs[0][(v / (CIN / 8)) * XR + (v % (CIN / 8)) * 8]) = rx[u];
+        } else {
+          const int tt = v / (kKP * CIN / 8);
+          const int rem = v - tt * (kKP * CIN / 8);
+          *reinterpret_cast<u32x4 *>(&xs[tt][(rem / (CIN / 8)) * XR + (rem % (CIN / 8)) * 8]) =
+              rx[u];
+        }
+      }
+    }
+  };
+  if (pbeg < pend) load(pbeg);
+  for (int64_t p0 = pbeg; p0 < pend; p0 += kKP) {
+    store();
     __syncthreads();
+    if (p0 + kKP < pend) load(p0 + kKP);
 #pragma unroll
     for (int b = 0; b < PER_WAVE; ++b) {
       const int blk = wave * PER_WAVE + b;
@@ -1084,7 +1142,17 @@ __global__ __launch_bounds__(256) void conv_bwd_weight_kernel(const uint16_t *__
         const int tt = blk / (MB * NB), rb = blk % (MB * NB);
         const int mb = rb / NB, nb = rb % NB;
         const u32x4 av = tr_operand(dzs, ZR, 0, mb * 16, lane);
-        const u32x4 bv = tr_operand(xs[tt], XR, 0, nb * 16, lane);
+        u32x4 bv;
+        if constexpr (REGION) {
+          // pixel k = 8g + (s >> 2) (+ 4) of the step reads region pixel
+          // (ky, 2k + kx) through tap (ky, kx)
+          const int tap = tap0 + tt, sl = lane & 15;
+          const int k = 8 * g + (sl >> 2);
+          bv = tr_pair(&xs[0][((tap / 3) * RW + 2 * k + tap % 3) * XR + nb * 16 + 4 * (sl & 3)],
+                       8 * XR);
+        } else {
+          bv = tr_operand(xs[tt], XR, 0, nb * 16, lane);
+        }
         acc[b] = mfma(av, bv, acc[b]);
       }
     }
