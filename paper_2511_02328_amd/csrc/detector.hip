@@ -770,12 +770,13 @@ int64_t bwd_data_lds_grid(int n) {
 //    from the staged signal and activation through transposed LDS reads,
 //    and the waves split the 9 taps.  Its bias gradient sums the owned
 //    pixels of the staged signal.
-// The grid is fixed (kB01Grid workgroups, each taking blocks blockIdx.x,
-// + gridDim.x, ...), so every workgroup's partial sums are in a fixed
-// order: partial[wg][0, 4608) layer 1's weights [co][tap][ci], then its 32
+// The grid is the number of workgroups resident at once (at most
+// kB01Grid), each taking blocks blockIdx.x, + gridDim.x, ..., and loading
+// the next block's staging while it works on the current one; every
+// workgroup's partial sums are in a fixed order: partial[wg][0, 4608) layer 1's weights [co][tap][ci], then its 32
 // biases, layer 0's weights [co][tap] and its 16 biases.
 constexpr int kB01Rows = 4, kB01Cols = 16;  // class rows / columns of a block
-constexpr int kB01Grid = 1024;
+constexpr int kB01Grid = 1024;  // at most this many workgroups (partial rows)
 constexpr int kB01W1 = 32 * 9 * 16, kB01B1 = kB01W1, kB01W0 = kB01B1 + 32, kB01B0 = kB01W0 + 144;
 constexpr int kB01Part = kB01B0 + 16;               // partial sums per workgroup
 constexpr int kB01ZW = kB01Cols + 1, kB01ZP = 48;   // staged signal: pixels per row, bf16 per pixel
@@ -783,9 +784,9 @@ constexpr int kB01XH = 2 * kB01Rows + 1, kB01XW = 2 * kB01Cols + 1;  // staged a
 constexpr int kB01TH = 4 * kB01Rows + 1, kB01TW = 4 * kB01Cols + 8;  // staged tile region
 constexpr int kB01WP = 9 * 32 + 8;  // staged transposed weights: bf16 per input channel
 
-// Four waves per SIMD: 128 registers hold it without spills (left alone,
-// the compiler takes 134 and three waves).
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) void bwd01_kernel(const uint16_t *__restrict__ dz1,
+// Three waves per SIMD: up to 168 registers, which hold the next block's
+// staging registers without spills.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void bwd01_kernel(const uint16_t *__restrict__ dz1,
                                                     const uint16_t *__restrict__ wt1,
                                                     const uint16_t *__restrict__ act0,
                                                     const uint16_t *__restrict__ tiles,
@@ -821,41 +822,76 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
 #pragma unroll
     for (int m = 0; m < 2; ++m) acc1[t][m] = floatx4{0.f, 0.f, 0.f, 0.f};
   float accb1 = 0.f;  // layer 1's bias: channel threadIdx.x % 32
+  // A block's staging in registers (this thread's 16-byte chunks of the
+  // signal, activation and tile regions); the next block's are loaded while
+  // the current one is worked on.
+  constexpr int ZCH = (kB01Rows + 1) * kB01ZW * 4, XCH = kB01XH * kB01XW * 2;
+  constexpr int TCH = kB01TH * (kB01TW / 8);
+  constexpr int NZ = (ZCH + 255) / 256, NX = (XCH + 255) / 256, NT = (TCH + 255) / 256;
+  u32x4 rz[NZ], rx[NX], rt[NT];
+  auto load = [&](int blk) {
+    const int nn = blk / (BY * BX), r = blk % (BY * BX);
+    const int Y0 = (r / BX) * 2 * kB01Rows, X0 = (r % BX) * 2 * kB01Cols;
+    // layer 1's signal at rows Y0/2 + i (i <= kB01Rows), columns X0/2 + j
+    // (j <= kB01Cols), zero outside the image
+#pragma unroll
+    for (int u = 0; u < NZ; ++u) {
+      const int v = threadIdx.x + 256 * u;
+      const int pix = v >> 2, q = v & 3;
+      const int oy = Y0 / 2 + pix / kB01ZW, ox = X0 / 2 + pix % kB01ZW;
+      rz[u] = u32x4{0u, 0u, 0u, 0u};
+      if (v < ZCH && oy < L1.hout && ox < L1.wout)
+        rz[u] = *reinterpret_cast<const u32x4 *>(
+            dz1 + ((int64_t)(nn * L1.hout + oy) * L1.wout + ox) * 32 + 8 * q);
+    }
+    // layer 0's activation at rows Y0 - 1 + i, columns X0 - 1 + j
+#pragma unroll
+    for (int u = 0; u < NX; ++u) {
+      const int v = threadIdx.x + 256 * u;
+      const int pix = v >> 1, q = v & 1;
+      const int iy = Y0 - 1 + pix / kB01XW, ix = X0 - 1 + pix % kB01XW;
+      rx[u] = u32x4{0u, 0u, 0u, 0u};
+      if (v < XCH && iy >= 0 && iy < L0.hout && ix >= 0 && ix < L0.wout)
+        rx[u] = *reinterpret_cast<const u32x4 *>(
+            act0 + ((int64_t)(nn * L0.hout + iy) * L0.wout + ix) * 16 + 8 * q);
+    }
+    // tile rows 2 Y0 - 1 + i, columns from 2 X0 - 8 (16-byte chunks)
+#pragma unroll
+    for (int u = 0; u < NT; ++u) {
+      const int v = threadIdx.x + 256 * u;
+      const int i = v / (kB01TW / 8), k = v % (kB01TW / 8);
+      const int ty = 2 * Y0 - 1 + i, tx = 2 * X0 - 8 + 8 * k;
+      rt[u] = u32x4{0u, 0u, 0u, 0u};
+      if (v < TCH && ty >= 0 && ty < L0.hin && tx >= 0 && tx < L0.win)
+        rt[u] = *reinterpret_cast<const u32x4 *>(tiles + ((int64_t)nn * L0.hin + ty) * L0.win + tx);
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int u = 0; u < NZ; ++u) {
+      const int v = threadIdx.x + 256 * u;
+      if (v < ZCH) *reinterpret_cast<u32x4 *>(&zs[(v >> 2) * kB01ZP + 8 * (v & 3)]) = rz[u];
+    }
+#pragma unroll
+    for (int u = 0; u < NX; ++u) {
+      const int v = threadIdx.x + 256 * u;
+      if (v < XCH) *reinterpret_cast<u32x4 *>(&xs[(v >> 1) * 16 + 8 * (v & 1)]) = rx[u];
+    }
+#pragma unroll
+    for (int u = 0; u < NT; ++u) {
+      const int v = threadIdx.x + 256 * u;
+      if (v < TCH)
+        *reinterpret_cast<u32x4 *>(&ts[(v / (kB01TW / 8)) * kB01TW + 8 * (v % (kB01TW / 8))]) = rt[u];
+    }
+  };
+  if ((int)blockIdx.x < nblocks) load(blockIdx.x);
   for (int blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
     const int nn = blk / (BY * BX), r = blk % (BY * BX);
     const int Y0 = (r / BX) * 2 * kB01Rows, X0 = (r % BX) * 2 * kB01Cols;
     __syncthreads();  // the previous block's readers are done
-    // layer 1's signal at rows Y0/2 + i (i <= kB01Rows), columns X0/2 + j
-    // (j <= kB01Cols), zero outside the image
-    for (int v = threadIdx.x; v < (kB01Rows + 1) * kB01ZW * 4; v += 256) {
-      const int pix = v >> 2, q = v & 3;
-      const int oy = Y0 / 2 + pix / kB01ZW, ox = X0 / 2 + pix % kB01ZW;
-      u32x4 d = {0u, 0u, 0u, 0u};
-      if (oy < L1.hout && ox < L1.wout)
-        d = *reinterpret_cast<const u32x4 *>(dz1 + ((int64_t)(nn * L1.hout + oy) * L1.wout + ox) *
-                                                       32 + 8 * q);
-      *reinterpret_cast<u32x4 *>(&zs[pix * kB01ZP + 8 * q]) = d;
-    }
-    // layer 0's activation at rows Y0 - 1 + i, columns X0 - 1 + j
-    for (int v = threadIdx.x; v < kB01XH * kB01XW * 2; v += 256) {
-      const int pix = v >> 1, q = v & 1;
-      const int iy = Y0 - 1 + pix / kB01XW, ix = X0 - 1 + pix % kB01XW;
-      u32x4 d = {0u, 0u, 0u, 0u};
-      if (iy >= 0 && iy < L0.hout && ix >= 0 && ix < L0.wout)
-        d = *reinterpret_cast<const u32x4 *>(act0 + ((int64_t)(nn * L0.hout + iy) * L0.wout + ix) *
-                                                        16 + 8 * q);
-      *reinterpret_cast<u32x4 *>(&xs[pix * 16 + 8 * q]) = d;
-    }
-    // tile rows 2 Y0 - 1 + i, columns from 2 X0 - 8 (16-byte chunks)
-    for (int v = threadIdx.x; v < kB01TH * (kB01TW / 8); v += 256) {
-      const int i = v / (kB01TW / 8), k = v % (kB01TW / 8);
-      const int ty = 2 * Y0 - 1 + i, tx = 2 * X0 - 8 + 8 * k;
-      u32x4 d = {0u, 0u, 0u, 0u};
-      if (ty >= 0 && ty < L0.hin && tx >= 0 && tx < L0.win)
-        d = *reinterpret_cast<const u32x4 *>(tiles + ((int64_t)nn * L0.hin + ty) * L0.win + tx);
-      *reinterpret_cast<u32x4 *>(&ts[i * kB01TW + 8 * k]) = d;
-    }
+    store();
     __syncthreads();
+    if (blk + (int)gridDim.x < nblocks) load(blk + gridDim.x);
     // layer 1's bias: owned pixels p = m + 8k of the staged signal
     {
       const int co = threadIdx.x & 31, m = threadIdx.x >> 5;
@@ -1321,7 +1357,19 @@ int64_t npix_in(int li, int n) { return (int64_t)n * kLayers[li].hin * kLayers[l
 int b01_blocks(int n) {
   return n * (kLayers[0].hout / (2 * kB01Rows)) * (kLayers[0].wout / (2 * kB01Cols));
 }
-int b01_grid(int n) { return b01_blocks(n) < kB01Grid ? b01_blocks(n) : kB01Grid; }
+int b01_grid(int n) {
+  static int resident = 0;
+  if (resident == 0) {
+    int per_cu = 0, dev = 0, cus = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, reinterpret_cast<const void *>(bwd01_kernel), 256, 0);
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int r = e == hipSuccess ? (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1) : kB01Grid;
+    resident = r < kB01Grid ? r : kB01Grid;
+  }
+  return b01_blocks(n) < resident ? b01_blocks(n) : resident;
+}
 
 // Workgroups of a layer's weight-gradient kernel along its other grid
 // dimension (9 / taps per workgroup) for layers 2..5; layers 0 and 1 take
