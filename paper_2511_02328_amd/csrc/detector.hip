@@ -1379,10 +1379,12 @@ int wgrad_groups(int li) {
   return g[li];
 }
 
-// Pixel splits of the weight-gradient reduction: about 864 workgroups in
-// total per layer, chunks a multiple of the staged K-step.
+// Pixel splits of the weight-gradient reduction: about 512 workgroups in
+// total per layer (two per compute unit; each prefetches its next K step,
+// so long pixel ranges cost little, and fewer splits mean fewer FP32
+// partials to write and sum), chunks a multiple of the staged K-step.
 int64_t split_chunk(int64_t npix, int li) {
-  const int64_t target = 864 / wgrad_groups(li);
+  const int64_t target = 512 / wgrad_groups(li);
   int64_t c = (npix + target - 1) / target;
   c = (c + kKP - 1) / kKP * kKP;
   return c < kKP ? kKP : c;
