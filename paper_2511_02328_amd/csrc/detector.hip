@@ -637,11 +637,15 @@ __device__ __forceinline__ u32x4 tr_pair(const uint16_t *p, int next) {
 // split the M blocks (WMG groups) and the class rows (4 / WMG groups), so a
 // weight fragment serves every class row of the wave.  A lane ends with 4
 // consecutive channels of one pixel: 8-byte mask loads and signal stores.
+// The grid is the resident workgroup count; each workgroup takes blocks
+// blockIdx.x, + gridDim.x, ... and loads the next block's signal region
+// into registers while it works on the current one.
 template <int LI, int WMG, int RPW>
 __global__ __launch_bounds__(256) void bwd_data_lds_kernel(const uint16_t *__restrict__ dz,
                                                            const uint16_t *__restrict__ wt,
                                                            const uint16_t *__restrict__ x,
-                                                           uint16_t *__restrict__ dx) {
+                                                           uint16_t *__restrict__ dx,
+                                                           int nblocks) {
   constexpr Layer L = kLayers[LI];
   constexpr int CIN = L.cin, COUT = L.cout, S = L.stride;
   constexpr int WRG = 4 / WMG, CR = WRG * RPW;       // class rows of a block
@@ -657,20 +661,41 @@ __global__ __launch_bounds__(256) void bwd_data_lds_kernel(const uint16_t *__res
   __shared__ __attribute__((aligned(16))) uint16_t zs[ZH * ZW * ZP];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, c16 = lane & 15;
   const int wm = wave % WMG, wr = wave / WMG;
-  const int blk = blockIdx.x;
-  const int nn = blk / (NBY * NBX), rb = blk % (NBY * NBX);
-  const int Y0 = (rb / NBX) * BH, X0 = (rb % NBX) * BW;
-  const int zy0 = S == 2 ? Y0 / 2 : Y0 - 1, zx0 = S == 2 ? X0 / 2 : X0 - 1;
-  for (int v = threadIdx.x; v < ZH * ZW * (COUT / 8); v += 256) {
-    const int pix = v / (COUT / 8), c8 = (v % (COUT / 8)) * 8;
-    const int oy = zy0 + pix / ZW, ox = zx0 + pix % ZW;
-    u32x4 d = {0u, 0u, 0u, 0u};
-    if (oy >= 0 && oy < L.hout && ox >= 0 && ox < L.wout)
-      d = *reinterpret_cast<const u32x4 *>(dz + ((int64_t)(nn * L.hout + oy) * L.wout + ox) *
-                                                    COUT + c8);
-    *reinterpret_cast<u32x4 *>(&zs[pix * ZP + c8]) = d;
+  constexpr int ZCH = ZH * ZW * (COUT / 8), NZ = (ZCH + 255) / 256;
+  u32x4 rz[NZ];
+  auto origin = [&](int blk, int &nn, int &Y0, int &X0) {
+    nn = blk / (NBY * NBX);
+    const int rb = blk % (NBY * NBX);
+    Y0 = (rb / NBX) * BH;
+    X0 = (rb % NBX) * BW;
+  };
+  auto load = [&](int blk) {
+    int nn, Y0, X0;
+    origin(blk, nn, Y0, X0);
+    const int zy0 = S == 2 ? Y0 / 2 : Y0 - 1, zx0 = S == 2 ? X0 / 2 : X0 - 1;
+#pragma unroll
+    for (int u = 0; u < NZ; ++u) {
+      const int v = threadIdx.x + 256 * u;
+      const int pix = v / (COUT / 8), c8 = (v % (COUT / 8)) * 8;
+      const int oy = zy0 + pix / ZW, ox = zx0 + pix % ZW;
+      rz[u] = u32x4{0u, 0u, 0u, 0u};
+      if (v < ZCH && oy >= 0 && oy < L.hout && ox >= 0 && ox < L.wout)
+        rz[u] = *reinterpret_cast<const u32x4 *>(dz + ((int64_t)(nn * L.hout + oy) * L.wout + ox) *
+                                                          COUT + c8);
+    }
+  };
+  if ((int)blockIdx.x < nblocks) load(blockIdx.x);
+  for (int blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
+  int nn, Y0, X0;
+  origin(blk, nn, Y0, X0);
+  __syncthreads();  // the previous block's readers are done
+#pragma unroll
+  for (int u = 0; u < NZ; ++u) {
+    const int v = threadIdx.x + 256 * u;
+    if (v < ZCH) *reinterpret_cast<u32x4 *>(&zs[(v / (COUT / 8)) * ZP + (v % (COUT / 8)) * 8]) = rz[u];
   }
   __syncthreads();
+  if (blk + (int)gridDim.x < nblocks) load(blk + gridDim.x);
   // A fragments: row ci = (wm * MBW + m) * 16 + c16, K = channels 8g..8g+7
   // of a 32-channel step
   const uint16_t *wrow = wt + (int64_t)(wm * MBW * 16 + c16) * K + 8 * g;
@@ -737,6 +762,7 @@ __global__ __launch_bounds__(256) void bwd_data_lds_kernel(const uint16_t *__res
       }
     __builtin_amdgcn_sched_barrier(0);
   }
+  }
 }
 
 // (WMG, RPW) of the backward-data kernel of layers 2..5 (entries 0 and 1
@@ -744,10 +770,28 @@ __global__ __launch_bounds__(256) void bwd_data_lds_kernel(const uint16_t *__res
 #define SPS_BWD_LDS_CONFIGS X(2, 2, 2) X(3, 4, 4) X(4, 4, 4) X(5, 4, 4)
 
 template <int LI, int WMG, int RPW>
-int64_t bwd_data_lds_grid(int n) {
+int bwd_data_lds_blocks(int n) {
   constexpr Layer L = kLayers[LI];
   constexpr int CR = (4 / WMG) * RPW;
-  return (int64_t)n * (L.hin / (L.stride * CR)) * (L.win / (L.stride * 16));
+  return n * (L.hin / (L.stride * CR)) * (L.win / (L.stride * 16));
+}
+
+// Workgroups resident at once for a persistent kernel (256 threads, no
+// dynamic LDS); 1024 if the query fails.
+int resident_workgroups(const void *kern) {
+  int per_cu = 0, dev = 0, cus = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0);
+  if (e == hipSuccess) e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  return e == hipSuccess ? (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1) : 1024;
+}
+
+template <int LI, int WMG, int RPW>
+int bwd_data_lds_grid(int n) {
+  static const int resident =
+      resident_workgroups(reinterpret_cast<const void *>(bwd_data_lds_kernel<LI, WMG, RPW>));
+  const int blocks = bwd_data_lds_blocks<LI, WMG, RPW>(n);
+  return blocks < resident ? blocks : resident;
 }
 
 // Layer 1's backward (data, weight and bias products) fused with layer 0's
@@ -1061,7 +1105,9 @@ __device__ __forceinline__ u32x4 tr_operand(const uint16_t *base, int row, int k
 }
 
 // partial[split][co][tap][ci] = sum over the split's output pixels q of
-// dz[q][co] * x[input of q through tap][ci], layers 1..5.  M = COUT,
+// dz[q][co] * x[input of q through tap][ci], layers 2..5, and (workgroups
+// of the first tap group) partial[split][W + co] = sum of dz[q][co], the
+// bias gradient; rows of W + COUT floats, W = COUT * 9 * CIN.  M = COUT,
 // N = CIN, K = pixels, staged 32 pixels at a time through LDS in their
 // natural [pixel][channel] layout with 16-byte copies; each lane's 8
 // K-values come from two transposed LDS reads.  A workgroup handles TAPS
@@ -1091,9 +1137,11 @@ __global__ __launch_bounds__(256) void conv_bwd_weight_kernel(const uint16_t *__
   const int64_t pbeg = split * chunk;
   const int64_t pend = pbeg + chunk < npix_out ? pbeg + chunk : npix_out;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4;
+  constexpr int64_t PW = (int64_t)COUT * 9 * CIN + COUT;  // partial row
   floatx4 acc[PER_WAVE];
 #pragma unroll
   for (int b = 0; b < PER_WAVE; ++b) acc[b] = floatx4{0.f, 0.f, 0.f, 0.f};
+  float accb = 0.f;  // bias: channel threadIdx.x (< COUT), tap group 0
   // One K step's staging in registers: the signal's and the input's 16-byte
   // chunks of this thread (fixed trip counts).  The next step's are loaded
   // while the current one's products run.
@@ -1171,6 +1219,10 @@ __global__ __launch_bounds__(256) void conv_bwd_weight_kernel(const uint16_t *__
     store();
     __syncthreads();
     if (p0 + kKP < pend) load(p0 + kKP);
+    if (blockIdx.x == 0 && threadIdx.x < COUT) {
+#pragma unroll 8
+      for (int k = 0; k < kKP; ++k) accb += bf2f(dzs[k * ZR + threadIdx.x]);
+    }
 #pragma unroll
     for (int b = 0; b < PER_WAVE; ++b) {
       const int blk = wave * PER_WAVE + b;
@@ -1204,49 +1256,21 @@ __global__ __launch_bounds__(256) void conv_bwd_weight_kernel(const uint16_t *__
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int co = mb * 16 + 4 * g + j;
-        partial[((split * COUT + co) * 9 + tap0 + tt) * CIN + ci] = acc[b][j];
+        partial[split * PW + ((int64_t)co * 9 + tap0 + tt) * CIN + ci] = acc[b][j];
       }
     }
   }
+  if (blockIdx.x == 0 && threadIdx.x < COUT)
+    partial[split * PW + (PW - COUT) + threadIdx.x] = accb;
 }
 
-// part[block][co] = sum over the block's pixels of dz[q][co].  A thread owns
-// one 16-byte group of 8 channels and strides over pixels (the stride is a
-// multiple of the groups per pixel, so its group never changes); the block
-// then reduces the threads of each group.
-template <int COUT>
-__global__ __launch_bounds__(256) void bias_partial_kernel(const uint16_t *__restrict__ dz,
-                                                           int64_t npix,
-                                                           float *__restrict__ part) {
-  constexpr int V = COUT / 8;  // 16-byte groups per pixel
-  __shared__ float red[256][9];
-  const int64_t nvec = npix * V;
-  const int64_t stride = (int64_t)gridDim.x * 256;
-  float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < nvec; v += stride) {
-    const u32x4 d = *reinterpret_cast<const u32x4 *>(dz + v * 8);
-    const uint16_t *h = reinterpret_cast<const uint16_t *>(&d);
-#pragma unroll
-    for (int i = 0; i < 8; ++i) acc[i] += bf2f(h[i]);
-  }
-#pragma unroll
-  for (int i = 0; i < 8; ++i) red[threadIdx.x][i] = acc[i];
-  __syncthreads();
-  if (threadIdx.x < COUT) {
-    const int g = threadIdx.x / 8, i = threadIdx.x % 8;
-    float t = 0.f;
-    for (int k = g; k < 256; k += V) t += red[k][i];
-    part[(int64_t)blockIdx.x * COUT + threadIdx.x] = t;
-  }
-}
-
-constexpr int kBiasBlocks = 1024;
 
 // Two-level sum of the weight-gradient partials, in a fixed order.  Level
 // one: tmp[g][i] = sum of partial[k][i] over the g-th of kWGroups contiguous
 // ranges of splits (grid (ceil(W / 256), kWGroups)); threads walk the
 // partials in their own layout so that the loads coalesce.  Level two:
-// grads[co][ci][tap] = sum_g tmp[g][i] (tmp rows `stride` floats apart).
+// grads[co][ci][tap] = sum_g tmp[g][i] (tmp rows `stride` floats apart),
+// and the cout biases that follow the weights in tmp's rows likewise.
 constexpr int kWGroups = 32;
 
 __global__ __launch_bounds__(256) void reduce_weight_partial_kernel(
@@ -1266,7 +1290,13 @@ __global__ __launch_bounds__(256) void reduce_weight_kernel(const float *__restr
                                                             float *__restrict__ grad) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t total = (int64_t)cout * cin * 9;
-  if (i >= total) return;
+  if (i >= total + cout) return;
+  if (i >= total) {  // bias
+    float s = 0.f;
+    for (int g = 0; g < kWGroups; ++g) s += tmp[(int64_t)g * stride + i];
+    grad[i] = s;
+    return;
+  }
   const int co = (int)(i / (9 * cin));
   const int rem = (int)(i - (int64_t)co * 9 * cin);
   const int tap = rem / cin, ci = rem % cin;
@@ -1400,14 +1430,13 @@ struct sps_cnn_s {
   uint16_t *wp[kNumLayers] = {}, *wt[kNumLayers] = {};
   uint16_t *act[kNumLayers] = {}, *dz[kNumLayers] = {};
   float *partial = nullptr;   // weight-gradient partials (largest layer)
-  float *bpart = nullptr;     // bias partials
   float *wtmp = nullptr;      // second level of the weight-gradient sum
   float *head_part = nullptr; // per head block: [3][128] + [3] + [1]
   float *loss = nullptr;      // device scalar of the last loss_grad
   float *head = nullptr;      // head outputs of the last forward
   float *w0f = nullptr;       // layer-0 weights rounded to bfloat16, as FP32 [16][9]
   float pos_weight = kPosWeight, lambda_box = kLambdaBox;
-  int64_t partial_cap = 0, bpart_cap = 0;
+  int64_t partial_cap = 0;
 };
 
 namespace {
@@ -1419,7 +1448,7 @@ sps_status cnn_dev_fail(hipError_t e, const char *what) {
 }
 
 void cnn_free(sps_cnn c) {
-  void *ptrs[] = {c->params, c->grads, c->m, c->v, c->partial, c->bpart, c->head_part, c->loss,
+  void *ptrs[] = {c->params, c->grads, c->m, c->v, c->partial, c->head_part, c->loss,
                   c->head, c->wtmp, c->w0f};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
@@ -1536,14 +1565,10 @@ sps_status run_backward(sps_cnn c, const uint16_t *tiles, int32_t n, hipStream_t
       hipLaunchKernelGGL(reduce_weight_partial_kernel,
                          dim3((unsigned)((kB01Part + 255) / 256), kWGroups), dim3(256), 0, s,
                          c->partial, nwg, (int64_t)kB01Part, c->wtmp);
-      hipLaunchKernelGGL(reduce_weight_kernel, dim3((unsigned)((kB01W1 + 255) / 256)), dim3(256),
-                         0, s, c->wtmp, (int64_t)kB01Part, 32, 16, gw);
-      hipLaunchKernelGGL(reduce_rows_kernel, dim3(32), dim3(256), 0, s, c->wtmp + kB01B1, kWGroups,
-                         kB01Part, gw + L.wcount());
+      hipLaunchKernelGGL(reduce_weight_kernel, dim3((unsigned)((kB01W1 + 32 + 255) / 256)),
+                         dim3(256), 0, s, c->wtmp, (int64_t)kB01Part, 32, 16, gw);
       hipLaunchKernelGGL(reduce_weight_kernel, dim3(1), dim3(256), 0, s, c->wtmp + kB01W0,
                          (int64_t)kB01Part, 16, 1, gw0);
-      hipLaunchKernelGGL(reduce_rows_kernel, dim3(16), dim3(256), 0, s, c->wtmp + kB01B0, kWGroups,
-                         kB01Part, gw0 + kLayers[0].wcount());
       SPS_LAUNCH_CHECK("backward launch");
       break;
     }
@@ -1560,30 +1585,20 @@ sps_status run_backward(sps_cnn c, const uint16_t *tiles, int32_t n, hipStream_t
       SPS_BWDW(2, 9) SPS_BWDW(3, 1) SPS_BWDW(4, 1) SPS_BWDW(5, 1)
 #undef SPS_BWDW
     }
-    hipLaunchKernelGGL(reduce_weight_partial_kernel,
-                       dim3((unsigned)((L.wcount() + 255) / 256), kWGroups), dim3(256), 0, s,
-                       c->partial, (int)nsplit, L.wcount(), c->wtmp);
-    hipLaunchKernelGGL(reduce_weight_kernel, dim3((unsigned)((L.wcount() + 255) / 256)), dim3(256),
-                       0, s, c->wtmp, L.wcount(), L.cout, L.cin, gw);
     {
-      const int64_t nvec = np * (L.cout / 8);
-      int64_t nb = (nvec + 255) / 256;
-      nb = nb < kBiasBlocks ? nb : kBiasBlocks;
-      if (L.cout == 64)
-        hipLaunchKernelGGL(bias_partial_kernel<64>, dim3((unsigned)nb), dim3(256), 0, s, c->dz[li],
-                           np, c->bpart);
-      else
-        hipLaunchKernelGGL(bias_partial_kernel<128>, dim3((unsigned)nb), dim3(256), 0, s,
-                           c->dz[li], np, c->bpart);
-      hipLaunchKernelGGL(reduce_rows_kernel, dim3((unsigned)L.cout), dim3(256), 0, s, c->bpart,
-                         (int)nb, L.cout, gw + L.wcount());
+      const int64_t pw = L.wcount() + L.cout;  // partial row: weights, then biases
+      hipLaunchKernelGGL(reduce_weight_partial_kernel, dim3((unsigned)((pw + 255) / 256), kWGroups),
+                         dim3(256), 0, s, c->partial, (int)nsplit, pw, c->wtmp);
+      hipLaunchKernelGGL(reduce_weight_kernel, dim3((unsigned)((pw + 255) / 256)), dim3(256), 0, s,
+                         c->wtmp, pw, L.cout, L.cin, gw);
     }
     switch (li) {
 #define X(LI, WMG, RPW)                                                                       \
   case LI:                                                                                    \
     hipLaunchKernelGGL((bwd_data_lds_kernel<LI, WMG, RPW>),                                   \
                        dim3((unsigned)bwd_data_lds_grid<LI, WMG, RPW>(n)), dim3(256), 0, s,   \
-                       c->dz[LI], c->wt[LI], c->act[LI - 1], c->dz[LI - 1]);                  \
+                       c->dz[LI], c->wt[LI], c->act[LI - 1], c->dz[LI - 1],                   \
+                       bwd_data_lds_blocks<LI, WMG, RPW>(n));                                 \
     break;
       SPS_BWD_LDS_CONFIGS
 #undef X
@@ -1620,12 +1635,11 @@ sps_status sps_cnn_create(int32_t max_batch, sps_cnn *out) {
   for (int i = 0; i < kNumLayers; ++i) {
     const int64_t np = npix_out(i, max_batch);
     const int64_t ns = (np + split_chunk(np, i) - 1) / split_chunk(np, i);
-    pmax = ns * kLayers[i].wcount() > pmax ? ns * kLayers[i].wcount() : pmax;
-    c->bpart_cap = ns * kLayers[i].cout > c->bpart_cap ? ns * kLayers[i].cout : c->bpart_cap;
+    const int64_t row = kLayers[i].wcount() + kLayers[i].cout;
+    pmax = ns * row > pmax ? ns * row : pmax;
   }
   pmax = (int64_t)kB01Grid * kB01Part > pmax ? (int64_t)kB01Grid * kB01Part : pmax;
   c->partial_cap = pmax;
-  c->bpart_cap = (int64_t)kBiasBlocks * 128;
   const int64_t nblk = ((int64_t)max_batch * kCells + 127) / 128;
   auto alloc = [&](void **p, size_t bytes) {
     if (e == hipSuccess) e = hipMalloc(p, bytes);
@@ -1635,8 +1649,8 @@ sps_status sps_cnn_create(int32_t max_batch, sps_cnn *out) {
   alloc((void **)&c->m, sizeof(float) * kParams);
   alloc((void **)&c->v, sizeof(float) * kParams);
   alloc((void **)&c->partial, sizeof(float) * (size_t)pmax);
-  alloc((void **)&c->bpart, sizeof(float) * (size_t)c->bpart_cap);
-  alloc((void **)&c->wtmp, sizeof(float) * (size_t)kWGroups * (size_t)kLayers[5].wcount());
+  alloc((void **)&c->wtmp,
+        sizeof(float) * (size_t)kWGroups * (size_t)(kLayers[5].wcount() + kLayers[5].cout));
   alloc((void **)&c->head_part, sizeof(float) * (size_t)(nblk * (kHead * kFeat + kHead + 1)));
   alloc((void **)&c->loss, sizeof(float) * 4);
   alloc((void **)&c->head, sizeof(float) * (size_t)max_batch * kHead * kCells);
