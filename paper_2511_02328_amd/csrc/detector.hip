@@ -1343,30 +1343,42 @@ __global__ __launch_bounds__(256) void adam_kernel(float *__restrict__ p,
   p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
 }
 
-// wp[co][tap * cin + ci] and (if wt) wt[ci][tap * cout + co] from the master
-// weights w[co][ci][tap]; padding of wp is zero.
-__global__ __launch_bounds__(256) void pack_weights_kernel(const float *__restrict__ w, int cin,
-                                                           int cout, int kpad,
-                                                           uint16_t *__restrict__ wp,
-                                                           uint16_t *__restrict__ wt) {
+// Weight packing of every layer in one launch, from the FP32 master
+// weights w[co][ci][tap]: wp[co][tap * cin + ci] (zero in the padding) and,
+// where the layer has one, wt[ci][tap * cout + co], both bfloat16; element e
+// belongs to the layer whose [begin, begin + cout * kpad) range holds it.
+// The 144 elements after the last layer write layer 0's weights rounded to
+// bfloat16 and kept as FP32 (w0f [16][9], for the forward kernel's scalar
+// loads).
+struct PackAll {
+  int64_t begin[kNumLayers + 1];  // element ranges; begin[kNumLayers] = total packed
+  int64_t param[kNumLayers];      // offset of each layer's master weights
+  uint16_t *wp[kNumLayers], *wt[kNumLayers];
+};
+
+__global__ __launch_bounds__(256) void pack_all_kernel(const float *__restrict__ params, PackAll a,
+                                                       float *__restrict__ w0f) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= (int64_t)cout * kpad) return;
-  const int co = (int)(e / kpad), k = (int)(e % kpad);
-  const int tap = k / cin, ci = k % cin;
-  if (tap >= 9) {
-    wp[e] = 0;
+  if (e >= a.begin[kNumLayers]) {
+    const int64_t i = e - a.begin[kNumLayers];
+    if (i < 16 * 9) w0f[i] = bf2f(f2bf(params[a.param[0] + i]));
     return;
   }
-  const uint16_t b = f2bf(w[((int64_t)co * cin + ci) * 9 + tap]);
-  wp[e] = b;
-  if (wt) wt[(int64_t)ci * 9 * cout + tap * cout + co] = b;
-}
-
-// Layer-0 weights (params [16][1][3][3], FP32 master copy) rounded to
-// bfloat16 and kept as FP32, for the forward kernel's scalar loads.
-__global__ __launch_bounds__(256) void round_w0_kernel(const float *__restrict__ w,
-                                                       float *__restrict__ w0f) {
-  if (threadIdx.x < 16 * 9) w0f[threadIdx.x] = bf2f(f2bf(w[threadIdx.x]));
+  int li = 0;
+#pragma unroll
+  for (int k = 1; k < kNumLayers; ++k) li += e >= a.begin[k] ? 1 : 0;
+  const Layer L = kLayers[li];
+  const int kpad = L.kpad();
+  const int64_t le = e - a.begin[li];
+  const int co = (int)(le / kpad), k = (int)(le % kpad);
+  const int tap = k / L.cin, ci = k % L.cin;
+  if (tap >= 9) {
+    a.wp[li][le] = 0;
+    return;
+  }
+  const uint16_t b = f2bf(params[a.param[li] + ((int64_t)co * L.cin + ci) * 9 + tap]);
+  a.wp[li][le] = b;
+  if (a.wt[li]) a.wt[li][(int64_t)ci * 9 * L.cout + tap * L.cout + co] = b;
 }
 
 int64_t layer_param_offset(int li) {
@@ -1461,14 +1473,18 @@ void cnn_free(sps_cnn c) {
 }
 
 hipError_t pack_all(sps_cnn c, hipStream_t s) {
+  PackAll a{};
+  int64_t total = 0;
   for (int i = 0; i < kNumLayers; ++i) {
-    const Layer &L = kLayers[i];
-    const int64_t total = (int64_t)L.cout * L.kpad();
-    hipLaunchKernelGGL(pack_weights_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
-                       c->params + layer_param_offset(i), L.cin, L.cout, L.kpad(), c->wp[i],
-                       c->wt[i]);
+    a.begin[i] = total;
+    a.param[i] = layer_param_offset(i);
+    a.wp[i] = c->wp[i];
+    a.wt[i] = c->wt[i];
+    total += (int64_t)kLayers[i].cout * kLayers[i].kpad();
   }
-  hipLaunchKernelGGL(round_w0_kernel, dim3(1), dim3(256), 0, s, c->params, c->w0f);
+  a.begin[kNumLayers] = total;
+  hipLaunchKernelGGL(pack_all_kernel, dim3((unsigned)((total + 16 * 9 + 255) / 256)), dim3(256), 0,
+                     s, c->params, a, c->w0f);
   return hipGetLastError();
 }
 
