@@ -518,7 +518,9 @@ sps_status sps_cnn_get_grads(sps_cnn net, float *host);
 sps_status sps_cnn_activations(sps_cnn net, int32_t layer, int32_t n, uint16_t *host);
 /* The bfloat16 signal back-propagated to the output of 3x3 layer `layer`
  * (gradient of the loss w.r.t. its pre-activation, masked by a > 0) for the
- * first n tiles of the last sps_cnn_loss_grad, NHWC (synchronous). */
+ * first n tiles of the last sps_cnn_loss_grad, NHWC (synchronous).
+ * sps_cnn_train_step keeps the signals of layers 1..5 but not layer 0's,
+ * which no product reads. */
 sps_status sps_cnn_signals(sps_cnn net, int32_t layer, int32_t n, uint16_t *host);
 
 /* Pools the S/N plane snr (device FP32 [ndm][pitch], first nout used) into
@@ -563,7 +565,8 @@ sps_status sps_cnn_loss_grad(sps_cnn net, const uint16_t *tiles, const float *la
 /* One Adam step (with bias correction) from the gradient buffer.  Asynchronous. */
 sps_status sps_cnn_adam(sps_cnn net, float lr, float beta1, float beta2, float eps,
                         void *stream);
-/* sps_cnn_loss_grad then sps_cnn_adam(lr, 0.9, 0.999, 1e-8). */
+/* sps_cnn_loss_grad then sps_cnn_adam(lr, 0.9, 0.999, 1e-8); layer 0's
+ * back-propagated signal is not stored (see sps_cnn_signals). */
 sps_status sps_cnn_train_step(sps_cnn net, const uint16_t *tiles, const float *labels, int32_t n,
                               float lr, float *loss, void *stream);
 /* Forward pass, then every cell whose objectness probability is >= threshold

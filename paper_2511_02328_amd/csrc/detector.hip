@@ -807,8 +807,9 @@ int bwd_data_lds_grid(int n) {
 //    N = 16 class pixels of one class row, K = the class's taps x 32 (one
 //    16x16x32 product per tap); a wave takes one class row.  The lane's 4
 //    channels of one pixel are masked by the staged activation, rounded to
-//    bfloat16 and stored, and then, as FP32, multiply the pixel's 9 tile
-//    values into the lane's layer-0 weight-gradient sums (and bias sums).
+//    bfloat16, stored if store0 (nothing else reads layer 0's signal), and
+//    then, as FP32, multiply the pixel's 9 tile values into the lane's
+//    layer-0 weight-gradient sums (and bias sums).
 //  - Layer 1's weight gradient: M = 32 output channels, N = 16 input
 //    channels per tap, K = the 64 owned output pixels; both operands come
 //    from the staged signal and activation through transposed LDS reads,
@@ -835,7 +836,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
                                                     const uint16_t *__restrict__ act0,
                                                     const uint16_t *__restrict__ tiles,
                                                     uint16_t *__restrict__ dz0,
-                                                    float *__restrict__ partial, int nblocks) {
+                                                    float *__restrict__ partial, int nblocks,
+                                                    int store0) {
   constexpr Layer L0 = kLayers[0], L1 = kLayers[1];
   static_assert(L1.cin == 16 && L1.cout == 32 && L1.stride == 2, "layer 1 shape");
   constexpr int BY = L0.hout / (2 * kB01Rows), BX = L0.wout / (2 * kB01Cols);
@@ -1004,9 +1006,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
           zf[j] = bf2f(zq[j]);
           accb[j] += zf[j];
         }
-        *reinterpret_cast<uint2 *>(dz0 + o) =
-            make_uint2((uint32_t)zq[0] | ((uint32_t)zq[1] << 16),
-                       (uint32_t)zq[2] | ((uint32_t)zq[3] << 16));
+        if (store0)
+          *reinterpret_cast<uint2 *>(dz0 + o) =
+              make_uint2((uint32_t)zq[0] | ((uint32_t)zq[1] << 16),
+                         (uint32_t)zq[2] | ((uint32_t)zq[3] << 16));
         // the tile values layer 0 read for this pixel: (2 iy + ky - 1,
         // 2 ix + kx - 1), staged at (2 (iy - Y0) + ky, 2 (ix - X0) + kx + 7)
         const uint16_t *tp = ts + (2 * (iy - Y0)) * kB01TW + 2 * (ix - X0) + 7;
@@ -1567,7 +1570,8 @@ sps_status run_head(sps_cnn c, const float *labels, int32_t n, bool train, hipSt
   return SPS_OK;
 }
 
-sps_status run_backward(sps_cnn c, const uint16_t *tiles, int32_t n, hipStream_t s) {
+// keep0: store layer 0's signal (for sps_cnn_signals); no product reads it.
+sps_status run_backward(sps_cnn c, const uint16_t *tiles, int32_t n, hipStream_t s, bool keep0) {
   for (int li = kNumLayers - 1; li >= 1; --li) {
     const Layer &L = kLayers[li];
     float *gw = c->grads + layer_param_offset(li);
@@ -1577,7 +1581,7 @@ sps_status run_backward(sps_cnn c, const uint16_t *tiles, int32_t n, hipStream_t
       float *gw0 = c->grads + layer_param_offset(0);
       const int nwg = b01_grid(n);
       hipLaunchKernelGGL(bwd01_kernel, dim3((unsigned)nwg), dim3(256), 0, s, c->dz[1], c->wt[1],
-                         c->act[0], tiles, c->dz[0], c->partial, b01_blocks(n));
+                         c->act[0], tiles, c->dz[0], c->partial, b01_blocks(n), keep0 ? 1 : 0);
       hipLaunchKernelGGL(reduce_weight_partial_kernel,
                          dim3((unsigned)((kB01Part + 255) / 256), kWGroups), dim3(256), 0, s,
                          c->partial, nwg, (int64_t)kB01Part, c->wtmp);
@@ -1839,21 +1843,28 @@ sps_status sps_cnn_infer(sps_cnn c, const uint16_t *tiles, int32_t n, float *hea
   return SPS_OK;
 }
 
-sps_status sps_cnn_loss_grad(sps_cnn c, const uint16_t *tiles, const float *labels, int32_t n,
-                             float *loss, void *stream) {
+namespace {
+sps_status loss_grad(sps_cnn c, const uint16_t *tiles, const float *labels, int32_t n, float *loss,
+                     void *stream, bool keep0) {
   sps_status r = check_batch(c, tiles, n);
   if (r != SPS_OK) return r;
   if (!labels) return sps::set_error(SPS_ERR_INVALID_ARG, "NULL labels");
   hipStream_t s = (hipStream_t)stream;
   r = run_forward(c, tiles, n, s, true);
   if (r == SPS_OK) r = run_head(c, labels, n, true, s);
-  if (r == SPS_OK) r = run_backward(c, tiles, n, s);
+  if (r == SPS_OK) r = run_backward(c, tiles, n, s, keep0);
   if (r != SPS_OK) return r;
   if (loss) {
     hipError_t e = hipMemcpyAsync(loss, c->loss, sizeof(float), hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return cnn_dev_fail(e, "loss copy");
   }
   return SPS_OK;
+}
+}  // namespace
+
+sps_status sps_cnn_loss_grad(sps_cnn c, const uint16_t *tiles, const float *labels, int32_t n,
+                             float *loss, void *stream) {
+  return loss_grad(c, tiles, labels, n, loss, stream, true);
 }
 
 sps_status sps_cnn_adam(sps_cnn c, float lr, float beta1, float beta2, float eps, void *stream) {
@@ -1875,7 +1886,7 @@ sps_status sps_cnn_adam(sps_cnn c, float lr, float beta1, float beta2, float eps
 
 sps_status sps_cnn_train_step(sps_cnn c, const uint16_t *tiles, const float *labels, int32_t n,
                               float lr, float *loss, void *stream) {
-  sps_status r = sps_cnn_loss_grad(c, tiles, labels, n, loss, stream);
+  sps_status r = loss_grad(c, tiles, labels, n, loss, stream, false);
   if (r != SPS_OK) return r;
   return sps_cnn_adam(c, lr, 0.9f, 0.999f, 1e-8f, stream);
 }
