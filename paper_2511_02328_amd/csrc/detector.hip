@@ -1086,7 +1086,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
 // Backward: weights and biases
 // ---------------------------------------------------------------------------
 
-constexpr int kKP = 32;  // pixels per staged K-step
+// Pixels per staged K step of a layer's weight gradient (a multiple of 32,
+// the K of one product).  Larger steps put more products between the
+// barriers and the prefetched loads, but their staging registers cost
+// occupancy: measured per layer at batch 256, 128 pixels took layer 3 from
+// 98 to 89 us, while layers 2, 4 and 5 were slower with 64 or 128 (one wave
+// per SIMD).  Layer 2's steps lie in one output row.
+constexpr int wg_kp(int li) { return li == 3 ? 128 : 32; }
 
 // bf16 per staged pixel row for C channels: the 4 rows that one group of 16
 // lanes reads in a transposed read then fall in disjoint LDS banks (row
@@ -1120,7 +1126,7 @@ __device__ __forceinline__ u32x4 tr_operand(const uint16_t *base, int row, int k
 // 2) the 32 pixels of a K step lie in one output row, and the input region
 // they read (3 rows x 65 pixels) is staged once for all taps; each lane
 // addresses its pixels' tap inputs inside it.
-template <int LI, int TAPS>
+template <int LI, int TAPS, int KP = wg_kp(LI)>
 __global__ __launch_bounds__(256) void conv_bwd_weight_kernel(const uint16_t *__restrict__ dz,
                                                               const uint16_t *__restrict__ x,
                                                               float *__restrict__ partial,
@@ -1131,10 +1137,10 @@ __global__ __launch_bounds__(256) void conv_bwd_weight_kernel(const uint16_t *__
   constexpr int PER_WAVE = (NBLK + 3) / 4;
   constexpr int ZR = wg_row(COUT), XR = wg_row(CIN);
   constexpr bool REGION = TAPS == 9;
-  static_assert(!REGION || (S == 2 && L.wout % kKP == 0), "region staging: whole K steps per row");
-  constexpr int RW = 2 * kKP + 1;  // region pixels per input row
-  __shared__ __attribute__((aligned(16))) uint16_t dzs[kKP * ZR];
-  __shared__ __attribute__((aligned(16))) uint16_t xs[REGION ? 1 : TAPS][(REGION ? 3 * RW : kKP) * XR];
+  static_assert(!REGION || (S == 2 && L.wout % KP == 0), "region staging: whole K steps per row");
+  constexpr int RW = 2 * KP + 1;  // region pixels per input row
+  __shared__ __attribute__((aligned(16))) uint16_t dzs[KP * ZR];
+  __shared__ __attribute__((aligned(16))) uint16_t xs[REGION ? 1 : TAPS][(REGION ? 3 * RW : KP) * XR];
   const int tap0 = blockIdx.x * TAPS;
   const int64_t split = blockIdx.y;
   const int64_t pbeg = split * chunk;
@@ -1148,8 +1154,8 @@ __global__ __launch_bounds__(256) void conv_bwd_weight_kernel(const uint16_t *__
   // One K step's staging in registers: the signal's and the input's 16-byte
   // chunks of this thread (fixed trip counts).  The next step's are loaded
   // while the current one's products run.
-  constexpr int ZCH = kKP * COUT / 8;
-  constexpr int XCH = REGION ? 3 * RW * CIN / 8 : TAPS * kKP * CIN / 8;
+  constexpr int ZCH = KP * COUT / 8;
+  constexpr int XCH = REGION ? 3 * RW * CIN / 8 : TAPS * KP * CIN / 8;
   constexpr int NZ = (ZCH + 255) / 256, NX = (XCH + 255) / 256;
   u32x4 rz[NZ], rx[NX];
   auto load = [&](int64_t p0) {
@@ -1162,7 +1168,7 @@ __global__ __launch_bounds__(256) void conv_bwd_weight_kernel(const uint16_t *__
       if (v < ZCH && q < pend) rz[u] = *reinterpret_cast<const u32x4 *>(dz + q * COUT + c8);
     }
     if constexpr (REGION) {
-      // input rows 2 oy - 1 .. + 2, columns 2 ox0 - 1 .. 2 ox0 + 2 kKP - 1
+      // input rows 2 oy - 1 .. + 2, columns 2 ox0 - 1 .. 2 ox0 + 2 KP - 1
       const int64_t n = p0 / (L.hout * L.wout);
       const int r0 = (int)(p0 - n * L.hout * L.wout);
       const int oy = r0 / L.wout, ox0 = r0 % L.wout;
@@ -1179,8 +1185,8 @@ __global__ __launch_bounds__(256) void conv_bwd_weight_kernel(const uint16_t *__
 #pragma unroll
       for (int u = 0; u < NX; ++u) {
         const int v = threadIdx.x + 256 * u;
-        const int tt = v / (kKP * CIN / 8);
-        const int rem = v - tt * (kKP * CIN / 8);
+        const int tt = v / (KP * CIN / 8);
+        const int rem = v - tt * (KP * CIN / 8);
         const int pix = rem / (CIN / 8), c8 = (rem % (CIN / 8)) * 8;
         const int tap = tap0 + tt;
         const int64_t q = p0 + pix;
@@ -1209,8 +1215,8 @@ __global__ __launch_bounds__(256) void conv_bwd_weight_kernel(const uint16_t *__
         if constexpr (REGION) {
           *reinterpret_cast<u32x4 *>(&xs[0][(v / (CIN / 8)) * XR + (v % (CIN / 8)) * 8]) = rx[u];
         } else {
-          const int tt = v / (kKP * CIN / 8);
-          const int rem = v - tt * (kKP * CIN / 8);
+          const int tt = v / (KP * CIN / 8);
+          const int rem = v - tt * (KP * CIN / 8);
           *reinterpret_cast<u32x4 *>(&xs[tt][(rem / (CIN / 8)) * XR + (rem % (CIN / 8)) * 8]) =
               rx[u];
         }
@@ -1218,13 +1224,13 @@ __global__ __launch_bounds__(256) void conv_bwd_weight_kernel(const uint16_t *__
     }
   };
   if (pbeg < pend) load(pbeg);
-  for (int64_t p0 = pbeg; p0 < pend; p0 += kKP) {
+  for (int64_t p0 = pbeg; p0 < pend; p0 += KP) {
     store();
     __syncthreads();
-    if (p0 + kKP < pend) load(p0 + kKP);
+    if (p0 + KP < pend) load(p0 + KP);
     if (blockIdx.x == 0 && threadIdx.x < COUT) {
 #pragma unroll 8
-      for (int k = 0; k < kKP; ++k) accb += bf2f(dzs[k * ZR + threadIdx.x]);
+      for (int k = 0; k < KP; ++k) accb += bf2f(dzs[k * ZR + threadIdx.x]);
     }
 #pragma unroll
     for (int b = 0; b < PER_WAVE; ++b) {
@@ -1232,19 +1238,22 @@ __global__ __launch_bounds__(256) void conv_bwd_weight_kernel(const uint16_t *__
       if (blk < NBLK) {
         const int tt = blk / (MB * NB), rb = blk % (MB * NB);
         const int mb = rb / NB, nb = rb % NB;
-        const u32x4 av = tr_operand(dzs, ZR, 0, mb * 16, lane);
-        u32x4 bv;
-        if constexpr (REGION) {
-          // pixel k = 8g + (s >> 2) (+ 4) of the step reads region pixel
-          // (ky, 2k + kx) through tap (ky, kx)
-          const int tap = tap0 + tt, sl = lane & 15;
-          const int k = 8 * g + (sl >> 2);
-          bv = tr_pair(&xs[0][((tap / 3) * RW + 2 * k + tap % 3) * XR + nb * 16 + 4 * (sl & 3)],
-                       8 * XR);
-        } else {
-          bv = tr_operand(xs[tt], XR, 0, nb * 16, lane);
+#pragma unroll
+        for (int ks = 0; ks < KP / 32; ++ks) {
+          const u32x4 av = tr_operand(dzs, ZR, 32 * ks, mb * 16, lane);
+          u32x4 bv;
+          if constexpr (REGION) {
+            // pixel k = 32 ks + 8g + (s >> 2) (+ 4) of the step reads region
+            // pixel (ky, 2k + kx) through tap (ky, kx)
+            const int tap = tap0 + tt, sl = lane & 15;
+            const int k = 32 * ks + 8 * g + (sl >> 2);
+            bv = tr_pair(&xs[0][((tap / 3) * RW + 2 * k + tap % 3) * XR + nb * 16 + 4 * (sl & 3)],
+                         8 * XR);
+          } else {
+            bv = tr_operand(xs[tt], XR, 32 * ks, nb * 16, lane);
+          }
+          acc[b] = mfma(av, bv, acc[b]);
         }
-        acc[b] = mfma(av, bv, acc[b]);
       }
     }
     __syncthreads();
@@ -1427,12 +1436,12 @@ int wgrad_groups(int li) {
 // Pixel splits of the weight-gradient reduction: about 512 workgroups in
 // total per layer (two per compute unit; each prefetches its next K step,
 // so long pixel ranges cost little, and fewer splits mean fewer FP32
-// partials to write and sum), chunks a multiple of the staged K-step.
+// partials to write and sum), chunks a multiple of the layer's K step.
 int64_t split_chunk(int64_t npix, int li) {
-  const int64_t target = 512 / wgrad_groups(li);
+  const int64_t target = 512 / wgrad_groups(li), kp = wg_kp(li);
   int64_t c = (npix + target - 1) / target;
-  c = (c + kKP - 1) / kKP * kKP;
-  return c < kKP ? kKP : c;
+  c = (c + kp - 1) / kp * kp;
+  return c < kp ? kp : c;
 }
 
 }  // namespace
