@@ -239,6 +239,19 @@ def main():
     t_obs = wl.nout * wl.tsamp_s
     print(f"[bench] {args.steps} steps: {ms_step:.2f} ms/step, dedisperse {dd.mean()*1e3:.2f} ms, "
           f"statistics+boxcar+detection {sr.mean()*1e3:.2f} ms, {n} candidates", flush=True)
+    # the same search of the last step's plane without S/N or width planes
+    # (candidates only): statistics, boxcar and detection at 4 B per output
+    wp = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
+    for k in range(args.steps):
+        wp[k][0].record(stream)
+        c_np, n_np = sps.sps_search(plan, Y, wl.nout, wl.widths, None, None, st, cap=4096,
+                                    stream=stream, allow_truncated=True, **det)
+        wp[k][1].record(stream)
+    torch.cuda.synchronize()
+    sr_np = np.array([e[0].elapsed_time(e[1]) for e in wp]) / 1e3
+    same_np = n_np == n and bool(np.array_equal(c_np, cands))
+    print(f"[bench] without planes: statistics+boxcar+detection {sr_np.mean()*1e3:.2f} ms, "
+          f"same candidates {same_np}", flush=True)
 
     # injected pulses recovered (outside the timed region), with and without
     # the zero-DM filter in front of the search
@@ -306,7 +319,13 @@ def main():
         "hbm_stages": {
             "stats_boxcar_detect": {"bytes": 13 * wl.ndm * wl.nout,
                                     "gb_per_s": 13 * wl.ndm * wl.nout / sr.mean() / 1e9,
-                                    "frac": 13 * wl.ndm * wl.nout / sr.mean() / HBM_PEAK_BPS}},
+                                    "frac": 13 * wl.ndm * wl.nout / sr.mean() / HBM_PEAK_BPS},
+            # the search writing no planes: statistics and boxcar each read
+            # the plane once (4 + 4 B per output)
+            "without_planes": {"ms": sr_np.mean() * 1e3, "bytes": 8 * wl.ndm * wl.nout,
+                               "gb_per_s": 8 * wl.ndm * wl.nout / sr_np.mean() / 1e9,
+                               "frac": 8 * wl.ndm * wl.nout / sr_np.mean() / HBM_PEAK_BPS,
+                               "same_candidates": same_np}},
         "candidates": n,
         "injection_recovery": recovery,
         "roofline": {"kernel": "dedisperse_kernel", "bound": "alu", "achieved": achieved,
@@ -395,6 +414,39 @@ def bench_batched(args, bw):
     ev1.record(stream)
     ev1.synchronize()
     t_graph = ev0.elapsed_time(ev1) / args.steps / 1e3
+    # the same search without S/N or width planes (candidates only; each
+    # tile key carries its peak's width): its own autotuned tiling, the same
+    # candidates
+    bare = sps.sps_batch_create(plan, [dict(b, snr=None, best_w=None) for b in beams],
+                                list(wl0.widths), **det)
+    sps.sps_batch_autotune(bare, 3, stream)
+    sps.sps_batch_launch_graph(batch, stream)
+    sps.sps_batch_launch_graph(bare, stream)
+    same = True
+    for i in range(bw.nbeams):
+        cf, nf = sps.sps_batch_candidates(batch, i, cap=4096, stream=stream, allow_truncated=True)
+        cb, nb = sps.sps_batch_candidates(bare, i, cap=4096, stream=stream, allow_truncated=True)
+        same = same and nf == nb and bool(np.array_equal(cf, cb))
+
+    def step_bare():
+        sps.sps_batch_launch_graph(bare, stream)
+        return sum(sps.sps_batch_candidates(bare, i, cap=4096, stream=stream,
+                                            allow_truncated=True)[1] for i in range(bw.nbeams))
+
+    for _ in range(args.warmup):
+        step_bare()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step_bare()
+    wall_bare = time.perf_counter() - t0
+    ev0.record(stream)
+    for _ in range(args.steps):
+        sps.sps_batch_launch_graph(bare, stream)
+    ev1.record(stream)
+    ev1.synchronize()
+    t_graph_bare = ev0.elapsed_time(ev1) / args.steps / 1e3
+    bare.close()
     samples = sum(wl0.ndm * n for n in lengths)
     adds = samples * wl0.nchan
     durations = [n * wl0.tsamp_s for n in lengths]
@@ -414,6 +466,10 @@ def bench_batched(args, bw):
         "real_time_factor_vs_shortest_chunk": min(durations) / float(np.percentile(lat, 99)),
         "real_time_sustained": bool(np.percentile(lat, 99) < min(durations)),
         "candidates": n,
+        "without_planes": {"value": samples / (wall_bare / args.steps),
+                           "ms_per_step": wall_bare / args.steps * 1e3,
+                           "graph_ms": t_graph_bare * 1e3, "same_candidates": same,
+                           "note": "the same search writing no S/N or width plane"},
         # the dominant kernel, timed by the batch autotuner with HIP events on
         # the launch stream (mean of its timed launches of the kept tiling);
         # the whole step's four launches beside it

@@ -165,8 +165,12 @@ sps_status sps_detect(sps_plan plan, const float *snr, const uint8_t *best_w, in
  * second pass over the S/N plane.  Same arguments, checks, results and
  * errors as sps_boxcar_snr followed by sps_detect on the same plan (Sec. 1
  * step iii; Sec. 2, candidate record); snr, best_w and stats receive the
- * same planes.  Uses the plan's detection scratch (grown on demand).
- * Synchronises the stream. */
+ * same planes.  snr and best_w may both be NULL: then no S/N or width plane
+ * is written (4 bytes of traffic per output instead of 13) and each tile's
+ * key carries the width of its peak; the candidates are the same.  That
+ * mode needs min(tile_dm, ndm) x min(tile_t, nout) <= 2^26 (else RANGE).
+ * Uses the plan's detection scratch (grown on demand).  Synchronises the
+ * stream. */
 sps_status sps_search(sps_plan plan, const uint32_t *Y, int64_t nout, const int32_t *widths,
                       int32_t nw, float *snr, uint8_t *best_w, int32_t *stats,
                       const sps_detect_params *params, sps_candidate *out, int32_t cap,
@@ -284,8 +288,8 @@ typedef struct {
   int64_t nsamp_in;
   uint32_t *Y;      /* [ndm][nout] */
   int64_t nout;     /* >= largest width */
-  float *snr;       /* [ndm][nout] */
-  uint8_t *best_w;  /* [ndm][nout] */
+  float *snr;       /* [ndm][nout], or NULL with best_w (see below) */
+  uint8_t *best_w;  /* [ndm][nout], or NULL with snr */
   int32_t *stats;   /* [ndm][2] */
 } sps_beam;
 
@@ -296,7 +300,10 @@ typedef struct sps_batch_s *sps_batch;
  * the batch allocates nothing and never waits on the host.  The plan's
  * current tiling is used (call sps_plan_autotune / sps_plan_set_tiling
  * first); the plan must outlive the batch.  RANGE if the plan needs the
- * plain kernel.  Every beam's candidates read "none" until its first run. */
+ * plain kernel.  Every beam's candidates read "none" until its first run.
+ * Either every beam has snr and best_w or none has (INVALID_ARG otherwise):
+ * without them the batch searches as sps_search does without planes (same
+ * candidates, same tile size limit). */
 sps_status sps_batch_create(sps_plan plan, int32_t nbeams, const sps_beam *beams,
                             const int32_t *widths, int32_t nw, const sps_detect_params *params,
                             uint32_t flags, sps_batch *out);

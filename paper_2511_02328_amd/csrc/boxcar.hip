@@ -62,10 +62,16 @@ __device__ uint32_t block_exclusive_scan256(uint32_t v, uint32_t *tmp /* >= 4 */
 // consecutive outputs a wave handles at a time share one column, and its
 // lanes change column, and leave the last segment's loop, together: a
 // flush reduces the wave's keys and issues one atomic.
-template <int TILES>
+// PK: the key's low word.  0: complement of the position (the planes hold
+// the width).  1 (no planes): packed position and width index, the width
+// tracked with each maximum.  2 (no planes, TILES = 1): packed; a thread
+// tracks S/N and position only, and finish() recomputes the width index of
+// the one output it reports (width_at(t_local)).
+template <int TILES, int PK = 0>
 struct TileTrack {
   float s = -INFINITY;
   int tl = 0;
+  int bi = 0;
   int64_t col = 0, col_end = 0;
 
   __device__ __forceinline__ void begin(const TileSink &k, int64_t t0) {
@@ -79,7 +85,13 @@ struct TileTrack {
     const int a = d / k.tile_dm;
     const uint32_t pos =
         (uint32_t)((t - col * k.tile_t) * k.tile_dm + (int64_t)(d - a * k.tile_dm));
-    return ((unsigned long long)snr_key_bits(s) << 32) | (unsigned long long)(~pos);
+    uint32_t lo;
+    if constexpr (PK == 0)
+      lo = ~pos;
+    else
+      lo = (((uint32_t)(kKeyPosLimit - 1) - pos) << kKeyWidthBits) |
+           ((uint32_t)bi & ((1u << kKeyWidthBits) - 1u));
+    return ((unsigned long long)snr_key_bits(s) << 32) | (unsigned long long)lo;
   }
   __device__ __forceinline__ void flush(const TileSink &k, int d, int64_t t0) {
     if constexpr (TILES == 3) {
@@ -98,8 +110,9 @@ struct TileTrack {
         atomicMax(k.keys + (int64_t)(d / k.tile_dm) * k.ntt + col, key(k, d, t0));
     }
   }
-  __device__ __forceinline__ void add(const TileSink &k, int d, int64_t t0, float v, int t_local) {
-    if constexpr (TILES == 1) {
+  __device__ __forceinline__ void add(const TileSink &k, int d, int64_t t0, float v, int t_local,
+                                      int b) {
+    if constexpr (TILES == 1 && PK == 0) {
       s = fmaxf(s, v);
       return;
     }
@@ -115,15 +128,17 @@ struct TileTrack {
       if (v > s) {
         s = v;
         tl = t_local;
+        if constexpr (PK == 1) bi = b;
       }
     }
   }
   // Every thread of the workgroup calls this once, after its last add;
-  // srow[0, len) are the S/N values this segment wrote (TILES = 1 reads
-  // back its own outputs).
+  // srow[0, len) are the S/N values this segment wrote (TILES = 1 with
+  // PK = 0 reads back its own outputs).
+  template <class W>
   __device__ __forceinline__ void finish(const TileSink &k, int d, int64_t t0,
                                          unsigned long long *red, const SPS_GLOBAL float *srow,
-                                         int len) {
+                                         int len, W &&width_at) {
     if constexpr (TILES == 1) {
       float m = s;
 #pragma unroll
@@ -134,18 +149,22 @@ struct TileTrack {
 #pragma unroll
       for (int w = 0; w < kThreads / 64; ++w) m = fmaxf(m, redf[w]);
       if (s == m && m != -INFINITY) {
-        // this thread's outputs are threadIdx.x + kThreads j, in order; all
-        // of them are read at once, the first equal to m wins
-        float v[kPer];
+        if constexpr (PK == 0) {
+          // this thread's outputs are threadIdx.x + kThreads j, in order; all
+          // of them are read at once, the first equal to m wins
+          float v[kPer];
 #pragma unroll
-        for (int j = 0; j < kPer; ++j) {
-          const int t = threadIdx.x + kThreads * j;
-          v[j] = t < len ? srow[t] : -INFINITY;
+          for (int j = 0; j < kPer; ++j) {
+            const int t = threadIdx.x + kThreads * j;
+            v[j] = t < len ? srow[t] : -INFINITY;
+          }
+          int first = kPer - 1;
+#pragma unroll
+          for (int j = kPer - 2; j >= 0; --j) first = v[j] == m ? j : first;
+          tl = threadIdx.x + kThreads * first;
+        } else if constexpr (PK == 2) {
+          bi = width_at(tl);
         }
-        int first = kPer - 1;
-#pragma unroll
-        for (int j = kPer - 2; j >= 0; --j) first = v[j] == m ? j : first;
-        tl = threadIdx.x + kThreads * first;
         atomicMax(k.keys + (int64_t)(d / k.tile_dm) * k.ntt + col, key(k, d, t0));
       }
     } else if constexpr (TILES >= 2) {
@@ -154,9 +173,16 @@ struct TileTrack {
   }
 };
 
+// finish() argument of segments whose sink needs no recomputed width.
+struct NoWidth {
+  __device__ __forceinline__ int operator()(int) const { return 0; }
+};
+
 // Where a segment's outputs go.  PlaneSink: the S/N and width planes, and
-// the tile maxima (TileTrack).  PoolSink: an LDS row of S/N values, for the
-// max-pooled detector tiles (first row of a pair stored, second maxed in).
+// the tile maxima (TileTrack).  KeySink: the tile maxima alone, with the
+// width index in the key (a search that writes no planes).  PoolSink: an
+// LDS row of S/N values, for the max-pooled detector tiles (first row of a
+// pair stored, second maxed in).
 template <int TILES>
 struct PlaneSink {
   SPS_GLOBAL float *srow;
@@ -170,9 +196,30 @@ struct PlaneSink {
   __device__ __forceinline__ void put(int tl, float v, int bi) {
     srow[tl] = v;
     brow[tl] = (uint8_t)bi;
-    tr.add(*tiles, d, t0, v, tl);
+    tr.add(*tiles, d, t0, v, tl, bi);
   }
-  __device__ __forceinline__ void finish() { tr.finish(*tiles, d, t0, red, srow, len); }
+  template <class W>
+  __device__ __forceinline__ void finish(W &&) {
+    tr.finish(*tiles, d, t0, red, srow, len, NoWidth{});
+  }
+};
+
+template <int TILES, int PK>
+struct KeySink {
+  static_assert(TILES != 0 && PK != 0, "a sink without planes gathers packed tile keys");
+  const TileSink *tiles;
+  unsigned long long *red;
+  int d;
+  int len;
+  int64_t t0;
+  TileTrack<TILES, PK> tr;
+  __device__ __forceinline__ void put(int tl, float v, int bi) {
+    tr.add(*tiles, d, t0, v, tl, bi);
+  }
+  template <class W>
+  __device__ __forceinline__ void finish(W &&width_at) {
+    tr.finish(*tiles, d, t0, red, nullptr, len, width_at);
+  }
 };
 
 struct PoolSink {
@@ -181,7 +228,8 @@ struct PoolSink {
   __device__ __forceinline__ void put(int tl, float v, int) {
     pv[tl] = first ? v : fmaxf(pv[tl], v);
   }
-  __device__ __forceinline__ void finish() {}
+  template <class W>
+  __device__ __forceinline__ void finish(W &&) {}
 };
 
 // Widths 1, 2, 4, ..., 2^(NPOW-1): window offsets are immediates of the LDS
@@ -271,13 +319,11 @@ __device__ __forceinline__ void pow2_filter(int n_left, int32_t med, int32_t mad
   float sc[NPOW];
 #pragma unroll
   for (int i = 0; i < NPOW; ++i) sc[i] = scale[i];
-#pragma unroll 2
-  for (int m = 0; m < kPer; ++m) {
-    const int tl = threadIdx.x + kThreads * m;
-    if (TAIL && tl >= seg_len) break;
+  // S/N of every width at output tl, their maximum, and the smallest width
+  // index that attains it
+  auto eval = [&](int tl, float (&s)[NPOW]) {
     const uint32_t *pt = P + tl;
     const uint32_t p0 = pt[0];
-    float s[NPOW];
 #pragma unroll
     for (int i = 0; i < NPOW; ++i) {
       s[i] = (float)(int32_t)(pt[1 << i] - p0) * sc[i];
@@ -286,11 +332,28 @@ __device__ __forceinline__ void pow2_filter(int n_left, int32_t med, int32_t mad
     float mx = s[0];
 #pragma unroll
     for (int i = 1; i < NPOW; ++i) mx = fmaxf(mx, s[i]);
+    return mx;
+  };
+  auto first_of = [](const float (&s)[NPOW], float mx) {
     int bi = NPOW - 1;
 #pragma unroll
     for (int i = NPOW - 2; i >= 0; --i) bi = s[i] == mx ? i : bi;
-    out.put(tl, live ? mx : 0.0f, bi);
+    return bi;
+  };
+#pragma unroll 2
+  for (int m = 0; m < kPer; ++m) {
+    const int tl = threadIdx.x + kThreads * m;
+    if (TAIL && tl >= seg_len) break;
+    float s[NPOW];
+    const float mx = eval(tl, s);
+    out.put(tl, live ? mx : 0.0f, first_of(s, mx));
   }
+  // the same arithmetic again, for a sink that tracks no width
+  out.finish([&](int tl) {
+    float s[NPOW];
+    const float mx = eval(tl, s);
+    return first_of(s, mx);
+  });
 }
 
 template <int NPOW, bool TAIL, class Sink>
@@ -307,7 +370,7 @@ __device__ __forceinline__ void pow2_segment(const SPS_GLOBAL uint32_t *src, int
 
 // NPOW > 0: power-of-two widths (pow2_segment); NPOW = 0: any width list.
 // One segment of row d: outputs [seg kSeg, seg kSeg + kSeg) go to `out`
-// (out.put(t - seg kSeg, S/N, width index)), then out.finish().
+// (out.put(t - seg kSeg, S/N, width index)), then out.finish(width_at).
 template <int NPOW, class Sink>
 __device__ __forceinline__ void boxcar_core(const uint32_t *__restrict__ Y, int64_t nout, int d,
                                             int seg, const int32_t *__restrict__ stats,
@@ -330,7 +393,6 @@ __device__ __forceinline__ void boxcar_core(const uint32_t *__restrict__ Y, int6
       pow2_segment<NPOW, false>(row + t0, kLen, med, mad, widths, scale, tmp, P, out);
     else
       pow2_segment<NPOW, true>(row + t0, (int)avail, med, mad, widths, scale, tmp, P, out);
-    out.finish();
     return;
   }
 
@@ -380,7 +442,7 @@ __device__ __forceinline__ void boxcar_core(const uint32_t *__restrict__ Y, int6
       }
       out.put(tl, live ? bs : 0.0f, bi);
     }
-    out.finish();
+    out.finish(NoWidth{});
     return;
   }
 
@@ -404,40 +466,22 @@ __device__ __forceinline__ void boxcar_core(const uint32_t *__restrict__ Y, int6
     }
     out.put(tl, bi == 0xFF ? 0.0f : bs, bi);
   }
-  out.finish();
+  out.finish(NoWidth{});
 }
 
-// The S/N and width planes of one segment, with the tile maxima.
-template <int NPOW, int TILES>
-__device__ __forceinline__ void boxcar_segment(const uint32_t *__restrict__ Y, int64_t nout, int d,
-                                               int seg, const int32_t *__restrict__ stats,
-                                               const WidthList &widths, float *__restrict__ snr,
-                                               uint8_t *__restrict__ best, uint32_t *P,
-                                               const TileSink &sink) {
-  __shared__ unsigned long long red[kThreads / 64];
-  const int64_t t0 = (int64_t)seg * kSeg;
-  PlaneSink<TILES> out{gmem(snr + (int64_t)d * nout + t0), gmem(best + (int64_t)d * nout + t0),
-                       &sink, red, d, (int)(nout - t0 < kSeg ? nout - t0 : kSeg), t0,
-                       TileTrack<TILES>{}};
-  out.tr.begin(sink, t0);
-  boxcar_core<NPOW>(Y, nout, d, seg, stats, widths, P, out);
-}
-
-// One segment of row d into the S/N and width planes, with the tile maxima.
-template <int NPOW, int TILES>
-__device__ __forceinline__ void boxcar_plane_segment(const uint32_t *__restrict__ Y, int64_t nout,
-                                                     int d, int seg,
-                                                     const int32_t *__restrict__ stats,
-                                                     const WidthList &widths,
-                                                     float *__restrict__ snr,
-                                                     uint8_t *__restrict__ best, uint32_t *P,
-                                                     const TileSink &sink) {
+// One segment of row d into `out` (planes and tile maxima, or tile maxima
+// alone); the power-of-two path issues the segment's loads first.
+template <int NPOW, class Sink>
+__device__ __forceinline__ void boxcar_sink_segment(const uint32_t *__restrict__ Y, int64_t nout,
+                                                    int d, int seg,
+                                                    const int32_t *__restrict__ stats,
+                                                    const WidthList &widths, uint32_t *P,
+                                                    Sink &out) {
   if constexpr (NPOW == 0) {
-    boxcar_segment<0, TILES>(Y, nout, d, seg, stats, widths, snr, best, P, sink);
+    boxcar_core<0>(Y, nout, d, seg, stats, widths, P, out);
   } else {
     __shared__ float scale[kMaxWidths];
     __shared__ uint32_t tmp[4];
-    __shared__ unsigned long long red[kThreads / 64];
     constexpr int kLen = Pow2<NPOW>::kLen;
     const int64_t t0 = (int64_t)seg * kSeg, avail = nout - t0;
     const SPS_GLOBAL uint32_t *src = gmem(Y + (int64_t)d * nout + t0);
@@ -450,15 +494,36 @@ __device__ __forceinline__ void boxcar_plane_segment(const uint32_t *__restrict_
       pow2_fetch<NPOW, true>(src, (int)avail, v);
     set_scales(widths, mad, scale);
     pow2_stage<NPOW>(v, med, P);
-    PlaneSink<TILES> out{gmem(snr + (int64_t)d * nout + t0), gmem(best + (int64_t)d * nout + t0),
-                         &sink, red, d, (int)(avail < kSeg ? avail : kSeg), t0,
-                         TileTrack<TILES>{}};
-    out.tr.begin(sink, t0);
     if (avail >= (int64_t)kLen)
       pow2_filter<NPOW, false>(kLen, med, mad, scale, tmp, P, out);
     else
       pow2_filter<NPOW, true>((int)avail, med, mad, scale, tmp, P, out);
-    out.finish();
+  }
+}
+
+// One segment of row d: with PK = 0 into the S/N and width planes, with
+// the tile maxima (TILES); with PK != 0 the packed tile maxima alone.
+template <int NPOW, int TILES, int PK>
+__device__ __forceinline__ void boxcar_plane_segment(const uint32_t *__restrict__ Y, int64_t nout,
+                                                     int d, int seg,
+                                                     const int32_t *__restrict__ stats,
+                                                     const WidthList &widths,
+                                                     float *__restrict__ snr,
+                                                     uint8_t *__restrict__ best, uint32_t *P,
+                                                     const TileSink &sink) {
+  static_assert(PK != 2 || (TILES == 1 && NPOW > 0), "widths recomputed only on power-of-two rows");
+  __shared__ unsigned long long red[kThreads / 64];
+  const int64_t t0 = (int64_t)seg * kSeg, avail = nout - t0;
+  const int len = (int)(avail < kSeg ? avail : kSeg);
+  if constexpr (PK == 0) {
+    PlaneSink<TILES> out{gmem(snr + (int64_t)d * nout + t0), gmem(best + (int64_t)d * nout + t0),
+                         &sink, red, d, len, t0, TileTrack<TILES>{}};
+    out.tr.begin(sink, t0);
+    boxcar_sink_segment<NPOW>(Y, nout, d, seg, stats, widths, P, out);
+  } else {
+    KeySink<TILES, PK> out{&sink, red, d, len, t0, TileTrack<TILES, PK>{}};
+    out.tr.begin(sink, t0);
+    boxcar_sink_segment<NPOW>(Y, nout, d, seg, stats, widths, P, out);
   }
 }
 
@@ -486,7 +551,7 @@ __device__ __forceinline__ void boxcar_pool_pair(const uint32_t *__restrict__ Y,
 }
 
 // One workgroup per (DM row, segment).
-template <int NPOW, int TILES>
+template <int NPOW, int TILES, int PK>
 __global__ __launch_bounds__(kThreads) void boxcar_kernel(
     const uint32_t *__restrict__ Y, int64_t nout, int nseg, const int32_t *__restrict__ stats,
     WidthList widths, float *__restrict__ snr, uint8_t *__restrict__ best, TileSink sink) {
@@ -494,12 +559,13 @@ __global__ __launch_bounds__(kThreads) void boxcar_kernel(
   const int64_t blk = blockIdx.x;
   const int d = (int)(blk / nseg);
   const int seg = (int)(blk - (int64_t)d * nseg);
-  boxcar_plane_segment<NPOW, TILES>(Y, nout, d, seg, stats, widths, snr, best, P, sink);
+  boxcar_plane_segment<NPOW, TILES, PK>(Y, nout, d, seg, stats, widths, snr, best, P, sink);
 }
 
 // One workgroup per (beam, DM row, segment) of a batch.  With TILES, the
-// beam's tile keys are the out array of its detection scratch.
-template <int NPOW, int TILES>
+// beam's tile keys are the out array of its detection scratch; with PK, no
+// beam has planes.
+template <int NPOW, int TILES, int PK>
 __global__ __launch_bounds__(kThreads) void boxcar_batch_kernel(
     const BeamWork *__restrict__ beams, int nbeams, WidthList widths, uint8_t *scratch, int ndm,
     int tile_dm, int64_t tile_t) {
@@ -517,9 +583,10 @@ __global__ __launch_bounds__(kThreads) void boxcar_batch_kernel(
     sink.tile_dm = tile_dm;
     sink.tile_t = tile_t;
     sink.ntt = bw.ntt;
+    sink.packed = PK != 0;
   }
-  boxcar_plane_segment<NPOW, TILES>(bw.Y, bw.nout, d, seg, bw.stats, widths, bw.snr, bw.best, P,
-                                    sink);
+  boxcar_plane_segment<NPOW, TILES, PK>(bw.Y, bw.nout, d, seg, bw.stats, widths, bw.snr, bw.best,
+                                        P, sink);
 }
 
 // Tile keys: zeroed (DECODE false) or turned into tile peak records.
@@ -533,7 +600,9 @@ __device__ __forceinline__ void tile_key(const TileSink &k, int ndm, int64_t nou
   const unsigned long long v = k.keys[i];
   const int a = (int)(i / k.ntt);
   const int64_t b = i - (int64_t)a * k.ntt;
-  const uint32_t pos = ~(uint32_t)v;
+  const uint32_t lo = (uint32_t)v;
+  const uint32_t pos =
+      k.packed ? (uint32_t)(kKeyPosLimit - 1) - (lo >> kKeyWidthBits) : ~lo;
   int64_t tl = pos / (uint32_t)k.tile_dm;
   int dl = (int)(pos - (uint32_t)tl * (uint32_t)k.tile_dm);
   const int d0 = a * k.tile_dm;
@@ -546,7 +615,10 @@ __device__ __forceinline__ void tile_key(const TileSink &k, int ndm, int64_t nou
   p.snr = v == 0ull ? 0.0f : snr_from_key_bits((uint32_t)(v >> 32));
   p.d = d0 + dl;
   p.t = (int32_t)(t0 + tl);
-  p.w = gmem(best)[(int64_t)p.d * nout + p.t];
+  if (k.packed)
+    p.w = v == 0ull ? 0 : (int32_t)(lo & ((1u << kKeyWidthBits) - 1u));
+  else
+    p.w = gmem(best)[(int64_t)p.d * nout + p.t];
   peaks[i] = p;
 }
 
@@ -562,7 +634,7 @@ __global__ __launch_bounds__(kThreads) void tile_keys_kernel(TileSink k, int64_t
 // One thread per (beam, tile) of a batch.
 __global__ __launch_bounds__(kThreads) void tile_keys_batch_kernel(
     const BeamWork *__restrict__ beams, int nbeams, int ndm, int64_t total_tiles, int tile_dm,
-    int64_t tile_t, uint8_t *scratch, int decode) {
+    int64_t tile_t, uint8_t *scratch, int decode, int packed) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i >= total_tiles) return;
   const BeamWork &bw = beams[find_beam<&BeamWork::tp_begin>(beams, nbeams, i)];
@@ -573,6 +645,7 @@ __global__ __launch_bounds__(kThreads) void tile_keys_batch_kernel(
   k.tile_dm = tile_dm;
   k.tile_t = tile_t;
   k.ntt = bw.ntt;
+  k.packed = packed;
   tile_key(k, ndm, bw.nout, bw.best, reinterpret_cast<TilePeak *>(scratch + bw.det_begin + L.peaks),
            i - bw.tp_begin, decode != 0);
 }
@@ -628,6 +701,81 @@ int tile_mode(const void *keys, int64_t tile_t, bool rows_of_64) {
   return tile_t % kSeg == 0 ? 1 : (tile_t % 64 == 0 && rows_of_64 ? 3 : 2);
 }
 
+// f.run<NPOW, TILES, PK>() for a launch: NPOW = number of widths when they
+// are 1, 2, 4, ... (else 0), TILES = tile mode; without planes PK = 2 where
+// widths can be recomputed (TILES = 1, power-of-two widths), else 1.
+template <int N, class F>
+void boxcar_dispatch_n(int tm, bool planes, F &f) {
+  if (planes) {
+    if (tm == 0) f.template run<N, 0, 0>();
+    else if (tm == 1) f.template run<N, 1, 0>();
+    else if (tm == 3) f.template run<N, 3, 0>();
+    else f.template run<N, 2, 0>();
+  } else {
+    if (tm == 1) f.template run<N, 1, (N > 0 ? 2 : 1)>();
+    else if (tm == 3) f.template run<N, 3, 1>();
+    else f.template run<N, 2, 1>();
+  }
+}
+
+template <class F>
+void boxcar_dispatch(const WidthList &widths, int tm, bool planes, F &f) {
+  bool pow2 = widths.n <= 13;
+  for (int i = 0; i < widths.n && pow2; ++i) pow2 = widths.w[i] == (1 << i);
+  switch (pow2 ? widths.n : 0) {
+    case 1: boxcar_dispatch_n<1>(tm, planes, f); break;
+    case 2: boxcar_dispatch_n<2>(tm, planes, f); break;
+    case 3: boxcar_dispatch_n<3>(tm, planes, f); break;
+    case 4: boxcar_dispatch_n<4>(tm, planes, f); break;
+    case 5: boxcar_dispatch_n<5>(tm, planes, f); break;
+    case 6: boxcar_dispatch_n<6>(tm, planes, f); break;
+    case 7: boxcar_dispatch_n<7>(tm, planes, f); break;
+    case 8: boxcar_dispatch_n<8>(tm, planes, f); break;
+    case 9: boxcar_dispatch_n<9>(tm, planes, f); break;
+    case 10: boxcar_dispatch_n<10>(tm, planes, f); break;
+    case 11: boxcar_dispatch_n<11>(tm, planes, f); break;
+    case 12: boxcar_dispatch_n<12>(tm, planes, f); break;
+    case 13: boxcar_dispatch_n<13>(tm, planes, f); break;
+    default: boxcar_dispatch_n<0>(tm, planes, f); break;
+  }
+}
+
+struct BoxcarLaunch {
+  dim3 grid;
+  size_t lds;
+  hipStream_t stream;
+  const uint32_t *Y;
+  int64_t nout;
+  int nseg;
+  const int32_t *stats;
+  WidthList widths;
+  float *snr;
+  uint8_t *best;
+  TileSink sink;
+  template <int N, int T, int K>
+  void run() {
+    hipLaunchKernelGGL((boxcar_kernel<N, T, K>), grid, dim3(kThreads), lds, stream, Y, nout, nseg,
+                       stats, widths, snr, best, sink);
+  }
+};
+
+struct BoxcarBatchLaunch {
+  dim3 grid;
+  size_t lds;
+  hipStream_t stream;
+  const BeamWork *beams;
+  int nbeams;
+  WidthList widths;
+  uint8_t *scratch;
+  int ndm, tile_dm;
+  int64_t tile_t;
+  template <int N, int T, int K>
+  void run() {
+    hipLaunchKernelGGL((boxcar_batch_kernel<N, T, K>), grid, dim3(kThreads), lds, stream, beams,
+                       nbeams, widths, scratch, ndm, tile_dm, tile_t);
+  }
+};
+
 }  // namespace
 
 hipError_t launch_boxcar(const uint32_t *Y, int ndm, int64_t nout, const int32_t *stats,
@@ -637,63 +785,27 @@ hipError_t launch_boxcar(const uint32_t *Y, int ndm, int64_t nout, const int32_t
   const int64_t grid = nseg * ndm;
   if (grid > 0x7FFFFFFF || nseg > 0x7FFFFFFF) return hipErrorInvalidValue;
   if (sink.keys && (sink.tile_dm < 1 || sink.tile_t < 1)) return hipErrorInvalidValue;
-  bool pow2 = widths.n <= 13;
-  for (int i = 0; i < widths.n && pow2; ++i) pow2 = widths.w[i] == (1 << i);
-  const size_t lds = boxcar_lds_bytes(widths);
+  const bool planes = snr != nullptr;
+  if (planes != (best != nullptr) || planes == (sink.packed != 0)) return hipErrorInvalidValue;
+  if (!planes && !sink.keys) return hipErrorInvalidValue;
   const int tm = tile_mode(sink.keys, sink.tile_t, nout % 64 == 0);
-#define SPS_BOXCAR_LAUNCH(n_, t_)                                                          \
-  hipLaunchKernelGGL((boxcar_kernel<n_, t_>), dim3((unsigned)grid), dim3(kThreads), lds, stream, \
-                     Y, nout, (int)nseg, stats, widths, snr, best, sink)
-#define SPS_BOXCAR_CASE(n_)                                 \
-  if (pow2 && widths.n == n_) {                             \
-    if (tm == 0) SPS_BOXCAR_LAUNCH(n_, 0);                  \
-    else if (tm == 1) SPS_BOXCAR_LAUNCH(n_, 1);             \
-    else if (tm == 3) SPS_BOXCAR_LAUNCH(n_, 3);             \
-    else SPS_BOXCAR_LAUNCH(n_, 2);                          \
-    return hipGetLastError();                               \
-  }
-  SPS_BOXCAR_CASE(1) SPS_BOXCAR_CASE(2) SPS_BOXCAR_CASE(3) SPS_BOXCAR_CASE(4) SPS_BOXCAR_CASE(5)
-  SPS_BOXCAR_CASE(6) SPS_BOXCAR_CASE(7) SPS_BOXCAR_CASE(8) SPS_BOXCAR_CASE(9) SPS_BOXCAR_CASE(10)
-  SPS_BOXCAR_CASE(11) SPS_BOXCAR_CASE(12) SPS_BOXCAR_CASE(13)
-  if (tm == 0) SPS_BOXCAR_LAUNCH(0, 0);
-  else if (tm == 1) SPS_BOXCAR_LAUNCH(0, 1);
-  else if (tm == 3) SPS_BOXCAR_LAUNCH(0, 3);
-  else SPS_BOXCAR_LAUNCH(0, 2);
-#undef SPS_BOXCAR_CASE
-#undef SPS_BOXCAR_LAUNCH
+  BoxcarLaunch f{dim3((unsigned)grid), boxcar_lds_bytes(widths), stream, Y, nout, (int)nseg,
+                 stats, widths, snr, best, sink};
+  boxcar_dispatch(widths, tm, planes, f);
   return hipGetLastError();
 }
 
 hipError_t launch_boxcar_batch(const BeamWork *beams, int nbeams, int64_t total_blocks,
                                const WidthList &widths, hipStream_t stream, uint8_t *scratch,
-                               int ndm, int tile_dm, int64_t tile_t, bool rows_of_64) {
+                               int ndm, int tile_dm, int64_t tile_t, bool rows_of_64,
+                               bool planes) {
   if (total_blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
   if (scratch && (tile_dm < 1 || tile_t < 1 || ndm < 1)) return hipErrorInvalidValue;
-  bool pow2 = widths.n <= 13;
-  for (int i = 0; i < widths.n && pow2; ++i) pow2 = widths.w[i] == (1 << i);
-  const size_t lds = boxcar_lds_bytes(widths);
+  if (!planes && !scratch) return hipErrorInvalidValue;
   const int tm = tile_mode(scratch, tile_t, rows_of_64);
-#define SPS_BOXCAR_BLAUNCH(n_, t_)                                                           \
-  hipLaunchKernelGGL((boxcar_batch_kernel<n_, t_>), dim3((unsigned)total_blocks), dim3(kThreads), \
-                     lds, stream, beams, nbeams, widths, scratch, ndm, tile_dm, tile_t)
-#define SPS_BOXCAR_BCASE(n_)                                \
-  if (pow2 && widths.n == n_) {                             \
-    if (tm == 0) SPS_BOXCAR_BLAUNCH(n_, 0);                 \
-    else if (tm == 1) SPS_BOXCAR_BLAUNCH(n_, 1);            \
-    else if (tm == 3) SPS_BOXCAR_BLAUNCH(n_, 3);            \
-    else SPS_BOXCAR_BLAUNCH(n_, 2);                         \
-    return hipGetLastError();                               \
-  }
-  SPS_BOXCAR_BCASE(1) SPS_BOXCAR_BCASE(2) SPS_BOXCAR_BCASE(3) SPS_BOXCAR_BCASE(4)
-  SPS_BOXCAR_BCASE(5) SPS_BOXCAR_BCASE(6) SPS_BOXCAR_BCASE(7) SPS_BOXCAR_BCASE(8)
-  SPS_BOXCAR_BCASE(9) SPS_BOXCAR_BCASE(10) SPS_BOXCAR_BCASE(11) SPS_BOXCAR_BCASE(12)
-  SPS_BOXCAR_BCASE(13)
-  if (tm == 0) SPS_BOXCAR_BLAUNCH(0, 0);
-  else if (tm == 1) SPS_BOXCAR_BLAUNCH(0, 1);
-  else if (tm == 3) SPS_BOXCAR_BLAUNCH(0, 3);
-  else SPS_BOXCAR_BLAUNCH(0, 2);
-#undef SPS_BOXCAR_BCASE
-#undef SPS_BOXCAR_BLAUNCH
+  BoxcarBatchLaunch f{dim3((unsigned)total_blocks), boxcar_lds_bytes(widths), stream, beams,
+                      nbeams, widths, scratch, ndm, tile_dm, tile_t};
+  boxcar_dispatch(widths, tm, planes, f);
   return hipGetLastError();
 }
 
@@ -711,12 +823,13 @@ hipError_t launch_tile_keys(const TileSink &sink, int ndm, int64_t nout, const u
 
 hipError_t launch_tile_keys_batch(const BeamWork *beams, int nbeams, int ndm, int64_t total_tiles,
                                   int tile_dm, int64_t tile_t, uint8_t *scratch, bool decode,
-                                  hipStream_t stream) {
+                                  bool packed, hipStream_t stream) {
   const int64_t grid = (total_tiles + kThreads - 1) / kThreads;
   if (grid > 0x7FFFFFFF || tile_dm < 1 || tile_t < 1) return hipErrorInvalidValue;
   if (grid == 0) return hipSuccess;
   hipLaunchKernelGGL(tile_keys_batch_kernel, dim3((unsigned)grid), dim3(kThreads), 0, stream,
-                     beams, nbeams, ndm, total_tiles, tile_dm, tile_t, scratch, decode ? 1 : 0);
+                     beams, nbeams, ndm, total_tiles, tile_dm, tile_t, scratch, decode ? 1 : 0,
+                     packed ? 1 : 0);
   return hipGetLastError();
 }
 

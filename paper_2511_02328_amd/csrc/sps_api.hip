@@ -336,6 +336,15 @@ sps_status check_boxcar(sps_plan plan, int64_t nout, const int32_t *widths, int3
   return SPS_OK;
 }
 
+// A search without planes carries the in-tile position and the width index
+// in one 32-bit key word: a tile (clipped to the plane) may hold at most
+// kKeyPosLimit outputs.
+bool packed_keys_fit(int ndm, int64_t nout, const sps_detect_params *prm) {
+  const int64_t td = prm->tile_dm < ndm ? prm->tile_dm : ndm;
+  const int64_t tt = prm->tile_t < nout ? prm->tile_t : nout;
+  return td * tt <= sps::kKeyPosLimit;
+}
+
 // sps_detect and sps_detect_noalloc: the same checks and kernels; the
 // scratch is the plan's (grown with hipMalloc on demand) or the fixed one.
 sps_status run_detect(sps_plan plan, const float *snr, const uint8_t *best_w, int64_t nout,
@@ -602,8 +611,8 @@ sps_status sps_search(sps_plan plan, const uint32_t *Y, int64_t nout, const int3
                       const sps_detect_params *prm, sps_candidate *out, int32_t cap,
                       int32_t *n_found, void *stream) {
   g_error.clear();
-  if (!plan || !Y || !widths || !snr || !best_w)
-    return fail(SPS_ERR_INVALID_ARG, "NULL plan or buffer");
+  if (!plan || !Y || !widths || (!snr) != (!best_w))
+    return fail(SPS_ERR_INVALID_ARG, "NULL plan or buffer (snr and best_w are NULL together)");
   sps::WidthList wl;
   uint32_t vmax = 0;
   sps_status st = check_boxcar(plan, nout, widths, nw, &wl, &vmax);
@@ -611,6 +620,10 @@ sps_status sps_search(sps_plan plan, const uint32_t *Y, int64_t nout, const int3
   DetectArgs a;
   st = check_detect(plan, nout, nw, prm, out, cap, n_found, &a);
   if (st != SPS_OK) return st;
+  const bool planes = snr != nullptr;
+  if (!planes && !packed_keys_fit(plan->ndm, nout, prm))
+    return fail(SPS_ERR_RANGE, "without planes a tile may hold at most %lld outputs",
+                (long long)sps::kKeyPosLimit);
   DeviceScope scope(plan->device);
   if (scope.err != hipSuccess) return hip_fail(scope.err, "selecting the plan's device");
   uint8_t *det = nullptr;
@@ -623,6 +636,7 @@ sps_status sps_search(sps_plan plan, const uint32_t *Y, int64_t nout, const int3
   sink.tile_dm = prm->tile_dm;
   sink.tile_t = prm->tile_t;
   sink.ntt = a.ntt;
+  sink.packed = planes ? 0 : 1;
   sps::TilePeak *peaks = reinterpret_cast<sps::TilePeak *>(det + a.L.peaks);
   hipError_t e = sps::launch_tile_keys(sink, plan->ndm, nout, best_w, peaks, false, s);
   if (e != hipSuccess) return hip_fail(e, "tile key clearing launch");
@@ -953,6 +967,7 @@ struct sps_batch_s {
   int64_t pl_blocks = 0, pool_tiles = 0;  // pooled-tile boxcar workgroups, detector tiles
   uint16_t *tiles = nullptr;              // tile mode (sps_batch_set_tiles): destination
   float tile_scale = 0.0f;
+  bool planes = true;  // false: no beam has S/N or width planes (packed tile keys)
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipStream_t graph_stream = nullptr;
@@ -1005,15 +1020,15 @@ sps_status batch_enqueue(sps_batch b, hipStream_t s) {
   }
   // tile maxima taken inside the boxcar pass: keys zeroed, gathered, decoded
   e = sps::launch_tile_keys_batch(b->d_beams, b->nbeams, p->ndm, b->tp_tiles, b->prm.tile_dm,
-                                  b->prm.tile_t, b->d_det, false, s);
+                                  b->prm.tile_t, b->d_det, false, !b->planes, s);
   if (e != hipSuccess) return hip_fail(e, "batched tile key clearing launch");
   bool rows_of_64 = true;
   for (int64_t n : b->nout) rows_of_64 = rows_of_64 && n % 64 == 0;
   e = sps::launch_boxcar_batch(b->d_beams, b->nbeams, b->bx_blocks, b->widths, s, b->d_det,
-                               p->ndm, b->prm.tile_dm, b->prm.tile_t, rows_of_64);
+                               p->ndm, b->prm.tile_dm, b->prm.tile_t, rows_of_64, b->planes);
   if (e != hipSuccess) return hip_fail(e, "batched boxcar launch");
   e = sps::launch_tile_keys_batch(b->d_beams, b->nbeams, p->ndm, b->tp_tiles, b->prm.tile_dm,
-                                  b->prm.tile_t, b->d_det, true, s);
+                                  b->prm.tile_t, b->d_det, true, !b->planes, s);
   if (e != hipSuccess) return hip_fail(e, "batched tile key decoding launch");
   e = sps::launch_select_nms_batch(b->d_beams, b->nbeams, p->ndm, b->prm.tile_dm, b->prm.tile_t,
                                    b->prm.threshold, b->prm.nms_dm, b->prm.nms_t, b->d_det, s);
@@ -1066,9 +1081,17 @@ sps_status sps_batch_create(sps_plan plan, int32_t nbeams, const sps_beam *beams
   const int64_t ntd = (plan->ndm + prm->tile_dm - 1) / prm->tile_dm;
   for (int i = 0; i < nbeams; ++i) {
     const sps_beam &q = beams[i];
-    if (!q.X || !q.Y || !q.snr || !q.best_w || !q.stats) {
+    if (i == 0) b->planes = q.snr != nullptr;
+    if (!q.X || !q.Y || !q.stats || (!q.snr) != (!q.best_w) || (q.snr != nullptr) != b->planes) {
       free_batch(b);
-      return fail(SPS_ERR_INVALID_ARG, "beam %d has a NULL buffer", i);
+      return fail(SPS_ERR_INVALID_ARG,
+                  "beam %d has a NULL buffer (snr and best_w may be NULL together, in every beam)",
+                  i);
+    }
+    if (!b->planes && !packed_keys_fit(plan->ndm, q.nout, prm)) {
+      free_batch(b);
+      return fail(SPS_ERR_RANGE, "without planes a tile may hold at most %lld outputs",
+                  (long long)sps::kKeyPosLimit);
     }
     if (!aligned16(q.X) || q.pitch % 16 != 0) {
       free_batch(b);

@@ -184,14 +184,23 @@ __device__ __forceinline__ float snr_from_key_bits(uint32_t k) {
 // in the low word, so the largest key is the tile's largest S/N at the
 // smallest t, then the smallest d (the order the tile peak kernel uses).
 // keys == nullptr: no tile maxima.  The keys must be zero before the pass.
+// packed != 0 (a pass that writes no planes): the low word is instead
+// (kKeyPosLimit - 1 - position) << kKeyWidthBits | width index, the same
+// order (a position holds one width), with the width carried in the key;
+// in-tile positions must stay below kKeyPosLimit.
+constexpr int kKeyWidthBits = 6;  // width indices < kMaxWidths = 64
+constexpr int64_t kKeyPosLimit = int64_t(1) << (32 - kKeyWidthBits);
+static_assert(kMaxWidths <= (1 << kKeyWidthBits), "width index must fit the key");
 struct TileSink {
   unsigned long long *keys;  // [ntd][ntt]
   int32_t tile_dm;
-  int32_t pad;
+  int32_t packed;
   int64_t tile_t;
   int64_t ntt;
 };
 
+// snr and best both null: no planes, tile maxima alone (sink.keys set,
+// sink.packed != 0); otherwise sink.packed must be 0.
 hipError_t launch_boxcar(const uint32_t *Y, int ndm, int64_t nout, const int32_t *stats,
                          const WidthList &widths, float *snr, uint8_t *best,
                          hipStream_t stream, const TileSink &sink = TileSink{});
@@ -280,11 +289,13 @@ hipError_t launch_row_stats_batch(const BeamWork *beams, int nbeams, int ndm, ui
 // scratch != nullptr: every beam's tile maxima go to the key array of its
 // detection scratch (the out array of detect_layout, at scratch +
 // det_begin), which must be zero.
-// rows_of_64: every beam's nout is a multiple of 64.
+// rows_of_64: every beam's nout is a multiple of 64.  planes == false: no
+// beam has S/N or width planes (snr, best null) and the keys are packed
+// (TileSink::packed); needs scratch.
 hipError_t launch_boxcar_batch(const BeamWork *beams, int nbeams, int64_t total_blocks,
                                const WidthList &widths, hipStream_t stream,
                                uint8_t *scratch = nullptr, int ndm = 0, int tile_dm = 1,
-                               int64_t tile_t = 1, bool rows_of_64 = false);
+                               int64_t tile_t = 1, bool rows_of_64 = false, bool planes = true);
 int64_t boxcar_segments(int64_t nout);
 
 // Detector tiles taken straight from the boxcar pass: the S/N of whole
@@ -302,15 +313,15 @@ hipError_t launch_boxcar_pool_batch(const BeamWork *beams, int nbeams, int64_t t
 
 // Tile keys of a plane (TileSink): decode == false zeroes them; decode ==
 // true turns them into the tile peak records (S/N, d, t and the width index
-// best[d][t]) that the selection kernel reads, as the tile peak kernel would
-// have written them.
+// best[d][t], or the key's own with packed keys, best unused) that the
+// selection kernel reads, as the tile peak kernel would have written them.
 hipError_t launch_tile_keys(const TileSink &sink, int ndm, int64_t nout, const uint8_t *best,
                             TilePeak *peaks, bool decode, hipStream_t stream);
 // The same over every beam of a batch: keys in the out array of each beam's
 // detection scratch, peaks in its peaks array.
 hipError_t launch_tile_keys_batch(const BeamWork *beams, int nbeams, int ndm, int64_t total_tiles,
                                   int tile_dm, int64_t tile_t, uint8_t *scratch, bool decode,
-                                  hipStream_t stream);
+                                  bool packed, hipStream_t stream);
 // Selection and suppression of every beam of a batch from its tile peaks.
 hipError_t launch_select_nms_batch(const BeamWork *beams, int nbeams, int ndm, int tile_dm,
                                    int64_t tile_t, float threshold, int nms_dm, int64_t nms_t,

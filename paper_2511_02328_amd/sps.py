@@ -224,6 +224,10 @@ def _dev(t: torch.Tensor, dtype, name: str) -> int:
     return t.data_ptr()
 
 
+def _dev_or_none(t: Optional[torch.Tensor], dtype, name: str) -> Optional[int]:
+    return None if t is None else _dev(t, dtype, name)
+
+
 class Plan:
     """Owns an sps_plan handle; closed explicitly or when garbage collected."""
 
@@ -312,11 +316,13 @@ def sps_boxcar_snr(plan: Plan, Y: torch.Tensor, nout: int, widths: Sequence[int]
            "sps_boxcar_snr")
 
 
-def sps_search(plan: Plan, Y: torch.Tensor, nout: int, widths: Sequence[int], snr: torch.Tensor,
-               best_w: torch.Tensor, stats: Optional[torch.Tensor], threshold: float,
+def sps_search(plan: Plan, Y: torch.Tensor, nout: int, widths: Sequence[int],
+               snr: Optional[torch.Tensor], best_w: Optional[torch.Tensor],
+               stats: Optional[torch.Tensor], threshold: float,
                tile_dm: int, tile_t: int, nms_dm: int, nms_t: int, cap: int = 4096,
                stream=None, allow_truncated: bool = False):
-    """Statistics, boxcar S/N and detection in one call; returns (candidates, number found)."""
+    """Statistics, boxcar S/N and detection in one call; returns (candidates, number found).
+    snr and best_w None together: no planes are written."""
     w = np.ascontiguousarray(widths, dtype=np.int32)
     yp = _dev(Y, torch.int32, "Y") if Y.dtype == torch.int32 else _dev(Y, torch.uint32, "Y")
     sp = _dev(stats, torch.int32, "stats") if stats is not None else None
@@ -324,7 +330,8 @@ def sps_search(plan: Plan, Y: torch.Tensor, nout: int, widths: Sequence[int], sn
     out = (sps_candidate * max(cap, 1))()
     n = ctypes.c_int32()
     rc = library().sps_search(plan.handle, yp, int(nout), w.ctypes.data, w.size,
-                              _dev(snr, torch.float32, "snr"), _dev(best_w, torch.uint8, "best_w"),
+                              _dev_or_none(snr, torch.float32, "snr"),
+                              _dev_or_none(best_w, torch.uint8, "best_w"),
                               sp, ctypes.byref(prm), out, int(cap), ctypes.byref(n),
                               _stream(stream))
     if not (rc == 6 and allow_truncated):
@@ -468,7 +475,8 @@ class Batch:
 
 def sps_batch_create(plan: Plan, beams: Sequence[dict], widths: Sequence[int], threshold: float,
                      tile_dm: int, tile_t: int, nms_dm: int, nms_t: int, flags: int = 0) -> Batch:
-    """beams: dicts with tensors X, Y, snr, best_w, stats and ints nsamp_in, nout."""
+    """beams: dicts with tensors X, Y, snr, best_w, stats and ints nsamp_in, nout; snr and
+    best_w may be None (in every beam): no planes are written."""
     arr = (sps_beam * len(beams))()
     keep = []
     for i, b in enumerate(beams):
@@ -477,8 +485,8 @@ def sps_batch_create(plan: Plan, beams: Sequence[dict], widths: Sequence[int], t
             raise ValueError("X must be [nchan][pitch] with unit sample stride")
         yp = _dev(Y, torch.int32, "Y") if Y.dtype == torch.int32 else _dev(Y, torch.uint32, "Y")
         arr[i] = sps_beam(_dev(X, torch.uint8, "X"), X.stride(0), int(b["nsamp_in"]), yp,
-                          int(b["nout"]), _dev(b["snr"], torch.float32, "snr"),
-                          _dev(b["best_w"], torch.uint8, "best_w"),
+                          int(b["nout"]), _dev_or_none(b.get("snr"), torch.float32, "snr"),
+                          _dev_or_none(b.get("best_w"), torch.uint8, "best_w"),
                           _dev(b["stats"], torch.int32, "stats"))
         keep.append(b)
     w = np.ascontiguousarray(widths, dtype=np.int32)

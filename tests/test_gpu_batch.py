@@ -177,3 +177,66 @@ def test_batch_autotune_keeps_results(sps):
             sps.sps_batch_launch_graph(batch, stream)
             stream.synchronize()
             _check_beams(sps, plan, batch, beams, widths)
+
+
+# tile lengths for each way the boxcar pass gathers tile maxima: a multiple
+# of the boxcar segment (one reduction per segment), multiples of 64 on rows
+# of 64-multiples (wave merges), and any other (per-thread merges)
+@pytest.mark.parametrize("nouts,tile_t", [([3000, 5000, 1281, 7777, 4096], 1024),
+                                          ([4096, 8192, 640, 12288], 1024),
+                                          ([9000, 4096, 300, 16384], 4096),
+                                          ([20000, 333, 6000], 777)])
+def test_batch_without_planes(sps, nouts, tile_t):
+    """A batch whose beams have no S/N or width planes (each tile key carries
+    its peak's width) writes the same dedispersed planes and statistics and
+    finds the same candidates as the batch with planes (held to the oracle
+    per beam), on an eager run and on graph replays with eager edits in
+    between."""
+    wl = _wl(nouts[0], 0)
+    widths = list(wl.widths)
+    det = dict(DET, tile_t=tile_t)
+    stream = torch.cuda.Stream()
+    print(f"case batch without planes {nouts} tile_t {tile_t}", flush=True)
+    with sps.plan_for(wl) as plan:
+        _, dmax = sps.sps_plan_delays(plan)
+        beams = _beams(sps, plan, nouts, dmax, pad=1)
+        bare = [dict(X=b["X"], nsamp_in=b["nsamp_in"], nout=b["nout"],
+                     Y=torch.zeros_like(b["Y"]), stats=torch.zeros_like(b["stats"]),
+                     snr=None, best_w=None) for b in beams]
+        D = oracle.delays(*_receiver(plan))
+        dargs = (det["threshold"], det["tile_dm"], det["tile_t"], det["nms_dm"], det["nms_t"])
+        with sps.sps_batch_create(plan, beams, widths, **det) as full, \
+                sps.sps_batch_create(plan, bare, widths, **det) as batch:
+            for rep in range(3):
+                with torch.cuda.stream(stream):
+                    if rep:
+                        beams[rep % len(beams)]["X"][:, :64].random_(0, 256)
+                        for b in bare:
+                            b["Y"].zero_()
+                    sps.sps_batch_enqueue(full, stream)
+                    if rep == 0:
+                        sps.sps_batch_enqueue(batch, stream)
+                    else:
+                        sps.sps_batch_launch_graph(batch, stream)
+                stream.synchronize()
+                for i, (b, q) in enumerate(zip(beams, bare)):
+                    label = f"beam {i} rep {rep}"
+                    assert torch.equal(q["Y"], b["Y"]), label
+                    assert torch.equal(q["stats"], b["stats"]), label
+                    cf, nf = sps.sps_batch_candidates(full, i, cap=1 << 16)
+                    cb, nb = sps.sps_batch_candidates(batch, i, cap=1 << 16)
+                    assert nb == nf and np.array_equal(cb, cf), label
+                    if rep == 0 or i == rep % len(beams):
+                        snr_g, best_g, _, _ = _oracle_beam(b, D, widths, label)
+                        check_candidates_exact(cf, nf, oracle.detect(snr_g, best_g, *dargs),
+                                               widths, label)
+
+
+def test_batch_planes_all_or_none(sps):
+    wl = _wl(3000, 0)
+    with sps.plan_for(wl) as plan:
+        _, dmax = sps.sps_plan_delays(plan)
+        beams = _beams(sps, plan, [3000, 2000], dmax, pad=0)
+        beams[1] = dict(beams[1], snr=None, best_w=None)
+        with pytest.raises(sps.SpsError, match="INVALID_ARG"):
+            sps.sps_batch_create(plan, beams, list(wl.widths), **DET)

@@ -6,8 +6,8 @@ sums of the input).  Detection is compared on the GPU's own full S/N plane.
 
 Covered: the full-scale chunk (4096 channels, 2048 DMs, 2^20 samples) on
 brute force and on the subband method, the 19-beam batch (graph replay,
-tiling from the batch autotuner) and a full-size stream of the streaming
-server."""
+tiling from the batch autotuner; with and without S/N planes) and a
+full-size stream of the streaming server."""
 import numpy as np
 import pytest
 
@@ -185,6 +185,22 @@ def test_batched_19_beams_full_size(sps):
             del snr_full, best_full
             cb, nb = sps.sps_batch_candidates(batch, i, cap=1 << 16)
             check_candidates_exact(cb, nb, co, list(wl0.widths), f"beam {i}")
+        # the same batch without planes (the search the benchmark also
+        # times): the same statistics and, in every beam, the same candidates
+        full = [sps.sps_batch_candidates(batch, i, cap=1 << 16) for i in range(len(beams))]
+        stats = [b["stats"].clone() for b in beams]
+        bare = [dict(b, snr=None, best_w=None) for b in beams]
+        with sps.sps_batch_create(plan, bare, list(wl0.widths), **DET) as nb_batch:
+            for b in beams:
+                b["stats"].zero_()
+            for _ in range(2):
+                sps.sps_batch_launch_graph(nb_batch, stream)
+            stream.synchronize()
+            for i, b in enumerate(beams):
+                assert torch.equal(b["stats"], stats[i]), f"beam {i} stats without planes"
+                cb, nb = sps.sps_batch_candidates(nb_batch, i, cap=1 << 16)
+                assert nb == full[i][1] and np.array_equal(cb, full[i][0]), \
+                    f"beam {i} candidates without planes"
     plan.close()
 
 
