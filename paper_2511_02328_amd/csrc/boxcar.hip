@@ -264,15 +264,21 @@ __device__ __forceinline__ void pow2_fetch(const SPS_GLOBAL uint32_t *src, int n
 }
 
 // P[i + 1] = sample i of the window minus the median (wrapping), for i
-// up to the padded scan extent (zero samples past the window); the caller
-// has made sure that every reader of the previous segment's P is done.  The
-// prefix of Y - med makes each numerator B_w - w med one subtraction.
-template <int NPOW>
-__device__ __forceinline__ void pow2_stage(const uint32_t (&v)[Pow2<NPOW>::kLd], int32_t med,
-                                           uint32_t *P) {
-  constexpr int kLd = Pow2<NPOW>::kLd, kCh = Pow2<NPOW>::kCh;
+// up to the padded scan extent, and 0 past the window or the row end (so
+// the prefix stays flat where only widths left out of the maximum, or no
+// output, read it); the caller has made sure that every reader of the
+// previous segment's P is done.  The prefix of Y - med makes each numerator
+// B_w - w med one subtraction.
+template <int NPOW, bool TAIL>
+__device__ __forceinline__ void pow2_stage(const uint32_t (&v)[Pow2<NPOW>::kLd], int n_left,
+                                           int32_t med, uint32_t *P) {
+  constexpr int kLen = Pow2<NPOW>::kLen, kLd = Pow2<NPOW>::kLd, kCh = Pow2<NPOW>::kCh;
 #pragma unroll
-  for (int k = 0; k < kCh; ++k) P[threadIdx.x + kThreads * k + 1] = (k < kLd ? v[k] : 0u) - (uint32_t)med;
+  for (int k = 0; k < kCh; ++k) {
+    const int i = threadIdx.x + kThreads * k;
+    const bool in = k < kLd && (TAIL ? i < n_left : (k + 1 < kLd || i < kLen));
+    P[i + 1] = in ? v[k] - (uint32_t)med : 0u;
+  }
 }
 
 // Width scales 1 / (1.4826 MAD sqrt(w)) into LDS (0 when MAD = 0); read
@@ -284,32 +290,23 @@ __device__ __forceinline__ void set_scales(const WidthList &widths, int32_t mad,
   }
 }
 
-template <int NPOW, bool TAIL, class Sink>
-__device__ __forceinline__ void pow2_filter(int n_left, int32_t med, int32_t mad,
-                                            const float *scale, uint32_t *tmp, uint32_t *P,
-                                            Sink &out) {
-  constexpr int kCh = Pow2<NPOW>::kCh;
+// True in every thread iff pred holds in every thread of the workgroup
+// (one barrier; flags: kThreads / 64 words of LDS).
+__device__ __forceinline__ bool block_all(bool pred, uint32_t *flags) {
+  const bool w = __all(pred);
+  if ((threadIdx.x & 63) == 0) flags[threadIdx.x >> 6] = w ? 1u : 0u;
   __syncthreads();
-
-  // Exclusive prefix over the padded extent: thread chunks of kCh samples
-  // (entries past the window are never read).
-  const int lo = threadIdx.x * kCh;
-  uint32_t c[kCh];
-  uint32_t part = 0;
+  bool r = true;
 #pragma unroll
-  for (int j = 0; j < kCh; ++j) {
-    c[j] = P[lo + j + 1];
-    part += c[j];
-  }
-  uint32_t run = block_exclusive_scan256(part, tmp);
-#pragma unroll
-  for (int j = 0; j < kCh; ++j) {
-    run += c[j];
-    P[lo + j + 1] = run;
-  }
-  if (threadIdx.x == 0) P[0] = 0u;
-  __syncthreads();
+  for (int i = 0; i < kThreads / 64; ++i) r = r && flags[i] != 0u;
+  return r;
+}
 
+// The outputs of one segment from its prefix P (FLT: stored as floats),
+// then out.finish(width_at).
+template <int NPOW, bool TAIL, bool FLT, class Sink>
+__device__ __forceinline__ void pow2_rows(int n_left, int32_t mad, const float *scale,
+                                          const uint32_t *P, Sink &out) {
   // The maximum first (three-input max), then the smallest width that
   // attains it: equal to the strict running comparison, since S/N values are
   // never NaN and never -0 (the numerator is an integer, the scale positive;
@@ -319,16 +316,25 @@ __device__ __forceinline__ void pow2_filter(int n_left, int32_t med, int32_t mad
   float sc[NPOW];
 #pragma unroll
   for (int i = 0; i < NPOW; ++i) sc[i] = scale[i];
-  // S/N of every width at output tl, their maximum, and the smallest width
-  // index that attains it
+  const float *Pf = reinterpret_cast<const float *>(P);
+  // S/N of every width at output tl, and their maximum.  The numerator is
+  // exact either way: with FLT, a float difference of two exact integers,
+  // rounded to nearest as the conversion of the integer difference is.
   auto eval = [&](int tl, float (&s)[NPOW]) {
-    const uint32_t *pt = P + tl;
-    const uint32_t p0 = pt[0];
+    if constexpr (FLT) {
+      const float *pt = Pf + tl;
+      const float p0 = pt[0];
 #pragma unroll
-    for (int i = 0; i < NPOW; ++i) {
-      s[i] = (float)(int32_t)(pt[1 << i] - p0) * sc[i];
-      if (TAIL && tl + (1 << i) > n_left) s[i] = -INFINITY;
+      for (int i = 0; i < NPOW; ++i) s[i] = (pt[1 << i] - p0) * sc[i];
+    } else {
+      const uint32_t *pt = P + tl;
+      const uint32_t p0 = pt[0];
+#pragma unroll
+      for (int i = 0; i < NPOW; ++i) s[i] = (float)(int32_t)(pt[1 << i] - p0) * sc[i];
     }
+#pragma unroll
+    for (int i = 0; i < NPOW; ++i)
+      if (TAIL && tl + (1 << i) > n_left) s[i] = -INFINITY;
     float mx = s[0];
 #pragma unroll
     for (int i = 1; i < NPOW; ++i) mx = fmaxf(mx, s[i]);
@@ -357,6 +363,63 @@ __device__ __forceinline__ void pow2_filter(int n_left, int32_t med, int32_t mad
 }
 
 template <int NPOW, bool TAIL, class Sink>
+__device__ __forceinline__ void pow2_filter(int n_left, int32_t med, int32_t mad,
+                                            const float *scale, uint32_t *tmp, uint32_t *P,
+                                            Sink &out) {
+  constexpr int kCh = Pow2<NPOW>::kCh;
+  __shared__ uint32_t flags[kThreads / 64];
+  __syncthreads();
+
+  // Exclusive prefix over the padded extent: thread chunks of kCh samples
+  // (entries past the window are never read).
+  const int lo = threadIdx.x * kCh;
+  uint32_t c[kCh];
+  uint32_t part = 0;
+#pragma unroll
+  for (int j = 0; j < kCh; ++j) {
+    c[j] = P[lo + j + 1];
+    part += c[j];
+  }
+  uint32_t run = block_exclusive_scan256(part, tmp);
+  // Where every prefix value of the window has magnitude below 2^24 (the
+  // usual case: the samples stay near the median) it is stored as a float,
+  // exactly, and a width's numerator costs one float subtraction instead of
+  // an integer subtraction and a conversion.  Steps |Y - med| < 2^24 keep a
+  // walk that stays inside +-2^24 from wrapping the 32-bit prefix.
+  // Widths up to 256 (chunks of at most 17 values, held twice in
+  // registers); longer windows keep the integers.
+  constexpr bool kFlt = kCh <= 17;
+  float f[kCh];
+  bool fits = kFlt;
+#pragma unroll
+  for (int j = 0; j < kCh; ++j) {
+    run += c[j];
+    c[j] = run;
+    if constexpr (kFlt) {
+      f[j] = (float)(int32_t)run;
+      fits &= fabsf(f[j]) < 0x1p24f;
+    }
+  }
+  const bool flt = kFlt && block_all(fits, flags);
+  if (flt) {
+#pragma unroll
+    for (int j = 0; j < kCh; ++j) P[lo + j + 1] = __float_as_uint(f[j]);
+  } else {
+#pragma unroll
+    for (int j = 0; j < kCh; ++j) P[lo + j + 1] = c[j];
+  }
+  if (threadIdx.x == 0) P[0] = 0u;  // 0 and 0.0f
+  __syncthreads();
+  if constexpr (kFlt) {
+    if (flt) {
+      pow2_rows<NPOW, TAIL, true>(n_left, mad, scale, P, out);
+      return;
+    }
+  }
+  pow2_rows<NPOW, TAIL, false>(n_left, mad, scale, P, out);
+}
+
+template <int NPOW, bool TAIL, class Sink>
 __device__ __forceinline__ void pow2_segment(const SPS_GLOBAL uint32_t *src, int n_left,
                                              int32_t med, int32_t mad, const WidthList &widths,
                                              float *scale, uint32_t *tmp, uint32_t *P,
@@ -364,7 +427,7 @@ __device__ __forceinline__ void pow2_segment(const SPS_GLOBAL uint32_t *src, int
   uint32_t v[Pow2<NPOW>::kLd];
   pow2_fetch<NPOW, TAIL>(src, n_left, v);
   set_scales(widths, mad, scale);
-  pow2_stage<NPOW>(v, med, P);
+  pow2_stage<NPOW, TAIL>(v, n_left, med, P);
   pow2_filter<NPOW, TAIL>(n_left, med, mad, scale, tmp, P, out);
 }
 
@@ -488,16 +551,17 @@ __device__ __forceinline__ void boxcar_sink_segment(const uint32_t *__restrict__
     const int32_t med = gmem(stats)[2 * (int64_t)d];
     const int32_t mad = gmem(stats)[2 * (int64_t)d + 1];
     uint32_t v[Pow2<NPOW>::kLd];
-    if (avail >= (int64_t)kLen)
+    if (avail >= (int64_t)kLen) {
       pow2_fetch<NPOW, false>(src, kLen, v);
-    else
-      pow2_fetch<NPOW, true>(src, (int)avail, v);
-    set_scales(widths, mad, scale);
-    pow2_stage<NPOW>(v, med, P);
-    if (avail >= (int64_t)kLen)
+      set_scales(widths, mad, scale);
+      pow2_stage<NPOW, false>(v, kLen, med, P);
       pow2_filter<NPOW, false>(kLen, med, mad, scale, tmp, P, out);
-    else
+    } else {
+      pow2_fetch<NPOW, true>(src, (int)avail, v);
+      set_scales(widths, mad, scale);
+      pow2_stage<NPOW, true>(v, (int)avail, med, P);
       pow2_filter<NPOW, true>((int)avail, med, mad, scale, tmp, P, out);
+    }
   }
 }
 
