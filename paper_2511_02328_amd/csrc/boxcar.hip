@@ -309,10 +309,19 @@ __device__ __forceinline__ void pow2_rows(int n_left, int32_t mad, const float *
                                           const uint32_t *P, Sink &out) {
   // The maximum first (three-input max), then the smallest width that
   // attains it: equal to the strict running comparison, since S/N values are
-  // never NaN and never -0 (the numerator is an integer, the scale positive;
-  // with MAD = 0 every value is +-0 and width index 0 is chosen, as there).
-  const bool live = mad > 0;
+  // never NaN and never -0 (the numerator is an integer, the scale positive).
   const int seg_len = TAIL ? (n_left < kSeg ? n_left : kSeg) : kSeg;
+  if (mad <= 0) {
+    // MAD 0 (scales 0): every S/N is 0 and width index 0 attains it
+#pragma unroll 4
+    for (int m = 0; m < kPer; ++m) {
+      const int tl = threadIdx.x + kThreads * m;
+      if (TAIL && tl >= seg_len) break;
+      out.put(tl, 0.0f, 0);
+    }
+    out.finish(NoWidth{});
+    return;
+  }
   float sc[NPOW];
 #pragma unroll
   for (int i = 0; i < NPOW; ++i) sc[i] = scale[i];
@@ -352,7 +361,7 @@ __device__ __forceinline__ void pow2_rows(int n_left, int32_t mad, const float *
     if (TAIL && tl >= seg_len) break;
     float s[NPOW];
     const float mx = eval(tl, s);
-    out.put(tl, live ? mx : 0.0f, first_of(s, mx));
+    out.put(tl, mx, first_of(s, mx));
   }
   // the same arithmetic again, for a sink that tracks no width
   out.finish([&](int tl) {

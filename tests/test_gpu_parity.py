@@ -250,6 +250,45 @@ def test_boxcar_pow2_segment_tails(sps, npow, nout):
         check_snr(snr.cpu().numpy(), best.cpu().numpy(), snro, besto, all_width_snr(Y, sto, widths))
 
 
+def test_boxcar_prefix_near_float_limit(sps):
+    """Segments whose window prefix of Y - med peaks just below, at and just
+    above +-2^24, where the kernel switches between a float and an integer
+    prefix (both exact).  Each row holds med + (+1, -1, 0) repeated (median
+    500000, MAD 1, so an S/N computed from a numerator off by one misses the
+    bound by far) and, inside its second segment, a plateau that lifts the
+    window's prefix to T; outputs after the plateau read prefix values T - 1
+    and T, whose odd members a float could not hold past 2^24."""
+    nchan, nout, med = 4096, 3 * 4096 + 100, 500000
+    widths = [2 ** i for i in range(9)]
+    targets = [2 ** 24 - 2, 2 ** 24 - 1, 2 ** 24, 2 ** 24 + 1, 2 ** 24 + 2001, -(2 ** 24 - 2),
+               -(2 ** 24 + 1), 2 ** 28]
+    Y = np.empty((len(targets), nout), dtype=np.int64)
+    base = med + np.tile(np.array([1, -1, 0]), nout // 3 + 1)[:nout]
+    t0 = 4096 + 999  # prefix 0 there (a multiple of 3 past the segment start)
+    for r, T in enumerate(targets):
+        Y[r] = base
+        D = 400000 if T > 0 else -400000
+        L, R = divmod(abs(T), 400000)
+        Y[r, t0:t0 + L] = med + D
+        Y[r, t0 + L] = med + (R if T > 0 else -R)
+        Y[r, t0 + L + 1:t0 + L + 4] = med  # then the pattern again, prefix T - 1 or T
+    assert Y.min() >= 0 and Y.max() <= 255 * nchan
+    Y = Y.astype(np.uint32)
+    sto = oracle.stats(Y)
+    assert np.all(sto[:, 0] == med) and np.all(sto[:, 1] == 1)
+    snro, besto = oracle.boxcar(Y, sto, widths)
+    wl = Workload("s", nchan, 1000.0, 1500.0, 1e-4, nout, len(targets), 0.0, 1.0, tuple(widths))
+    with sps.plan_for(wl) as plan:
+        Yd = torch.from_numpy(Y.view(np.int32)).cuda()
+        snr = torch.empty(Y.shape, dtype=torch.float32, device="cuda")
+        best = torch.empty(Y.shape, dtype=torch.uint8, device="cuda")
+        st = torch.empty((len(targets), 2), dtype=torch.int32, device="cuda")
+        sps.sps_boxcar_snr(plan, Yd, nout, widths, snr, best, st)
+        torch.cuda.synchronize()
+        assert np.array_equal(st.cpu().numpy().astype(np.int64), sto)
+        check_snr(snr.cpu().numpy(), best.cpu().numpy(), snro, besto, all_width_snr(Y, sto, widths))
+
+
 @pytest.mark.parametrize("seed", range(6))
 def test_detect_same_plane(sps, seed):
     rng = np.random.Generator(np.random.PCG64(seed))
