@@ -34,14 +34,24 @@ constexpr int kThreads = 256;
 constexpr int kSeg = 4096;
 constexpr int kPer = kSeg / kThreads;
 
+// Inclusive sum over the lanes of a wave up to this one, with DPP moves
+// (registers only): Hillis-Steele steps of 1, 2, 4, 8 lanes inside each row
+// of 16, then the row totals broadcast from lane 15 into rows 1 and 3 and
+// from lane 31 into rows 2 and 3.  Lanes whose source lies outside the row,
+// and rows left out by the row mask, add 0.
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t x) {
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);  // row_shr:1
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);  // row_shr:2
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);  // row_shr:4
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);  // row_shr:8
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return x;
+}
+
 __device__ uint32_t block_exclusive_scan256(uint32_t v, uint32_t *tmp /* >= 4 */) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  uint32_t inc = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t y = __shfl_up(inc, o, 64);
-    if (lane >= o) inc += y;
-  }
+  const uint32_t inc = wave_inclusive_scan(v);
   if (lane == 63) tmp[wave] = inc;
   __syncthreads();
   uint32_t off = 0;
@@ -125,11 +135,10 @@ struct TileTrack {
       }
     }
     if constexpr (TILES != 0) {
-      if (v > s) {
-        s = v;
-        tl = t_local;
-        if constexpr (PK == 1) bi = b;
-      }
+      const bool gt = v > s;  // the first output of a run of equal maxima stays
+      tl = gt ? t_local : tl;
+      if constexpr (PK == 1) bi = gt ? b : bi;
+      s = fmaxf(s, v);
     }
   }
   // Every thread of the workgroup calls this once, after its last add;
@@ -399,17 +408,17 @@ __device__ __forceinline__ void pow2_filter(int n_left, int32_t med, int32_t mad
   // registers); longer windows keep the integers.
   constexpr bool kFlt = kCh <= 17;
   float f[kCh];
-  bool fits = kFlt;
+  float amax = 0.0f;
 #pragma unroll
   for (int j = 0; j < kCh; ++j) {
     run += c[j];
     c[j] = run;
     if constexpr (kFlt) {
       f[j] = (float)(int32_t)run;
-      fits &= fabsf(f[j]) < 0x1p24f;
+      amax = fmaxf(amax, fabsf(f[j]));
     }
   }
-  const bool flt = kFlt && block_all(fits, flags);
+  const bool flt = kFlt && block_all(amax < 0x1p24f, flags);
   if (flt) {
 #pragma unroll
     for (int j = 0; j < kCh; ++j) P[lo + j + 1] = __float_as_uint(f[j]);
