@@ -49,6 +49,27 @@ __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t x) {
   return x;
 }
 
+// One DPP step of a running maximum: lanes whose source lies outside the
+// row, and rows left out by the row mask, take their own value.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_max_step(float x) {
+  const int y = __builtin_amdgcn_update_dpp(__float_as_int(x), __float_as_int(x), CTRL, ROWS, 0xf,
+                                            false);
+  return fmaxf(x, __int_as_float(y));
+}
+
+// Maximum over the wave (the same steps as wave_inclusive_scan; lane 63
+// ends with the whole wave's maximum), in every lane.
+__device__ __forceinline__ float wave_max(float x) {
+  x = dpp_max_step<0x111, 0xf>(x);
+  x = dpp_max_step<0x112, 0xf>(x);
+  x = dpp_max_step<0x114, 0xf>(x);
+  x = dpp_max_step<0x118, 0xf>(x);
+  x = dpp_max_step<0x142, 0xa>(x);
+  x = dpp_max_step<0x143, 0xc>(x);
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+}
+
 __device__ uint32_t block_exclusive_scan256(uint32_t v, uint32_t *tmp /* >= 4 */) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t inc = wave_inclusive_scan(v);
@@ -149,9 +170,7 @@ struct TileTrack {
                                          unsigned long long *red, const SPS_GLOBAL float *srow,
                                          int len, W &&width_at) {
     if constexpr (TILES == 1) {
-      float m = s;
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+      float m = wave_max(s);
       float *redf = reinterpret_cast<float *>(red);
       if ((threadIdx.x & 63) == 0) redf[threadIdx.x >> 6] = m;
       __syncthreads();
