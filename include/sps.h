@@ -395,7 +395,10 @@ sps_status sps_probe_peaks(int32_t device, double *rates, int32_t n);
  * before chunk 0).  Worker w owns a HIP stream, a staging buffer for one
  * chunk, one plan per observing set-up and output planes sized for the
  * largest stream; streams of one set-up share its plans.  One chunk's
- * kernels run at a time; uploads of other chunks overlap them. */
+ * kernels run at a time; uploads of other chunks overlap them.  A chunk is
+ * searched as sps_search does it; without an attached detector (which reads
+ * the S/N plane) no S/N or width plane is written, where the stream's tiles
+ * fit the packed tile keys. */
 typedef struct sps_server_s *sps_server;
 
 /* hbm_budget: device bytes the server may hold (rings, plans, planes);

@@ -289,27 +289,29 @@ sps_status process_chunk(sps_server s, Worker &w, int sid, const uint8_t *src, i
                        hipMemcpyDeviceToDevice, hs);
     if (e != hipSuccess) return dev_fail(e, "plane copy");
   }
-  r = sps_boxcar_snr(plan, w.Y, st.chunk, st.widths.data(), (int32_t)st.widths.size(), w.snr,
-                     w.best, w.stats, hs);
-  if (r != SPS_OK) return r;
-  const bool learned = s->detector != nullptr;
-  if (learned) {
-    r = run_detector(s, w, st);
-    if (r != SPS_OK) return r;
-  }
   // The last D_max samples move to the front of the ring, in pieces no
   // longer than the chunk, so that no piece's source overlaps its
   // destination; in stream order every piece reads its source before a
-  // later piece overwrites it.
+  // later piece overwrites it.  The search below reads only the plane.
   for (int64_t off = 0; off < st.overlap; off += st.chunk) {
     const int64_t len = std::min(st.chunk, st.overlap - off);
     e = copy_rows(st.ring, st.pitch, st.chunk + off, st.ring, st.pitch, off, len, st.nchan, hs);
     if (e != hipSuccess) return dev_fail(e, "overlap move");
   }
-  r = sps_detect(plan, w.snr, w.best, st.chunk, st.widths.data(), (int32_t)st.widths.size(),
-                 &st.det, out, cap, n_found, hs);
+  // Statistics, boxcar and detection in one call, the tile maxima gathered
+  // by the boxcar pass.  Without the learned detector (which reads the S/N
+  // plane) no plane is written, where the tiles fit the packed keys.
+  const bool learned = s->detector != nullptr;
+  const int64_t tdm = std::min<int64_t>(st.det.tile_dm, st.ndm);
+  const int64_t tt = std::min<int64_t>(st.det.tile_t, st.chunk);
+  const bool planes = learned || tdm * tt > sps::kKeyPosLimit;
+  r = sps_search(plan, w.Y, st.chunk, st.widths.data(), (int32_t)st.widths.size(),
+                 planes ? w.snr : nullptr, planes ? w.best : nullptr, w.stats, &st.det, out, cap,
+                 n_found, hs);
   if (learned && (r == SPS_OK || r == SPS_ERR_TRUNCATED)) {
-    e = hipStreamSynchronize(hs);  // normally idle already: detection waits for its outputs
+    const sps_status rd = run_detector(s, w, st);
+    if (rd != SPS_OK) return rd;
+    e = hipStreamSynchronize(hs);
     if (e != hipSuccess) return dev_fail(e, "detector count");
     *n_cnn = *w.h_cnn;
   }

@@ -157,4 +157,21 @@ def test_batch_tile_mode(sps):
             sps.sps_batch_set_tiles(b, None)
             sps.sps_batch_launch_graph(b, stream)
             stream.synchronize()
-            sps.sps_batch_candidates(b, 0)
+            full = [sps.sps_batch_candidates(b, i) for i in range(len(beams))]
+        # a batch without planes: the same tiles in tile mode, the same
+        # candidates when switched back
+        bare = [dict(bm, snr=None, best_w=None) for bm in beams]
+        with sps.sps_batch_create(plan, bare, list(wl.widths), 8.0, 64, 4096, 16, 64) as b:
+            stream = torch.cuda.Stream()
+            assert sps.sps_batch_set_tiles(b, tiles, SCALE) == 4
+            tiles.zero_()
+            stream.wait_stream(torch.cuda.current_stream())
+            sps.sps_batch_launch_graph(b, stream)
+            stream.synchronize()
+            assert torch.equal(tiles, want), "tiles without planes"
+            sps.sps_batch_set_tiles(b, None)
+            sps.sps_batch_launch_graph(b, stream)
+            stream.synchronize()
+            for i in range(len(beams)):
+                c, n = sps.sps_batch_candidates(b, i)
+                assert n == full[i][1] and np.array_equal(c, full[i][0]), f"beam {i}"
