@@ -82,7 +82,9 @@ CASES = [
     (5, 1, (1,), 3, 7, 1, 1, 0.5),                                              # one output per row
     (21, 4736, (1, 2, 4, 8, 16, 32, 64), 3, 512, 2, 100, 2.0),                  # tiles of 64-multiples,
     (12, 8192, (1, 3, 5, 7, 12, 100), 4, 192, 1, 30, 2.0),                      # wave-level merges
-]
+    (20, 3 * 4096 + 100, (1, 3, 5, 7, 12, 100), 5, 4096, 2, 100, 2.0),         # generic widths,
+    (8, 4096 + 2, (3, 5, 7), 3, 4096, 1, 10, 1.0),                              # whole segments; the
+]                                                                               # last outputs fit no width
 
 
 def _case_input(case):
