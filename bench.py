@@ -697,6 +697,21 @@ def bench_detector(args):
     e1.record(stream)
     e1.synchronize()
     search_ms = e0.elapsed_time(e1) / reps / fac.batch
+    # the plain search writing no S/N or width planes (candidates only), on
+    # the same beams
+    bare = sps.sps_batch_create(
+        fac.plan, [dict(X=fac.X[i], nsamp_in=fac.nsamp, nout=fac.wl.nout, Y=fac.Y[i],
+                        stats=fac.stats[i], snr=None, best_w=None) for i in range(fac.batch)],
+        list(fac.wl.widths), **detector.SEARCH)
+    for _ in range(2):
+        sps.sps_batch_launch_graph(bare, stream)
+    e0.record(stream)
+    for _ in range(reps):
+        sps.sps_batch_launch_graph(bare, stream)
+    e1.record(stream)
+    e1.synchronize()
+    bare_ms = e0.elapsed_time(e1) / reps / fac.batch
+    bare.close()
     # the detector path on the same batch: dedispersion, statistics and the
     # boxcar pass writing the network's tiles directly (no S/N or width
     # planes, no threshold search), then the network on those tiles
@@ -758,6 +773,9 @@ def bench_detector(args):
             "detector_path": {"ms_per_tile": det_path_ms, "tiles_per_s": 1e3 / det_path_ms,
                               "dm_time_samples_per_s": dm_t_per_tile * 1e3 / det_path_ms},
             "detector_path_over_plain": search_ms / det_path_ms,
+            "plain_search_without_planes": {"ms_per_tile": bare_ms, "tiles_per_s": 1e3 / bare_ms,
+                                            "dm_time_samples_per_s": dm_t_per_tile * 1e3 / bare_ms},
+            "detector_path_over_plain_without_planes": bare_ms / det_path_ms,
             "tiles_identical_to_pooled_planes": tiles_identical},
         "operating_point": operating,
         "vs_boxcar_by_rfi": {str(th): {g: {k: (round(v, 4) if isinstance(v, float) else v)
