@@ -389,11 +389,8 @@ def bench_batched(args, bw):
 
     def step():
         sps.sps_batch_launch_graph(batch, stream)
-        n = 0
-        for i in range(bw.nbeams):
-            _, k = sps.sps_batch_candidates(batch, i, cap=4096, stream=stream, allow_truncated=True)
-            n += k
-        return n
+        return sum(k for _, k in sps.sps_batch_candidates_all(batch, cap=4096, stream=stream,
+                                                              allow_truncated=True))
 
     for _ in range(args.warmup):
         step()
@@ -430,8 +427,8 @@ def bench_batched(args, bw):
 
     def step_bare():
         sps.sps_batch_launch_graph(bare, stream)
-        return sum(sps.sps_batch_candidates(bare, i, cap=4096, stream=stream,
-                                            allow_truncated=True)[1] for i in range(bw.nbeams))
+        return sum(k for _, k in sps.sps_batch_candidates_all(bare, cap=4096, stream=stream,
+                                                              allow_truncated=True))
 
     for _ in range(args.warmup):
         step_bare()
@@ -459,7 +456,8 @@ def bench_batched(args, bw):
                    "beam_lengths": lengths, "tsamp_us": wl0.tsamp_s * 1e6,
                    "widths": list(wl0.widths), "tiling": tiling, "autotune_ms": ms,
                    "launch": "one HIP graph per step: batched dedispersion (one workgroup per item) + "
-                             "batched stats, boxcar, detection", "detect": det},
+                             "batched stats, boxcar, detection; every beam's candidates read back "
+                             "in one call (sps_batch_candidates_all)", "detect": det},
         "chunk_latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
                              "p99": float(np.percentile(lat, 99) * 1e3),
                              "shortest_chunk_duration_ms": min(durations) * 1e3},

@@ -347,6 +347,17 @@ sps_status sps_batch_set_tiles(sps_batch batch, uint16_t *tiles, float scale, in
 sps_status sps_batch_candidates(sps_batch batch, int32_t beam, sps_candidate *out, int32_t cap,
                                 int32_t *n_found, void *stream);
 
+/* Every beam's candidates in one call (Sec. 2, candidate record): out is
+ * host [nbeams][cap], beam b's first min(n_b, cap) candidates at out + b cap
+ * in sps_detect's order; n_found is host [nbeams] and receives every n_b.
+ * One gather launch and one copy into pinned memory the batch allocated at
+ * creation bring back up to 512 records per beam, then one synchronisation
+ * of the stream; a beam with more than 512 candidates to return takes its
+ * own further copies.  Allocates nothing.  TRUNCATED (after filling) if any
+ * n_b > cap; INVALID_ARG in tile mode. */
+sps_status sps_batch_candidates_all(sps_batch batch, sps_candidate *out, int32_t cap,
+                                    int32_t *n_found, void *stream);
+
 /* Autotuner: times every compiled dedispersion tiling that fits the plan on
  * a probe of nout_probe output samples (iters timed runs each, HIP events,
  * after one warm-up) and keeps the fastest.  ms_out (optional) receives the

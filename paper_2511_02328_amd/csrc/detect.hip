@@ -389,7 +389,37 @@ __global__ __launch_bounds__(kNmsThreads) void select_nms_batch_kernel(
              threshold, nms_dm, nt);
 }
 
+// Candidate read-back of a whole batch: workgroup b copies beam b's status
+// words and its first min(k, ntiles) accepted-offer records into slot b of
+// staging (kGatherHeader bytes of status, then k records).  Records past the
+// accepted count are copied as they are and ignored by the reader.
+__global__ __launch_bounds__(256) void gather_candidates_kernel(
+    const BeamWork *__restrict__ beams, int ndm, int tile_dm, const uint8_t *__restrict__ scratch,
+    int k, uint8_t *__restrict__ staging) {
+  const BeamWork &bw = beams[blockIdx.x];
+  const int64_t ntiles = (int64_t)((ndm + tile_dm - 1) / tile_dm) * bw.ntt;
+  const DetectLayout L = detect_layout(ntiles);
+  const uint8_t *src = scratch + bw.det_begin;
+  uint8_t *dst = staging + (int64_t)blockIdx.x * (kGatherHeader + 16 * (int64_t)k);
+  if (threadIdx.x < 4)
+    reinterpret_cast<int32_t *>(dst)[threadIdx.x] =
+        reinterpret_cast<const int32_t *>(src + L.status)[threadIdx.x];
+  const int64_t n = ntiles < k ? ntiles : k;
+  const uint4 *rec = reinterpret_cast<const uint4 *>(src + L.out);
+  uint4 *out = reinterpret_cast<uint4 *>(dst + kGatherHeader);
+  for (int64_t i = threadIdx.x; i < n; i += 256) out[i] = rec[i];
+}
+
 }  // namespace
+
+hipError_t launch_gather_candidates(const BeamWork *beams, int nbeams, int ndm, int tile_dm,
+                                    const uint8_t *scratch, int k, uint8_t *staging,
+                                    hipStream_t stream) {
+  if (nbeams < 1 || k < 0 || tile_dm < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(gather_candidates_kernel, dim3(nbeams), dim3(256), 0, stream, beams, ndm,
+                     tile_dm, scratch, k, staging);
+  return hipGetLastError();
+}
 
 hipError_t launch_tile_peaks(const float *snr, const uint8_t *best, int ndm, int64_t nout,
                              int tile_dm, int64_t tile_t, TilePeak *peaks,

@@ -183,6 +183,21 @@ sps_status restage(sps_plan p) {
 
 bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
+// A tile peak record as a candidate (Sec. 2): DM, TOA at the top of the band
+// (the window's centre), width and S/N.
+sps_candidate to_candidate(const sps::TilePeak &q, const int32_t *widths, int nw,
+                           const double *dm, int ndm, double tsamp_s) {
+  sps_candidate c;
+  c.dm_idx = q.d;
+  c.t_idx = q.t;
+  c.width = (q.w >= 0 && q.w < nw) ? widths[q.w] : 0;
+  c.snr = q.snr;
+  c.reserved = 0.0f;
+  c.dm = (q.d >= 0 && q.d < ndm) ? dm[q.d] : 0.0;
+  c.toa_s = ((double)q.t + 0.5 * (double)c.width) * tsamp_s;
+  return c;
+}
+
 // Reads the result of the selection kernel from a plane's detection scratch
 // (d_scratch, laid out by sps::detect_layout(ntiles)) and converts the first
 // min(n, cap) accepted offers into candidate records (Sec. 2: DM, TOA at the
@@ -211,18 +226,8 @@ sps_status read_candidates(const uint8_t *d_scratch, int64_t ntiles, const int32
     e = hipMemcpyAsync(buf, src + i0, sizeof(sps::TilePeak) * (size_t)m, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "reading candidates");
-    for (int32_t k = 0; k < m; ++k) {
-      const sps::TilePeak &q = buf[k];
-      sps_candidate c;
-      c.dm_idx = q.d;
-      c.t_idx = q.t;
-      c.width = (q.w >= 0 && q.w < nw) ? widths[q.w] : 0;
-      c.snr = q.snr;
-      c.reserved = 0.0f;
-      c.dm = (q.d >= 0 && q.d < ndm) ? dm[q.d] : 0.0;
-      c.toa_s = ((double)q.t + 0.5 * (double)c.width) * tsamp_s;
-      out[i0 + k] = c;
-    }
+    for (int32_t k = 0; k < m; ++k)
+      out[i0 + k] = to_candidate(buf[k], widths, nw, dm, ndm, tsamp_s);
   }
   *n_found = na;
   if (na > cap) return fail(SPS_ERR_TRUNCATED, "%d candidates found, %d returned", na, cap);
@@ -948,6 +953,11 @@ sps_status sps_downsample_sqrt(const uint8_t *X, int64_t pitch, int64_t nsamp, i
 
 }  // extern "C"
 
+// Accepted offers per beam that sps_batch_candidates_all brings back in its
+// one copy; a beam with more reads the rest through its own copies.
+constexpr int kGatherRecords = 512;
+constexpr size_t kGatherSlot = sps::kGatherHeader + sizeof(sps::TilePeak) * kGatherRecords;
+
 struct sps_batch_s {
   sps_plan plan = nullptr;
   int nbeams = 0;
@@ -963,6 +973,8 @@ struct sps_batch_s {
   sps::StagedDelays staged;  // the plan's table for cfg, owned by the batch
   int grid_dd = 0;
   uint8_t *d_det = nullptr;  // detection scratch of every beam (BeamWork::det_begin)
+  uint8_t *d_gather = nullptr;  // sps_batch_candidates_all: device slots of every beam
+  uint8_t *h_gather = nullptr;  // and their pinned host copy
   int64_t det_bytes = 0;
   int64_t pl_blocks = 0, pool_tiles = 0;  // pooled-tile boxcar workgroups, detector tiles
   uint16_t *tiles = nullptr;              // tile mode (sps_batch_set_tiles): destination
@@ -981,6 +993,8 @@ void free_batch(sps_batch b) {
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->d_beams) (void)hipFree(b->d_beams);
   if (b->d_det) (void)hipFree(b->d_det);
+  if (b->d_gather) (void)hipFree(b->d_gather);
+  if (b->h_gather) (void)hipHostFree(b->h_gather);
   sps::free_staged(b->staged);
   delete b;
 }
@@ -1142,6 +1156,9 @@ sps_status sps_batch_create(sps_plan plan, int32_t nbeams, const sps_beam *beams
   if (e == hipSuccess) e = hipMalloc(&b->d_det, (size_t)b->det_bytes);
   // zero statuses: candidates read before the first run are none
   if (e == hipSuccess) e = hipMemset(b->d_det, 0, (size_t)b->det_bytes);
+  const size_t gather_bytes = (size_t)nbeams * kGatherSlot;
+  if (e == hipSuccess) e = hipMalloc(&b->d_gather, gather_bytes);
+  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&b->h_gather), gather_bytes);
   if (e == hipSuccess)
     e = hipMemcpy(b->d_beams, b->beams.data(), sizeof(sps::BeamWork) * (size_t)nbeams,
                   hipMemcpyHostToDevice);
@@ -1319,6 +1336,63 @@ sps_status sps_batch_candidates(sps_batch batch, int32_t beam, sps_candidate *ou
                          batch->plan->ndm, batch->plan->tsamp_s, out, cap, n_found,
                          (hipStream_t)stream);
 }
+
+sps_status sps_batch_candidates_all(sps_batch batch, sps_candidate *out, int32_t cap,
+                                    int32_t *n_found, void *stream) {
+  g_error.clear();
+  if (!batch || !n_found) return fail(SPS_ERR_INVALID_ARG, "NULL argument");
+  if (batch->tiles)
+    return fail(SPS_ERR_INVALID_ARG, "the batch is in tile mode: it searches for no candidates");
+  if (cap < 0 || (cap > 0 && !out)) return fail(SPS_ERR_INVALID_ARG, "bad output array");
+  DeviceScope scope(batch->plan->device);
+  if (scope.err != hipSuccess) return hip_fail(scope.err, "selecting the plan's device");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = sps::launch_gather_candidates(batch->d_beams, batch->nbeams, batch->plan->ndm,
+                                               batch->prm.tile_dm, batch->d_det, kGatherRecords,
+                                               batch->d_gather, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(batch->h_gather, batch->d_gather, (size_t)batch->nbeams * kGatherSlot,
+                       hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "reading the batch's candidates");
+  const int32_t *widths = batch->widths_host.data();
+  const int nw = (int)batch->widths_host.size();
+  const int64_t ntd = (batch->plan->ndm + batch->prm.tile_dm - 1) / batch->prm.tile_dm;
+  bool truncated = false;
+  for (int bi = 0; bi < batch->nbeams; ++bi) {
+    const sps::BeamWork &w = batch->beams[(size_t)bi];
+    const int64_t ntiles = ntd * w.ntt;
+    const uint8_t *slot = batch->h_gather + (size_t)bi * kGatherSlot;
+    int32_t status[4];
+    memcpy(status, slot, sizeof status);
+    const int32_t na = status[1];
+    if (na < 0 || (int64_t)na > ntiles || status[0] < na) {
+      n_found[bi] = 0;
+      return fail(SPS_ERR_DEVICE, "beam %d: detection status is inconsistent", bi);
+    }
+    const int32_t ncopy = na < cap ? na : cap;
+    const int64_t held = ntiles < kGatherRecords ? ntiles : kGatherRecords;
+    sps_candidate *dst = out ? out + (int64_t)bi * cap : nullptr;
+    if (ncopy <= held) {
+      const sps::TilePeak *rec = reinterpret_cast<const sps::TilePeak *>(slot + sps::kGatherHeader);
+      for (int32_t k = 0; k < ncopy; ++k)
+        dst[k] = to_candidate(rec[k], widths, nw, batch->plan->dm.data(), batch->plan->ndm,
+                              batch->plan->tsamp_s);
+      n_found[bi] = na;
+    } else {
+      // more accepted offers than the slot holds: this beam's own copies
+      const sps_status st =
+          read_candidates(batch->d_det + w.det_begin, ntiles, widths, nw, batch->plan->dm.data(),
+                          batch->plan->ndm, batch->plan->tsamp_s, dst, cap, &n_found[bi], s);
+      if (st != SPS_OK && st != SPS_ERR_TRUNCATED) return st;
+      g_error.clear();
+    }
+    truncated = truncated || na > cap;
+  }
+  if (truncated) return fail(SPS_ERR_TRUNCATED, "a beam found more than %d candidates", cap);
+  return SPS_OK;
+}
+
 
 sps_status sps_plan_autotune(sps_plan plan, int64_t nout_probe, int32_t iters, void *stream,
                              float *ms_out, int32_t *n_tried) {

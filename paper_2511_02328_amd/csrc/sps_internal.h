@@ -212,6 +212,7 @@ struct TilePeak {
   int32_t t;
   int32_t w;
 };
+static_assert(sizeof(TilePeak) == 16, "tile peak records are copied as 16-byte units");
 
 // Offers that the selection kernel keeps in LDS; larger offer sets (and tile
 // grids larger than this) use the global arrays of the detection scratch.
@@ -326,6 +327,13 @@ hipError_t launch_tile_keys_batch(const BeamWork *beams, int nbeams, int ndm, in
 hipError_t launch_select_nms_batch(const BeamWork *beams, int nbeams, int ndm, int tile_dm,
                                    int64_t tile_t, float threshold, int nms_dm, int64_t nms_t,
                                    uint8_t *scratch, hipStream_t stream);
+// Every beam's detection status and first k accepted offers in one launch:
+// slot b of staging holds beam b's 4 status words (kGatherHeader bytes) and
+// then k TilePeak records (nbeams * (kGatherHeader + 16 k) bytes).
+constexpr int kGatherHeader = 16;
+hipError_t launch_gather_candidates(const BeamWork *beams, int nbeams, int ndm, int tile_dm,
+                                    const uint8_t *scratch, int k, uint8_t *staging,
+                                    hipStream_t stream);
 
 // Forward pass of n tiles (device) through net; adds to *count (device int32)
 // the number of cells whose objectness probability is >= threshold, decided

@@ -123,6 +123,8 @@ def library() -> ctypes.CDLL:
         lib.sps_batch_launch_graph.argtypes = [P, P]
         lib.sps_batch_candidates.argtypes = [P, i32, ctypes.POINTER(sps_candidate), i32,
                                              ctypes.POINTER(i32), P]
+        lib.sps_batch_candidates_all.argtypes = [P, ctypes.POINTER(sps_candidate), i32,
+                                                 ctypes.POINTER(i32), P]
         lib.sps_plan_autotune.argtypes = [P, i64, i32, P, P, ctypes.POINTER(i32)]
         lib.sps_batch_autotune.argtypes = [P, i32, P, P, ctypes.POINTER(i32)]
         lib.sps_tiling_count.argtypes = []
@@ -185,7 +187,7 @@ def library() -> ctypes.CDLL:
                   "sps_subband_plan_create", "sps_subband_tables", "sps_dedisperse_subband",
                   "sps_zero_dm", "sps_downsample_sqrt", "sps_batch_create", "sps_batch_destroy",
                   "sps_batch_enqueue", "sps_batch_launch_graph", "sps_batch_candidates",
-                  "sps_plan_autotune", "sps_batch_autotune", "sps_tiling_describe",
+                  "sps_batch_candidates_all", "sps_plan_autotune", "sps_batch_autotune", "sps_tiling_describe",
                   "sps_probe_peaks"):
             getattr(lib, f).restype = ctypes.c_int
         lib.sps_last_error.argtypes = []
@@ -455,6 +457,7 @@ class Batch:
 
     def __init__(self, handle, plan, keep, widths):
         self.handle, self.plan, self._keep, self.widths = handle, plan, keep, widths
+        self.nbeams = len(keep)
 
     def close(self) -> None:
         if self.handle:
@@ -534,6 +537,19 @@ def sps_batch_candidates(batch: Batch, beam: int, cap: int = 4096, stream=None,
     k = min(int(n.value), cap)
     arr = np.frombuffer(bytes(out)[:k * ctypes.sizeof(sps_candidate)], dtype=CANDIDATE_DTYPE).copy()
     return arr, int(n.value)
+
+
+def sps_batch_candidates_all(batch: Batch, cap: int = 4096, stream=None,
+                             allow_truncated: bool = False):
+    """Every beam's candidates in one call: a list of (candidates, number found) per beam."""
+    nb = batch.nbeams
+    out = (sps_candidate * max(nb * cap, 1))()
+    n = (ctypes.c_int32 * nb)()
+    rc = library().sps_batch_candidates_all(batch.handle, out, int(cap), n, _stream(stream))
+    if not (rc == 6 and allow_truncated):
+        _check(rc, "sps_batch_candidates_all")
+    view = np.frombuffer(out, dtype=CANDIDATE_DTYPE)  # no copy of the whole array
+    return [(view[b * cap:b * cap + min(int(n[b]), cap)].copy(), int(n[b])) for b in range(nb)]
 
 
 def sps_tiling_count() -> int:

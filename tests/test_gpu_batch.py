@@ -240,3 +240,31 @@ def test_batch_planes_all_or_none(sps):
         beams[1] = dict(beams[1], snr=None, best_w=None)
         with pytest.raises(sps.SpsError, match="INVALID_ARG"):
             sps.sps_batch_create(plan, beams, list(wl.widths), **DET)
+
+
+def test_batch_candidates_all(sps):
+    """Every beam's candidates in one call equal the per-beam calls: before
+    the first run (none), with room for every record, with a cap that
+    truncates, and with beams holding more records than one gathered slot
+    (512), which take their own copies."""
+    nouts = [20000, 3000, 8192, 16]
+    wl = _wl(nouts[0], 0)
+    widths = list(wl.widths)
+    many = dict(threshold=1.0, tile_dm=4, tile_t=64, nms_dm=1, nms_t=4)
+    with sps.plan_for(wl) as plan:
+        _, dmax = sps.sps_plan_delays(plan)
+        beams = _beams(sps, plan, nouts, dmax, pad=0)
+        for det in (DET, many):
+            print(f"case candidates_all {det}", flush=True)
+            with sps.sps_batch_create(plan, beams, widths, **det) as batch:
+                assert all(n == 0 for _, n in sps.sps_batch_candidates_all(batch, cap=16))
+                sps.sps_batch_enqueue(batch)
+                torch.cuda.synchronize()
+                for cap in (1 << 16, 3):
+                    got = sps.sps_batch_candidates_all(batch, cap=cap, allow_truncated=True)
+                    for i in range(len(beams)):
+                        c, n = sps.sps_batch_candidates(batch, i, cap=cap, allow_truncated=True)
+                        assert got[i][1] == n and np.array_equal(got[i][0], c), (det, cap, i)
+                if det is many:
+                    counts = [n for _, n in sps.sps_batch_candidates_all(batch, cap=1 << 16)]
+                    assert max(counts) > 512, counts
