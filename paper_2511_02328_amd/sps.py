@@ -339,7 +339,7 @@ def sps_search(plan: Plan, Y: torch.Tensor, nout: int, widths: Sequence[int],
     if not (rc == 6 and allow_truncated):
         _check(rc, "sps_search")
     k = min(int(n.value), cap)
-    arr = np.frombuffer(bytes(out)[:k * ctypes.sizeof(sps_candidate)], dtype=CANDIDATE_DTYPE).copy()
+    arr = np.frombuffer(out, dtype=CANDIDATE_DTYPE)[:k].copy()
     return arr, int(n.value)
 
 
@@ -392,7 +392,7 @@ def _detect(name, plan, snr, best_w, nout, widths, threshold, tile_dm, tile_t, n
     if not (rc == 6 and allow_truncated):
         _check(rc, name)
     k = min(int(n.value), cap)
-    arr = np.frombuffer(bytes(out)[:k * ctypes.sizeof(sps_candidate)], dtype=CANDIDATE_DTYPE).copy()
+    arr = np.frombuffer(out, dtype=CANDIDATE_DTYPE)[:k].copy()
     return arr, int(n.value)
 
 
@@ -535,7 +535,7 @@ def sps_batch_candidates(batch: Batch, beam: int, cap: int = 4096, stream=None,
     if not (rc == 6 and allow_truncated):
         _check(rc, "sps_batch_candidates")
     k = min(int(n.value), cap)
-    arr = np.frombuffer(bytes(out)[:k * ctypes.sizeof(sps_candidate)], dtype=CANDIDATE_DTYPE).copy()
+    arr = np.frombuffer(out, dtype=CANDIDATE_DTYPE)[:k].copy()
     return arr, int(n.value)
 
 
@@ -699,7 +699,7 @@ def sps_server_push(server: Server, stream_id: int, chunk, Y_copy: Optional[torc
     if not (rc == 6 and allow_truncated):
         _check(rc, "sps_server_push")
     k = min(int(n.value), cap)
-    arr = np.frombuffer(bytes(out)[:k * ctypes.sizeof(sps_candidate)], dtype=CANDIDATE_DTYPE).copy()
+    arr = np.frombuffer(out, dtype=CANDIDATE_DTYPE)[:k].copy()
     if with_cnn:
         return arr, int(n.value), int(ncnn.value)
     return arr, int(n.value)
