@@ -458,6 +458,7 @@ class Batch:
     def __init__(self, handle, plan, keep, widths):
         self.handle, self.plan, self._keep, self.widths = handle, plan, keep, widths
         self.nbeams = len(keep)
+        self._all_out = None  # sps_batch_candidates_all's record array, reused per cap
 
     def close(self) -> None:
         if self.handle:
@@ -543,7 +544,9 @@ def sps_batch_candidates_all(batch: Batch, cap: int = 4096, stream=None,
                              allow_truncated: bool = False):
     """Every beam's candidates in one call: a list of (candidates, number found) per beam."""
     nb = batch.nbeams
-    out = (sps_candidate * max(nb * cap, 1))()
+    if batch._all_out is None or len(batch._all_out) != max(nb * cap, 1):
+        batch._all_out = (sps_candidate * max(nb * cap, 1))()
+    out = batch._all_out  # every record returned is copied out below
     n = (ctypes.c_int32 * nb)()
     rc = library().sps_batch_candidates_all(batch.handle, out, int(cap), n, _stream(stream))
     if not (rc == 6 and allow_truncated):
