@@ -167,7 +167,7 @@ def main():
     from paper_2511_02328_amd import sps
 
     from sps_inputs import synth
-    from sps_inputs.workloads import BATCH_WORKLOADS, STREAMING_WORKLOADS, WORKLOADS
+    from sps_inputs.workloads import BATCH_WORKLOADS, STREAMING_WORKLOADS, SWEEPS, WORKLOADS
 
     if args.workload == "detector":
         return bench_detector(args)
@@ -175,6 +175,8 @@ def main():
         return bench_streaming(args, STREAMING_WORKLOADS[args.workload])
     if args.workload in BATCH_WORKLOADS:
         return bench_batched(args, BATCH_WORKLOADS[args.workload])
+    if args.workload in SWEEPS:
+        return bench_sweep(args, args.workload, SWEEPS[args.workload])
     if args.method == "subband":
         return bench_subband(args, WORKLOADS[args.workload])
     wl = WORKLOADS[args.workload]
@@ -862,6 +864,98 @@ def bench_subband(args, wl):
     }
     print(json.dumps(rec), flush=True)
     plan.close()
+
+
+# Dedispersion kernel times the paper prints for its own code at the two
+# ends of each sweep (RTX 4090, Sec. 3.1 and 3.2), in seconds: context from
+# other hardware, never a target of this line.
+PAPER_SWEEP_KERNEL_S = {"sweep_channels": {512: 0.11, 8192: 0.96},
+                        "sweep_dms": {512: 0.091, 8192: 1.295}}
+
+
+def bench_sweep(args, name, points):
+    """The paper's dedispersion timing sweeps: kernel time against the number
+    of channels (Sec. 3.1, 1500 trials, 22 s span) or of trial DMs (Sec. 3.2,
+    2048 channels, 20 s span), with R = span / kernel time at each point.
+    The kernel alone is timed (HIP events around `--steps` calls, at most 5,
+    after one untimed call), its input resident on the device, each point
+    with the tiling the autotuner keeps for it."""
+    import torch
+
+    from paper_2511_02328_amd import sps
+    from sps_inputs import synth
+    torch.cuda.set_device(0)
+    reps = max(2, min(args.steps, 5))
+    subband = args.method == "subband"
+    rows = []
+    for wl in points:
+        if subband:
+            plan = sps.sps_subband_plan_create(wl.freqs_mhz(), wl.fref_mhz, wl.tsamp_s, wl.ndm,
+                                               wl.dm_lo, (wl.dm_hi - wl.dm_lo) / (wl.ndm - 1),
+                                               args.n0, args.nsub)
+            _, rtab, _, emax = sps.sps_subband_tables(plan)
+            # the method's own integer adds: stage 1 (coarse trials x channels
+            # x stage-1 row length) + stage 2 (trials x subbands x outputs)
+            adds = (-(-wl.ndm // args.n0) * wl.nchan * ((wl.nout + int(rtab.max()) + 3) // 4 * 4)
+                    + wl.ndm * args.nsub * wl.nout)
+        else:
+            plan, emax, adds = sps.plan_for(wl), 0, wl.sample_adds()
+        nsamp = wl.nout + max(emax, sps.sps_plan_delays(plan)[1])
+        sps.sps_plan_autotune(plan, 1 << 18, 2)
+        X, _ = synth.make_filterbank(wl, nsamp, device="cuda", pitch=(nsamp + 255) // 256 * 256)
+        Y = torch.empty((wl.ndm, wl.nout), dtype=torch.int32, device="cuda")
+        if subband:
+            def fn():
+                sps.sps_dedisperse_subband(plan, X, nsamp, Y, wl.nout)
+        else:
+            def fn():
+                sps.sps_dedisperse(plan, X, nsamp, Y, wl.nout)
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        b.synchronize()
+        t = a.elapsed_time(b) / reps / 1e3
+        span = wl.nout * wl.tsamp_s
+        row = {"workload": wl.name, "nchan": wl.nchan, "ndm": wl.ndm, "nout": wl.nout,
+               "nsamp_in": nsamp, "kernel_s": t, "R": span / t,
+               "dm_time_samples_per_s": wl.dm_time_samples() / t,
+               "integer_adds_per_s": adds / t}
+        if not subband:
+            row["tiling"] = sps.sps_plan_get_tiling(plan)
+        rows.append(row)
+        print(f"[bench] {wl.name}: {t * 1e3:.1f} ms, R = {span / t:.0f}", flush=True)
+        del X, Y
+        plan.close()
+        torch.cuda.empty_cache()
+    key = "nchan" if name == "sweep_channels" else "ndm"
+    paper = PAPER_SWEEP_KERNEL_S[name]
+    last = rows[-1]
+    rec = {
+        "metric": "DM×time samples/s dedispersed" + (" (subband method)" if subband else ""),
+        "value": last["dm_time_samples_per_s"], "unit": "DM-time samples/s", "n_gpus": 1,
+        "steps": reps, "warmup": 1, "ms_per_step": last["kernel_s"] * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": name, "method": args.method, "value_at": last["workload"]},
+        "points": rows,
+        # linear in the swept size: time per unit of it, first and last point
+        "kernel_s_per_unit": {str(r[key]): r["kernel_s"] / r[key] for r in (rows[0], last)},
+        "paper_kernel_s_rtx4090": {str(k): v for k, v in paper.items()},
+        "kernel_time_ratio_paper_over_this": {
+            str(k): v / r["kernel_s"] for k, v in paper.items() for r in rows if r[key] == k},
+        "roofline": {"kernel": "sps_dedisperse_subband" if subband else "dedisperse_kernel",
+                     "bound": "alu", "unit": "TOP/s", "peak": ALU_PEAK_TOPS,
+                     "achieved": last["integer_adds_per_s"] / 1e12,
+                     "frac": last["integer_adds_per_s"] / 1e12 / ALU_PEAK_TOPS, "traffic": None,
+                     "work_per_launch": (f"{last['integer_adds_per_s'] * last['kernel_s']:.4g} "
+                                         "integer adds (stage 1 + stage 2)") if subband else
+                                        f"{last['ndm']} x {last['nout']} x {last['nchan']} sample-adds"},
+    }
+    print(json.dumps(rec), flush=True)
 
 
 def host_cpu():

@@ -177,6 +177,25 @@ STREAMING = StreamingWorkload(
     name="streaming_24_mixed",
     groups=((8, _STREAM_A), (12, FULL_SCALE), (4, _STREAM_C)))
 
+
+def _sweep_point(name: str, nchan: int, ndm: int, span_s: float) -> Workload:
+    return Workload(
+        name=name, nchan=nchan, f_lo_mhz=1000.0, f_hi_mhz=1500.0, tsamp_s=40e-6,
+        nout=int(round(span_s / 40e-6)), ndm=ndm, dm_lo=0.0, dm_hi=1024.0, widths=(1,),
+        pulses=PulseModel(count=4, dm_range=(50.0, 1000.0)), seed=21)
+
+
+# The paper's two dedispersion timing sweeps (Sec. 3.1 and 3.2): 8-bit data
+# at 40 us over 1000-1500 MHz (centre 1250 MHz), DMs 0-1024.  Channel sweep:
+# 1500 trials over a 22 s dedispersed span, 512..8192 channels.  DM sweep:
+# 2048 channels over a 20 s span, 512..8192 trials.
+SWEEPS = {
+    "sweep_channels": tuple(_sweep_point(f"sweep_{c}ch_1500dm_22s", c, 1500, 22.0)
+                            for c in (512, 1024, 2048, 4096, 8192)),
+    "sweep_dms": tuple(_sweep_point(f"sweep_2048ch_{d}dm_20s", 2048, d, 20.0)
+                       for d in (512, 1024, 2048, 4096, 8192)),
+}
+
 WORKLOADS = {w.name: w for w in (SINGLE_BEAM, FULL_SCALE)}
 BATCH_WORKLOADS = {BATCHED.name: BATCHED}
 STREAMING_WORKLOADS = {STREAMING.name: STREAMING}

@@ -73,6 +73,20 @@ def test_batched_and_streaming_compositions():
                       (8192, 4096, 1 << 18): 4}
 
 
+def test_paper_sweep_shapes():
+    """The two dedispersion timing sweeps of Sec. 3.1 (channel count) and
+    Sec. 3.2 (trial DMs): 40 us sampling, 500 MHz around 1250 MHz, DMs 0-1024."""
+    ch, dm = workloads.SWEEPS["sweep_channels"], workloads.SWEEPS["sweep_dms"]
+    assert [w.nchan for w in ch] == [512, 1024, 2048, 4096, 8192]
+    assert {(w.ndm, w.nout) for w in ch} == {(1500, 550000)}   # 22 s span
+    assert [w.ndm for w in dm] == [512, 1024, 2048, 4096, 8192]
+    assert {(w.nchan, w.nout) for w in dm} == {(2048, 500000)}  # 20 s span
+    for w in ch + dm:
+        assert w.tsamp_s == 40e-6 and (w.f_lo_mhz + w.f_hi_mhz) / 2 == 1250.0
+        assert w.f_hi_mhz - w.f_lo_mhz == 500.0
+        assert w.dms()[0] == 0.0 and w.dms()[-1] == pytest.approx(1024.0)
+
+
 def _meta(n_pos, n_neg):
     n = n_pos + n_neg
     meta = {
