@@ -30,8 +30,9 @@ constexpr int kPerThread = kBins / kThreads;
 constexpr int kSampleRuns = 8;
 constexpr int kSampleRun = 4 * kThreads / kSampleRuns;  // 512: one 16-byte load per thread
 
-// Exclusive scan of one value per thread across the workgroup.
-__device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *tmp /* >= 16 */) {
+// Exclusive scan of one value per thread across a workgroup of NT threads.
+template <int NT = kThreads>
+__device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *tmp /* >= NT / 64 */) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t inc = v;
 #pragma unroll
@@ -42,14 +43,14 @@ __device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *tmp /* >= 16 */) 
   if (lane == 63) tmp[wave] = inc;
   __syncthreads();
   if (wave == 0) {
-    uint32_t s = lane < kThreads / 64 ? tmp[lane] : 0u;
+    uint32_t s = lane < NT / 64 ? tmp[lane] : 0u;
     uint32_t si = s;
 #pragma unroll
-    for (int o = 1; o < 16; o <<= 1) {
+    for (int o = 1; o < NT / 64; o <<= 1) {
       const uint32_t y = __shfl_up(si, o, 64);
       if (lane >= o) si += y;
     }
-    if (lane < kThreads / 64) tmp[lane] = si - s;
+    if (lane < NT / 64) tmp[lane] = si - s;
   }
   __syncthreads();
   const uint32_t r = tmp[wave] + inc - v;
@@ -386,6 +387,209 @@ __device__ void row_stats_row(const uint32_t *__restrict__ row, int64_t nout, in
   }
 }
 
+// ---------------------------------------------------------------------------
+// Short rows (nout <= kShortMax): the fixed cost of the path above (clearing
+// and scanning 4096- and 16384-bin histograms with 16 waves) outweighs a row
+// of a few thousand values.  Here one workgroup of 4 waves owns a row, holds
+// it in registers (16 values per thread, read once) and centres a window of
+// kShortWin unit bins on the row's mean.  The same exact tests as the
+// one-read path decide whether the window holds the median and every
+// deviation up to the MAD; rows that fail them (a spread wider than the
+// window) take an exact radix selection over the registers, 8 bits a pass.
+
+constexpr int kShortThreads = 256;
+constexpr int kShortPer = 16;                          // values per thread
+constexpr int kShortMax = kShortThreads * kShortPer;   // 4096
+constexpr int kShortWin = 4096;                        // window bins (16 KiB)
+constexpr int kShortBinsPer = kShortWin / kShortThreads;
+static_assert(kShortBinsPer % 4 == 0, "bins are read as 16-byte vectors");
+static_assert(kShortThreads == 256, "one radix bin per thread");
+
+// Value j of thread t is row element 1024 (j / 4) + 4 t + j % 4: one 16-byte
+// load per group of four, coalesced across the workgroup.
+__device__ __forceinline__ int short_index(int j) {
+  return (j >> 2) * (4 * kShortThreads) + 4 * (int)threadIdx.x + (j & 3);
+}
+
+// The k-th smallest (from 0) of key(v) over the row's n values, keys < 2^24,
+// by three 8-bit radix passes over a 256-bin histogram.  The rare path: it
+// reads the row again rather than keep the values live in registers.
+template <typename Key>
+__device__ uint32_t short_select(const SPS_GLOBAL uint32_t *row, int n, uint32_t k, Key key,
+                                 uint32_t *hist, uint32_t *tmp, uint32_t *sel) {
+  uint32_t prefix = 0;
+#pragma unroll 1
+  for (int sh = 16; sh >= 0; sh -= 8) {
+    hist[threadIdx.x] = 0u;
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += kShortThreads) {
+      const uint32_t x = key(row[i]);
+      if ((x >> (sh + 8)) == (prefix >> (sh + 8))) atomicAdd(&hist[(x >> sh) & 255u], 1u);
+    }
+    __syncthreads();
+    const uint32_t c = hist[threadIdx.x];
+    const uint32_t below = block_exclusive_scan<kShortThreads>(c, tmp);
+    if (k >= below && k < below + c) {
+      sel[0] = threadIdx.x;
+      sel[1] = below;
+    }
+    __syncthreads();
+    prefix |= sel[0] << sh;
+    k -= sel[1];
+    __syncthreads();
+  }
+  return prefix;
+}
+
+// Exact median and MAD by radix selection, packed as med | mad << 32 (kept
+// out of line: the fast path's registers stay free of it).
+__device__ __noinline__ uint64_t short_select_both(const SPS_GLOBAL uint32_t *row, int n,
+                                                   uint32_t k, uint32_t *hist, uint32_t *tmp,
+                                                   uint32_t *sel) {
+  const uint32_t med = short_select(row, n, k, [](uint32_t x) { return x; }, hist, tmp, sel);
+  const uint32_t mad = short_select(
+      row, n, k, [med](uint32_t x) { return x >= med ? x - med : med - x; }, hist, tmp, sel);
+  return (uint64_t)med | ((uint64_t)mad << 32);
+}
+
+// Median and MAD of a row of 1 <= n <= kShortMax values (the whole
+// workgroup), written to out[0..1].
+__device__ void row_stats_short_row(const uint32_t *__restrict__ row_in, int n,
+                                    int32_t *__restrict__ out) {
+  __shared__ __align__(16) uint32_t hist[kShortWin];
+  __shared__ uint32_t tmp[kShortThreads / 64];
+  __shared__ uint32_t sel[3];
+  const SPS_GLOBAL uint32_t *row = gmem(row_in);
+  const bool vec = ((reinterpret_cast<uintptr_t>(row_in) & 15) == 0);
+  uint32_t v[kShortPer];
+#pragma unroll
+  for (int g = 0; g < kShortPer / 4; ++g) {
+    const int i = short_index(4 * g);
+    if (vec && i + 3 < n) {
+      const u32x4 q = *(const SPS_GLOBAL u32x4 *)(row + i);
+      v[4 * g] = q.x;
+      v[4 * g + 1] = q.y;
+      v[4 * g + 2] = q.z;
+      v[4 * g + 3] = q.w;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[4 * g + e] = i + e < n ? row[i + e] : 0u;
+    }
+  }
+  const uint32_t k = (uint32_t)(n - 1) / 2;
+  // window [lo, lo + kShortWin) around the mean (from the values' top 16 of
+  // 24 bits: 4096 of them sum below 2^28)
+  uint32_t s = 0;
+#pragma unroll
+  for (int j = 0; j < kShortPer; ++j) s += v[j] >> 8;
+  s = block_sum(s, &sel[2]);
+  const uint32_t centre = (uint32_t)(((uint64_t)s << 8) / (uint32_t)n) + 128u;
+  const uint32_t lo = centre > (uint32_t)(kShortWin / 2) ? centre - (uint32_t)(kShortWin / 2) : 0u;
+#pragma unroll
+  for (int q = 0; q < kShortBinsPer; ++q) hist[threadIdx.x + kShortThreads * q] = 0u;
+  __syncthreads();
+  uint32_t below = 0, inside = 0;
+#pragma unroll
+  for (int j = 0; j < kShortPer; ++j) {
+    if (short_index(j) < n) {
+      const uint32_t x = v[j] - lo;
+      if (x < (uint32_t)kShortWin) {
+        atomicAdd(&hist[x], 1u);
+        ++inside;
+      }
+      below += v[j] < lo ? 1u : 0u;
+    }
+  }
+  // both counts are at most 4096: one sum carries the two
+  const uint32_t bi = block_sum(below | (inside << 16), &sel[2]);
+  below = bi & 0xFFFFu;
+  inside = bi >> 16;
+  uint32_t med = 0, mad = 0;
+  bool ok = k >= below && k - below < inside;  // the window holds the median
+  if (ok) {
+    // thread t owns bins [t kShortBinsPer, (t + 1) kShortBinsPer)
+    const int b0 = threadIdx.x * kShortBinsPer;
+    uint32_t h[kShortBinsPer];
+    uint32_t part = 0;
+#pragma unroll
+    for (int q = 0; q < kShortBinsPer / 4; ++q) {
+      const uint4 w = *reinterpret_cast<const uint4 *>(&hist[b0 + 4 * q]);
+      h[4 * q] = w.x;
+      h[4 * q + 1] = w.y;
+      h[4 * q + 2] = w.z;
+      h[4 * q + 3] = w.w;
+    }
+#pragma unroll
+    for (int q = 0; q < kShortBinsPer; ++q) part += h[q];
+    uint32_t run = block_exclusive_scan<kShortThreads>(part, tmp);
+    const uint32_t kk = k - below;
+    if (kk >= run && kk < run + part) {
+#pragma unroll
+      for (int q = 0; q < kShortBinsPer; ++q) {
+        if (kk >= run && kk < run + h[q]) sel[0] = (uint32_t)(b0 + q);
+        run += h[q];
+      }
+    }
+    __syncthreads();
+    const int mloc = (int)sel[0];  // median - lo
+    // dev[m] = #(|v - med| == m) for m < mspan, where med +- m both lie in
+    // the window; thread t owns m in [t kShortBinsPer, (t + 1) kShortBinsPer)
+    const int mspan = min(mloc + 1, kShortWin - mloc);
+    part = 0;
+#pragma unroll
+    for (int q = 0; q < kShortBinsPer; ++q) {
+      const int m = b0 + q;
+      uint32_t c = 0;
+      if (m < mspan) {
+        c = hist[mloc - m];
+        if (m > 0) c += hist[mloc + m];
+      }
+      h[q] = c;
+      part += c;
+    }
+    // #(|v - med| < mspan) must exceed k for the MAD to lie below mspan
+    ok = block_sum(part, &sel[2]) >= k + 1;
+    if (ok) {
+      run = block_exclusive_scan<kShortThreads>(part, tmp);
+      if (k >= run && k < run + part) {
+#pragma unroll
+        for (int q = 0; q < kShortBinsPer; ++q) {
+          if (k >= run && k < run + h[q]) sel[1] = (uint32_t)(b0 + q);
+          run += h[q];
+        }
+      }
+      __syncthreads();
+      med = lo + (uint32_t)mloc;
+      mad = sel[1];
+    }
+    __syncthreads();
+  }
+  if (!ok) {
+    const uint64_t r = short_select_both(row, n, k, hist, tmp, sel);
+    med = (uint32_t)r;
+    mad = (uint32_t)(r >> 32);
+  }
+  if (threadIdx.x == 0) {
+    out[0] = (int32_t)med;
+    out[1] = (int32_t)mad;
+  }
+}
+
+__global__ __launch_bounds__(kShortThreads) void row_stats_short_kernel(
+    const uint32_t *__restrict__ Y, int nout, int32_t *__restrict__ stats) {
+  const int d = blockIdx.x;
+  row_stats_short_row(Y + (int64_t)d * nout, nout, stats + 2 * (int64_t)d);
+}
+
+// One workgroup per (beam, DM row) of a batch whose beams are all short.
+__global__ __launch_bounds__(kShortThreads) void row_stats_short_batch_kernel(
+    const BeamWork *__restrict__ beams, int ndm) {
+  const int b = blockIdx.x / ndm;
+  const int d = blockIdx.x - b * ndm;
+  const BeamWork &bw = beams[b];
+  row_stats_short_row(bw.Y + (int64_t)d * bw.nout, (int)bw.nout, bw.stats + 2 * (int64_t)d);
+}
+
 __global__ __launch_bounds__(kThreads) void row_stats_kernel(const uint32_t *__restrict__ Y,
                                                              int64_t nout, int shift,
                                                              int32_t *__restrict__ stats) {
@@ -410,20 +614,29 @@ static int stats_shift(uint32_t vmax) {
 }
 
 hipError_t launch_row_stats_batch(const BeamWork *beams, int nbeams, int ndm, uint32_t vmax,
-                                  hipStream_t stream) {
+                                  int64_t max_nout, hipStream_t stream) {
   const int shift = stats_shift(vmax);
-  if (shift < 0 || (int64_t)nbeams * ndm > 0x7FFFFFFF) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(row_stats_batch_kernel, dim3(nbeams * ndm), dim3(kThreads), 0, stream, beams,
-                     ndm, shift);
+  if (shift < 0 || (int64_t)nbeams * ndm > 0x7FFFFFFF || max_nout < 1)
+    return hipErrorInvalidValue;
+  if (max_nout <= kShortMax)
+    hipLaunchKernelGGL(row_stats_short_batch_kernel, dim3(nbeams * ndm), dim3(kShortThreads), 0,
+                       stream, beams, ndm);
+  else
+    hipLaunchKernelGGL(row_stats_batch_kernel, dim3(nbeams * ndm), dim3(kThreads), 0, stream,
+                       beams, ndm, shift);
   return hipGetLastError();
 }
 
 hipError_t launch_row_stats(const uint32_t *Y, int ndm, int64_t nout, uint32_t vmax,
                             int32_t *stats, hipStream_t stream) {
   const int shift = stats_shift(vmax);
-  if (shift < 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(row_stats_kernel, dim3(ndm), dim3(kThreads), 0, stream, Y, nout, shift,
-                     stats);
+  if (shift < 0 || nout < 1) return hipErrorInvalidValue;
+  if (nout <= kShortMax)
+    hipLaunchKernelGGL(row_stats_short_kernel, dim3(ndm), dim3(kShortThreads), 0, stream, Y,
+                       (int)nout, stats);
+  else
+    hipLaunchKernelGGL(row_stats_kernel, dim3(ndm), dim3(kThreads), 0, stream, Y, nout, shift,
+                       stats);
   return hipGetLastError();
 }
 

@@ -1023,7 +1023,8 @@ sps_status batch_enqueue(sps_batch b, hipStream_t s) {
                                               b->dd_items, b->staged, p->nchan, p->ndm,
                                               b->grid_dd, s);
   if (e != hipSuccess) return hip_fail(e, "batched dedispersion launch");
-  e = sps::launch_row_stats_batch(b->d_beams, b->nbeams, p->ndm, 255u * (uint32_t)p->nchan, s);
+  e = sps::launch_row_stats_batch(b->d_beams, b->nbeams, p->ndm, 255u * (uint32_t)p->nchan,
+                                  *std::max_element(b->nout.begin(), b->nout.end()), s);
   if (e != hipSuccess) return hip_fail(e, "batched statistics launch");
   if (b->tiles) {
     // tile mode: detector tiles straight from the boxcar pass, no planes

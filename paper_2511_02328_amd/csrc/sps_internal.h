@@ -285,8 +285,10 @@ int64_t plan_device_bytes(sps_plan plan);
 // returns s.
 sps_status set_error(sps_status s, const char *msg);
 
+// max_nout: the longest beam's nout (picks the short-row form when every
+// beam has at most 4096 outputs).
 hipError_t launch_row_stats_batch(const BeamWork *beams, int nbeams, int ndm, uint32_t vmax,
-                                  hipStream_t stream);
+                                  int64_t max_nout, hipStream_t stream);
 // scratch != nullptr: every beam's tile maxima go to the key array of its
 // detection scratch (the out array of detect_layout, at scratch +
 // det_begin), which must be zero.

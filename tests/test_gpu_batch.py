@@ -99,7 +99,8 @@ def _receiver(plan):
 # the beams' first work items) takes several levels, with tiny, ragged and
 # segment-edge lengths side by side
 @pytest.mark.parametrize("nouts", [[3000, 5000, 1281, 7777, 4096], [16], [20000] * 3,
-                                   [16, 17, 1000, 4095, 4096, 4097, 333, 8191] * 5])
+                                   [16, 17, 1000, 4095, 4096, 4097, 333, 8191] * 5,
+                                   [4096, 3001, 17, 1000, 4095, 333]])
 def test_batch_matches_oracle(sps, nouts):
     wl = _wl(nouts[0], 0)
     widths = list(wl.widths)

@@ -377,6 +377,51 @@ def test_detect_dense_chains(sps, radius):
     assert np.array_equal(cands["dm_idx"], co["d"]) and np.array_equal(cands["t_idx"], co["t"])
 
 
+@pytest.mark.parametrize("case", ["noise", "narrow", "near_zero", "near_top", "constant",
+                                  "wide_mad", "spread", "bimodal", "spikes"])
+@pytest.mark.parametrize("nout", [1, 2, 3, 5, 64, 1023, 3001, 4095, 4096])
+def test_stats_short_rows(sps, case, nout):
+    """Rows of at most 4096 values take the short-row form: a window of
+    unit bins around the row mean, with the exact radix fallback for rows it
+    cannot hold (a spread far wider than the window, two clusters far from
+    their mean, a MAD wider than the window's half).  Odd lengths leave every
+    row after the first unaligned."""
+    rng = np.random.Generator(np.random.PCG64(1000 * nout + len(case)))
+    nchan, ndm = 4096, 5
+    vmax = 255 * nchan
+    if case == "noise":
+        Y = rng.normal(32768, 256, (ndm, nout))
+    elif case == "narrow":
+        Y = rng.normal(300000, 3, (ndm, nout))
+    elif case == "near_zero":
+        Y = np.abs(rng.normal(0, 700, (ndm, nout)))
+    elif case == "near_top":
+        Y = vmax - np.abs(rng.normal(0, 900, (ndm, nout)))
+    elif case == "constant":
+        Y = np.full((ndm, nout), 123457.0)
+    elif case == "wide_mad":   # MAD near or past the window's half-width
+        Y = rng.normal(500000, 3100, (ndm, nout))
+    elif case == "spread":
+        Y = rng.uniform(0, vmax, (ndm, nout))
+    elif case == "bimodal":
+        centre = rng.choice([100000, 900000], size=(ndm, nout))
+        Y = centre + rng.integers(-5, 6, size=(ndm, nout))
+    else:                      # noise with a few huge samples pulling the mean
+        Y = rng.normal(400000, 300, (ndm, nout))
+        Y[:, ::97] += 600000
+    Y = np.clip(np.rint(Y), 0, vmax).astype(np.uint32)
+    sto = oracle.stats(Y)
+    wl = Workload("s", nchan, 1000.0, 1500.0, 1e-4, nout, ndm, 0.0, 1.0, (1,))
+    with sps.plan_for(wl) as plan:
+        snr = torch.empty((ndm, nout), dtype=torch.float32, device="cuda")
+        best = torch.empty((ndm, nout), dtype=torch.uint8, device="cuda")
+        st = torch.empty((ndm, 2), dtype=torch.int32, device="cuda")
+        sps.sps_boxcar_snr(plan, torch.from_numpy(Y.view(np.int32)).cuda(), nout, [1], snr,
+                           best, st)
+        torch.cuda.synchronize()
+        assert np.array_equal(st.cpu().numpy().astype(np.int64), sto)
+
+
 @pytest.mark.parametrize("case", ["noise", "narrow", "near_zero", "near_top", "spiky", "step",
                                   "trimodal", "short"])
 def test_stats_windowed_rows(sps, case):
