@@ -452,13 +452,38 @@ __device__ __noinline__ uint64_t short_select_both(const SPS_GLOBAL uint32_t *ro
   return (uint64_t)med | ((uint64_t)mad << 32);
 }
 
+// Wave-level sum and inclusive scan (64 lanes).
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_inclusive(uint32_t v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(v, o, 64);
+    if (lane >= o) v += y;
+  }
+  return v;
+}
+
+// Each reduction below has LDS slots of its own (one word per wave), written
+// once per row, so one barrier completes it and none has to guard reuse.
+struct ShortSlots {
+  uint32_t mean[4], count[4], hscan[4];
+};
+
 // Median and MAD of a row of 1 <= n <= kShortMax values (the whole
 // workgroup), written to out[0..1].
 __device__ void row_stats_short_row(const uint32_t *__restrict__ row_in, int n,
                                     int32_t *__restrict__ out) {
   __shared__ __align__(16) uint32_t hist[kShortWin];
   __shared__ uint32_t tmp[kShortThreads / 64];
-  __shared__ uint32_t sel[3];
+  __shared__ uint32_t sel[2];
+  __shared__ ShortSlots sl;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const SPS_GLOBAL uint32_t *row = gmem(row_in);
   const bool vec = ((reinterpret_cast<uintptr_t>(row_in) & 15) == 0);
   uint32_t v[kShortPer];
@@ -476,18 +501,21 @@ __device__ void row_stats_short_row(const uint32_t *__restrict__ row_in, int n,
       for (int e = 0; e < 4; ++e) v[4 * g + e] = i + e < n ? row[i + e] : 0u;
     }
   }
+  // the window is cleared under the same barrier as the mean's sum
+#pragma unroll
+  for (int q = 0; q < kShortBinsPer; ++q) hist[threadIdx.x + kShortThreads * q] = 0u;
   const uint32_t k = (uint32_t)(n - 1) / 2;
   // window [lo, lo + kShortWin) around the mean (from the values' top 16 of
   // 24 bits: 4096 of them sum below 2^28)
   uint32_t s = 0;
 #pragma unroll
   for (int j = 0; j < kShortPer; ++j) s += v[j] >> 8;
-  s = block_sum(s, &sel[2]);
+  s = wave_sum(s);
+  if (lane == 0) sl.mean[wave] = s;
+  __syncthreads();
+  s = sl.mean[0] + sl.mean[1] + sl.mean[2] + sl.mean[3];
   const uint32_t centre = (uint32_t)(((uint64_t)s << 8) / (uint32_t)n) + 128u;
   const uint32_t lo = centre > (uint32_t)(kShortWin / 2) ? centre - (uint32_t)(kShortWin / 2) : 0u;
-#pragma unroll
-  for (int q = 0; q < kShortBinsPer; ++q) hist[threadIdx.x + kShortThreads * q] = 0u;
-  __syncthreads();
   uint32_t below = 0, inside = 0;
 #pragma unroll
   for (int j = 0; j < kShortPer; ++j) {
@@ -500,17 +528,21 @@ __device__ void row_stats_short_row(const uint32_t *__restrict__ row_in, int n,
       below += v[j] < lo ? 1u : 0u;
     }
   }
-  // both counts are at most 4096: one sum carries the two
-  const uint32_t bi = block_sum(below | (inside << 16), &sel[2]);
+  // both counts are at most 4096: one sum carries the two; its barrier also
+  // completes the histogram
+  uint32_t bi = wave_sum(below | (inside << 16));
+  if (lane == 0) sl.count[wave] = bi;
+  __syncthreads();
+  bi = sl.count[0] + sl.count[1] + sl.count[2] + sl.count[3];
   below = bi & 0xFFFFu;
   inside = bi >> 16;
   uint32_t med = 0, mad = 0;
   bool ok = k >= below && k - below < inside;  // the window holds the median
   if (ok) {
-    // thread t owns bins [t kShortBinsPer, (t + 1) kShortBinsPer)
+    // The window's counts become their inclusive prefix P in place: thread t
+    // owns bins [t kShortBinsPer, (t + 1) kShortBinsPer).
     const int b0 = threadIdx.x * kShortBinsPer;
     uint32_t h[kShortBinsPer];
-    uint32_t part = 0;
 #pragma unroll
     for (int q = 0; q < kShortBinsPer / 4; ++q) {
       const uint4 w = *reinterpret_cast<const uint4 *>(&hist[b0 + 4 * q]);
@@ -520,51 +552,56 @@ __device__ void row_stats_short_row(const uint32_t *__restrict__ row_in, int n,
       h[4 * q + 3] = w.w;
     }
 #pragma unroll
-    for (int q = 0; q < kShortBinsPer; ++q) part += h[q];
-    uint32_t run = block_exclusive_scan<kShortThreads>(part, tmp);
+    for (int q = 1; q < kShortBinsPer; ++q) h[q] += h[q - 1];
+    const uint32_t part = h[kShortBinsPer - 1];
+    const uint32_t inc = wave_inclusive(part);
+    if (lane == 63) sl.hscan[wave] = inc;
+    __syncthreads();
+    uint32_t run = inc - part;
+    for (int w = 0; w < wave; ++w) run += sl.hscan[w];
+#pragma unroll
+    for (int q = 0; q < kShortBinsPer / 4; ++q)
+      *reinterpret_cast<uint4 *>(&hist[b0 + 4 * q]) =
+          make_uint4(h[4 * q] + run, h[4 * q + 1] + run, h[4 * q + 2] + run, h[4 * q + 3] + run);
+    // the median's bin: the first whose prefix exceeds its rank in the window
     const uint32_t kk = k - below;
     if (kk >= run && kk < run + part) {
+      int q = 0;  // prefixes are non-decreasing: count those not above kk
 #pragma unroll
-      for (int q = 0; q < kShortBinsPer; ++q) {
-        if (kk >= run && kk < run + h[q]) sel[0] = (uint32_t)(b0 + q);
-        run += h[q];
-      }
+      for (int j = 0; j < kShortBinsPer; ++j) q += run + h[j] <= kk ? 1 : 0;
+      sel[0] = (uint32_t)(b0 + q);
     }
     __syncthreads();
     const int mloc = (int)sel[0];  // median - lo
-    // dev[m] = #(|v - med| == m) for m < mspan, where med +- m both lie in
-    // the window; thread t owns m in [t kShortBinsPer, (t + 1) kShortBinsPer)
+    // #(|v - med| <= m) = P[mloc + m] - P[mloc - m - 1] for m < mspan, where
+    // med +- m both lie in the window.  The MAD is the least m at which it
+    // exceeds k: one wave finds it in two steps, m = 33 l + 32 over the lanes
+    // l (33 is odd: the 64 reads fall in distinct banks, and 64 x 33 covers
+    // the widest mspan, 2048), then the 33 values below the first hit.
     const int mspan = min(mloc + 1, kShortWin - mloc);
-    part = 0;
-#pragma unroll
-    for (int q = 0; q < kShortBinsPer; ++q) {
-      const int m = b0 + q;
-      uint32_t c = 0;
-      if (m < mspan) {
-        c = hist[mloc - m];
-        if (m > 0) c += hist[mloc + m];
+    if (wave == 0) {
+      auto reaches = [&](int m) {
+        m = min(m, mspan - 1);
+        const uint32_t lo_p = m < mloc ? hist[mloc - m - 1] : 0u;
+        return hist[mloc + m] - lo_p >= k + 1;
+      };
+      const uint64_t b1 = __ballot(reaches(33 * lane + 32));
+      if (b1 == 0) {
+        // fewer than k + 1 deviations below mspan: the MAD lies outside
+        if (lane == 0) sel[1] = 0xFFFFFFFFu;
+      } else {
+        const int f = __ffsll((unsigned long long)b1) - 1;
+        const uint64_t b2 = __ballot(lane < 33 && reaches(33 * f + lane));
+        if (lane == 0) sel[1] = (uint32_t)(33 * f + __ffsll((unsigned long long)b2) - 1);
       }
-      h[q] = c;
-      part += c;
-    }
-    // #(|v - med| < mspan) must exceed k for the MAD to lie below mspan
-    ok = block_sum(part, &sel[2]) >= k + 1;
-    if (ok) {
-      run = block_exclusive_scan<kShortThreads>(part, tmp);
-      if (k >= run && k < run + part) {
-#pragma unroll
-        for (int q = 0; q < kShortBinsPer; ++q) {
-          if (k >= run && k < run + h[q]) sel[1] = (uint32_t)(b0 + q);
-          run += h[q];
-        }
-      }
-      __syncthreads();
-      med = lo + (uint32_t)mloc;
-      mad = sel[1];
     }
     __syncthreads();
+    ok = sel[1] != 0xFFFFFFFFu;
+    med = lo + (uint32_t)mloc;
+    mad = sel[1];
   }
   if (!ok) {
+    __syncthreads();
     const uint64_t r = short_select_both(row, n, k, hist, tmp, sel);
     med = (uint32_t)r;
     mad = (uint32_t)(r >> 32);
