@@ -703,6 +703,7 @@ def bench_detector(args):
         fac.plan, [dict(X=fac.X[i], nsamp_in=fac.nsamp, nout=fac.wl.nout, Y=fac.Y[i],
                         stats=fac.stats[i], snr=None, best_w=None) for i in range(fac.batch)],
         list(fac.wl.widths), **detector.SEARCH)
+    sps.sps_batch_autotune(bare, 3, stream)
     for _ in range(2):
         sps.sps_batch_launch_graph(bare, stream)
     e0.record(stream)
@@ -754,6 +755,7 @@ def bench_detector(args):
         "config": {"workload": "detector_tiles_256x512_bf16", "train_tiles": args.train_tiles,
                    "val_tiles": args.val_tiles, "epochs": args.epochs, "batch": args.batch,
                    "lr": args.lr, "tile_generation_s": gen_s,
+                   "search_autotune_ms": [round(x, 3) for x in fac.autotune_ms],
                    "positives_train": int(tr_meta["positive"].sum())},
         "loss_first": float(losses[0]), "loss_last20": float(np.mean(losses[-20:])),
         "train_tflops_mfma_conv": 3 * flops * tiles_trained / (train_ms / 1e3) / 1e12,

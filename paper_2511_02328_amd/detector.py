@@ -131,6 +131,9 @@ class TileFactory:
                  for i in range(batch)]
         self.handle = sps.sps_batch_create(self.plan, beams, list(wl.widths), **SEARCH)
         self.stream = torch.cuda.Stream()
+        # the dedispersion tiling: the fastest on this batch's own launch
+        # (4096 outputs fit some time tiles better than others)
+        self.autotune_ms = sps.sps_batch_autotune(self.handle, 3, self.stream)
 
     def close(self):
         self.handle.close()
