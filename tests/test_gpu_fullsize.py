@@ -6,8 +6,9 @@ sums of the input).  Detection is compared on the GPU's own full S/N plane.
 
 Covered: the full-scale chunk (4096 channels, 2048 DMs, 2^20 samples) on
 brute force and on the subband method, the 19-beam batch (graph replay,
-tiling from the batch autotuner; with and without S/N planes) and a
-full-size stream of the streaming server."""
+tiling from the batch autotuner; with and without S/N planes), a full-size
+stream of the streaming server, and the ends of the paper's two
+dedispersion timing sweeps."""
 import numpy as np
 import pytest
 
@@ -232,3 +233,52 @@ def test_streaming_setup_a_full_size(sps):
             sums_o = oracle.row_checksums(win, D, L)
             sums_g = Y.sum(dim=1, dtype=torch.int64).cpu().numpy().astype(np.uint64)
             assert np.array_equal(sums_g, sums_o), f"chunk {k} row sums"
+
+
+@pytest.mark.parametrize("sweep,point", [("sweep_channels", 0), ("sweep_channels", -1),
+                                         ("sweep_dms", -1)])
+def test_sweep_ends_full_size(sps, sweep, point):
+    """The ends of the paper's dedispersion timing sweeps (Sec. 3.1: 512 and
+    8192 channels, 1500 DMs, 550,000 outputs; Sec. 3.2: 8192 DMs over 2048
+    channels, 500,000 outputs) with the tiling the autotuner keeps, as the
+    benchmark times them: sampled rows bit-exact, every row's sum exact.  At
+    512 channels the subband method (32 subbands of 16 channels) too."""
+    from sps_inputs.workloads import SWEEPS
+    wl = SWEEPS[sweep][point]
+    with sps.plan_for(wl) as plan:
+        D, dmax = sps.sps_plan_delays(plan)
+        nsamp = wl.nout + dmax
+        sps.sps_plan_autotune(plan, 1 << 18, 2)
+        X, _ = synth.make_filterbank(wl, nsamp, device="cuda", pitch=(nsamp + 255) // 256 * 256)
+        Y = torch.empty((wl.ndm, wl.nout), dtype=torch.int32, device="cuda")
+        sps.sps_dedisperse(plan, X, nsamp, Y, wl.nout)
+        torch.cuda.synchronize()
+        Xh = X.cpu().numpy()
+        Do = oracle.delays(wl.freqs_mhz(), wl.fref_mhz, wl.tsamp_s, wl.dms())
+        assert np.array_equal(D, Do)
+        rows = _rows(wl.ndm, 2)
+        Yo = oracle.dedisperse(Xh, Do[rows], wl.nout, nsamp)
+        assert np.array_equal(Y[torch.from_numpy(rows).cuda()].cpu().numpy().view(np.uint32), Yo)
+        sums_o = oracle.row_checksums(Xh, Do, wl.nout, nsamp)
+        sums_g = Y.sum(dim=1, dtype=torch.int64).cpu().numpy().astype(np.uint64)
+        assert np.array_equal(sums_g, sums_o)
+    if wl.nchan == 512:
+        n0, nsub = 8, 32
+        ddm = (wl.dm_hi - wl.dm_lo) / (wl.ndm - 1)
+        with sps.sps_subband_plan_create(wl.freqs_mhz(), wl.fref_mhz, wl.tsamp_s, wl.ndm,
+                                         wl.dm_lo, ddm, n0, nsub) as plan:
+            emax = sps.sps_subband_tables(plan)[3]
+            sps.sps_plan_autotune(plan, 1 << 18, 2)
+            # effective delays past the input read as zero, as in the oracle
+            sps.sps_dedisperse_subband(plan, X, nsamp, Y, wl.nout,
+                                       flags=sps.SPS_ZERO_PAD if emax > dmax else 0)
+            torch.cuda.synchronize()
+            sub = oracle.equal_subbands(wl.nchan, nsub)
+            Ro, _, dmc = oracle.subband_residuals(wl.freqs_mhz(), wl.fref_mhz, wl.tsamp_s, sub,
+                                                  wl.ndm, wl.dm_lo, ddm, n0)
+            Dco = oracle.delays(wl.freqs_mhz(), wl.fref_mhz, wl.tsamp_s, dmc)
+            s_of_c = np.repeat(np.arange(nsub), np.diff(sub))
+            Deff = (Dco[rows // n0] + Ro[rows][:, s_of_c]).astype(np.int32)
+            Yo = oracle.dedisperse(Xh, Deff, wl.nout, nsamp)
+            assert np.array_equal(Y[torch.from_numpy(rows).cuda()].cpu().numpy().view(np.uint32),
+                                  Yo)
