@@ -379,13 +379,14 @@ def test_detect_dense_chains(sps, radius):
 
 @pytest.mark.parametrize("case", ["noise", "narrow", "near_zero", "near_top", "constant",
                                   "wide_mad", "spread", "bimodal", "spikes"])
-@pytest.mark.parametrize("nout", [1, 2, 3, 5, 64, 1023, 3001, 4095, 4096])
+@pytest.mark.parametrize("nout", [1, 2, 3, 5, 64, 1023, 3001, 4095, 4096, 4097])
 def test_stats_short_rows(sps, case, nout):
     """Rows of at most 4096 values take the short-row form: a window of
     unit bins around the row mean, with the exact radix fallback for rows it
     cannot hold (a spread far wider than the window, two clusters far from
     their mean, a MAD wider than the window's half).  Odd lengths leave every
-    row after the first unaligned."""
+    row after the first unaligned; 4097 takes the long-row form on the same
+    shapes."""
     rng = np.random.Generator(np.random.PCG64(1000 * nout + len(case)))
     nchan, ndm = 4096, 5
     vmax = 255 * nchan
