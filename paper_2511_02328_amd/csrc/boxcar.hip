@@ -631,16 +631,53 @@ __device__ __forceinline__ void boxcar_plane_segment(const uint32_t *__restrict_
 // Trials d, d + 1 of one segment pooled over 2 trials x 8 samples, scaled
 // and rounded to bfloat16: pooled[t / 8] of the segment, 512 values (the
 // same S/N values the planes would hold; pooling as the tile kernels do).
+// Power-of-two widths: both trials' windows are fetched into registers before
+// the first is filtered, so the second trial's loads overlap the first's
+// work instead of following it.
+template <int NPOW, bool TAIL>
+__device__ __forceinline__ void pow2_pool_pair(const uint32_t *__restrict__ Y, int64_t nout,
+                                               int d, int64_t t0, int n_left,
+                                               const int32_t *__restrict__ stats,
+                                               const WidthList &widths, uint32_t *P, float *pv) {
+  __shared__ float scale[kMaxWidths];
+  __shared__ uint32_t tmp[4];
+  const SPS_GLOBAL uint32_t *ra = gmem(Y + (int64_t)d * nout + t0);
+  const SPS_GLOBAL uint32_t *rb = gmem(Y + (int64_t)(d + 1) * nout + t0);
+  uint32_t va[Pow2<NPOW>::kLd], vb[Pow2<NPOW>::kLd];
+  pow2_fetch<NPOW, TAIL>(ra, n_left, va);
+  pow2_fetch<NPOW, TAIL>(rb, n_left, vb);
+  const int32_t med_a = gmem(stats)[2 * (int64_t)d], mad_a = gmem(stats)[2 * (int64_t)d + 1];
+  const int32_t med_b = gmem(stats)[2 * (int64_t)d + 2], mad_b = gmem(stats)[2 * (int64_t)d + 3];
+  PoolSink first{pv, true};
+  set_scales(widths, mad_a, scale);
+  pow2_stage<NPOW, TAIL>(va, n_left, med_a, P);
+  pow2_filter<NPOW, TAIL>(n_left, med_a, mad_a, scale, tmp, P, first);
+  __syncthreads();  // P and the scales are refilled for the second trial
+  PoolSink second{pv, false};
+  set_scales(widths, mad_b, scale);
+  pow2_stage<NPOW, TAIL>(vb, n_left, med_b, P);
+  pow2_filter<NPOW, TAIL>(n_left, med_b, mad_b, scale, tmp, P, second);
+}
+
 template <int NPOW>
 __device__ __forceinline__ void boxcar_pool_pair(const uint32_t *__restrict__ Y, int64_t nout,
                                                  int d, int seg, const int32_t *__restrict__ stats,
                                                  const WidthList &widths, uint32_t *P, float *pv,
                                                  float scale, uint16_t *__restrict__ pooled) {
-  PoolSink first{pv, true};
-  boxcar_core<NPOW>(Y, nout, d, seg, stats, widths, P, first);
-  __syncthreads();  // P is refilled for the second trial
-  PoolSink second{pv, false};
-  boxcar_core<NPOW>(Y, nout, d + 1, seg, stats, widths, P, second);
+  if constexpr (NPOW > 0) {
+    constexpr int kLen = Pow2<NPOW>::kLen;
+    const int64_t t0 = (int64_t)seg * kSeg, avail = nout - t0;
+    if (avail >= (int64_t)kLen)
+      pow2_pool_pair<NPOW, false>(Y, nout, d, t0, kLen, stats, widths, P, pv);
+    else
+      pow2_pool_pair<NPOW, true>(Y, nout, d, t0, (int)avail, stats, widths, P, pv);
+  } else {
+    PoolSink first{pv, true};
+    boxcar_core<NPOW>(Y, nout, d, seg, stats, widths, P, first);
+    __syncthreads();  // P is refilled for the second trial
+    PoolSink second{pv, false};
+    boxcar_core<NPOW>(Y, nout, d + 1, seg, stats, widths, P, second);
+  }
   __syncthreads();
   for (int j = threadIdx.x; j < kSeg / 8; j += kThreads) {
     float m = pv[8 * j];
